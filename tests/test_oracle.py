@@ -1,0 +1,469 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics,
+independent of the oracle's own code: a hand-worked round, closed forms
+(prefix sums of chained read-modify-writes), library set operations
+(np.isin, lexsort last-writer-wins, flatnonzero compaction), invariants
+(conservation, replica equality, WS within RS, granule monotonicity) and a
+published test vector of the splitmix64 mixer."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1905_00661_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _bits_to_set(bm: np.ndarray, nbits: int) -> set:
+    b = np.unpackbits(bm.view(np.uint8), bitorder="little")[:nbits]
+    return set(np.flatnonzero(b).tolist())
+
+
+def _mk_batch(txns):
+    lens = np.array([len(t["idx"]) for t in txns], np.uint64)
+    off = np.zeros(len(txns) + 1, np.uint32)
+    off[1:] = np.cumsum(lens)
+    return wl.OplistBatch(offsets=off, idx=np.array(sum((t["idx"] for t in txns), []), np.uint32),
+                          n_writes=np.array([t["n_writes"] for t in txns], np.uint8),
+                          tid=np.array([t["tid"] for t in txns], np.uint32))
+
+
+def _mk_log(entries):
+    log = np.zeros(len(entries), wl.LOG4_DTYPE)
+    for k, (w, v, ts) in enumerate(entries):
+        log[k] = (w, v, ts)
+    return log
+
+
+# ----------------------------------------------------------------- golden round
+
+@pytest.mark.parametrize("which", ["A", "B"])
+def test_golden_hand_worked_round(orc, which):
+    g = json.load(open(os.path.join(GOLDEN, "round_small.json")))
+    N, G = g["n_words"], g["granule"]
+    S = np.array(g["init"], np.uint32)
+    H = S.copy()
+    batch = _mk_batch(g["txns"])
+    res, RS, WS = orc.replay_oplist(S, G, batch, np.array(g["order"], np.uint32))
+    for t, exp in enumerate(g["expect_results"]):
+        assert res[batch.offsets[t]:batch.offsets[t + 1]].tolist() == exp
+    assert S.tolist() == g["expect_after_exec"]
+    assert _bits_to_set(RS, 4) == set(g["expect_rs_granules"])
+    assert _bits_to_set(WS, 4) == set(g["expect_ws_granules"])
+    L = g["logs"][which]
+    log = _mk_log(L["entries"])
+    flags, conflict = orc.validate(log, RS, G, N)
+    assert [(int(flags[0]) >> k) & 1 for k in range(len(L["entries"]))] == L["expect_flags"]
+    assert conflict == L["expect_conflict"]
+    TS = np.zeros(N, np.uint64)
+    mx = orc.apply(S, TS, log, 0)
+    assert mx == max(e[2] for e in L["entries"])
+    assert S.tolist() == L["expect_after_apply"]
+    assert TS.tolist() == L["expect_ts"]
+    orc.apply(H, np.zeros(N, np.uint64), log, 0)
+    ids, runs = orc.merge(conflict, WS, G, S, H)
+    assert ids.tolist() == L["expect_dirty"]
+    assert S.tolist() == L["expect_final"] and H.tolist() == L["expect_final"]
+
+
+# ----------------------------------------------------------------- execution: OPLIST
+
+def test_oplist_chain_prefix_sum(orc):
+    """n transactions each read-modify-write the same word: the value read by
+    the p-th committed one is S0 + sum of the tids committed before it, and
+    the final value is S0 + sum of all tids (mod 2^32)."""
+    g = np.random.default_rng(1)
+    n = 300
+    batch = wl.OplistBatch(offsets=np.arange(n + 1, dtype=np.uint32), idx=np.full(n, 5, np.uint32),
+                           n_writes=np.ones(n, np.uint8),
+                           tid=g.integers(1, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32))
+    S = g.integers(0, 2 ** 32, size=16, dtype=np.uint64).astype(np.uint32)
+    S0 = S.copy()
+    order = g.permutation(n).astype(np.uint32)
+    res, RS, WS = orc.replay_oplist(S, 4, batch, order)
+    tids_in_order = batch.tid[order].astype(np.uint64)
+    before = (np.concatenate([[0], np.cumsum(tids_in_order)[:-1]]) + int(S0[5])) % 2 ** 32
+    assert np.array_equal(res[order], before.astype(np.uint32))
+    assert int(S[5]) == (int(S0[5]) + int(tids_in_order.sum())) % 2 ** 32
+    S0[5] = S[5]
+    assert np.array_equal(S, S0)
+    assert _bits_to_set(RS, 4) == {1} and _bits_to_set(WS, 4) == {1}
+
+
+def test_oplist_disjoint_sets_any_order(orc):
+    """Pairwise-disjoint access sets: every order gives the same state, which
+    is S0 plus tid on each written word (a vectorised closed form)."""
+    g = np.random.default_rng(2)
+    N, n, L = 4096, 200, 6
+    words = g.permutation(N)[: n * L].astype(np.uint32)
+    nw = g.integers(0, L + 1, size=n).astype(np.uint8)
+    batch = wl.OplistBatch(offsets=(np.arange(n + 1) * L).astype(np.uint32), idx=words, n_writes=nw,
+                           tid=(np.arange(n) + 1).astype(np.uint32))
+    S0 = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    expect = S0.copy()
+    pos = np.arange(n * L)
+    written = (pos % L) < np.repeat(nw, L)
+    expect[words[written]] += np.repeat(batch.tid, L)[written]
+    outs = []
+    for seed in range(3):
+        S = S0.copy()
+        res, RS, WS = orc.replay_oplist(S, 1, batch, np.random.default_rng(seed).permutation(n))
+        assert np.array_equal(S, expect)
+        assert np.array_equal(res, S0[words])
+        assert _bits_to_set(RS, N) == set(words.tolist())
+        assert _bits_to_set(WS, N) == set(words[written].tolist())
+        outs.append(res)
+    assert all(np.array_equal(outs[0], o) for o in outs)
+
+
+def test_oplist_read_only_batch(orc):
+    ri = wl.c2(n_words=1 << 16, n_txn=2000, n_log=10, p_hot=0.5)
+    b = ri.batch
+    b.n_writes[:] = 0
+    S = ri.init.copy()
+    res, RS, WS = orc.replay_oplist(S, 16, b, np.arange(b.n))
+    assert np.array_equal(S, ri.init)
+    assert not WS.any()
+    assert np.array_equal(res, ri.init[b.idx])
+    assert _bits_to_set(RS, (1 << 16) // 16) == set(np.unique(b.idx // 16).tolist())
+
+
+@pytest.mark.parametrize("G", [1, 3, 64])
+def test_oplist_bitmaps_are_access_sets(orc, G):
+    ri = wl.c1()
+    S = ri.init.copy()
+    b = ri.batch
+    res, RS, WS = orc.replay_oplist(S, G, b, np.random.default_rng(G).permutation(b.n))
+    ng = (ri.n_words + G - 1) // G
+    wmask = (np.arange(b.idx.shape[0]) - np.repeat(b.offsets[:-1], 4)) < np.repeat(b.n_writes, 4)
+    assert _bits_to_set(RS, ng) == set((b.idx // G).tolist())
+    assert _bits_to_set(WS, ng) == set((b.idx[wmask] // G).tolist())
+    assert not np.any(WS & ~RS)
+
+
+def test_oplist_duplicate_index(orc):
+    b = wl.OplistBatch(offsets=np.array([0, 3], np.uint32), idx=np.array([2, 2, 1], np.uint32),
+                       n_writes=np.array([2], np.uint8), tid=np.array([7], np.uint32))
+    S = np.array([0, 10, 20, 30], np.uint32)
+    res, _, _ = orc.replay_oplist(S, 1, b, np.array([0]))
+    assert res.tolist() == [20, 20, 10]
+    assert S.tolist() == [0, 10, 27, 30]
+
+
+def test_oplist_rejects_bad_input(orc):
+    b = wl.OplistBatch(offsets=np.array([0, 1], np.uint32), idx=np.array([9], np.uint32),
+                       n_writes=np.array([1], np.uint8), tid=np.array([1], np.uint32))
+    with pytest.raises(orc.OracleError):
+        orc.replay_oplist(np.zeros(4, np.uint32), 1, b, np.array([0]))
+    b.idx[0] = 1
+    with pytest.raises(orc.OracleError):      # order not a permutation
+        orc.replay_oplist(np.zeros(4, np.uint32), 1, b, np.array([1]))
+
+
+# ----------------------------------------------------------------- validation
+
+@pytest.mark.parametrize("variant", ["", "w"])
+def test_validate_granule1_is_set_intersection(orc, variant):
+    """At granule 1 validation is the exact intersection of the host write
+    set with the GPU's read-or-write set."""
+    ri = wl.c1(variant)
+    S = ri.init.copy()
+    _, RS, _ = orc.replay_oplist(S, 1, ri.batch, np.arange(ri.batch.n))
+    flags, conflict = orc.validate(ri.log, RS, 1, ri.n_words)
+    expect = np.isin(ri.log["word"], ri.batch.idx)
+    got = np.unpackbits(flags.view(np.uint8), bitorder="little")[: ri.log.shape[0]].astype(bool)
+    assert np.array_equal(got, expect)
+    assert conflict == int(expect.any())
+    assert 1500 < expect.sum() < 3000     # about 22% of 10,000 entries
+
+
+def test_validate_granule_monotone(orc):
+    ri = wl.c1()
+    prev = None
+    for G in [1, 2, 4, 8, 16, 64]:
+        S = ri.init.copy()
+        _, RS, _ = orc.replay_oplist(S, G, ri.batch, np.arange(ri.batch.n))
+        flags, _ = orc.validate(ri.log, RS, G, ri.n_words)
+        if prev is not None:
+            assert not np.any(prev & ~flags)
+        prev = flags
+    # at granule 64 every granule of the 2^16 words is read: all entries conflict
+    n = ri.log.shape[0]
+    assert np.unpackbits(prev.view(np.uint8), bitorder="little")[:n].all()
+
+
+def test_validate_partitioned_commits(orc):
+    ri = wl.c1("p")
+    S = ri.init.copy()
+    _, RS, _ = orc.replay_oplist(S, ri.granule, ri.batch, np.arange(ri.batch.n))
+    flags, conflict = orc.validate(ri.log, RS, ri.granule, ri.n_words)
+    assert conflict == 0 and not flags.any()
+
+
+# ----------------------------------------------------------------- apply
+
+def _lww(S0, log, TS0=None):
+    """Last-writer-wins by key via a stable lexsort: among entries fresher
+    than TS0[word], the one with the largest timestamp sets the word."""
+    S = S0.copy()
+    w, v, ts = log["word"].astype(np.int64), log["value"], log["ts"]
+    keep = np.ones(w.shape[0], bool) if TS0 is None else ts > TS0[w]
+    w, v, ts = w[keep], v[keep], ts[keep]
+    o = np.lexsort((ts, w))
+    last = np.r_[w[o][1:] != w[o][:-1], True]
+    S[w[o][last]] = v[o][last]
+    return S
+
+
+def test_apply_is_last_writer_wins(orc):
+    g = np.random.default_rng(3)
+    N = 1000
+    log = wl.host_log_uniform(g, 5000, 0, N, 100)
+    S0 = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    S, TS = S0.copy(), np.zeros(N, np.uint64)
+    mx = orc.apply(S, TS, log, 100)
+    assert mx == 5100
+    assert np.array_equal(S, _lww(S0, log))
+    tsmax = np.zeros(N, np.uint64)
+    np.maximum.at(tsmax, log["word"].astype(np.int64), log["ts"])
+    assert np.array_equal(TS, tsmax)
+
+
+def test_apply_order_independent(orc):
+    g = np.random.default_rng(4)
+    N = 512
+    log = wl.host_log_uniform(g, 3000, 0, N, 0)
+    S0 = np.zeros(N, np.uint32)
+    ref = S0.copy()
+    orc.apply(ref, np.zeros(N, np.uint64), log, 0)
+    for s in range(3):
+        S = S0.copy()
+        orc.apply(S, np.zeros(N, np.uint64), log[np.random.default_rng(s).permutation(log.shape[0])], 0)
+        assert np.array_equal(S, ref)
+
+
+def test_apply_freshness_against_existing_ts(orc):
+    """An entry older than the word's TS entry is not applied (the freshness
+    test of the validation kernel)."""
+    g = np.random.default_rng(5)
+    N = 256
+    log = wl.host_log_uniform(g, 600, 0, N, 0)
+    TS0 = g.integers(0, 700, size=N, dtype=np.uint64)
+    # keep the ordering precondition: no entry's ts may equal TS0 of its word
+    log = log[log["ts"] != TS0[log["word"].astype(np.int64)]]   # keep ts distinct per word
+    S0 = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    S, TS = S0.copy(), TS0.copy()
+    orc.apply(S, TS, log, 0)
+    assert np.array_equal(S, _lww(S0, log, TS0))
+    assert np.all(TS >= TS0)
+
+
+def test_apply_preconditions(orc):
+    N = 16
+    S, TS = np.arange(N, dtype=np.uint32), np.zeros(N, np.uint64)
+    bad_word = _mk_log([(1, 5, 11), (16, 5, 12)])
+    assert orc.apply_rc(S, TS, bad_word, 10) == orc.EINVAL
+    stale = _mk_log([(1, 5, 11), (2, 5, 10)])
+    assert orc.apply_rc(S, TS, stale, 10) == orc.EORDER
+    huge = _mk_log([(1, 5, 11), (2, 5, 1 << 63)])
+    assert orc.apply_rc(S, TS, huge, 10) == orc.EORDER
+    assert np.array_equal(S, np.arange(N)) and not TS.any()     # nothing applied
+    dup = _mk_log([(3, 5, 20), (3, 6, 20)])
+    assert orc.apply_rc(S, TS, dup, 10) == orc.EORDER
+
+
+def test_apply_word64_log(orc):
+    log = np.zeros(3, orc.LOG8)
+    log["word"], log["value"], log["ts"] = [2, 2, 0], [2 ** 40, 7, 2 ** 63 - 1], [5, 4, 9]
+    S, TS = np.zeros(4, np.int64), np.zeros(4, np.uint64)
+    orc.apply(S, TS, log, 0)
+    assert S.view(np.uint64).tolist() == [2 ** 63 - 1, 0, 2 ** 40, 0]
+
+
+# ----------------------------------------------------------------- merge
+
+@pytest.mark.parametrize("G,N", [(1, 100), (7, 100), (64, 1000), (16, 16)])
+def test_merge_is_stream_compaction(orc, G, N):
+    g = np.random.default_rng(G * N)
+    ng = (N + G - 1) // G
+    bits = g.random(ng) < 0.3
+    WS = np.zeros((ng + 31) // 32, np.uint32)
+    WS.view(np.uint8)[: (ng + 7) // 8] = np.packbits(bits, bitorder="little")
+    S = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    H = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    for conflict in (0, 1):
+        s, h = S.copy(), H.copy()
+        ids, runs = orc.merge(conflict, WS, G, s, h)
+        assert np.array_equal(ids, np.flatnonzero(bits))
+        starts = bits & ~np.r_[False, bits[:-1]]
+        assert runs == int(starts.sum())
+        word_dirty = np.repeat(bits, G)[:N]
+        src, dst0 = (S, H) if conflict == 0 else (H, S)
+        out = h if conflict == 0 else s
+        other = s if conflict == 0 else h
+        assert np.array_equal(out[word_dirty], src[word_dirty])
+        assert np.array_equal(out[~word_dirty], dst0[~word_dirty])
+        assert np.array_equal(other, src)
+
+
+# ----------------------------------------------------------------- whole round
+
+@pytest.mark.parametrize("variant", ["", "w", "p"])
+def test_round_replicas_equal(orc, variant):
+    ri = wl.c1(variant)
+    S, H, TS = ri.init.copy(), ri.init.copy(), np.zeros(ri.n_words, np.uint64)
+    out = orc.round_oplist(S, H, TS, ri.granule, ri.batch, np.arange(ri.batch.n), ri.log, 0)
+    assert np.array_equal(S, H)
+    assert out["conflict"] == (0 if variant == "p" else 1)
+    if out["conflict"]:
+        # the GPU's effects are undone: the replicas hold S0 plus the host log
+        assert np.array_equal(S, _lww(ri.init, ri.log))
+
+
+def test_round_success_is_serial_cpu_then_gpu(orc):
+    """On success the final state equals the serial execution T^CPU -> T^GPU:
+    host log in timestamp order, then the GPU batch in its commit order."""
+    ri = wl.c1("p")
+    order = np.random.default_rng(9).permutation(ri.batch.n)
+    S, H, TS = ri.init.copy(), ri.init.copy(), np.zeros(ri.n_words, np.uint64)
+    out = orc.round_oplist(S, H, TS, ri.granule, ri.batch, order, ri.log, 0)
+    assert out["conflict"] == 0
+    serial = _lww(ri.init, ri.log)
+    res2, _, _ = orc.replay_oplist(serial, ri.granule, ri.batch, order)
+    assert np.array_equal(S, serial) and np.array_equal(H, serial)
+    assert np.array_equal(res2, out["results"])
+
+
+# ----------------------------------------------------------------- transfer
+
+def test_transfer_conservation_and_nonnegative(orc):
+    d = wl.c3(n_accounts=1 << 14, host_accounts=1 << 8, n_txn=20000, n_host=100)
+    S = d["init"].copy()
+    b = d["batch"]
+    order = np.random.default_rng(0).permutation(b.n)
+    res, RS, WS = orc.replay_transfer(S, 8, b, order)
+    assert int(S.sum()) == 1000 * (1 << 14)
+    assert S.min() >= 0
+    applied = res[2 * b.n:]
+    assert np.all(applied[res[:b.n] < b.amt.astype(np.int64)] == 0)
+    # balances read before an applied transfer cover the amount
+    assert np.all(res[:b.n][applied == 1] >= b.amt[applied == 1])
+
+
+@pytest.mark.parametrize("a,B", [(7, 100), (7, 70)])
+def test_transfer_chain_closed_form(orc, a, B):
+    """k transfers 0 -> 1 of amount a from balance B: the first floor(B/a)
+    apply (the last of them with exactly a left when a divides B), the rest
+    do not; the i-th reads B - i*a (while applied)."""
+    k = 50
+    b = wl.TransferBatch(src=np.zeros(k, np.uint32), dst=np.ones(k, np.uint32),
+                         amt=np.full(k, a, np.uint32))
+    S = np.array([B, 0, 0], np.int64)
+    res, _, WS = orc.replay_transfer(S, 1, b, np.arange(k))
+    m = B // a
+    assert res[2 * k:].tolist() == [1] * m + [0] * (k - m)
+    assert res[:k].tolist() == [B - i * a for i in range(m)] + [B - m * a] * (k - m)
+    assert S.tolist() == [B - m * a, m * a, 0]
+    same = wl.TransferBatch(src=np.array([2], np.uint32), dst=np.array([2], np.uint32),
+                            amt=np.array([1], np.uint32))
+    S2 = np.array([5, 5, 5], np.int64)
+    res2, _, WS2 = orc.replay_transfer(S2, 1, same, np.array([0]))
+    assert res2[2] == 0 and not WS2.any() and S2.tolist() == [5, 5, 5]
+
+
+def test_host_transfers_log_replays(orc):
+    d = wl.c3(n_accounts=1 << 12, host_accounts=1 << 8, n_txn=10, n_host=3000)
+    H = d["init"].copy()
+    log = orc.host_transfers(H, d["host"], 500)
+    assert int(H.sum()) == 1000 * (1 << 12)
+    S = d["init"].copy()
+    orc.apply(S, np.zeros(S.shape[0], np.uint64), log, 500)
+    assert np.array_equal(S, H)
+
+
+# ----------------------------------------------------------------- cache
+
+def test_splitmix64_published_vector(orc):
+    """splitmix64 from state 0 first returns 0xe220a8397b1dcdaf: the
+    finalizer applied to the golden-ratio increment."""
+    assert orc.mix64(0x9E3779B97F4A7C15) == 0xE220A8397B1DCDAF
+    assert orc.mix64(2 * 0x9E3779B97F4A7C15 % 2 ** 64) == 0x6E789E6AA1B965F4
+
+
+def _check_cache_invariants(orc, S, nsets):
+    sets = S.reshape(nsets, 128)
+    keys = sets[:, 0:16].reshape(nsets, 8, 2).astype(np.uint64)
+    keys = keys[:, :, 0] | (keys[:, :, 1] << np.uint64(32))
+    vals = sets[:, 32:96].reshape(nsets, 8, 8)
+    n_full = 0
+    for s in range(nsets):
+        ks = keys[s][keys[s] != 0]
+        assert len(set(ks.tolist())) == ks.shape[0], "duplicate key in a set"
+        for w in range(8):
+            k = int(keys[s, w])
+            if k == 0:
+                continue
+            n_full += 1
+            assert orc.cache_set(k, nsets) == s
+            chk = np.uint32(orc.mix64(k) & 0xFFFFFFFF)
+            assert (np.bitwise_xor.reduce(vals[s, w, :7]) ^ chk) == vals[s, w, 7], "torn entry"
+    return n_full
+
+
+def test_cache_invariants_and_get_after_put(orc):
+    nsets = 64
+    N = nsets * 128
+    g = np.random.default_rng(6)
+    n = 3000
+    keys = g.integers(1, 400, size=n, dtype=np.uint64)
+    ops = (g.random(n) < 0.5).astype(np.uint8)
+    b = wl.CacheBatch(key=keys, op=ops, tid=(np.arange(n) + 1).astype(np.uint32))
+    S = np.zeros(N, np.uint32)
+    res, RS, WS = orc.replay_cache(S, 4, b, np.arange(n))
+    assert _check_cache_invariants(orc, S, nsets) > 0
+    assert not np.any(WS & ~RS)
+    r = res.reshape(n, 9)
+    last_put = {}
+    for t in range(n):
+        k = int(keys[t])
+        if ops[t] == 1:
+            last_put[k] = t
+            assert (r[t, 0] & 0x200) and np.array_equal(r[t, 1:], orc.cache_value(k, t + 1))
+        elif r[t, 0] & 0x100:
+            # a hit returns the value of the latest PUT of the key
+            assert k in last_put
+            assert np.array_equal(r[t, 1:], orc.cache_value(k, int(b.tid[last_put[k]])))
+
+
+def test_cache_lru_eviction_hand_example(orc):
+    """Fill one set with 8 keys (stamps 1..8), GET the first (stamp 9); a 9th
+    key then evicts the way with the smallest stamp: the second key's."""
+    nsets = 4
+    same = [k for k in range(2, 4000, 2) if orc.cache_set(k, nsets) == 0][:9]
+    keys = np.array(same[:8] + [same[0]] + [same[8]], np.uint64)
+    ops = np.array([1] * 8 + [0, 1], np.uint8)
+    b = wl.CacheBatch(key=keys, op=ops, tid=np.arange(1, 11, dtype=np.uint32))
+    S = np.zeros(nsets * 128, np.uint32)
+    res, _, _ = orc.replay_cache(S, 1, b, np.arange(10))
+    r = res.reshape(10, 9)
+    assert [int(x) & 0x2FF for x in r[:8, 0]] == [0x200 | w for w in range(8)]
+    assert r[8, 0] == 0x100
+    assert r[9, 0] == 0x200 | 1
+    assert S[16:24].tolist() == [9, 10, 3, 4, 5, 6, 7, 8]
+    assert S[24] == 10
+    key1 = int(S[2]) | (int(S[3]) << 32)
+    assert key1 == same[8]
+
+
+def test_host_cache_puts_log_replays(orc):
+    nsets = 32
+    N = nsets * 128
+    H = np.zeros(N, np.uint32)
+    keys = np.random.default_rng(7).integers(1, 300, size=500, dtype=np.uint64) | np.uint64(1)
+    log = orc.host_cache_puts(H, keys, 1000)
+    assert log.shape[0] == 12 * 500
+    S = np.zeros(N, np.uint32)
+    orc.apply(S, np.zeros(N, np.uint64), log, 1000)
+    assert np.array_equal(S, H)
+    assert np.all(np.array([orc.cache_set(int(k), nsets) for k in keys]) % 2 == 1)
