@@ -1,0 +1,262 @@
+/*
+ * hetm.h -- C ABI of libhetm, the GPU side of one Speculative HeTM (SHeTM)
+ * synchronization round on an AMD Instinct MI355X (gfx950).
+ *
+ * Paper: D. Castro, P. Romano, A. Ilic, A. M. Khan, "HeTM: Transactional
+ * Memory for Heterogeneous Systems" (arXiv:1905.00661).
+ *
+ * A round (§IV-C) has three phases:
+ *   execution  -- batches of GPU transactions run speculatively against the
+ *                 GPU's replica of the shared region (STMR); each committed
+ *                 transaction marks its read and written granules in the
+ *                 read-set and write-set bitmaps (§IV-B, GPU instrumentation);
+ *   validation -- the host's write log of <word, value, timestamp> entries
+ *                 (§IV-B, CPU instrumentation) is checked against the
+ *                 read-set bitmap and always applied to the GPU replica under
+ *                 the per-word timestamp freshness rule (§IV-C.2);
+ *   merge      -- the write-set granules are copied GPU->host on success, or
+ *                 host->GPU on conflict (§IV-C.3; CPU-wins policy, §IV-E).
+ *
+ * Conventions for every call:
+ *   - Pointers named "device" must be device memory or pinned host memory
+ *     (hipHostMalloc) of this context's GPU; "host" pointers are ordinary
+ *     host memory; "host-or-device" accepts either.  Sizes are in elements.
+ *   - The caller owns every buffer it passes; the library only borrows it
+ *     until the call's work has finished on the context's stream.  The
+ *     context owns all device state it allocates.
+ *   - Calls return HETM_OK (0) or a negative HETM_E* code and never throw.
+ *     Errors detected on the device (bad log entries, retry cap) are latched
+ *     and returned by the next call that synchronizes.  A failed call leaves
+ *     the context usable unless it returned HETM_EDEVICE.
+ *   - A context is driven by one host thread (the paper's GPU-controller
+ *     thread, §IV-A); calls on one context are not reentrant.  Work is
+ *     queued on the context's stream in call order.
+ */
+#ifndef HETM_H
+#define HETM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define HETM_OK          0
+#define HETM_EINVAL     (-1)  /* bad argument, or a log word outside the STMR   */
+#define HETM_ENOMEM     (-2)  /* device or pinned allocation failed             */
+#define HETM_EORDER     (-3)  /* log timestamp not above the watermark, >= 2^63,
+                                 or two entries carry one word's winning ts     */
+#define HETM_ECAPACITY  (-4)  /* batch or log larger than the context capacity  */
+#define HETM_EDEVICE    (-5)  /* a HIP runtime call failed                      */
+#define HETM_ERETRY     (-6)  /* a transaction exceeded the local retry cap     */
+#define HETM_ESTATE     (-7)  /* call out of round order                        */
+
+/* --------------------------------------------------------------- programs */
+/* Built-in transactional kernels (the paper's "transactional kernel",
+ * §IV-A: one kernel runs a whole batch of transactions of one type). */
+#define HETM_PROG_OPLIST   1u  /* word-list read / read-modify-write (§V-A)  */
+#define HETM_PROG_TRANSFER 2u  /* int64 bank transfer                         */
+#define HETM_PROG_CACHE    3u  /* 8-way set-associative object cache (§V-D)  */
+
+/* ------------------------------------------------------------------ modes */
+#define HETM_MODE_PLAIN 0u  /* one launch per round step, host reads the outcome */
+#define HETM_MODE_GRAPH 1u  /* whole round replayed as one captured hipGraph,
+                               outcome decided on the device                    */
+
+/* Pass as `conflict` to hetm_copyback_dirty to use the outcome the device
+ * accumulated during validation instead of a host-supplied one. */
+#define HETM_OUTCOME_DEVICE 0xFFFFFFFFu
+
+typedef struct hetm_ctx hetm_ctx;
+
+typedef struct {
+    uint64_t n_words;            /* N: STMR size in words, 1 <= N <= 2^32        */
+    uint32_t word_bytes;         /* W: 4 (OPLIST, CACHE) or 8 (TRANSFER)         */
+    uint32_t granule_words;      /* G: words per bitmap bit, >= 1                */
+    uint32_t lock_stripe_words;  /* S: words per lock, power of two, >= 1        */
+    uint32_t max_txn_ops;        /* longest OPLIST transaction, 1..64            */
+    uint64_t batch_capacity;     /* most transactions per hetm_submit_batch      */
+    uint64_t log_capacity;       /* most log entries per hetm_validate_apply_log */
+    uint32_t mode;               /* HETM_MODE_*                                  */
+    int32_t  device;             /* HIP device ordinal                           */
+    void    *stream;             /* hipStream_t for all work; NULL = a stream the
+                                    library creates (default priority)          */
+    uint32_t exec_workgroups;    /* transaction-kernel workgroups; 0 = auto      */
+    uint32_t retry_cap;          /* local attempts per transaction; 0 = 1<<20    */
+} hetm_config;
+
+/* One host log entry (§IV-B, CPU instrumentation): the word a committed
+ * host transaction updated, its new value and a timestamp that totally
+ * orders the updates of that word.  W = 4 uses hetm_log_entry4 (16 bytes),
+ * W = 8 uses hetm_log_entry8 (24 bytes). */
+typedef struct { uint32_t word; uint32_t value; uint64_t ts; } hetm_log_entry4;
+typedef struct { uint32_t word; uint32_t pad; uint64_t value; uint64_t ts; } hetm_log_entry8;
+
+/* Batch descriptors: a host struct of device pointers, one per program.
+ *
+ * OPLIST: transaction i reads words idx[offsets[i] .. offsets[i+1]) in
+ * order, then writes each of its first n_writes[i] words with
+ * (value read + tid[i]) mod 2^32.  1 <= length <= max_txn_ops,
+ * n_writes[i] <= length.  Results: uint32 per op, results[offsets[i]+j] is
+ * the value read by op j.
+ *
+ * TRANSFER: reads accounts src[i] and dst[i]; if src != dst and the source
+ * balance is >= amt[i], moves amt[i] from src to dst.  Results: int64
+ * [3 * n]: results[i] = source balance read, results[n+i] = destination
+ * balance read, results[2n+i] = 1 if applied else 0.
+ *
+ * CACHE: op[i] = 0 GET or 1 PUT of key[i] (nonzero) by tid[i].  STMR
+ * layout: one 128-word record per set (N/128 sets, a power of two >= 2):
+ * words 0..15 keys of ways 0..7 (u64, low word first, 0 = empty), 16..23
+ * LRU stamps, 24 set PUT stamp, 32..95 values (8 words per way, word 7 a
+ * checksum).  set(key) = (splitmix64-finalizer(key) mod nsets) with the low
+ * bit replaced by the key's low bit.  Results: uint32 [9 * n]: status
+ * (GET hit 0x100|way, GET miss 0, PUT 0x200|(0x100 if key present)|way)
+ * then the 8 value words read or written.
+ */
+typedef struct {
+    const uint32_t *offsets;   /* [n + 1] */
+    const uint32_t *idx;       /* [offsets[n]] word indices < N */
+    const uint8_t  *n_writes;  /* [n] */
+    const uint32_t *tid;       /* [n] value added by the writes */
+} hetm_oplist_desc;
+
+typedef struct {
+    const uint32_t *src;       /* [n] account indices < N */
+    const uint32_t *dst;       /* [n] */
+    const uint32_t *amt;       /* [n] */
+} hetm_transfer_desc;
+
+typedef struct {
+    const uint64_t *key;       /* [n] nonzero */
+    const uint8_t  *op;        /* [n] 0 GET, 1 PUT */
+    const uint32_t *tid;       /* [n] LRU stamp / value seed */
+} hetm_cache_desc;
+
+/* ------------------------------------------------------------- lifecycle */
+
+/* Allocates the GPU replica of the STMR (N words of W bytes), its lock table
+ * (one u64 per S words: bit 63 lock, bits 0..62 version), the per-word
+ * timestamp array TS (u64, zeroed; §IV-C.2), the read-set and write-set
+ * granule bitmaps (N/G bits each, §IV-B) and round scratch, all in HBM and
+ * outside the STMR, so merges may overwrite the STMR non-transactionally
+ * (§IV-B, additional assumptions).  init_image (host-or-device, N*W bytes,
+ * NULL = zeros) becomes the replica.  The watermark starts at 0.
+ * Errors: EINVAL (bad config), ENOMEM, EDEVICE. */
+int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **out);
+
+/* Waits for outstanding work and releases everything the context owns. */
+int hetm_free(hetm_ctx *ctx);
+
+/* ------------------------------------------------------------- the round */
+
+/* Execution phase (§IV-C.1): runs n_txns transactions of `program` against
+ * the GPU replica with the library's GPU TM (versioned lock table, local
+ * conflicts only, retry until local commit) and marks the committed
+ * attempts' read and written granules in the bitmaps.  descs points to the
+ * program's descriptor struct (host struct, device arrays).  results
+ * (device) and tickets (device, uint32 [n]) receive each transaction's
+ * values and its commit ticket: ascending tickets give a serial order that
+ * explains every result (gaps allowed).  Results stay speculative until the
+ * round's outcome is known (§III).  Asynchronous; may be called several
+ * times per round.  Errors: EINVAL, ECAPACITY (n > batch_capacity),
+ * ESTATE (after validation started in this round); ERETRY latched. */
+int hetm_submit_batch(hetm_ctx *ctx, uint32_t program, const void *descs, uint64_t n_txns,
+                      void *results, uint32_t *tickets);
+
+/* Validation phase (§IV-C.2) for one chunk of the host log (host-or-device,
+ * n entries of the context's entry type, n <= log_capacity).  Entry k is
+ * flagged iff the granule of its word is set in the read-set bitmap; flags
+ * accumulate into the round outcome.  The chunk is then applied even if it
+ * conflicts: word w takes the value of the entry with the largest ts among
+ * those fresher than TS[w], and TS[w] that ts.  Preconditions: word < N
+ * (else EINVAL) and watermark < ts < 2^63 (else EORDER), checked on the
+ * device before anything of the chunk is applied; a chunk failing them
+ * applies nothing.  Two entries (in any chunks of the round) carrying one
+ * word's winning ts give EORDER and leave that word unspecified.
+ * flags_bits (device, nullable, ceil(n/32) uint32) receives bit k = flag k.
+ * conflict_out (host, nullable): if given, the call synchronizes and
+ * stores the round outcome so far (0/1), returning any latched error. */
+int hetm_validate_apply_log(hetm_ctx *ctx, const void *log, uint64_t n, uint32_t *flags_bits,
+                            uint32_t *conflict_out);
+
+/* Merge phase (§IV-C.3) and round end.  conflict: 0 success, 1 conflict,
+ * or HETM_OUTCOME_DEVICE.  On success the write-set granules are copied
+ * GPU->host_replica, on conflict host_replica->GPU (undoing the GPU
+ * transactions, CPU-wins, §IV-E); either way the replicas agree on return.
+ * Contiguous dirty granules are found by a prefix sum over the write-set
+ * bitmap.  host_replica: pinned host memory (hipHostMalloc), N*W bytes,
+ * holding the host's state with its own writes of this round.
+ * n_dirty_out (host, nullable; synchronizes), ids_out (device, nullable,
+ * ceil(N/G) uint32: ascending dirty granule ids).  Then clears the
+ * bitmaps and raises the watermark to the largest ts applied.
+ * Errors: EINVAL, ESTATE, latched device errors when synchronizing. */
+int hetm_copyback_dirty(hetm_ctx *ctx, uint32_t conflict, void *host_replica, uint64_t *n_dirty_out,
+                        uint32_t *ids_out);
+
+typedef struct {
+    uint32_t    program;       /* HETM_PROG_* */
+    const void *descs;         /* as hetm_submit_batch */
+    uint64_t    n_txns;
+    void       *results;       /* device */
+    uint32_t   *tickets;       /* device */
+    const void *log;           /* device (log entries resident in HBM) or host */
+    uint64_t    n_log;         /* <= log_capacity */
+    uint32_t   *flags_bits;    /* device, nullable */
+    void       *host_replica;  /* pinned host, N*W bytes */
+    uint32_t   *ids_out;       /* device, nullable */
+} hetm_round_args;
+
+typedef struct {
+    uint32_t conflict;         /* 1: GPU transactions of the round aborted      */
+    int32_t  error;            /* latched device error, HETM_OK if none         */
+    uint64_t n_committed;      /* transactions committed by the round           */
+    uint64_t n_aborted;        /* transactions discarded by the round           */
+    uint64_t n_local_retries;  /* attempts beyond the first (local conflicts)   */
+    uint64_t n_dirty;          /* write-set granules merged                     */
+    uint64_t n_runs;           /* maximal runs of consecutive dirty granules    */
+    uint64_t max_ts;           /* watermark after the round                     */
+    double   us_exec;          /* step times from HIP events (PLAIN mode)       */
+    double   us_validate;
+    double   us_merge;
+    double   us_total;
+} hetm_round_result;
+
+/* A whole round: execution, validation+apply, merge, reset, in the
+ * context's mode.  PLAIN launches one kernel per step and reads the
+ * outcome on the host before the merge; GRAPH replays one captured hipGraph
+ * whose merge kernels read the outcome on the device.  Synchronizes and
+ * fills *res.  On conflict every transaction of the round is reported
+ * aborted and the caller may resubmit it. */
+int hetm_round(hetm_ctx *ctx, const hetm_round_args *args, hetm_round_result *res);
+
+/* ------------------------------------------------------------- auxiliary */
+
+const char *hetm_strerror(int code);
+const char *hetm_last_error(hetm_ctx *ctx);   /* detail of the last failure */
+int hetm_sync(hetm_ctx *ctx);                 /* waits; returns a latched error */
+
+typedef struct {
+    uint64_t rounds, rounds_conflicted, txns_committed, txns_aborted, local_retries;
+    uint64_t log_entries, dirty_granules, watermark;
+    uint64_t device_bytes;     /* HBM the context allocated */
+} hetm_stats;
+int hetm_stats_get(hetm_ctx *ctx, hetm_stats *out);
+
+/* Copies context state out (synchronizes).  what: 0 STMR (N*W bytes),
+ * 1 TS (N u64), 2 read-set bitmap, 3 write-set bitmap (ceil(ceil(N/G)/32)
+ * u32 each), 4 lock table.  dst host-or-device, bytes = its size. */
+#define HETM_STATE_STMR 0u
+#define HETM_STATE_TS   1u
+#define HETM_STATE_RS   2u
+#define HETM_STATE_WS   3u
+#define HETM_STATE_LOCKS 4u
+int hetm_read_state(hetm_ctx *ctx, uint32_t what, void *dst, uint64_t bytes);
+uint64_t hetm_state_bytes(hetm_ctx *ctx, uint32_t what);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HETM_H */

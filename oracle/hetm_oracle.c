@@ -349,15 +349,25 @@ int orc_validate(const void *log, int W, uint64_t n, const uint32_t *RS, uint64_
 /*
  * Apply (§IV-C.2): the whole log is applied, also after a conflict.  Entries
  * arrive in arbitrary order, so an entry overwrites word w only if its
- * timestamp is fresher than TS[w]; TS[w] then takes that timestamp.
- * Timestamps totally order the updates of one word (§IV-B), so two entries
- * with the same word and timestamp are an ordering error.
+ * timestamp is fresher than TS[w]; TS[w] then takes that timestamp.  The
+ * outcome is the entry with the largest timestamp per word.
+ *
+ * Timestamps must totally order the updates of one word (§IV-B), so the
+ * result is undetermined when a word's winning timestamp is carried by two
+ * or more entries -- of this chunk, or of this chunk and an earlier chunk
+ * of the same round.  That case returns -3 after the apply; ties below a
+ * word's winning timestamp do not change the result and pass.
  *
  * Preconditions, checked before anything is applied: word < N (else -1) and
  * floor < ts < 2^63 (else -3), where floor is the largest timestamp applied
- * in earlier rounds.  A duplicate (word, ts) pair returns -3 after the
- * entries before it were applied.  *max_ts receives the largest ts seen.
+ * in earlier rounds.  *max_ts receives the largest ts seen.
  */
+static int cmp_u64_pair(const void *a, const void *b)
+{
+    const uint64_t *x = a, *y = b;
+    return x[0] < y[0] ? -1 : x[0] > y[0] ? 1 : 0;
+}
+
 int orc_apply(void *S, int W, uint64_t *TS, uint64_t N, const void *log, uint64_t n,
               uint64_t floor, uint64_t *max_ts)
 {
@@ -368,19 +378,39 @@ int orc_apply(void *S, int W, uint64_t *TS, uint64_t N, const void *log, uint64_
         uint64_t ts = entry_ts(log, W, k);
         if (ts <= floor || ts >= TS_LIMIT) return ORC_EORDER;
     }
+    uint64_t *before = malloc((n ? n : 1) * sizeof(uint64_t));
+    if (!before) return ORC_EINVAL;
+    for (uint64_t k = 0; k < n; k++) before[k] = TS[entry_word(log, W, k)];
     uint64_t mx = floor;
     for (uint64_t k = 0; k < n; k++) {
         uint64_t w = entry_word(log, W, k), ts = entry_ts(log, W, k);
         if (ts > mx) mx = ts;
-        if (ts == TS[w]) return ORC_EORDER;
-        if (ts > TS[w]) {
+        if (ts > TS[w]) {                      /* freshness test */
             if (W == 4) ((uint32_t *)S)[w] = ((const orc_entry4 *)log)[k].value;
             else        ((uint64_t *)S)[w] = ((const orc_entry8 *)log)[k].value;
             TS[w] = ts;
         }
     }
+    /* ties at a word's winning timestamp: the winners of this chunk sorted
+     * by word must be distinct, and none may equal a winner of an earlier
+     * chunk (its timestamp already in TS before this chunk) */
+    int rc = ORC_OK;
+    uint64_t *win = malloc((n ? n : 1) * sizeof(uint64_t));
+    uint64_t nwin = 0;
+    if (!win) { free(before); return ORC_EINVAL; }
+    for (uint64_t k = 0; k < n; k++) {
+        uint64_t w = entry_word(log, W, k), ts = entry_ts(log, W, k);
+        if (ts != TS[w]) continue;
+        if (before[k] == ts) rc = ORC_EORDER;
+        win[nwin++] = w;
+    }
+    qsort(win, nwin, sizeof(uint64_t), cmp_u64_pair);
+    for (uint64_t i = 1; i < nwin; i++)
+        if (win[i] == win[i - 1]) rc = ORC_EORDER;
+    free(win);
+    free(before);
     if (max_ts) *max_ts = mx;
-    return ORC_OK;
+    return rc;
 }
 
 /* -------------------------------------------------------------- merge */

@@ -1,0 +1,161 @@
+// hetm_dev.h -- device-side state, argument blocks and CDNA wavefront helpers
+// shared by the libhetm kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hetm.h"
+
+namespace hetm {
+
+constexpr uint64_t kLockBit = 1ull << 63;   // lock-table word: bit 63 lock, 0..62 version
+constexpr uint64_t kTsLimit = 1ull << 63;   // host timestamps must stay below
+constexpr int kWave = 64;
+constexpr int kExecWaves = 4;               // waves per transaction-kernel workgroup
+constexpr int kOplistMaxWrites = 8;         // LDS write-buffer slots per lane (OPLIST)
+constexpr int kCacheMaxWrites = 12;         // a PUT writes key(2) + value(8) + stamp + set stamp
+constexpr uint32_t kNoTxn = 0xFFFFFFFFu;
+constexpr uint32_t kDoneTxn = 0xFFFFFFFEu;
+
+// Counters the kernels update during a round (device memory).
+struct DevCounters {
+    uint32_t conflict;          // OR of the validation flags of the round
+    int32_t error;              // first latched error code (HETM_E*), 0 if none
+    uint32_t ticket;            // next commit ticket
+    uint32_t queue_head;        // next transaction of the current batch
+    unsigned long long max_ts;  // largest ts seen in this round's log chunks
+    unsigned long long floor_ts;  // watermark: largest ts applied by earlier rounds
+    unsigned long long committed; // local commits in this round
+    unsigned long long retries;   // local aborts in this round
+    uint32_t n_dirty;           // write-set granules found by the compaction
+    uint32_t n_runs;            // maximal runs of consecutive dirty granules
+    uint32_t retry_txn;         // first transaction that hit the retry cap
+    uint32_t scan_ticket;       // blocks finished in the compaction count pass
+    uint32_t err_index;         // index of the first bad log entry
+    uint32_t pad_;
+};
+
+// Everything a kernel needs: constant context state plus the arguments of
+// the current call.  Lives in device memory; kernels receive its address.
+struct DevArgs {
+    // ---- context (set once)
+    void *stmr;
+    uint64_t *locks;
+    uint64_t *ts;
+    uint32_t *rs;
+    uint32_t *ws;
+    uint32_t *suspect;      // one bit per staged log entry (apply pass 1 -> 2)
+    uint32_t *blocksums;    // compaction: per-block dirty counts, then offsets
+    uint32_t *blockruns;
+    uint32_t *ids_scratch;  // ceil(N/G) dirty granule ids
+    DevCounters *cnt;
+    uint64_t n_words;
+    uint32_t word_bytes;
+    uint32_t granule;       // G
+    uint32_t stripe_shift;  // log2(S)
+    uint32_t n_granules;    // ceil(N/G)
+    uint32_t n_bm_words;    // ceil(n_granules / 32)
+    uint32_t retry_cap;
+    uint32_t max_ops;
+    uint32_t n_scan_blocks;
+    // ---- current call
+    uint32_t program;
+    uint32_t n_txns;
+    const uint32_t *off;    // OPLIST
+    const uint32_t *idx;
+    const uint8_t *nw;
+    const uint32_t *tid;    // OPLIST, CACHE
+    const uint32_t *src;    // TRANSFER
+    const uint32_t *dst;
+    const uint32_t *amt;
+    const uint64_t *key;    // CACHE
+    const uint8_t *op;
+    void *results;
+    uint32_t *tickets;
+    const void *log;        // device-resident log chunk
+    uint32_t n_log;
+    uint32_t *flags;        // nullable
+    void *host;             // merge target (pinned host, device-mapped)
+    uint32_t *ids_out;      // nullable
+    uint32_t outcome;       // 0 / 1 / HETM_OUTCOME_DEVICE
+    uint32_t pad_;
+};
+
+// ------------------------------------------------------------------ atomics
+// All transactional data (STMR words, lock words) is accessed with
+// agent-scope atomics, which gfx950 serves at the device coherence point
+// (the per-XCD L2s are not coherent with each other).
+
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_agent(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_agent(uint64_t *p, uint64_t expect, uint64_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acq_rel() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent"); }
+
+__device__ __forceinline__ void latch_error(DevCounters *c, int32_t code, uint32_t where) {
+    int32_t zero = 0;
+    if (__hip_atomic_compare_exchange_strong(&c->error, &zero, code, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+        st_agent(&c->err_index, where);
+}
+
+// ---------------------------------------------------------------- wavefront
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// One atomic add per wavefront: lanes with `want` receive consecutive
+// values in lane order.  Must be reached by all 64 lanes.
+__device__ __forceinline__ uint32_t wave_fetch_add(uint32_t *ctr, bool want) {
+    uint64_t m = __ballot(want);
+    uint32_t base = 0;
+    if (m) {
+        int leader = __ffsll((unsigned long long)m) - 1;
+        if ((int)lane_id() == leader)
+            base = __hip_atomic_fetch_add(ctr, (uint32_t)__popcll(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        base = __shfl(base, leader);
+    }
+    return base + lanes_below(m);
+}
+
+// Sets bit g of an agent-visible bitmap; skips the atomic when the bit is
+// already visible as set (bits only go 0 -> 1 within a round).
+__device__ __forceinline__ void bitmap_set(uint32_t *bm, uint32_t g) {
+    uint32_t w = g >> 5, b = 1u << (g & 31);
+    uint32_t cur = __hip_atomic_load(bm + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (!(cur & b)) __hip_atomic_fetch_or(bm + w, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t div_granule(uint64_t w, uint32_t G) { return (uint32_t)(w / G); }
+
+// ------------------------------------------------------------- launchers
+// Host-side launch wrappers, one per kernel family (defined next to the
+// kernels).  `a` is the device address of the DevArgs block.
+void launch_set_args(const DevArgs &host_copy, DevArgs *dev, hipStream_t s);
+void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, hipStream_t s);
+void launch_validate(const DevArgs *a, uint32_t max_log, hipStream_t s);
+void launch_apply(const DevArgs *a, uint32_t max_log, hipStream_t s);
+void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s);
+void launch_copy(const DevArgs *a, uint32_t n_granules, uint32_t granule, uint32_t word_bytes, hipStream_t s);
+void launch_reset(const DevArgs *a, uint32_t n_bm_words, hipStream_t s);
+void launch_begin_round(const DevArgs *a, hipStream_t s);
+uint32_t exec_max_workgroups(uint32_t program);
+
+constexpr uint32_t kScanWordsPerBlock = 2048;   // bitmap words per compaction block
+constexpr uint32_t kScanThreads = 256;
+
+}  // namespace hetm

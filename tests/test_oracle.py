@@ -273,6 +273,25 @@ def test_apply_preconditions(orc):
     assert orc.apply_rc(S, TS, dup, 10) == orc.EORDER
 
 
+def test_apply_ties_only_matter_at_the_winner(orc):
+    """A duplicate (word, ts) below the word's largest ts leaves the result
+    determined and passes; a duplicate at the winner is an ordering error,
+    also across two chunks of one round."""
+    N = 8
+    for perm in ([0, 1, 2], [2, 0, 1], [1, 2, 0]):
+        S, TS = np.zeros(N, np.uint32), np.zeros(N, np.uint64)
+        log = _mk_log([(3, 5, 20), (3, 6, 20), (3, 7, 30)])[perm]
+        assert orc.apply_rc(S, TS, log, 10) == orc.OK
+        assert S[3] == 7 and TS[3] == 30
+    S, TS = np.zeros(N, np.uint32), np.zeros(N, np.uint64)
+    assert orc.apply_rc(S, TS, _mk_log([(3, 5, 20), (4, 1, 21)]), 10) == orc.OK
+    assert orc.apply_rc(S, TS, _mk_log([(3, 6, 20)]), 10) == orc.EORDER      # ties chunk 1's winner
+    S, TS = np.zeros(N, np.uint32), np.zeros(N, np.uint64)
+    assert orc.apply_rc(S, TS, _mk_log([(3, 5, 20)]), 10) == orc.OK
+    assert orc.apply_rc(S, TS, _mk_log([(3, 6, 20), (3, 9, 25)]), 10) == orc.OK   # superseded tie
+    assert S[3] == 9
+
+
 def test_apply_word64_log(orc):
     log = np.zeros(3, orc.LOG8)
     log["word"], log["value"], log["ts"] = [2, 2, 0], [2 ** 40, 7, 2 ** 63 - 1], [5, 4, 9]
