@@ -1,0 +1,206 @@
+"""Benchmark: whole SHeTM rounds (GPU side) on one MI355X.
+
+Workload (the large synthetic STMR configuration): 2^28 u32 words (1 GiB),
+batches of 2^20 GPU transactions (90% read-only with 16 reads, 10% update
+with 4 read-modify-writes), 1% hot set drawing 50% of the accesses, a host
+log of 2^20 entries per round in the host-owned half, granule 16 words.
+
+A step is one whole round: execution of the batch, validation + apply of the
+log, dirty-granule compaction, merge copy into the pinned host replica and
+reset.  Inputs (descriptors, per-round logs) are resident in HBM before the
+timed region.  The headline form replays the round as one captured hipGraph;
+the plain form (one launch per step, host reads the outcome) is timed beside
+it and provides per-kernel event timings for the roofline.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def exec_alg_bytes(batch) -> float:
+    """Algorithmic bytes the execution kernel must move for a batch (per
+    transaction: offsets 8 B, n_writes 1 B, tid 4 B, ticket 4 B; per read:
+    index 4 B, lock word read twice 16 B, value 4 B, result 4 B; per write:
+    lock load 8 B, lock CAS 16 B, value 4 B, unlock 16 B)."""
+    L = np.diff(batch.offsets.astype(np.int64))
+    nw = batch.n_writes.astype(np.int64)
+    return float(batch.n * 17 + L.sum() * 28 + nw.sum() * 44)
+
+
+VALIDATE_APPLY_BYTES_PER_ENTRY = 40.0   # 16 B entry + 4 B bitmap + 8+8 B TS + 4 B value
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1905_00661_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1905_00661_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM traffic per launch from committed rocprofv3 counter runs, only if
+    they were taken on the current kernel sources."""
+    p = os.path.join(PROFILES, "traffic.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2-words", type=int, default=28)
+    ap.add_argument("--log2-txns", type=int, default=20)
+    ap.add_argument("--log2-log", type=int, default=20)
+    ap.add_argument("--granule", type=int, default=16)
+    ap.add_argument("--p-hot", type=float, default=0.5)
+    ap.add_argument("--stripe", type=int, default=1)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1905_00661_amd import hetm as hm
+    from paper_1905_00661_amd import workloads as wl
+
+    N, n_txn, n_log = 1 << args.log2_words, 1 << args.log2_txns, 1 << args.log2_log
+    G = args.granule
+    t0 = time.time()
+    ri = wl.c2(n_words=N, n_txn=n_txn, n_log=n_log, p_hot=args.p_hot, granule=G)
+    log(f"inputs generated in {time.time() - t0:.1f}s")
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    rounds = args.warmup + args.steps
+
+    # per-round logs resident in HBM: same words/values, timestamps shifted
+    base_log = hm.to_device(ri.log, dev)
+    logs = []
+    for r in range(rounds + 1):
+        t = base_log.clone()
+        ts = t.view(torch.int64).view(-1, 2)[:, 1]
+        ts.add_(r * n_log)
+        logs.append(t)
+    torch.cuda.synchronize()
+
+    host = hm.pinned(N * 4)
+    host.numpy()[:] = ri.init.view(np.uint8)
+
+    def run(mode: int, k_steps: int, warm: int):
+        ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=n_txn,
+                         log_capacity=n_log, mode=mode)
+        b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
+        flags = torch.zeros(((n_log + 31) // 32) * 4, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        res = []
+        for r in range(warm):
+            ctx.round(b, logs[r], n_log, host, flags)
+        torch.cuda.synchronize()
+        lat = []
+        t_start = time.perf_counter()
+        for r in range(warm, warm + k_steps):
+            t1 = time.perf_counter()
+            rr = ctx.round(b, logs[r], n_log, host, flags)
+            lat.append(time.perf_counter() - t1)
+            res.append(rr.as_dict())
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        tickets = b.tickets_np().copy()
+        ctx.close()
+        return elapsed, lat, res, tickets
+
+    log("graph form ...")
+    el_g, lat_g, res_g, tickets = run(hm.HETM_MODE_GRAPH, args.steps, args.warmup)
+    committed = sum(r["n_committed"] for r in res_g)
+    value = committed / el_g
+    out = {
+        "metric": "committed txns/s + validate/apply GB/s vs HBM peak; p50/p99 commit latency",
+        "value": value, "unit": "txn/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * el_g / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"large synthetic STMR: 2^{args.log2_words} u32 words, 2^{args.log2_txns} txns/batch "
+                               f"(90% RO x16 reads, 10% 4RMW), hot 1% at p={args.p_hot}, host log "
+                               f"2^{args.log2_log}, granule {G}, lock stripe {args.stripe}",
+                   "form": "graph"},
+        "p50_commit_latency_ms": 1e3 * float(np.percentile(lat_g, 50)),
+        "p99_commit_latency_ms": 1e3 * float(np.percentile(lat_g, 99)),
+        "conflict_rounds": sum(r["conflict"] for r in res_g),
+        "local_retries_per_round": float(np.mean([r["n_local_retries"] for r in res_g])),
+        "dirty_granules_per_round": float(np.mean([r["n_dirty"] for r in res_g])),
+    }
+
+    if not args.no_plain:
+        log("plain form ...")
+        el_p, lat_p, res_p, _ = run(hm.HETM_MODE_PLAIN, args.steps, args.warmup)
+        us = {k: float(np.mean([r[k] for r in res_p])) for k in ("us_exec", "us_validate", "us_merge", "us_total")}
+        out["plain"] = {"value": sum(r["n_committed"] for r in res_p) / el_p, "ms_per_step": 1e3 * el_p / args.steps,
+                        "p50_commit_latency_ms": 1e3 * float(np.percentile(lat_p, 50)),
+                        "p99_commit_latency_ms": 1e3 * float(np.percentile(lat_p, 99)), **us}
+        va_bytes = VALIDATE_APPLY_BYTES_PER_ENTRY * n_log
+        out["validate_apply"] = {"achieved_GBps": va_bytes / (us["us_validate"] * 1e-6) / 1e9,
+                                 "frac_of_hbm_peak": va_bytes / (us["us_validate"] * 1e-6) / 1e9 / HBM_PEAK_GBPS,
+                                 "bytes_per_entry": VALIDATE_APPLY_BYTES_PER_ENTRY}
+        steps_us = {"exec": us["us_exec"], "validate_apply": us["us_validate"], "merge": us["us_merge"]}
+        dominant = max(steps_us, key=steps_us.get)
+        if dominant == "exec":
+            alg = exec_alg_bytes(ri.batch)
+            kern = "k_exec_oplist"
+        elif dominant == "validate_apply":
+            alg = va_bytes
+            kern = "k_validate+k_apply"
+        else:
+            alg = 2.0 * out["dirty_granules_per_round"] * G * 4
+            kern = "k_compact+k_copy"
+        ach = alg / (steps_us[dominant] * 1e-6) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": kern, "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBPS, "traffic": load_traffic(kern),
+                           "alg_bytes_per_launch": alg, "avg_launch_us": steps_us[dominant]}
+
+    if not args.no_cpu:
+        import oracle as orc
+        log("cpu baseline (oracle, one round) ...")
+        S, H = ri.init.copy(), ri.init.copy()
+        TS = np.zeros(N, np.uint64)
+        order = orc.order_from_tickets(tickets)
+        t1 = time.perf_counter()
+        o = orc.round_oplist(S, H, TS, G, ri.batch, order, ri.log, 0)
+        el_c = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": ri.batch.n / el_c if not o["conflict"] else 0.0, "unit": "txn/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one full round of the same workload ({ri.batch.n} txns, {n_log} log "
+                                         f"entries) replayed by the single-threaded C oracle: {el_c:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -207,19 +207,21 @@ def host_cache_puts(H: np.ndarray, keys: np.ndarray, ts0: int) -> np.ndarray:
 
 # ---------------------------------------------------------------- whole round
 
-def round_oplist(S: np.ndarray, H: np.ndarray, TS: np.ndarray, G: int, batch, order, log,
-                 floor: int, host_TS: np.ndarray | None = None) -> dict:
-    """One full round for OPLIST (§IV-C): replay, validate, apply, host-side
-    apply of the same log (the host already holds its own writes), merge.
-    S, H, TS are updated in place."""
-    res, RS, WS = replay_oplist(S, G, batch, order)
+def round_generic(replay, S: np.ndarray, H: np.ndarray, TS: np.ndarray, G: int, batch, order, log,
+                  floor: int) -> dict:
+    """One full round (§IV-C): replay the batch in commit order, validate the
+    host log, apply it, merge.  H is the host replica holding the host's own
+    writes of the round.  S, H, TS are updated in place."""
+    res, RS, WS = replay(S, G, batch, order)
     flags, conflict = validate(log, RS, G, S.shape[0])
     mx = apply(S, TS, log, floor)
-    hts = np.zeros(H.shape[0], np.uint64) if host_TS is None else host_TS
-    apply(H, hts, log, floor)
     ids, runs = merge(conflict, WS, G, S, H)
     return {"results": res, "RS": RS, "WS": WS, "flags": flags, "conflict": conflict,
             "ids": ids, "n_runs": runs, "max_ts": mx}
+
+
+def round_oplist(S, H, TS, G, batch, order, log, floor) -> dict:
+    return round_generic(replay_oplist, S, H, TS, G, batch, order, log, floor)
 
 
 def order_from_tickets(tickets: np.ndarray) -> np.ndarray:

@@ -1,0 +1,580 @@
+// api.hip -- the libhetm C ABI: context lifecycle and the orchestration of a
+// SHeTM round (§IV-C) on one GPU, in two forms:
+//   PLAIN -- one launch per round step; the host (the paper's GPU-controller
+//            thread, §IV-A) reads the validation outcome before the merge;
+//   GRAPH -- the whole round (argument upload, execution, validation + apply,
+//            compaction, merge copy, reset, result download) is captured once
+//            as a hipGraph and replayed; the merge reads the outcome on the
+//            device, so a round costs one graph launch and one wait.
+// Kernels take their arguments from a device-resident DevArgs block, so one
+// captured graph serves rounds whose buffers differ.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "hetm.h"
+#include "hetm_dev.h"
+
+using namespace hetm;
+
+struct hetm_ctx {
+    hetm_config cfg{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    uint32_t exec_wg = 0;
+    uint32_t log_entry_bytes = 16;
+
+    // device state
+    void *stmr = nullptr;
+    uint64_t *locks = nullptr;
+    uint64_t *ts = nullptr;
+    uint32_t *rs = nullptr, *ws = nullptr, *suspect = nullptr;
+    uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;
+    void *log_staging = nullptr;
+    DevCounters *cnt = nullptr;
+    DevCounters *snap_dev = nullptr;
+    DevArgs *dargs = nullptr;
+    uint64_t device_bytes = 0;
+
+    // pinned host mirrors
+    DevArgs *hargs = nullptr;        // argument block uploaded by the graph
+    DevCounters *snap_host = nullptr;
+    DevCounters *cnt_host = nullptr;
+
+    DevArgs args{};                  // host copy of the current arguments
+    hipEvent_t ev[4] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint32_t graph_program = 0;
+
+    bool in_validation = false;      // this round's log has started
+    hetm_stats stats{};
+    char err[512] = {0};
+};
+
+namespace {
+
+int fail(hetm_ctx *c, int code, const char *fmt, ...) {
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof c->err, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIP_TRY(c, call)                                                                       \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return fail((c), HETM_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+int dev_alloc(hetm_ctx *c, T **p, uint64_t bytes) {
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) return fail(c, HETM_ENOMEM, "hipMalloc(%llu) failed: %s", (unsigned long long)bytes,
+                                     hipGetErrorString(e));
+    c->device_bytes += bytes;
+    return HETM_OK;
+}
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+uint32_t ilog2(uint64_t x) {
+    uint32_t r = 0;
+    while ((1ull << r) < x) ++r;
+    return r;
+}
+
+// Device-visible address of a host-or-device pointer: device and pinned
+// memory are used in place; anything else gets nullptr.
+const void *device_view(const void *p) {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged) return p;
+    if (at.type == hipMemoryTypeHost) return at.devicePointer ? at.devicePointer : p;
+    return nullptr;
+}
+
+int push_args(hetm_ctx *c) {
+    launch_set_args(c->args, c->dargs, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HETM_OK;
+}
+
+int read_counters(hetm_ctx *c, DevCounters *out) {
+    HIP_TRY(c, hipMemcpyAsync(c->cnt_host, c->cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *out = *c->cnt_host;
+    return HETM_OK;
+}
+
+// Returns a latched device error (and clears it so the context stays usable).
+int take_device_error(hetm_ctx *c, int32_t code, uint32_t where) {
+    if (code == HETM_OK) return HETM_OK;
+    launch_clear_error(c->cnt, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    return fail(c, code, "device reported %s at index %u", hetm_strerror(code), where);
+}
+
+int set_batch_args(hetm_ctx *c, uint32_t program, const void *descs, uint64_t n, void *results, uint32_t *tickets) {
+    if (!descs || !results || !tickets) return fail(c, HETM_EINVAL, "null batch argument");
+    if (n > c->cfg.batch_capacity) return fail(c, HETM_ECAPACITY, "batch of %llu > capacity", (unsigned long long)n);
+    DevArgs &a = c->args;
+    a.program = program;
+    a.n_txns = (uint32_t)n;
+    a.results = results;
+    a.tickets = tickets;
+    if (program == HETM_PROG_OPLIST) {
+        if (c->cfg.word_bytes != 4) return fail(c, HETM_EINVAL, "OPLIST needs 4-byte words");
+        const hetm_oplist_desc *d = (const hetm_oplist_desc *)descs;
+        if (!d->offsets || !d->idx || !d->n_writes || !d->tid) return fail(c, HETM_EINVAL, "null OPLIST array");
+        a.off = d->offsets, a.idx = d->idx, a.nw = d->n_writes, a.tid = d->tid;
+    } else if (program == HETM_PROG_TRANSFER) {
+        if (c->cfg.word_bytes != 8) return fail(c, HETM_EINVAL, "TRANSFER needs 8-byte words");
+        const hetm_transfer_desc *d = (const hetm_transfer_desc *)descs;
+        if (!d->src || !d->dst || !d->amt) return fail(c, HETM_EINVAL, "null TRANSFER array");
+        a.src = d->src, a.dst = d->dst, a.amt = d->amt;
+    } else if (program == HETM_PROG_CACHE) {
+        if (c->cfg.word_bytes != 4) return fail(c, HETM_EINVAL, "CACHE needs 4-byte words");
+        uint64_t nsets = c->cfg.n_words / 128;
+        if (c->cfg.n_words % 128 || nsets < 2 || !is_pow2(nsets))
+            return fail(c, HETM_EINVAL, "CACHE needs N = 128 * 2^k words");
+        const hetm_cache_desc *d = (const hetm_cache_desc *)descs;
+        if (!d->key || !d->op || !d->tid) return fail(c, HETM_EINVAL, "null CACHE array");
+        a.key = d->key, a.op = d->op, a.tid = d->tid;
+    } else {
+        return fail(c, HETM_EINVAL, "unknown program %u", program);
+    }
+    return HETM_OK;
+}
+
+// Places a log chunk where the kernels can read it: device and pinned
+// memory in place, pageable host memory through the staging buffer.
+int stage_log(hetm_ctx *c, const void *log, uint64_t n, const void **dev_log) {
+    const void *v = device_view(log);
+    if (v) {
+        *dev_log = v;
+        return HETM_OK;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->log_staging, log, n * c->log_entry_bytes, hipMemcpyHostToDevice, c->stream));
+    *dev_log = c->log_staging;
+    return HETM_OK;
+}
+
+int enqueue_validate(hetm_ctx *c, const void *dev_log, uint64_t n, uint32_t *flags) {
+    c->args.log = dev_log;
+    c->args.n_log = (uint32_t)n;
+    c->args.flags = flags;
+    int rc = push_args(c);
+    if (rc) return rc;
+    launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, c->stream);
+    launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HETM_OK;
+}
+
+int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t *ids_out) {
+    c->args.outcome = outcome;
+    c->args.host = const_cast<void *>(host_dev);
+    c->args.ids_out = ids_out;
+    int rc = push_args(c);
+    if (rc) return rc;
+    launch_compact(c->dargs, c->args.n_scan_blocks, c->stream);
+    launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->stream);
+    launch_finish(c->dargs, c->snap_dev, c->args.n_bm_words, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream));
+    return HETM_OK;
+}
+
+void account_round(hetm_ctx *c, const DevCounters &s, uint64_t n_txns, hetm_round_result *res) {
+    c->stats.rounds++;
+    if (s.conflict) {
+        c->stats.rounds_conflicted++;
+        c->stats.txns_aborted += s.committed;
+    } else {
+        c->stats.txns_committed += s.committed;
+    }
+    c->stats.local_retries += s.retries;
+    c->stats.dirty_granules += s.n_dirty;
+    c->stats.watermark = s.floor_ts;
+    if (res) {
+        res->conflict = s.conflict;
+        res->error = s.error;
+        res->n_committed = s.conflict ? 0 : s.committed;
+        res->n_aborted = s.conflict ? n_txns : 0;
+        res->n_local_retries = s.retries;
+        res->n_dirty = s.n_dirty;
+        res->n_runs = s.n_runs;
+        res->max_ts = s.floor_ts;
+    }
+}
+
+int check_host_replica(hetm_ctx *c, void *host, const void **dev) {
+    if (!host) return fail(c, HETM_EINVAL, "null host replica");
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, host) != hipSuccess || at.type != hipMemoryTypeHost) {
+        (void)hipGetLastError();
+        return fail(c, HETM_EINVAL, "host replica must be pinned host memory (hipHostMalloc)");
+    }
+    *dev = at.devicePointer ? at.devicePointer : host;
+    return HETM_OK;
+}
+
+int build_graph(hetm_ctx *c) {
+    if (c->graph_exec) return HETM_OK;
+    hipStream_t s = c->stream;
+    HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    (void)hipMemcpyAsync(c->dargs, c->hargs, sizeof(DevArgs), hipMemcpyHostToDevice, s);
+    launch_exec(c->args.program, c->dargs, c->exec_wg, s);
+    launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
+    launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
+    launch_compact(c->dargs, c->args.n_scan_blocks, s);
+    launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
+    launch_finish(c->dargs, c->snap_dev, c->args.n_bm_words, s);
+    (void)hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) return fail(c, HETM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(c, HETM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    c->graph = g;
+    return HETM_OK;
+}
+
+float elapsed_us(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.f;
+    }
+    return ms * 1000.f;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hetm_strerror(int code) {
+    switch (code) {
+    case HETM_OK: return "ok";
+    case HETM_EINVAL: return "invalid argument";
+    case HETM_ENOMEM: return "out of memory";
+    case HETM_EORDER: return "timestamp order violated";
+    case HETM_ECAPACITY: return "capacity exceeded";
+    case HETM_EDEVICE: return "HIP runtime error";
+    case HETM_ERETRY: return "transaction exceeded the local retry cap";
+    case HETM_ESTATE: return "call out of round order";
+    default: return "unknown error";
+    }
+}
+
+const char *hetm_last_error(hetm_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+
+int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **out) {
+    if (!cfg || !out) return HETM_EINVAL;
+    *out = nullptr;
+    const hetm_config &k = *cfg;
+    if (k.n_words == 0 || k.n_words > (1ull << 32) || (k.word_bytes != 4 && k.word_bytes != 8) ||
+        k.granule_words == 0 || !is_pow2(k.lock_stripe_words) || k.max_txn_ops == 0 || k.max_txn_ops > 64 ||
+        k.batch_capacity == 0 || k.batch_capacity >= (1ull << 32) || k.log_capacity == 0 ||
+        k.log_capacity >= (1ull << 32) || k.mode > HETM_MODE_GRAPH)
+        return HETM_EINVAL;
+    hetm_ctx *c = new (std::nothrow) hetm_ctx();
+    if (!c) return HETM_ENOMEM;
+    c->cfg = k;
+    if (c->cfg.retry_cap == 0) c->cfg.retry_cap = 1u << 20;
+    c->device = k.device;
+    c->log_entry_bytes = k.word_bytes == 4 ? sizeof(hetm_log_entry4) : sizeof(hetm_log_entry8);
+    int rc = HETM_OK;
+#define TRY(x)                      \
+    do {                            \
+        rc = (x);                   \
+        if (rc) {                   \
+            hetm_free(c);           \
+            return rc;              \
+        }                           \
+    } while (0)
+    if (hipSetDevice(k.device) != hipSuccess) {
+        delete c;
+        return HETM_EDEVICE;
+    }
+    if (k.stream) {
+        c->stream = (hipStream_t)k.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return HETM_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    const uint64_t N = k.n_words, G = k.granule_words;
+    const uint64_t nG = (N + G - 1) / G;
+    const uint64_t nbw = (nG + 31) / 32;
+    const uint64_t nblocks = (nbw + kScanWordsPerBlock - 1) / kScanWordsPerBlock;
+    const uint64_t nlocks = (N + k.lock_stripe_words - 1) / k.lock_stripe_words;
+    TRY(dev_alloc(c, &c->stmr, N * k.word_bytes));
+    TRY(dev_alloc(c, &c->locks, nlocks * 8));
+    TRY(dev_alloc(c, &c->ts, N * 8));
+    TRY(dev_alloc(c, &c->rs, nbw * 4));
+    TRY(dev_alloc(c, &c->ws, nbw * 4));
+    TRY(dev_alloc(c, &c->suspect, ((k.log_capacity + 63) / 64) * 8));
+    TRY(dev_alloc(c, &c->blocksums, nblocks * 4));
+    TRY(dev_alloc(c, &c->blockruns, nblocks * 4));
+    TRY(dev_alloc(c, &c->ids, nG * 4));
+    TRY(dev_alloc(c, &c->log_staging, k.log_capacity * c->log_entry_bytes));
+    TRY(dev_alloc(c, &c->cnt, sizeof(DevCounters)));
+    TRY(dev_alloc(c, &c->snap_dev, sizeof(DevCounters)));
+    TRY(dev_alloc(c, &c->dargs, sizeof(DevArgs)));
+    if (hipHostMalloc((void **)&c->hargs, sizeof(DevArgs), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->snap_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->cnt_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess) {
+        hetm_free(c);
+        return HETM_ENOMEM;
+    }
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            hetm_free(c);
+            return HETM_EDEVICE;
+        }
+    hipStream_t s = c->stream;
+    bool ok = hipMemsetAsync(c->locks, 0, nlocks * 8, s) == hipSuccess &&
+              hipMemsetAsync(c->ts, 0, N * 8, s) == hipSuccess &&
+              hipMemsetAsync(c->rs, 0, nbw * 4, s) == hipSuccess &&
+              hipMemsetAsync(c->ws, 0, nbw * 4, s) == hipSuccess &&
+              hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), s) == hipSuccess &&
+              hipMemsetAsync(c->blocksums, 0, nblocks * 4, s) == hipSuccess;
+    if (ok)
+        ok = init_image ? hipMemcpyAsync(c->stmr, init_image, N * k.word_bytes, hipMemcpyDefault, s) == hipSuccess
+                        : hipMemsetAsync(c->stmr, 0, N * k.word_bytes, s) == hipSuccess;
+    if (!ok || hipStreamSynchronize(s) != hipSuccess) {
+        hetm_free(c);
+        return HETM_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, k.device) == hipSuccess) cus = prop.multiProcessorCount;
+    c->exec_wg = k.exec_workgroups ? k.exec_workgroups : (uint32_t)cus * exec_workgroups_per_cu(HETM_PROG_OPLIST);
+
+    DevArgs &a = c->args;
+    a.stmr = c->stmr, a.locks = c->locks, a.ts = c->ts, a.rs = c->rs, a.ws = c->ws;
+    a.suspect = c->suspect, a.blocksums = c->blocksums, a.blockruns = c->blockruns, a.ids_scratch = c->ids;
+    a.cnt = c->cnt;
+    a.n_words = N, a.word_bytes = k.word_bytes, a.granule = (uint32_t)G;
+    a.stripe_shift = ilog2(k.lock_stripe_words);
+    a.n_granules = (uint32_t)nG, a.n_bm_words = (uint32_t)nbw, a.retry_cap = c->cfg.retry_cap;
+    a.max_ops = k.max_txn_ops, a.n_scan_blocks = (uint32_t)nblocks;
+    a.outcome = HETM_OUTCOME_DEVICE;
+    c->stats.device_bytes = c->device_bytes;
+    *out = c;
+    return HETM_OK;
+#undef TRY
+}
+
+int hetm_free(hetm_ctx *c) {
+    if (!c) return HETM_EINVAL;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->suspect, c->blocksums, c->blockruns,
+                   c->ids, c->log_staging, c->cnt, c->snap_dev, c->dargs};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    if (c->hargs) (void)hipHostFree(c->hargs);
+    if (c->snap_host) (void)hipHostFree(c->snap_host);
+    if (c->cnt_host) (void)hipHostFree(c->cnt_host);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return HETM_OK;
+}
+
+int hetm_submit_batch(hetm_ctx *c, uint32_t program, const void *descs, uint64_t n_txns, void *results,
+                      uint32_t *tickets) {
+    if (!c) return HETM_EINVAL;
+    if (c->in_validation) return fail(c, HETM_ESTATE, "submit after validation started in this round");
+    if (n_txns == 0) return HETM_OK;
+    int rc = set_batch_args(c, program, descs, n_txns, results, tickets);
+    if (rc) return rc;
+    if ((rc = push_args(c))) return rc;
+    launch_exec(program, c->dargs, c->exec_wg, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HETM_OK;
+}
+
+int hetm_validate_apply_log(hetm_ctx *c, const void *log, uint64_t n, uint32_t *flags_bits, uint32_t *conflict_out) {
+    if (!c) return HETM_EINVAL;
+    if (n > c->cfg.log_capacity) return fail(c, HETM_ECAPACITY, "log chunk %llu > capacity", (unsigned long long)n);
+    if (n && !log) return fail(c, HETM_EINVAL, "null log");
+    c->in_validation = true;
+    if (n) {
+        const void *dlog = nullptr;
+        int rc = stage_log(c, log, n, &dlog);
+        if (rc) return rc;
+        if ((rc = enqueue_validate(c, dlog, n, flags_bits))) return rc;
+    }
+    if (conflict_out) {
+        DevCounters k;
+        int rc = read_counters(c, &k);
+        if (rc) return rc;
+        *conflict_out = k.conflict;
+        if (k.error) return take_device_error(c, k.error, k.err_index);
+    }
+    return HETM_OK;
+}
+
+int hetm_copyback_dirty(hetm_ctx *c, uint32_t conflict, void *host_replica, uint64_t *n_dirty_out,
+                        uint32_t *ids_out) {
+    if (!c) return HETM_EINVAL;
+    if (conflict > 1 && conflict != HETM_OUTCOME_DEVICE) return fail(c, HETM_EINVAL, "bad outcome %u", conflict);
+    const void *hdev = nullptr;
+    int rc = check_host_replica(c, host_replica, &hdev);
+    if (rc) return rc;
+    if ((rc = enqueue_merge(c, conflict, hdev, ids_out))) return rc;
+    c->in_validation = false;
+    if (n_dirty_out) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        const DevCounters s = *c->snap_host;
+        if (s.error) return take_device_error(c, s.error, s.err_index);
+        account_round(c, s, 0, nullptr);
+        *n_dirty_out = s.n_dirty;
+    }
+    return HETM_OK;
+}
+
+int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
+    if (!c || !r) return HETM_EINVAL;
+    if (res) memset(res, 0, sizeof *res);
+    if (c->in_validation) return fail(c, HETM_ESTATE, "hetm_round inside an open round");
+    if (r->n_log > c->cfg.log_capacity) return fail(c, HETM_ECAPACITY, "log %llu > capacity", (unsigned long long)r->n_log);
+    if (r->n_log && !r->log) return fail(c, HETM_EINVAL, "null log");
+    const void *hdev = nullptr;
+    int rc = check_host_replica(c, r->host_replica, &hdev);
+    if (rc) return rc;
+    if (r->n_txns) {
+        if ((rc = set_batch_args(c, r->program, r->descs, r->n_txns, r->results, r->tickets))) return rc;
+    } else {
+        c->args.n_txns = 0;
+    }
+    hipStream_t s = c->stream;
+    if (c->cfg.mode == HETM_MODE_GRAPH) {
+        if (r->n_txns == 0) c->args.program = c->args.program ? c->args.program : HETM_PROG_OPLIST;
+        const void *dlog = nullptr;
+        if (r->n_log && (rc = stage_log(c, r->log, r->n_log, &dlog))) return rc;
+        c->args.log = dlog;
+        c->args.n_log = (uint32_t)r->n_log;
+        c->args.flags = r->flags_bits;
+        c->args.outcome = HETM_OUTCOME_DEVICE;
+        c->args.host = const_cast<void *>(hdev);
+        c->args.ids_out = r->ids_out;
+        if (c->graph_exec && c->graph_program != c->args.program) {
+            (void)hipGraphExecDestroy(c->graph_exec);
+            (void)hipGraphDestroy(c->graph);
+            c->graph_exec = nullptr;
+            c->graph = nullptr;
+        }
+        if ((rc = build_graph(c))) return rc;
+        c->graph_program = c->args.program;
+        HIP_TRY(c, hipStreamSynchronize(s));   // the pinned argument block is free to overwrite
+        *c->hargs = c->args;
+        HIP_TRY(c, hipEventRecord(c->ev[0], s));
+        HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
+        HIP_TRY(c, hipEventRecord(c->ev[3], s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        const DevCounters snap = *c->snap_host;
+        if (snap.error) return take_device_error(c, snap.error, snap.err_index);
+        account_round(c, snap, r->n_txns, res);
+        if (res) res->us_total = elapsed_us(c->ev[0], c->ev[3]);
+        c->stats.log_entries += r->n_log;
+        return HETM_OK;
+    }
+    // PLAIN: one launch per step, outcome read on the host
+    HIP_TRY(c, hipEventRecord(c->ev[0], s));
+    if (r->n_txns) {
+        if ((rc = push_args(c))) return rc;
+        launch_exec(r->program, c->dargs, c->exec_wg, s);
+        HIP_TRY(c, hipGetLastError());
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[1], s));
+    if (r->n_log) {
+        const void *dlog = nullptr;
+        if ((rc = stage_log(c, r->log, r->n_log, &dlog))) return rc;
+        if ((rc = enqueue_validate(c, dlog, r->n_log, r->flags_bits))) return rc;
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[2], s));
+    DevCounters k;
+    if ((rc = read_counters(c, &k))) return rc;
+    if (k.error) return take_device_error(c, k.error, k.err_index);
+    if ((rc = enqueue_merge(c, k.conflict, hdev, r->ids_out))) return rc;
+    HIP_TRY(c, hipEventRecord(c->ev[3], s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const DevCounters snap = *c->snap_host;
+    if (snap.error) return take_device_error(c, snap.error, snap.err_index);
+    account_round(c, snap, r->n_txns, res);
+    c->stats.log_entries += r->n_log;
+    if (res) {
+        res->us_exec = elapsed_us(c->ev[0], c->ev[1]);
+        res->us_validate = elapsed_us(c->ev[1], c->ev[2]);
+        res->us_merge = elapsed_us(c->ev[2], c->ev[3]);
+        res->us_total = elapsed_us(c->ev[0], c->ev[3]);
+    }
+    return HETM_OK;
+}
+
+int hetm_sync(hetm_ctx *c) {
+    if (!c) return HETM_EINVAL;
+    DevCounters k;
+    int rc = read_counters(c, &k);
+    if (rc) return rc;
+    return take_device_error(c, k.error, k.err_index);
+}
+
+int hetm_stats_get(hetm_ctx *c, hetm_stats *out) {
+    if (!c || !out) return HETM_EINVAL;
+    *out = c->stats;
+    return HETM_OK;
+}
+
+uint64_t hetm_state_bytes(hetm_ctx *c, uint32_t what) {
+    if (!c) return 0;
+    const uint64_t N = c->cfg.n_words;
+    switch (what) {
+    case HETM_STATE_STMR: return N * c->cfg.word_bytes;
+    case HETM_STATE_TS: return N * 8;
+    case HETM_STATE_RS:
+    case HETM_STATE_WS: return (uint64_t)c->args.n_bm_words * 4;
+    case HETM_STATE_LOCKS: return ((N + c->cfg.lock_stripe_words - 1) / c->cfg.lock_stripe_words) * 8;
+    default: return 0;
+    }
+}
+
+int hetm_read_state(hetm_ctx *c, uint32_t what, void *dst, uint64_t bytes) {
+    if (!c || !dst) return HETM_EINVAL;
+    const void *src = what == HETM_STATE_STMR ? c->stmr
+                      : what == HETM_STATE_TS  ? (const void *)c->ts
+                      : what == HETM_STATE_RS  ? (const void *)c->rs
+                      : what == HETM_STATE_WS  ? (const void *)c->ws
+                      : what == HETM_STATE_LOCKS ? (const void *)c->locks
+                                                 : nullptr;
+    if (!src || bytes != hetm_state_bytes(c, what)) return fail(c, HETM_EINVAL, "bad state request");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(dst, src, bytes, hipMemcpyDefault));
+    return HETM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,520 @@
+// exec.hip -- execution phase (§IV-C.1): the GPU's local TM running a batch of
+// transactions against the GPU replica of the STMR, with the read-set and
+// write-set granule bitmaps of §IV-B updated by every committed transaction.
+//
+// Design (gfx950, wave64):
+//  * One transaction per lane.  A wave pulls work from a device queue with
+//    one atomic per refill, so finished or committed lanes take the next
+//    transaction while conflicting lanes retry (persistent kernel).
+//  * Lock table: one u64 per stripe of S words, bit 63 = lock, bits 0..62 =
+//    version.  Reads are a batched seqlock: load every read stripe's lock
+//    word, one acquire fence, load every value, so the number of fences per
+//    attempt does not grow with the transaction's length.  The read set is
+//    remembered as the sum of the versions seen (versions only grow, and a
+//    round commits fewer than 2^32 times, so equal sums mean equal versions).
+//  * Commit: try-lock each distinct write stripe with a 64-bit CAS (a lane
+//    never waits on a lock, so lanes of one wave cannot deadlock), take a
+//    commit ticket (one atomic per wave, lanes ranked by mbcnt), re-load the
+//    read stripes' lock words and compare with the first pass, write the
+//    LDS-staged write buffer, release with version+1.  A lock acquired before
+//    the ticket and a validation after it make ascending tickets a valid
+//    serial order for update and read-only transactions alike.
+//  * Bitmaps are set only by the committed attempt: the read-set bitmap gets
+//    every word read or written (writes included, so WS is within RS and the
+//    validation also excludes write-write conflicts, §IV-C.2).
+#include "hetm_dev.h"
+
+namespace hetm {
+
+namespace {
+
+// Per-lane write buffer staged in LDS, [slot][lane] so that the 64 lanes of a
+// wave touch 64 consecutive dwords per slot (no bank conflicts).
+template <typename Word, int MAXW>
+struct WriteBuf {
+    uint32_t (*addr)[kWave];
+    Word (*val)[kWave];
+    uint32_t lane;
+    uint32_t n;
+    uint32_t locked;   // slots whose stripe this lane holds
+
+    __device__ void put(uint32_t w, Word v) {
+        addr[n][lane] = w;
+        val[n][lane] = v;
+        ++n;
+    }
+    __device__ uint32_t at(uint32_t k) const { return addr[k][lane]; }
+
+    // Try-lock every distinct write stripe in ascending stripe order (so two
+    // lanes wanting the same stripes collide on the first one instead of each
+    // holding one of them in lockstep); on failure release what was taken.
+    __device__ bool lock_all(uint64_t *locks, uint32_t sh) {
+        locked = 0;
+        int64_t last = -1;
+        for (;;) {
+            uint32_t kmin = n;
+            uint32_t smin = 0;
+            for (uint32_t k = 0; k < n; ++k) {
+                const uint32_t s = at(k) >> sh;
+                if ((int64_t)s > last && (kmin == n || s < smin)) {
+                    kmin = k;
+                    smin = s;
+                }
+            }
+            if (kmin == n) return true;
+            uint64_t cur = ld_agent(&locks[smin]);
+            if ((cur & kLockBit) || !cas_agent(&locks[smin], cur, cur | kLockBit)) {
+                release(locks, sh, false);
+                return false;
+            }
+            locked |= 1u << kmin;
+            last = smin;
+        }
+    }
+    __device__ bool mine(uint32_t s, uint32_t sh) const {
+        for (uint32_t k = 0; k < n; ++k)
+            if (((locked >> k) & 1u) && (at(k) >> sh) == s) return true;
+        return false;
+    }
+    // commit: version+1 and unlock; abort: unlock with the version unchanged
+    __device__ void release(uint64_t *locks, uint32_t sh, bool commit) {
+        for (uint32_t k = 0; k < n; ++k) {
+            if (!((locked >> k) & 1u)) continue;
+            uint64_t *p = &locks[at(k) >> sh];
+            if (commit)
+                __hip_atomic_fetch_add(p, 1ull - kLockBit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                __hip_atomic_fetch_and(p, ~kLockBit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        locked = 0;
+    }
+    __device__ void write_back(Word *stmr) {
+        for (uint32_t k = 0; k < n; ++k) st_agent(&stmr[at(k)], val[k][lane]);
+    }
+    __device__ void mark_writes(uint32_t *rs, uint32_t *ws, uint32_t G) {
+        for (uint32_t k = 0; k < n; ++k) {
+            uint32_t g = div_granule(at(k), G);
+            bitmap_set(rs, g);
+            bitmap_set(ws, g);
+        }
+    }
+};
+
+// Revalidation of one read stripe after the ticket: returns the version to
+// add to the second sum, or sets ok = false if another transaction holds it.
+template <typename WB>
+__device__ __forceinline__ uint64_t reread(const uint64_t *locks, uint32_t s, uint32_t sh, const WB &wb,
+                                           bool &ok) {
+    uint64_t l = ld_agent(&locks[s]);
+    if (l & kLockBit) {
+        if (!wb.mine(s, sh)) ok = false;
+        l &= ~kLockBit;
+    }
+    return l;
+}
+
+// Per-lane bookkeeping of the persistent loop.
+struct LaneState {
+    uint32_t txn = kNoTxn;
+    uint32_t attempts = 0;
+    uint32_t wait = 0;      // loop iterations to sit out after a local abort
+    uint64_t commits = 0;
+    uint64_t retries = 0;
+};
+
+// Contention manager: after its k-th local abort a transaction sits out a
+// pseudo-random number of iterations below min(2^k, 64).  Lanes of one wave
+// run in lockstep, so two transactions that each write what the other read
+// would otherwise abort each other identically forever; the random wait
+// breaks the symmetry.
+__device__ __forceinline__ uint32_t backoff(uint32_t txn, uint32_t attempts) {
+    uint32_t h = txn * 0x9E3779B1u ^ attempts * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    const uint32_t window = attempts >= 6 ? 64u : (1u << attempts);
+    return h & (window - 1);
+}
+
+// Whether this lane runs an attempt in this iteration (it has a transaction
+// and is not backing off).
+__device__ __forceinline__ bool lane_turn(LaneState &ls, uint32_t n) {
+    if (ls.txn >= n) return false;
+    if (ls.wait) {
+        --ls.wait;
+        return false;
+    }
+    return true;
+}
+
+// Refill lanes without work from the device queue; returns false when the
+// whole wave is out of work.  Reached by all 64 lanes.
+__device__ __forceinline__ bool refill(LaneState &ls, DevCounters *cnt, uint32_t n) {
+    bool need = ls.txn == kNoTxn;
+    uint32_t got = wave_fetch_add(&cnt->queue_head, need);
+    if (need) {
+        ls.txn = got < n ? got : kDoneTxn;
+        ls.attempts = 0;
+    }
+    return __ballot(ls.txn < n) != 0;
+}
+
+// After an attempt: account, then free the lane on commit, retry cap, or a
+// malformed transaction (already latched as HETM_EINVAL, never executed).
+__device__ __forceinline__ void settle(LaneState &ls, bool act, bool malformed, bool ok, uint32_t ticket,
+                                       uint32_t *tickets, DevCounters *cnt, uint32_t retry_cap) {
+    if (malformed) {
+        ls.txn = kNoTxn;
+    } else if (ok) {
+        tickets[ls.txn] = ticket;
+        ls.commits++;
+        ls.txn = kNoTxn;
+    } else if (act) {
+        ls.retries++;
+        if (++ls.attempts >= retry_cap) {
+            latch_error(cnt, HETM_ERETRY, ls.txn);
+            ls.txn = kNoTxn;
+        } else {
+            ls.wait = backoff(ls.txn, ls.attempts);
+        }
+    }
+}
+
+__device__ __forceinline__ void flush_counts(const LaneState &ls, DevCounters *cnt) {
+    unsigned long long c = ls.commits, r = ls.retries;
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o);
+        r += __shfl_xor(r, o);
+    }
+    if (lane_id() == 0) {
+        if (c) __hip_atomic_fetch_add(&cnt->committed, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (r) __hip_atomic_fetch_add(&cnt->retries, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ------------------------------------------------------------------ OPLIST
+// Transaction i reads idx[off[i] .. off[i+1]) in order, then writes each of
+// its first nw[i] words with (value read + tid[i]) mod 2^32.
+__global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs *__restrict__ a) {
+    __shared__ uint32_t s_addr[kExecWaves][kOplistMaxWrites][kWave];
+    __shared__ uint32_t s_val[kExecWaves][kOplistMaxWrites][kWave];
+    const uint32_t wv = threadIdx.x / kWave;
+    uint32_t *stmr = (uint32_t *)a->stmr;
+    uint64_t *locks = a->locks;
+    uint32_t *rs = a->rs, *ws = a->ws;
+    DevCounters *cnt = a->cnt;
+    const uint32_t n = a->n_txns, sh = a->stripe_shift, G = a->granule, max_ops = a->max_ops;
+    const uint64_t N = a->n_words;
+    const uint32_t *off = a->off, *idx = a->idx, *tid = a->tid;
+    const uint8_t *nw = a->nw;
+    uint32_t *res = (uint32_t *)a->results;
+    WriteBuf<uint32_t, kOplistMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
+    LaneState ls;
+
+    while (refill(ls, cnt, n)) {
+        const bool act = lane_turn(ls, n);
+        if (!__ballot(act)) {          // every lane is backing off
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        uint32_t o = 0, L = 0, nwr = 0, tv = 0;
+        bool malformed = false;
+        if (act) {
+            o = off[ls.txn];
+            uint32_t e = off[ls.txn + 1];
+            nwr = nw[ls.txn];
+            tv = tid[ls.txn];
+            L = e - o;
+            malformed = e < o || L > max_ops || nwr > L || nwr > kOplistMaxWrites;
+            for (uint32_t j = 0; j < L && !malformed; ++j) malformed = idx[o + j] >= N;
+            if (malformed) {
+                latch_error(cnt, HETM_EINVAL, ls.txn);
+                L = 0;
+            }
+        }
+        bool ok = act && !malformed;
+        // first pass over the read stripes
+        uint64_t sum1 = 0;
+        for (uint32_t j = 0; j < L; ++j) {
+            uint64_t l = ld_agent(&locks[idx[o + j] >> sh]);
+            ok &= !(l & kLockBit);
+            sum1 += l;
+        }
+        fence_acquire();
+        wb.n = 0;
+        if (ok) {
+            for (uint32_t j = 0; j < L; ++j) {
+                uint32_t w = idx[o + j];
+                uint32_t v = ld_agent(&stmr[w]);
+                res[o + j] = v;
+                if (j < nwr) wb.put(w, v + tv);
+            }
+            if (nwr) ok = wb.lock_all(locks, sh);
+        }
+        fence_release();
+        uint32_t ticket = wave_fetch_add(&cnt->ticket, ok);
+        fence_acquire();
+        if (ok) {
+            uint64_t sum2 = 0;
+            for (uint32_t j = 0; j < L && ok; ++j) sum2 += reread(locks, idx[o + j] >> sh, sh, wb, ok);
+            ok &= sum2 == sum1;
+        }
+        if (ok) wb.write_back(stmr);
+        fence_release();
+        if (wb.locked) wb.release(locks, sh, ok);
+        if (ok) {
+            for (uint32_t j = nwr; j < L; ++j) bitmap_set(rs, div_granule(idx[o + j], G));
+            wb.mark_writes(rs, ws, G);
+        }
+        settle(ls, act, malformed, ok, ticket, a->tickets, cnt, a->retry_cap);
+    }
+    flush_counts(ls, cnt);
+}
+
+// ---------------------------------------------------------------- TRANSFER
+// Reads balances of src and dst (int64 words); if src != dst and the source
+// balance covers amt, moves amt.  Results: [bs | bd | applied] (3 x n int64).
+__global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevArgs *__restrict__ a) {
+    __shared__ uint32_t s_addr[kExecWaves][2][kWave];
+    __shared__ uint64_t s_val[kExecWaves][2][kWave];
+    const uint32_t wv = threadIdx.x / kWave;
+    uint64_t *stmr = (uint64_t *)a->stmr;
+    uint64_t *locks = a->locks;
+    uint32_t *rs = a->rs, *ws = a->ws;
+    DevCounters *cnt = a->cnt;
+    const uint32_t n = a->n_txns, sh = a->stripe_shift, G = a->granule;
+    const uint64_t N = a->n_words;
+    int64_t *res = (int64_t *)a->results;
+    WriteBuf<uint64_t, 2> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
+    LaneState ls;
+
+    while (refill(ls, cnt, n)) {
+        const bool act = lane_turn(ls, n);
+        if (!__ballot(act)) {          // every lane is backing off
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        bool ok = act;
+        uint32_t s = 0, d = 0, am = 0;
+        if (act) {
+            s = a->src[ls.txn];
+            d = a->dst[ls.txn];
+            am = a->amt[ls.txn];
+            if (s >= N || d >= N) {
+                latch_error(cnt, HETM_EINVAL, ls.txn);
+                ok = false;
+            }
+        }
+        uint64_t sum1 = 0;
+        if (ok) {
+            uint64_t l1 = ld_agent(&locks[s >> sh]);
+            uint64_t l2 = ld_agent(&locks[d >> sh]);
+            ok = !((l1 | l2) & kLockBit);
+            sum1 = l1 + l2;
+        }
+        fence_acquire();
+        wb.n = 0;
+        if (ok) {
+            int64_t bs = (int64_t)ld_agent(&stmr[s]);
+            int64_t bd = (int64_t)ld_agent(&stmr[d]);
+            bool applied = s != d && bs >= (int64_t)am;
+            res[ls.txn] = bs;
+            res[n + ls.txn] = bd;
+            res[2 * (uint64_t)n + ls.txn] = applied;
+            if (applied) {
+                wb.put(s, (uint64_t)(bs - (int64_t)am));
+                wb.put(d, (uint64_t)(bd + (int64_t)am));
+                ok = wb.lock_all(locks, sh);
+            }
+        }
+        fence_release();
+        uint32_t ticket = wave_fetch_add(&cnt->ticket, ok);
+        fence_acquire();
+        if (ok) {
+            uint64_t sum2 = reread(locks, s >> sh, sh, wb, ok);
+            sum2 += reread(locks, d >> sh, sh, wb, ok);
+            ok &= sum2 == sum1;
+        }
+        if (ok) wb.write_back(stmr);
+        fence_release();
+        if (wb.locked) wb.release(locks, sh, ok);
+        if (ok) {
+            bitmap_set(rs, div_granule(s, G));
+            bitmap_set(rs, div_granule(d, G));
+            wb.mark_writes(rs, ws, G);
+        }
+        settle(ls, act, act && (s >= N || d >= N), ok, ticket, a->tickets, cnt, a->retry_cap);
+    }
+    flush_counts(ls, cnt);
+}
+
+// ------------------------------------------------------------------- CACHE
+// 8-way set-associative cache in 32-bit words, one 128-word record per set:
+// keys at 0..15 (u64 per way, low word first), LRU stamps at 16..23, set PUT
+// stamp at 24, values at 32 + 8*way.  GET reads the set stamp and the keys;
+// on a hit it reads the value and writes the way's stamp := tid.  PUT also
+// reads the stamps, picks the way holding the key or else the smallest
+// stamp (lowest way on ties) and writes key, value, stamp and set stamp.
+constexpr uint32_t kSetWords = 128, kStampBase = 16, kSetStamp = 24, kValBase = 32;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {   // splitmix64 finalizer
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// j-th word of the header read list: 8 keys (16 words), set stamp, 8 stamps
+__device__ __forceinline__ uint32_t header_word(uint32_t j) {
+    return j < 16 ? j : (j == 16 ? kSetStamp : kStampBase + (j - 17));
+}
+
+__global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs *__restrict__ a) {
+    __shared__ uint32_t s_addr[kExecWaves][kCacheMaxWrites][kWave];
+    __shared__ uint32_t s_val[kExecWaves][kCacheMaxWrites][kWave];
+    const uint32_t wv = threadIdx.x / kWave;
+    uint32_t *stmr = (uint32_t *)a->stmr;
+    uint64_t *locks = a->locks;
+    uint32_t *rs = a->rs, *ws = a->ws;
+    DevCounters *cnt = a->cnt;
+    const uint32_t n = a->n_txns, sh = a->stripe_shift, G = a->granule;
+    const uint64_t nsets = a->n_words / kSetWords;
+    uint32_t *res = (uint32_t *)a->results;
+    WriteBuf<uint32_t, kCacheMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
+    LaneState ls;
+
+    while (refill(ls, cnt, n)) {
+        const bool act = lane_turn(ls, n);
+        if (!__ballot(act)) {          // every lane is backing off
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        bool ok = act;
+        uint64_t key = 0;
+        uint32_t put = 0, tv = 0, base = 0, nh = 0;
+        if (act) {
+            key = a->key[ls.txn];
+            put = a->op[ls.txn];
+            tv = a->tid[ls.txn];
+            if (key == 0 || put > 1) {
+                latch_error(cnt, HETM_EINVAL, ls.txn);
+                ok = false;
+            }
+            base = (uint32_t)(((mix64(key) & (nsets - 1) & ~1ull) | (key & 1ull)) * kSetWords);
+            nh = put ? 25u : 17u;
+        }
+        uint64_t sum1 = 0;
+        if (ok)
+            for (uint32_t j = 0; j < nh; ++j) {
+                uint64_t l = ld_agent(&locks[(base + header_word(j)) >> sh]);
+                ok &= !(l & kLockBit);
+                sum1 += l;
+            }
+        fence_acquire();
+        uint32_t hdr[25];
+#pragma unroll
+        for (uint32_t j = 0; j < 25; ++j) hdr[j] = (ok && j < nh) ? ld_agent(&stmr[base + header_word(j)]) : 0u;
+        int hit = -1;
+#pragma unroll
+        for (int w = 7; w >= 0; --w)
+            if (ok && ((uint64_t)hdr[2 * w] | ((uint64_t)hdr[2 * w + 1] << 32)) == key) hit = w;
+        // GET hit: second read phase over the way's value words
+        const bool get_hit = ok && !put && hit >= 0;
+        if (get_hit)
+            for (uint32_t i = 0; i < 8; ++i) {
+                uint64_t l = ld_agent(&locks[(base + kValBase + 8 * hit + i) >> sh]);
+                ok &= !(l & kLockBit);
+                sum1 += l;
+            }
+        fence_acquire();
+        wb.n = 0;
+        uint32_t *r = res + 9ull * (act ? ls.txn : 0);
+        if (ok && !put) {
+            if (hit >= 0) {
+                r[0] = 0x100u | (uint32_t)hit;
+                for (uint32_t i = 0; i < 8; ++i) r[1 + i] = ld_agent(&stmr[base + kValBase + 8 * hit + i]);
+                wb.put(base + kStampBase + hit, tv);
+            } else {
+                for (uint32_t i = 0; i < 9; ++i) r[i] = 0u;
+            }
+        } else if (ok) {
+            uint32_t victim = 0, vmin = hdr[17];
+#pragma unroll
+            for (uint32_t w = 1; w < 8; ++w)
+                if (hdr[17 + w] < vmin) {
+                    vmin = hdr[17 + w];
+                    victim = w;
+                }
+            if (hit >= 0) victim = (uint32_t)hit;
+            uint32_t chk = (uint32_t)mix64(key);
+            uint32_t vb = base + kValBase + 8 * victim;
+            r[0] = 0x200u | (hit >= 0 ? 0x100u : 0u) | victim;
+            wb.put(base + 2 * victim, (uint32_t)key);
+            wb.put(base + 2 * victim + 1, (uint32_t)(key >> 32));
+            for (uint32_t i = 0; i < 7; ++i) {
+                uint32_t v = (uint32_t)mix64(key ^ ((uint64_t)tv << 32) ^ i);
+                chk ^= v;
+                wb.put(vb + i, v);
+                r[1 + i] = v;
+            }
+            wb.put(vb + 7, chk);
+            r[8] = chk;
+            wb.put(base + kStampBase + victim, tv);
+            wb.put(base + kSetStamp, tv);
+        }
+        if (ok && wb.n) ok = wb.lock_all(locks, sh);
+        fence_release();
+        uint32_t ticket = wave_fetch_add(&cnt->ticket, ok);
+        fence_acquire();
+        if (ok) {
+            uint64_t sum2 = 0;
+            for (uint32_t j = 0; j < nh && ok; ++j) sum2 += reread(locks, (base + header_word(j)) >> sh, sh, wb, ok);
+            if (get_hit)
+                for (uint32_t i = 0; i < 8 && ok; ++i)
+                    sum2 += reread(locks, (base + kValBase + 8 * hit + i) >> sh, sh, wb, ok);
+            ok &= sum2 == sum1;
+        }
+        if (ok) wb.write_back(stmr);
+        fence_release();
+        if (wb.locked) wb.release(locks, sh, ok);
+        if (ok) {
+            for (uint32_t j = 0; j < nh; ++j) bitmap_set(rs, div_granule(base + header_word(j), G));
+            if (get_hit)
+                for (uint32_t i = 0; i < 8; ++i) bitmap_set(rs, div_granule(base + kValBase + 8 * hit + i, G));
+            wb.mark_writes(rs, ws, G);
+        }
+        settle(ls, act, act && (key == 0 || put > 1), ok, ticket, a->tickets, cnt, a->retry_cap);
+    }
+    flush_counts(ls, cnt);
+}
+
+__global__ void k_begin_batch(const DevArgs *__restrict__ a) {
+    if (threadIdx.x == 0) st_agent(&a->cnt->queue_head, 0u);
+}
+
+}  // namespace
+
+uint32_t exec_workgroups_per_cu(uint32_t program) {
+    int blocks = 0;
+    const int threads = kExecWaves * kWave;
+    hipError_t e;
+    if (program == HETM_PROG_OPLIST)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_exec_oplist, threads, 0);
+    else if (program == HETM_PROG_TRANSFER)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_exec_transfer, threads, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_exec_cache, threads, 0);
+    return (e == hipSuccess && blocks > 0) ? (uint32_t)blocks : 2u;
+}
+
+void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, hipStream_t s) {
+    hipLaunchKernelGGL(k_begin_batch, dim3(1), dim3(64), 0, s, a);
+    dim3 grid(workgroups), block(kExecWaves * kWave);
+    if (program == HETM_PROG_OPLIST)
+        hipLaunchKernelGGL(k_exec_oplist, grid, block, 0, s, a);
+    else if (program == HETM_PROG_TRANSFER)
+        hipLaunchKernelGGL(k_exec_transfer, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(k_exec_cache, grid, block, 0, s, a);
+}
+
+}  // namespace hetm

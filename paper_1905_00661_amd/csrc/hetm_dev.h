@@ -20,20 +20,21 @@ constexpr uint32_t kDoneTxn = 0xFFFFFFFEu;
 
 // Counters the kernels update during a round (device memory).
 struct DevCounters {
-    uint32_t conflict;          // OR of the validation flags of the round
-    int32_t error;              // first latched error code (HETM_E*), 0 if none
-    uint32_t ticket;            // next commit ticket
-    uint32_t queue_head;        // next transaction of the current batch
-    unsigned long long max_ts;  // largest ts seen in this round's log chunks
+    uint32_t conflict;            // OR of the validation flags of the round
+    int32_t error;                // first latched error code (HETM_E*), 0 if none
+    uint32_t ticket;              // next commit ticket
+    uint32_t queue_head;          // next transaction of the current batch
+    unsigned long long max_ts;    // largest ts of this round's applied log chunks
     unsigned long long floor_ts;  // watermark: largest ts applied by earlier rounds
     unsigned long long committed; // local commits in this round
     unsigned long long retries;   // local aborts in this round
-    uint32_t n_dirty;           // write-set granules found by the compaction
-    uint32_t n_runs;            // maximal runs of consecutive dirty granules
-    uint32_t retry_txn;         // first transaction that hit the retry cap
-    uint32_t scan_ticket;       // blocks finished in the compaction count pass
-    uint32_t err_index;         // index of the first bad log entry
-    uint32_t pad_;
+    unsigned long long chunk_max_ts;  // the current chunk's, folded in when it applies
+    uint32_t n_dirty;             // write-set granules found by the compaction
+    uint32_t n_runs;              // maximal runs of consecutive dirty granules
+    uint32_t retry_txn;           // first transaction that hit the retry cap
+    uint32_t scan_ticket;         // blocks finished in the compaction count pass
+    uint32_t err_index;           // index of the first bad log entry / transaction
+    uint32_t chunk_conflict;      // the current chunk's flags, folded in when it applies
 };
 
 // Everything a kernel needs: constant context state plus the arguments of
@@ -143,17 +144,17 @@ __device__ __forceinline__ void bitmap_set(uint32_t *bm, uint32_t g) {
 __device__ __forceinline__ uint32_t div_granule(uint64_t w, uint32_t G) { return (uint32_t)(w / G); }
 
 // ------------------------------------------------------------- launchers
-// Host-side launch wrappers, one per kernel family (defined next to the
-// kernels).  `a` is the device address of the DevArgs block.
+// Host-side launch wrappers, defined next to their kernels.  `a` is the
+// device address of the DevArgs block every kernel reads its arguments from.
 void launch_set_args(const DevArgs &host_copy, DevArgs *dev, hipStream_t s);
+void launch_clear_error(DevCounters *cnt, hipStream_t s);
 void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, hipStream_t s);
-void launch_validate(const DevArgs *a, uint32_t max_log, hipStream_t s);
-void launch_apply(const DevArgs *a, uint32_t max_log, hipStream_t s);
+void launch_validate(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);
+void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s);
-void launch_copy(const DevArgs *a, uint32_t n_granules, uint32_t granule, uint32_t word_bytes, hipStream_t s);
-void launch_reset(const DevArgs *a, uint32_t n_bm_words, hipStream_t s);
-void launch_begin_round(const DevArgs *a, hipStream_t s);
-uint32_t exec_max_workgroups(uint32_t program);
+void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
+void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hipStream_t s);
+uint32_t exec_workgroups_per_cu(uint32_t program);
 
 constexpr uint32_t kScanWordsPerBlock = 2048;   // bitmap words per compaction block
 constexpr uint32_t kScanThreads = 256;

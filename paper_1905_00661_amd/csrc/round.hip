@@ -1,0 +1,409 @@
+// round.hip -- validation, apply and merge of one SHeTM round (§IV-C.2,
+// §IV-C.3) and the round reset, for gfx950.
+//
+//  validate : streams the host log chunk (16- or 24-byte entries, coalesced)
+//             against the read-set bitmap; a wave ballot gives 64 flag bits
+//             per store; checks the entry preconditions.
+//  apply    : two passes instead of a per-word lock.  Pass 1 raises TS[w] to
+//             the largest timestamp of the entries for w with a 64-bit atomic
+//             max and marks an entry "suspect" when the max it met already
+//             equalled its own timestamp.  Pass 2 lets the entry whose
+//             timestamp equals the final TS[w] store its value; a suspect
+//             entry that equals it means two entries carry w's winning
+//             timestamp (an ordering error).  The result is the freshest entry
+//             per word, independent of arrival order, with no spinning.
+//  compact  : popcount + prefix sum over the write-set bitmap (per-block
+//             counts, the last block scans the block sums, then each block
+//             emits ascending dirty granule ids); runs of consecutive ids are
+//             counted from run-start bits.
+//  copy     : moves the dirty granules between the GPU replica and the
+//             device-mapped pinned host replica, GPU->host on success and
+//             host->GPU on conflict; the direction is read on the device.
+//  finish   : snapshots the round's counters, clears the bitmaps and raises
+//             the timestamp watermark.
+#include "hetm_dev.h"
+
+namespace hetm {
+
+namespace {
+
+struct Entry4 {
+    uint32_t word;
+    uint32_t value;
+    uint64_t ts;
+};
+struct Entry8 {
+    uint32_t word;
+    uint32_t pad;
+    uint64_t value;
+    uint64_t ts;
+};
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t t = __shfl_xor((unsigned long long)v, o);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void store_bits(uint32_t *dst, uint64_t kb, uint64_t m, uint32_t nwords) {
+    uint64_t w = kb >> 5;
+    dst[w] = (uint32_t)m;
+    if (w + 1 < nwords) dst[w + 1] = (uint32_t)(m >> 32);
+}
+
+// ------------------------------------------------------------------ validate
+template <typename E>
+__global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a) {
+    const E *log = (const E *)a->log;
+    const uint64_t n = a->n_log, N = a->n_words;
+    const uint32_t G = a->granule;
+    const uint32_t *rs = a->rs;
+    uint32_t *flags = a->flags;
+    DevCounters *cnt = a->cnt;
+    const uint64_t floor_ts = ld_agent(&cnt->floor_ts);
+    const uint32_t nflagw = (uint32_t)((n + 31) / 32);
+    const uint32_t lane = lane_id();
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t mx = 0;
+    bool conflict = false;
+    for (uint64_t kb = wave * kWave; kb < n; kb += stride) {
+        const uint64_t k = kb + lane;
+        bool f = false;
+        if (k < n) {
+            const E e = log[k];
+            if (e.word >= N) {
+                latch_error(cnt, HETM_EINVAL, (uint32_t)k);
+            } else if (e.ts <= floor_ts || e.ts >= kTsLimit) {
+                latch_error(cnt, HETM_EORDER, (uint32_t)k);
+            } else {
+                const uint32_t g = div_granule(e.word, G);
+                f = (rs[g >> 5] >> (g & 31)) & 1u;
+                mx = e.ts > mx ? e.ts : mx;
+            }
+        }
+        const uint64_t m = __ballot(f);
+        if (flags && lane == 0) store_bits(flags, kb, m, nflagw);
+        conflict |= m != 0;
+    }
+    // staged per chunk: a chunk that fails its preconditions must not count
+    mx = wave_max_u64(mx);
+    if (lane == 0) {
+        if (mx) __hip_atomic_fetch_max(&cnt->chunk_max_ts, (unsigned long long)mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (conflict) __hip_atomic_fetch_or(&cnt->chunk_conflict, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ------------------------------------------------------------------- apply
+template <typename E>
+__global__ __launch_bounds__(256) void k_apply_max(const DevArgs *__restrict__ a) {
+    DevCounters *cnt = a->cnt;
+    if (ld_agent(&cnt->error)) return;   // a chunk failing its preconditions applies nothing
+    if (blockIdx.x == 0 && threadIdx.x == 0) {   // the chunk counts: fold its outcome into the round's
+        if (ld_agent(&cnt->chunk_conflict)) st_agent(&cnt->conflict, 1u);
+        const unsigned long long m = ld_agent(&cnt->chunk_max_ts);
+        if (m > ld_agent(&cnt->max_ts)) st_agent(&cnt->max_ts, m);
+    }
+    const E *log = (const E *)a->log;
+    const uint64_t n = a->n_log;
+    uint64_t *ts = a->ts;
+    uint32_t *suspect = a->suspect;
+    const uint32_t nw = (uint32_t)((n + 31) / 32);
+    const uint32_t lane = lane_id();
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t kb = wave * kWave; kb < n; kb += stride) {
+        const uint64_t k = kb + lane;
+        bool sus = false;
+        if (k < n) {
+            const E e = log[k];
+            uint64_t old = __hip_atomic_fetch_max(&ts[e.word], (uint64_t)e.ts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sus = old == e.ts;
+        }
+        const uint64_t m = __ballot(sus);
+        if (lane == 0) store_bits(suspect, kb, m, nw);
+    }
+}
+
+template <typename E, typename Word>
+__global__ __launch_bounds__(256) void k_apply_store(const DevArgs *__restrict__ a) {
+    DevCounters *cnt = a->cnt;
+    if (ld_agent(&cnt->error)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {   // pass 1 consumed the chunk counters
+        st_agent(&cnt->chunk_conflict, 0u);
+        st_agent(&cnt->chunk_max_ts, 0ull);
+    }
+    const E *log = (const E *)a->log;
+    const uint64_t n = a->n_log;
+    const uint64_t *ts = a->ts;
+    const uint32_t *suspect = a->suspect;
+    Word *stmr = (Word *)a->stmr;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += stride) {
+        const E e = log[k];
+        if (ts[e.word] != e.ts) continue;     // a fresher entry (or an earlier round) holds the word
+        if ((suspect[k >> 5] >> (k & 31)) & 1u)
+            latch_error(cnt, HETM_EORDER, (uint32_t)k);
+        else
+            stmr[e.word] = (Word)e.value;
+    }
+}
+
+// ------------------------------------------------------------------ compact
+constexpr uint32_t kWordsPerThread = kScanWordsPerBlock / kScanThreads;   // 8
+
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const uint32_t wv = threadIdx.x / kWave;
+    if (lane_id() == 0) sh[wv] = v;
+    __syncthreads();
+    uint32_t t = 0;
+    for (uint32_t i = 0; i < kScanThreads / kWave; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// exclusive prefix of v over the block (256 threads)
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    uint32_t inc = v;
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t t = __shfl_up(inc, o);
+        if ((int)lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) sh[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (uint32_t i = 0; i < kScanThreads / kWave; ++i) {
+        if (i < wv) before += sh[i];
+        total += sh[i];
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_compact_count(const DevArgs *__restrict__ a) {
+    __shared__ uint32_t sh[kScanThreads / kWave];
+    __shared__ uint32_t s_last;
+    const uint32_t *ws = a->ws;
+    const uint32_t nbw = a->n_bm_words;
+    DevCounters *cnt = a->cnt;
+    const uint64_t w0 = (uint64_t)blockIdx.x * kScanWordsPerBlock + threadIdx.x * kWordsPerThread;
+    uint32_t c = 0, r = 0;
+    uint32_t prev = (w0 > 0 && w0 - 1 < nbw) ? ws[w0 - 1] >> 31 : 0u;
+    for (uint32_t i = 0; i < kWordsPerThread; ++i) {
+        const uint32_t x = (w0 + i < nbw) ? ws[w0 + i] : 0u;
+        c += __popc(x);
+        r += __popc(x & ~((x << 1) | prev));     // run starts: set bits whose predecessor is clear
+        prev = x >> 31;
+    }
+    c = block_sum(c, sh);
+    r = block_sum(r, sh);
+    if (threadIdx.x == 0) {
+        st_agent(&a->blocksums[blockIdx.x], c);
+        st_agent(&a->blockruns[blockIdx.x], r);
+        fence_release();
+        uint32_t done = __hip_atomic_fetch_add(&cnt->scan_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = done == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    // last block: exclusive scan of the block sums, in place
+    fence_acquire();
+    const uint32_t nb = gridDim.x;
+    const uint32_t per = (nb + kScanThreads - 1) / kScanThreads;
+    const uint32_t lo = threadIdx.x * per, hi = min(lo + per, nb);
+    uint32_t local = 0, runs = 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+        local += ld_agent(&a->blocksums[i]);
+        runs += ld_agent(&a->blockruns[i]);
+    }
+    uint32_t total = 0;
+    uint32_t run = block_exclusive_scan(local, sh, total);
+    runs = block_sum(runs, sh);
+    for (uint32_t i = lo; i < hi; ++i) {
+        uint32_t v = ld_agent(&a->blocksums[i]);
+        st_agent(&a->blocksums[i], run);
+        run += v;
+    }
+    if (threadIdx.x == 0) {
+        st_agent(&cnt->n_dirty, total);
+        st_agent(&cnt->n_runs, runs);
+        st_agent(&cnt->scan_ticket, 0u);
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_compact_emit(const DevArgs *__restrict__ a) {
+    __shared__ uint32_t sh[kScanThreads / kWave];
+    const uint32_t *ws = a->ws;
+    const uint32_t nbw = a->n_bm_words;
+    uint32_t *ids = a->ids_scratch, *ids_out = a->ids_out;
+    const uint64_t w0 = (uint64_t)blockIdx.x * kScanWordsPerBlock + threadIdx.x * kWordsPerThread;
+    uint32_t x[kWordsPerThread];
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kWordsPerThread; ++i) {
+        x[i] = (w0 + i < nbw) ? ws[w0 + i] : 0u;
+        c += __popc(x[i]);
+    }
+    uint32_t total;
+    uint32_t pos = ld_agent(&a->blocksums[blockIdx.x]) + block_exclusive_scan(c, sh, total);
+#pragma unroll
+    for (uint32_t i = 0; i < kWordsPerThread; ++i) {
+        uint32_t v = x[i];
+        while (v) {
+            const uint32_t g = (uint32_t)((w0 + i) * 32 + __ffs(v) - 1);
+            ids[pos] = g;
+            if (ids_out) ids_out[pos] = g;
+            ++pos;
+            v &= v - 1;
+        }
+    }
+}
+
+// --------------------------------------------------------------------- copy
+// Moves the dirty granules in units of U bytes (16 when granules are whole
+// multiples of 16 bytes, else one word); upg = units per granule.
+template <typename U>
+__global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uint32_t upg, uint64_t total_units) {
+    DevCounters *cnt = a->cnt;
+    if (ld_agent(&cnt->error)) return;
+    const uint32_t outcome = a->outcome == HETM_OUTCOME_DEVICE ? ld_agent(&cnt->conflict) : a->outcome;
+    const uint64_t D = ld_agent(&cnt->n_dirty);
+    const uint32_t *ids = a->ids_scratch;
+    U *dev = (U *)a->stmr;
+    U *host = (U *)a->host;
+    const uint64_t work = D * upg;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < work; u += stride) {
+        const uint64_t i = u / upg, j = u - i * upg;
+        const uint64_t pos = (uint64_t)ids[i] * upg + j;
+        if (pos >= total_units) continue;
+        if (outcome)
+            dev[pos] = host[pos];
+        else
+            host[pos] = dev[pos];
+    }
+}
+
+// ------------------------------------------------------------------- finish
+__global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, DevCounters *snap) {
+    DevCounters *cnt = a->cnt;
+    const int32_t err = ld_agent(&cnt->error);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        DevCounters c;
+        c.conflict = ld_agent(&cnt->conflict);
+        c.error = err;
+        c.ticket = ld_agent(&cnt->ticket);
+        c.queue_head = 0;
+        c.max_ts = ld_agent(&cnt->max_ts);
+        c.floor_ts = ld_agent(&cnt->floor_ts);
+        c.committed = ld_agent(&cnt->committed);
+        c.retries = ld_agent(&cnt->retries);
+        c.n_dirty = ld_agent(&cnt->n_dirty);
+        c.n_runs = ld_agent(&cnt->n_runs);
+        c.retry_txn = ld_agent(&cnt->retry_txn);
+        c.scan_ticket = 0;
+        c.err_index = ld_agent(&cnt->err_index);
+        c.chunk_max_ts = 0;
+        c.chunk_conflict = 0;
+        if (!err) {
+            const uint64_t f = c.max_ts > c.floor_ts ? c.max_ts : c.floor_ts;
+            c.floor_ts = f;
+            st_agent(&cnt->floor_ts, (unsigned long long)f);
+            st_agent(&cnt->conflict, 0u);
+            st_agent(&cnt->ticket, 0u);
+            st_agent(&cnt->max_ts, 0ull);
+            st_agent(&cnt->committed, 0ull);
+            st_agent(&cnt->retries, 0ull);
+            st_agent(&cnt->n_dirty, 0u);
+            st_agent(&cnt->n_runs, 0u);
+        }
+        *snap = c;
+    }
+    if (err) return;      // keep the round open: the caller can fix the log and merge again
+    const uint32_t nbw = a->n_bm_words;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nbw; i += gridDim.x * blockDim.x) {
+        a->rs[i] = 0u;
+        a->ws[i] = 0u;
+    }
+}
+
+__global__ void k_set_args(DevArgs v, DevArgs *dst) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
+__global__ void k_clear_error(DevCounters *cnt) {
+    if (threadIdx.x == 0) {
+        st_agent(&cnt->error, 0);
+        st_agent(&cnt->err_index, 0u);
+        st_agent(&cnt->retry_txn, 0u);
+        st_agent(&cnt->chunk_conflict, 0u);
+        st_agent(&cnt->chunk_max_ts, 0ull);
+    }
+}
+
+uint32_t stream_grid(uint64_t items, uint32_t threads, uint32_t cap) {
+    uint64_t b = (items + threads - 1) / threads;
+    if (b < 1) b = 1;
+    return (uint32_t)(b < cap ? b : cap);
+}
+
+}  // namespace
+
+void launch_set_args(const DevArgs &host_copy, DevArgs *dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_args, dim3(1), dim3(64), 0, s, host_copy, dev);
+}
+
+void launch_clear_error(DevCounters *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_error, dim3(1), dim3(64), 0, s, cnt);
+}
+
+void launch_validate(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s) {
+    const uint32_t grid = stream_grid(max_log, 256, 8192);
+    if (word_bytes == 4)
+        hipLaunchKernelGGL(k_validate<Entry4>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_validate<Entry8>, dim3(grid), dim3(256), 0, s, a);
+}
+
+void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s) {
+    const uint32_t grid = stream_grid(max_log, 256, 8192);
+    if (word_bytes == 4) {
+        hipLaunchKernelGGL(k_apply_max<Entry4>, dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_apply_store<Entry4, uint32_t>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_apply_max<Entry8>, dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_apply_store<Entry8, uint64_t>), dim3(grid), dim3(256), 0, s, a);
+    }
+}
+
+void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_count, dim3(n_scan_blocks), dim3(kScanThreads), 0, s, a);
+    hipLaunchKernelGGL(k_compact_emit, dim3(n_scan_blocks), dim3(kScanThreads), 0, s, a);
+}
+
+void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s) {
+    const uint64_t gbytes = (uint64_t)granule * word_bytes;
+    const uint64_t n_granules = (n_words + granule - 1) / granule;
+    if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0) {
+        const uint32_t upg = (uint32_t)(gbytes / 16);
+        const uint32_t grid = stream_grid(n_granules * upg, 256, 16384);
+        hipLaunchKernelGGL(k_copy<uint4>, dim3(grid), dim3(256), 0, s, a, upg, n_words * word_bytes / 16);
+    } else if (word_bytes == 4) {
+        const uint32_t grid = stream_grid(n_granules * granule, 256, 16384);
+        hipLaunchKernelGGL(k_copy<uint32_t>, dim3(grid), dim3(256), 0, s, a, granule, n_words);
+    } else {
+        const uint32_t grid = stream_grid(n_granules * granule, 256, 16384);
+        hipLaunchKernelGGL(k_copy<uint64_t>, dim3(grid), dim3(256), 0, s, a, granule, n_words);
+    }
+}
+
+void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(stream_grid(n_bm_words, 256, 4096)), dim3(256), 0, s, a, snap);
+}
+
+}  // namespace hetm

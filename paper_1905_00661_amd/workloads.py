@@ -137,6 +137,19 @@ def host_log_uniform(g: np.random.Generator, n: int, lo: int, hi: int, watermark
     return log
 
 
+def host_replica(init: np.ndarray, log: np.ndarray) -> np.ndarray:
+    """The host replica at the round cut: the host executed the logged writes
+    itself, one after the other in timestamp order, so each word holds the
+    value of its last write.  (This is the CPU side of the round, which
+    produces the log; it is an input of the GPU round.)"""
+    H = init.copy()
+    o = np.argsort(log["ts"], kind="stable")[::-1]      # latest write first
+    w = log["word"][o].astype(np.int64)
+    uniq, first = np.unique(w, return_index=True)
+    H[uniq] = log["value"][o][first]
+    return H
+
+
 # ----------------------------------------------------------------------------
 # C1: plain single round, small
 # ----------------------------------------------------------------------------

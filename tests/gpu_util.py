@@ -1,0 +1,94 @@
+"""Helpers for the GPU parity tests: run a round through libhetm (the C ABI
+via the ctypes binding) and the same round through the CPU oracle, on the
+same seeded inputs, in the GPU's recorded commit order."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle as orc
+from paper_1905_00661_amd import hetm as hm
+from paper_1905_00661_amd import workloads as wl
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def bits(bm: np.ndarray, n: int) -> np.ndarray:
+    return np.unpackbits(bm.view(np.uint8), bitorder="little")[:n].astype(bool)
+
+
+def gpu_round(ri: wl.RoundInputs, mode=hm.HETM_MODE_PLAIN, stripe=1, host=None, ctx=None, exec_workgroups=0,
+              flags=True, ids=True, keep=False):
+    """One whole round (hetm_round) on the GPU.  Returns a dict of numpy
+    results and the context (if keep)."""
+    import torch
+    program = ri.program
+    if ctx is None:
+        ctx = hm.Context(ri.n_words, ri.word_bytes, ri.granule, init=ri.init, stripe=stripe,
+                         batch_capacity=max(ri.batch.n, 1), log_capacity=max(ri.log.shape[0], 1),
+                         mode=mode, exec_workgroups=exec_workgroups)
+    H0 = wl.host_replica(ri.init, ri.log) if host is None else host
+    host_t = hm.pinned(H0.nbytes)
+    host_t.numpy()[:] = H0.view(np.uint8)
+    b = hm.Batch(program, ri.batch, ctx.dev)
+    n_log = ri.log.shape[0]
+    log_t = hm.to_device(ri.log, ctx.dev) if n_log else torch.zeros(16, dtype=torch.uint8, device=ctx.dev)
+    flags_t = torch.zeros(max((n_log + 31) // 32, 1) * 4, dtype=torch.uint8, device=ctx.dev) if flags else None
+    ids_t = torch.zeros(max(ctx.n_granules, 1) * 4, dtype=torch.uint8, device=ctx.dev) if ids else None
+    torch.cuda.synchronize()
+    res = ctx.round(b if ri.batch.n else None, log_t, n_log, host_t, flags_t, ids_t)
+    out = {
+        "res": res,
+        "results": b.results_np(),
+        "tickets": b.tickets_np(),
+        "S": ctx.read_state(hm.HETM_STATE_STMR).copy(),
+        "TS": ctx.read_state(hm.HETM_STATE_TS).copy(),
+        "H": host_t.numpy().view(ri.init.dtype).copy(),
+        "flags": hm.tensor_to_numpy(flags_t, np.uint32) if flags else None,
+        "ids": hm.tensor_to_numpy(ids_t, np.uint32, int(res.n_dirty)) if ids else None,
+        "H0": H0,
+    }
+    if keep:
+        out["ctx"] = ctx
+    else:
+        ctx.close()
+    return out
+
+
+REPLAY = {wl.PROG_OPLIST: orc.replay_oplist, wl.PROG_TRANSFER: orc.replay_transfer, wl.PROG_CACHE: orc.replay_cache}
+
+
+def oracle_round(ri: wl.RoundInputs, tickets: np.ndarray, H0: np.ndarray, S0=None, TS0=None, floor=0):
+    order = orc.order_from_tickets(tickets)
+    S = (ri.init if S0 is None else S0).copy()
+    TS = np.zeros(ri.n_words, np.uint64) if TS0 is None else TS0.copy()
+    H = H0.copy()
+    out = orc.round_generic(REPLAY[ri.program], S, H, TS, ri.granule, ri.batch, order, ri.log, floor)
+    out.update({"S": S, "H": H, "TS": TS, "order": order})
+    return out
+
+
+def assert_round_equal(g: dict, o: dict, ri: wl.RoundInputs, check_ts=True):
+    """Element-wise, bit-exact comparison of every output of the round."""
+    n_log = ri.log.shape[0]
+    r = g["res"]
+    assert r.error == 0
+    assert r.conflict == o["conflict"], (r.conflict, o["conflict"])
+    assert np.array_equal(g["results"], o["results"]), "transaction results differ"
+    if g["flags"] is not None:
+        assert np.array_equal(bits(g["flags"], n_log), bits(o["flags"], n_log)), "validation flags differ"
+    assert int(r.n_dirty) == o["ids"].shape[0]
+    assert int(r.n_runs) == o["n_runs"]
+    if g["ids"] is not None:
+        assert np.array_equal(g["ids"], o["ids"]), "dirty granule ids differ"
+    assert np.array_equal(g["S"], o["S"]), f"GPU replica differs at {np.flatnonzero(g['S'] != o['S'])[:8]}"
+    assert np.array_equal(g["H"], o["H"]), "host replica differs"
+    assert np.array_equal(g["S"], g["H"]), "replicas differ after the merge"
+    if check_ts:
+        assert np.array_equal(g["TS"], o["TS"]), "TS array differs"
+    if o["conflict"] == 0:
+        assert int(r.n_committed) == ri.batch.n

@@ -1,0 +1,209 @@
+"""GPU parity: libhetm (HIP, gfx950) against the CPU oracle, bit-exact, on the
+same seeded inputs, replayed in the GPU's recorded commit order."""
+import itertools
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_round_equal, bits, gpu_round, oracle_round, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_00661_amd import hetm
+    hetm.lib()
+    return hetm
+
+
+@pytest.fixture(scope="module")
+def wl():
+    from paper_1905_00661_amd import workloads
+    return workloads
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["plain", "graph"])
+@pytest.mark.parametrize("variant", ["", "w", "p"])
+def test_c1_round(hm, wl, variant, mode):
+    """The plain single round (2^16 words, 4096 4R/4W txns, 10,000-entry log,
+    granule 64) and its granule-1 and partitioned variants."""
+    ri = wl.c1(variant)
+    say(f"c1{variant} mode={mode}")
+    g = gpu_round(ri, mode=mode)
+    o = oracle_round(ri, g["tickets"], g["H0"])
+    assert_round_equal(g, o, ri)
+    assert o["conflict"] == (0 if variant == "p" else 1)
+    if variant == "w":
+        assert 1500 < bits(o["flags"], 10000).sum() < 3000
+
+
+def test_c1_steps(hm, wl):
+    """The step API: bitmaps after execution, flags and TS after
+    validate+apply, replicas after copy-back with the device outcome."""
+    import torch
+    ri = wl.c1("w")
+    ctx = hm.Context(ri.n_words, 4, ri.granule, init=ri.init, batch_capacity=ri.batch.n, log_capacity=20000)
+    b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch)
+    half = ri.batch.subset(0, 2000), ri.batch.subset(2000, ri.batch.n)
+    b1, b2 = hm.Batch(1, half[0]), hm.Batch(1, half[1])
+    ctx.submit(b1)
+    ctx.submit(b2)
+    RS, WS = ctx.read_state(hm.HETM_STATE_RS).copy(), ctx.read_state(hm.HETM_STATE_WS).copy()
+    t1, t2 = b1.tickets_np(), b2.tickets_np()
+    tickets = np.concatenate([t1, t2])
+    import oracle as orc
+    order = orc.order_from_tickets(tickets)
+    S = ri.init.copy()
+    res, oRS, oWS = orc.replay_oplist(S, ri.granule, ri.batch, order)
+    assert np.array_equal(np.concatenate([b1.results_np(), b2.results_np()]), res)
+    assert np.array_equal(RS, oRS) and np.array_equal(WS, oWS)
+    # two log chunks
+    log_t = hm.to_device(ri.log)
+    flags = torch.zeros(((10000 + 31) // 32) * 4, dtype=torch.uint8, device="cuda")
+    c = ctx.validate_apply(log_t, 10000, flags)
+    ofl, oc = orc.validate(ri.log, oRS, ri.granule, ri.n_words)
+    TS = np.zeros(ri.n_words, np.uint64)
+    orc.apply(S, TS, ri.log, 0)
+    assert c == oc == 1
+    assert np.array_equal(bits(hm.tensor_to_numpy(flags, np.uint32), 10000), bits(ofl, 10000))
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S)
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_TS), TS)
+    H = wl.host_replica(ri.init, ri.log)
+    host_t = hm.pinned(H.nbytes)
+    host_t.numpy()[:] = H.view(np.uint8)
+    nd = ctx.copyback(hm.HETM_OUTCOME_DEVICE, host_t)
+    ids, runs = orc.merge(oc, oWS, ri.granule, S, H)
+    assert nd == ids.shape[0]
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S)
+    assert np.array_equal(host_t.numpy().view(np.uint32), H)
+    assert not ctx.read_state(hm.HETM_STATE_RS).any() and not ctx.read_state(hm.HETM_STATE_WS).any()
+    ctx.close()
+
+
+@pytest.mark.parametrize("p_hot,G,stripe", [(0.0, 16, 1), (0.9, 16, 1), (0.5, 4096, 4), (0.9, 1, 1), (0.5, 64, 16)])
+@pytest.mark.parametrize("mode", [0, 1], ids=["plain", "graph"])
+def test_c2_scaled(hm, wl, p_hot, G, stripe, mode):
+    """The large synthetic mix at 1/256 of its size, with hot sets, granule
+    and lock-stripe sweeps and an injected conflict."""
+    ri = wl.c2(n_words=1 << 20, n_txn=1 << 16, n_log=1 << 14, p_hot=p_hot, granule=G,
+               conflict_rate=1.0 if p_hot == 0.5 else 0.0)
+    say(f"c2 scaled p_hot={p_hot} G={G} S={stripe} mode={mode}")
+    g = gpu_round(ri, mode=mode, stripe=stripe)
+    o = oracle_round(ri, g["tickets"], g["H0"])
+    assert_round_equal(g, o, ri)
+    assert o["conflict"] == (1 if p_hot == 0.5 else 0)
+
+
+@pytest.mark.parametrize("N,G,n_txn,n_log", [(1000, 7, 100, 33), (4099, 3, 1, 1), (64, 64, 65, 130), (128, 1, 0, 5),
+                                             (300, 10, 70, 0)])
+def test_ragged_and_empty(hm, wl, N, G, n_txn, n_log):
+    """Sizes that are not multiples of a wave, a granule that does not divide
+    N (ragged last granule), one-element and empty batches and logs."""
+    g0 = np.random.default_rng(N + n_txn)
+    init = g0.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    lens = g0.integers(1, 9, size=n_txn).astype(np.uint64)
+    nws = np.array([g0.integers(0, min(int(L), 8) + 1) for L in lens], dtype=np.int64)
+    idx = g0.integers(0, N, size=int(lens.sum()), dtype=np.uint64)
+    batch = wl._oplist_from_lists(lens, nws, idx, 0)
+    log = wl.host_log_uniform(g0, n_log, 0, N, 0)
+    ri = wl.RoundInputs(cfg="ragged", n_words=N, word_bytes=4, granule=G, program=1, init=init, batch=batch, log=log)
+    say(f"ragged N={N} G={G} n={n_txn} log={n_log}")
+    g = gpu_round(ri)
+    o = oracle_round(ri, g["tickets"], g["H0"])
+    assert_round_equal(g, o, ri)
+
+
+def test_rounds_in_sequence(hm, wl):
+    """Three rounds on one context: TS and the watermark persist, bitmaps are
+    cleared, every round matches the oracle continued from the last."""
+    N = 1 << 16
+    base = wl.c1("w")
+    ctx = hm.Context(N, 4, 1, init=base.init, batch_capacity=4096, log_capacity=10000)
+    S, TS, floor = base.init.copy(), np.zeros(N, np.uint64), 0
+    for r in range(3):
+        g0 = np.random.default_rng(100 + r)
+        batch = wl._oplist_from_lists(np.full(4096, 4, np.uint64), np.full(4096, 2 if r == 1 else 4),
+                                      g0.integers(0, N // 2, size=4 * 4096, dtype=np.uint64), r * 4096)
+        log = wl.host_log_uniform(g0, 10000, N // 2 if r != 2 else 0, N, floor)
+        ri = wl.RoundInputs(cfg="seq", n_words=N, word_bytes=4, granule=1, program=1, init=S, batch=batch, log=log,
+                            watermark=floor)
+        say(f"sequence round {r}")
+        H0 = wl.host_replica(S, log)
+        g = gpu_round(ri, ctx=ctx, host=H0, keep=True)
+        o = oracle_round(ri, g["tickets"], H0, S0=S, TS0=TS, floor=floor)
+        assert_round_equal(g, o, ri)
+        S, TS, floor = o["S"], o["TS"], int(o["max_ts"])
+        assert int(g["res"].max_ts) == floor
+    ctx.close()
+
+
+def test_log_preconditions(hm, wl):
+    """A log word outside the STMR (EINVAL) or a timestamp not above the
+    watermark (EORDER) applies nothing; a tie at a word's winning timestamp
+    is EORDER; the context stays usable."""
+    import torch
+    N = 256
+    init = np.arange(N, dtype=np.uint32)
+    ctx = hm.Context(N, 4, 4, init=init, batch_capacity=64, log_capacity=64)
+    LOG = wl.LOG4_DTYPE
+
+    def mk(entries):
+        a = np.zeros(len(entries), LOG)
+        for k, e in enumerate(entries):
+            a[k] = e
+        return hm.to_device(a)
+
+    for entries, code in [([(1, 5, 3), (N, 1, 4)], hm.HETM_EINVAL), ([(1, 5, 3), (2, 1, 0)], hm.HETM_EORDER),
+                          ([(1, 5, 3), (2, 1, 1 << 63)], hm.HETM_EORDER)]:
+        with pytest.raises(hm.HetmError) as e:
+            ctx.validate_apply(mk(entries), len(entries))
+        assert e.value.code == code
+        assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), init)
+        assert not ctx.read_state(hm.HETM_STATE_TS).any()
+    with pytest.raises(hm.HetmError) as e:
+        ctx.validate_apply(mk([(7, 1, 9), (7, 2, 9), (8, 3, 2)]), 3)
+    assert e.value.code == hm.HETM_EORDER
+    # ties below the winner pass, and the context is usable again
+    assert ctx.validate_apply(mk([(9, 1, 20), (9, 2, 20), (9, 3, 30)]), 3) == 0
+    S = ctx.read_state(hm.HETM_STATE_STMR)
+    assert S[9] == 3 and S[8] == 3
+    ctx.close()
+
+
+def test_brute_force_tiny(hm, wl):
+    """At most 6 transactions on 16 words: the GPU outcome (final replica and
+    every value read) is one of the n! serial outcomes, namely the one of
+    its recorded commit order."""
+    import oracle as orc
+    for seed in range(12):
+        ri = wl.tiny(seed, n_txn=6)
+        ri.log = ri.log[:0]
+        g = gpu_round(ri)
+        outcomes = set()
+        for perm in itertools.permutations(range(ri.batch.n)):
+            S = ri.init.copy()
+            res, _, _ = orc.replay_oplist(S, ri.granule, ri.batch, np.array(perm))
+            outcomes.add((S.tobytes(), res.tobytes()))
+        assert (g["S"].tobytes(), g["results"].tobytes()) in outcomes
+        o = oracle_round(ri, g["tickets"], g["H0"])
+        assert_round_equal(g, o, ri)
+
+
+def test_hot_word_contention(hm, wl):
+    """Every transaction read-modify-writes one of 4 words: heavy local
+    conflicts, retries, and still one serial order (prefix sums)."""
+    N = 1024
+    n = 20000
+    g0 = np.random.default_rng(5)
+    batch = wl._oplist_from_lists(np.full(n, 2, np.uint64), np.full(n, 2),
+                                  g0.integers(0, 4, size=2 * n, dtype=np.uint64), 0)
+    ri = wl.RoundInputs(cfg="hot", n_words=N, word_bytes=4, granule=1, program=1,
+                        init=np.zeros(N, np.uint32), batch=batch, log=wl.host_log_uniform(g0, 0, 0, N, 0))
+    g = gpu_round(ri)
+    o = oracle_round(ri, g["tickets"], g["H0"])
+    assert_round_equal(g, o, ri)
+    say(f"hot: retries={g['res'].n_local_retries}")

@@ -61,7 +61,7 @@ def test_golden_hand_worked_round(orc, which):
     assert mx == max(e[2] for e in L["entries"])
     assert S.tolist() == L["expect_after_apply"]
     assert TS.tolist() == L["expect_ts"]
-    orc.apply(H, np.zeros(N, np.uint64), log, 0)
+    H = wl.host_replica(H, log)
     ids, runs = orc.merge(conflict, WS, G, S, H)
     assert ids.tolist() == L["expect_dirty"]
     assert S.tolist() == L["expect_final"] and H.tolist() == L["expect_final"]
@@ -331,7 +331,7 @@ def test_merge_is_stream_compaction(orc, G, N):
 @pytest.mark.parametrize("variant", ["", "w", "p"])
 def test_round_replicas_equal(orc, variant):
     ri = wl.c1(variant)
-    S, H, TS = ri.init.copy(), ri.init.copy(), np.zeros(ri.n_words, np.uint64)
+    S, H, TS = ri.init.copy(), wl.host_replica(ri.init, ri.log), np.zeros(ri.n_words, np.uint64)
     out = orc.round_oplist(S, H, TS, ri.granule, ri.batch, np.arange(ri.batch.n), ri.log, 0)
     assert np.array_equal(S, H)
     assert out["conflict"] == (0 if variant == "p" else 1)
@@ -345,7 +345,7 @@ def test_round_success_is_serial_cpu_then_gpu(orc):
     host log in timestamp order, then the GPU batch in its commit order."""
     ri = wl.c1("p")
     order = np.random.default_rng(9).permutation(ri.batch.n)
-    S, H, TS = ri.init.copy(), ri.init.copy(), np.zeros(ri.n_words, np.uint64)
+    S, H, TS = ri.init.copy(), wl.host_replica(ri.init, ri.log), np.zeros(ri.n_words, np.uint64)
     out = orc.round_oplist(S, H, TS, ri.granule, ri.batch, order, ri.log, 0)
     assert out["conflict"] == 0
     serial = _lww(ri.init, ri.log)
@@ -486,3 +486,15 @@ def test_host_cache_puts_log_replays(orc):
     orc.apply(S, np.zeros(N, np.uint64), log, 1000)
     assert np.array_equal(S, H)
     assert np.all(np.array([orc.cache_set(int(k), nsets) for k in keys]) % 2 == 1)
+
+
+def test_host_replica_matches_sequential_host_execution(orc):
+    """The generator's host replica equals the host writing the log entries
+    one by one in timestamp order."""
+    g = np.random.default_rng(11)
+    log = wl.host_log_uniform(g, 400, 0, 64, 0)
+    init = g.integers(0, 2 ** 32, size=64, dtype=np.uint64).astype(np.uint32)
+    H = init.copy()
+    for k in np.argsort(log["ts"]):
+        H[log["word"][k]] = log["value"][k]
+    assert np.array_equal(wl.host_replica(init, log), H)
