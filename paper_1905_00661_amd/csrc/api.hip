@@ -36,6 +36,7 @@ struct hetm_ctx {
     uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;
     void *log_staging = nullptr;
     DevCounters *cnt = nullptr;
+    HotCounters *hot = nullptr;
     DevCounters *snap_dev = nullptr;
     DevArgs *dargs = nullptr;
     uint64_t device_bytes = 0;
@@ -337,6 +338,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     TRY(dev_alloc(c, &c->ids, nG * 4));
     TRY(dev_alloc(c, &c->log_staging, k.log_capacity * c->log_entry_bytes));
     TRY(dev_alloc(c, &c->cnt, sizeof(DevCounters)));
+    TRY(dev_alloc(c, &c->hot, sizeof(HotCounters)));
     TRY(dev_alloc(c, &c->snap_dev, sizeof(DevCounters)));
     TRY(dev_alloc(c, &c->dargs, sizeof(DevArgs)));
     if (hipHostMalloc((void **)&c->hargs, sizeof(DevArgs), hipHostMallocDefault) != hipSuccess ||
@@ -356,6 +358,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
               hipMemsetAsync(c->rs, 0, nbw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->ws, 0, nbw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), s) == hipSuccess &&
+              hipMemsetAsync(c->hot, 0, sizeof(HotCounters), s) == hipSuccess &&
               hipMemsetAsync(c->blocksums, 0, nblocks * 4, s) == hipSuccess;
     if (ok)
         ok = init_image ? hipMemcpyAsync(c->stmr, init_image, N * k.word_bytes, hipMemcpyDefault, s) == hipSuccess
@@ -373,6 +376,8 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     a.stmr = c->stmr, a.locks = c->locks, a.ts = c->ts, a.rs = c->rs, a.ws = c->ws;
     a.suspect = c->suspect, a.blocksums = c->blocksums, a.blockruns = c->blockruns, a.ids_scratch = c->ids;
     a.cnt = c->cnt;
+    a.hot = c->hot;
+    a.gdiv = make_div32((uint32_t)G);
     a.n_words = N, a.word_bytes = k.word_bytes, a.granule = (uint32_t)G;
     a.stripe_shift = ilog2(k.lock_stripe_words);
     a.n_granules = (uint32_t)nG, a.n_bm_words = (uint32_t)nbw, a.retry_cap = c->cfg.retry_cap;
@@ -393,7 +398,7 @@ int hetm_free(hetm_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->suspect, c->blocksums, c->blockruns,
-                   c->ids, c->log_staging, c->cnt, c->snap_dev, c->dargs};
+                   c->ids, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->hargs) (void)hipHostFree(c->hargs);

@@ -91,9 +91,9 @@ struct WriteBuf {
     __device__ void write_back(Word *stmr) {
         for (uint32_t k = 0; k < n; ++k) st_agent(&stmr[at(k)], val[k][lane]);
     }
-    __device__ void mark_writes(uint32_t *rs, uint32_t *ws, uint32_t G) {
+    __device__ void mark_writes(uint32_t *rs, uint32_t *ws, const Div32 &G) {
         for (uint32_t k = 0; k < n; ++k) {
-            uint32_t g = div_granule(at(k), G);
+            uint32_t g = div32(at(k), G);
             bitmap_set(rs, g);
             bitmap_set(ws, g);
         }
@@ -147,14 +147,26 @@ __device__ __forceinline__ bool lane_turn(LaneState &ls, uint32_t n) {
     return true;
 }
 
+// Lane g of the grid starts with transaction g; later work comes from the
+// device queue, which hands out transactions n_lanes, n_lanes+1, ...
+__device__ __forceinline__ LaneState first_txn(uint32_t n) {
+    LaneState ls;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    ls.txn = g < n ? g : kDoneTxn;
+    return ls;
+}
+
 // Refill lanes without work from the device queue; returns false when the
 // whole wave is out of work.  Reached by all 64 lanes.
-__device__ __forceinline__ bool refill(LaneState &ls, DevCounters *cnt, uint32_t n) {
-    bool need = ls.txn == kNoTxn;
-    uint32_t got = wave_fetch_add(&cnt->queue_head, need);
-    if (need) {
-        ls.txn = got < n ? got : kDoneTxn;
-        ls.attempts = 0;
+__device__ __forceinline__ bool refill(LaneState &ls, HotCounters *hot, uint32_t n) {
+    const bool need = ls.txn == kNoTxn;
+    if (__ballot(need)) {
+        const uint32_t got = wave_fetch_add(&hot->queue_head.v, need);
+        if (need) {
+            const uint64_t t = (uint64_t)gridDim.x * blockDim.x + got;
+            ls.txn = t < n ? (uint32_t)t : kDoneTxn;
+            ls.attempts = 0;
+        }
     }
     return __ballot(ls.txn < n) != 0;
 }
@@ -203,15 +215,16 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     uint64_t *locks = a->locks;
     uint32_t *rs = a->rs, *ws = a->ws;
     DevCounters *cnt = a->cnt;
-    const uint32_t n = a->n_txns, sh = a->stripe_shift, G = a->granule, max_ops = a->max_ops;
+    const uint32_t n = a->n_txns, sh = a->stripe_shift, max_ops = a->max_ops;
+    const Div32 G = a->gdiv;
     const uint64_t N = a->n_words;
     const uint32_t *off = a->off, *idx = a->idx, *tid = a->tid;
     const uint8_t *nw = a->nw;
     uint32_t *res = (uint32_t *)a->results;
     WriteBuf<uint32_t, kOplistMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
-    LaneState ls;
+    LaneState ls = first_txn(n);
 
-    while (refill(ls, cnt, n)) {
+    while (refill(ls, a->hot, n)) {
         const bool act = lane_turn(ls, n);
         if (!__ballot(act)) {          // every lane is backing off
             __builtin_amdgcn_s_sleep(2);
@@ -240,7 +253,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
             ok &= !(l & kLockBit);
             sum1 += l;
         }
-        fence_acquire();
+        hw_order();
         wb.n = 0;
         if (ok) {
             for (uint32_t j = 0; j < L; ++j) {
@@ -251,19 +264,19 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
             }
             if (nwr) ok = wb.lock_all(locks, sh);
         }
-        fence_release();
-        uint32_t ticket = wave_fetch_add(&cnt->ticket, ok);
-        fence_acquire();
+        hw_order();
+        uint32_t ticket = wave_fetch_add(&a->hot->ticket.v, ok);
+        hw_order();
         if (ok) {
             uint64_t sum2 = 0;
             for (uint32_t j = 0; j < L && ok; ++j) sum2 += reread(locks, idx[o + j] >> sh, sh, wb, ok);
             ok &= sum2 == sum1;
         }
         if (ok) wb.write_back(stmr);
-        fence_release();
+        hw_order();
         if (wb.locked) wb.release(locks, sh, ok);
         if (ok) {
-            for (uint32_t j = nwr; j < L; ++j) bitmap_set(rs, div_granule(idx[o + j], G));
+            for (uint32_t j = nwr; j < L; ++j) bitmap_set(rs, div32(idx[o + j], G));
             wb.mark_writes(rs, ws, G);
         }
         settle(ls, act, malformed, ok, ticket, a->tickets, cnt, a->retry_cap);
@@ -282,13 +295,14 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
     uint64_t *locks = a->locks;
     uint32_t *rs = a->rs, *ws = a->ws;
     DevCounters *cnt = a->cnt;
-    const uint32_t n = a->n_txns, sh = a->stripe_shift, G = a->granule;
+    const uint32_t n = a->n_txns, sh = a->stripe_shift;
+    const Div32 G = a->gdiv;
     const uint64_t N = a->n_words;
     int64_t *res = (int64_t *)a->results;
     WriteBuf<uint64_t, 2> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
-    LaneState ls;
+    LaneState ls = first_txn(n);
 
-    while (refill(ls, cnt, n)) {
+    while (refill(ls, a->hot, n)) {
         const bool act = lane_turn(ls, n);
         if (!__ballot(act)) {          // every lane is backing off
             __builtin_amdgcn_s_sleep(2);
@@ -312,7 +326,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
             ok = !((l1 | l2) & kLockBit);
             sum1 = l1 + l2;
         }
-        fence_acquire();
+        hw_order();
         wb.n = 0;
         if (ok) {
             int64_t bs = (int64_t)ld_agent(&stmr[s]);
@@ -327,20 +341,20 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
                 ok = wb.lock_all(locks, sh);
             }
         }
-        fence_release();
-        uint32_t ticket = wave_fetch_add(&cnt->ticket, ok);
-        fence_acquire();
+        hw_order();
+        uint32_t ticket = wave_fetch_add(&a->hot->ticket.v, ok);
+        hw_order();
         if (ok) {
             uint64_t sum2 = reread(locks, s >> sh, sh, wb, ok);
             sum2 += reread(locks, d >> sh, sh, wb, ok);
             ok &= sum2 == sum1;
         }
         if (ok) wb.write_back(stmr);
-        fence_release();
+        hw_order();
         if (wb.locked) wb.release(locks, sh, ok);
         if (ok) {
-            bitmap_set(rs, div_granule(s, G));
-            bitmap_set(rs, div_granule(d, G));
+            bitmap_set(rs, div32(s, G));
+            bitmap_set(rs, div32(d, G));
             wb.mark_writes(rs, ws, G);
         }
         settle(ls, act, act && (s >= N || d >= N), ok, ticket, a->tickets, cnt, a->retry_cap);
@@ -376,13 +390,14 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
     uint64_t *locks = a->locks;
     uint32_t *rs = a->rs, *ws = a->ws;
     DevCounters *cnt = a->cnt;
-    const uint32_t n = a->n_txns, sh = a->stripe_shift, G = a->granule;
+    const uint32_t n = a->n_txns, sh = a->stripe_shift;
+    const Div32 G = a->gdiv;
     const uint64_t nsets = a->n_words / kSetWords;
     uint32_t *res = (uint32_t *)a->results;
     WriteBuf<uint32_t, kCacheMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
-    LaneState ls;
+    LaneState ls = first_txn(n);
 
-    while (refill(ls, cnt, n)) {
+    while (refill(ls, a->hot, n)) {
         const bool act = lane_turn(ls, n);
         if (!__ballot(act)) {          // every lane is backing off
             __builtin_amdgcn_s_sleep(2);
@@ -409,7 +424,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
                 ok &= !(l & kLockBit);
                 sum1 += l;
             }
-        fence_acquire();
+        hw_order();
         uint32_t hdr[25];
 #pragma unroll
         for (uint32_t j = 0; j < 25; ++j) hdr[j] = (ok && j < nh) ? ld_agent(&stmr[base + header_word(j)]) : 0u;
@@ -425,7 +440,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
                 ok &= !(l & kLockBit);
                 sum1 += l;
             }
-        fence_acquire();
+        hw_order();
         wb.n = 0;
         uint32_t *r = res + 9ull * (act ? ls.txn : 0);
         if (ok && !put) {
@@ -462,9 +477,9 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
             wb.put(base + kSetStamp, tv);
         }
         if (ok && wb.n) ok = wb.lock_all(locks, sh);
-        fence_release();
-        uint32_t ticket = wave_fetch_add(&cnt->ticket, ok);
-        fence_acquire();
+        hw_order();
+        uint32_t ticket = wave_fetch_add(&a->hot->ticket.v, ok);
+        hw_order();
         if (ok) {
             uint64_t sum2 = 0;
             for (uint32_t j = 0; j < nh && ok; ++j) sum2 += reread(locks, (base + header_word(j)) >> sh, sh, wb, ok);
@@ -474,12 +489,12 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
             ok &= sum2 == sum1;
         }
         if (ok) wb.write_back(stmr);
-        fence_release();
+        hw_order();
         if (wb.locked) wb.release(locks, sh, ok);
         if (ok) {
-            for (uint32_t j = 0; j < nh; ++j) bitmap_set(rs, div_granule(base + header_word(j), G));
+            for (uint32_t j = 0; j < nh; ++j) bitmap_set(rs, div32(base + header_word(j), G));
             if (get_hit)
-                for (uint32_t i = 0; i < 8; ++i) bitmap_set(rs, div_granule(base + kValBase + 8 * hit + i, G));
+                for (uint32_t i = 0; i < 8; ++i) bitmap_set(rs, div32(base + kValBase + 8 * hit + i, G));
             wb.mark_writes(rs, ws, G);
         }
         settle(ls, act, act && (key == 0 || put > 1), ok, ticket, a->tickets, cnt, a->retry_cap);
@@ -488,7 +503,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
 }
 
 __global__ void k_begin_batch(const DevArgs *__restrict__ a) {
-    if (threadIdx.x == 0) st_agent(&a->cnt->queue_head, 0u);
+    if (threadIdx.x == 0) st_agent(&a->hot->queue_head.v, 0u);
 }
 
 }  // namespace

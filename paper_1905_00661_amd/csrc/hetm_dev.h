@@ -19,11 +19,45 @@ constexpr uint32_t kNoTxn = 0xFFFFFFFFu;
 constexpr uint32_t kDoneTxn = 0xFFFFFFFEu;
 
 // Counters the kernels update during a round (device memory).
+// Exact 32-bit division by a runtime constant d >= 1 (Lemire, Kaser and
+// Kurz, "Faster remainder by direct computation", 2019): with
+// M = floor((2^64 - 1) / d) + 1, n / d = high 64 bits of the 128-bit
+// product M * n for every 32-bit n.  d = 1 and powers of two use a shift.
+struct Div32 {
+    uint64_t magic;
+    uint32_t shift;
+    uint32_t use_shift;
+};
+inline Div32 make_div32(uint32_t d) {
+    Div32 r{0, 0, 0};
+    if ((d & (d - 1)) == 0) {
+        r.use_shift = 1;
+        while ((1u << r.shift) < d) ++r.shift;
+    } else {
+        r.magic = UINT64_MAX / d + 1;
+    }
+    return r;
+}
+__device__ __forceinline__ uint32_t div32(uint32_t n, const Div32 &d) {
+    return d.use_shift ? (n >> d.shift) : (uint32_t)__umul64hi(d.magic, (uint64_t)n);
+}
+
+// The two counters every wave hits during execution sit on cache lines of
+// their own (same-address atomics serialize at ~90 M/s per line).
+struct alignas(256) HotCounter {
+    uint32_t v;
+    uint32_t pad_[63];
+};
+struct HotCounters {
+    HotCounter ticket;            // next commit ticket
+    HotCounter queue_head;        // next transaction of the current batch (after the static first pass)
+};
+
 struct DevCounters {
     uint32_t conflict;            // OR of the validation flags of the round
     int32_t error;                // first latched error code (HETM_E*), 0 if none
-    uint32_t ticket;              // next commit ticket
-    uint32_t queue_head;          // next transaction of the current batch
+    uint32_t ticket_snapshot;     // tickets handed out in the round (at finish)
+    uint32_t unused_;
     unsigned long long max_ts;    // largest ts of this round's applied log chunks
     unsigned long long floor_ts;  // watermark: largest ts applied by earlier rounds
     unsigned long long committed; // local commits in this round
@@ -51,6 +85,8 @@ struct DevArgs {
     uint32_t *blockruns;
     uint32_t *ids_scratch;  // ceil(N/G) dirty granule ids
     DevCounters *cnt;
+    HotCounters *hot;
+    Div32 gdiv;             // division by G
     uint64_t n_words;
     uint32_t word_bytes;
     uint32_t granule;       // G
@@ -102,7 +138,21 @@ __device__ __forceinline__ bool cas_agent(uint64_t *p, uint64_t expect, uint64_t
 }
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void fence_acq_rel() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent"); }
+
+// Orders this wave's device-coherent accesses: every earlier vector memory
+// operation has completed before any later one issues.  The transactional
+// kernels touch shared data only through agent-scope atomics (sc1 loads,
+// stores and RMWs, performed at the device coherence point), so completion
+// order is all they need; an agent-scope C++ fence would in addition write
+// back (release) or invalidate (acquire) the whole XCD L2 for the sake of
+// plain accesses, which measures 6x (acquire) to 30x (release) slower than
+// the load it orders.  The signal fences keep the compiler from moving
+// memory operations across the wait.
+__device__ __forceinline__ void hw_order() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 __device__ __forceinline__ void latch_error(DevCounters *c, int32_t code, uint32_t where) {
     int32_t zero = 0;
@@ -134,14 +184,15 @@ __device__ __forceinline__ uint32_t wave_fetch_add(uint32_t *ctr, bool want) {
 }
 
 // Sets bit g of an agent-visible bitmap; skips the atomic when the bit is
-// already visible as set (bits only go 0 -> 1 within a round).
+// already set (bits only go 0 -> 1 within a round).  The test load is
+// device-coherent so bits set from other XCDs are seen; bitmap lines stay
+// cache-resident, so the test costs far less than the atomic it avoids.
 __device__ __forceinline__ void bitmap_set(uint32_t *bm, uint32_t g) {
     uint32_t w = g >> 5, b = 1u << (g & 31);
-    uint32_t cur = __hip_atomic_load(bm + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    uint32_t cur = ld_agent(bm + w);
     if (!(cur & b)) __hip_atomic_fetch_or(bm + w, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint32_t div_granule(uint64_t w, uint32_t G) { return (uint32_t)(w / G); }
 
 // ------------------------------------------------------------- launchers
 // Host-side launch wrappers, defined next to their kernels.  `a` is the

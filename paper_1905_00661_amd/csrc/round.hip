@@ -58,7 +58,7 @@ template <typename E>
 __global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a) {
     const E *log = (const E *)a->log;
     const uint64_t n = a->n_log, N = a->n_words;
-    const uint32_t G = a->granule;
+    const Div32 G = a->gdiv;
     const uint32_t *rs = a->rs;
     uint32_t *flags = a->flags;
     DevCounters *cnt = a->cnt;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a)
             } else if (e.ts <= floor_ts || e.ts >= kTsLimit) {
                 latch_error(cnt, HETM_EORDER, (uint32_t)k);
             } else {
-                const uint32_t g = div_granule(e.word, G);
+                const uint32_t g = div32(e.word, G);
                 f = (rs[g >> 5] >> (g & 31)) & 1u;
                 mx = e.ts > mx ? e.ts : mx;
             }
@@ -88,11 +88,29 @@ __global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a)
         if (flags && lane == 0) store_bits(flags, kb, m, nflagw);
         conflict |= m != 0;
     }
-    // staged per chunk: a chunk that fails its preconditions must not count
+    // Staged per chunk (a chunk that fails its preconditions must not count),
+    // reduced per block first: same-address atomics serialize, so each block
+    // issues at most one, and only when it raises the value.
+    __shared__ unsigned long long s_mx[256 / kWave];
+    __shared__ uint32_t s_cf[256 / kWave];
     mx = wave_max_u64(mx);
+    const uint64_t cf = __ballot(conflict);
     if (lane == 0) {
-        if (mx) __hip_atomic_fetch_max(&cnt->chunk_max_ts, (unsigned long long)mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (conflict) __hip_atomic_fetch_or(&cnt->chunk_conflict, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_mx[threadIdx.x / kWave] = mx;
+        s_cf[threadIdx.x / kWave] = cf != 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long bm = 0;
+        uint32_t bc = 0;
+        for (uint32_t i = 0; i < blockDim.x / kWave; ++i) {
+            bm = s_mx[i] > bm ? s_mx[i] : bm;
+            bc |= s_cf[i];
+        }
+        if (bm > ld_agent(&cnt->chunk_max_ts))
+            __hip_atomic_fetch_max(&cnt->chunk_max_ts, bm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (bc && !ld_agent(&cnt->chunk_conflict))
+            __hip_atomic_fetch_or(&cnt->chunk_conflict, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -297,8 +315,8 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         DevCounters c;
         c.conflict = ld_agent(&cnt->conflict);
         c.error = err;
-        c.ticket = ld_agent(&cnt->ticket);
-        c.queue_head = 0;
+        c.ticket_snapshot = ld_agent(&a->hot->ticket.v);
+        c.unused_ = 0;
         c.max_ts = ld_agent(&cnt->max_ts);
         c.floor_ts = ld_agent(&cnt->floor_ts);
         c.committed = ld_agent(&cnt->committed);
@@ -315,7 +333,7 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
             c.floor_ts = f;
             st_agent(&cnt->floor_ts, (unsigned long long)f);
             st_agent(&cnt->conflict, 0u);
-            st_agent(&cnt->ticket, 0u);
+            st_agent(&a->hot->ticket.v, 0u);
             st_agent(&cnt->max_ts, 0ull);
             st_agent(&cnt->committed, 0ull);
             st_agent(&cnt->retries, 0ull);
