@@ -81,8 +81,8 @@ typedef struct {
     uint64_t log_capacity;       /* most log entries per hetm_validate_apply_log */
     uint32_t mode;               /* HETM_MODE_*                                  */
     int32_t  device;             /* HIP device ordinal                           */
-    void    *stream;             /* hipStream_t for all work; NULL = a stream the
-                                    library creates (default priority)          */
+    void    *stream;             /* hipStream_t for all work; NULL = the device's
+                                    default (null) stream                        */
     uint32_t exec_workgroups;    /* transaction-kernel workgroups; 0 = auto      */
     uint32_t retry_cap;          /* local attempts per transaction; 0 = 1<<20    */
 } hetm_config;
@@ -255,6 +255,39 @@ int hetm_stats_get(hetm_ctx *ctx, hetm_stats *out);
 #define HETM_STATE_LOCKS 4u
 int hetm_read_state(hetm_ctx *ctx, uint32_t what, void *dst, uint64_t bytes);
 uint64_t hetm_state_bytes(hetm_ctx *ctx, uint32_t what);
+
+/* --------------------------------------------------- host side of a round */
+
+/* The host's worker threads (§IV-A) running transactions on the host
+ * replica and producing the round's write log: at each commit the
+ * <word, value, timestamp> of every updated word is appended to a
+ * thread-local log (§IV-B, CPU instrumentation); the logs are concatenated
+ * at the round cut, in no particular order.  Concurrency control: two-phase
+ * locking over per-stripe spinlocks (stripe = lock_stripe_words words),
+ * commit timestamps from one global clock starting after ts_start, taken
+ * while the locks are held, so timestamps totally order the updates of each
+ * word.  host_replica (host memory, N*W bytes) is borrowed for the handle's
+ * lifetime.  Errors: EINVAL, ENOMEM. */
+typedef struct hetm_host_tm hetm_host_tm;
+int hetm_host_tm_create(void *host_replica, uint64_t n_words, uint32_t word_bytes, uint32_t lock_stripe_words,
+                        uint64_t ts_start, hetm_host_tm **out);
+int hetm_host_tm_free(hetm_host_tm *tm);
+uint64_t hetm_host_tm_clock(hetm_host_tm *tm);     /* last timestamp handed out */
+
+/* n bank transfers (W = 8: move amt[i] from src[i] to dst[i] if src != dst
+ * and the source balance covers it) on n_threads threads.  ts_out[i]
+ * (host, n) receives transaction i's commit timestamp; log_out (host,
+ * log_capacity entries) receives two entries per applied transfer;
+ * *n_log_out the entry count (ECAPACITY if it exceeds log_capacity). */
+int hetm_host_run_transfers(hetm_host_tm *tm, const uint32_t *src, const uint32_t *dst, const uint32_t *amt,
+                            uint64_t n, uint32_t n_threads, uint64_t *ts_out, hetm_log_entry8 *log_out,
+                            uint64_t log_capacity, uint64_t *n_log_out);
+
+/* n PUTs of keys[i] (nonzero) into the CACHE layout (W = 4) with way and
+ * set stamps := (uint32_t) commit timestamp; 12 log entries per PUT. */
+int hetm_host_run_cache_puts(hetm_host_tm *tm, const uint64_t *keys, uint64_t n, uint32_t n_threads,
+                             uint64_t *ts_out, hetm_log_entry4 *log_out, uint64_t log_capacity,
+                             uint64_t *n_log_out);
 
 #ifdef __cplusplus
 }

@@ -60,8 +60,8 @@ def lib() -> ctypes.CDLL:
         L.orc_mix64.argtypes, L.orc_mix64.restype = [U64], U64
         L.orc_cache_set.argtypes, L.orc_cache_set.restype = [U64, U64], U64
         L.orc_cache_value.argtypes, L.orc_cache_value.restype = [U64, ctypes.c_uint32, P], None
-        L.orc_host_transfers.argtypes, L.orc_host_transfers.restype = [P, U64, P, P, P, U64, U64, P], U64
-        L.orc_host_cache_puts.argtypes, L.orc_host_cache_puts.restype = [P, U64, P, U64, U64, P], U64
+        L.orc_host_transfers.argtypes, L.orc_host_transfers.restype = [P, U64, P, P, P, P, U64, P], U64
+        L.orc_host_cache_puts.argtypes, L.orc_host_cache_puts.restype = [P, U64, P, P, U64, P], U64
         _lib = L
     return _lib
 
@@ -191,17 +191,21 @@ def cache_value(key: int, tid: int) -> np.ndarray:
     return v
 
 
-def host_transfers(H: np.ndarray, batch, ts0: int) -> np.ndarray:
-    log = np.zeros(2 * batch.n, LOG8)
-    m = lib().orc_host_transfers(_p(H), H.shape[0], _p(batch.src), _p(batch.dst), _p(batch.amt),
-                                 batch.n, ts0, _p(log))
+def host_transfers(H: np.ndarray, batch, ts: np.ndarray) -> np.ndarray:
+    """Replays host transfers serially in the given order with the given
+    commit timestamps; returns the log."""
+    ts = np.ascontiguousarray(ts, dtype=np.uint64)
+    log = np.zeros(max(2 * batch.n, 1), LOG8)
+    m = lib().orc_host_transfers(_p(H), H.shape[0], _p(batch.src), _p(batch.dst), _p(batch.amt), _p(ts),
+                                 batch.n, _p(log))
     return log[:m].copy()
 
 
-def host_cache_puts(H: np.ndarray, keys: np.ndarray, ts0: int) -> np.ndarray:
+def host_cache_puts(H: np.ndarray, keys: np.ndarray, ts: np.ndarray) -> np.ndarray:
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
-    log = np.zeros(12 * keys.shape[0], LOG4)
-    m = lib().orc_host_cache_puts(_p(H), H.shape[0], _p(keys), keys.shape[0], ts0, _p(log))
+    ts = np.ascontiguousarray(ts, dtype=np.uint64)
+    log = np.zeros(max(12 * keys.shape[0], 1), LOG4)
+    m = lib().orc_host_cache_puts(_p(H), H.shape[0], _p(keys), _p(ts), keys.shape[0], _p(log))
     return log[:m].copy()
 
 

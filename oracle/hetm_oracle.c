@@ -260,13 +260,16 @@ int orc_replay_cache(uint32_t *S, uint64_t N, uint64_t G,
     return ORC_OK;
 }
 
-/* ------------------------------------------- host side (test inputs only) */
+/* ---------------------------------------------------- host side replay */
 
 /*
- * The host runs its own transactions serially in timestamp order on its
- * replica H and logs the <word, value, timestamp> of every word each
- * committed transaction updated (§IV-B "CPU instrumentation").  These two
- * helpers produce such logs for the transfer and cache workloads.
+ * The host runs its own transactions and logs the <word, value, timestamp>
+ * of every word each committed transaction updated (§IV-B "CPU
+ * instrumentation"); timestamps totally order the updates of each word.
+ * These helpers replay host transactions serially in the order given (the
+ * caller sorts them by their commit timestamps ts[]) on replica H and emit
+ * the log that replay produces, so a host TM's concurrent result and log
+ * can be checked against it.
  * Entry layout, W = 8: {u32 word, u32 pad, u64 value, u64 ts};
  * W = 4: {u32 word, u32 value, u64 ts}.  Return the number of entries.
  */
@@ -274,37 +277,35 @@ typedef struct { uint32_t word; uint32_t value; uint64_t ts; } orc_entry4;
 typedef struct { uint32_t word; uint32_t pad; uint64_t value; uint64_t ts; } orc_entry8;
 
 uint64_t orc_host_transfers(int64_t *H, uint64_t N, const uint32_t *src, const uint32_t *dst,
-                            const uint32_t *amt, uint64_t n, uint64_t ts0, orc_entry8 *log)
+                            const uint32_t *amt, const uint64_t *ts, uint64_t n, orc_entry8 *log)
 {
-    uint64_t m = 0, ts = ts0;
+    uint64_t m = 0;
     for (uint64_t t = 0; t < n; t++) {
         if (src[t] >= N || dst[t] >= N) continue;
         int64_t bs = H[src[t]], bd = H[dst[t]];
         if (src[t] == dst[t] || bs < (int64_t)amt[t]) continue;
-        ts++;
         H[src[t]] = bs - (int64_t)amt[t];
         H[dst[t]] = bd + (int64_t)amt[t];
-        log[m++] = (orc_entry8){src[t], 0, (uint64_t)H[src[t]], ts};
-        log[m++] = (orc_entry8){dst[t], 0, (uint64_t)H[dst[t]], ts};
+        log[m++] = (orc_entry8){src[t], 0, (uint64_t)H[src[t]], ts[t]};
+        log[m++] = (orc_entry8){dst[t], 0, (uint64_t)H[dst[t]], ts[t]};
     }
     return m;
 }
 
-uint64_t orc_host_cache_puts(uint32_t *H, uint64_t N, const uint64_t *key, uint64_t n,
-                             uint64_t ts0, orc_entry4 *log)
+uint64_t orc_host_cache_puts(uint32_t *H, uint64_t N, const uint64_t *key, const uint64_t *ts, uint64_t n,
+                             orc_entry4 *log)
 {
     uint64_t nsets = N / C_SET_WORDS, m = 0;
     for (uint64_t t = 0; t < n; t++) {
-        uint64_t ts = ts0 + t + 1;
         uint64_t base = orc_cache_set(key[t], nsets) * C_SET_WORDS;
         uint32_t res[9];
-        cache_op(H, nsets, 1, key[t], 1, (uint32_t)ts, res, NULL, NULL);
+        cache_op(H, nsets, 1, key[t], 1, (uint32_t)ts[t], res, NULL, NULL);
         uint32_t v = res[0] & 7u;
         uint32_t written[12] = {C_KEY(v), C_KEY(v) + 1, C_VAL(v) + 0, C_VAL(v) + 1,
                                 C_VAL(v) + 2, C_VAL(v) + 3, C_VAL(v) + 4, C_VAL(v) + 5,
                                 C_VAL(v) + 6, C_VAL(v) + 7, C_STAMP(v), C_SETSTAMP};
         for (uint32_t i = 0; i < 12; i++)
-            log[m++] = (orc_entry4){(uint32_t)(base + written[i]), H[base + written[i]], ts};
+            log[m++] = (orc_entry4){(uint32_t)(base + written[i]), H[base + written[i]], ts[t]};
     }
     return m;
 }

@@ -12,7 +12,7 @@ LIB = os.path.join(PKG, "libhetm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-FLAGS = [
+FLAGS = ["-pthread",
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
@@ -21,7 +21,7 @@ FLAGS = [
 
 
 def sources() -> list[str]:
-    return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
+    return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")) + glob.glob(os.path.join(PKG, "csrc", "*.cpp")))
 
 
 def build(verbose: bool = False) -> str:

@@ -22,8 +22,8 @@ using namespace hetm;
 
 struct hetm_ctx {
     hetm_config cfg{};
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    hipStream_t stream = nullptr;      // the caller's stream (nullptr = default stream)
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture the round graph
     int device = 0;
     uint32_t exec_wg = 0;
     uint32_t log_entry_bytes = 16;
@@ -232,9 +232,12 @@ int check_host_replica(hetm_ctx *c, void *host, const void **dev) {
     return HETM_OK;
 }
 
+// Captures the round once on a private stream (the default stream cannot
+// be captured); the instantiated graph is launched on the caller's stream.
 int build_graph(hetm_ctx *c) {
     if (c->graph_exec) return HETM_OK;
-    hipStream_t s = c->stream;
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t s = c->cap_stream;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     (void)hipMemcpyAsync(c->dargs, c->hargs, sizeof(DevArgs), hipMemcpyHostToDevice, s);
     launch_exec(c->args.program, c->dargs, c->exec_wg, s);
@@ -313,15 +316,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
         delete c;
         return HETM_EDEVICE;
     }
-    if (k.stream) {
-        c->stream = (hipStream_t)k.stream;
-    } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete c;
-            return HETM_EDEVICE;
-        }
-        c->own_stream = true;
-    }
+    c->stream = (hipStream_t)k.stream;
     const uint64_t N = k.n_words, G = k.granule_words;
     const uint64_t nG = (N + G - 1) / G;
     const uint64_t nbw = (nG + 31) / 32;
@@ -404,7 +399,7 @@ int hetm_free(hetm_ctx *c) {
     if (c->hargs) (void)hipHostFree(c->hargs);
     if (c->snap_host) (void)hipHostFree(c->snap_host);
     if (c->cnt_host) (void)hipHostFree(c->cnt_host);
-    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return HETM_OK;
 }

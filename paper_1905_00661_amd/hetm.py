@@ -30,7 +30,8 @@ HETM_STATE_STMR, HETM_STATE_TS, HETM_STATE_RS, HETM_STATE_WS, HETM_STATE_LOCKS =
 
 EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_apply_log",
            "hetm_copyback_dirty", "hetm_round", "hetm_strerror", "hetm_last_error", "hetm_sync",
-           "hetm_stats_get", "hetm_read_state", "hetm_state_bytes"]
+           "hetm_stats_get", "hetm_read_state", "hetm_state_bytes", "hetm_host_tm_create",
+           "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts"]
 
 P = ctypes.c_void_p
 U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -106,6 +107,11 @@ def lib() -> ctypes.CDLL:
             "hetm_stats_get": ([P, ctypes.POINTER(hetm_stats)], ctypes.c_int),
             "hetm_read_state": ([P, U32, P, U64], ctypes.c_int),
             "hetm_state_bytes": ([P, U32], U64),
+            "hetm_host_tm_create": ([P, U64, U32, U32, U64, ctypes.POINTER(P)], ctypes.c_int),
+            "hetm_host_tm_free": ([P], ctypes.c_int),
+            "hetm_host_tm_clock": ([P], U64),
+            "hetm_host_run_transfers": ([P, P, P, P, U64, U32, P, P, U64, ctypes.POINTER(U64)], ctypes.c_int),
+            "hetm_host_run_cache_puts": ([P, P, U64, U32, P, P, U64, ctypes.POINTER(U64)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -180,6 +186,60 @@ def hetm_read_state(ctx: int, what: int, dst: int, nbytes: int) -> None:
 
 def hetm_state_bytes(ctx: int, what: int) -> int:
     return int(lib().hetm_state_bytes(ctx, what))
+
+
+# ------------------------------------------------------------- host side
+
+class HostTM:
+    """The host's TM threads over a host replica (numpy array, borrowed)."""
+
+    LOG4 = np.dtype([("word", "<u4"), ("value", "<u4"), ("ts", "<u8")])
+    LOG8 = np.dtype([("word", "<u4"), ("pad", "<u4"), ("value", "<u8"), ("ts", "<u8")])
+
+    def __init__(self, replica: np.ndarray, stripe: int = 1, ts_start: int = 0):
+        assert replica.flags["C_CONTIGUOUS"] and replica.itemsize in (4, 8)
+        self.replica = replica
+        h = P()
+        _check(lib().hetm_host_tm_create(replica.ctypes.data, replica.shape[0], replica.itemsize, stripe, ts_start,
+                                         ctypes.byref(h)), "hetm_host_tm_create")
+        self.h = h.value
+
+    def close(self):
+        if self.h:
+            lib().hetm_host_tm_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # noqa: BLE001
+            pass
+
+    @property
+    def clock(self) -> int:
+        return int(lib().hetm_host_tm_clock(self.h))
+
+    def transfers(self, src, dst, amt, threads: int = 4):
+        n = len(src)
+        src, dst, amt = (np.ascontiguousarray(x, dtype=np.uint32) for x in (src, dst, amt))
+        ts = np.zeros(max(n, 1), np.uint64)
+        log = np.zeros(max(2 * n, 1), self.LOG8)
+        m = U64(0)
+        _check(lib().hetm_host_run_transfers(self.h, src.ctypes.data, dst.ctypes.data, amt.ctypes.data, n, threads,
+                                             ts.ctypes.data, log.ctypes.data, log.shape[0], ctypes.byref(m)),
+               "hetm_host_run_transfers")
+        return ts[:n], log[:m.value]
+
+    def cache_puts(self, keys, threads: int = 4):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        n = keys.shape[0]
+        ts = np.zeros(max(n, 1), np.uint64)
+        log = np.zeros(max(12 * n, 1), self.LOG4)
+        m = U64(0)
+        _check(lib().hetm_host_run_cache_puts(self.h, keys.ctypes.data, n, threads, ts.ctypes.data,
+                                              log.ctypes.data, log.shape[0], ctypes.byref(m)),
+               "hetm_host_run_cache_puts")
+        return ts[:n], log[:m.value]
 
 
 # ------------------------------------------------------------- torch helpers

@@ -394,7 +394,7 @@ def test_transfer_chain_closed_form(orc, a, B):
 def test_host_transfers_log_replays(orc):
     d = wl.c3(n_accounts=1 << 12, host_accounts=1 << 8, n_txn=10, n_host=3000)
     H = d["init"].copy()
-    log = orc.host_transfers(H, d["host"], 500)
+    log = orc.host_transfers(H, d["host"], np.arange(501, 501 + d["host"].n, dtype=np.uint64))
     assert int(H.sum()) == 1000 * (1 << 12)
     S = d["init"].copy()
     orc.apply(S, np.zeros(S.shape[0], np.uint64), log, 500)
@@ -480,7 +480,7 @@ def test_host_cache_puts_log_replays(orc):
     N = nsets * 128
     H = np.zeros(N, np.uint32)
     keys = np.random.default_rng(7).integers(1, 300, size=500, dtype=np.uint64) | np.uint64(1)
-    log = orc.host_cache_puts(H, keys, 1000)
+    log = orc.host_cache_puts(H, keys, np.arange(1001, 1501, dtype=np.uint64))
     assert log.shape[0] == 12 * 500
     S = np.zeros(N, np.uint32)
     orc.apply(S, np.zeros(N, np.uint64), log, 1000)
