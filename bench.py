@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--stripe", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a plain 256 MiB device copy, the known-size reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -101,6 +103,14 @@ def main():
     log(f"inputs generated in {time.time() - t0:.1f}s")
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.calibrate:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     rounds = args.warmup + args.steps
 
     # per-round logs resident in HBM: same words/values, timestamps shifted
