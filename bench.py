@@ -82,10 +82,11 @@ def main():
     ap.add_argument("--granule", type=int, default=16)
     ap.add_argument("--p-hot", type=float, default=0.5)
     ap.add_argument("--stripe", type=int, default=1)
+    ap.add_argument("--exec-wg", type=int, default=0, help="transaction-kernel workgroups (0 = occupancy x CUs)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
-                    help="first run a plain 256 MiB device copy, the known-size reference for HBM counters")
+                    help="first run a plain 1 GiB device copy, the known-size reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -104,9 +105,12 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     if args.calibrate:
-        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
         a.fill_(1)
+        big = torch.empty(1 << 30, dtype=torch.uint8, device=dev)   # evicts `a` from the caches
+        big.fill_(2)
+        del big
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
@@ -128,7 +132,7 @@ def main():
 
     def run(mode: int, k_steps: int, warm: int):
         ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=n_txn,
-                         log_capacity=n_log, mode=mode)
+                         log_capacity=n_log, mode=mode, exec_workgroups=args.exec_wg)
         b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
         flags = torch.zeros(((n_log + 31) // 32) * 4, dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()

@@ -85,6 +85,12 @@ typedef struct {
                                     default (null) stream                        */
     uint32_t exec_workgroups;    /* transaction-kernel workgroups; 0 = auto      */
     uint32_t retry_cap;          /* local attempts per transaction; 0 = 1<<20    */
+    uint32_t async_merge;        /* GRAPH mode only: 1 = double-buffered merge --
+                                    the round gathers its dirty granules into one
+                                    of two HBM staging buffers and a copy stream
+                                    writes them to the host replica while the
+                                    next round executes (GPU double buffering,
+                                    §IV-D); 0 = the merge copy ends the round    */
 } hetm_config;
 
 /* One host log entry (§IV-B, CPU instrumentation): the word a committed
@@ -218,6 +224,9 @@ typedef struct {
     uint64_t n_dirty;          /* write-set granules merged                     */
     uint64_t n_runs;           /* maximal runs of consecutive dirty granules    */
     uint64_t max_ts;           /* watermark after the round                     */
+    uint32_t merge_pending;    /* 1: the copy to the host replica is still in
+                                  flight (async_merge); hetm_sync waits for it   */
+    uint32_t pad_;
     double   us_exec;          /* step times from HIP events (PLAIN mode)       */
     double   us_validate;
     double   us_merge;
@@ -225,7 +234,12 @@ typedef struct {
 } hetm_round_result;
 
 /* A whole round: execution, validation+apply, merge, reset, in the
- * context's mode.  PLAIN launches one kernel per step and reads the
+ * context's mode.  With async_merge, a successful round returns as soon as
+ * its dirty granules are staged in HBM (merge_pending = 1); the host replica
+ * is complete after hetm_sync or after a later round (the next round waits
+ * for the staging buffer it reuses); a conflicting round first waits for the
+ * previous round's copy, then restores its dirty granules from the host
+ * replica before returning.  PLAIN launches one kernel per step and reads the
  * outcome on the host before the merge; GRAPH replays one captured hipGraph
  * whose merge kernels read the outcome on the device.  Synchronizes and
  * fills *res.  On conflict every transaction of the round is reported
@@ -236,7 +250,9 @@ int hetm_round(hetm_ctx *ctx, const hetm_round_args *args, hetm_round_result *re
 
 const char *hetm_strerror(int code);
 const char *hetm_last_error(hetm_ctx *ctx);   /* detail of the last failure */
-int hetm_sync(hetm_ctx *ctx);                 /* waits; returns a latched error */
+int hetm_sync(hetm_ctx *ctx);                 /* waits for all work, including
+                                                 pending merge copies; returns a
+                                                 latched error */
 
 typedef struct {
     uint64_t rounds, rounds_conflicted, txns_committed, txns_aborted, local_retries;

@@ -52,6 +52,17 @@ struct hetm_ctx {
     hipGraphExec_t graph_exec = nullptr;
     uint32_t graph_program = 0;
 
+    // double-buffered merge (GRAPH mode with async_merge)
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t graph_done[2] = {};
+    hipEvent_t copied[2] = {};
+    bool pending[2] = {false, false};
+    int buf = 0;
+    void *staging[2] = {};
+    uint32_t *stage_ids[2] = {};
+    uint32_t *stage_count[2] = {};
+    const void *pending_host = nullptr;
+
     bool in_validation = false;      // this round's log has started
     hetm_stats stats{};
     char err[512] = {0};
@@ -232,6 +243,13 @@ int check_host_replica(hetm_ctx *c, void *host, const void **dev) {
     return HETM_OK;
 }
 
+// Waits until every staged merge copy has reached the host replica.
+int drain_merges(hetm_ctx *c) {
+    if (c->copy_stream) HIP_TRY(c, hipStreamSynchronize(c->copy_stream));
+    c->pending[0] = c->pending[1] = false;
+    return HETM_OK;
+}
+
 // Captures the round once on a private stream (the default stream cannot
 // be captured); the instantiated graph is launched on the caller's stream.
 int build_graph(hetm_ctx *c) {
@@ -244,7 +262,10 @@ int build_graph(hetm_ctx *c) {
     launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
     launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
     launch_compact(c->dargs, c->args.n_scan_blocks, s);
-    launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
+    if (c->cfg.async_merge)
+        launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
+    else
+        launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
     launch_finish(c->dargs, c->snap_dev, c->args.n_bm_words, s);
     (void)hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, s);
     hipGraph_t g = nullptr;
@@ -295,7 +316,8 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     if (k.n_words == 0 || k.n_words > (1ull << 32) || (k.word_bytes != 4 && k.word_bytes != 8) ||
         k.granule_words == 0 || !is_pow2(k.lock_stripe_words) || k.max_txn_ops == 0 || k.max_txn_ops > 64 ||
         k.batch_capacity == 0 || k.batch_capacity >= (1ull << 32) || k.log_capacity == 0 ||
-        k.log_capacity >= (1ull << 32) || k.mode > HETM_MODE_GRAPH)
+        k.log_capacity >= (1ull << 32) || k.mode > HETM_MODE_GRAPH || k.async_merge > 1 ||
+        (k.async_merge && k.mode != HETM_MODE_GRAPH))
         return HETM_EINVAL;
     hetm_ctx *c = new (std::nothrow) hetm_ctx();
     if (!c) return HETM_ENOMEM;
@@ -336,6 +358,23 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     TRY(dev_alloc(c, &c->hot, sizeof(HotCounters)));
     TRY(dev_alloc(c, &c->snap_dev, sizeof(DevCounters)));
     TRY(dev_alloc(c, &c->dargs, sizeof(DevArgs)));
+    if (k.async_merge) {
+        for (int b = 0; b < 2; ++b) {
+            TRY(dev_alloc(c, &c->staging[b], nG * G * k.word_bytes));
+            TRY(dev_alloc(c, &c->stage_ids[b], nG * 4));
+            TRY(dev_alloc(c, &c->stage_count[b], 256));
+        }
+        if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+            hetm_free(c);
+            return HETM_EDEVICE;
+        }
+        for (int b = 0; b < 2; ++b)
+            if (hipEventCreateWithFlags(&c->graph_done[b], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming) != hipSuccess) {
+                hetm_free(c);
+                return HETM_EDEVICE;
+            }
+    }
     if (hipHostMalloc((void **)&c->hargs, sizeof(DevArgs), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->snap_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->cnt_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess) {
@@ -388,6 +427,7 @@ int hetm_free(hetm_ctx *c) {
     if (!c) return HETM_EINVAL;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     for (auto &e : c->ev)
@@ -400,6 +440,14 @@ int hetm_free(hetm_ctx *c) {
     if (c->snap_host) (void)hipHostFree(c->snap_host);
     if (c->cnt_host) (void)hipHostFree(c->cnt_host);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (int b = 0; b < 2; ++b) {
+        if (c->graph_done[b]) (void)hipEventDestroy(c->graph_done[b]);
+        if (c->copied[b]) (void)hipEventDestroy(c->copied[b]);
+        if (c->staging[b]) (void)hipFree(c->staging[b]);
+        if (c->stage_ids[b]) (void)hipFree(c->stage_ids[b]);
+        if (c->stage_count[b]) (void)hipFree(c->stage_count[b]);
+    }
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     delete c;
     return HETM_OK;
 }
@@ -490,14 +538,45 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
         }
         if ((rc = build_graph(c))) return rc;
         c->graph_program = c->args.program;
+        const int b = c->buf;
+        if (c->cfg.async_merge) {
+            // the staging buffer this round fills must have reached the host
+            if (c->pending[b]) HIP_TRY(c, hipStreamWaitEvent(s, c->copied[b], 0));
+            c->args.staging = c->staging[b];
+            c->args.stage_ids = c->stage_ids[b];
+            c->args.stage_count = c->stage_count[b];
+        }
         HIP_TRY(c, hipStreamSynchronize(s));   // the pinned argument block is free to overwrite
         *c->hargs = c->args;
         HIP_TRY(c, hipEventRecord(c->ev[0], s));
         HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
         HIP_TRY(c, hipEventRecord(c->ev[3], s));
+        if (c->cfg.async_merge) HIP_TRY(c, hipEventRecord(c->graph_done[b], s));
         HIP_TRY(c, hipStreamSynchronize(s));
         const DevCounters snap = *c->snap_host;
         if (snap.error) return take_device_error(c, snap.error, snap.err_index);
+        if (c->cfg.async_merge) {
+            if (!snap.conflict) {
+                // success: the copy stream writes the staged granules to the host
+                HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->graph_done[b], 0));
+                launch_staged_copy(true, c->stmr, const_cast<void *>(hdev), c->staging[b], c->stage_ids[b],
+                                   c->stage_count[b], c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes,
+                                   c->copy_stream);
+                HIP_TRY(c, hipGetLastError());
+                HIP_TRY(c, hipEventRecord(c->copied[b], c->copy_stream));
+                c->pending[b] = true;
+                c->buf = b ^ 1;
+                if (res) res->merge_pending = 1;
+            } else {
+                // conflict (CPU wins): restore the dirty granules from the host
+                // replica once the previous round's copy has landed there
+                if ((rc = drain_merges(c))) return rc;
+                launch_staged_copy(false, c->stmr, const_cast<void *>(hdev), nullptr, c->stage_ids[b],
+                                   c->stage_count[b], c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
+                HIP_TRY(c, hipGetLastError());
+                HIP_TRY(c, hipStreamSynchronize(s));
+            }
+        }
         account_round(c, snap, r->n_txns, res);
         if (res) res->us_total = elapsed_us(c->ev[0], c->ev[3]);
         c->stats.log_entries += r->n_log;
@@ -538,6 +617,8 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
 
 int hetm_sync(hetm_ctx *c) {
     if (!c) return HETM_EINVAL;
+    int dr = drain_merges(c);
+    if (dr) return dr;
     DevCounters k;
     int rc = read_counters(c, &k);
     if (rc) return rc;
@@ -573,6 +654,8 @@ int hetm_read_state(hetm_ctx *c, uint32_t what, void *dst, uint64_t bytes) {
                                                  : nullptr;
     if (!src || bytes != hetm_state_bytes(c, what)) return fail(c, HETM_EINVAL, "bad state request");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int dr = drain_merges(c);
+    if (dr) return dr;
     HIP_TRY(c, hipMemcpy(dst, src, bytes, hipMemcpyDefault));
     return HETM_OK;
 }

@@ -115,6 +115,9 @@ struct DevArgs {
     uint32_t *flags;        // nullable
     void *host;             // merge target (pinned host, device-mapped)
     uint32_t *ids_out;      // nullable
+    void *staging;          // async merge: packed dirty granules of this round
+    uint32_t *stage_ids;    // async merge: their ids
+    uint32_t *stage_count;  // async merge: their number
     uint32_t outcome;       // 0 / 1 / HETM_OUTCOME_DEVICE
     uint32_t pad_;
 };
@@ -205,6 +208,9 @@ void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipSt
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s);
 void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
 void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hipStream_t s);
+void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
+void launch_staged_copy(bool to_host, void *stmr, void *host, const void *staging, const uint32_t *ids,
+                        const uint32_t *count, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
 uint32_t exec_workgroups_per_cu(uint32_t program);
 
 constexpr uint32_t kScanWordsPerBlock = 2048;   // bitmap words per compaction block

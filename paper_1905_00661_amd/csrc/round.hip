@@ -307,6 +307,53 @@ __global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uin
     }
 }
 
+// ------------------------------------------------------- double-buffered merge
+// gather: the round's dirty ids and count are staged always; on success the
+// granules themselves are packed into the staging buffer (a conflict leaves
+// the restore to the host side, after the previous copy has landed).
+template <typename U>
+__global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, uint32_t upg, uint64_t total_units) {
+    DevCounters *cnt = a->cnt;
+    if (ld_agent(&cnt->error)) return;
+    const uint32_t outcome = ld_agent(&cnt->conflict);
+    const uint64_t D = ld_agent(&cnt->n_dirty);
+    const uint32_t *ids = a->ids_scratch;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    for (uint64_t i = t0; i < D; i += stride) a->stage_ids[i] = ids[i];
+    if (t0 == 0) *a->stage_count = (uint32_t)D;
+    if (outcome) return;
+    const U *dev = (const U *)a->stmr;
+    U *stg = (U *)a->staging;
+    const uint64_t work = D * upg;
+    for (uint64_t u = t0; u < work; u += stride) {
+        const uint64_t i = u / upg, j = u - i * upg;
+        const uint64_t pos = (uint64_t)ids[i] * upg + j;
+        if (pos < total_units) stg[u] = dev[pos];
+    }
+}
+
+// staged copy between the packed staging buffer / the host replica and the
+// replica: to_host scatters staged granules into the host replica (copy
+// stream, success); !to_host restores the staged ids from the host replica
+// into the GPU replica (conflict).
+template <typename U>
+__global__ __launch_bounds__(256) void k_staged_copy(bool to_host, U *stmr, U *host, const U *stg, const uint32_t *ids,
+                                                     const uint32_t *count, uint32_t upg, uint64_t total_units) {
+    const uint64_t D = ld_agent(count);
+    const uint64_t work = D * upg;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < work; u += stride) {
+        const uint64_t i = u / upg, j = u - i * upg;
+        const uint64_t pos = (uint64_t)ld_agent(&ids[i]) * upg + j;
+        if (pos >= total_units) continue;
+        if (to_host)
+            host[pos] = stg[u];
+        else
+            stmr[pos] = host[pos];
+    }
+}
+
 // ------------------------------------------------------------------- finish
 __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, DevCounters *snap) {
     DevCounters *cnt = a->cnt;
@@ -418,6 +465,38 @@ void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t 
         const uint32_t grid = stream_grid(n_granules * granule, 256, 16384);
         hipLaunchKernelGGL(k_copy<uint64_t>, dim3(grid), dim3(256), 0, s, a, granule, n_words);
     }
+}
+
+void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s) {
+    const uint64_t gbytes = (uint64_t)granule * word_bytes;
+    const uint64_t n_granules = (n_words + granule - 1) / granule;
+    if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0) {
+        const uint32_t upg = (uint32_t)(gbytes / 16);
+        hipLaunchKernelGGL(k_gather<uint4>, dim3(stream_grid(n_granules * upg, 256, 16384)), dim3(256), 0, s, a, upg,
+                           n_words * word_bytes / 16);
+    } else if (word_bytes == 4) {
+        hipLaunchKernelGGL(k_gather<uint32_t>, dim3(stream_grid(n_granules * granule, 256, 16384)), dim3(256), 0, s, a,
+                           granule, n_words);
+    } else {
+        hipLaunchKernelGGL(k_gather<uint64_t>, dim3(stream_grid(n_granules * granule, 256, 16384)), dim3(256), 0, s, a,
+                           granule, n_words);
+    }
+}
+
+void launch_staged_copy(bool to_host, void *stmr, void *host, const void *staging, const uint32_t *ids,
+                        const uint32_t *count, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s) {
+    // the host link bounds this copy, so a modest grid leaves the CUs to the next round
+    const uint32_t grid = to_host ? 256 : 4096;
+    const uint64_t gbytes = (uint64_t)granule * word_bytes;
+    if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0)
+        hipLaunchKernelGGL(k_staged_copy<uint4>, dim3(grid), dim3(256), 0, s, to_host, (uint4 *)stmr, (uint4 *)host,
+                           (const uint4 *)staging, ids, count, (uint32_t)(gbytes / 16), n_words * word_bytes / 16);
+    else if (word_bytes == 4)
+        hipLaunchKernelGGL(k_staged_copy<uint32_t>, dim3(grid), dim3(256), 0, s, to_host, (uint32_t *)stmr,
+                           (uint32_t *)host, (const uint32_t *)staging, ids, count, granule, n_words);
+    else
+        hipLaunchKernelGGL(k_staged_copy<uint64_t>, dim3(grid), dim3(256), 0, s, to_host, (uint64_t *)stmr,
+                           (uint64_t *)host, (const uint64_t *)staging, ids, count, granule, n_words);
 }
 
 void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hipStream_t s) {

@@ -41,7 +41,7 @@ class hetm_config(ctypes.Structure):
     _fields_ = [("n_words", U64), ("word_bytes", U32), ("granule_words", U32),
                 ("lock_stripe_words", U32), ("max_txn_ops", U32), ("batch_capacity", U64),
                 ("log_capacity", U64), ("mode", U32), ("device", I32), ("stream", P),
-                ("exec_workgroups", U32), ("retry_cap", U32)]
+                ("exec_workgroups", U32), ("retry_cap", U32), ("async_merge", U32)]
 
 
 class hetm_oplist_desc(ctypes.Structure):
@@ -64,7 +64,7 @@ class hetm_round_args(ctypes.Structure):
 class hetm_round_result(ctypes.Structure):
     _fields_ = [("conflict", U32), ("error", I32), ("n_committed", U64), ("n_aborted", U64),
                 ("n_local_retries", U64), ("n_dirty", U64), ("n_runs", U64), ("max_ts", U64),
-                ("us_exec", ctypes.c_double), ("us_validate", ctypes.c_double),
+                ("merge_pending", U32), ("pad_", U32), ("us_exec", ctypes.c_double), ("us_validate", ctypes.c_double),
                 ("us_merge", ctypes.c_double), ("us_total", ctypes.c_double)]
 
     def as_dict(self) -> dict:
@@ -304,7 +304,7 @@ class Context:
     def __init__(self, n_words: int, word_bytes: int, granule: int, init: np.ndarray | None = None,
                  stripe: int = 1, max_ops: int = 64, batch_capacity: int = 1 << 20,
                  log_capacity: int = 1 << 20, mode: int = HETM_MODE_PLAIN, exec_workgroups: int = 0,
-                 retry_cap: int = 0, device: int = 0):
+                 retry_cap: int = 0, device: int = 0, async_merge: bool = False):
         torch = _torch()
         self.torch = torch
         self.dev = f"cuda:{device}"
@@ -316,7 +316,7 @@ class Context:
                                lock_stripe_words=stripe, max_txn_ops=max_ops, batch_capacity=batch_capacity,
                                log_capacity=log_capacity, mode=mode, device=device,
                                stream=self.stream.cuda_stream, exec_workgroups=exec_workgroups,
-                               retry_cap=retry_cap)
+                               retry_cap=retry_cap, async_merge=int(async_merge))
         init_t = None
         if init is not None:
             assert init.nbytes == n_words * word_bytes
@@ -349,6 +349,9 @@ class Context:
 
     def stats(self) -> hetm_stats:
         return hetm_stats_get(self.ctx)
+
+    def sync(self) -> None:
+        hetm_sync(self.ctx)
 
     # -- round steps
     def submit(self, b: Batch) -> None:

@@ -22,7 +22,7 @@ def bits(bm: np.ndarray, n: int) -> np.ndarray:
 
 
 def gpu_round(ri: wl.RoundInputs, mode=hm.HETM_MODE_PLAIN, stripe=1, host=None, ctx=None, exec_workgroups=0,
-              flags=True, ids=True, keep=False):
+              flags=True, ids=True, keep=False, async_merge=False):
     """One whole round (hetm_round) on the GPU.  Returns a dict of numpy
     results and the context (if keep)."""
     import torch
@@ -30,7 +30,7 @@ def gpu_round(ri: wl.RoundInputs, mode=hm.HETM_MODE_PLAIN, stripe=1, host=None, 
     if ctx is None:
         ctx = hm.Context(ri.n_words, ri.word_bytes, ri.granule, init=ri.init, stripe=stripe,
                          batch_capacity=max(ri.batch.n, 1), log_capacity=max(ri.log.shape[0], 1),
-                         mode=mode, exec_workgroups=exec_workgroups)
+                         mode=mode, exec_workgroups=exec_workgroups, async_merge=async_merge)
     H0 = wl.host_replica(ri.init, ri.log) if host is None else host
     host_t = hm.pinned(H0.nbytes)
     host_t.numpy()[:] = H0.view(np.uint8)
@@ -41,6 +41,7 @@ def gpu_round(ri: wl.RoundInputs, mode=hm.HETM_MODE_PLAIN, stripe=1, host=None, 
     ids_t = torch.zeros(max(ctx.n_granules, 1) * 4, dtype=torch.uint8, device=ctx.dev) if ids else None
     torch.cuda.synchronize()
     res = ctx.round(b if ri.batch.n else None, log_t, n_log, host_t, flags_t, ids_t)
+    ctx.sync()     # the merge copy of a double-buffered round may still be in flight
     out = {
         "res": res,
         "results": b.results_np(),

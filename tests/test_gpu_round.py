@@ -84,15 +84,19 @@ def test_c1_steps(hm, wl):
     ctx.close()
 
 
+FORMS = {"plain": (0, False), "graph": (1, False), "graph_async": (1, True)}
+
+
 @pytest.mark.parametrize("p_hot,G,stripe", [(0.0, 16, 1), (0.9, 16, 1), (0.5, 4096, 4), (0.9, 1, 1), (0.5, 64, 16)])
-@pytest.mark.parametrize("mode", [0, 1], ids=["plain", "graph"])
-def test_c2_scaled(hm, wl, p_hot, G, stripe, mode):
+@pytest.mark.parametrize("form", list(FORMS))
+def test_c2_scaled(hm, wl, p_hot, G, stripe, form):
     """The large synthetic mix at 1/256 of its size, with hot sets, granule
     and lock-stripe sweeps and an injected conflict."""
     ri = wl.c2(n_words=1 << 20, n_txn=1 << 16, n_log=1 << 14, p_hot=p_hot, granule=G,
                conflict_rate=1.0 if p_hot == 0.5 else 0.0)
-    say(f"c2 scaled p_hot={p_hot} G={G} S={stripe} mode={mode}")
-    g = gpu_round(ri, mode=mode, stripe=stripe)
+    mode, am = FORMS[form]
+    say(f"c2 scaled p_hot={p_hot} G={G} S={stripe} form={form}")
+    g = gpu_round(ri, mode=mode, stripe=stripe, async_merge=am)
     o = oracle_round(ri, g["tickets"], g["H0"])
     assert_round_equal(g, o, ri)
     assert o["conflict"] == (1 if p_hot == 0.5 else 0)
@@ -117,14 +121,18 @@ def test_ragged_and_empty(hm, wl, N, G, n_txn, n_log):
     assert_round_equal(g, o, ri)
 
 
-def test_rounds_in_sequence(hm, wl):
-    """Three rounds on one context: TS and the watermark persist, bitmaps are
-    cleared, every round matches the oracle continued from the last."""
+@pytest.mark.parametrize("form", list(FORMS))
+def test_rounds_in_sequence(hm, wl, form):
+    """Five rounds on one context (the third conflicts): TS and the watermark
+    persist, bitmaps are cleared, every round matches the oracle continued
+    from the last -- also with the double-buffered merge, whose conflicting
+    round must wait for the previous copy before restoring."""
     N = 1 << 16
     base = wl.c1("w")
-    ctx = hm.Context(N, 4, 1, init=base.init, batch_capacity=4096, log_capacity=10000)
+    mode, am = FORMS[form]
+    ctx = hm.Context(N, 4, 1, init=base.init, batch_capacity=4096, log_capacity=10000, mode=mode, async_merge=am)
     S, TS, floor = base.init.copy(), np.zeros(N, np.uint64), 0
-    for r in range(3):
+    for r in range(5):
         g0 = np.random.default_rng(100 + r)
         batch = wl._oplist_from_lists(np.full(4096, 4, np.uint64), np.full(4096, 2 if r == 1 else 4),
                                       g0.integers(0, N // 2, size=4 * 4096, dtype=np.uint64), r * 4096)
@@ -207,3 +215,47 @@ def test_hot_word_contention(hm, wl):
     o = oracle_round(ri, g["tickets"], g["H0"])
     assert_round_equal(g, o, ri)
     say(f"hot: retries={g['res'].n_local_retries}")
+
+
+def test_async_merge_back_to_back(hm, wl):
+    """Double-buffered merge: six rounds back to back on one host replica,
+    each round starting while the previous copy may still be in flight; the
+    host writes its own half between rounds; round 3's log also hits the
+    GPU's half (conflict: wait for the copies, then restore).  Every round's
+    results and outcome match the oracle continued from the last, and the
+    final replicas match after hetm_sync."""
+    import torch
+    import oracle as orc
+    N, G = 1 << 18, 16
+    g0 = np.random.default_rng(77)
+    init = g0.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    ctx = hm.Context(N, 4, G, init=init, batch_capacity=1 << 14, log_capacity=1 << 13, mode=1, async_merge=True)
+    host_t = hm.pinned(N * 4)
+    host = host_t.numpy().view(np.uint32)
+    host[:] = init
+    S, H, TS, floor = init.copy(), init.copy(), np.zeros(N, np.uint64), 0
+    keep = []
+    for r in range(6):
+        batch = wl.c2_batch(np.random.default_rng(200 + r), N, 1 << 14, 0.5, tid0=r << 14)
+        lo = 0 if r == 3 else N // 2
+        log = wl.host_log_uniform(np.random.default_rng(300 + r), 1 << 13, lo, N, floor)
+        if r == 3:
+            ctx.sync()                      # the host's writes touch granules a copy may still be writing
+        H = wl.host_replica(H, log)         # the host runs its transactions ...
+        host[lo:] = H[lo:]                  # ... on its replica
+        b = hm.Batch(1, batch)
+        log_t = hm.to_device(log)
+        torch.cuda.synchronize()
+        res = ctx.round(b, log_t, log.shape[0], host_t)
+        keep.append((b, log_t))
+        o = orc.round_oplist(S, H, TS, G, batch, orc.order_from_tickets(b.tickets_np()), log, floor)
+        assert res.conflict == o["conflict"] == (1 if r == 3 else 0)
+        assert res.merge_pending == (0 if r == 3 else 1)
+        assert np.array_equal(b.results_np(), o["results"])
+        assert int(res.n_dirty) == o["ids"].shape[0]
+        floor = int(o["max_ts"])
+    ctx.sync()
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S)
+    assert np.array_equal(host, H)
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_TS), TS)
+    ctx.close()
