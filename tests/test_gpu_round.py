@@ -241,8 +241,10 @@ def test_async_merge_back_to_back(hm, wl):
         log = wl.host_log_uniform(np.random.default_rng(300 + r), 1 << 13, lo, N, floor)
         if r == 3:
             ctx.sync()                      # the host's writes touch granules a copy may still be writing
-        H = wl.host_replica(H, log)         # the host runs its transactions ...
-        host[lo:] = H[lo:]                  # ... on its replica
+        # the host runs its transactions on its replica (only its half is
+        # written back, where no GPU copy can be in flight) ...
+        host[lo:] = wl.host_replica(host.copy(), log)[lo:]
+        H = wl.host_replica(H, log)         # ... and the oracle's model of it does the same
         b = hm.Batch(1, batch)
         log_t = hm.to_device(log)
         torch.cuda.synchronize()
