@@ -272,6 +272,65 @@ int hetm_stats_get(hetm_ctx *ctx, hetm_stats *out);
 int hetm_read_state(hetm_ctx *ctx, uint32_t what, void *dst, uint64_t bytes);
 uint64_t hetm_state_bytes(hetm_ctx *ctx, uint32_t what);
 
+/* ---------------------------------------------------------------- serving */
+
+/* A request loop over one context (the GPU-controller thread of §IV-A):
+ * OPLIST requests arrive open-loop at given times; rounds are formed from
+ * the requests that have arrived, admitted in arrival order (aborted ones
+ * first) while the round's device footprint -- descriptors and results
+ * (8 B per op + 17 B per request), the host log chunk and the two bitmaps
+ * -- fits mem_budget_bytes, at most max_batch per round.  Before each round
+ * the host commits its next host_log_per_round entries of the host log
+ * stream (entries in timestamp order, above the context's watermark) to
+ * host_replica, and they are validated and applied in the round.
+ *
+ * pipelined = 1 (continuous batching; needs a GRAPH context with
+ * async_merge): while a round runs on the GPU the next one is packed and
+ * uploaded on an upload stream, and a round's requests commit when its
+ * double-buffered merge copy reaches the host replica, overlapping the
+ * next round's execution.  The host log stream must stay in a region the
+ * requests never write (the host's writes then never touch a granule whose
+ * copy is in flight).  pipelined = 0: one plain round at a time.
+ *
+ * A conflicting round is aborted (CPU wins, §IV-E) and its requests are
+ * admitted again first; a request's latency runs from its arrival to the
+ * commit of the round that executed it successfully.  All arrays are host
+ * memory owned by the caller.  Errors: EINVAL, ESTATE (context mode),
+ * ECAPACITY (a request larger than the budget), latched device errors. */
+typedef struct {
+    uint64_t        n_requests;
+    const double   *arrival_s;          /* [n] seconds from the start, non-decreasing */
+    const uint32_t *offsets;            /* [n+1] CSR into idx */
+    const uint32_t *idx;                /* [offsets[n]] word indices < N */
+    const uint8_t  *n_writes;           /* [n] */
+    const uint32_t *tid;                /* [n] */
+    const hetm_log_entry4 *host_log;    /* [host_log_len] the host's log stream */
+    uint64_t        host_log_len;
+    uint64_t        host_log_per_round;
+    uint64_t        max_batch;          /* <= the context's batch_capacity */
+    uint64_t        mem_budget_bytes;
+    uint32_t        pipelined;
+    uint32_t        pad_;
+} hetm_serve_spec;
+
+typedef struct {
+    uint64_t  served;                   /* requests committed */
+    uint64_t  rounds;
+    uint64_t  conflicted_rounds;
+    uint64_t  requeued;                 /* request executions discarded by conflicts */
+    double    wall_s;                   /* first arrival to last commit */
+    double    throughput;               /* served / wall_s */
+    double    p50_latency_us, p99_latency_us, mean_latency_us, max_latency_us;
+    double   *latency_us;               /* out [n], nullable */
+    uint32_t *results;                  /* out [offsets[n]], nullable: values read by the committed execution */
+    uint64_t *commit_seq;               /* out [n], nullable: (round << 32) | ticket of the committed execution */
+    uint8_t  *round_conflict;           /* out [max_rounds], nullable: 1 for an aborted round */
+    uint64_t  max_rounds;
+    uint64_t *round_log_end;            /* out [max_rounds], nullable: host log entries consumed after round r */
+} hetm_serve_report;
+
+int hetm_serve(hetm_ctx *ctx, const hetm_serve_spec *spec, void *host_replica, hetm_serve_report *rep);
+
 /* --------------------------------------------------- host side of a round */
 
 /* The host's worker threads (§IV-A) running transactions on the host

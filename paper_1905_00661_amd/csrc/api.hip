@@ -16,57 +16,11 @@
 #include <new>
 
 #include "hetm.h"
+#include "hetm_ctx.h"
 #include "hetm_dev.h"
 
 using namespace hetm;
 
-struct hetm_ctx {
-    hetm_config cfg{};
-    hipStream_t stream = nullptr;      // the caller's stream (nullptr = default stream)
-    hipStream_t cap_stream = nullptr;  // private stream used only to capture the round graph
-    int device = 0;
-    uint32_t exec_wg = 0;
-    uint32_t log_entry_bytes = 16;
-
-    // device state
-    void *stmr = nullptr;
-    uint64_t *locks = nullptr;
-    uint64_t *ts = nullptr;
-    uint32_t *rs = nullptr, *ws = nullptr, *suspect = nullptr;
-    uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;
-    void *log_staging = nullptr;
-    DevCounters *cnt = nullptr;
-    HotCounters *hot = nullptr;
-    DevCounters *snap_dev = nullptr;
-    DevArgs *dargs = nullptr;
-    uint64_t device_bytes = 0;
-
-    // pinned host mirrors
-    DevArgs *hargs = nullptr;        // argument block uploaded by the graph
-    DevCounters *snap_host = nullptr;
-    DevCounters *cnt_host = nullptr;
-
-    DevArgs args{};                  // host copy of the current arguments
-    hipEvent_t ev[4] = {};
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    uint32_t graph_program = 0;
-
-    // double-buffered merge (GRAPH mode with async_merge)
-    hipStream_t copy_stream = nullptr;
-    hipEvent_t graph_done[2] = {};
-    hipEvent_t copied[2] = {};
-    bool pending[2] = {false, false};
-    int buf = 0;
-    void *staging[2] = {};
-    uint32_t *stage_ids[2] = {};
-    uint32_t *stage_count[2] = {};
-    const void *pending_host = nullptr;
-
-    bool in_validation = false;      // this round's log has started
-    hetm_stats stats{};
-    char err[512] = {0};
-};
 
 namespace {
 
@@ -291,6 +245,105 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
 
 }  // namespace
 
+namespace hetm {
+
+int round_begin(hetm_ctx *c, const hetm_round_args *r) {
+    if (c->cfg.mode != HETM_MODE_GRAPH) return fail(c, HETM_ESTATE, "round_begin needs GRAPH mode");
+    if (c->in_validation || c->round_open) return fail(c, HETM_ESTATE, "a round is already open");
+    if (r->n_log > c->cfg.log_capacity) return fail(c, HETM_ECAPACITY, "log %llu > capacity", (unsigned long long)r->n_log);
+    if (r->n_log && !r->log) return fail(c, HETM_EINVAL, "null log");
+    const void *hdev = nullptr;
+    int rc = check_host_replica(c, r->host_replica, &hdev);
+    if (rc) return rc;
+    if (r->n_txns) {
+        if ((rc = set_batch_args(c, r->program, r->descs, r->n_txns, r->results, r->tickets))) return rc;
+    } else {
+        c->args.n_txns = 0;
+        if (!c->args.program) c->args.program = HETM_PROG_OPLIST;
+    }
+    hipStream_t s = c->stream;
+    const void *dlog = nullptr;
+    if (r->n_log && (rc = stage_log(c, r->log, r->n_log, &dlog))) return rc;
+    c->args.log = dlog;
+    c->args.n_log = (uint32_t)r->n_log;
+    c->args.flags = r->flags_bits;
+    c->args.outcome = HETM_OUTCOME_DEVICE;
+    c->args.host = const_cast<void *>(hdev);
+    c->args.ids_out = r->ids_out;
+    if (c->graph_exec && c->graph_program != c->args.program) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        (void)hipGraphDestroy(c->graph);
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+    }
+    if ((rc = build_graph(c))) return rc;
+    c->graph_program = c->args.program;
+    const int b = c->buf;
+    if (c->cfg.async_merge) {
+        // the staging buffer this round fills must have reached the host
+        if (c->pending[b]) HIP_TRY(c, hipStreamWaitEvent(s, c->copied[b], 0));
+        c->args.staging = c->staging[b];
+        c->args.stage_ids = c->stage_ids[b];
+        c->args.stage_count = c->stage_count[b];
+    }
+    // the previous round_end synchronized the stream, so the graph's upload
+    // node has consumed the pinned argument block
+    *c->hargs = c->args;
+    HIP_TRY(c, hipEventRecord(c->ev[0], s));
+    HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
+    HIP_TRY(c, hipEventRecord(c->ev[3], s));
+    if (c->cfg.async_merge) HIP_TRY(c, hipEventRecord(c->graph_done[b], s));
+    c->round_open = true;
+    c->round_hdev = hdev;
+    c->round_buf = b;
+    return HETM_OK;
+}
+
+int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
+    if (!c->round_open) return fail(c, HETM_ESTATE, "no round open");
+    c->round_open = false;
+    hipStream_t s = c->stream;
+    const void *hdev = c->round_hdev;
+    const int b = c->round_buf;
+    int rc;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const DevCounters snap = *c->snap_host;
+    if (snap.error) return take_device_error(c, snap.error, snap.err_index);
+    if (c->cfg.async_merge) {
+        if (!snap.conflict) {
+            // success: the copy stream writes the staged granules to the host
+            HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->graph_done[b], 0));
+            launch_staged_copy(true, c->stmr, const_cast<void *>(hdev), c->staging[b], c->stage_ids[b],
+                               c->stage_count[b], c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes,
+                               c->copy_stream);
+            HIP_TRY(c, hipGetLastError());
+            HIP_TRY(c, hipEventRecord(c->copied[b], c->copy_stream));
+            c->pending[b] = true;
+            c->last_copy = b;
+            c->buf = b ^ 1;
+            if (res) res->merge_pending = 1;
+        } else {
+            // conflict (CPU wins): restore the dirty granules from the host
+            // replica once the previous round's copy has landed there
+            if ((rc = drain_merges(c))) return rc;
+            launch_staged_copy(false, c->stmr, const_cast<void *>(hdev), nullptr, c->stage_ids[b],
+                               c->stage_count[b], c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
+            HIP_TRY(c, hipGetLastError());
+            HIP_TRY(c, hipStreamSynchronize(s));
+        }
+    }
+    account_round(c, snap, r->n_txns, res);
+    if (res) res->us_total = elapsed_us(c->ev[0], c->ev[3]);
+    c->stats.log_entries += r->n_log;
+    return HETM_OK;
+}
+
+hipEvent_t last_copy_event(hetm_ctx *c) {
+    return (c->cfg.async_merge && c->last_copy >= 0 && c->pending[c->last_copy]) ? c->copied[c->last_copy] : nullptr;
+}
+
+}  // namespace hetm
+
 extern "C" {
 
 const char *hetm_strerror(int code) {
@@ -508,6 +561,11 @@ int hetm_copyback_dirty(hetm_ctx *c, uint32_t conflict, void *host_replica, uint
 int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     if (!c || !r) return HETM_EINVAL;
     if (res) memset(res, 0, sizeof *res);
+    if (c->cfg.mode == HETM_MODE_GRAPH) {
+        int rc = hetm::round_begin(c, r);
+        if (rc) return rc;
+        return hetm::round_end(c, r, res);
+    }
     if (c->in_validation) return fail(c, HETM_ESTATE, "hetm_round inside an open round");
     if (r->n_log > c->cfg.log_capacity) return fail(c, HETM_ECAPACITY, "log %llu > capacity", (unsigned long long)r->n_log);
     if (r->n_log && !r->log) return fail(c, HETM_EINVAL, "null log");
@@ -520,68 +578,6 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
         c->args.n_txns = 0;
     }
     hipStream_t s = c->stream;
-    if (c->cfg.mode == HETM_MODE_GRAPH) {
-        if (r->n_txns == 0) c->args.program = c->args.program ? c->args.program : HETM_PROG_OPLIST;
-        const void *dlog = nullptr;
-        if (r->n_log && (rc = stage_log(c, r->log, r->n_log, &dlog))) return rc;
-        c->args.log = dlog;
-        c->args.n_log = (uint32_t)r->n_log;
-        c->args.flags = r->flags_bits;
-        c->args.outcome = HETM_OUTCOME_DEVICE;
-        c->args.host = const_cast<void *>(hdev);
-        c->args.ids_out = r->ids_out;
-        if (c->graph_exec && c->graph_program != c->args.program) {
-            (void)hipGraphExecDestroy(c->graph_exec);
-            (void)hipGraphDestroy(c->graph);
-            c->graph_exec = nullptr;
-            c->graph = nullptr;
-        }
-        if ((rc = build_graph(c))) return rc;
-        c->graph_program = c->args.program;
-        const int b = c->buf;
-        if (c->cfg.async_merge) {
-            // the staging buffer this round fills must have reached the host
-            if (c->pending[b]) HIP_TRY(c, hipStreamWaitEvent(s, c->copied[b], 0));
-            c->args.staging = c->staging[b];
-            c->args.stage_ids = c->stage_ids[b];
-            c->args.stage_count = c->stage_count[b];
-        }
-        HIP_TRY(c, hipStreamSynchronize(s));   // the pinned argument block is free to overwrite
-        *c->hargs = c->args;
-        HIP_TRY(c, hipEventRecord(c->ev[0], s));
-        HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
-        HIP_TRY(c, hipEventRecord(c->ev[3], s));
-        if (c->cfg.async_merge) HIP_TRY(c, hipEventRecord(c->graph_done[b], s));
-        HIP_TRY(c, hipStreamSynchronize(s));
-        const DevCounters snap = *c->snap_host;
-        if (snap.error) return take_device_error(c, snap.error, snap.err_index);
-        if (c->cfg.async_merge) {
-            if (!snap.conflict) {
-                // success: the copy stream writes the staged granules to the host
-                HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->graph_done[b], 0));
-                launch_staged_copy(true, c->stmr, const_cast<void *>(hdev), c->staging[b], c->stage_ids[b],
-                                   c->stage_count[b], c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes,
-                                   c->copy_stream);
-                HIP_TRY(c, hipGetLastError());
-                HIP_TRY(c, hipEventRecord(c->copied[b], c->copy_stream));
-                c->pending[b] = true;
-                c->buf = b ^ 1;
-                if (res) res->merge_pending = 1;
-            } else {
-                // conflict (CPU wins): restore the dirty granules from the host
-                // replica once the previous round's copy has landed there
-                if ((rc = drain_merges(c))) return rc;
-                launch_staged_copy(false, c->stmr, const_cast<void *>(hdev), nullptr, c->stage_ids[b],
-                                   c->stage_count[b], c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
-                HIP_TRY(c, hipGetLastError());
-                HIP_TRY(c, hipStreamSynchronize(s));
-            }
-        }
-        account_round(c, snap, r->n_txns, res);
-        if (res) res->us_total = elapsed_us(c->ev[0], c->ev[3]);
-        c->stats.log_entries += r->n_log;
-        return HETM_OK;
-    }
     // PLAIN: one launch per step, outcome read on the host
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     if (r->n_txns) {

@@ -1,0 +1,78 @@
+// hetm_ctx.h -- the context behind the opaque hetm_ctx handle, and the
+// internal round steps shared by the C ABI and the serve loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hetm.h"
+#include "hetm_dev.h"
+
+using hetm::DevArgs;
+using hetm::DevCounters;
+using hetm::HotCounters;
+
+struct hetm_ctx {
+    hetm_config cfg{};
+    hipStream_t stream = nullptr;      // the caller's stream (nullptr = default stream)
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture the round graph
+    int device = 0;
+    uint32_t exec_wg = 0;
+    uint32_t log_entry_bytes = 16;
+
+    // device state
+    void *stmr = nullptr;
+    uint64_t *locks = nullptr;
+    uint64_t *ts = nullptr;
+    uint32_t *rs = nullptr, *ws = nullptr, *suspect = nullptr;
+    uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;
+    void *log_staging = nullptr;
+    DevCounters *cnt = nullptr;
+    HotCounters *hot = nullptr;
+    DevCounters *snap_dev = nullptr;
+    DevArgs *dargs = nullptr;
+    uint64_t device_bytes = 0;
+
+    // pinned host mirrors
+    DevArgs *hargs = nullptr;        // argument block uploaded by the graph
+    DevCounters *snap_host = nullptr;
+    DevCounters *cnt_host = nullptr;
+
+    DevArgs args{};                  // host copy of the current arguments
+    hipEvent_t ev[4] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint32_t graph_program = 0;
+
+    // double-buffered merge (GRAPH mode with async_merge)
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t graph_done[2] = {};
+    hipEvent_t copied[2] = {};
+    bool pending[2] = {false, false};
+    int buf = 0;
+    int last_copy = -1;
+    void *staging[2] = {};
+    uint32_t *stage_ids[2] = {};
+    uint32_t *stage_count[2] = {};
+    const void *pending_host = nullptr;
+
+    // the GRAPH round between round_begin and round_end
+    bool round_open = false;
+    const void *round_hdev = nullptr;
+    int round_buf = 0;
+
+    bool in_validation = false;      // this round's log has started
+    hetm_stats stats{};
+    char err[512] = {0};
+};
+
+namespace hetm {
+// GRAPH-mode round split in two so a caller can overlap host work with it:
+// round_begin checks the arguments, uploads them and launches the captured
+// graph; round_end waits for it and handles the outcome (error, staged or
+// synchronous merge, restore on conflict) and fills *res.
+int round_begin(hetm_ctx *c, const hetm_round_args *r);
+int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res);
+// The event that completes when the last staged merge copy reaches the host
+// replica (async merge), or nullptr.
+hipEvent_t last_copy_event(hetm_ctx *c);
+}  // namespace hetm

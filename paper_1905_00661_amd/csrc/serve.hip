@@ -1,0 +1,360 @@
+// serve.hip -- the request loop of the GPU-controller thread (§IV-A): open-loop
+// arrivals, admission by the round's device footprint, continuous batching
+// over the double-buffered round, commit-latency accounting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <vector>
+
+#include "hetm.h"
+#include "hetm_ctx.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+double seconds_since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
+
+// One set of round buffers: pinned packing area and device copies.
+struct RoundSet {
+    uint32_t *h_off = nullptr, *h_idx = nullptr, *h_tid = nullptr;
+    uint8_t *h_nw = nullptr;
+    hetm_log_entry4 *h_log = nullptr;
+    uint32_t *h_res = nullptr, *h_tick = nullptr;
+    uint32_t *d_off = nullptr, *d_idx = nullptr, *d_tid = nullptr, *d_res = nullptr, *d_tick = nullptr;
+    uint8_t *d_nw = nullptr;
+    hetm_log_entry4 *d_log = nullptr;
+    hipEvent_t uploaded = nullptr;
+    std::vector<uint64_t> reqs;   // request ids in packing order
+    uint64_t n_ops = 0, n_log = 0;
+    uint64_t log_end = 0;         // host log entries consumed once this round is in
+};
+
+struct Serve {
+    hetm_ctx *c;
+    const hetm_serve_spec &sp;
+    void *host;
+    hetm_serve_report *rep;
+    hipStream_t upload = nullptr;
+    RoundSet set[2];
+    std::deque<uint64_t> requeue;
+    uint64_t head = 0;            // next request not yet admitted
+    uint64_t log_pos = 0;         // host log entries consumed
+    uint64_t round_no = 0;
+    uint64_t max_ops_round = 0;
+    std::vector<double> latency_us;
+    std::vector<uint64_t> pos_of;  // request -> first op in spec CSR
+    clk::time_point t0;
+    uint64_t served = 0;
+    double last_commit_s = 0;
+    int err = HETM_OK;
+
+    Serve(hetm_ctx *c_, const hetm_serve_spec &s_, void *h_, hetm_serve_report *r_) : c(c_), sp(s_), host(h_), rep(r_) {}
+
+    uint64_t req_ops(uint64_t i) const { return sp.offsets[i + 1] - sp.offsets[i]; }
+
+    int alloc() {
+        const uint64_t mb = sp.max_batch;
+        max_ops_round = mb * c->cfg.max_txn_ops;
+        const uint64_t nl = std::max<uint64_t>(sp.host_log_per_round, 1);
+        if (hipStreamCreateWithFlags(&upload, hipStreamNonBlocking) != hipSuccess) return HETM_EDEVICE;
+        for (auto &r : set) {
+            bool ok = hipHostMalloc((void **)&r.h_off, (mb + 1) * 4, 0) == hipSuccess &&
+                      hipHostMalloc((void **)&r.h_idx, max_ops_round * 4, 0) == hipSuccess &&
+                      hipHostMalloc((void **)&r.h_tid, mb * 4, 0) == hipSuccess &&
+                      hipHostMalloc((void **)&r.h_nw, mb, 0) == hipSuccess &&
+                      hipHostMalloc((void **)&r.h_log, nl * sizeof(hetm_log_entry4), 0) == hipSuccess &&
+                      hipHostMalloc((void **)&r.h_res, max_ops_round * 4, 0) == hipSuccess &&
+                      hipHostMalloc((void **)&r.h_tick, mb * 4, 0) == hipSuccess &&
+                      hipMalloc((void **)&r.d_off, (mb + 1) * 4) == hipSuccess &&
+                      hipMalloc((void **)&r.d_idx, max_ops_round * 4) == hipSuccess &&
+                      hipMalloc((void **)&r.d_tid, mb * 4) == hipSuccess &&
+                      hipMalloc((void **)&r.d_nw, mb) == hipSuccess &&
+                      hipMalloc((void **)&r.d_log, nl * sizeof(hetm_log_entry4)) == hipSuccess &&
+                      hipMalloc((void **)&r.d_res, max_ops_round * 4) == hipSuccess &&
+                      hipMalloc((void **)&r.d_tick, mb * 4) == hipSuccess &&
+                      hipEventCreateWithFlags(&r.uploaded, hipEventDisableTiming) == hipSuccess;
+            if (!ok) return HETM_ENOMEM;
+        }
+        return HETM_OK;
+    }
+    void release() {
+        if (upload) (void)hipStreamSynchronize(upload);
+        for (auto &r : set) {
+            for (void *p : {(void *)r.h_off, (void *)r.h_idx, (void *)r.h_tid, (void *)r.h_nw, (void *)r.h_log,
+                            (void *)r.h_res, (void *)r.h_tick})
+                if (p) (void)hipHostFree(p);
+            for (void *p : {(void *)r.d_off, (void *)r.d_idx, (void *)r.d_tid, (void *)r.d_nw, (void *)r.d_log,
+                            (void *)r.d_res, (void *)r.d_tick})
+                if (p) (void)hipFree(p);
+            if (r.uploaded) (void)hipEventDestroy(r.uploaded);
+        }
+        if (upload) (void)hipStreamDestroy(upload);
+    }
+
+    uint64_t arrived() const {
+        const double now = seconds_since(t0);
+        return (uint64_t)(std::upper_bound(sp.arrival_s, sp.arrival_s + sp.n_requests, now) - sp.arrival_s);
+    }
+    bool work_waiting() const { return !requeue.empty() || head < arrived(); }
+
+    // Admission: aborted requests first, then arrivals in order, while the
+    // round's footprint fits the budget.
+    void admit(RoundSet &r) {
+        const uint64_t fixed = sp.host_log_per_round * sizeof(hetm_log_entry4) +
+                               2ull * ((c->args.n_bm_words) * 4ull);
+        uint64_t bytes = fixed;
+        const uint64_t arr = arrived();
+        r.reqs.clear();
+        r.n_ops = 0;
+        auto fits = [&](uint64_t i) {
+            const uint64_t b = req_ops(i) * 8 + 17;
+            if (r.reqs.size() >= sp.max_batch || bytes + b > sp.mem_budget_bytes ||
+                r.n_ops + req_ops(i) > max_ops_round)
+                return false;
+            bytes += b;
+            r.n_ops += req_ops(i);
+            r.reqs.push_back(i);
+            return true;
+        };
+        while (!requeue.empty() && fits(requeue.front())) requeue.pop_front();
+        if (requeue.empty())
+            while (head < arr && fits(head)) ++head;
+    }
+
+    // Packs the admitted requests and the host's next log chunk, uploads them.
+    int pack_upload(RoundSet &r) {
+        uint32_t o = 0;
+        for (size_t k = 0; k < r.reqs.size(); ++k) {
+            const uint64_t i = r.reqs[k];
+            const uint32_t L = (uint32_t)req_ops(i);
+            r.h_off[k] = o;
+            memcpy(r.h_idx + o, sp.idx + sp.offsets[i], L * 4);
+            r.h_nw[k] = sp.n_writes[i];
+            r.h_tid[k] = sp.tid[i];
+            o += L;
+        }
+        r.h_off[r.reqs.size()] = o;
+        r.n_log = std::min<uint64_t>(sp.host_log_per_round, sp.host_log_len - log_pos);
+        if (r.n_log) memcpy(r.h_log, sp.host_log + log_pos, r.n_log * sizeof(hetm_log_entry4));
+        log_pos += r.n_log;
+        r.log_end = log_pos;
+        const uint64_t n = r.reqs.size();
+        bool ok = hipMemcpyAsync(r.d_off, r.h_off, (n + 1) * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
+                  hipMemcpyAsync(r.d_idx, r.h_idx, std::max<uint64_t>(o, 1) * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
+                  hipMemcpyAsync(r.d_nw, r.h_nw, std::max<uint64_t>(n, 1), hipMemcpyHostToDevice, upload) == hipSuccess &&
+                  hipMemcpyAsync(r.d_tid, r.h_tid, std::max<uint64_t>(n, 1) * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
+                  (r.n_log == 0 || hipMemcpyAsync(r.d_log, r.h_log, r.n_log * sizeof(hetm_log_entry4),
+                                                  hipMemcpyHostToDevice, upload) == hipSuccess) &&
+                  hipEventRecord(r.uploaded, upload) == hipSuccess;
+        return ok ? HETM_OK : HETM_EDEVICE;
+    }
+
+    // The host commits its log chunk to its replica (entries in ts order).
+    void host_commit(const RoundSet &r) {
+        uint32_t *H = (uint32_t *)host;
+        for (uint64_t k = 0; k < r.n_log; ++k) H[r.h_log[k].word] = r.h_log[k].value;
+    }
+
+    hetm_round_args round_args(RoundSet &r, hetm_oplist_desc &d) {
+        d = {r.d_off, r.d_idx, r.d_nw, r.d_tid};
+        hetm_round_args a{};
+        a.program = HETM_PROG_OPLIST;
+        a.descs = &d;
+        a.n_txns = r.reqs.size();
+        a.results = r.d_res;
+        a.tickets = r.d_tick;
+        a.log = r.d_log;
+        a.n_log = r.n_log;
+        a.host_replica = host;
+        return a;
+    }
+
+    // After a round's compute: conflict -> requeue; success -> copy results
+    // out and queue the requests for commit stamping.
+    int settle(RoundSet &r, const hetm_round_result &res, std::deque<std::pair<hipEvent_t, std::vector<uint64_t>>> *pend,
+               std::vector<uint64_t> &done_now) {
+        const uint64_t rn = round_no++;
+        if (rep->round_conflict && rn < rep->max_rounds) rep->round_conflict[rn] = res.conflict ? 1 : 0;
+        if (rep->round_log_end && rn < rep->max_rounds) rep->round_log_end[rn] = r.log_end;
+        rep->rounds++;
+        if (res.conflict) {
+            rep->conflicted_rounds++;
+            rep->requeued += r.reqs.size();
+            for (auto it = r.reqs.rbegin(); it != r.reqs.rend(); ++it) requeue.push_front(*it);
+            return HETM_OK;
+        }
+        const uint64_t n = r.reqs.size();
+        if (n) {
+            if (hipMemcpy(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+                return HETM_EDEVICE;
+        }
+        uint32_t o = 0;
+        for (size_t k = 0; k < n; ++k) {
+            const uint64_t i = r.reqs[k];
+            const uint32_t L = (uint32_t)req_ops(i);
+            if (rep->results) memcpy(rep->results + sp.offsets[i], r.h_res + o, L * 4);
+            if (rep->commit_seq) rep->commit_seq[i] = (rn << 32) | r.h_tick[k];
+            o += L;
+        }
+        hipEvent_t ev = hetm::last_copy_event(c);
+        if (pend && ev)
+            pend->emplace_back(ev, r.reqs);
+        else
+            done_now.insert(done_now.end(), r.reqs.begin(), r.reqs.end());
+        return HETM_OK;
+    }
+
+    void stamp(const std::vector<uint64_t> &reqs) {
+        const double now = seconds_since(t0);
+        for (uint64_t i : reqs) latency_us[i] = (now - sp.arrival_s[i]) * 1e6;
+        served += reqs.size();
+        last_commit_s = now;
+    }
+
+    void wait_for_arrival() {
+        if (head < sp.n_requests) {
+            const double dt = sp.arrival_s[head] - seconds_since(t0);
+            if (dt > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(dt - 1e-4));
+        }
+    }
+
+    int run_plain() {
+        RoundSet &r = set[0];
+        while (served < sp.n_requests) {
+            if (!work_waiting()) {
+                wait_for_arrival();
+                continue;
+            }
+            admit(r);
+            if (r.reqs.empty()) return HETM_ECAPACITY;
+            if ((err = pack_upload(r))) return err;
+            if (hipStreamSynchronize(upload) != hipSuccess) return HETM_EDEVICE;
+            host_commit(r);
+            hetm_oplist_desc d;
+            hetm_round_args a = round_args(r, d);
+            hetm_round_result res;
+            if ((err = hetm_round(c, &a, &res))) return err;
+            std::vector<uint64_t> done;
+            if ((err = settle(r, res, nullptr, done))) return err;
+            stamp(done);
+        }
+        return HETM_OK;
+    }
+
+    int run_pipelined() {
+        std::deque<std::pair<hipEvent_t, std::vector<uint64_t>>> pend;
+        int cur = -1;            // set of the round on the GPU
+        int nxt = -1;            // set packed and uploaded for the next round
+        hetm_oplist_desc d[2];
+        hetm_round_args a[2];
+        auto poll = [&](bool block) {
+            while (!pend.empty()) {
+                if (block) {
+                    if (hipEventSynchronize(pend.front().first) != hipSuccess) return HETM_EDEVICE;
+                } else if (hipEventQuery(pend.front().first) != hipSuccess) {
+                    break;
+                }
+                stamp(pend.front().second);
+                pend.pop_front();
+            }
+            return HETM_OK;
+        };
+        while (served < sp.n_requests) {
+            if (nxt < 0 && work_waiting()) {
+                const int s = cur < 0 ? 0 : cur ^ 1;
+                admit(set[s]);
+                if (!set[s].reqs.empty()) {
+                    if ((err = pack_upload(set[s]))) return err;
+                    nxt = s;
+                } else if (cur < 0) {
+                    return HETM_ECAPACITY;
+                }
+            }
+            if (cur >= 0) {
+                hetm_round_result res{};
+                if ((err = hetm::round_end(c, &a[cur], &res))) return err;
+                std::vector<uint64_t> done;
+                if ((err = settle(set[cur], res, &pend, done))) return err;
+                stamp(done);
+                cur = -1;
+            }
+            if ((err = poll(false))) return err;
+            if (cur < 0 && nxt >= 0) {
+                RoundSet &r = set[nxt];
+                host_commit(r);
+                a[nxt] = round_args(r, d[nxt]);
+                if (hipStreamWaitEvent(c->stream, r.uploaded, 0) != hipSuccess) return HETM_EDEVICE;
+                if ((err = hetm::round_begin(c, &a[nxt]))) return err;
+                cur = nxt;
+                nxt = -1;
+            } else if (cur < 0 && nxt < 0) {
+                if (!pend.empty())
+                    poll(true);
+                else
+                    wait_for_arrival();
+            }
+        }
+        return poll(true);
+    }
+};
+
+}  // namespace
+
+extern "C" int hetm_serve(hetm_ctx *c, const hetm_serve_spec *sp, void *host_replica, hetm_serve_report *rep) {
+    if (!c || !sp || !rep || !host_replica) return HETM_EINVAL;
+    if (c->cfg.word_bytes != 4 || sp->max_batch == 0 || sp->max_batch > c->cfg.batch_capacity ||
+        sp->host_log_per_round > c->cfg.log_capacity || (sp->n_requests && (!sp->arrival_s || !sp->offsets || !sp->idx ||
+                                                                           !sp->n_writes || !sp->tid)) ||
+        (sp->host_log_len && !sp->host_log))
+        return HETM_EINVAL;
+    if (sp->pipelined && !(c->cfg.mode == HETM_MODE_GRAPH && c->cfg.async_merge)) return HETM_ESTATE;
+    if (!sp->pipelined && c->cfg.mode != HETM_MODE_PLAIN) return HETM_ESTATE;
+    for (uint64_t i = 0; i < sp->n_requests; ++i)
+        if (sp->offsets[i + 1] < sp->offsets[i] || sp->offsets[i + 1] - sp->offsets[i] > c->cfg.max_txn_ops ||
+            (i && sp->arrival_s[i] < sp->arrival_s[i - 1]))
+            return HETM_EINVAL;
+    for (uint64_t k = 0; k < sp->host_log_len; ++k)
+        if (sp->host_log[k].word >= c->cfg.n_words) return HETM_EINVAL;
+    double *lat_out = rep->latency_us;
+    uint32_t *res_out = rep->results;
+    uint64_t *seq_out = rep->commit_seq;
+    uint8_t *rc_out = rep->round_conflict;
+    uint64_t *rl_out = rep->round_log_end;
+    const uint64_t max_rounds = rep->max_rounds;
+    memset(rep, 0, sizeof *rep);
+    rep->latency_us = lat_out, rep->results = res_out, rep->commit_seq = seq_out;
+    rep->round_conflict = rc_out, rep->max_rounds = max_rounds, rep->round_log_end = rl_out;
+
+    Serve S(c, *sp, host_replica, rep);
+    S.latency_us.assign(sp->n_requests, 0.0);
+    int rc = S.alloc();
+    if (rc == HETM_OK) {
+        S.t0 = clk::now();
+        rc = sp->pipelined ? S.run_pipelined() : S.run_plain();
+        if (rc == HETM_OK) rc = hetm_sync(c);
+    }
+    S.release();
+    if (rc) return rc;
+    rep->served = S.served;
+    rep->wall_s = S.last_commit_s - (sp->n_requests ? sp->arrival_s[0] : 0.0);
+    rep->throughput = rep->wall_s > 0 ? S.served / rep->wall_s : 0;
+    if (sp->n_requests) {
+        std::vector<double> l = S.latency_us;
+        std::sort(l.begin(), l.end());
+        auto pct = [&](double q) { return l[std::min<size_t>(l.size() - 1, (size_t)(q * (l.size() - 1) + 0.5))]; };
+        rep->p50_latency_us = pct(0.50);
+        rep->p99_latency_us = pct(0.99);
+        rep->max_latency_us = l.back();
+        double sum = 0;
+        for (double x : l) sum += x;
+        rep->mean_latency_us = sum / l.size();
+        if (lat_out) memcpy(lat_out, S.latency_us.data(), sp->n_requests * sizeof(double));
+    }
+    return HETM_OK;
+}

@@ -31,7 +31,8 @@ HETM_STATE_STMR, HETM_STATE_TS, HETM_STATE_RS, HETM_STATE_WS, HETM_STATE_LOCKS =
 EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_apply_log",
            "hetm_copyback_dirty", "hetm_round", "hetm_strerror", "hetm_last_error", "hetm_sync",
            "hetm_stats_get", "hetm_read_state", "hetm_state_bytes", "hetm_host_tm_create",
-           "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts"]
+           "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts",
+           "hetm_serve"]
 
 P = ctypes.c_void_p
 U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -69,6 +70,20 @@ class hetm_round_result(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class hetm_serve_spec(ctypes.Structure):
+    _fields_ = [("n_requests", U64), ("arrival_s", P), ("offsets", P), ("idx", P), ("n_writes", P), ("tid", P),
+                ("host_log", P), ("host_log_len", U64), ("host_log_per_round", U64), ("max_batch", U64),
+                ("mem_budget_bytes", U64), ("pipelined", U32), ("pad_", U32)]
+
+
+class hetm_serve_report(ctypes.Structure):
+    _fields_ = [("served", U64), ("rounds", U64), ("conflicted_rounds", U64), ("requeued", U64),
+                ("wall_s", ctypes.c_double), ("throughput", ctypes.c_double), ("p50_latency_us", ctypes.c_double),
+                ("p99_latency_us", ctypes.c_double), ("mean_latency_us", ctypes.c_double),
+                ("max_latency_us", ctypes.c_double), ("latency_us", P), ("results", P), ("commit_seq", P),
+                ("round_conflict", P), ("max_rounds", U64), ("round_log_end", P)]
 
 
 class hetm_stats(ctypes.Structure):
@@ -112,6 +127,7 @@ def lib() -> ctypes.CDLL:
             "hetm_host_tm_clock": ([P], U64),
             "hetm_host_run_transfers": ([P, P, P, P, U64, U32, P, P, U64, ctypes.POINTER(U64)], ctypes.c_int),
             "hetm_host_run_cache_puts": ([P, P, U64, U32, P, P, U64, ctypes.POINTER(U64)], ctypes.c_int),
+            "hetm_serve": ([P, ctypes.POINTER(hetm_serve_spec), P, ctypes.POINTER(hetm_serve_report)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -363,6 +379,35 @@ class Context:
 
     def copyback(self, conflict: int, host, ids=None) -> int:
         return hetm_copyback_dirty(self.ctx, conflict, host.data_ptr(), ids.data_ptr() if ids is not None else None)
+
+    def serve(self, arrival_s: np.ndarray, batch, host, host_log: np.ndarray, host_log_per_round: int,
+              max_batch: int, mem_budget_bytes: int, pipelined: bool, max_rounds: int = 1 << 16) -> dict:
+        """Runs the request loop (hetm_serve) over OPLIST requests; returns the
+        report and per-request latencies, results and commit positions."""
+        arrival_s = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        n = arrival_s.shape[0]
+        host_log = np.ascontiguousarray(host_log)
+        lat = np.zeros(max(n, 1), np.float64)
+        res = np.zeros(max(int(batch.offsets[-1]), 1), np.uint32)
+        seq = np.zeros(max(n, 1), np.uint64)
+        rconf = np.zeros(max_rounds, np.uint8)
+        rlog = np.zeros(max_rounds, np.uint64)
+        spec = hetm_serve_spec(n_requests=n, arrival_s=arrival_s.ctypes.data, offsets=batch.offsets.ctypes.data,
+                               idx=batch.idx.ctypes.data, n_writes=batch.n_writes.ctypes.data,
+                               tid=batch.tid.ctypes.data, host_log=host_log.ctypes.data if host_log.size else None,
+                               host_log_len=host_log.shape[0], host_log_per_round=host_log_per_round,
+                               max_batch=max_batch, mem_budget_bytes=mem_budget_bytes, pipelined=int(pipelined))
+        rep = hetm_serve_report(latency_us=lat.ctypes.data, results=res.ctypes.data, commit_seq=seq.ctypes.data,
+                                round_conflict=rconf.ctypes.data, max_rounds=max_rounds,
+                                round_log_end=rlog.ctypes.data)
+        _check(lib().hetm_serve(self.ctx, ctypes.byref(spec), host.data_ptr(), ctypes.byref(rep)), "hetm_serve",
+               self.ctx)
+        out = {f: getattr(rep, f) for f, _ in hetm_serve_report._fields_ if f not in
+               ("latency_us", "results", "commit_seq", "round_conflict", "round_log_end", "max_rounds")}
+        R = int(rep.rounds)
+        out.update(latency_us=lat[:n], results=res[:int(batch.offsets[-1])], commit_seq=seq[:n],
+                   round_conflict=rconf[:R], round_log_end=rlog[:R])
+        return out
 
     def round(self, b: Batch | None, log_dev, n_log: int, host, flags=None, ids=None) -> hetm_round_result:
         a = hetm_round_args(program=b.program if b else 0, descs=ctypes.addressof(b.desc) if b else None,

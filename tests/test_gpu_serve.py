@@ -1,0 +1,155 @@
+"""Serving (hetm_serve): open-loop arrivals, continuous batching over the
+double-buffered round, re-queue on conflict.  Oracle parity of a whole
+served run, and probe requests whose results are the same alone and in the
+mix (tolerance 0)."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+N = 1 << 20
+HOST_LO = N - N // 16
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_00661_amd import hetm
+    hetm.lib()
+    return hetm
+
+
+@pytest.fixture(scope="module")
+def wl():
+    from paper_1905_00661_amd import workloads
+    return workloads
+
+
+def host_stream(wl, seed, n, lo, hi, inject_every=0, gpu_hi=HOST_LO):
+    """The host's log stream: uniform words in [lo, hi), increasing ts; with
+    inject_every > 0 every inject_every-th entry lands in the GPU range."""
+    log = wl.host_log_uniform(np.random.default_rng(seed), n, lo, hi, 0, shuffle_ts=False)
+    if inject_every:
+        k = np.arange(0, n, inject_every)      # one write into the GPU's hot words every few rounds
+        log["word"][k] = np.random.default_rng(seed + 1).integers(0, 1000, size=k.shape[0]).astype(np.uint32)
+    return log
+
+
+def replay_served(init, batch, out, log, per_round, G):
+    """Oracle: round by round, the committed requests of the round in ticket
+    order, then the round's host log chunk (serialized before the GPU's
+    transactions by validation; the sets are disjoint when the round
+    commits, so the order inside the round does not change any result)."""
+    S = init.copy()
+    TS = np.zeros(S.shape[0], np.uint64)
+    res_all = np.zeros_like(out["results"])
+    seq = out["commit_seq"]
+    rnd = (seq >> np.uint64(32)).astype(np.int64)
+    start = 0
+    for r in range(int(out["rounds"])):
+        end = int(out["round_log_end"][r])
+        if not out["round_conflict"][r]:
+            ids = np.flatnonzero(rnd == r)
+            ids = ids[np.argsort(seq[ids] & np.uint64(0xFFFFFFFF), kind="stable")]
+            sub = _subset(batch, ids)
+            res, _, _ = orc.replay_oplist(S, G, sub, np.arange(ids.shape[0]))
+            o = 0
+            for k, i in enumerate(ids):
+                L = int(batch.offsets[i + 1] - batch.offsets[i])
+                res_all[batch.offsets[i]:batch.offsets[i] + L] = res[o:o + L]
+                o += L
+        else:
+            assert not np.any(rnd == r)
+        if end > start:
+            orc.apply(S, TS, log[start:end], 0)
+        start = end
+    return S, res_all
+
+
+def _subset(b, ids):
+    from paper_1905_00661_amd import workloads as wl
+    lens = (b.offsets[ids + 1] - b.offsets[ids]).astype(np.uint64)
+    idx = np.concatenate([b.idx[b.offsets[i]:b.offsets[i + 1]] for i in ids]) if len(ids) else np.zeros(0, np.uint32)
+    off = np.zeros(len(ids) + 1, np.uint32)
+    off[1:] = np.cumsum(lens)
+    return wl.OplistBatch(offsets=off, idx=idx.astype(np.uint32), n_writes=b.n_writes[ids].copy(), tid=b.tid[ids].copy())
+
+
+def make_ctx(hm, init, pipelined, G=64, max_batch=8192):
+    if pipelined:
+        return hm.Context(N, 4, G, init=init, max_ops=64, batch_capacity=max_batch, log_capacity=4096, mode=1,
+                          async_merge=True)
+    return hm.Context(N, 4, G, init=init, max_ops=64, batch_capacity=max_batch, log_capacity=4096, mode=0)
+
+
+@pytest.mark.parametrize("pipelined,rate,inject", [(True, 2e6, 0), (False, 2e6, 0), (False, 5e5, 3 * 4096),
+                                                   (True, 2e7, 0)])
+def test_serve_matches_oracle(hm, wl, pipelined, rate, inject):
+    """20,000 lognormal-length requests (median 4, capped at 64) arriving
+    Poisson at `rate`, 5% hot words, host log stream of 4096 entries per
+    round in the host's region (plus injected inter-device conflicts)."""
+    g = wl.rng("c5", 0, 3)
+    init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    req = wl.c5_requests(g, 20000, rate, n_words=N, host_lo=HOST_LO)
+    log = host_stream(wl, 5, 1 << 20, HOST_LO, N, inject_every=inject)
+    ctx = make_ctx(hm, init, pipelined)
+    host_t = hm.pinned(N * 4)
+    host_t.numpy()[:] = init.view(np.uint8)
+    out = ctx.serve(req["arrival_s"], req["batch"], host_t, log, 4096, 8192, 64 << 20, pipelined)
+    say(f"serve pipelined={pipelined} rate={rate:g}: rounds={out['rounds']} conflicted={out['conflicted_rounds']} "
+        f"p50={out['p50_latency_us']:.0f}us p99={out['p99_latency_us']:.0f}us thr={out['throughput']:.3g}/s")
+    assert out["served"] == 20000
+    if inject:
+        assert out["conflicted_rounds"] > 0 and out["requeued"] > 0
+    S, res = replay_served(init, req["batch"], out, log, 4096, 64)
+    assert np.array_equal(out["results"], res), "request results differ from the oracle replay"
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S)
+    assert np.array_equal(host_t.numpy().view(np.uint32), S)
+    assert np.all(out["latency_us"] > 0)
+    ctx.close()
+
+
+def test_serve_alone_vs_mix(hm, wl):
+    """Probe requests each touch 4 private words no other request touches:
+    their results and final words are identical served alone and served
+    inside a 20,000-request mix (tolerance 0)."""
+    P0 = HOST_LO - 4096
+    n_probe = 512
+    g = wl.rng("c5", 1, 3)
+    init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    probe_idx = (P0 + np.arange(n_probe * 4)).astype(np.uint64)
+    probes = wl._oplist_from_lists(np.full(n_probe, 4, np.uint64), np.full(n_probe, 2), probe_idx, 10 ** 6)
+    mix = wl.c5_requests(g, 20000, 4e6, n_words=N, host_lo=P0)     # the mix stays below the probes
+    log = host_stream(wl, 9, 1 << 20, HOST_LO, N)
+
+    def run(arr, batch):
+        ctx = make_ctx(hm, init, True)
+        host_t = hm.pinned(N * 4)
+        host_t.numpy()[:] = init.view(np.uint8)
+        out = ctx.serve(arr, batch, host_t, log, 1024, 4096, 32 << 20, True)
+        S = ctx.read_state(hm.HETM_STATE_STMR).copy()
+        ctx.close()
+        return out, S
+
+    t_probe = np.sort(np.random.default_rng(3).uniform(0, 0.004, n_probe))
+    alone, S_alone = run(t_probe, probes)
+    # interleave probes with the mix by arrival time
+    arr = np.concatenate([mix["arrival_s"], t_probe])
+    order = np.argsort(arr, kind="stable")
+    mb = mix["batch"]
+    allb = wl.OplistBatch(offsets=np.concatenate([mb.offsets, mb.offsets[-1] + probes.offsets[1:]]).astype(np.uint32),
+                          idx=np.concatenate([mb.idx, probes.idx]), n_writes=np.concatenate([mb.n_writes, probes.n_writes]),
+                          tid=np.concatenate([mb.tid, probes.tid]))
+    sub = _subset(allb, order)
+    mixed, S_mixed = run(arr[order], sub)
+    pos = np.flatnonzero(order >= mix["arrival_s"].shape[0])            # probes inside the mixed request list
+    assert pos.shape[0] == n_probe
+    got = np.concatenate([mixed["results"][sub.offsets[p]:sub.offsets[p + 1]] for p in pos])
+    assert np.array_equal(got, alone["results"])
+    assert np.array_equal(S_mixed[P0:P0 + 4 * n_probe], S_alone[P0:P0 + 4 * n_probe])
+    say(f"alone p99={alone['p99_latency_us']:.0f}us  mixed p99={mixed['p99_latency_us']:.0f}us rounds={mixed['rounds']}")
