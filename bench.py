@@ -71,6 +71,35 @@ def load_traffic(kernel: str):
     return e.get("bytes_per_launch")
 
 
+def serve_forms(args, hm, wl, torch) -> dict:
+    """The serving configuration: open-loop Poisson arrivals of lognormal
+    (median 4, capped at 64 ops) transactions over a 2^27-word STMR with 5%
+    hot words; rounds admitted under a 2 GiB budget; continuous batching
+    (pipelined) against plain per-round serving at the same rate."""
+    N = 1 << 27
+    host_lo = N - N // 16
+    g = wl.rng("c5", 0, 3)
+    init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    req = wl.c5_requests(g, args.serve_requests, args.serve_rate, n_words=N, host_lo=host_lo)
+    per_round = 1 << 16
+    hlog = wl.host_log_uniform(np.random.default_rng(5), 1 << 23, host_lo, N, 0, shuffle_ts=False)
+    res = {"workload": f"2^27 u32 words, {args.serve_requests} requests at {args.serve_rate:g} txn/s Poisson, "
+                       f"lognormal lengths (median 4, max 64), 5% hot words, host log {per_round}/round, "
+                       f"budget 2 GiB, granule 64"}
+    for name, pipelined in (("pipelined", True), ("plain", False)):
+        log(f"served form: {name} ...")
+        kw = dict(mode=1, async_merge=True) if pipelined else dict(mode=0)
+        ctx = hm.Context(N, 4, 64, init=init, max_ops=64, batch_capacity=1 << 20, log_capacity=per_round, **kw)
+        host = hm.pinned(N * 4)
+        host.numpy()[:] = init.view(np.uint8)
+        o = ctx.serve(req["arrival_s"], req["batch"], host, hlog, per_round, 1 << 20, 2 << 30, pipelined)
+        ctx.close()
+        res[name] = {"throughput_txn_s": o["throughput"], "p50_latency_us": o["p50_latency_us"],
+                     "p99_latency_us": o["p99_latency_us"], "rounds": int(o["rounds"]),
+                     "conflicted_rounds": int(o["conflicted_rounds"])}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +113,9 @@ def main():
     ap.add_argument("--stripe", type=int, default=1)
     ap.add_argument("--exec-wg", type=int, default=0, help="transaction-kernel workgroups (0 = occupancy x CUs)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=3e7, help="Poisson arrival rate of the served form (txn/s)")
+    ap.add_argument("--serve-requests", type=int, default=1 << 21)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 1 GiB device copy, the known-size reference for HBM counters")
@@ -130,9 +162,9 @@ def main():
     host = hm.pinned(N * 4)
     host.numpy()[:] = ri.init.view(np.uint8)
 
-    def run(mode: int, k_steps: int, warm: int):
+    def run(mode: int, k_steps: int, warm: int, async_merge: bool = False):
         ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=n_txn,
-                         log_capacity=n_log, mode=mode, exec_workgroups=args.exec_wg)
+                         log_capacity=n_log, mode=mode, exec_workgroups=args.exec_wg, async_merge=async_merge)
         b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
         flags = torch.zeros(((n_log + 31) // 32) * 4, dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()
@@ -147,14 +179,15 @@ def main():
             rr = ctx.round(b, logs[r], n_log, host, flags)
             lat.append(time.perf_counter() - t1)
             res.append(rr.as_dict())
+        ctx.sync()                       # the last round's merge copy has landed
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         tickets = b.tickets_np().copy()
         ctx.close()
         return elapsed, lat, res, tickets
 
-    log("graph form ...")
-    el_g, lat_g, res_g, tickets = run(hm.HETM_MODE_GRAPH, args.steps, args.warmup)
+    log("batched form (graph + double-buffered merge) ...")
+    el_g, lat_g, res_g, tickets = run(hm.HETM_MODE_GRAPH, args.steps, args.warmup, async_merge=True)
     committed = sum(r["n_committed"] for r in res_g)
     value = committed / el_g
     out = {
@@ -165,21 +198,26 @@ def main():
         "config": {"workload": f"large synthetic STMR: 2^{args.log2_words} u32 words, 2^{args.log2_txns} txns/batch "
                                f"(90% RO x16 reads, 10% 4RMW), hot 1% at p={args.p_hot}, host log "
                                f"2^{args.log2_log}, granule {G}, lock stripe {args.stripe}",
-                   "form": "graph"},
-        "p50_commit_latency_ms": 1e3 * float(np.percentile(lat_g, 50)),
-        "p99_commit_latency_ms": 1e3 * float(np.percentile(lat_g, 99)),
+                   "form": "batched: hipGraph round, persistent transaction kernel, double-buffered merge"},
+        "p50_round_ms": 1e3 * float(np.percentile(lat_g, 50)),
+        "p99_round_ms": 1e3 * float(np.percentile(lat_g, 99)),
         "conflict_rounds": sum(r["conflict"] for r in res_g),
         "local_retries_per_round": float(np.mean([r["n_local_retries"] for r in res_g])),
         "dirty_granules_per_round": float(np.mean([r["n_dirty"] for r in res_g])),
     }
+    log("graph form, merge inside the round ...")
+    el_s, lat_s, res_s, _ = run(hm.HETM_MODE_GRAPH, args.steps, args.warmup)
+    out["graph_sync_merge"] = {"value": sum(r["n_committed"] for r in res_s) / el_s,
+                               "ms_per_step": 1e3 * el_s / args.steps}
 
     if not args.no_plain:
         log("plain form ...")
         el_p, lat_p, res_p, _ = run(hm.HETM_MODE_PLAIN, args.steps, args.warmup)
         us = {k: float(np.mean([r[k] for r in res_p])) for k in ("us_exec", "us_validate", "us_merge", "us_total")}
         out["plain"] = {"value": sum(r["n_committed"] for r in res_p) / el_p, "ms_per_step": 1e3 * el_p / args.steps,
-                        "p50_commit_latency_ms": 1e3 * float(np.percentile(lat_p, 50)),
-                        "p99_commit_latency_ms": 1e3 * float(np.percentile(lat_p, 99)), **us}
+                        "p50_round_ms": 1e3 * float(np.percentile(lat_p, 50)),
+                        "p99_round_ms": 1e3 * float(np.percentile(lat_p, 99)), **us}
+        out["batched_vs_plain"] = value / out["plain"]["value"]
         va_bytes = VALIDATE_APPLY_BYTES_PER_ENTRY * n_log
         out["validate_apply"] = {"achieved_GBps": va_bytes / (us["us_validate"] * 1e-6) / 1e9,
                                  "frac_of_hbm_peak": va_bytes / (us["us_validate"] * 1e-6) / 1e9 / HBM_PEAK_GBPS,
@@ -199,6 +237,9 @@ def main():
         out["roofline"] = {"bound": "hbm", "kernel": kern, "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBPS, "traffic": load_traffic(kern),
                            "alg_bytes_per_launch": alg, "avg_launch_us": steps_us[dominant]}
+
+    if not args.no_serve:
+        out["served"] = serve_forms(args, hm, wl, torch)
 
     if not args.no_cpu:
         import oracle as orc

@@ -261,6 +261,11 @@ typedef struct {
 } hetm_stats;
 int hetm_stats_get(hetm_ctx *ctx, hetm_stats *out);
 
+/* Sets the number of workgroups of the transaction kernel (0 = occupancy x
+ * compute units) for later batches; a captured round graph is re-captured.
+ * Used by the autotuner.  Errors: EINVAL. */
+int hetm_set_exec_workgroups(hetm_ctx *ctx, uint32_t workgroups);
+
 /* Copies context state out (synchronizes).  what: 0 STMR (N*W bytes),
  * 1 TS (N u64), 2 read-set bitmap, 3 write-set bitmap (ceil(ceil(N/G)/32)
  * u32 each), 4 lock table.  dst host-or-device, bytes = its size. */

@@ -611,6 +611,25 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     return HETM_OK;
 }
 
+int hetm_set_exec_workgroups(hetm_ctx *c, uint32_t workgroups) {
+    if (!c || c->round_open) return HETM_EINVAL;
+    if (workgroups == 0) {
+        hipDeviceProp_t prop;
+        int cus = 256;
+        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) cus = prop.multiProcessorCount;
+        workgroups = (uint32_t)cus * exec_workgroups_per_cu(HETM_PROG_OPLIST);
+    }
+    c->exec_wg = workgroups;
+    if (c->graph_exec) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipGraphExecDestroy(c->graph_exec);
+        (void)hipGraphDestroy(c->graph);
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+    }
+    return HETM_OK;
+}
+
 int hetm_sync(hetm_ctx *c) {
     if (!c) return HETM_EINVAL;
     int dr = drain_merges(c);

@@ -32,7 +32,7 @@ EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_a
            "hetm_copyback_dirty", "hetm_round", "hetm_strerror", "hetm_last_error", "hetm_sync",
            "hetm_stats_get", "hetm_read_state", "hetm_state_bytes", "hetm_host_tm_create",
            "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts",
-           "hetm_serve"]
+           "hetm_serve", "hetm_set_exec_workgroups"]
 
 P = ctypes.c_void_p
 U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -127,6 +127,7 @@ def lib() -> ctypes.CDLL:
             "hetm_host_tm_clock": ([P], U64),
             "hetm_host_run_transfers": ([P, P, P, P, U64, U32, P, P, U64, ctypes.POINTER(U64)], ctypes.c_int),
             "hetm_host_run_cache_puts": ([P, P, U64, U32, P, P, U64, ctypes.POINTER(U64)], ctypes.c_int),
+            "hetm_set_exec_workgroups": ([P, U32], ctypes.c_int),
             "hetm_serve": ([P, ctypes.POINTER(hetm_serve_spec), P, ctypes.POINTER(hetm_serve_report)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
@@ -368,6 +369,9 @@ class Context:
 
     def sync(self) -> None:
         hetm_sync(self.ctx)
+
+    def set_exec_workgroups(self, wg: int) -> None:
+        _check(lib().hetm_set_exec_workgroups(self.ctx, wg), "hetm_set_exec_workgroups", self.ctx)
 
     # -- round steps
     def submit(self, b: Batch) -> None:
