@@ -508,18 +508,6 @@ __global__ void k_begin_batch(const DevArgs *__restrict__ a) {
 
 }  // namespace
 
-uint32_t exec_workgroups_per_cu(uint32_t program) {
-    int blocks = 0;
-    const int threads = kExecWaves * kWave;
-    hipError_t e;
-    if (program == HETM_PROG_OPLIST)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_exec_oplist, threads, 0);
-    else if (program == HETM_PROG_TRANSFER)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_exec_transfer, threads, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_exec_cache, threads, 0);
-    return (e == hipSuccess && blocks > 0) ? (uint32_t)blocks : 2u;
-}
 
 void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, hipStream_t s) {
     hipLaunchKernelGGL(k_begin_batch, dim3(1), dim3(64), 0, s, a);

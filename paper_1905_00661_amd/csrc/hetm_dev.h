@@ -80,7 +80,8 @@ struct DevArgs {
     uint64_t *ts;
     uint32_t *rs;
     uint32_t *ws;
-    uint32_t *suspect;      // one bit per staged log entry (apply pass 1 -> 2)
+    uint32_t *suspect;      // apply pass 1 -> 2: entry met its own ts (a tie), one bit per entry
+    uint32_t *multi;        // apply pass 1 -> 2: entry met another entry of the round for its word
     uint32_t *blocksums;    // compaction: per-block dirty counts, then offsets
     uint32_t *blockruns;
     uint32_t *ids_scratch;  // ceil(N/G) dirty granule ids
@@ -211,7 +212,6 @@ void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hip
 void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
 void launch_staged_copy(bool to_host, void *stmr, void *host, const void *staging, const uint32_t *ids,
                         const uint32_t *count, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
-uint32_t exec_workgroups_per_cu(uint32_t program);
 
 constexpr uint32_t kScanWordsPerBlock = 2048;   // bitmap words per compaction block
 constexpr uint32_t kScanThreads = 256;

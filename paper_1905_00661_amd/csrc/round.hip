@@ -6,12 +6,14 @@
 //             per store; checks the entry preconditions.
 //  apply    : two passes instead of a per-word lock.  Pass 1 raises TS[w] to
 //             the largest timestamp of the entries for w with a 64-bit atomic
-//             max and marks an entry "suspect" when the max it met already
-//             equalled its own timestamp.  Pass 2 lets the entry whose
-//             timestamp equals the final TS[w] store its value; a suspect
-//             entry that equals it means two entries carry w's winning
-//             timestamp (an ordering error).  The result is the freshest entry
-//             per word, independent of arrival order, with no spinning.
+//             max; the first entry of the round for a word stores its value
+//             right away, later ones are flagged.  Pass 2 scans the flag bits
+//             and lets the flagged entry whose timestamp equals the final
+//             TS[w] store; a tie flag on it means two entries carry w's
+//             winning timestamp (an ordering error).  The result is the
+//             freshest entry per word, independent of arrival order, with no
+//             spinning, and the random accesses of pass 2 are only for words
+//             the chunk writes more than once.
 //  compact  : popcount + prefix sum over the write-set bitmap (per-block
 //             counts, the last block scans the block sums, then each block
 //             emits ascending dirty granule ids); runs of consecutive ids are
@@ -115,7 +117,12 @@ __global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a)
 }
 
 // ------------------------------------------------------------------- apply
-template <typename E>
+// Pass 1: atomic max of the entry's ts into TS[w].  If the old value is at
+// or below the watermark, no entry of this round has touched w before: the
+// entry stores its value at once (if a later entry of the round raises TS
+// further, that entry is flagged and re-stores in pass 2).  Otherwise the
+// entry is flagged "multi", and "tie" too if the old value equals its own ts.
+template <typename E, typename Word>
 __global__ __launch_bounds__(256) void k_apply_max(const DevArgs *__restrict__ a) {
     DevCounters *cnt = a->cnt;
     if (ld_agent(&cnt->error)) return;   // a chunk failing its preconditions applies nothing
@@ -126,25 +133,37 @@ __global__ __launch_bounds__(256) void k_apply_max(const DevArgs *__restrict__ a
     }
     const E *log = (const E *)a->log;
     const uint64_t n = a->n_log;
+    const uint64_t floor_ts = ld_agent(&cnt->floor_ts);
     uint64_t *ts = a->ts;
-    uint32_t *suspect = a->suspect;
+    Word *stmr = (Word *)a->stmr;
+    uint32_t *tie = a->suspect, *multi = a->multi;
     const uint32_t nw = (uint32_t)((n + 31) / 32);
     const uint32_t lane = lane_id();
     const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t kb = wave * kWave; kb < n; kb += stride) {
         const uint64_t k = kb + lane;
-        bool sus = false;
+        bool t = false, m = false;
         if (k < n) {
             const E e = log[k];
-            uint64_t old = __hip_atomic_fetch_max(&ts[e.word], (uint64_t)e.ts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sus = old == e.ts;
+            const uint64_t old = __hip_atomic_fetch_max(&ts[e.word], (uint64_t)e.ts, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            if (old <= floor_ts)
+                stmr[e.word] = (Word)e.value;
+            else
+                m = true;
+            t = old == e.ts;
         }
-        const uint64_t m = __ballot(sus);
-        if (lane == 0) store_bits(suspect, kb, m, nw);
+        const uint64_t tb = __ballot(t), mb = __ballot(m);
+        if (lane == 0) {
+            store_bits(tie, kb, tb, nw);
+            store_bits(multi, kb, mb, nw);
+        }
     }
 }
 
+// Pass 2: only flagged entries; the one whose ts is the final TS[w] stores
+// its value, and a tie flag on it means two entries carry w's winning ts.
 template <typename E, typename Word>
 __global__ __launch_bounds__(256) void k_apply_store(const DevArgs *__restrict__ a) {
     DevCounters *cnt = a->cnt;
@@ -156,16 +175,24 @@ __global__ __launch_bounds__(256) void k_apply_store(const DevArgs *__restrict__
     const E *log = (const E *)a->log;
     const uint64_t n = a->n_log;
     const uint64_t *ts = a->ts;
-    const uint32_t *suspect = a->suspect;
+    const uint32_t *tie = a->suspect, *multi = a->multi;
     Word *stmr = (Word *)a->stmr;
+    const uint64_t nwords = (n + 31) / 32;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += stride) {
-        const E e = log[k];
-        if (ts[e.word] != e.ts) continue;     // a fresher entry (or an earlier round) holds the word
-        if ((suspect[k >> 5] >> (k & 31)) & 1u)
-            latch_error(cnt, HETM_EORDER, (uint32_t)k);
-        else
-            stmr[e.word] = (Word)e.value;
+    for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < nwords; w += stride) {
+        uint32_t m = multi[w];
+        const uint32_t t = tie[w];
+        while (m) {
+            const uint32_t b = __ffs(m) - 1;
+            m &= m - 1;
+            const uint64_t k = w * 32 + b;
+            const E e = log[k];
+            if (ts[e.word] != e.ts) continue;     // a fresher entry holds the word
+            if ((t >> b) & 1u)
+                latch_error(cnt, HETM_EORDER, (uint32_t)k);
+            else
+                stmr[e.word] = (Word)e.value;
+        }
     }
 }
 
@@ -437,12 +464,13 @@ void launch_validate(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hi
 
 void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s) {
     const uint32_t grid = stream_grid(max_log, 256, 8192);
+    const uint32_t grid2 = stream_grid((max_log + 31) / 32, 256, 2048);
     if (word_bytes == 4) {
-        hipLaunchKernelGGL(k_apply_max<Entry4>, dim3(grid), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_apply_store<Entry4, uint32_t>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_apply_max<Entry4, uint32_t>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_apply_store<Entry4, uint32_t>), dim3(grid2), dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL(k_apply_max<Entry8>, dim3(grid), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_apply_store<Entry8, uint64_t>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_apply_max<Entry8, uint64_t>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_apply_store<Entry8, uint64_t>), dim3(grid2), dim3(256), 0, s, a);
     }
 }
 
@@ -486,7 +514,7 @@ void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_
 void launch_staged_copy(bool to_host, void *stmr, void *host, const void *staging, const uint32_t *ids,
                         const uint32_t *count, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s) {
     // the host link bounds this copy, so a modest grid leaves the CUs to the next round
-    const uint32_t grid = to_host ? 256 : 4096;
+    const uint32_t grid = to_host ? 128 : 4096;
     const uint64_t gbytes = (uint64_t)granule * word_bytes;
     if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0)
         hipLaunchKernelGGL(k_staged_copy<uint4>, dim3(grid), dim3(256), 0, s, to_host, (uint4 *)stmr, (uint4 *)host,
