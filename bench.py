@@ -204,6 +204,7 @@ def main():
         "conflict_rounds": sum(r["conflict"] for r in res_g),
         "local_retries_per_round": float(np.mean([r["n_local_retries"] for r in res_g])),
         "dirty_granules_per_round": float(np.mean([r["n_dirty"] for r in res_g])),
+        "graph_us": float(np.mean([r["us_total"] for r in res_g])),
     }
     log("graph form, merge inside the round ...")
     el_s, lat_s, res_s, _ = run(hm.HETM_MODE_GRAPH, args.steps, args.warmup)

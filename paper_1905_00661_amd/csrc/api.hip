@@ -207,16 +207,21 @@ int check_host_replica(hetm_ctx *c, void *host, const void **dev) {
 
 // Waits until every staged merge copy has reached the host replica.
 int drain_merges(hetm_ctx *c) {
+    if (c->cap_stream) HIP_TRY(c, hipStreamSynchronize(c->cap_stream));
     if (c->copy_stream) HIP_TRY(c, hipStreamSynchronize(c->copy_stream));
     c->pending[0] = c->pending[1] = false;
     return HETM_OK;
 }
 
-// Captures the round once on a private stream (the default stream cannot
-// be captured); the instantiated graph is launched on the caller's stream.
+// Captures the round once on a private non-blocking stream (the default
+// stream cannot be captured).  The graph also runs there, after an event
+// from the caller's stream, so that it never waits on unrelated work (the
+// legacy default stream synchronizes with other blocking streams) and the
+// merge copy of the previous round, on its own stream, overlaps it.
 int build_graph(hetm_ctx *c) {
     if (c->graph_exec) return HETM_OK;
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (!c->caller_ready) HIP_TRY(c, hipEventCreateWithFlags(&c->caller_ready, hipEventDisableTiming));
     hipStream_t s = c->cap_stream;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     (void)hipMemcpyAsync(c->dargs, c->hargs, sizeof(DevArgs), hipMemcpyHostToDevice, s);
@@ -269,7 +274,6 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
         c->args.n_txns = 0;
         if (!c->args.program) c->args.program = HETM_PROG_OPLIST;
     }
-    hipStream_t s = c->stream;
     const void *dlog = nullptr;
     if (r->n_log && (rc = stage_log(c, r->log, r->n_log, &dlog))) return rc;
     c->args.log = dlog;
@@ -286,6 +290,9 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
     }
     if ((rc = build_graph(c))) return rc;
     c->graph_program = c->args.program;
+    hipStream_t s = c->cap_stream;
+    HIP_TRY(c, hipEventRecord(c->caller_ready, c->stream));   // after the caller's uploads, staged log, ...
+    HIP_TRY(c, hipStreamWaitEvent(s, c->caller_ready, 0));
     const int b = c->buf;
     if (c->cfg.async_merge) {
         // the staging buffer this round fills must have reached the host
@@ -310,7 +317,7 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
 int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     if (!c->round_open) return fail(c, HETM_ESTATE, "no round open");
     c->round_open = false;
-    hipStream_t s = c->stream;
+    hipStream_t s = c->cap_stream;
     const void *hdev = c->round_hdev;
     const int b = c->round_buf;
     int rc;
@@ -501,7 +508,9 @@ int hetm_free(hetm_ctx *c) {
     if (c->hargs) (void)hipHostFree(c->hargs);
     if (c->snap_host) (void)hipHostFree(c->snap_host);
     if (c->cnt_host) (void)hipHostFree(c->cnt_host);
+    if (c->cap_stream) (void)hipStreamSynchronize(c->cap_stream);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->caller_ready) (void)hipEventDestroy(c->caller_ready);
     for (int b = 0; b < 2; ++b) {
         if (c->graph_done[b]) (void)hipEventDestroy(c->graph_done[b]);
         if (c->copied[b]) (void)hipEventDestroy(c->copied[b]);

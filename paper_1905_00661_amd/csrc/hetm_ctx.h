@@ -14,7 +14,8 @@ using hetm::HotCounters;
 struct hetm_ctx {
     hetm_config cfg{};
     hipStream_t stream = nullptr;      // the caller's stream (nullptr = default stream)
-    hipStream_t cap_stream = nullptr;  // private stream used only to capture the round graph
+    hipStream_t cap_stream = nullptr;  // private non-blocking stream: captures and runs the round graph
+    hipEvent_t caller_ready = nullptr; // orders the graph after the caller's earlier work
     int device = 0;
     uint32_t exec_wg = 0;
     uint32_t log_entry_bytes = 16;

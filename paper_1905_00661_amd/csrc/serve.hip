@@ -289,6 +289,7 @@ struct Serve {
                 RoundSet &r = set[nxt];
                 host_commit(r);
                 a[nxt] = round_args(r, d[nxt]);
+                // round_begin orders the graph after the caller's stream
                 if (hipStreamWaitEvent(c->stream, r.uploaded, 0) != hipSuccess) return HETM_EDEVICE;
                 if ((err = hetm::round_begin(c, &a[nxt]))) return err;
                 cur = nxt;
