@@ -224,7 +224,12 @@ int build_graph(hetm_ctx *c) {
     if (!c->caller_ready) HIP_TRY(c, hipEventCreateWithFlags(&c->caller_ready, hipEventDisableTiming));
     hipStream_t s = c->cap_stream;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    (void)hipMemcpyAsync(c->dargs, c->hargs, sizeof(DevArgs), hipMemcpyHostToDevice, s);
+    // The arguments enter the graph as the by-value parameters of a one-thread
+    // kernel node, updated per round (hipGraphExecKernelNodeSetParams): the
+    // host writes kernel parameters into device memory, whereas a host-to-
+    // device copy node would issue PCIe reads that queue behind the previous
+    // round's merge copy (device-to-host posted writes) and stall the launch.
+    launch_set_args(c->args, c->dargs, s);
     launch_exec(c->args.program, c->dargs, c->exec_wg, s);
     launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
     launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
@@ -244,6 +249,23 @@ int build_graph(hetm_ctx *c) {
         return fail(c, HETM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
     }
     c->graph = g;
+    // find the argument-upload node
+    size_t nn = 0;
+    HIP_TRY(c, hipGraphGetNodes(g, nullptr, &nn));
+    hipGraphNode_t nodes[64];
+    if (nn > 64) return fail(c, HETM_EDEVICE, "unexpected graph size %zu", nn);
+    HIP_TRY(c, hipGraphGetNodes(g, nodes, &nn));
+    c->args_node = nullptr;
+    for (size_t i = 0; i < nn; ++i) {
+        hipGraphNodeType t;
+        if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp{};
+        if (hipGraphKernelNodeGetParams(nodes[i], &kp) == hipSuccess && kp.func == set_args_kernel()) {
+            c->args_node = nodes[i];
+            c->args_params = kp;
+        }
+    }
+    if (!c->args_node) return fail(c, HETM_EDEVICE, "argument node not found in the round graph");
     return HETM_OK;
 }
 
@@ -301,9 +323,12 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
         c->args.stage_ids = c->stage_ids[b];
         c->args.stage_count = c->stage_count[b];
     }
-    // the previous round_end synchronized the stream, so the graph's upload
-    // node has consumed the pinned argument block
-    *c->hargs = c->args;
+    DevArgs *dst = c->dargs;
+    void *kargs[2] = {&c->args, &dst};
+    hipKernelNodeParams kp = c->args_params;
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    HIP_TRY(c, hipGraphExecKernelNodeSetParams(c->graph_exec, c->args_node, &kp));
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
     HIP_TRY(c, hipEventRecord(c->ev[3], s));

@@ -43,6 +43,8 @@ struct hetm_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     uint32_t graph_program = 0;
+    hipGraphNode_t args_node = nullptr;     // the graph's argument-upload kernel node
+    hipKernelNodeParams args_params{};
 
     // double-buffered merge (GRAPH mode with async_merge)
     hipStream_t copy_stream = nullptr;

@@ -202,6 +202,7 @@ __device__ __forceinline__ void bitmap_set(uint32_t *bm, uint32_t g) {
 // Host-side launch wrappers, defined next to their kernels.  `a` is the
 // device address of the DevArgs block every kernel reads its arguments from.
 void launch_set_args(const DevArgs &host_copy, DevArgs *dev, hipStream_t s);
+const void *set_args_kernel();   // host handle of the argument-upload kernel
 void launch_clear_error(DevCounters *cnt, hipStream_t s);
 void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, hipStream_t s);
 void launch_validate(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);

@@ -450,6 +450,8 @@ void launch_set_args(const DevArgs &host_copy, DevArgs *dev, hipStream_t s) {
     hipLaunchKernelGGL(k_set_args, dim3(1), dim3(64), 0, s, host_copy, dev);
 }
 
+const void *set_args_kernel() { return reinterpret_cast<const void *>(&k_set_args); }
+
 void launch_clear_error(DevCounters *cnt, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_error, dim3(1), dim3(64), 0, s, cnt);
 }
