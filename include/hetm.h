@@ -84,7 +84,7 @@ typedef struct {
     void    *stream;             /* hipStream_t for all work; NULL = the device's
                                     default (null) stream                        */
     uint32_t exec_workgroups;    /* transaction-kernel workgroups; 0 = auto      */
-    uint32_t retry_cap;          /* local attempts per transaction; 0 = 1<<20    */
+    uint32_t retry_cap;          /* local attempts per transaction; 0 = 1<<24    */
     uint32_t async_merge;        /* GRAPH mode only: 1 = double-buffered merge --
                                     the round gathers its dirty granules into one
                                     of two HBM staging buffers and a copy stream
@@ -188,6 +188,25 @@ int hetm_submit_batch(hetm_ctx *ctx, uint32_t program, const void *descs, uint64
 int hetm_validate_apply_log(hetm_ctx *ctx, const void *log, uint64_t n, uint32_t *flags_bits,
                             uint32_t *conflict_out);
 
+/* Early validation (§IV-D), step API of a PLAIN context: validates, without
+ * applying, a chunk of the host log (n entries, device memory or pinned host
+ * memory, complete when the call is made: the CPU's transactions wrote it)
+ * against the read-set bitmap as it stands while batches submitted with
+ * hetm_submit_batch may still be executing.  It runs on a stream of its own,
+ * ordered only after the previous round's merge, so it overlaps the
+ * transaction kernels.  A hit dooms the round: the CPU wins, so the running
+ * transaction kernel stops at its next iteration, later batches of the round
+ * execute nothing, and the round's outcome is a conflict.  Every chunk must
+ * still go through hetm_validate_apply_log, which applies it; early
+ * validation may miss a conflict (the bitmap is still growing), never invent
+ * one.  Entries that fail the log's preconditions are skipped here and
+ * reported by hetm_validate_apply_log.  The chunk is read until the round's
+ * merge starts.
+ * doomed_out (host, nullable): if given, waits for this chunk and stores 1 if
+ * an early validation of the open round found a conflict.
+ * Errors: EINVAL, ESTATE (a GRAPH context, whose round is one graph launch). */
+int hetm_early_validate(hetm_ctx *ctx, const void *log, uint64_t n, uint32_t *doomed_out);
+
 /* Merge phase (§IV-C.3) and round end.  conflict: 0 success, 1 conflict,
  * or HETM_OUTCOME_DEVICE.  On success the write-set granules are copied
  * GPU->host_replica, on conflict host_replica->GPU (undoing the GPU
@@ -226,7 +245,8 @@ typedef struct {
     uint64_t max_ts;           /* watermark after the round                     */
     uint32_t merge_pending;    /* 1: the copy to the host replica is still in
                                   flight (async_merge); hetm_sync waits for it   */
-    uint32_t pad_;
+    uint32_t doomed;           /* 1: early validation found the conflict and the
+                                  transaction kernels stopped short            */
     double   us_exec;          /* step times from HIP events (PLAIN mode)       */
     double   us_validate;
     double   us_merge;

@@ -80,6 +80,7 @@ const void *device_view(const void *p) {
 }
 
 int push_args(hetm_ctx *c) {
+    c->args.epoch = c->epoch;
     launch_set_args(c->args, c->dargs, c->stream);
     HIP_TRY(c, hipGetLastError());
     return HETM_OK;
@@ -158,6 +159,9 @@ int enqueue_validate(hetm_ctx *c, const void *dev_log, uint64_t n, uint32_t *fla
 }
 
 int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t *ids_out) {
+    // the round closes after its early validations (they read the caller's log chunks)
+    if (c->early_used) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->early_ev, 0));
+    c->early_used = false;
     c->args.outcome = outcome;
     c->args.host = const_cast<void *>(host_dev);
     c->args.ids_out = ids_out;
@@ -168,6 +172,9 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
     launch_finish(c->dargs, c->snap_dev, c->args.n_bm_words, c->stream);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipEventRecord(c->closed_ev, c->stream));
+    c->closed_recorded = true;
+    ++c->epoch;
     return HETM_OK;
 }
 
@@ -191,6 +198,7 @@ void account_round(hetm_ctx *c, const DevCounters &s, uint64_t n_txns, hetm_roun
         res->n_dirty = s.n_dirty;
         res->n_runs = s.n_runs;
         res->max_ts = s.floor_ts;
+        res->doomed = s.doomed == c->epoch - 1;     // the round just closed
     }
 }
 
@@ -323,6 +331,7 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
         c->args.stage_ids = c->stage_ids[b];
         c->args.stage_count = c->stage_count[b];
     }
+    c->args.epoch = c->epoch;
     DevArgs *dst = c->dargs;
     void *kargs[2] = {&c->args, &dst};
     hipKernelNodeParams kp = c->args_params;
@@ -342,6 +351,7 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
 int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     if (!c->round_open) return fail(c, HETM_ESTATE, "no round open");
     c->round_open = false;
+    ++c->epoch;
     hipStream_t s = c->cap_stream;
     const void *hdev = c->round_hdev;
     const int b = c->round_buf;
@@ -415,7 +425,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     hetm_ctx *c = new (std::nothrow) hetm_ctx();
     if (!c) return HETM_ENOMEM;
     c->cfg = k;
-    if (c->cfg.retry_cap == 0) c->cfg.retry_cap = 1u << 20;
+    if (c->cfg.retry_cap == 0) c->cfg.retry_cap = 1u << 24;
     c->device = k.device;
     c->log_entry_bytes = k.word_bytes == 4 ? sizeof(hetm_log_entry4) : sizeof(hetm_log_entry8);
     int rc = HETM_OK;
@@ -480,6 +490,13 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
             hetm_free(c);
             return HETM_EDEVICE;
         }
+    if (hipStreamCreateWithFlags(&c->early_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->closed_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->early_ev, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void **)&c->early_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        hetm_free(c);
+        return HETM_EDEVICE;
+    }
     hipStream_t s = c->stream;
     bool ok = hipMemsetAsync(c->locks, 0, nlocks * 8, s) == hipSuccess &&
               hipMemsetAsync(c->ts, 0, N * 8, s) == hipSuccess &&
@@ -520,8 +537,9 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
 int hetm_free(hetm_ctx *c) {
     if (!c) return HETM_EINVAL;
     (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+    // every queue of the context drains before its memory goes
+    for (hipStream_t s : {c->stream, c->cap_stream, c->copy_stream, c->early_stream})
+        if (s) (void)hipStreamSynchronize(s);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     for (auto &e : c->ev)
@@ -533,7 +551,7 @@ int hetm_free(hetm_ctx *c) {
     if (c->hargs) (void)hipHostFree(c->hargs);
     if (c->snap_host) (void)hipHostFree(c->snap_host);
     if (c->cnt_host) (void)hipHostFree(c->cnt_host);
-    if (c->cap_stream) (void)hipStreamSynchronize(c->cap_stream);
+    if (c->early_host) (void)hipHostFree(c->early_host);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->caller_ready) (void)hipEventDestroy(c->caller_ready);
     for (int b = 0; b < 2; ++b) {
@@ -544,6 +562,9 @@ int hetm_free(hetm_ctx *c) {
         if (c->stage_count[b]) (void)hipFree(c->stage_count[b]);
     }
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+    if (c->early_stream) (void)hipStreamDestroy(c->early_stream);
+    if (c->closed_ev) (void)hipEventDestroy(c->closed_ev);
+    if (c->early_ev) (void)hipEventDestroy(c->early_ev);
     delete c;
     return HETM_OK;
 }
@@ -650,6 +671,29 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
         res->us_validate = elapsed_us(c->ev[1], c->ev[2]);
         res->us_merge = elapsed_us(c->ev[2], c->ev[3]);
         res->us_total = elapsed_us(c->ev[0], c->ev[3]);
+    }
+    return HETM_OK;
+}
+
+int hetm_early_validate(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out) {
+    if (!c || (n && !log)) return HETM_EINVAL;
+    if (c->cfg.mode != HETM_MODE_PLAIN) return fail(c, HETM_ESTATE, "early validation needs the step API");
+    if (n) {
+        const void *dlog = device_view(log);
+        if (!dlog) return fail(c, HETM_EINVAL, "early validation needs a device or pinned log");
+        // the context's stream carries the batch: wait only for the last round's bitmap reset
+        if (c->closed_recorded) HIP_TRY(c, hipStreamWaitEvent(c->early_stream, c->closed_ev, 0));
+        launch_early_validate(dlog, n, c->cfg.word_bytes, c->rs, c->args.gdiv, c->cfg.n_words, c->epoch, c->cnt,
+                              c->early_stream);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipEventRecord(c->early_ev, c->early_stream));
+        c->early_used = true;
+    }
+    if (doomed_out) {
+        HIP_TRY(c, hipMemcpyAsync(c->early_host, &c->cnt->doomed, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                  c->early_stream));
+        HIP_TRY(c, hipStreamSynchronize(c->early_stream));
+        *doomed_out = *c->early_host == c->epoch;
     }
     return HETM_OK;
 }

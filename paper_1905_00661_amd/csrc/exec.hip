@@ -123,7 +123,7 @@ struct LaneState {
 };
 
 // Contention manager: after its k-th local abort a transaction sits out a
-// pseudo-random number of iterations below min(2^k, 64).  Lanes of one wave
+// pseudo-random number of iterations below min(2^k, 256).  Lanes of one wave
 // run in lockstep, so two transactions that each write what the other read
 // would otherwise abort each other identically forever; the random wait
 // breaks the symmetry.
@@ -132,7 +132,7 @@ __device__ __forceinline__ uint32_t backoff(uint32_t txn, uint32_t attempts) {
     h ^= h >> 15;
     h *= 0x2C1B3C6Du;
     h ^= h >> 12;
-    const uint32_t window = attempts >= 6 ? 64u : (1u << attempts);
+    const uint32_t window = attempts >= 8 ? 256u : (1u << attempts);
     return h & (window - 1);
 }
 
@@ -204,6 +204,18 @@ __device__ __forceinline__ void flush_counts(const LaneState &ls, DevCounters *c
     }
 }
 
+// Early validation doomed this round (§IV-D): the CPU wins, so the rest of
+// the batch is not worth executing.  The round is marked conflicted here, so
+// the skipped transactions can never be reported as committed even if the
+// chunk that doomed it is left out of the final validation.  Checked at the
+// top of the loop, where a lane holds no lock; the flag is wave-uniform.
+__device__ __forceinline__ bool doomed(DevCounters *cnt, uint32_t epoch) {
+    const uint32_t d = __builtin_amdgcn_readfirstlane(ld_agent(&cnt->doomed));
+    if (d != epoch) return false;
+    if (lane_id() == 0) st_agent(&cnt->conflict, 1u);
+    return true;
+}
+
 // ------------------------------------------------------------------ OPLIST
 // Transaction i reads idx[off[i] .. off[i+1]) in order, then writes each of
 // its first nw[i] words with (value read + tid[i]) mod 2^32.
@@ -222,10 +234,12 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     const uint8_t *nw = a->nw;
     uint32_t *res = (uint32_t *)a->results;
     WriteBuf<uint32_t, kOplistMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
+    const uint32_t epoch = a->epoch;
     LaneState ls = first_txn(n);
 
     while (refill(ls, a->hot, n)) {
         const bool act = lane_turn(ls, n);
+        if (doomed(cnt, epoch)) break;
         if (!__ballot(act)) {          // every lane is backing off
             __builtin_amdgcn_s_sleep(2);
             continue;
@@ -300,10 +314,12 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
     const uint64_t N = a->n_words;
     int64_t *res = (int64_t *)a->results;
     WriteBuf<uint64_t, 2> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
+    const uint32_t epoch = a->epoch;
     LaneState ls = first_txn(n);
 
     while (refill(ls, a->hot, n)) {
         const bool act = lane_turn(ls, n);
+        if (doomed(cnt, epoch)) break;
         if (!__ballot(act)) {          // every lane is backing off
             __builtin_amdgcn_s_sleep(2);
             continue;
@@ -395,10 +411,12 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
     const uint64_t nsets = a->n_words / kSetWords;
     uint32_t *res = (uint32_t *)a->results;
     WriteBuf<uint32_t, kCacheMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
+    const uint32_t epoch = a->epoch;
     LaneState ls = first_txn(n);
 
     while (refill(ls, a->hot, n)) {
         const bool act = lane_turn(ls, n);
+        if (doomed(cnt, epoch)) break;
         if (!__ballot(act)) {          // every lane is backing off
             __builtin_amdgcn_s_sleep(2);
             continue;

@@ -48,6 +48,13 @@ struct hetm_ctx {
 
     // double-buffered merge (GRAPH mode with async_merge)
     hipStream_t copy_stream = nullptr;
+    hipStream_t early_stream = nullptr;     // early validation, beside the running batch
+    hipEvent_t closed_ev = nullptr;         // PLAIN: the last round's bitmaps are cleared
+    hipEvent_t early_ev = nullptr;          // the last early validation of the round
+    bool early_used = false;                // an early validation is queued in the open round
+    bool closed_recorded = false;           // closed_ev has been recorded
+    uint32_t *early_host = nullptr;         // pinned: doomed flag read back
+    uint32_t epoch = 1;                     // number of the open round (tags a doomed round)
     hipEvent_t graph_done[2] = {};
     hipEvent_t copied[2] = {};
     bool pending[2] = {false, false};

@@ -69,6 +69,8 @@ struct DevCounters {
     uint32_t scan_ticket;         // blocks finished in the compaction count pass
     uint32_t err_index;           // index of the first bad log entry / transaction
     uint32_t chunk_conflict;      // the current chunk's flags, folded in when it applies
+    uint32_t doomed;              // epoch of the last round early validation doomed
+    uint32_t pad_[3];
 };
 
 // Everything a kernel needs: constant context state plus the arguments of
@@ -120,7 +122,7 @@ struct DevArgs {
     uint32_t *stage_ids;    // async merge: their ids
     uint32_t *stage_count;  // async merge: their number
     uint32_t outcome;       // 0 / 1 / HETM_OUTCOME_DEVICE
-    uint32_t pad_;
+    uint32_t epoch;         // the open round's number, as early validation tags a doomed round
 };
 
 // ------------------------------------------------------------------ atomics
@@ -210,6 +212,8 @@ void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipSt
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s);
 void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
 void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hipStream_t s);
+void launch_early_validate(const void *log, uint64_t n, uint32_t word_bytes, const uint32_t *rs, Div32 gdiv,
+                           uint64_t n_words, uint32_t epoch, DevCounters *cnt, hipStream_t s);
 void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
 void launch_staged_copy(bool to_host, void *stmr, void *host, const void *staging, const uint32_t *ids,
                         const uint32_t *count, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);

@@ -116,6 +116,27 @@ __global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a)
     }
 }
 
+// -------------------------------------------------------- early validation
+// Validation only (no apply) of a host log chunk against the read-set bitmap
+// as it stands while the batch still executes (§IV-D, early validation).  A
+// hit dooms the round: the CPU wins, so the transaction kernel stops at its
+// next iteration.  Missing a conflict here is harmless -- the validation at
+// the end of the round sees the final bitmap -- so entries failing the
+// preconditions are simply skipped (the final validation reports them).
+template <typename E>
+__global__ __launch_bounds__(256) void k_early_validate(const E *__restrict__ log, uint64_t n, const uint32_t *rs,
+                                                        Div32 G, uint64_t N, uint32_t epoch, DevCounters *cnt) {
+    bool hit = false;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n && !hit; k += stride) {
+        const E e = log[k];
+        if (e.word >= N) continue;
+        const uint32_t g = div32(e.word, G);
+        hit = (ld_agent(&rs[g >> 5]) >> (g & 31)) & 1u;
+    }
+    if (__ballot(hit) && lane_id() == 0) st_agent(&cnt->doomed, epoch);
+}
+
 // ------------------------------------------------------------------- apply
 // Pass 1: atomic max of the entry's ts into TS[w].  If the old value is at
 // or below the watermark, no entry of this round has touched w before: the
@@ -402,6 +423,8 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         c.err_index = ld_agent(&cnt->err_index);
         c.chunk_max_ts = 0;
         c.chunk_conflict = 0;
+        c.pad_[0] = c.pad_[1] = c.pad_[2] = 0;
+        c.doomed = ld_agent(&cnt->doomed);
         if (!err) {
             const uint64_t f = c.max_ts > c.floor_ts ? c.max_ts : c.floor_ts;
             c.floor_ts = f;
@@ -495,6 +518,17 @@ void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t 
         const uint32_t grid = stream_grid(n_granules * granule, 256, 16384);
         hipLaunchKernelGGL(k_copy<uint64_t>, dim3(grid), dim3(256), 0, s, a, granule, n_words);
     }
+}
+
+void launch_early_validate(const void *log, uint64_t n, uint32_t word_bytes, const uint32_t *rs, Div32 gdiv,
+                           uint64_t n_words, uint32_t epoch, DevCounters *cnt, hipStream_t s) {
+    const uint32_t grid = stream_grid(n, 256, 4096);
+    if (word_bytes == 4)
+        hipLaunchKernelGGL(k_early_validate<Entry4>, dim3(grid), dim3(256), 0, s, (const Entry4 *)log, n, rs, gdiv,
+                           n_words, epoch, cnt);
+    else
+        hipLaunchKernelGGL(k_early_validate<Entry8>, dim3(grid), dim3(256), 0, s, (const Entry8 *)log, n, rs, gdiv,
+                           n_words, epoch, cnt);
 }
 
 void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s) {

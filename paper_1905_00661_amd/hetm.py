@@ -32,7 +32,7 @@ EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_a
            "hetm_copyback_dirty", "hetm_round", "hetm_strerror", "hetm_last_error", "hetm_sync",
            "hetm_stats_get", "hetm_read_state", "hetm_state_bytes", "hetm_host_tm_create",
            "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts",
-           "hetm_serve", "hetm_set_exec_workgroups"]
+           "hetm_serve", "hetm_set_exec_workgroups", "hetm_early_validate"]
 
 P = ctypes.c_void_p
 U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -65,7 +65,7 @@ class hetm_round_args(ctypes.Structure):
 class hetm_round_result(ctypes.Structure):
     _fields_ = [("conflict", U32), ("error", I32), ("n_committed", U64), ("n_aborted", U64),
                 ("n_local_retries", U64), ("n_dirty", U64), ("n_runs", U64), ("max_ts", U64),
-                ("merge_pending", U32), ("pad_", U32), ("us_exec", ctypes.c_double), ("us_validate", ctypes.c_double),
+                ("merge_pending", U32), ("doomed", U32), ("us_exec", ctypes.c_double), ("us_validate", ctypes.c_double),
                 ("us_merge", ctypes.c_double), ("us_total", ctypes.c_double)]
 
     def as_dict(self) -> dict:
@@ -128,6 +128,7 @@ def lib() -> ctypes.CDLL:
             "hetm_host_run_transfers": ([P, P, P, P, U64, U32, P, P, U64, ctypes.POINTER(U64)], ctypes.c_int),
             "hetm_host_run_cache_puts": ([P, P, U64, U32, P, P, U64, ctypes.POINTER(U64)], ctypes.c_int),
             "hetm_set_exec_workgroups": ([P, U32], ctypes.c_int),
+            "hetm_early_validate": ([P, P, U64, P], ctypes.c_int),
             "hetm_serve": ([P, ctypes.POINTER(hetm_serve_spec), P, ctypes.POINTER(hetm_serve_report)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
@@ -369,6 +370,12 @@ class Context:
 
     def sync(self) -> None:
         hetm_sync(self.ctx)
+
+    def early_validate(self, log_dev, n: int, wait: bool = False):
+        d = U32(0)
+        _check(lib().hetm_early_validate(self.ctx, log_dev.data_ptr() if n else None, n,
+                                         ctypes.byref(d) if wait else None), "hetm_early_validate", self.ctx)
+        return int(d.value) if wait else None
 
     def set_exec_workgroups(self, wg: int) -> None:
         _check(lib().hetm_set_exec_workgroups(self.ctx, wg), "hetm_set_exec_workgroups", self.ctx)
