@@ -10,6 +10,7 @@
 // captured graph serves rounds whose buffers differ.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -217,6 +218,11 @@ int check_host_replica(hetm_ctx *c, void *host, const void **dev) {
 int drain_merges(hetm_ctx *c) {
     if (c->cap_stream) HIP_TRY(c, hipStreamSynchronize(c->cap_stream));
     if (c->copy_stream) HIP_TRY(c, hipStreamSynchronize(c->copy_stream));
+    if (c->merger) {
+        const uint64_t last = std::max(c->merge_seq[0], c->merge_seq[1]);
+        if (last && hetm::merge_wait(c->merger, last) != HETM_OK)
+            return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
+    }
     c->pending[0] = c->pending[1] = false;
     return HETM_OK;
 }
@@ -286,6 +292,39 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
     return ms * 1000.f;
 }
 
+// Success path of the double-buffered merge for staging buffer b holding D
+// packed granules: the pinned host staging b is free once the worker is done
+// with the round that used it last; it grows on demand (rarely: it keeps the
+// largest size seen).  The DMA runs on the copy stream after the graph.
+int stage_to_host(hetm_ctx *c, int b, uint64_t D) {
+    const uint64_t gbytes = (uint64_t)c->cfg.granule_words * c->cfg.word_bytes;
+    if (c->merge_seq[b] && hetm::merge_wait(c->merger, c->merge_seq[b]) != HETM_OK)
+        return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
+    if (D > c->host_cap[b]) {
+        const uint64_t nG = (c->cfg.n_words + c->cfg.granule_words - 1) / c->cfg.granule_words;
+        const uint64_t cap = std::min<uint64_t>(nG, D + D / 4 + 1024);
+        if (c->host_stage[b]) (void)hipHostFree(c->host_stage[b]);
+        if (c->host_ids[b]) (void)hipHostFree(c->host_ids[b]);
+        c->host_stage[b] = nullptr;
+        c->host_ids[b] = nullptr;
+        c->host_cap[b] = 0;
+        if (hipHostMalloc((void **)&c->host_stage[b], cap * gbytes, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&c->host_ids[b], cap * 4, hipHostMallocDefault) != hipSuccess)
+            return fail(c, HETM_ENOMEM, "pinned merge staging of %llu granules", (unsigned long long)cap);
+        c->host_cap[b] = cap;
+    }
+    HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->graph_done[b], 0));
+    if (D) {
+        HIP_TRY(c, hipMemcpyAsync(c->host_ids[b], c->stage_ids[b], D * 4, hipMemcpyDeviceToHost, c->copy_stream));
+        HIP_TRY(c, hipMemcpyAsync(c->host_stage[b], c->staging[b], D * gbytes, hipMemcpyDeviceToHost, c->copy_stream));
+    }
+    HIP_TRY(c, hipEventRecord(c->copied[b], c->copy_stream));
+    c->merge_seq[b] = hetm::merge_submit(c->merger, c->copied[b], c->host_ids[b], c->host_stage[b], D,
+                                         (uint8_t *)c->round_host, gbytes, c->cfg.n_words * c->cfg.word_bytes);
+    c->round_merge_seq = c->merge_seq[b];
+    return HETM_OK;
+}
+
 }  // namespace
 
 namespace hetm {
@@ -312,6 +351,7 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
     c->args.outcome = HETM_OUTCOME_DEVICE;
     c->args.host = const_cast<void *>(hdev);
     c->args.ids_out = r->ids_out;
+    c->round_host = r->host_replica;
     if (c->graph_exec && c->graph_program != c->args.program) {
         (void)hipGraphExecDestroy(c->graph_exec);
         (void)hipGraphDestroy(c->graph);
@@ -359,15 +399,12 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     HIP_TRY(c, hipStreamSynchronize(s));
     const DevCounters snap = *c->snap_host;
     if (snap.error) return take_device_error(c, snap.error, snap.err_index);
+    c->round_merge_seq = 0;
     if (c->cfg.async_merge) {
         if (!snap.conflict) {
-            // success: the copy stream writes the staged granules to the host
-            HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->graph_done[b], 0));
-            launch_staged_copy(true, c->stmr, const_cast<void *>(hdev), c->staging[b], c->stage_ids[b],
-                               c->stage_count[b], c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes,
-                               c->copy_stream);
-            HIP_TRY(c, hipGetLastError());
-            HIP_TRY(c, hipEventRecord(c->copied[b], c->copy_stream));
+            // success: DMA the staged granules to pinned host staging on the
+            // copy stream; the merge worker scatters them into the host replica
+            if ((rc = stage_to_host(c, b, snap.n_dirty))) return rc;
             c->pending[b] = true;
             c->last_copy = b;
             c->buf = b ^ 1;
@@ -376,8 +413,8 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
             // conflict (CPU wins): restore the dirty granules from the host
             // replica once the previous round's copy has landed there
             if ((rc = drain_merges(c))) return rc;
-            launch_staged_copy(false, c->stmr, const_cast<void *>(hdev), nullptr, c->stage_ids[b],
-                               c->stage_count[b], c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
+            launch_restore(c->stmr, hdev, c->stage_ids[b], c->stage_count[b], c->cfg.n_words, c->cfg.granule_words,
+                           c->cfg.word_bytes, s);
             HIP_TRY(c, hipGetLastError());
             HIP_TRY(c, hipStreamSynchronize(s));
         }
@@ -388,8 +425,13 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     return HETM_OK;
 }
 
-hipEvent_t last_copy_event(hetm_ctx *c) {
-    return (c->cfg.async_merge && c->last_copy >= 0 && c->pending[c->last_copy]) ? c->copied[c->last_copy] : nullptr;
+uint64_t last_merge_seq(hetm_ctx *c) { return c->round_merge_seq; }
+
+uint64_t merged_seq(hetm_ctx *c) { return c->merger ? merge_done(c->merger) : 0; }
+
+int wait_merged(hetm_ctx *c, uint64_t seq) {
+    if (!c->merger || !seq) return HETM_OK;
+    return merge_wait(c->merger, seq) == HETM_OK ? HETM_OK : fail(c, HETM_EDEVICE, "merge copy failed");
 }
 
 }  // namespace hetm
@@ -472,6 +514,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
             hetm_free(c);
             return HETM_EDEVICE;
         }
+        c->merger = hetm::merge_worker_create();
         for (int b = 0; b < 2; ++b)
             if (hipEventCreateWithFlags(&c->graph_done[b], hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming) != hipSuccess) {
@@ -540,6 +583,11 @@ int hetm_free(hetm_ctx *c) {
     // every queue of the context drains before its memory goes
     for (hipStream_t s : {c->stream, c->cap_stream, c->copy_stream, c->early_stream})
         if (s) (void)hipStreamSynchronize(s);
+    hetm::merge_worker_destroy(c->merger);     // finishes the queued scatters first
+    for (int b = 0; b < 2; ++b) {
+        if (c->host_stage[b]) (void)hipHostFree(c->host_stage[b]);
+        if (c->host_ids[b]) (void)hipHostFree(c->host_ids[b]);
+    }
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     for (auto &e : c->ev)

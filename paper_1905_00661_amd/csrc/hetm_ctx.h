@@ -6,6 +6,7 @@
 
 #include "hetm.h"
 #include "hetm_dev.h"
+#include "merge_host.h"
 
 using hetm::DevArgs;
 using hetm::DevCounters;
@@ -63,11 +64,17 @@ struct hetm_ctx {
     void *staging[2] = {};
     uint32_t *stage_ids[2] = {};
     uint32_t *stage_count[2] = {};
-    const void *pending_host = nullptr;
+    uint8_t *host_stage[2] = {};            // pinned: the DMA'd granules, scattered by the merge worker
+    uint32_t *host_ids[2] = {};
+    uint64_t host_cap[2] = {0, 0};          // granules the pinned staging holds
+    uint64_t merge_seq[2] = {0, 0};         // worker job that last read host_stage[b]
+    uint64_t round_merge_seq = 0;           // the last closed round's merge job (0: none pending)
+    hetm::MergeWorker *merger = nullptr;
 
     // the GRAPH round between round_begin and round_end
     bool round_open = false;
     const void *round_hdev = nullptr;
+    void *round_host = nullptr;
     int round_buf = 0;
 
     bool in_validation = false;      // this round's log has started
@@ -82,7 +89,10 @@ namespace hetm {
 // synchronous merge, restore on conflict) and fills *res.
 int round_begin(hetm_ctx *c, const hetm_round_args *r);
 int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res);
-// The event that completes when the last staged merge copy reaches the host
-// replica (async merge), or nullptr.
-hipEvent_t last_copy_event(hetm_ctx *c);
+// Double-buffered merge progress: the merge job of the round round_end just
+// closed (0 if it left nothing in flight), the last job whose granules are
+// in the host replica, and a wait for a job.
+uint64_t last_merge_seq(hetm_ctx *c);
+uint64_t merged_seq(hetm_ctx *c);
+int wait_merged(hetm_ctx *c, uint64_t seq);
 }  // namespace hetm

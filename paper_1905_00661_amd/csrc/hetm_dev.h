@@ -215,8 +215,8 @@ void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hip
 void launch_early_validate(const void *log, uint64_t n, uint32_t word_bytes, const uint32_t *rs, Div32 gdiv,
                            uint64_t n_words, uint32_t epoch, DevCounters *cnt, hipStream_t s);
 void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
-void launch_staged_copy(bool to_host, void *stmr, void *host, const void *staging, const uint32_t *ids,
-                        const uint32_t *count, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
+void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uint32_t *count, uint64_t n_words,
+                    uint32_t granule, uint32_t word_bytes, hipStream_t s);
 
 constexpr uint32_t kScanWordsPerBlock = 2048;   // bitmap words per compaction block
 constexpr uint32_t kScanThreads = 256;

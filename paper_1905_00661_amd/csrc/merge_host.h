@@ -1,0 +1,33 @@
+// merge_host.h -- host half of the double-buffered merge (§IV-C.3, §IV-D).
+//
+// A kernel storing into pinned host memory holds back kernels on every other
+// queue until its stores drain over the host link, so the staged granules of
+// a committed round cross the link by DMA instead (one copy of the packed
+// staging buffer into pinned host staging, on the copy stream), and a host
+// worker thread scatters them into the host replica once the copy's event
+// completes.  Jobs complete in submission order; each gets a sequence number.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hetm {
+
+struct MergeWorker;
+
+MergeWorker *merge_worker_create();
+// Waits for every queued job, then stops the thread.
+void merge_worker_destroy(MergeWorker *w);
+// After `ready` completes, copies granule k of `data` (gbytes each, packed)
+// to host + ids[k] * gbytes, clipped to total_bytes.  Returns the job's
+// sequence number (> 0).
+uint64_t merge_submit(MergeWorker *w, hipEvent_t ready, const uint32_t *ids, const uint8_t *data, uint64_t n,
+                      uint8_t *host, uint64_t gbytes, uint64_t total_bytes);
+// Blocks until job `seq` (and all before it) is done; HETM_OK or the first
+// error a job met.
+int merge_wait(MergeWorker *w, uint64_t seq);
+// Sequence number of the last finished job.
+uint64_t merge_done(MergeWorker *w);
+
+}  // namespace hetm

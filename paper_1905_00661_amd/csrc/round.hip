@@ -381,24 +381,19 @@ __global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, u
     }
 }
 
-// staged copy between the packed staging buffer / the host replica and the
-// replica: to_host scatters staged granules into the host replica (copy
-// stream, success); !to_host restores the staged ids from the host replica
-// into the GPU replica (conflict).
+// Restore after a conflicting double-buffered round (CPU wins): the staged
+// dirty granule ids are copied from the host replica back into the GPU
+// replica.
 template <typename U>
-__global__ __launch_bounds__(256) void k_staged_copy(bool to_host, U *stmr, U *host, const U *stg, const uint32_t *ids,
-                                                     const uint32_t *count, uint32_t upg, uint64_t total_units) {
+__global__ __launch_bounds__(256) void k_restore(U *stmr, const U *host, const uint32_t *ids, const uint32_t *count,
+                                                 uint32_t upg, uint64_t total_units) {
     const uint64_t D = ld_agent(count);
     const uint64_t work = D * upg;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < work; u += stride) {
         const uint64_t i = u / upg, j = u - i * upg;
         const uint64_t pos = (uint64_t)ld_agent(&ids[i]) * upg + j;
-        if (pos >= total_units) continue;
-        if (to_host)
-            host[pos] = stg[u];
-        else
-            stmr[pos] = host[pos];
+        if (pos < total_units) stmr[pos] = host[pos];
     }
 }
 
@@ -547,20 +542,19 @@ void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_
     }
 }
 
-void launch_staged_copy(bool to_host, void *stmr, void *host, const void *staging, const uint32_t *ids,
-                        const uint32_t *count, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s) {
-    // the host link bounds this copy, so a modest grid leaves the CUs to the next round
-    const uint32_t grid = to_host ? 128 : 4096;
+void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uint32_t *count, uint64_t n_words,
+                    uint32_t granule, uint32_t word_bytes, hipStream_t s) {
+    const uint32_t grid = 4096;
     const uint64_t gbytes = (uint64_t)granule * word_bytes;
     if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0)
-        hipLaunchKernelGGL(k_staged_copy<uint4>, dim3(grid), dim3(256), 0, s, to_host, (uint4 *)stmr, (uint4 *)host,
-                           (const uint4 *)staging, ids, count, (uint32_t)(gbytes / 16), n_words * word_bytes / 16);
+        hipLaunchKernelGGL(k_restore<uint4>, dim3(grid), dim3(256), 0, s, (uint4 *)stmr, (const uint4 *)host, ids,
+                           count, (uint32_t)(gbytes / 16), n_words * word_bytes / 16);
     else if (word_bytes == 4)
-        hipLaunchKernelGGL(k_staged_copy<uint32_t>, dim3(grid), dim3(256), 0, s, to_host, (uint32_t *)stmr,
-                           (uint32_t *)host, (const uint32_t *)staging, ids, count, granule, n_words);
+        hipLaunchKernelGGL(k_restore<uint32_t>, dim3(grid), dim3(256), 0, s, (uint32_t *)stmr, (const uint32_t *)host,
+                           ids, count, granule, n_words);
     else
-        hipLaunchKernelGGL(k_staged_copy<uint64_t>, dim3(grid), dim3(256), 0, s, to_host, (uint64_t *)stmr,
-                           (uint64_t *)host, (const uint64_t *)staging, ids, count, granule, n_words);
+        hipLaunchKernelGGL(k_restore<uint64_t>, dim3(grid), dim3(256), 0, s, (uint64_t *)stmr, (const uint64_t *)host,
+                           ids, count, granule, n_words);
 }
 
 void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hipStream_t s) {

@@ -176,7 +176,7 @@ struct Serve {
 
     // After a round's compute: conflict -> requeue; success -> copy results
     // out and queue the requests for commit stamping.
-    int settle(RoundSet &r, const hetm_round_result &res, std::deque<std::pair<hipEvent_t, std::vector<uint64_t>>> *pend,
+    int settle(RoundSet &r, const hetm_round_result &res, std::deque<std::pair<uint64_t, std::vector<uint64_t>>> *pend,
                std::vector<uint64_t> &done_now) {
         const uint64_t rn = round_no++;
         if (rep->round_conflict && rn < rep->max_rounds) rep->round_conflict[rn] = res.conflict ? 1 : 0;
@@ -202,9 +202,9 @@ struct Serve {
             if (rep->commit_seq) rep->commit_seq[i] = (rn << 32) | r.h_tick[k];
             o += L;
         }
-        hipEvent_t ev = hetm::last_copy_event(c);
-        if (pend && ev)
-            pend->emplace_back(ev, r.reqs);
+        const uint64_t seq = hetm::last_merge_seq(c);
+        if (pend && seq)
+            pend->emplace_back(seq, r.reqs);
         else
             done_now.insert(done_now.end(), r.reqs.begin(), r.reqs.end());
         return HETM_OK;
@@ -248,7 +248,7 @@ struct Serve {
     }
 
     int run_pipelined() {
-        std::deque<std::pair<hipEvent_t, std::vector<uint64_t>>> pend;
+        std::deque<std::pair<uint64_t, std::vector<uint64_t>>> pend;   // merge job, its requests
         int cur = -1;            // set of the round on the GPU
         int nxt = -1;            // set packed and uploaded for the next round
         hetm_oplist_desc d[2];
@@ -256,8 +256,8 @@ struct Serve {
         auto poll = [&](bool block) {
             while (!pend.empty()) {
                 if (block) {
-                    if (hipEventSynchronize(pend.front().first) != hipSuccess) return HETM_EDEVICE;
-                } else if (hipEventQuery(pend.front().first) != hipSuccess) {
+                    if (hetm::wait_merged(c, pend.front().first) != HETM_OK) return HETM_EDEVICE;
+                } else if (hetm::merged_seq(c) < pend.front().first) {
                     break;
                 }
                 stamp(pend.front().second);

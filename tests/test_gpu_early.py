@@ -101,11 +101,13 @@ def test_doom_stops_later_batches(hm, wl):
     ctx.close()
 
 
-def test_doom_while_executing(hm, wl):
-    """A chunk with a write to a hot word, early-validated right after a large
-    batch is submitted: whatever the early kernel saw, the round is a
+@pytest.mark.parametrize("delay_us", [0, 300])
+def test_doom_while_executing(hm, wl, delay_us):
+    """A chunk with a write to a hot word, early-validated `delay_us` after a
+    large batch is submitted: whatever the early kernel saw, the round is a
     conflict and the replicas equal the host's.  Reports how much of the
     batch ran before the kernel stopped."""
+    import time
     n_words = 1 << 22
     n = 1 << 18
     g = np.random.default_rng(11)
@@ -124,10 +126,13 @@ def test_doom_while_executing(hm, wl):
     import torch
     torch.cuda.synchronize()
     ctx.submit(b)
+    t_end = time.perf_counter() + delay_us * 1e-6
+    while time.perf_counter() < t_end:
+        pass
     d = ctx.early_validate(log_t, 4096, wait=True)
     c, nd = _close(hm, ctx, log_t, 4096, host_t)
     ran = ctx.stats().txns_aborted
-    say(f"doomed={d} transactions run before the stop: {ran} of {n}")
+    say(f"delay {delay_us} us: doomed={d} transactions run before the stop: {ran} of {n}")
     assert c == 1
     if d:
         assert ran <= n
