@@ -87,10 +87,12 @@ typedef struct {
     uint32_t retry_cap;          /* local attempts per transaction; 0 = 1<<24    */
     uint32_t async_merge;        /* GRAPH mode only: 1 = double-buffered merge --
                                     the round gathers its dirty granules into one
-                                    of two HBM staging buffers and a copy stream
-                                    writes them to the host replica while the
-                                    next round executes (GPU double buffering,
-                                    §IV-D); 0 = the merge copy ends the round    */
+                                    of two HBM staging buffers; a DMA on a copy
+                                    stream moves them to pinned host staging and
+                                    a library thread scatters them into the host
+                                    replica while the next round executes (GPU
+                                    double buffering, §IV-D); 0 = the merge copy
+                                    ends the round                              */
 } hetm_config;
 
 /* One host log entry (§IV-B, CPU instrumentation): the word a committed
@@ -256,9 +258,11 @@ typedef struct {
 /* A whole round: execution, validation+apply, merge, reset, in the
  * context's mode.  With async_merge, a successful round returns as soon as
  * its dirty granules are staged in HBM (merge_pending = 1); the host replica
- * is complete after hetm_sync or after a later round (the next round waits
- * for the staging buffer it reuses); a conflicting round first waits for the
- * previous round's copy, then restores its dirty granules from the host
+ * holds them after hetm_sync or once the next round returns (each round
+ * waits for the previous merge before starting its own).  Until then the
+ * caller must not write the host replica: the merge would overwrite granules
+ * it shares with those writes.  A conflicting round first waits for the
+ * previous round's merge, then restores its dirty granules from the host
  * replica before returning.  PLAIN launches one kernel per step and reads the
  * outcome on the host before the merge; GRAPH replays one captured hipGraph
  * whose merge kernels read the outcome on the device.  Synchronizes and

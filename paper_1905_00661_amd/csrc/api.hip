@@ -293,12 +293,14 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
 }
 
 // Success path of the double-buffered merge for staging buffer b holding D
-// packed granules: the pinned host staging b is free once the worker is done
-// with the round that used it last; it grows on demand (rarely: it keeps the
-// largest size seen).  The DMA runs on the copy stream after the graph.
+// packed granules.  The pinned host staging grows on demand (rarely: it keeps
+// the largest size seen).  The DMA runs on the copy stream after the graph.
 int stage_to_host(hetm_ctx *c, int b, uint64_t D) {
     const uint64_t gbytes = (uint64_t)c->cfg.granule_words * c->cfg.word_bytes;
-    if (c->merge_seq[b] && hetm::merge_wait(c->merger, c->merge_seq[b]) != HETM_OK)
+    // every earlier merge lands before this one starts, so after a round
+    // returns only its own merge can still be in flight
+    const uint64_t prev = std::max(c->merge_seq[0], c->merge_seq[1]);
+    if (prev && hetm::merge_wait(c->merger, prev) != HETM_OK)
         return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
     if (D > c->host_cap[b]) {
         const uint64_t nG = (c->cfg.n_words + c->cfg.granule_words - 1) / c->cfg.granule_words;

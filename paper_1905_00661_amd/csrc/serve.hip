@@ -287,11 +287,15 @@ struct Serve {
             if ((err = poll(false))) return err;
             if (cur < 0 && nxt >= 0) {
                 RoundSet &r = set[nxt];
-                host_commit(r);
                 a[nxt] = round_args(r, d[nxt]);
                 // round_begin orders the graph after the caller's stream
                 if (hipStreamWaitEvent(c->stream, r.uploaded, 0) != hipSuccess) return HETM_EDEVICE;
                 if ((err = hetm::round_begin(c, &a[nxt]))) return err;
+                // the host's writes of this round go into the host replica
+                // while the GPU runs it, after the last round's merge has
+                // landed there (it must not overwrite them)
+                if ((err = hetm::wait_merged(c, hetm::last_merge_seq(c)))) return err;
+                host_commit(r);
                 cur = nxt;
                 nxt = -1;
             } else if (cur < 0 && nxt < 0) {
