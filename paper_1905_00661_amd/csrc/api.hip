@@ -244,7 +244,7 @@ int build_graph(hetm_ctx *c) {
     // device copy node would issue PCIe reads that queue behind the previous
     // round's merge copy (device-to-host posted writes) and stall the launch.
     launch_set_args(c->args, c->dargs, s);
-    launch_exec(c->args.program, c->dargs, c->exec_wg, s);
+    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, s);
     launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
     launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
     launch_compact(c->dargs, c->args.n_scan_blocks, s);
@@ -561,6 +561,11 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     int cus = 256;
     if (hipGetDeviceProperties(&prop, k.device) == hipSuccess) cus = prop.multiProcessorCount;
     c->exec_wg = k.exec_workgroups ? k.exec_workgroups : default_exec_workgroups(cus);
+    if (exec_prepare(k.max_txn_ops) != hipSuccess) {
+        (void)hipGetLastError();
+        hetm_free(c);
+        return HETM_EDEVICE;
+    }
 
     DevArgs &a = c->args;
     a.stmr = c->stmr, a.locks = c->locks, a.ts = c->ts, a.rs = c->rs, a.ws = c->ws;
@@ -627,7 +632,7 @@ int hetm_submit_batch(hetm_ctx *c, uint32_t program, const void *descs, uint64_t
     int rc = set_batch_args(c, program, descs, n_txns, results, tickets);
     if (rc) return rc;
     if ((rc = push_args(c))) return rc;
-    launch_exec(program, c->dargs, c->exec_wg, c->stream);
+    launch_exec(program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->stream);
     HIP_TRY(c, hipGetLastError());
     return HETM_OK;
 }
@@ -696,7 +701,7 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     if (r->n_txns) {
         if ((rc = push_args(c))) return rc;
-        launch_exec(r->program, c->dargs, c->exec_wg, s);
+        launch_exec(r->program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, s);
         HIP_TRY(c, hipGetLastError());
     }
     HIP_TRY(c, hipEventRecord(c->ev[1], s));

@@ -219,9 +219,13 @@ __device__ __forceinline__ bool doomed(DevCounters *cnt, uint32_t epoch) {
 // ------------------------------------------------------------------ OPLIST
 // Transaction i reads idx[off[i] .. off[i+1]) in order, then writes each of
 // its first nw[i] words with (value read + tid[i]) mod 2^32.
+// An attempt loads its word list from HBM once, into LDS ([op][lane] per
+// wave, max_ops x 64 dwords, dynamic), and every later pass -- lock words,
+// values, revalidation, bitmaps -- reads it from there.
 __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs *__restrict__ a) {
     __shared__ uint32_t s_addr[kExecWaves][kOplistMaxWrites][kWave];
     __shared__ uint32_t s_val[kExecWaves][kOplistMaxWrites][kWave];
+    extern __shared__ uint32_t s_dyn[];
     const uint32_t wv = threadIdx.x / kWave;
     uint32_t *stmr = (uint32_t *)a->stmr;
     uint64_t *locks = a->locks;
@@ -234,6 +238,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     const uint8_t *nw = a->nw;
     uint32_t *res = (uint32_t *)a->results;
     WriteBuf<uint32_t, kOplistMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
+    uint32_t *ix = s_dyn + wv * max_ops * kWave + lane_id();     // ix[j * kWave]: word j of this lane's txn
     const uint32_t epoch = a->epoch;
     LaneState ls = first_txn(n);
 
@@ -253,7 +258,13 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
             tv = tid[ls.txn];
             L = e - o;
             malformed = e < o || L > max_ops || nwr > L || nwr > kOplistMaxWrites;
-            for (uint32_t j = 0; j < L && !malformed; ++j) malformed = idx[o + j] >= N;
+            if (!malformed) {
+                for (uint32_t j = 0; j < L; ++j) {
+                    const uint32_t w = idx[o + j];
+                    ix[j * kWave] = w;
+                    malformed |= w >= N;
+                }
+            }
             if (malformed) {
                 latch_error(cnt, HETM_EINVAL, ls.txn);
                 L = 0;
@@ -263,7 +274,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
         // first pass over the read stripes
         uint64_t sum1 = 0;
         for (uint32_t j = 0; j < L; ++j) {
-            uint64_t l = ld_agent(&locks[idx[o + j] >> sh]);
+            uint64_t l = ld_agent(&locks[ix[j * kWave] >> sh]);
             ok &= !(l & kLockBit);
             sum1 += l;
         }
@@ -271,7 +282,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
         wb.n = 0;
         if (ok) {
             for (uint32_t j = 0; j < L; ++j) {
-                uint32_t w = idx[o + j];
+                uint32_t w = ix[j * kWave];
                 uint32_t v = ld_agent(&stmr[w]);
                 res[o + j] = v;
                 if (j < nwr) wb.put(w, v + tv);
@@ -283,14 +294,14 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
         hw_order();
         if (ok) {
             uint64_t sum2 = 0;
-            for (uint32_t j = 0; j < L && ok; ++j) sum2 += reread(locks, idx[o + j] >> sh, sh, wb, ok);
+            for (uint32_t j = 0; j < L && ok; ++j) sum2 += reread(locks, ix[j * kWave] >> sh, sh, wb, ok);
             ok &= sum2 == sum1;
         }
         if (ok) wb.write_back(stmr);
         hw_order();
         if (wb.locked) wb.release(locks, sh, ok);
         if (ok) {
-            for (uint32_t j = nwr; j < L; ++j) bitmap_set(rs, div32(idx[o + j], G));
+            for (uint32_t j = nwr; j < L; ++j) bitmap_set(rs, div32(ix[j * kWave], G));
             wb.mark_writes(rs, ws, G);
         }
         settle(ls, act, malformed, ok, ticket, a->tickets, cnt, a->retry_cap);
@@ -527,11 +538,16 @@ __global__ void k_begin_batch(const DevArgs *__restrict__ a) {
 }  // namespace
 
 
-void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, hipStream_t s) {
+hipError_t exec_prepare(uint32_t max_ops) {
+    return hipFuncSetAttribute((const void *)k_exec_oplist, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)oplist_lds_bytes(max_ops));
+}
+
+void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, hipStream_t s) {
     hipLaunchKernelGGL(k_begin_batch, dim3(1), dim3(64), 0, s, a);
     dim3 grid(workgroups), block(kExecWaves * kWave);
     if (program == HETM_PROG_OPLIST)
-        hipLaunchKernelGGL(k_exec_oplist, grid, block, 0, s, a);
+        hipLaunchKernelGGL(k_exec_oplist, grid, block, oplist_lds_bytes(max_ops), s, a);
     else if (program == HETM_PROG_TRANSFER)
         hipLaunchKernelGGL(k_exec_transfer, grid, block, 0, s, a);
     else

@@ -206,7 +206,11 @@ __device__ __forceinline__ void bitmap_set(uint32_t *bm, uint32_t g) {
 void launch_set_args(const DevArgs &host_copy, DevArgs *dev, hipStream_t s);
 const void *set_args_kernel();   // host handle of the argument-upload kernel
 void launch_clear_error(DevCounters *cnt, hipStream_t s);
-void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, hipStream_t s);
+void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, hipStream_t s);
+// allows the OPLIST kernel the dynamic LDS a context's max_ops needs
+hipError_t exec_prepare(uint32_t max_ops);
+// dynamic LDS of the OPLIST transaction kernel: each lane's word list
+constexpr uint32_t oplist_lds_bytes(uint32_t max_ops) { return kExecWaves * max_ops * kWave * 4u; }
 void launch_validate(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);
 void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s);
