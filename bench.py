@@ -86,17 +86,21 @@ def serve_forms(args, hm, wl, torch) -> dict:
     res = {"workload": f"2^27 u32 words, {args.serve_requests} requests at {args.serve_rate:g} txn/s Poisson, "
                        f"lognormal lengths (median 4, max 64), 5% hot words, host log {per_round}/round, "
                        f"budget 2 GiB, granule 64"}
-    for name, pipelined in (("pipelined", True), ("plain", False)):
+    forms = (("pipelined", True, dict(mode=1, async_merge=True)),
+             ("pipelined_sync_merge", True, dict(mode=1)),
+             ("plain", False, dict(mode=0)))
+    for name, pipelined, kw in forms:
         log(f"served form: {name} ...")
-        kw = dict(mode=1, async_merge=True) if pipelined else dict(mode=0)
         ctx = hm.Context(N, 4, 64, init=init, max_ops=64, batch_capacity=1 << 20, log_capacity=per_round, **kw)
         host = hm.pinned(N * 4)
         host.numpy()[:] = init.view(np.uint8)
         o = ctx.serve(req["arrival_s"], req["batch"], host, hlog, per_round, 1 << 20, 2 << 30, pipelined)
+        st = ctx.stats()
         ctx.close()
         res[name] = {"throughput_txn_s": o["throughput"], "p50_latency_us": o["p50_latency_us"],
                      "p99_latency_us": o["p99_latency_us"], "rounds": int(o["rounds"]),
-                     "conflicted_rounds": int(o["conflicted_rounds"])}
+                     "conflicted_rounds": int(o["conflicted_rounds"]),
+                     "host_scatter_ms": st.us_host_scatter / 1e3, "merge_wait_ms": st.us_merge_wait / 1e3}
     return res
 
 
@@ -183,7 +187,9 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         tickets = b.tickets_np().copy()
+        st = ctx.stats()
         ctx.close()
+        run.scatter_ms = st.us_host_scatter / 1e3 / (warm + k_steps)
         return elapsed, lat, res, tickets
 
     log("batched form (graph + double-buffered merge) ...")
@@ -205,6 +211,7 @@ def main():
         "local_retries_per_round": float(np.mean([r["n_local_retries"] for r in res_g])),
         "dirty_granules_per_round": float(np.mean([r["n_dirty"] for r in res_g])),
         "graph_us": float(np.mean([r["us_total"] for r in res_g])),
+        "host_scatter_ms_per_round": run.scatter_ms,
     }
     log("graph form, merge inside the round ...")
     el_s, lat_s, res_s, _ = run(hm.HETM_MODE_GRAPH, args.steps, args.warmup)

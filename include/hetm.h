@@ -282,6 +282,9 @@ typedef struct {
     uint64_t rounds, rounds_conflicted, txns_committed, txns_aborted, local_retries;
     uint64_t log_entries, dirty_granules, watermark;
     uint64_t device_bytes;     /* HBM the context allocated */
+    double   us_host_scatter;  /* double-buffered merge: host time scattering
+                                  DMA'd granules into the host replica        */
+    double   us_merge_wait;    /* time calls spent waiting for such merges    */
 } hetm_stats;
 int hetm_stats_get(hetm_ctx *ctx, hetm_stats *out);
 

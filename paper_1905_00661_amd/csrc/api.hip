@@ -785,6 +785,7 @@ int hetm_sync(hetm_ctx *c) {
 int hetm_stats_get(hetm_ctx *c, hetm_stats *out) {
     if (!c || !out) return HETM_EINVAL;
     *out = c->stats;
+    if (c->merger) hetm::merge_times(c->merger, &out->us_host_scatter, &out->us_merge_wait);
     return HETM_OK;
 }
 

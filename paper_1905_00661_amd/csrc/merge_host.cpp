@@ -5,6 +5,7 @@
 #include <emmintrin.h>
 
 #include <algorithm>
+#include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -76,6 +77,7 @@ struct MergeWorker {
     std::deque<Job> q;
     uint64_t issued = 0, done = 0;
     int err = HETM_OK;
+    double us_scatter = 0, us_wait = 0;
     bool stop = false;
     std::thread th;
 
@@ -89,9 +91,12 @@ struct MergeWorker {
                 j = q.front();
             }
             const int e = hipEventSynchronize(j.ready) == hipSuccess ? HETM_OK : HETM_EDEVICE;
+            const auto t0 = std::chrono::steady_clock::now();
             if (e == HETM_OK) scatter(j);
+            const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
             {
                 std::lock_guard<std::mutex> l(m);
+                us_scatter += us;
                 q.pop_front();
                 if (e != HETM_OK && err == HETM_OK) err = e;
                 done = j.seq;
@@ -132,8 +137,17 @@ uint64_t merge_submit(MergeWorker *w, hipEvent_t ready, const uint32_t *ids, con
 
 int merge_wait(MergeWorker *w, uint64_t seq) {
     std::unique_lock<std::mutex> l(w->m);
+    if (w->done >= seq) return w->err;
+    const auto t0 = std::chrono::steady_clock::now();
     w->cv_done.wait(l, [&] { return w->done >= seq; });
+    w->us_wait += std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     return w->err;
+}
+
+void merge_times(MergeWorker *w, double *us_scatter, double *us_wait) {
+    std::lock_guard<std::mutex> l(w->m);
+    *us_scatter = w->us_scatter;
+    *us_wait = w->us_wait;
 }
 
 uint64_t merge_done(MergeWorker *w) {

@@ -29,5 +29,7 @@ uint64_t merge_submit(MergeWorker *w, hipEvent_t ready, const uint32_t *ids, con
 int merge_wait(MergeWorker *w, uint64_t seq);
 // Sequence number of the last finished job.
 uint64_t merge_done(MergeWorker *w);
+// Host time spent scattering, and time merge_wait blocked, in microseconds.
+void merge_times(MergeWorker *w, double *us_scatter, double *us_wait);
 
 }  // namespace hetm

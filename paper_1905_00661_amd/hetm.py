@@ -89,7 +89,8 @@ class hetm_serve_report(ctypes.Structure):
 class hetm_stats(ctypes.Structure):
     _fields_ = [("rounds", U64), ("rounds_conflicted", U64), ("txns_committed", U64),
                 ("txns_aborted", U64), ("local_retries", U64), ("log_entries", U64),
-                ("dirty_granules", U64), ("watermark", U64), ("device_bytes", U64)]
+                ("dirty_granules", U64), ("watermark", U64), ("device_bytes", U64),
+                ("us_host_scatter", ctypes.c_double), ("us_merge_wait", ctypes.c_double)]
 
 
 class HetmError(RuntimeError):
