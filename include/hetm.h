@@ -316,13 +316,13 @@ uint64_t hetm_state_bytes(hetm_ctx *ctx, uint32_t what);
  * stream (entries in timestamp order, above the context's watermark) to
  * host_replica, and they are validated and applied in the round.
  *
- * pipelined = 1 (continuous batching; needs a GRAPH context with
- * async_merge): while a round runs on the GPU the next one is packed and
- * uploaded on an upload stream, and a round's requests commit when its
- * double-buffered merge copy reaches the host replica, overlapping the
- * next round's execution.  The host log stream must stay in a region the
- * requests never write (the host's writes then never touch a granule whose
- * copy is in flight).  pipelined = 0: one plain round at a time.
+ * pipelined = 1 (continuous batching; needs a GRAPH context): while a round
+ * runs on the GPU the next one is packed and uploaded on an upload stream.
+ * With async_merge a round's requests commit when its double-buffered merge
+ * reaches the host replica, overlapping the next round's execution; the
+ * host's writes of the next round go into the host replica once that merge
+ * has landed, while the GPU already runs the round.  pipelined = 0: one
+ * round at a time through hetm_round (a context without async_merge).
  *
  * A conflicting round is aborted (CPU wins, §IV-E) and its requests are
  * admitted again first; a request's latency runs from its arrival to the

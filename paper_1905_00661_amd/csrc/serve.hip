@@ -318,8 +318,8 @@ extern "C" int hetm_serve(hetm_ctx *c, const hetm_serve_spec *sp, void *host_rep
                                                                            !sp->n_writes || !sp->tid)) ||
         (sp->host_log_len && !sp->host_log))
         return HETM_EINVAL;
-    if (sp->pipelined && !(c->cfg.mode == HETM_MODE_GRAPH && c->cfg.async_merge)) return HETM_ESTATE;
-    if (!sp->pipelined && c->cfg.mode != HETM_MODE_PLAIN) return HETM_ESTATE;
+    if (sp->pipelined && c->cfg.mode != HETM_MODE_GRAPH) return HETM_ESTATE;
+    if (!sp->pipelined && c->cfg.async_merge) return HETM_ESTATE;
     for (uint64_t i = 0; i < sp->n_requests; ++i)
         if (sp->offsets[i + 1] < sp->offsets[i] || sp->offsets[i + 1] - sp->offsets[i] > c->cfg.max_txn_ops ||
             (i && sp->arrival_s[i] < sp->arrival_s[i - 1]))

@@ -88,7 +88,7 @@ def make_ctx(hm, init, pipelined, G=64, max_batch=8192):
 
 
 @pytest.mark.parametrize("pipelined,rate,inject", [(True, 2e6, 0), (False, 2e6, 0), (False, 5e5, 3 * 4096),
-                                                   (True, 2e7, 0)])
+                                                   (True, 2e7, 0), (True, 5e5, 3 * 4096)])
 def test_serve_matches_oracle(hm, wl, pipelined, rate, inject):
     """20,000 lognormal-length requests (median 4, capped at 64) arriving
     Poisson at `rate`, 5% hot words, host log stream of 4096 entries per
