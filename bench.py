@@ -20,6 +20,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -49,26 +50,33 @@ def exec_alg_bytes(batch) -> float:
 VALIDATE_APPLY_BYTES_PER_ENTRY = 40.0   # 16 B entry + 4 B bitmap + 8+8 B TS + 4 B value
 
 
-def source_hash() -> str:
+KERNEL_SOURCES = {"k_exec_oplist": ("exec.hip", "hetm_dev.h")}
+TRAFFIC_FILES = {"k_exec_oplist": "exec_oplist_large_traffic.md"}
+
+
+def source_hash(kernel: str) -> str:
+    """Hash of the sources a kernel is compiled from."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1905_00661_amd", "csrc"))):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1905_00661_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel: str):
-    """HBM traffic per launch from committed rocprofv3 counter runs, only if
-    they were taken on the current kernel sources."""
-    p = os.path.join(PROFILES, "traffic.json")
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    only if it was taken on the kernel's current sources."""
+    if kernel not in TRAFFIC_FILES:
+        return None
     try:
-        d = json.load(open(p))
-    except (OSError, ValueError):
+        text = open(os.path.join(PROFILES, TRAFFIC_FILES[kernel])).read()
+    except OSError:
         return None
-    e = d.get(kernel)
-    if not e or e.get("source_hash") != source_hash():
+    h = re.search(r"^source_hash: (\w+)", text, re.M)
+    b = re.search(r"^bytes_per_launch: (\d+)", text, re.M)
+    if not h or not b or h.group(1) != source_hash(kernel):
         return None
-    return e.get("bytes_per_launch")
+    return int(b.group(1))
 
 
 def serve_forms(args, hm, wl, torch) -> dict:

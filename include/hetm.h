@@ -91,8 +91,9 @@ typedef struct {
                                     stream moves them to pinned host staging and
                                     a library thread scatters them into the host
                                     replica while the next round executes (GPU
-                                    double buffering, §IV-D); 0 = the merge copy
-                                    ends the round                              */
+                                    double buffering, §IV-D; costs 2*N*W bytes
+                                    of HBM and of pinned host memory); 0 = the
+                                    merge copy ends the round                   */
 } hetm_config;
 
 /* One host log entry (§IV-B, CPU instrumentation): the word a committed

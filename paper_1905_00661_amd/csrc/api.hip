@@ -293,8 +293,8 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
 }
 
 // Success path of the double-buffered merge for staging buffer b holding D
-// packed granules.  The pinned host staging grows on demand (rarely: it keeps
-// the largest size seen).  The DMA runs on the copy stream after the graph.
+// packed granules: DMA on the copy stream after the graph, then a job for
+// the merge worker.
 int stage_to_host(hetm_ctx *c, int b, uint64_t D) {
     const uint64_t gbytes = (uint64_t)c->cfg.granule_words * c->cfg.word_bytes;
     // every earlier merge lands before this one starts, so after a round
@@ -302,19 +302,7 @@ int stage_to_host(hetm_ctx *c, int b, uint64_t D) {
     const uint64_t prev = std::max(c->merge_seq[0], c->merge_seq[1]);
     if (prev && hetm::merge_wait(c->merger, prev) != HETM_OK)
         return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
-    if (D > c->host_cap[b]) {
-        const uint64_t nG = (c->cfg.n_words + c->cfg.granule_words - 1) / c->cfg.granule_words;
-        const uint64_t cap = std::min<uint64_t>(nG, D + D / 4 + 1024);
-        if (c->host_stage[b]) (void)hipHostFree(c->host_stage[b]);
-        if (c->host_ids[b]) (void)hipHostFree(c->host_ids[b]);
-        c->host_stage[b] = nullptr;
-        c->host_ids[b] = nullptr;
-        c->host_cap[b] = 0;
-        if (hipHostMalloc((void **)&c->host_stage[b], cap * gbytes, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&c->host_ids[b], cap * 4, hipHostMallocDefault) != hipSuccess)
-            return fail(c, HETM_ENOMEM, "pinned merge staging of %llu granules", (unsigned long long)cap);
-        c->host_cap[b] = cap;
-    }
+    if (D > c->host_cap[b]) return fail(c, HETM_ECAPACITY, "%llu dirty granules", (unsigned long long)D);
     HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->graph_done[b], 0));
     if (D) {
         HIP_TRY(c, hipMemcpyAsync(c->host_ids[b], c->stage_ids[b], D * 4, hipMemcpyDeviceToHost, c->copy_stream));
@@ -511,6 +499,14 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
             TRY(dev_alloc(c, &c->staging[b], nG * G * k.word_bytes));
             TRY(dev_alloc(c, &c->stage_ids[b], nG * 4));
             TRY(dev_alloc(c, &c->stage_count[b], 256));
+            // pinned host staging for every granule: sized once, so no
+            // allocation (or the device-wide wait of a free) sits in a round
+            if (hipHostMalloc((void **)&c->host_stage[b], nG * G * k.word_bytes, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void **)&c->host_ids[b], nG * 4, hipHostMallocDefault) != hipSuccess) {
+                hetm_free(c);
+                return HETM_ENOMEM;
+            }
+            c->host_cap[b] = nG;
         }
         if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
             hetm_free(c);

@@ -66,7 +66,7 @@ struct hetm_ctx {
     uint32_t *stage_count[2] = {};
     uint8_t *host_stage[2] = {};            // pinned: the DMA'd granules, scattered by the merge worker
     uint32_t *host_ids[2] = {};
-    uint64_t host_cap[2] = {0, 0};          // granules the pinned staging holds
+    uint64_t host_cap[2] = {0, 0};          // granules the pinned staging holds (all of them)
     uint64_t merge_seq[2] = {0, 0};         // worker job that last read host_stage[b]
     uint64_t round_merge_seq = 0;           // the last closed round's merge job (0: none pending)
     hetm::MergeWorker *merger = nullptr;

@@ -174,10 +174,23 @@ struct Serve {
         return a;
     }
 
+    // Queues the copies of a round's results and tickets to pinned host
+    // memory right behind its graph, so they run before the round's merge
+    // DMA is queued (the merge would hold them back on the copy engine).
+    int fetch_after_round(RoundSet &r) {
+        const uint64_t n = r.reqs.size();
+        if (!n) return HETM_OK;
+        if (hipMemcpyAsync(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost, c->cap_stream) != hipSuccess ||
+            hipMemcpyAsync(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost, c->cap_stream) != hipSuccess)
+            return HETM_EDEVICE;
+        return HETM_OK;
+    }
+
     // After a round's compute: conflict -> requeue; success -> copy results
-    // out and queue the requests for commit stamping.
+    // out (unless fetch_after_round already did) and queue the requests for
+    // commit stamping.
     int settle(RoundSet &r, const hetm_round_result &res, std::deque<std::pair<uint64_t, std::vector<uint64_t>>> *pend,
-               std::vector<uint64_t> &done_now) {
+               std::vector<uint64_t> &done_now, bool fetched = false) {
         const uint64_t rn = round_no++;
         if (rep->round_conflict && rn < rep->max_rounds) rep->round_conflict[rn] = res.conflict ? 1 : 0;
         if (rep->round_log_end && rn < rep->max_rounds) rep->round_log_end[rn] = r.log_end;
@@ -189,7 +202,7 @@ struct Serve {
             return HETM_OK;
         }
         const uint64_t n = r.reqs.size();
-        if (n) {
+        if (n && !fetched) {
             if (hipMemcpy(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost) != hipSuccess ||
                 hipMemcpy(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
                 return HETM_EDEVICE;
@@ -280,7 +293,7 @@ struct Serve {
                 hetm_round_result res{};
                 if ((err = hetm::round_end(c, &a[cur], &res))) return err;
                 std::vector<uint64_t> done;
-                if ((err = settle(set[cur], res, &pend, done))) return err;
+                if ((err = settle(set[cur], res, &pend, done, true))) return err;
                 stamp(done);
                 cur = -1;
             }
@@ -291,6 +304,7 @@ struct Serve {
                 // round_begin orders the graph after the caller's stream
                 if (hipStreamWaitEvent(c->stream, r.uploaded, 0) != hipSuccess) return HETM_EDEVICE;
                 if ((err = hetm::round_begin(c, &a[nxt]))) return err;
+                if ((err = fetch_after_round(r))) return err;
                 // the host's writes of this round go into the host replica
                 // while the GPU runs it, after the last round's merge has
                 // landed there (it must not overwrite them)
