@@ -98,6 +98,8 @@ def serve_forms(args, hm, wl, torch) -> dict:
              ("pipelined_sync_merge", True, dict(mode=1)),
              ("plain", False, dict(mode=0)))
     for name, pipelined, kw in forms:
+        if args.serve_forms and name not in args.serve_forms.split(","):
+            continue
         log(f"served form: {name} ...")
         ctx = hm.Context(N, 4, 64, init=init, max_ops=64, batch_capacity=1 << 20, log_capacity=per_round, **kw)
         host = hm.pinned(N * 4)
@@ -108,7 +110,9 @@ def serve_forms(args, hm, wl, torch) -> dict:
         res[name] = {"throughput_txn_s": o["throughput"], "p50_latency_us": o["p50_latency_us"],
                      "p99_latency_us": o["p99_latency_us"], "rounds": int(o["rounds"]),
                      "conflicted_rounds": int(o["conflicted_rounds"]),
-                     "host_scatter_ms": st.us_host_scatter / 1e3, "merge_wait_ms": st.us_merge_wait / 1e3}
+                     "host_scatter_ms": st.us_host_scatter / 1e3, "merge_wait_ms": st.us_merge_wait / 1e3,
+                     "serving_thread_ms": {k: round(o["us_" + k] / 1e3, 2) for k in
+                                           ("pack", "wait_round", "settle", "host_commit", "wait_merge", "idle")}}
     return res
 
 
@@ -128,6 +132,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=3e7, help="Poisson arrival rate of the served form (txn/s)")
     ap.add_argument("--serve-requests", type=int, default=1 << 21)
+    ap.add_argument("--serve-forms", default="", help="comma list of served forms to run (default: all)")
+    ap.add_argument("--serve-only", action="store_true", help="run only the served forms")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 1 GiB device copy, the known-size reference for HBM counters")
@@ -140,6 +146,10 @@ def main():
 
     from paper_1905_00661_amd import hetm as hm
     from paper_1905_00661_amd import workloads as wl
+
+    if args.serve_only:
+        print(json.dumps({"served": serve_forms(args, hm, wl, torch)}), flush=True)
+        return
 
     N, n_txn, n_log = 1 << args.log2_words, 1 << args.log2_txns, 1 << args.log2_log
     G = args.granule

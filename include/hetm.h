@@ -360,6 +360,10 @@ typedef struct {
     uint8_t  *round_conflict;           /* out [max_rounds], nullable: 1 for an aborted round */
     uint64_t  max_rounds;
     uint64_t *round_log_end;            /* out [max_rounds], nullable: host log entries consumed after round r */
+    /* where the serving thread's time went, microseconds: admission and
+       packing, waiting for rounds (round_end), settling results, the host's
+       own log commits, waiting for merges, waiting for arrivals */
+    double    us_pack, us_wait_round, us_settle, us_host_commit, us_wait_merge, us_idle;
 } hetm_serve_report;
 
 int hetm_serve(hetm_ctx *ctx, const hetm_serve_spec *spec, void *host_replica, hetm_serve_report *rep);

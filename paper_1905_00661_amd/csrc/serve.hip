@@ -19,6 +19,14 @@ using clk = std::chrono::steady_clock;
 
 double seconds_since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
 
+// Adds the time from its construction to its destruction to *acc (microseconds).
+struct Span {
+    double *acc;
+    clk::time_point t = clk::now();
+    explicit Span(double *a) : acc(a) {}
+    ~Span() { *acc += std::chrono::duration<double, std::micro>(clk::now() - t).count(); }
+};
+
 // One set of round buffers: pinned packing area and device copies.
 struct RoundSet {
     uint32_t *h_off = nullptr, *h_idx = nullptr, *h_tid = nullptr;
@@ -241,18 +249,29 @@ struct Serve {
         RoundSet &r = set[0];
         while (served < sp.n_requests) {
             if (!work_waiting()) {
+                Span t(&rep->us_idle);
                 wait_for_arrival();
                 continue;
             }
-            admit(r);
-            if (r.reqs.empty()) return HETM_ECAPACITY;
-            if ((err = pack_upload(r))) return err;
-            if (hipStreamSynchronize(upload) != hipSuccess) return HETM_EDEVICE;
-            host_commit(r);
+            {
+                Span t(&rep->us_pack);
+                admit(r);
+                if (r.reqs.empty()) return HETM_ECAPACITY;
+                if ((err = pack_upload(r))) return err;
+                if (hipStreamSynchronize(upload) != hipSuccess) return HETM_EDEVICE;
+            }
+            {
+                Span t(&rep->us_host_commit);
+                host_commit(r);
+            }
             hetm_oplist_desc d;
             hetm_round_args a = round_args(r, d);
             hetm_round_result res;
-            if ((err = hetm_round(c, &a, &res))) return err;
+            {
+                Span t(&rep->us_wait_round);
+                if ((err = hetm_round(c, &a, &res))) return err;
+            }
+            Span t(&rep->us_settle);
             std::vector<uint64_t> done;
             if ((err = settle(r, res, nullptr, done))) return err;
             stamp(done);
@@ -280,6 +299,7 @@ struct Serve {
         };
         while (served < sp.n_requests) {
             if (nxt < 0 && work_waiting()) {
+                Span t(&rep->us_pack);
                 const int s = cur < 0 ? 0 : cur ^ 1;
                 admit(set[s]);
                 if (!set[s].reqs.empty()) {
@@ -291,28 +311,44 @@ struct Serve {
             }
             if (cur >= 0) {
                 hetm_round_result res{};
-                if ((err = hetm::round_end(c, &a[cur], &res))) return err;
+                {
+                    Span t(&rep->us_wait_round);
+                    if ((err = hetm::round_end(c, &a[cur], &res))) return err;
+                }
+                Span t(&rep->us_settle);
                 std::vector<uint64_t> done;
                 if ((err = settle(set[cur], res, &pend, done, true))) return err;
                 stamp(done);
                 cur = -1;
+                if ((err = poll(false))) return err;
             }
-            if ((err = poll(false))) return err;
             if (cur < 0 && nxt >= 0) {
                 RoundSet &r = set[nxt];
                 a[nxt] = round_args(r, d[nxt]);
                 // round_begin orders the graph after the caller's stream
                 if (hipStreamWaitEvent(c->stream, r.uploaded, 0) != hipSuccess) return HETM_EDEVICE;
-                if ((err = hetm::round_begin(c, &a[nxt]))) return err;
-                if ((err = fetch_after_round(r))) return err;
+                {
+                    Span t(&rep->us_wait_round);
+                    if ((err = hetm::round_begin(c, &a[nxt]))) return err;
+                    if ((err = fetch_after_round(r))) return err;
+                }
                 // the host's writes of this round go into the host replica
                 // while the GPU runs it, after the last round's merge has
                 // landed there (it must not overwrite them)
-                if ((err = hetm::wait_merged(c, hetm::last_merge_seq(c)))) return err;
-                host_commit(r);
+                {
+                    Span t(&rep->us_wait_merge);
+                    if ((err = hetm::wait_merged(c, hetm::last_merge_seq(c)))) return err;
+                }
+                {
+                    Span t(&rep->us_host_commit);
+                    host_commit(r);
+                }
+                Span t(&rep->us_settle);
+                if ((err = poll(false))) return err;    // the last round's merge has landed
                 cur = nxt;
                 nxt = -1;
             } else if (cur < 0 && nxt < 0) {
+                Span t(&rep->us_idle);
                 if (!pend.empty())
                     poll(true);
                 else

@@ -83,7 +83,9 @@ class hetm_serve_report(ctypes.Structure):
                 ("wall_s", ctypes.c_double), ("throughput", ctypes.c_double), ("p50_latency_us", ctypes.c_double),
                 ("p99_latency_us", ctypes.c_double), ("mean_latency_us", ctypes.c_double),
                 ("max_latency_us", ctypes.c_double), ("latency_us", P), ("results", P), ("commit_seq", P),
-                ("round_conflict", P), ("max_rounds", U64), ("round_log_end", P)]
+                ("round_conflict", P), ("max_rounds", U64), ("round_log_end", P),
+                ("us_pack", ctypes.c_double), ("us_wait_round", ctypes.c_double), ("us_settle", ctypes.c_double),
+                ("us_host_commit", ctypes.c_double), ("us_wait_merge", ctypes.c_double), ("us_idle", ctypes.c_double)]
 
 
 class hetm_stats(ctypes.Structure):
