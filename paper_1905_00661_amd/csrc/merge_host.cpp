@@ -52,9 +52,10 @@ void scatter_range(const Job &j, uint64_t lo, uint64_t hi) {
 }
 
 void scatter(const Job &j) {
-    // one thread per 2 MiB of granules, at most 8
+    // one thread per 4 MiB of granules, at most 4 (the caller's threads need
+    // the host's memory bandwidth too)
     const uint64_t bytes = j.n * j.gbytes;
-    const unsigned t = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(8, bytes >> 21));
+    const unsigned t = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(4, bytes >> 22));
     if (t == 1) {
         scatter_range(j, 0, j.n);
         return;

@@ -19,6 +19,22 @@ using clk = std::chrono::steady_clock;
 
 double seconds_since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
 
+// Runs f(lo, hi) over [0, n) split across up to 6 threads (this one
+// included), one per `grain` items; small ranges stay on this thread.
+template <class F>
+void parallel_for(uint64_t n, uint64_t grain, F f) {
+    const unsigned T = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(6, n / grain));
+    if (T == 1) {
+        f(0, n);
+        return;
+    }
+    const uint64_t per = (n + T - 1) / T;
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < T; ++t) th.emplace_back(f, std::min(n, t * per), std::min(n, (t + 1) * per));
+    f(0, std::min(n, per));
+    for (auto &x : th) x.join();
+}
+
 // Adds the time from its construction to its destruction to *acc (microseconds).
 struct Span {
     double *acc;
@@ -136,17 +152,23 @@ struct Serve {
 
     // Packs the admitted requests and the host's next log chunk, uploads them.
     int pack_upload(RoundSet &r) {
+        const uint64_t n_req = r.reqs.size();
         uint32_t o = 0;
-        for (size_t k = 0; k < r.reqs.size(); ++k) {
-            const uint64_t i = r.reqs[k];
-            const uint32_t L = (uint32_t)req_ops(i);
+        for (size_t k = 0; k < n_req; ++k) {     // offsets (sequential prefix sum)
             r.h_off[k] = o;
-            memcpy(r.h_idx + o, sp.idx + sp.offsets[i], L * 4);
-            r.h_nw[k] = sp.n_writes[i];
-            r.h_tid[k] = sp.tid[i];
-            o += L;
+            o += (uint32_t)req_ops(r.reqs[k]);
         }
-        r.h_off[r.reqs.size()] = o;
+        r.h_off[n_req] = o;
+        parallel_for(n_req, 16384, [&](uint64_t lo, uint64_t hi) {
+            for (uint64_t k = lo; k < hi; ++k) {
+                const uint64_t i = r.reqs[k];
+                const uint32_t *src = sp.idx + sp.offsets[i];
+                uint32_t *dst = r.h_idx + r.h_off[k];
+                for (uint32_t j = 0, L = r.h_off[k + 1] - r.h_off[k]; j < L; ++j) dst[j] = src[j];
+                r.h_nw[k] = sp.n_writes[i];
+                r.h_tid[k] = sp.tid[i];
+            }
+        });
         r.n_log = std::min<uint64_t>(sp.host_log_per_round, sp.host_log_len - log_pos);
         if (r.n_log) memcpy(r.h_log, sp.host_log + log_pos, r.n_log * sizeof(hetm_log_entry4));
         log_pos += r.n_log;
@@ -215,14 +237,17 @@ struct Serve {
                 hipMemcpy(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
                 return HETM_EDEVICE;
         }
-        uint32_t o = 0;
-        for (size_t k = 0; k < n; ++k) {
-            const uint64_t i = r.reqs[k];
-            const uint32_t L = (uint32_t)req_ops(i);
-            if (rep->results) memcpy(rep->results + sp.offsets[i], r.h_res + o, L * 4);
-            if (rep->commit_seq) rep->commit_seq[i] = (rn << 32) | r.h_tick[k];
-            o += L;
-        }
+        parallel_for(n, 16384, [&](uint64_t lo, uint64_t hi) {
+            for (uint64_t k = lo; k < hi; ++k) {
+                const uint64_t i = r.reqs[k];
+                if (rep->results) {
+                    const uint32_t *src = r.h_res + r.h_off[k];
+                    uint32_t *dst = rep->results + sp.offsets[i];
+                    for (uint32_t j = 0, L = r.h_off[k + 1] - r.h_off[k]; j < L; ++j) dst[j] = src[j];
+                }
+                if (rep->commit_seq) rep->commit_seq[i] = (rn << 32) | r.h_tick[k];
+            }
+        });
         const uint64_t seq = hetm::last_merge_seq(c);
         if (pend && seq)
             pend->emplace_back(seq, r.reqs);
