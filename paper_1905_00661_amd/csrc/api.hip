@@ -170,7 +170,7 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
     if (rc) return rc;
     launch_compact(c->dargs, c->args.n_scan_blocks, c->stream);
     launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->stream);
-    launch_finish(c->dargs, c->snap_dev, c->args.n_bm_words, c->stream);
+    launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, c->stream);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipEventRecord(c->closed_ev, c->stream));
@@ -252,7 +252,7 @@ int build_graph(hetm_ctx *c) {
         launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
     else
         launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
-    launch_finish(c->dargs, c->snap_dev, c->args.n_bm_words, s);
+    launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, s);
     (void)hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
@@ -477,12 +477,13 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     const uint64_t N = k.n_words, G = k.granule_words;
     const uint64_t nG = (N + G - 1) / G;
     const uint64_t nbw = (nG + 31) / 32;
+    const uint64_t nrw = (nG + 3) / 4;
     const uint64_t nblocks = (nbw + kScanWordsPerBlock - 1) / kScanWordsPerBlock;
     const uint64_t nlocks = (N + k.lock_stripe_words - 1) / k.lock_stripe_words;
     TRY(dev_alloc(c, &c->stmr, N * k.word_bytes));
     TRY(dev_alloc(c, &c->locks, nlocks * 8));
     TRY(dev_alloc(c, &c->ts, N * 8));
-    TRY(dev_alloc(c, &c->rs, nbw * 4));
+    TRY(dev_alloc(c, &c->rs, nrw * 4));
     TRY(dev_alloc(c, &c->ws, nbw * 4));
     TRY(dev_alloc(c, &c->suspect, ((k.log_capacity + 63) / 64) * 8));
     TRY(dev_alloc(c, &c->multi, ((k.log_capacity + 63) / 64) * 8));
@@ -541,7 +542,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     hipStream_t s = c->stream;
     bool ok = hipMemsetAsync(c->locks, 0, nlocks * 8, s) == hipSuccess &&
               hipMemsetAsync(c->ts, 0, N * 8, s) == hipSuccess &&
-              hipMemsetAsync(c->rs, 0, nbw * 4, s) == hipSuccess &&
+              hipMemsetAsync(c->rs, 0, nrw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->ws, 0, nbw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), s) == hipSuccess &&
               hipMemsetAsync(c->hot, 0, sizeof(HotCounters), s) == hipSuccess &&
@@ -571,7 +572,8 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     a.gdiv = make_div32((uint32_t)G);
     a.n_words = N, a.word_bytes = k.word_bytes, a.granule = (uint32_t)G;
     a.stripe_shift = ilog2(k.lock_stripe_words);
-    a.n_granules = (uint32_t)nG, a.n_bm_words = (uint32_t)nbw, a.retry_cap = c->cfg.retry_cap;
+    a.n_granules = (uint32_t)nG, a.n_bm_words = (uint32_t)nbw, a.n_rs_words = (uint32_t)nrw;
+    a.retry_cap = c->cfg.retry_cap;
     a.max_ops = k.max_txn_ops, a.n_scan_blocks = (uint32_t)nblocks;
     a.outcome = HETM_OUTCOME_DEVICE;
     c->stats.device_bytes = c->device_bytes;
@@ -810,6 +812,24 @@ int hetm_read_state(hetm_ctx *c, uint32_t what, void *dst, uint64_t bytes) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     int dr = drain_merges(c);
     if (dr) return dr;
+    if (what == HETM_STATE_RS) {
+        // the device keeps one byte per granule; callers get the bitmap
+        const uint64_t nG = c->args.n_granules;
+        const uint64_t off = (nG + 3) & ~3ull;
+        uint8_t *bytes_map = new (std::nothrow) uint8_t[off + bytes];
+        if (!bytes_map) return fail(c, HETM_ENOMEM, "read-set copy");
+        uint32_t *bits = (uint32_t *)(bytes_map + off);
+        memset(bits, 0, bytes);
+        hipError_t e = hipMemcpy(bytes_map, src, nG, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) {
+            for (uint64_t g = 0; g < nG; ++g)
+                if (bytes_map[g]) bits[g >> 5] |= 1u << (g & 31);
+            e = hipMemcpy(dst, bits, bytes, hipMemcpyDefault);
+        }
+        delete[] bytes_map;
+        if (e != hipSuccess) return fail(c, HETM_EDEVICE, "%s", hipGetErrorString(e));
+        return HETM_OK;
+    }
     HIP_TRY(c, hipMemcpy(dst, src, bytes, hipMemcpyDefault));
     return HETM_OK;
 }

@@ -91,10 +91,10 @@ struct WriteBuf {
     __device__ void write_back(Word *stmr) {
         for (uint32_t k = 0; k < n; ++k) st_agent(&stmr[at(k)], val[k][lane]);
     }
-    __device__ void mark_writes(uint32_t *rs, uint32_t *ws, const Div32 &G) {
+    __device__ void mark_writes(uint8_t *rs, uint32_t *ws, const Div32 &G) {
         for (uint32_t k = 0; k < n; ++k) {
             uint32_t g = div32(at(k), G);
-            bitmap_set(rs, g);
+            rs_mark(rs, g);
             bitmap_set(ws, g);
         }
     }
@@ -229,7 +229,8 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     const uint32_t wv = threadIdx.x / kWave;
     uint32_t *stmr = (uint32_t *)a->stmr;
     uint64_t *locks = a->locks;
-    uint32_t *rs = a->rs, *ws = a->ws;
+    uint8_t *rs = a->rs;
+    uint32_t *ws = a->ws;
     DevCounters *cnt = a->cnt;
     const uint32_t n = a->n_txns, sh = a->stripe_shift, max_ops = a->max_ops;
     const Div32 G = a->gdiv;
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
         hw_order();
         if (wb.locked) wb.release(locks, sh, ok);
         if (ok) {
-            for (uint32_t j = nwr; j < L; ++j) bitmap_set(rs, div32(ix[j * kWave], G));
+            for (uint32_t j = nwr; j < L; ++j) rs_mark(rs, div32(ix[j * kWave], G));
             wb.mark_writes(rs, ws, G);
         }
         settle(ls, act, malformed, ok, ticket, a->tickets, cnt, a->retry_cap);
@@ -318,7 +319,8 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
     const uint32_t wv = threadIdx.x / kWave;
     uint64_t *stmr = (uint64_t *)a->stmr;
     uint64_t *locks = a->locks;
-    uint32_t *rs = a->rs, *ws = a->ws;
+    uint8_t *rs = a->rs;
+    uint32_t *ws = a->ws;
     DevCounters *cnt = a->cnt;
     const uint32_t n = a->n_txns, sh = a->stripe_shift;
     const Div32 G = a->gdiv;
@@ -380,8 +382,8 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
         hw_order();
         if (wb.locked) wb.release(locks, sh, ok);
         if (ok) {
-            bitmap_set(rs, div32(s, G));
-            bitmap_set(rs, div32(d, G));
+            rs_mark(rs, div32(s, G));
+            rs_mark(rs, div32(d, G));
             wb.mark_writes(rs, ws, G);
         }
         settle(ls, act, act && (s >= N || d >= N), ok, ticket, a->tickets, cnt, a->retry_cap);
@@ -415,7 +417,8 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
     const uint32_t wv = threadIdx.x / kWave;
     uint32_t *stmr = (uint32_t *)a->stmr;
     uint64_t *locks = a->locks;
-    uint32_t *rs = a->rs, *ws = a->ws;
+    uint8_t *rs = a->rs;
+    uint32_t *ws = a->ws;
     DevCounters *cnt = a->cnt;
     const uint32_t n = a->n_txns, sh = a->stripe_shift;
     const Div32 G = a->gdiv;
@@ -521,9 +524,9 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
         hw_order();
         if (wb.locked) wb.release(locks, sh, ok);
         if (ok) {
-            for (uint32_t j = 0; j < nh; ++j) bitmap_set(rs, div32(base + header_word(j), G));
+            for (uint32_t j = 0; j < nh; ++j) rs_mark(rs, div32(base + header_word(j), G));
             if (get_hit)
-                for (uint32_t i = 0; i < 8; ++i) bitmap_set(rs, div32(base + kValBase + 8 * hit + i, G));
+                for (uint32_t i = 0; i < 8; ++i) rs_mark(rs, div32(base + kValBase + 8 * hit + i, G));
             wb.mark_writes(rs, ws, G);
         }
         settle(ls, act, act && (key == 0 || put > 1), ok, ticket, a->tickets, cnt, a->retry_cap);

@@ -25,7 +25,8 @@ struct hetm_ctx {
     void *stmr = nullptr;
     uint64_t *locks = nullptr;
     uint64_t *ts = nullptr;
-    uint32_t *rs = nullptr, *ws = nullptr, *suspect = nullptr, *multi = nullptr;
+    uint8_t *rs = nullptr;             // read set, one byte per granule
+    uint32_t *ws = nullptr, *suspect = nullptr, *multi = nullptr;
     uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;
     void *log_staging = nullptr;
     DevCounters *cnt = nullptr;

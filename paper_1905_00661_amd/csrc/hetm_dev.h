@@ -80,7 +80,7 @@ struct DevArgs {
     void *stmr;
     uint64_t *locks;
     uint64_t *ts;
-    uint32_t *rs;
+    uint8_t *rs;            // read set: one byte per granule (see rs_mark)
     uint32_t *ws;
     uint32_t *suspect;      // apply pass 1 -> 2: entry met its own ts (a tie), one bit per entry
     uint32_t *multi;        // apply pass 1 -> 2: entry met another entry of the round for its word
@@ -95,7 +95,8 @@ struct DevArgs {
     uint32_t granule;       // G
     uint32_t stripe_shift;  // log2(S)
     uint32_t n_granules;    // ceil(N/G)
-    uint32_t n_bm_words;    // ceil(n_granules / 32)
+    uint32_t n_bm_words;    // ceil(n_granules / 32): words of the write-set bitmap
+    uint32_t n_rs_words;    // ceil(n_granules / 4): words of the read-set byte map
     uint32_t retry_cap;
     uint32_t max_ops;
     uint32_t n_scan_blocks;
@@ -199,6 +200,16 @@ __device__ __forceinline__ void bitmap_set(uint32_t *bm, uint32_t g) {
     if (!(cur & b)) __hip_atomic_fetch_or(bm + w, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The read set is a byte map, so marking a granule is an idempotent store
+// instead of an atomic OR on a shared bitmap word (a committed transaction
+// marks every granule it read: millions per round).  The test is a plain
+// load -- a stale zero only costs a repeated store -- and the store goes to
+// the device coherence point, where early validation can see it while the
+// batch still runs.
+__device__ __forceinline__ void rs_mark(uint8_t *rs, uint32_t g) {
+    if (!rs[g]) st_agent(&rs[g], (uint8_t)1);
+}
+
 
 // ------------------------------------------------------------- launchers
 // Host-side launch wrappers, defined next to their kernels.  `a` is the
@@ -215,8 +226,8 @@ void launch_validate(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hi
 void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s);
 void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
-void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hipStream_t s);
-void launch_early_validate(const void *log, uint64_t n, uint32_t word_bytes, const uint32_t *rs, Div32 gdiv,
+void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_rs_words, hipStream_t s);
+void launch_early_validate(const void *log, uint64_t n, uint32_t word_bytes, const uint8_t *rs, Div32 gdiv,
                            uint64_t n_words, uint32_t epoch, DevCounters *cnt, hipStream_t s);
 void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
 void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uint32_t *count, uint64_t n_words,

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a)
     const E *log = (const E *)a->log;
     const uint64_t n = a->n_log, N = a->n_words;
     const Div32 G = a->gdiv;
-    const uint32_t *rs = a->rs;
+    const uint8_t *rs = a->rs;
     uint32_t *flags = a->flags;
     DevCounters *cnt = a->cnt;
     const uint64_t floor_ts = ld_agent(&cnt->floor_ts);
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a)
                 latch_error(cnt, HETM_EORDER, (uint32_t)k);
             } else {
                 const uint32_t g = div32(e.word, G);
-                f = (rs[g >> 5] >> (g & 31)) & 1u;
+                f = ld_agent(&rs[g]) != 0;
                 mx = e.ts > mx ? e.ts : mx;
             }
         }
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a)
 // the end of the round sees the final bitmap -- so entries failing the
 // preconditions are simply skipped (the final validation reports them).
 template <typename E>
-__global__ __launch_bounds__(256) void k_early_validate(const E *__restrict__ log, uint64_t n, const uint32_t *rs,
+__global__ __launch_bounds__(256) void k_early_validate(const E *__restrict__ log, uint64_t n, const uint8_t *rs,
                                                         Div32 G, uint64_t N, uint32_t epoch, DevCounters *cnt) {
     bool hit = false;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_early_validate(const E *__restrict__ lo
         const E e = log[k];
         if (e.word >= N) continue;
         const uint32_t g = div32(e.word, G);
-        hit = (ld_agent(&rs[g >> 5]) >> (g & 31)) & 1u;
+        hit = ld_agent(&rs[g]) != 0;
     }
     if (__ballot(hit) && lane_id() == 0) st_agent(&cnt->doomed, epoch);
 }
@@ -435,10 +435,11 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         *snap = c;
     }
     if (err) return;      // keep the round open: the caller can fix the log and merge again
-    const uint32_t nbw = a->n_bm_words;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nbw; i += gridDim.x * blockDim.x) {
-        a->rs[i] = 0u;
-        a->ws[i] = 0u;
+    const uint32_t nbw = a->n_bm_words, nrw = a->n_rs_words;
+    uint32_t *rs = (uint32_t *)a->rs;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nrw; i += gridDim.x * blockDim.x) {
+        rs[i] = 0u;
+        if (i < nbw) a->ws[i] = 0u;
     }
 }
 
@@ -515,7 +516,7 @@ void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t 
     }
 }
 
-void launch_early_validate(const void *log, uint64_t n, uint32_t word_bytes, const uint32_t *rs, Div32 gdiv,
+void launch_early_validate(const void *log, uint64_t n, uint32_t word_bytes, const uint8_t *rs, Div32 gdiv,
                            uint64_t n_words, uint32_t epoch, DevCounters *cnt, hipStream_t s) {
     const uint32_t grid = stream_grid(n, 256, 4096);
     if (word_bytes == 4)
@@ -557,8 +558,8 @@ void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uin
                            ids, count, granule, n_words);
 }
 
-void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_bm_words, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(stream_grid(n_bm_words, 256, 4096)), dim3(256), 0, s, a, snap);
+void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_rs_words, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(stream_grid(n_rs_words, 256, 4096)), dim3(256), 0, s, a, snap);
 }
 
 }  // namespace hetm
