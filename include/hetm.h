@@ -297,8 +297,11 @@ int hetm_set_exec_workgroups(hetm_ctx *ctx, uint32_t workgroups);
 /* Copies context state out (synchronizes).  what: 0 STMR (N*W bytes),
  * 1 TS (N u64), 2 read-set bitmap, 3 write-set bitmap (ceil(ceil(N/G)/32)
  * u32 each, bit g of word g/32 for granule g; the device keeps the read set
- * as one byte per granule and this call packs it), 4 lock table.  dst
- * host-or-device, bytes = its size. */
+ * as one byte per granule and this call packs it), 4 lock table
+ * (ceil(N/S) u64: bit 63 lock, the rest version; for u32 words with S = 1
+ * the replica keeps value, version and lock of a word in one u64 -- bits
+ * 0..31 value, 32..62 version, 63 lock -- and this returns those words).
+ * dst host-or-device, bytes = its size. */
 #define HETM_STATE_STMR 0u
 #define HETM_STATE_TS   1u
 #define HETM_STATE_RS   2u

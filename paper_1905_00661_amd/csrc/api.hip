@@ -169,7 +169,7 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
     int rc = push_args(c);
     if (rc) return rc;
     launch_compact(c->dargs, c->args.n_scan_blocks, c->stream);
-    launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->stream);
+    launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, c->stream);
     launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, c->stream);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream));
@@ -244,14 +244,14 @@ int build_graph(hetm_ctx *c) {
     // device copy node would issue PCIe reads that queue behind the previous
     // round's merge copy (device-to-host posted writes) and stall the launch.
     launch_set_args(c->args, c->dargs, s);
-    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, s);
+    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, s);
     launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
     launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
     launch_compact(c->dargs, c->args.n_scan_blocks, s);
     if (c->cfg.async_merge)
-        launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
+        launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
     else
-        launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, s);
+        launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
     launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, s);
     (void)hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, s);
     hipGraph_t g = nullptr;
@@ -404,7 +404,7 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
             // replica once the previous round's copy has landed there
             if ((rc = drain_merges(c))) return rc;
             launch_restore(c->stmr, hdev, c->stage_ids[b], c->stage_count[b], c->cfg.n_words, c->cfg.granule_words,
-                           c->cfg.word_bytes, s);
+                           c->cfg.word_bytes, c->slot, s);
             HIP_TRY(c, hipGetLastError());
             HIP_TRY(c, hipStreamSynchronize(s));
         }
@@ -480,8 +480,15 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     const uint64_t nrw = (nG + 3) / 4;
     const uint64_t nblocks = (nbw + kScanWordsPerBlock - 1) / kScanWordsPerBlock;
     const uint64_t nlocks = (N + k.lock_stripe_words - 1) / k.lock_stripe_words;
-    TRY(dev_alloc(c, &c->stmr, N * k.word_bytes));
-    TRY(dev_alloc(c, &c->locks, nlocks * 8));
+    // u32 words with one lock per word use the slot layout (value, version
+    // and lock in one u64); otherwise a value array plus a lock table
+    c->slot = k.word_bytes == 4 && k.lock_stripe_words == 1;
+    if (c->slot) {
+        TRY(dev_alloc(c, &c->stmr, N * 8));
+    } else {
+        TRY(dev_alloc(c, &c->stmr, N * k.word_bytes));
+        TRY(dev_alloc(c, &c->locks, nlocks * 8));
+    }
     TRY(dev_alloc(c, &c->ts, N * 8));
     TRY(dev_alloc(c, &c->rs, nrw * 4));
     TRY(dev_alloc(c, &c->ws, nbw * 4));
@@ -540,16 +547,22 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
         return HETM_EDEVICE;
     }
     hipStream_t s = c->stream;
-    bool ok = hipMemsetAsync(c->locks, 0, nlocks * 8, s) == hipSuccess &&
-              hipMemsetAsync(c->ts, 0, N * 8, s) == hipSuccess &&
+    bool ok = (c->slot || hipMemsetAsync(c->locks, 0, nlocks * 8, s) == hipSuccess) &&
               hipMemsetAsync(c->rs, 0, nrw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->ws, 0, nbw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), s) == hipSuccess &&
               hipMemsetAsync(c->hot, 0, sizeof(HotCounters), s) == hipSuccess &&
               hipMemsetAsync(c->blocksums, 0, nblocks * 4, s) == hipSuccess;
-    if (ok)
+    if (ok && c->slot && init_image) {
+        // the image goes through the TS array (N u64, cleared afterwards)
+        ok = hipMemcpyAsync(c->ts, init_image, N * 4, hipMemcpyDefault, s) == hipSuccess;
+        if (ok) launch_to_slots((const uint32_t *)c->ts, (uint64_t *)c->stmr, N, s);
+        ok = ok && hipGetLastError() == hipSuccess;
+    } else if (ok) {
         ok = init_image ? hipMemcpyAsync(c->stmr, init_image, N * k.word_bytes, hipMemcpyDefault, s) == hipSuccess
-                        : hipMemsetAsync(c->stmr, 0, N * k.word_bytes, s) == hipSuccess;
+                        : hipMemsetAsync(c->stmr, 0, c->slot ? N * 8 : N * k.word_bytes, s) == hipSuccess;
+    }
+    ok = ok && hipMemsetAsync(c->ts, 0, N * 8, s) == hipSuccess;
     if (!ok || hipStreamSynchronize(s) != hipSuccess) {
         hetm_free(c);
         return HETM_EDEVICE;
@@ -566,6 +579,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
 
     DevArgs &a = c->args;
     a.stmr = c->stmr, a.locks = c->locks, a.ts = c->ts, a.rs = c->rs, a.ws = c->ws;
+    a.word_shift = c->slot ? 1u : 0u;
     a.suspect = c->suspect, a.multi = c->multi, a.blocksums = c->blocksums, a.blockruns = c->blockruns, a.ids_scratch = c->ids;
     a.cnt = c->cnt;
     a.hot = c->hot;
@@ -630,7 +644,7 @@ int hetm_submit_batch(hetm_ctx *c, uint32_t program, const void *descs, uint64_t
     int rc = set_batch_args(c, program, descs, n_txns, results, tickets);
     if (rc) return rc;
     if ((rc = push_args(c))) return rc;
-    launch_exec(program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->stream);
+    launch_exec(program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->stream);
     HIP_TRY(c, hipGetLastError());
     return HETM_OK;
 }
@@ -699,7 +713,7 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     if (r->n_txns) {
         if ((rc = push_args(c))) return rc;
-        launch_exec(r->program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, s);
+        launch_exec(r->program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, s);
         HIP_TRY(c, hipGetLastError());
     }
     HIP_TRY(c, hipEventRecord(c->ev[1], s));
@@ -806,12 +820,24 @@ int hetm_read_state(hetm_ctx *c, uint32_t what, void *dst, uint64_t bytes) {
                       : what == HETM_STATE_TS  ? (const void *)c->ts
                       : what == HETM_STATE_RS  ? (const void *)c->rs
                       : what == HETM_STATE_WS  ? (const void *)c->ws
-                      : what == HETM_STATE_LOCKS ? (const void *)c->locks
+                      : what == HETM_STATE_LOCKS ? (c->slot ? c->stmr : (const void *)c->locks)
                                                  : nullptr;
     if (!src || bytes != hetm_state_bytes(c, what)) return fail(c, HETM_EINVAL, "bad state request");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     int dr = drain_merges(c);
     if (dr) return dr;
+    if (what == HETM_STATE_STMR && c->slot) {
+        // the values of the slots, through a scratch buffer
+        uint32_t *tmp = nullptr;
+        HIP_TRY(c, hipMalloc((void **)&tmp, bytes ? bytes : 4));
+        launch_from_slots((const uint64_t *)c->stmr, tmp, c->cfg.n_words, c->stream);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = hipMemcpy(dst, tmp, bytes, hipMemcpyDefault);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(c, HETM_EDEVICE, "%s", hipGetErrorString(e));
+        return HETM_OK;
+    }
     if (what == HETM_STATE_RS) {
         // the device keeps one byte per granule; callers get the bitmap
         const uint64_t nG = c->args.n_granules;

@@ -22,11 +22,43 @@
 //  * Bitmaps are set only by the committed attempt: the read-set bitmap gets
 //    every word read or written (writes included, so WS is within RS and the
 //    validation also excludes write-write conflicts, §IV-C.2).
+//  * Two layouts of the replica.  Split: a value array plus a lock table of
+//    one word per stripe of S words.  Slot (u32 words, S = 1): each word's
+//    value, version and lock share one u64 (bits 0..31 value, 32..62
+//    version, 63 lock), so one load returns a value together with the
+//    version it belongs to, one store publishes a commit, and a read touches
+//    one cache line instead of two.
 #include "hetm_dev.h"
 
 namespace hetm {
 
 namespace {
+
+// Replica layouts (see above).  lock(w) is the lock word covering word w,
+// stripe(w) its identity, load(w) a device-coherent read of the value.
+template <typename Word>
+struct Split {
+    Word *vals;
+    uint64_t *locks;
+    uint32_t sh;
+    static constexpr bool kFused = false;
+    __device__ uint64_t *lock(uint32_t w) const { return &locks[w >> sh]; }
+    __device__ uint32_t stripe(uint32_t w) const { return w >> sh; }
+    __device__ Word load(uint32_t w) const { return ld_agent(&vals[w]); }
+};
+
+struct Slot {
+    uint64_t *slots;
+    static constexpr bool kFused = true;
+    __device__ uint64_t *lock(uint32_t w) const { return &slots[w]; }
+    __device__ uint32_t stripe(uint32_t w) const { return w; }
+    __device__ uint32_t load(uint32_t w) const { return (uint32_t)ld_agent(&slots[w]); }
+    // a slot without its lock bit: version above, value below
+    static __device__ uint64_t commit_word(uint64_t locked, uint32_t value) {
+        const uint64_t ver = ((locked >> 32) + 1) & 0x7FFFFFFFull;
+        return (ver << 32) | value;
+    }
+};
 
 // Per-lane write buffer staged in LDS, [slot][lane] so that the 64 lanes of a
 // wave touch 64 consecutive dwords per slot (no bank conflicts).
@@ -36,7 +68,7 @@ struct WriteBuf {
     Word (*val)[kWave];
     uint32_t lane;
     uint32_t n;
-    uint32_t locked;   // slots whose stripe this lane holds
+    uint32_t locked;   // entries whose lock word this lane holds
 
     __device__ void put(uint32_t w, Word v) {
         addr[n][lane] = w;
@@ -45,51 +77,67 @@ struct WriteBuf {
     }
     __device__ uint32_t at(uint32_t k) const { return addr[k][lane]; }
 
-    // Try-lock every distinct write stripe in ascending stripe order (so two
+    // Try-lock every distinct lock word in ascending stripe order (so two
     // lanes wanting the same stripes collide on the first one instead of each
     // holding one of them in lockstep); on failure release what was taken.
-    __device__ bool lock_all(uint64_t *locks, uint32_t sh) {
+    template <typename Lay>
+    __device__ bool lock_all(const Lay &lay) {
         locked = 0;
         int64_t last = -1;
         for (;;) {
             uint32_t kmin = n;
             uint32_t smin = 0;
             for (uint32_t k = 0; k < n; ++k) {
-                const uint32_t s = at(k) >> sh;
+                const uint32_t s = lay.stripe(at(k));
                 if ((int64_t)s > last && (kmin == n || s < smin)) {
                     kmin = k;
                     smin = s;
                 }
             }
             if (kmin == n) return true;
-            uint64_t cur = ld_agent(&locks[smin]);
-            if ((cur & kLockBit) || !cas_agent(&locks[smin], cur, cur | kLockBit)) {
-                release(locks, sh, false);
+            uint64_t *p = lay.lock(at(kmin));
+            uint64_t cur = ld_agent(p);
+            if ((cur & kLockBit) || !cas_agent(p, cur, cur | kLockBit)) {
+                abort(lay);
                 return false;
             }
             locked |= 1u << kmin;
             last = smin;
         }
     }
-    __device__ bool mine(uint32_t s, uint32_t sh) const {
+    template <typename Lay>
+    __device__ bool mine(const Lay &lay, uint32_t s) const {
         for (uint32_t k = 0; k < n; ++k)
-            if (((locked >> k) & 1u) && (at(k) >> sh) == s) return true;
+            if (((locked >> k) & 1u) && lay.stripe(at(k)) == s) return true;
         return false;
     }
-    // commit: version+1 and unlock; abort: unlock with the version unchanged
-    __device__ void release(uint64_t *locks, uint32_t sh, bool commit) {
-        for (uint32_t k = 0; k < n; ++k) {
-            if (!((locked >> k) & 1u)) continue;
-            uint64_t *p = &locks[at(k) >> sh];
-            if (commit)
-                __hip_atomic_fetch_add(p, 1ull - kLockBit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else
-                __hip_atomic_fetch_and(p, ~kLockBit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+    // unlock with the version unchanged
+    template <typename Lay>
+    __device__ void abort(const Lay &lay) {
+        for (uint32_t k = 0; k < n; ++k)
+            if ((locked >> k) & 1u)
+                __hip_atomic_fetch_and(lay.lock(at(k)), ~kLockBit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         locked = 0;
     }
-    __device__ void write_back(Word *stmr) {
-        for (uint32_t k = 0; k < n; ++k) st_agent(&stmr[at(k)], val[k][lane]);
+    // Publish the buffered writes.  Split: store every value, then release
+    // each held stripe with version + 1.  Slot: one store per held word
+    // writes value, version + 1 and the cleared lock together (duplicate
+    // entries of a word carry the same value, so the held one suffices).
+    __device__ void commit(const Split<Word> &lay) {
+        for (uint32_t k = 0; k < n; ++k) st_agent(&lay.vals[at(k)], val[k][lane]);
+        hw_order();
+        for (uint32_t k = 0; k < n; ++k)
+            if ((locked >> k) & 1u)
+                __hip_atomic_fetch_add(lay.lock(at(k)), 1ull - kLockBit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        locked = 0;
+    }
+    __device__ void commit(const Slot &lay) {
+        for (uint32_t k = 0; k < n; ++k) {
+            if (!((locked >> k) & 1u)) continue;
+            uint64_t *p = lay.lock(at(k));
+            st_agent(p, Slot::commit_word(ld_agent(p), (uint32_t)val[k][lane]));
+        }
+        locked = 0;
     }
     __device__ void mark_writes(uint8_t *rs, uint32_t *ws, const Div32 &G) {
         for (uint32_t k = 0; k < n; ++k) {
@@ -100,14 +148,13 @@ struct WriteBuf {
     }
 };
 
-// Revalidation of one read stripe after the ticket: returns the version to
-// add to the second sum, or sets ok = false if another transaction holds it.
-template <typename WB>
-__device__ __forceinline__ uint64_t reread(const uint64_t *locks, uint32_t s, uint32_t sh, const WB &wb,
-                                           bool &ok) {
-    uint64_t l = ld_agent(&locks[s]);
+// Revalidation of one read word after the ticket: returns its lock word
+// without the lock bit, or sets ok = false if another transaction holds it.
+template <typename Lay, typename WB>
+__device__ __forceinline__ uint64_t reread(const Lay &lay, uint32_t w, const WB &wb, bool &ok) {
+    uint64_t l = ld_agent(lay.lock(w));
     if (l & kLockBit) {
-        if (!wb.mine(s, sh)) ok = false;
+        if (!wb.mine(lay, lay.stripe(w))) ok = false;
         l &= ~kLockBit;
     }
     return l;
@@ -216,23 +263,38 @@ __device__ __forceinline__ bool doomed(DevCounters *cnt, uint32_t epoch) {
     return true;
 }
 
+template <typename Lay>
+__device__ __forceinline__ Lay make_layout(const DevArgs *a);
+template <>
+__device__ __forceinline__ Slot make_layout<Slot>(const DevArgs *a) {
+    return Slot{(uint64_t *)a->stmr};
+}
+template <>
+__device__ __forceinline__ Split<uint32_t> make_layout<Split<uint32_t>>(const DevArgs *a) {
+    return Split<uint32_t>{(uint32_t *)a->stmr, a->locks, a->stripe_shift};
+}
+template <>
+__device__ __forceinline__ Split<uint64_t> make_layout<Split<uint64_t>>(const DevArgs *a) {
+    return Split<uint64_t>{(uint64_t *)a->stmr, a->locks, a->stripe_shift};
+}
+
 // ------------------------------------------------------------------ OPLIST
 // Transaction i reads idx[off[i] .. off[i+1]) in order, then writes each of
 // its first nw[i] words with (value read + tid[i]) mod 2^32.
 // An attempt loads its word list from HBM once, into LDS ([op][lane] per
 // wave, max_ops x 64 dwords, dynamic), and every later pass -- lock words,
 // values, revalidation, bitmaps -- reads it from there.
+template <typename Lay>
 __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs *__restrict__ a) {
     __shared__ uint32_t s_addr[kExecWaves][kOplistMaxWrites][kWave];
     __shared__ uint32_t s_val[kExecWaves][kOplistMaxWrites][kWave];
     extern __shared__ uint32_t s_dyn[];
     const uint32_t wv = threadIdx.x / kWave;
-    uint32_t *stmr = (uint32_t *)a->stmr;
-    uint64_t *locks = a->locks;
+    const Lay lay = make_layout<Lay>(a);
     uint8_t *rs = a->rs;
     uint32_t *ws = a->ws;
     DevCounters *cnt = a->cnt;
-    const uint32_t n = a->n_txns, sh = a->stripe_shift, max_ops = a->max_ops;
+    const uint32_t n = a->n_txns, max_ops = a->max_ops;
     const Div32 G = a->gdiv;
     const uint64_t N = a->n_words;
     const uint32_t *off = a->off, *idx = a->idx, *tid = a->tid;
@@ -272,35 +334,50 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
             }
         }
         bool ok = act && !malformed;
-        // first pass over the read stripes
-        uint64_t sum1 = 0;
-        for (uint32_t j = 0; j < L; ++j) {
-            uint64_t l = ld_agent(&locks[ix[j * kWave] >> sh]);
-            ok &= !(l & kLockBit);
-            sum1 += l;
-        }
-        hw_order();
         wb.n = 0;
-        if (ok) {
+        uint64_t sum1 = 0;
+        if (Lay::kFused) {
+            // one load per read: value and version together
             for (uint32_t j = 0; j < L; ++j) {
-                uint32_t w = ix[j * kWave];
-                uint32_t v = ld_agent(&stmr[w]);
+                const uint32_t w = ix[j * kWave];
+                const uint64_t l = ld_agent(lay.lock(w));
+                ok &= !(l & kLockBit);
+                sum1 += l;
+                const uint32_t v = (uint32_t)l;
                 res[o + j] = v;
                 if (j < nwr) wb.put(w, v + tv);
             }
-            if (nwr) ok = wb.lock_all(locks, sh);
+            if (ok && nwr) ok = wb.lock_all(lay);
+        } else {
+            // first pass over the read stripes, then the values
+            for (uint32_t j = 0; j < L; ++j) {
+                uint64_t l = ld_agent(lay.lock(ix[j * kWave]));
+                ok &= !(l & kLockBit);
+                sum1 += l;
+            }
+            hw_order();
+            if (ok) {
+                for (uint32_t j = 0; j < L; ++j) {
+                    uint32_t w = ix[j * kWave];
+                    uint32_t v = lay.load(w);
+                    res[o + j] = v;
+                    if (j < nwr) wb.put(w, v + tv);
+                }
+                if (nwr) ok = wb.lock_all(lay);
+            }
         }
         hw_order();
         uint32_t ticket = wave_fetch_add(&a->hot->ticket.v, ok);
         hw_order();
         if (ok) {
             uint64_t sum2 = 0;
-            for (uint32_t j = 0; j < L && ok; ++j) sum2 += reread(locks, ix[j * kWave] >> sh, sh, wb, ok);
+            for (uint32_t j = 0; j < L && ok; ++j) sum2 += reread(lay, ix[j * kWave], wb, ok);
             ok &= sum2 == sum1;
         }
-        if (ok) wb.write_back(stmr);
-        hw_order();
-        if (wb.locked) wb.release(locks, sh, ok);
+        if (ok)
+            wb.commit(lay);
+        else if (wb.locked)
+            wb.abort(lay);
         if (ok) {
             for (uint32_t j = nwr; j < L; ++j) rs_mark(rs, div32(ix[j * kWave], G));
             wb.mark_writes(rs, ws, G);
@@ -317,12 +394,11 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
     __shared__ uint32_t s_addr[kExecWaves][2][kWave];
     __shared__ uint64_t s_val[kExecWaves][2][kWave];
     const uint32_t wv = threadIdx.x / kWave;
-    uint64_t *stmr = (uint64_t *)a->stmr;
-    uint64_t *locks = a->locks;
+    const Split<uint64_t> lay = make_layout<Split<uint64_t>>(a);
     uint8_t *rs = a->rs;
     uint32_t *ws = a->ws;
     DevCounters *cnt = a->cnt;
-    const uint32_t n = a->n_txns, sh = a->stripe_shift;
+    const uint32_t n = a->n_txns;
     const Div32 G = a->gdiv;
     const uint64_t N = a->n_words;
     int64_t *res = (int64_t *)a->results;
@@ -350,16 +426,16 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
         }
         uint64_t sum1 = 0;
         if (ok) {
-            uint64_t l1 = ld_agent(&locks[s >> sh]);
-            uint64_t l2 = ld_agent(&locks[d >> sh]);
+            uint64_t l1 = ld_agent(lay.lock(s));
+            uint64_t l2 = ld_agent(lay.lock(d));
             ok = !((l1 | l2) & kLockBit);
             sum1 = l1 + l2;
         }
         hw_order();
         wb.n = 0;
         if (ok) {
-            int64_t bs = (int64_t)ld_agent(&stmr[s]);
-            int64_t bd = (int64_t)ld_agent(&stmr[d]);
+            int64_t bs = (int64_t)lay.load(s);
+            int64_t bd = (int64_t)lay.load(d);
             bool applied = s != d && bs >= (int64_t)am;
             res[ls.txn] = bs;
             res[n + ls.txn] = bd;
@@ -367,20 +443,21 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
             if (applied) {
                 wb.put(s, (uint64_t)(bs - (int64_t)am));
                 wb.put(d, (uint64_t)(bd + (int64_t)am));
-                ok = wb.lock_all(locks, sh);
+                ok = wb.lock_all(lay);
             }
         }
         hw_order();
         uint32_t ticket = wave_fetch_add(&a->hot->ticket.v, ok);
         hw_order();
         if (ok) {
-            uint64_t sum2 = reread(locks, s >> sh, sh, wb, ok);
-            sum2 += reread(locks, d >> sh, sh, wb, ok);
+            uint64_t sum2 = reread(lay, s, wb, ok);
+            sum2 += reread(lay, d, wb, ok);
             ok &= sum2 == sum1;
         }
-        if (ok) wb.write_back(stmr);
-        hw_order();
-        if (wb.locked) wb.release(locks, sh, ok);
+        if (ok)
+            wb.commit(lay);
+        else if (wb.locked)
+            wb.abort(lay);
         if (ok) {
             rs_mark(rs, div32(s, G));
             rs_mark(rs, div32(d, G));
@@ -411,16 +488,16 @@ __device__ __forceinline__ uint32_t header_word(uint32_t j) {
     return j < 16 ? j : (j == 16 ? kSetStamp : kStampBase + (j - 17));
 }
 
+template <typename Lay>
 __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs *__restrict__ a) {
     __shared__ uint32_t s_addr[kExecWaves][kCacheMaxWrites][kWave];
     __shared__ uint32_t s_val[kExecWaves][kCacheMaxWrites][kWave];
     const uint32_t wv = threadIdx.x / kWave;
-    uint32_t *stmr = (uint32_t *)a->stmr;
-    uint64_t *locks = a->locks;
+    const Lay lay = make_layout<Lay>(a);
     uint8_t *rs = a->rs;
     uint32_t *ws = a->ws;
     DevCounters *cnt = a->cnt;
-    const uint32_t n = a->n_txns, sh = a->stripe_shift;
+    const uint32_t n = a->n_txns;
     const Div32 G = a->gdiv;
     const uint64_t nsets = a->n_words / kSetWords;
     uint32_t *res = (uint32_t *)a->results;
@@ -452,14 +529,14 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
         uint64_t sum1 = 0;
         if (ok)
             for (uint32_t j = 0; j < nh; ++j) {
-                uint64_t l = ld_agent(&locks[(base + header_word(j)) >> sh]);
+                uint64_t l = ld_agent(lay.lock(base + header_word(j)));
                 ok &= !(l & kLockBit);
                 sum1 += l;
             }
         hw_order();
         uint32_t hdr[25];
 #pragma unroll
-        for (uint32_t j = 0; j < 25; ++j) hdr[j] = (ok && j < nh) ? ld_agent(&stmr[base + header_word(j)]) : 0u;
+        for (uint32_t j = 0; j < 25; ++j) hdr[j] = (ok && j < nh) ? lay.load(base + header_word(j)) : 0u;
         int hit = -1;
 #pragma unroll
         for (int w = 7; w >= 0; --w)
@@ -468,7 +545,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
         const bool get_hit = ok && !put && hit >= 0;
         if (get_hit)
             for (uint32_t i = 0; i < 8; ++i) {
-                uint64_t l = ld_agent(&locks[(base + kValBase + 8 * hit + i) >> sh]);
+                uint64_t l = ld_agent(lay.lock(base + kValBase + 8 * hit + i));
                 ok &= !(l & kLockBit);
                 sum1 += l;
             }
@@ -478,7 +555,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
         if (ok && !put) {
             if (hit >= 0) {
                 r[0] = 0x100u | (uint32_t)hit;
-                for (uint32_t i = 0; i < 8; ++i) r[1 + i] = ld_agent(&stmr[base + kValBase + 8 * hit + i]);
+                for (uint32_t i = 0; i < 8; ++i) r[1 + i] = lay.load(base + kValBase + 8 * hit + i);
                 wb.put(base + kStampBase + hit, tv);
             } else {
                 for (uint32_t i = 0; i < 9; ++i) r[i] = 0u;
@@ -508,21 +585,21 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
             wb.put(base + kStampBase + victim, tv);
             wb.put(base + kSetStamp, tv);
         }
-        if (ok && wb.n) ok = wb.lock_all(locks, sh);
+        if (ok && wb.n) ok = wb.lock_all(lay);
         hw_order();
         uint32_t ticket = wave_fetch_add(&a->hot->ticket.v, ok);
         hw_order();
         if (ok) {
             uint64_t sum2 = 0;
-            for (uint32_t j = 0; j < nh && ok; ++j) sum2 += reread(locks, (base + header_word(j)) >> sh, sh, wb, ok);
+            for (uint32_t j = 0; j < nh && ok; ++j) sum2 += reread(lay, base + header_word(j), wb, ok);
             if (get_hit)
-                for (uint32_t i = 0; i < 8 && ok; ++i)
-                    sum2 += reread(locks, (base + kValBase + 8 * hit + i) >> sh, sh, wb, ok);
+                for (uint32_t i = 0; i < 8 && ok; ++i) sum2 += reread(lay, base + kValBase + 8 * hit + i, wb, ok);
             ok &= sum2 == sum1;
         }
-        if (ok) wb.write_back(stmr);
-        hw_order();
-        if (wb.locked) wb.release(locks, sh, ok);
+        if (ok)
+            wb.commit(lay);
+        else if (wb.locked)
+            wb.abort(lay);
         if (ok) {
             for (uint32_t j = 0; j < nh; ++j) rs_mark(rs, div32(base + header_word(j), G));
             if (get_hit)
@@ -542,19 +619,29 @@ __global__ void k_begin_batch(const DevArgs *__restrict__ a) {
 
 
 hipError_t exec_prepare(uint32_t max_ops) {
-    return hipFuncSetAttribute((const void *)k_exec_oplist, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)oplist_lds_bytes(max_ops));
+    const int lds = (int)oplist_lds_bytes(max_ops);
+    hipError_t e = hipFuncSetAttribute((const void *)k_exec_oplist<Slot>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_exec_oplist<Split<uint32_t>>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               lds);
 }
 
-void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, hipStream_t s) {
+void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, bool slot, hipStream_t s) {
     hipLaunchKernelGGL(k_begin_batch, dim3(1), dim3(64), 0, s, a);
     dim3 grid(workgroups), block(kExecWaves * kWave);
-    if (program == HETM_PROG_OPLIST)
-        hipLaunchKernelGGL(k_exec_oplist, grid, block, oplist_lds_bytes(max_ops), s, a);
-    else if (program == HETM_PROG_TRANSFER)
+    const uint32_t lds = oplist_lds_bytes(max_ops);
+    if (program == HETM_PROG_OPLIST) {
+        if (slot)
+            hipLaunchKernelGGL(k_exec_oplist<Slot>, grid, block, lds, s, a);
+        else
+            hipLaunchKernelGGL(k_exec_oplist<Split<uint32_t>>, grid, block, lds, s, a);
+    } else if (program == HETM_PROG_TRANSFER) {
         hipLaunchKernelGGL(k_exec_transfer, grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL(k_exec_cache, grid, block, 0, s, a);
+    } else if (slot) {
+        hipLaunchKernelGGL(k_exec_cache<Slot>, grid, block, 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_exec_cache<Split<uint32_t>>, grid, block, 0, s, a);
+    }
 }
 
 }  // namespace hetm

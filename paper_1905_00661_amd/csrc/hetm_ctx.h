@@ -22,6 +22,7 @@ struct hetm_ctx {
     uint32_t log_entry_bytes = 16;
 
     // device state
+    bool slot = false;                 // u32 words in the slot layout (stmr holds N u64 slots, no lock table)
     void *stmr = nullptr;
     uint64_t *locks = nullptr;
     uint64_t *ts = nullptr;

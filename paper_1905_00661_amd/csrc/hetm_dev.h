@@ -92,6 +92,7 @@ struct DevArgs {
     Div32 gdiv;             // division by G
     uint64_t n_words;
     uint32_t word_bytes;
+    uint32_t word_shift;    // 1 in the slot layout: word w's value is u32 number 2w of the replica
     uint32_t granule;       // G
     uint32_t stripe_shift;  // log2(S)
     uint32_t n_granules;    // ceil(N/G)
@@ -217,7 +218,9 @@ __device__ __forceinline__ void rs_mark(uint8_t *rs, uint32_t g) {
 void launch_set_args(const DevArgs &host_copy, DevArgs *dev, hipStream_t s);
 const void *set_args_kernel();   // host handle of the argument-upload kernel
 void launch_clear_error(DevCounters *cnt, hipStream_t s);
-void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, hipStream_t s);
+// slot: the context keeps u32 words in the slot layout (value, version and
+// lock in one u64 per word) instead of a value array plus a lock table
+void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, bool slot, hipStream_t s);
 // allows the OPLIST kernel the dynamic LDS a context's max_ops needs
 hipError_t exec_prepare(uint32_t max_ops);
 // dynamic LDS of the OPLIST transaction kernel: each lane's word list
@@ -225,13 +228,16 @@ constexpr uint32_t oplist_lds_bytes(uint32_t max_ops) { return kExecWaves * max_
 void launch_validate(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);
 void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s);
-void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
+void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, bool slot, hipStream_t s);
 void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_rs_words, hipStream_t s);
 void launch_early_validate(const void *log, uint64_t n, uint32_t word_bytes, const uint8_t *rs, Div32 gdiv,
                            uint64_t n_words, uint32_t epoch, DevCounters *cnt, hipStream_t s);
-void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s);
+void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, bool slot,
+                   hipStream_t s);
 void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uint32_t *count, uint64_t n_words,
-                    uint32_t granule, uint32_t word_bytes, hipStream_t s);
+                    uint32_t granule, uint32_t word_bytes, bool slot, hipStream_t s);
+void launch_to_slots(const uint32_t *src, uint64_t *slots, uint64_t n, hipStream_t s);
+void launch_from_slots(const uint64_t *slots, uint32_t *dst, uint64_t n, hipStream_t s);
 
 constexpr uint32_t kScanWordsPerBlock = 2048;   // bitmap words per compaction block
 constexpr uint32_t kScanThreads = 256;

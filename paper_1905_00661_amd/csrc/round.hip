@@ -157,6 +157,7 @@ __global__ __launch_bounds__(256) void k_apply_max(const DevArgs *__restrict__ a
     const uint64_t floor_ts = ld_agent(&cnt->floor_ts);
     uint64_t *ts = a->ts;
     Word *stmr = (Word *)a->stmr;
+    const uint32_t wsh = a->word_shift;      // slot layout: a word's value sits at u32 index 2w
     uint32_t *tie = a->suspect, *multi = a->multi;
     const uint32_t nw = (uint32_t)((n + 31) / 32);
     const uint32_t lane = lane_id();
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(256) void k_apply_max(const DevArgs *__restrict__ a
             const uint64_t old = __hip_atomic_fetch_max(&ts[e.word], (uint64_t)e.ts, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
             if (old <= floor_ts)
-                stmr[e.word] = (Word)e.value;
+                stmr[(uint64_t)e.word << wsh] = (Word)e.value;
             else
                 m = true;
             t = old == e.ts;
@@ -198,6 +199,7 @@ __global__ __launch_bounds__(256) void k_apply_store(const DevArgs *__restrict__
     const uint64_t *ts = a->ts;
     const uint32_t *tie = a->suspect, *multi = a->multi;
     Word *stmr = (Word *)a->stmr;
+    const uint32_t wsh = a->word_shift;      // slot layout: a word's value sits at u32 index 2w
     const uint64_t nwords = (n + 31) / 32;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < nwords; w += stride) {
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(256) void k_apply_store(const DevArgs *__restrict__
             if ((t >> b) & 1u)
                 latch_error(cnt, HETM_EORDER, (uint32_t)k);
             else
-                stmr[e.word] = (Word)e.value;
+                stmr[(uint64_t)e.word << wsh] = (Word)e.value;
         }
     }
 }
@@ -332,8 +334,9 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_emit(const DevArgs *__
 
 // --------------------------------------------------------------------- copy
 // Moves the dirty granules in units of U bytes (16 when granules are whole
-// multiples of 16 bytes, else one word); upg = units per granule.
-template <typename U>
+// multiples of 16 bytes, else one word); upg = units per granule.  DS = 1:
+// the replica is in the slot layout, unit (word) pos sits at u32 index 2 pos.
+template <typename U, int DS>
 __global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uint32_t upg, uint64_t total_units) {
     DevCounters *cnt = a->cnt;
     if (ld_agent(&cnt->error)) return;
@@ -349,9 +352,9 @@ __global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uin
         const uint64_t pos = (uint64_t)ids[i] * upg + j;
         if (pos >= total_units) continue;
         if (outcome)
-            dev[pos] = host[pos];
+            dev[pos << DS] = host[pos];
         else
-            host[pos] = dev[pos];
+            host[pos] = dev[pos << DS];
     }
 }
 
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uin
 // gather: the round's dirty ids and count are staged always; on success the
 // granules themselves are packed into the staging buffer (a conflict leaves
 // the restore to the host side, after the previous copy has landed).
-template <typename U>
+template <typename U, int DS>
 __global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, uint32_t upg, uint64_t total_units) {
     DevCounters *cnt = a->cnt;
     if (ld_agent(&cnt->error)) return;
@@ -377,14 +380,14 @@ __global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, u
     for (uint64_t u = t0; u < work; u += stride) {
         const uint64_t i = u / upg, j = u - i * upg;
         const uint64_t pos = (uint64_t)ids[i] * upg + j;
-        if (pos < total_units) stg[u] = dev[pos];
+        if (pos < total_units) stg[u] = dev[pos << DS];
     }
 }
 
 // Restore after a conflicting double-buffered round (CPU wins): the staged
 // dirty granule ids are copied from the host replica back into the GPU
 // replica.
-template <typename U>
+template <typename U, int DS>
 __global__ __launch_bounds__(256) void k_restore(U *stmr, const U *host, const uint32_t *ids, const uint32_t *count,
                                                  uint32_t upg, uint64_t total_units) {
     const uint64_t D = ld_agent(count);
@@ -393,8 +396,18 @@ __global__ __launch_bounds__(256) void k_restore(U *stmr, const U *host, const u
     for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < work; u += stride) {
         const uint64_t i = u / upg, j = u - i * upg;
         const uint64_t pos = (uint64_t)ld_agent(&ids[i]) * upg + j;
-        if (pos < total_units) stmr[pos] = host[pos];
+        if (pos < total_units) stmr[pos << DS] = host[pos];
     }
+}
+
+// Slot layout <-> plain words (initial image in, state out).
+__global__ __launch_bounds__(256) void k_to_slots(const uint32_t *src, uint64_t *slots, uint64_t n) {
+    for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < n; w += (uint64_t)gridDim.x * blockDim.x)
+        slots[w] = src[w];
+}
+__global__ __launch_bounds__(256) void k_from_slots(const uint64_t *slots, uint32_t *dst, uint64_t n) {
+    for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < n; w += (uint64_t)gridDim.x * blockDim.x)
+        dst[w] = (uint32_t)slots[w];
 }
 
 // ------------------------------------------------------------------- finish
@@ -500,19 +513,20 @@ void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_compact_emit, dim3(n_scan_blocks), dim3(kScanThreads), 0, s, a);
 }
 
-void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s) {
+void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, bool slot, hipStream_t s) {
     const uint64_t gbytes = (uint64_t)granule * word_bytes;
     const uint64_t n_granules = (n_words + granule - 1) / granule;
-    if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0) {
+    const uint32_t wgrid = stream_grid(n_granules * granule, 256, 16384);
+    if (slot) {
+        hipLaunchKernelGGL((k_copy<uint32_t, 1>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
+    } else if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0) {
         const uint32_t upg = (uint32_t)(gbytes / 16);
         const uint32_t grid = stream_grid(n_granules * upg, 256, 16384);
-        hipLaunchKernelGGL(k_copy<uint4>, dim3(grid), dim3(256), 0, s, a, upg, n_words * word_bytes / 16);
+        hipLaunchKernelGGL((k_copy<uint4, 0>), dim3(grid), dim3(256), 0, s, a, upg, n_words * word_bytes / 16);
     } else if (word_bytes == 4) {
-        const uint32_t grid = stream_grid(n_granules * granule, 256, 16384);
-        hipLaunchKernelGGL(k_copy<uint32_t>, dim3(grid), dim3(256), 0, s, a, granule, n_words);
+        hipLaunchKernelGGL((k_copy<uint32_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
     } else {
-        const uint32_t grid = stream_grid(n_granules * granule, 256, 16384);
-        hipLaunchKernelGGL(k_copy<uint64_t>, dim3(grid), dim3(256), 0, s, a, granule, n_words);
+        hipLaunchKernelGGL((k_copy<uint64_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
     }
 }
 
@@ -527,35 +541,47 @@ void launch_early_validate(const void *log, uint64_t n, uint32_t word_bytes, con
                            n_words, epoch, cnt);
 }
 
-void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, hipStream_t s) {
+void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, bool slot,
+                   hipStream_t s) {
     const uint64_t gbytes = (uint64_t)granule * word_bytes;
     const uint64_t n_granules = (n_words + granule - 1) / granule;
-    if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0) {
+    const uint32_t wgrid = stream_grid(n_granules * granule, 256, 16384);
+    if (slot) {
+        hipLaunchKernelGGL((k_gather<uint32_t, 1>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
+    } else if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0) {
         const uint32_t upg = (uint32_t)(gbytes / 16);
-        hipLaunchKernelGGL(k_gather<uint4>, dim3(stream_grid(n_granules * upg, 256, 16384)), dim3(256), 0, s, a, upg,
-                           n_words * word_bytes / 16);
+        hipLaunchKernelGGL((k_gather<uint4, 0>), dim3(stream_grid(n_granules * upg, 256, 16384)), dim3(256), 0, s, a,
+                           upg, n_words * word_bytes / 16);
     } else if (word_bytes == 4) {
-        hipLaunchKernelGGL(k_gather<uint32_t>, dim3(stream_grid(n_granules * granule, 256, 16384)), dim3(256), 0, s, a,
-                           granule, n_words);
+        hipLaunchKernelGGL((k_gather<uint32_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
     } else {
-        hipLaunchKernelGGL(k_gather<uint64_t>, dim3(stream_grid(n_granules * granule, 256, 16384)), dim3(256), 0, s, a,
-                           granule, n_words);
+        hipLaunchKernelGGL((k_gather<uint64_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
     }
 }
 
 void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uint32_t *count, uint64_t n_words,
-                    uint32_t granule, uint32_t word_bytes, hipStream_t s) {
+                    uint32_t granule, uint32_t word_bytes, bool slot, hipStream_t s) {
     const uint32_t grid = 4096;
     const uint64_t gbytes = (uint64_t)granule * word_bytes;
-    if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0)
-        hipLaunchKernelGGL(k_restore<uint4>, dim3(grid), dim3(256), 0, s, (uint4 *)stmr, (const uint4 *)host, ids,
+    if (slot)
+        hipLaunchKernelGGL((k_restore<uint32_t, 1>), dim3(grid), dim3(256), 0, s, (uint32_t *)stmr,
+                           (const uint32_t *)host, ids, count, granule, n_words);
+    else if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0)
+        hipLaunchKernelGGL((k_restore<uint4, 0>), dim3(grid), dim3(256), 0, s, (uint4 *)stmr, (const uint4 *)host, ids,
                            count, (uint32_t)(gbytes / 16), n_words * word_bytes / 16);
     else if (word_bytes == 4)
-        hipLaunchKernelGGL(k_restore<uint32_t>, dim3(grid), dim3(256), 0, s, (uint32_t *)stmr, (const uint32_t *)host,
-                           ids, count, granule, n_words);
+        hipLaunchKernelGGL((k_restore<uint32_t, 0>), dim3(grid), dim3(256), 0, s, (uint32_t *)stmr,
+                           (const uint32_t *)host, ids, count, granule, n_words);
     else
-        hipLaunchKernelGGL(k_restore<uint64_t>, dim3(grid), dim3(256), 0, s, (uint64_t *)stmr, (const uint64_t *)host,
-                           ids, count, granule, n_words);
+        hipLaunchKernelGGL((k_restore<uint64_t, 0>), dim3(grid), dim3(256), 0, s, (uint64_t *)stmr,
+                           (const uint64_t *)host, ids, count, granule, n_words);
+}
+
+void launch_to_slots(const uint32_t *src, uint64_t *slots, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_slots, dim3(stream_grid(n, 256, 16384)), dim3(256), 0, s, src, slots, n);
+}
+void launch_from_slots(const uint64_t *slots, uint32_t *dst, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_from_slots, dim3(stream_grid(n, 256, 16384)), dim3(256), 0, s, slots, dst, n);
 }
 
 void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_rs_words, hipStream_t s) {
