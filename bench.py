@@ -38,13 +38,15 @@ def log(*a):
 
 
 def exec_alg_bytes(batch) -> float:
-    """Algorithmic bytes the execution kernel must move for a batch (per
-    transaction: offsets 8 B, n_writes 1 B, tid 4 B, ticket 4 B; per read:
-    index 4 B, lock word read twice 16 B, value 4 B, result 4 B; per write:
-    lock load 8 B, lock CAS 16 B, value 4 B, unlock 16 B)."""
+    """Algorithmic bytes the execution kernel moves for a batch of u32 words
+    in the slot layout (value, version and lock in one u64 per word): per
+    transaction, offsets 8 B, n_writes 1 B, tid 4 B, ticket 4 B; per read,
+    index 4 B, the slot read before and after the commit ticket 16 B, the
+    result 4 B; per write, the slot read and CAS-locked 24 B, re-read and
+    stored with the new value 16 B."""
     L = np.diff(batch.offsets.astype(np.int64))
     nw = batch.n_writes.astype(np.int64)
-    return float(batch.n * 17 + L.sum() * 28 + nw.sum() * 44)
+    return float(batch.n * 17 + L.sum() * 24 + nw.sum() * 40)
 
 
 VALIDATE_APPLY_BYTES_PER_ENTRY = 40.0   # 16 B entry + 4 B bitmap + 8+8 B TS + 4 B value
