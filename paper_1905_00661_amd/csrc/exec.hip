@@ -38,19 +38,19 @@ namespace {
 // stripe(w) its identity, load(w) a device-coherent read of the value.
 template <typename Word>
 struct Split {
-    Word *vals;
-    uint64_t *locks;
+    gmem<Word> *vals;
+    gmem<uint64_t> *locks;
     uint32_t sh;
     static constexpr bool kFused = false;
-    __device__ uint64_t *lock(uint32_t w) const { return &locks[w >> sh]; }
+    __device__ gmem<uint64_t> *lock(uint32_t w) const { return &locks[w >> sh]; }
     __device__ uint32_t stripe(uint32_t w) const { return w >> sh; }
     __device__ Word load(uint32_t w) const { return ld_agent(&vals[w]); }
 };
 
 struct Slot {
-    uint64_t *slots;
+    gmem<uint64_t> *slots;
     static constexpr bool kFused = true;
-    __device__ uint64_t *lock(uint32_t w) const { return &slots[w]; }
+    __device__ gmem<uint64_t> *lock(uint32_t w) const { return &slots[w]; }
     __device__ uint32_t stripe(uint32_t w) const { return w; }
     __device__ uint32_t load(uint32_t w) const { return (uint32_t)ld_agent(&slots[w]); }
     // a slot without its lock bit: version above, value below
@@ -95,7 +95,7 @@ struct WriteBuf {
                 }
             }
             if (kmin == n) return true;
-            uint64_t *p = lay.lock(at(kmin));
+            gmem<uint64_t> *p = lay.lock(at(kmin));
             uint64_t cur = ld_agent(p);
             if ((cur & kLockBit) || !cas_agent(p, cur, cur | kLockBit)) {
                 abort(lay);
@@ -132,14 +132,17 @@ struct WriteBuf {
         locked = 0;
     }
     __device__ void commit(const Slot &lay) {
-        for (uint32_t k = 0; k < n; ++k) {
-            if (!((locked >> k) & 1u)) continue;
-            uint64_t *p = lay.lock(at(k));
-            st_agent(p, Slot::commit_word(ld_agent(p), (uint32_t)val[k][lane]));
-        }
+        // all slot loads first, then the stores (one memory round trip)
+        uint64_t cur[MAXW];
+#pragma unroll
+        for (uint32_t k = 0; k < (uint32_t)MAXW; ++k)
+            cur[k] = ((locked >> k) & 1u) ? ld_agent(lay.lock(at(k))) : 0;
+#pragma unroll
+        for (uint32_t k = 0; k < (uint32_t)MAXW; ++k)
+            if ((locked >> k) & 1u) st_agent(lay.lock(at(k)), Slot::commit_word(cur[k], (uint32_t)val[k][lane]));
         locked = 0;
     }
-    __device__ void mark_writes(uint8_t *rs, uint32_t *ws, const Div32 &G) {
+    __device__ void mark_writes(gmem<uint8_t> *rs, gmem<uint32_t> *ws, const Div32 &G) {
         for (uint32_t k = 0; k < n; ++k) {
             uint32_t g = div32(at(k), G);
             rs_mark(rs, g);
@@ -267,15 +270,15 @@ template <typename Lay>
 __device__ __forceinline__ Lay make_layout(const DevArgs *a);
 template <>
 __device__ __forceinline__ Slot make_layout<Slot>(const DevArgs *a) {
-    return Slot{(uint64_t *)a->stmr};
+    return Slot{glob((uint64_t *)a->stmr)};
 }
 template <>
 __device__ __forceinline__ Split<uint32_t> make_layout<Split<uint32_t>>(const DevArgs *a) {
-    return Split<uint32_t>{(uint32_t *)a->stmr, a->locks, a->stripe_shift};
+    return Split<uint32_t>{glob((uint32_t *)a->stmr), glob(a->locks), a->stripe_shift};
 }
 template <>
 __device__ __forceinline__ Split<uint64_t> make_layout<Split<uint64_t>>(const DevArgs *a) {
-    return Split<uint64_t>{(uint64_t *)a->stmr, a->locks, a->stripe_shift};
+    return Split<uint64_t>{glob((uint64_t *)a->stmr), glob(a->locks), a->stripe_shift};
 }
 
 // ------------------------------------------------------------------ OPLIST
@@ -284,6 +287,13 @@ __device__ __forceinline__ Split<uint64_t> make_layout<Split<uint64_t>>(const De
 // An attempt loads its word list from HBM once, into LDS ([op][lane] per
 // wave, max_ops x 64 dwords, dynamic), and every later pass -- lock words,
 // values, revalidation, bitmaps -- reads it from there.
+// Memory accesses of a pass go out in chunks of kChunk independent loads
+// before any result is used, so a lane keeps kChunk requests in flight
+// instead of waiting out each one in turn.  Lanes past their transaction's
+// length load a word already in the chunk (a cache hit) instead of
+// branching, which keeps the loads in one straight-line block.
+constexpr uint32_t kChunk = 8;
+
 template <typename Lay>
 __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs *__restrict__ a) {
     __shared__ uint32_t s_addr[kExecWaves][kOplistMaxWrites][kWave];
@@ -291,15 +301,15 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     extern __shared__ uint32_t s_dyn[];
     const uint32_t wv = threadIdx.x / kWave;
     const Lay lay = make_layout<Lay>(a);
-    uint8_t *rs = a->rs;
-    uint32_t *ws = a->ws;
+    gmem<uint8_t> *rs = glob(a->rs);
+    gmem<uint32_t> *ws = glob(a->ws);
     DevCounters *cnt = a->cnt;
     const uint32_t n = a->n_txns, max_ops = a->max_ops;
     const Div32 G = a->gdiv;
     const uint64_t N = a->n_words;
-    const uint32_t *off = a->off, *idx = a->idx, *tid = a->tid;
-    const uint8_t *nw = a->nw;
-    uint32_t *res = (uint32_t *)a->results;
+    const gmem<uint32_t> *off = glob(a->off), *idx = glob(a->idx), *tid = glob(a->tid);
+    const gmem<uint8_t> *nw = glob(a->nw);
+    gmem<uint32_t> *res = glob((uint32_t *)a->results);
     WriteBuf<uint32_t, kOplistMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
     uint32_t *ix = s_dyn + wv * max_ops * kWave + lane_id();     // ix[j * kWave]: word j of this lane's txn
     const uint32_t epoch = a->epoch;
@@ -321,12 +331,18 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
             tv = tid[ls.txn];
             L = e - o;
             malformed = e < o || L > max_ops || nwr > L || nwr > kOplistMaxWrites;
-            if (!malformed) {
-                for (uint32_t j = 0; j < L; ++j) {
-                    const uint32_t w = idx[o + j];
-                    ix[j * kWave] = w;
-                    malformed |= w >= N;
-                }
+            if (malformed) L = 0;
+            // the word list, into LDS
+            for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
+                uint32_t w[kChunk];
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k) w[k] = idx[o + (j0 + k < L ? j0 + k : j0)];
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k)
+                    if (j0 + k < L) {
+                        ix[(j0 + k) * kWave] = w[k];
+                        malformed |= w[k] >= N;
+                    }
             }
             if (malformed) {
                 latch_error(cnt, HETM_EINVAL, ls.txn);
@@ -338,30 +354,55 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
         uint64_t sum1 = 0;
         if (Lay::kFused) {
             // one load per read: value and version together
-            for (uint32_t j = 0; j < L; ++j) {
-                const uint32_t w = ix[j * kWave];
-                const uint64_t l = ld_agent(lay.lock(w));
-                ok &= !(l & kLockBit);
-                sum1 += l;
-                const uint32_t v = (uint32_t)l;
-                res[o + j] = v;
-                if (j < nwr) wb.put(w, v + tv);
+            for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
+                uint32_t w[kChunk];
+                uint64_t l[kChunk];
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k) w[k] = ix[(j0 + k < L ? j0 + k : j0) * kWave];
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k) l[k] = ld_agent(lay.lock(w[k]));
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k) {
+                    const uint32_t j = j0 + k;
+                    if (j < L) {
+                        ok &= !(l[k] & kLockBit);
+                        sum1 += l[k];
+                        const uint32_t v = (uint32_t)l[k];
+                        res[o + j] = v;
+                        if (j < nwr) wb.put(w[k], v + tv);
+                    }
+                }
             }
             if (ok && nwr) ok = wb.lock_all(lay);
         } else {
             // first pass over the read stripes, then the values
-            for (uint32_t j = 0; j < L; ++j) {
-                uint64_t l = ld_agent(lay.lock(ix[j * kWave]));
-                ok &= !(l & kLockBit);
-                sum1 += l;
+            for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
+                uint64_t l[kChunk];
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k) l[k] = ld_agent(lay.lock(ix[(j0 + k < L ? j0 + k : j0) * kWave]));
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k)
+                    if (j0 + k < L) {
+                        ok &= !(l[k] & kLockBit);
+                        sum1 += l[k];
+                    }
             }
             hw_order();
             if (ok) {
-                for (uint32_t j = 0; j < L; ++j) {
-                    uint32_t w = ix[j * kWave];
-                    uint32_t v = lay.load(w);
-                    res[o + j] = v;
-                    if (j < nwr) wb.put(w, v + tv);
+                for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
+                    uint32_t w[kChunk], v[kChunk];
+#pragma unroll
+                    for (uint32_t k = 0; k < kChunk; ++k) w[k] = ix[(j0 + k < L ? j0 + k : j0) * kWave];
+#pragma unroll
+                    for (uint32_t k = 0; k < kChunk; ++k) v[k] = lay.load(w[k]);
+#pragma unroll
+                    for (uint32_t k = 0; k < kChunk; ++k) {
+                        const uint32_t j = j0 + k;
+                        if (j < L) {
+                            res[o + j] = v[k];
+                            if (j < nwr) wb.put(w[k], v[k] + tv);
+                        }
+                    }
                 }
                 if (nwr) ok = wb.lock_all(lay);
             }
@@ -370,8 +411,25 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
         uint32_t ticket = wave_fetch_add(&a->hot->ticket.v, ok);
         hw_order();
         if (ok) {
+            // revalidation: reload every read word's lock word
             uint64_t sum2 = 0;
-            for (uint32_t j = 0; j < L && ok; ++j) sum2 += reread(lay, ix[j * kWave], wb, ok);
+            for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
+                uint32_t w[kChunk];
+                uint64_t l[kChunk];
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k) w[k] = ix[(j0 + k < L ? j0 + k : j0) * kWave];
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k) l[k] = ld_agent(lay.lock(w[k]));
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k)
+                    if (j0 + k < L) {
+                        if (l[k] & kLockBit) {
+                            if (!wb.mine(lay, lay.stripe(w[k]))) ok = false;
+                            l[k] &= ~kLockBit;
+                        }
+                        sum2 += l[k];
+                    }
+            }
             ok &= sum2 == sum1;
         }
         if (ok)
@@ -379,7 +437,18 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
         else if (wb.locked)
             wb.abort(lay);
         if (ok) {
-            for (uint32_t j = nwr; j < L; ++j) rs_mark(rs, div32(ix[j * kWave], G));
+            // read-set marks: test every granule of the chunk, then store where clear
+            for (uint32_t j0 = nwr; j0 < L; j0 += kChunk) {
+                uint32_t g[kChunk];
+                uint8_t b[kChunk];
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k) g[k] = div32(ix[(j0 + k < L ? j0 + k : j0) * kWave], G);
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k) b[k] = rs[g[k]];
+#pragma unroll
+                for (uint32_t k = 0; k < kChunk; ++k)
+                    if (j0 + k < L && !b[k]) st_agent(&rs[g[k]], (uint8_t)1);
+            }
             wb.mark_writes(rs, ws, G);
         }
         settle(ls, act, malformed, ok, ticket, a->tickets, cnt, a->retry_cap);
@@ -395,8 +464,8 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
     __shared__ uint64_t s_val[kExecWaves][2][kWave];
     const uint32_t wv = threadIdx.x / kWave;
     const Split<uint64_t> lay = make_layout<Split<uint64_t>>(a);
-    uint8_t *rs = a->rs;
-    uint32_t *ws = a->ws;
+    gmem<uint8_t> *rs = glob(a->rs);
+    gmem<uint32_t> *ws = glob(a->ws);
     DevCounters *cnt = a->cnt;
     const uint32_t n = a->n_txns;
     const Div32 G = a->gdiv;
@@ -494,8 +563,8 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
     __shared__ uint32_t s_val[kExecWaves][kCacheMaxWrites][kWave];
     const uint32_t wv = threadIdx.x / kWave;
     const Lay lay = make_layout<Lay>(a);
-    uint8_t *rs = a->rs;
-    uint32_t *ws = a->ws;
+    gmem<uint8_t> *rs = glob(a->rs);
+    gmem<uint32_t> *ws = glob(a->ws);
     DevCounters *cnt = a->cnt;
     const uint32_t n = a->n_txns;
     const Div32 G = a->gdiv;

@@ -144,6 +144,35 @@ __device__ __forceinline__ bool cas_agent(uint64_t *p, uint64_t expect, uint64_t
     return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
 }
+// Global-memory (address space 1) views.  Pointers read out of the argument
+// block are generic, so accesses through them compile to flat instructions,
+// which count against the LDS/scalar counter as well and force a wait on
+// every LDS access between a load and its use; through a global view the
+// same accesses are global instructions that only the vector-memory counter
+// tracks, so a batch of them stays in flight.
+template <typename T>
+using gmem = T __attribute__((address_space(1)));
+template <typename T>
+__device__ __forceinline__ gmem<T> *glob(T *p) {
+    return (gmem<T> *)p;
+}
+template <typename T>
+__device__ __forceinline__ const gmem<T> *glob(const T *p) {
+    return (const gmem<T> *)p;
+}
+template <typename T>
+__device__ __forceinline__ T ld_agent(const gmem<T> *p) {
+    return __hip_atomic_load(const_cast<gmem<T> *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_agent(gmem<T> *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_agent(gmem<uint64_t> *p, uint64_t expect, uint64_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
@@ -209,6 +238,14 @@ __device__ __forceinline__ void bitmap_set(uint32_t *bm, uint32_t g) {
 // batch still runs.
 __device__ __forceinline__ void rs_mark(uint8_t *rs, uint32_t g) {
     if (!rs[g]) st_agent(&rs[g], (uint8_t)1);
+}
+__device__ __forceinline__ void rs_mark(gmem<uint8_t> *rs, uint32_t g) {
+    if (!rs[g]) st_agent(&rs[g], (uint8_t)1);
+}
+__device__ __forceinline__ void bitmap_set(gmem<uint32_t> *bm, uint32_t g) {
+    uint32_t w = g >> 5, b = 1u << (g & 31);
+    uint32_t cur = ld_agent(bm + w);
+    if (!(cur & b)) __hip_atomic_fetch_or(bm + w, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 
