@@ -69,6 +69,18 @@ extern "C" {
  * accumulated during validation instead of a host-supplied one. */
 #define HETM_OUTCOME_DEVICE 0xFFFFFFFFu
 
+/* Inter-device conflict resolution of a round (§IV-E).  CPU_WINS (the
+ * default): the GPU's transactions of the round abort, the host log is
+ * applied and the GPU's dirty granules are restored from the host replica.
+ * GPU_WINS: the host's round is discarded instead -- validation runs over
+ * the whole log first and the log is applied only if it found no conflict;
+ * on a conflict the GPU's transactions commit, TS and the watermark stay
+ * as they were, and the granules written by either side are copied GPU ->
+ * host replica, which undoes the host's writes there (the host must also
+ * discard the rest of its round's effects, e.g. from a shadow copy). */
+#define HETM_POLICY_CPU_WINS 0u
+#define HETM_POLICY_GPU_WINS 1u
+
 typedef struct hetm_ctx hetm_ctx;
 
 typedef struct {
@@ -235,6 +247,8 @@ typedef struct {
     uint32_t   *flags_bits;    /* device, nullable */
     void       *host_replica;  /* pinned host, N*W bytes */
     uint32_t   *ids_out;       /* device, nullable */
+    uint32_t    policy;        /* HETM_POLICY_* (hetm_round only) */
+    uint32_t    pad_;
 } hetm_round_args;
 
 typedef struct {
@@ -254,6 +268,10 @@ typedef struct {
     double   us_validate;
     double   us_merge;
     double   us_total;
+    uint32_t host_discarded;   /* 1: GPU_WINS resolved a conflict against the
+                                  host's round, whose log was not applied      */
+    uint32_t gpu_losses;       /* rounds in a row, this one included, whose GPU
+                                  transactions aborted (starvation signal)     */
 } hetm_round_result;
 
 /* A whole round: execution, validation+apply, merge, reset, in the
@@ -331,7 +349,9 @@ uint64_t hetm_state_bytes(hetm_ctx *ctx, uint32_t what);
  * round at a time through hetm_round (a context without async_merge).
  *
  * A conflicting round is aborted (CPU wins, §IV-E) and its requests are
- * admitted again first; a request's latency runs from its arrival to the
+ * admitted again first.  Starvation guard (§IV-E): with starvation_limit K,
+ * after K aborted rounds in a row the next round to be packed carries no
+ * host writes, so it validates; the host's log waits for the round after; a request's latency runs from its arrival to the
  * commit of the round that executed it successfully.  All arrays are host
  * memory owned by the caller.  Errors: EINVAL, ESTATE (context mode),
  * ECAPACITY (a request larger than the budget), latched device errors. */
@@ -348,7 +368,9 @@ typedef struct {
     uint64_t        max_batch;          /* <= the context's batch_capacity */
     uint64_t        mem_budget_bytes;
     uint32_t        pipelined;
-    uint32_t        pad_;
+    uint32_t        starvation_limit;   /* 0: off; else after this many aborted
+                                           rounds in a row the host holds back
+                                           its writes for one round (§IV-E) */
 } hetm_serve_spec;
 
 typedef struct {
@@ -369,6 +391,7 @@ typedef struct {
        packing, waiting for rounds (round_end), settling results, the host's
        own log commits, waiting for merges, waiting for arrivals */
     double    us_pack, us_wait_round, us_settle, us_host_commit, us_wait_merge, us_idle;
+    uint64_t  starved_rounds;           /* rounds run without host writes by the starvation guard */
 } hetm_serve_report;
 
 int hetm_serve(hetm_ctx *ctx, const hetm_serve_spec *spec, void *host_replica, hetm_serve_report *rep);

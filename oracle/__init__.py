@@ -211,21 +211,43 @@ def host_cache_puts(H: np.ndarray, keys: np.ndarray, ts: np.ndarray) -> np.ndarr
 
 # ---------------------------------------------------------------- whole round
 
+POLICY_CPU_WINS, POLICY_GPU_WINS = 0, 1
+
+
+def log_granules(log: np.ndarray, G: int, N: int) -> np.ndarray:
+    """Bitmap (uint32 words, bit g of word g/32) of the granules the host log
+    writes: the host's write set at granule resolution (§IV-B)."""
+    bm = np.zeros(bitmap_words(n_granules(N, G)), np.uint32)
+    g = log["word"].astype(np.int64) // G
+    np.bitwise_or.at(bm, g >> 5, np.left_shift(np.uint32(1), (g & 31).astype(np.uint32)))
+    return bm
+
+
 def round_generic(replay, S: np.ndarray, H: np.ndarray, TS: np.ndarray, G: int, batch, order, log,
-                  floor: int) -> dict:
+                  floor: int, policy: int = POLICY_CPU_WINS) -> dict:
     """One full round (§IV-C): replay the batch in commit order, validate the
     host log, apply it, merge.  H is the host replica holding the host's own
-    writes of the round.  S, H, TS are updated in place."""
+    writes of the round.  S, H, TS are updated in place.
+
+    policy (§IV-E): CPU_WINS applies the log always and, on a conflict,
+    restores the GPU's written granules from H.  GPU_WINS applies the log
+    only when validation found no conflict; on a conflict the host's round is
+    discarded -- nothing of its log is applied, the watermark stays -- and the
+    granules written by either side go from S to H."""
     res, RS, WS = replay(S, G, batch, order)
     flags, conflict = validate(log, RS, G, S.shape[0])
-    mx = apply(S, TS, log, floor)
-    ids, runs = merge(conflict, WS, G, S, H)
+    if policy == POLICY_GPU_WINS and conflict:
+        mx = floor
+        ids, runs = merge(0, WS | log_granules(log, G, S.shape[0]), G, S, H)
+    else:
+        mx = apply(S, TS, log, floor)
+        ids, runs = merge(conflict, WS, G, S, H)
     return {"results": res, "RS": RS, "WS": WS, "flags": flags, "conflict": conflict,
             "ids": ids, "n_runs": runs, "max_ts": mx}
 
 
-def round_oplist(S, H, TS, G, batch, order, log, floor) -> dict:
-    return round_generic(replay_oplist, S, H, TS, G, batch, order, log, floor)
+def round_oplist(S, H, TS, G, batch, order, log, floor, policy: int = POLICY_CPU_WINS) -> dict:
+    return round_generic(replay_oplist, S, H, TS, G, batch, order, log, floor, policy)
 
 
 def order_from_tickets(tickets: np.ndarray) -> np.ndarray:

@@ -180,21 +180,25 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
 }
 
 void account_round(hetm_ctx *c, const DevCounters &s, uint64_t n_txns, hetm_round_result *res) {
+    const bool gpu_won = s.conflict && c->args.policy == HETM_POLICY_GPU_WINS;
+    const bool gpu_lost = s.conflict && !gpu_won;
     c->stats.rounds++;
-    if (s.conflict) {
-        c->stats.rounds_conflicted++;
+    if (s.conflict) c->stats.rounds_conflicted++;
+    if (gpu_lost)
         c->stats.txns_aborted += s.committed;
-    } else {
+    else
         c->stats.txns_committed += s.committed;
-    }
+    c->gpu_losses = gpu_lost ? c->gpu_losses + 1 : 0;
     c->stats.local_retries += s.retries;
     c->stats.dirty_granules += s.n_dirty;
     c->stats.watermark = s.floor_ts;
     if (res) {
         res->conflict = s.conflict;
         res->error = s.error;
-        res->n_committed = s.conflict ? 0 : s.committed;
-        res->n_aborted = s.conflict ? n_txns : 0;
+        res->n_committed = gpu_lost ? 0 : s.committed;
+        res->n_aborted = gpu_lost ? n_txns : 0;
+        res->host_discarded = gpu_won;
+        res->gpu_losses = c->gpu_losses;
         res->n_local_retries = s.retries;
         res->n_dirty = s.n_dirty;
         res->n_runs = s.n_runs;
@@ -322,6 +326,8 @@ namespace hetm {
 int round_begin(hetm_ctx *c, const hetm_round_args *r) {
     if (c->cfg.mode != HETM_MODE_GRAPH) return fail(c, HETM_ESTATE, "round_begin needs GRAPH mode");
     if (c->in_validation || c->round_open) return fail(c, HETM_ESTATE, "a round is already open");
+    if (r->policy > HETM_POLICY_GPU_WINS) return fail(c, HETM_EINVAL, "bad policy %u", r->policy);
+    c->args.policy = r->policy;
     if (r->n_log > c->cfg.log_capacity) return fail(c, HETM_ECAPACITY, "log %llu > capacity", (unsigned long long)r->n_log);
     if (r->n_log && !r->log) return fail(c, HETM_EINVAL, "null log");
     const void *hdev = nullptr;
@@ -391,8 +397,8 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     if (snap.error) return take_device_error(c, snap.error, snap.err_index);
     c->round_merge_seq = 0;
     if (c->cfg.async_merge) {
-        if (!snap.conflict) {
-            // success: DMA the staged granules to pinned host staging on the
+        if (!snap.conflict || c->args.policy == HETM_POLICY_GPU_WINS) {
+            // the GPU's granules go to the host replica: DMA the staged granules to pinned host staging on the
             // copy stream; the merge worker scatters them into the host replica
             if ((rc = stage_to_host(c, b, snap.n_dirty))) return rc;
             c->pending[b] = true;
@@ -640,6 +646,7 @@ int hetm_submit_batch(hetm_ctx *c, uint32_t program, const void *descs, uint64_t
                       uint32_t *tickets) {
     if (!c) return HETM_EINVAL;
     if (c->in_validation) return fail(c, HETM_ESTATE, "submit after validation started in this round");
+    c->args.policy = HETM_POLICY_CPU_WINS;     // the step API applies each chunk as it comes
     if (n_txns == 0) return HETM_OK;
     int rc = set_batch_args(c, program, descs, n_txns, results, tickets);
     if (rc) return rc;
@@ -654,6 +661,7 @@ int hetm_validate_apply_log(hetm_ctx *c, const void *log, uint64_t n, uint32_t *
     if (n > c->cfg.log_capacity) return fail(c, HETM_ECAPACITY, "log chunk %llu > capacity", (unsigned long long)n);
     if (n && !log) return fail(c, HETM_EINVAL, "null log");
     c->in_validation = true;
+    c->args.policy = HETM_POLICY_CPU_WINS;
     if (n) {
         const void *dlog = nullptr;
         int rc = stage_log(c, log, n, &dlog);
@@ -698,6 +706,8 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
         return hetm::round_end(c, r, res);
     }
     if (c->in_validation) return fail(c, HETM_ESTATE, "hetm_round inside an open round");
+    if (r->policy > HETM_POLICY_GPU_WINS) return fail(c, HETM_EINVAL, "bad policy %u", r->policy);
+    c->args.policy = r->policy;
     if (r->n_log > c->cfg.log_capacity) return fail(c, HETM_ECAPACITY, "log %llu > capacity", (unsigned long long)r->n_log);
     if (r->n_log && !r->log) return fail(c, HETM_EINVAL, "null log");
     const void *hdev = nullptr;

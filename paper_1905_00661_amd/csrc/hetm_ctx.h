@@ -80,6 +80,7 @@ struct hetm_ctx {
     int round_buf = 0;
 
     bool in_validation = false;      // this round's log has started
+    uint32_t gpu_losses = 0;         // rounds in a row whose GPU transactions aborted
     hetm_stats stats{};
     char err[512] = {0};
 };

@@ -125,6 +125,8 @@ struct DevArgs {
     uint32_t *stage_count;  // async merge: their number
     uint32_t outcome;       // 0 / 1 / HETM_OUTCOME_DEVICE
     uint32_t epoch;         // the open round's number, as early validation tags a doomed round
+    uint32_t policy;        // HETM_POLICY_*: who wins an inter-device conflict
+    uint32_t pad2_;
 };
 
 // ------------------------------------------------------------------ atomics

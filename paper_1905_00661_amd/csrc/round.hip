@@ -147,13 +147,23 @@ template <typename E, typename Word>
 __global__ __launch_bounds__(256) void k_apply_max(const DevArgs *__restrict__ a) {
     DevCounters *cnt = a->cnt;
     if (ld_agent(&cnt->error)) return;   // a chunk failing its preconditions applies nothing
+    // GPU_WINS and a conflict: the host's round is discarded, nothing of its
+    // log is applied; its granules join the write set, so the merge copies
+    // the GPU's values over the host's writes
+    const bool discard = a->policy == HETM_POLICY_GPU_WINS && ld_agent(&cnt->chunk_conflict) != 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {   // the chunk counts: fold its outcome into the round's
         if (ld_agent(&cnt->chunk_conflict)) st_agent(&cnt->conflict, 1u);
         const unsigned long long m = ld_agent(&cnt->chunk_max_ts);
-        if (m > ld_agent(&cnt->max_ts)) st_agent(&cnt->max_ts, m);
+        if (!discard && m > ld_agent(&cnt->max_ts)) st_agent(&cnt->max_ts, m);
     }
     const E *log = (const E *)a->log;
     const uint64_t n = a->n_log;
+    if (discard) {
+        const Div32 G = a->gdiv;
+        for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
+            bitmap_set(a->ws, div32(log[k].word, G));
+        return;
+    }
     const uint64_t floor_ts = ld_agent(&cnt->floor_ts);
     uint64_t *ts = a->ts;
     Word *stmr = (Word *)a->stmr;
@@ -194,6 +204,7 @@ __global__ __launch_bounds__(256) void k_apply_store(const DevArgs *__restrict__
         st_agent(&cnt->chunk_conflict, 0u);
         st_agent(&cnt->chunk_max_ts, 0ull);
     }
+    if (a->policy == HETM_POLICY_GPU_WINS && ld_agent(&cnt->conflict)) return;   // log discarded
     const E *log = (const E *)a->log;
     const uint64_t n = a->n_log;
     const uint64_t *ts = a->ts;
@@ -340,7 +351,8 @@ template <typename U, int DS>
 __global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uint32_t upg, uint64_t total_units) {
     DevCounters *cnt = a->cnt;
     if (ld_agent(&cnt->error)) return;
-    const uint32_t outcome = a->outcome == HETM_OUTCOME_DEVICE ? ld_agent(&cnt->conflict) : a->outcome;
+    const uint32_t conflict = a->outcome == HETM_OUTCOME_DEVICE ? ld_agent(&cnt->conflict) : a->outcome;
+    const bool restore = conflict && a->policy != HETM_POLICY_GPU_WINS;   // else GPU -> host
     const uint64_t D = ld_agent(&cnt->n_dirty);
     const uint32_t *ids = a->ids_scratch;
     U *dev = (U *)a->stmr;
@@ -351,7 +363,7 @@ __global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uin
         const uint64_t i = u / upg, j = u - i * upg;
         const uint64_t pos = (uint64_t)ids[i] * upg + j;
         if (pos >= total_units) continue;
-        if (outcome)
+        if (restore)
             dev[pos << DS] = host[pos];
         else
             host[pos] = dev[pos << DS];
@@ -373,7 +385,7 @@ __global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, u
     const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     for (uint64_t i = t0; i < D; i += stride) a->stage_ids[i] = ids[i];
     if (t0 == 0) *a->stage_count = (uint32_t)D;
-    if (outcome) return;
+    if (outcome && a->policy != HETM_POLICY_GPU_WINS) return;   // restored from the host instead
     const U *dev = (const U *)a->stmr;
     U *stg = (U *)a->staging;
     const uint64_t work = D * upg;

@@ -69,6 +69,8 @@ struct Serve {
     uint64_t head = 0;            // next request not yet admitted
     uint64_t log_pos = 0;         // host log entries consumed
     uint64_t round_no = 0;
+    uint32_t losses = 0;          // aborted rounds in a row
+    bool starve_next = false;     // the next packed round carries no host writes
     uint64_t max_ops_round = 0;
     std::vector<double> latency_us;
     std::vector<uint64_t> pos_of;  // request -> first op in spec CSR
@@ -170,6 +172,11 @@ struct Serve {
             }
         });
         r.n_log = std::min<uint64_t>(sp.host_log_per_round, sp.host_log_len - log_pos);
+        if (starve_next) {       // the GPU lost too often: hold the host's writes back one round
+            r.n_log = 0;
+            starve_next = false;
+            rep->starved_rounds++;
+        }
         if (r.n_log) memcpy(r.h_log, sp.host_log + log_pos, r.n_log * sizeof(hetm_log_entry4));
         log_pos += r.n_log;
         r.log_end = log_pos;
@@ -225,6 +232,11 @@ struct Serve {
         if (rep->round_conflict && rn < rep->max_rounds) rep->round_conflict[rn] = res.conflict ? 1 : 0;
         if (rep->round_log_end && rn < rep->max_rounds) rep->round_log_end[rn] = r.log_end;
         rep->rounds++;
+        losses = res.conflict ? losses + 1 : 0;
+        if (sp.starvation_limit && losses >= sp.starvation_limit) {
+            starve_next = true;
+            losses = 0;
+        }
         if (res.conflict) {
             rep->conflicted_rounds++;
             rep->requeued += r.reqs.size();

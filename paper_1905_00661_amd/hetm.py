@@ -26,6 +26,7 @@ HETM_ECAPACITY, HETM_EDEVICE, HETM_ERETRY, HETM_ESTATE = -4, -5, -6, -7
 HETM_PROG_OPLIST, HETM_PROG_TRANSFER, HETM_PROG_CACHE = 1, 2, 3
 HETM_MODE_PLAIN, HETM_MODE_GRAPH = 0, 1
 HETM_OUTCOME_DEVICE = 0xFFFFFFFF
+HETM_POLICY_CPU_WINS, HETM_POLICY_GPU_WINS = 0, 1
 HETM_STATE_STMR, HETM_STATE_TS, HETM_STATE_RS, HETM_STATE_WS, HETM_STATE_LOCKS = 0, 1, 2, 3, 4
 
 EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_apply_log",
@@ -59,14 +60,16 @@ class hetm_cache_desc(ctypes.Structure):
 
 class hetm_round_args(ctypes.Structure):
     _fields_ = [("program", U32), ("descs", P), ("n_txns", U64), ("results", P), ("tickets", P),
-                ("log", P), ("n_log", U64), ("flags_bits", P), ("host_replica", P), ("ids_out", P)]
+                ("log", P), ("n_log", U64), ("flags_bits", P), ("host_replica", P), ("ids_out", P),
+                ("policy", U32), ("pad_", U32)]
 
 
 class hetm_round_result(ctypes.Structure):
     _fields_ = [("conflict", U32), ("error", I32), ("n_committed", U64), ("n_aborted", U64),
                 ("n_local_retries", U64), ("n_dirty", U64), ("n_runs", U64), ("max_ts", U64),
                 ("merge_pending", U32), ("doomed", U32), ("us_exec", ctypes.c_double), ("us_validate", ctypes.c_double),
-                ("us_merge", ctypes.c_double), ("us_total", ctypes.c_double)]
+                ("us_merge", ctypes.c_double), ("us_total", ctypes.c_double),
+                ("host_discarded", U32), ("gpu_losses", U32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -75,7 +78,7 @@ class hetm_round_result(ctypes.Structure):
 class hetm_serve_spec(ctypes.Structure):
     _fields_ = [("n_requests", U64), ("arrival_s", P), ("offsets", P), ("idx", P), ("n_writes", P), ("tid", P),
                 ("host_log", P), ("host_log_len", U64), ("host_log_per_round", U64), ("max_batch", U64),
-                ("mem_budget_bytes", U64), ("pipelined", U32), ("pad_", U32)]
+                ("mem_budget_bytes", U64), ("pipelined", U32), ("starvation_limit", U32)]
 
 
 class hetm_serve_report(ctypes.Structure):
@@ -85,7 +88,8 @@ class hetm_serve_report(ctypes.Structure):
                 ("max_latency_us", ctypes.c_double), ("latency_us", P), ("results", P), ("commit_seq", P),
                 ("round_conflict", P), ("max_rounds", U64), ("round_log_end", P),
                 ("us_pack", ctypes.c_double), ("us_wait_round", ctypes.c_double), ("us_settle", ctypes.c_double),
-                ("us_host_commit", ctypes.c_double), ("us_wait_merge", ctypes.c_double), ("us_idle", ctypes.c_double)]
+                ("us_host_commit", ctypes.c_double), ("us_wait_merge", ctypes.c_double), ("us_idle", ctypes.c_double),
+                ("starved_rounds", U64)]
 
 
 class hetm_stats(ctypes.Structure):
@@ -395,7 +399,8 @@ class Context:
         return hetm_copyback_dirty(self.ctx, conflict, host.data_ptr(), ids.data_ptr() if ids is not None else None)
 
     def serve(self, arrival_s: np.ndarray, batch, host, host_log: np.ndarray, host_log_per_round: int,
-              max_batch: int, mem_budget_bytes: int, pipelined: bool, max_rounds: int = 1 << 16) -> dict:
+              max_batch: int, mem_budget_bytes: int, pipelined: bool, max_rounds: int = 1 << 16,
+              starvation_limit: int = 0) -> dict:
         """Runs the request loop (hetm_serve) over OPLIST requests; returns the
         report and per-request latencies, results and commit positions."""
         arrival_s = np.ascontiguousarray(arrival_s, dtype=np.float64)
@@ -410,7 +415,8 @@ class Context:
                                idx=batch.idx.ctypes.data, n_writes=batch.n_writes.ctypes.data,
                                tid=batch.tid.ctypes.data, host_log=host_log.ctypes.data if host_log.size else None,
                                host_log_len=host_log.shape[0], host_log_per_round=host_log_per_round,
-                               max_batch=max_batch, mem_budget_bytes=mem_budget_bytes, pipelined=int(pipelined))
+                               max_batch=max_batch, mem_budget_bytes=mem_budget_bytes, pipelined=int(pipelined),
+                               starvation_limit=starvation_limit)
         rep = hetm_serve_report(latency_us=lat.ctypes.data, results=res.ctypes.data, commit_seq=seq.ctypes.data,
                                 round_conflict=rconf.ctypes.data, max_rounds=max_rounds,
                                 round_log_end=rlog.ctypes.data)
@@ -423,11 +429,12 @@ class Context:
                    round_conflict=rconf[:R], round_log_end=rlog[:R])
         return out
 
-    def round(self, b: Batch | None, log_dev, n_log: int, host, flags=None, ids=None) -> hetm_round_result:
+    def round(self, b: Batch | None, log_dev, n_log: int, host, flags=None, ids=None,
+              policy: int = HETM_POLICY_CPU_WINS) -> hetm_round_result:
         a = hetm_round_args(program=b.program if b else 0, descs=ctypes.addressof(b.desc) if b else None,
                             n_txns=b.n if b else 0, results=b.results.data_ptr() if b else None,
                             tickets=b.tickets.data_ptr() if b else None,
-                            log=log_dev.data_ptr() if n_log else None, n_log=n_log,
+                            log=log_dev.data_ptr() if n_log else None, n_log=n_log, policy=policy,
                             flags_bits=flags.data_ptr() if flags is not None else None,
                             host_replica=host.data_ptr(), ids_out=ids.data_ptr() if ids is not None else None)
         return hetm_round(self.ctx, a)

@@ -22,7 +22,7 @@ def bits(bm: np.ndarray, n: int) -> np.ndarray:
 
 
 def gpu_round(ri: wl.RoundInputs, mode=hm.HETM_MODE_PLAIN, stripe=1, host=None, ctx=None, exec_workgroups=0,
-              flags=True, ids=True, keep=False, async_merge=False):
+              flags=True, ids=True, keep=False, async_merge=False, policy=hm.HETM_POLICY_CPU_WINS):
     """One whole round (hetm_round) on the GPU.  Returns a dict of numpy
     results and the context (if keep)."""
     import torch
@@ -40,7 +40,7 @@ def gpu_round(ri: wl.RoundInputs, mode=hm.HETM_MODE_PLAIN, stripe=1, host=None, 
     flags_t = torch.zeros(max((n_log + 31) // 32, 1) * 4, dtype=torch.uint8, device=ctx.dev) if flags else None
     ids_t = torch.zeros(max(ctx.n_granules, 1) * 4, dtype=torch.uint8, device=ctx.dev) if ids else None
     torch.cuda.synchronize()
-    res = ctx.round(b if ri.batch.n else None, log_t, n_log, host_t, flags_t, ids_t)
+    res = ctx.round(b if ri.batch.n else None, log_t, n_log, host_t, flags_t, ids_t, policy=policy)
     ctx.sync()     # the merge copy of a double-buffered round may still be in flight
     out = {
         "res": res,
@@ -63,12 +63,13 @@ def gpu_round(ri: wl.RoundInputs, mode=hm.HETM_MODE_PLAIN, stripe=1, host=None, 
 REPLAY = {wl.PROG_OPLIST: orc.replay_oplist, wl.PROG_TRANSFER: orc.replay_transfer, wl.PROG_CACHE: orc.replay_cache}
 
 
-def oracle_round(ri: wl.RoundInputs, tickets: np.ndarray, H0: np.ndarray, S0=None, TS0=None, floor=0):
+def oracle_round(ri: wl.RoundInputs, tickets: np.ndarray, H0: np.ndarray, S0=None, TS0=None, floor=0,
+                 policy=orc.POLICY_CPU_WINS):
     order = orc.order_from_tickets(tickets)
     S = (ri.init if S0 is None else S0).copy()
     TS = np.zeros(ri.n_words, np.uint64) if TS0 is None else TS0.copy()
     H = H0.copy()
-    out = orc.round_generic(REPLAY[ri.program], S, H, TS, ri.granule, ri.batch, order, ri.log, floor)
+    out = orc.round_generic(REPLAY[ri.program], S, H, TS, ri.granule, ri.batch, order, ri.log, floor, policy)
     out.update({"S": S, "H": H, "TS": TS, "order": order})
     return out
 
@@ -91,5 +92,5 @@ def assert_round_equal(g: dict, o: dict, ri: wl.RoundInputs, check_ts=True):
     assert np.array_equal(g["S"], g["H"]), "replicas differ after the merge"
     if check_ts:
         assert np.array_equal(g["TS"], o["TS"]), "TS array differs"
-    if o["conflict"] == 0:
+    if o["conflict"] == 0 or r.host_discarded:
         assert int(r.n_committed) == ri.batch.n

@@ -149,6 +149,37 @@ def test_rounds_in_sequence(hm, wl, form):
     ctx.close()
 
 
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("variant", ["w", "p"])
+def test_gpu_wins_policy(hm, wl, variant, form):
+    """Favor-GPU resolution (§IV-E) in every round form: a conflicting round
+    keeps the GPU's transactions, applies nothing of the host log and copies
+    the granules either side wrote to the host replica; a clean round equals
+    the CPU-wins round.  Then a CPU-wins round on the same context continues
+    from that state."""
+    mode, am = FORMS[form]
+    ri = wl.c1(variant)
+    g = gpu_round(ri, mode=mode, async_merge=am, policy=hm.HETM_POLICY_GPU_WINS, keep=True)
+    o = oracle_round(ri, g["tickets"], g["H0"], policy=1)
+    assert_round_equal(g, o, ri)
+    r = g["res"]
+    assert r.conflict == (1 if variant == "w" else 0)
+    assert r.host_discarded == r.conflict and r.gpu_losses == 0
+    # the next round (CPU wins) starts from the replicas the last one left
+    ctx = g["ctx"]
+    S, TS, floor = o["S"], o["TS"], int(o["max_ts"])
+    batch = wl.c2_batch(np.random.default_rng(61), ri.n_words, 2048, 0.5, tid0=1 << 20)
+    log = wl.host_log_uniform(np.random.default_rng(62), 3000, 0, ri.n_words, floor)
+    ri2 = wl.RoundInputs(cfg="next", n_words=ri.n_words, word_bytes=4, granule=ri.granule, program=1, init=S,
+                         batch=batch, log=log, watermark=floor)
+    H1 = wl.host_replica(S, log)
+    g2 = gpu_round(ri2, ctx=ctx, host=H1, keep=True)
+    o2 = oracle_round(ri2, g2["tickets"], H1, S0=S, TS0=TS, floor=floor)
+    assert_round_equal(g2, o2, ri2)
+    assert g2["res"].gpu_losses == o2["conflict"]
+    ctx.close()
+
+
 def test_log_preconditions(hm, wl):
     """A log word outside the STMR (EINVAL) or a timestamp not above the
     watermark (EORDER) applies nothing; a tie at a word's winning timestamp

@@ -114,6 +114,31 @@ def test_serve_matches_oracle(hm, wl, pipelined, rate, inject):
     ctx.close()
 
 
+@pytest.mark.parametrize("pipelined", [False, True])
+def test_serve_starvation_guard(hm, wl, pipelined):
+    """Every host log chunk writes a hot GPU word, so every round with host
+    writes aborts; with a starvation limit of 2 the guard runs a round
+    without host writes after two losses in a row, the GPU makes progress,
+    and the whole run still matches the oracle replay."""
+    g = wl.rng("c5", 2, 3)
+    init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    req = wl.c5_requests(g, 6000, 1e6, n_words=N, host_lo=HOST_LO)
+    log = host_stream(wl, 21, 1 << 18, HOST_LO, N, inject_every=64)
+    ctx = make_ctx(hm, init, pipelined)
+    host_t = hm.pinned(N * 4)
+    host_t.numpy()[:] = init.view(np.uint8)
+    out = ctx.serve(req["arrival_s"], req["batch"], host_t, log, 4096, 8192, 64 << 20, pipelined, starvation_limit=2)
+    say(f"starvation guard pipelined={pipelined}: rounds={out['rounds']} conflicted={out['conflicted_rounds']} "
+        f"starved={out['starved_rounds']}")
+    assert out["served"] == 6000
+    assert out["starved_rounds"] > 0 and out["conflicted_rounds"] > 0
+    S, res = replay_served(init, req["batch"], out, log, 4096, 64)
+    assert np.array_equal(out["results"], res)
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S)
+    assert np.array_equal(host_t.numpy().view(np.uint32), S)
+    ctx.close()
+
+
 def test_serve_alone_vs_mix(hm, wl):
     """Probe requests each touch 4 private words no other request touches:
     their results and final words are identical served alone and served

@@ -354,6 +354,56 @@ def test_round_success_is_serial_cpu_then_gpu(orc):
     assert np.array_equal(res2, out["results"])
 
 
+def test_round_gpu_wins_hand_example(orc):
+    """Favor-GPU resolution (§IV-E) on 8 words, G = 2: the GPU's one
+    transaction increments word 0 (tid 1); the host wrote word 1 (same
+    granule: a conflict) and word 6.  The host's round is discarded: nothing
+    of its log is applied, the GPU keeps its write, and granules 0 and 3 go
+    GPU -> host, undoing the host's writes there."""
+    S0 = np.arange(10, 18, dtype=np.uint32)
+    batch = wl._oplist_from_lists(np.array([1]), np.array([1]), np.array([0]), 0)
+    log = np.zeros(2, wl.LOG4_DTYPE)
+    log["word"], log["value"], log["ts"] = [1, 6], [100, 200], [1, 2]
+    H0 = S0.copy()
+    H0[1], H0[6] = 100, 200
+    S, H, TS = S0.copy(), H0.copy(), np.zeros(8, np.uint64)
+    out = orc.round_oplist(S, H, TS, 2, batch, np.arange(1), log, 0, policy=orc.POLICY_GPU_WINS)
+    assert out["conflict"] == 1
+    assert list(S) == [11, 11, 12, 13, 14, 15, 16, 17]
+    assert np.array_equal(H, S)
+    assert not TS.any() and out["max_ts"] == 0
+    assert list(out["ids"]) == [0, 3] and out["n_runs"] == 2
+    # CPU wins on the same round: the log applies, the GPU's granule 0 is restored from H
+    S, H, TS = S0.copy(), H0.copy(), np.zeros(8, np.uint64)
+    out = orc.round_oplist(S, H, TS, 2, batch, np.arange(1), log, 0)
+    assert out["conflict"] == 1
+    assert np.array_equal(S, H0) and np.array_equal(H, H0)
+    assert list(out["ids"]) == [0]
+
+
+@pytest.mark.parametrize("variant", ["", "w", "p"])
+def test_round_gpu_wins_invariants(orc, variant):
+    """Favor-GPU on the small configuration: with a conflict the replicas end
+    equal to the GPU batch replayed alone on S0 and TS is untouched; without
+    one the round is the CPU-wins round."""
+    ri = wl.c1(variant)
+    order = np.random.default_rng(4).permutation(ri.batch.n)
+    H0 = wl.host_replica(ri.init, ri.log)
+    S, H, TS = ri.init.copy(), H0.copy(), np.zeros(ri.n_words, np.uint64)
+    out = orc.round_oplist(S, H, TS, ri.granule, ri.batch, order, ri.log, 0, policy=orc.POLICY_GPU_WINS)
+    assert np.array_equal(S, H)
+    if out["conflict"]:
+        alone = ri.init.copy()
+        res, _, _ = orc.replay_oplist(alone, ri.granule, ri.batch, order)
+        assert np.array_equal(S, alone) and np.array_equal(res, out["results"])
+        assert not TS.any()
+    else:
+        S2, H2, TS2 = ri.init.copy(), H0.copy(), np.zeros(ri.n_words, np.uint64)
+        orc.round_oplist(S2, H2, TS2, ri.granule, ri.batch, order, ri.log, 0)
+        assert np.array_equal(S, S2) and np.array_equal(TS, TS2)
+    assert out["conflict"] == (0 if variant == "p" else 1)
+
+
 # ----------------------------------------------------------------- transfer
 
 def test_transfer_conservation_and_nonnegative(orc):
