@@ -304,6 +304,7 @@ typedef struct {
     double   us_host_scatter;  /* double-buffered merge: host time scattering
                                   DMA'd granules into the host replica        */
     double   us_merge_wait;    /* time calls spent waiting for such merges    */
+    uint64_t version_resets;   /* slot layout: version-clock resets so far    */
 } hetm_stats;
 int hetm_stats_get(hetm_ctx *ctx, hetm_stats *out);
 
@@ -311,6 +312,18 @@ int hetm_stats_get(hetm_ctx *ctx, hetm_stats *out);
  * compute units) for later batches; a captured round graph is re-captured.
  * Used by the autotuner.  Errors: EINVAL. */
 int hetm_set_exec_workgroups(hetm_ctx *ctx, uint32_t workgroups);
+
+/* Slot layout (u32 words, stripe 1): GPU transactions validate reads against
+ * a version clock that persists across rounds (versions are clock values, 31
+ * bits).  When a round ends with the clock past 2^30 -- checked where the
+ * round's outcome reaches the host: hetm_round, or hetm_copyback_dirty with
+ * n_dirty_out -- the library resets every version and the clock to 0 before
+ * the next round; a writer that would run the clock out latches
+ * HETM_ECAPACITY.  This call moves the
+ * clock forward between rounds -- for callers that want to exercise that
+ * reset.  Errors: EINVAL (backwards or past the limit), ESTATE (split
+ * layout, or a round is open). */
+int hetm_set_version_clock(hetm_ctx *ctx, uint32_t value);
 
 /* Copies context state out (synchronizes).  what: 0 STMR (N*W bytes),
  * 1 TS (N u64), 2 read-set bitmap, 3 write-set bitmap (ceil(ceil(N/G)/32)

@@ -250,10 +250,22 @@ def round_oplist(S, H, TS, G, batch, order, log, floor, policy: int = POLICY_CPU
     return round_generic(replay_oplist, S, H, TS, G, batch, order, log, floor, policy)
 
 
-def order_from_tickets(tickets: np.ndarray) -> np.ndarray:
-    """Commit order pi from per-transaction tickets (unique, gaps allowed)."""
+def order_from_tickets(tickets: np.ndarray, even_ties: bool = False) -> np.ndarray:
+    """Commit order pi from per-transaction tickets (gaps allowed).  Tickets
+    are unique, except with even_ties, where transactions may share an even
+    ticket (read-only transactions serialized at the same snapshot, which
+    commute; the caller checks that they read only); ties replay in index
+    order."""
     order = np.argsort(tickets, kind="stable").astype(np.uint32)
     t = tickets[order]
-    if t.shape[0] > 1 and not np.all(t[1:] > t[:-1]):
-        raise ValueError("tickets are not unique")
+    if t.shape[0] > 1:
+        tie = t[1:] == t[:-1]
+        if tie.any() and not (even_ties and np.all(t[1:][tie] % 2 == 0)):
+            raise ValueError("tickets are not unique")
     return order
+
+
+def tied_tickets(tickets: np.ndarray) -> np.ndarray:
+    """Indices of the transactions whose ticket another one shares."""
+    vals, counts = np.unique(tickets, return_counts=True)
+    return np.flatnonzero(np.isin(tickets, vals[counts > 1]))

@@ -179,7 +179,17 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
     return HETM_OK;
 }
 
+// Slot layout: once the version clock has run past kClockReset, every
+// version and the clock go back to 0 before the next round (queued on the
+// context's stream, which the next round's work follows).
+void maybe_reset_versions(hetm_ctx *c, uint32_t clock) {
+    if (!c->slot || clock < kClockReset) return;
+    launch_version_reset((uint64_t *)c->stmr, c->cfg.n_words, c->hot, c->cnt, c->stream);
+    c->stats.version_resets++;
+}
+
 void account_round(hetm_ctx *c, const DevCounters &s, uint64_t n_txns, hetm_round_result *res) {
+    if (!s.error) maybe_reset_versions(c, s.clock_base);
     const bool gpu_won = s.conflict && c->args.policy == HETM_POLICY_GPU_WINS;
     const bool gpu_lost = s.conflict && !gpu_won;
     c->stats.rounds++;
@@ -772,6 +782,20 @@ int hetm_early_validate(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doom
         HIP_TRY(c, hipStreamSynchronize(c->early_stream));
         *doomed_out = *c->early_host == c->epoch;
     }
+    return HETM_OK;
+}
+
+int hetm_set_version_clock(hetm_ctx *c, uint32_t value) {
+    if (!c) return HETM_EINVAL;
+    if (!c->slot) return fail(c, HETM_ESTATE, "the context keeps no version clock (split layout)");
+    if (c->round_open || c->in_validation) return fail(c, HETM_ESTATE, "a round is open");
+    if (value >= kClockLimit) return fail(c, HETM_EINVAL, "clock %u past the limit", value);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    uint32_t cur = 0;
+    HIP_TRY(c, hipMemcpy(&cur, &c->hot->clock.v, 4, hipMemcpyDeviceToHost));
+    if (value < cur) return fail(c, HETM_EINVAL, "the clock only moves forward (%u < %u)", value, cur);
+    HIP_TRY(c, hipMemcpy(&c->hot->clock.v, &value, 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(&c->cnt->clock_base, &value, 4, hipMemcpyHostToDevice));
     return HETM_OK;
 }
 

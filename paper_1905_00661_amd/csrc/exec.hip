@@ -53,10 +53,10 @@ struct Slot {
     __device__ gmem<uint64_t> *lock(uint32_t w) const { return &slots[w]; }
     __device__ uint32_t stripe(uint32_t w) const { return w; }
     __device__ uint32_t load(uint32_t w) const { return (uint32_t)ld_agent(&slots[w]); }
-    // a slot without its lock bit: version above, value below
-    static __device__ uint64_t commit_word(uint64_t locked, uint32_t value) {
-        const uint64_t ver = ((locked >> 32) + 1) & 0x7FFFFFFFull;
-        return (ver << 32) | value;
+    static __device__ uint32_t version(uint64_t slot) { return (uint32_t)(slot >> 32) & 0x7FFFFFFFu; }
+    // an unlocked slot: version above, value below
+    static __device__ uint64_t make(uint32_t ver, uint32_t value) {
+        return ((uint64_t)(ver & 0x7FFFFFFFu) << 32) | value;
     }
 };
 
@@ -131,15 +131,12 @@ struct WriteBuf {
                 __hip_atomic_fetch_add(lay.lock(at(k)), 1ull - kLockBit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         locked = 0;
     }
-    __device__ void commit(const Slot &lay) {
-        // all slot loads first, then the stores (one memory round trip)
-        uint64_t cur[MAXW];
-#pragma unroll
-        for (uint32_t k = 0; k < (uint32_t)MAXW; ++k)
-            cur[k] = ((locked >> k) & 1u) ? ld_agent(lay.lock(at(k))) : 0;
-#pragma unroll
-        for (uint32_t k = 0; k < (uint32_t)MAXW; ++k)
-            if ((locked >> k) & 1u) st_agent(lay.lock(at(k)), Slot::commit_word(cur[k], (uint32_t)val[k][lane]));
+    // Slot: one store per held word writes the value, the writer's version
+    // and the cleared lock together (duplicate entries of a word carry the
+    // same value, so the held one suffices)
+    __device__ void commit(const Slot &lay, uint32_t ver) {
+        for (uint32_t k = 0; k < n; ++k)
+            if ((locked >> k) & 1u) st_agent(lay.lock(at(k)), Slot::make(ver, (uint32_t)val[k][lane]));
         locked = 0;
     }
     __device__ void mark_writes(gmem<uint8_t> *rs, gmem<uint32_t> *ws, const Div32 &G) {
@@ -313,6 +310,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     WriteBuf<uint32_t, kOplistMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
     uint32_t *ix = s_dyn + wv * max_ops * kWave + lane_id();     // ix[j * kWave]: word j of this lane's txn
     const uint32_t epoch = a->epoch;
+    const uint32_t clock_base = ld_agent(&cnt->clock_base);
     LaneState ls = first_txn(n);
 
     while (refill(ls, a->hot, n)) {
@@ -351,9 +349,17 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
         }
         bool ok = act && !malformed;
         wb.n = 0;
-        uint64_t sum1 = 0;
-        if (Lay::kFused) {
-            // one load per read: value and version together
+        uint32_t ticket;
+        if constexpr (Lay::kFused) {
+            // Slot layout, TL2-style: the wave takes one snapshot rv of the
+            // version clock; a read is valid if its slot is unlocked and no
+            // newer than rv, so one load per read returns a consistent
+            // value.  A read-only transaction commits at rv with no lock,
+            // ticket or second pass; an update locks its writes, draws its
+            // write version wv from the clock and re-checks its reads only
+            // if another writer drew in between (wv != rv).
+            const uint32_t rv = __builtin_amdgcn_readfirstlane(ld_agent(&a->hot->clock.v));
+            hw_order();
             for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
                 uint32_t w[kChunk];
                 uint64_t l[kChunk];
@@ -365,17 +371,44 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
                 for (uint32_t k = 0; k < kChunk; ++k) {
                     const uint32_t j = j0 + k;
                     if (j < L) {
-                        ok &= !(l[k] & kLockBit);
-                        sum1 += l[k];
+                        ok &= !(l[k] & kLockBit) && Slot::version(l[k]) <= rv;
                         const uint32_t v = (uint32_t)l[k];
                         res[o + j] = v;
                         if (j < nwr) wb.put(w[k], v + tv);
                     }
                 }
             }
-            if (ok && nwr) ok = wb.lock_all(lay);
+            const bool upd = nwr != 0;
+            if (ok && upd) ok = wb.lock_all(lay);
+            hw_order();
+            const uint32_t wv = wave_fetch_add(&a->hot->clock.v, ok && upd);
+            hw_order();
+            if (ok && upd && wv != rv) {
+                for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
+                    uint32_t w[kChunk];
+                    uint64_t l[kChunk];
+#pragma unroll
+                    for (uint32_t k = 0; k < kChunk; ++k) w[k] = ix[(j0 + k < L ? j0 + k : j0) * kWave];
+#pragma unroll
+                    for (uint32_t k = 0; k < kChunk; ++k) l[k] = ld_agent(lay.lock(w[k]));
+#pragma unroll
+                    for (uint32_t k = 0; k < kChunk; ++k)
+                        if (j0 + k < L && (((l[k] & kLockBit) && !wb.mine(lay, w[k])) || Slot::version(l[k]) > rv))
+                            ok = false;
+                }
+            }
+            if (ok && upd && wv >= kClockLimit) {
+                latch_error(cnt, HETM_ECAPACITY, ls.txn);
+                ok = false;
+            }
+            if (ok && upd)
+                wb.commit(lay, wv + 1);
+            else if (wb.locked)
+                wb.abort(lay);
+            ticket = upd ? 2u * (wv - clock_base) + 1u : 2u * (rv - clock_base);
         } else {
-            // first pass over the read stripes, then the values
+            // Split layout: first pass over the read stripes, then the values
+            uint64_t sum1 = 0;
             for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
                 uint64_t l[kChunk];
 #pragma unroll
@@ -406,36 +439,36 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
                 }
                 if (nwr) ok = wb.lock_all(lay);
             }
-        }
-        hw_order();
-        uint32_t ticket = wave_fetch_add(&a->hot->ticket.v, ok);
-        hw_order();
-        if (ok) {
-            // revalidation: reload every read word's lock word
-            uint64_t sum2 = 0;
-            for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
-                uint32_t w[kChunk];
-                uint64_t l[kChunk];
+            hw_order();
+            ticket = wave_fetch_add(&a->hot->ticket.v, ok);
+            hw_order();
+            if (ok) {
+                // revalidation: reload every read stripe's lock word
+                uint64_t sum2 = 0;
+                for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
+                    uint32_t w[kChunk];
+                    uint64_t l[kChunk];
 #pragma unroll
-                for (uint32_t k = 0; k < kChunk; ++k) w[k] = ix[(j0 + k < L ? j0 + k : j0) * kWave];
+                    for (uint32_t k = 0; k < kChunk; ++k) w[k] = ix[(j0 + k < L ? j0 + k : j0) * kWave];
 #pragma unroll
-                for (uint32_t k = 0; k < kChunk; ++k) l[k] = ld_agent(lay.lock(w[k]));
+                    for (uint32_t k = 0; k < kChunk; ++k) l[k] = ld_agent(lay.lock(w[k]));
 #pragma unroll
-                for (uint32_t k = 0; k < kChunk; ++k)
-                    if (j0 + k < L) {
-                        if (l[k] & kLockBit) {
-                            if (!wb.mine(lay, lay.stripe(w[k]))) ok = false;
-                            l[k] &= ~kLockBit;
+                    for (uint32_t k = 0; k < kChunk; ++k)
+                        if (j0 + k < L) {
+                            if (l[k] & kLockBit) {
+                                if (!wb.mine(lay, lay.stripe(w[k]))) ok = false;
+                                l[k] &= ~kLockBit;
+                            }
+                            sum2 += l[k];
                         }
-                        sum2 += l[k];
-                    }
+                }
+                ok &= sum2 == sum1;
             }
-            ok &= sum2 == sum1;
+            if (ok)
+                wb.commit(lay);
+            else if (wb.locked)
+                wb.abort(lay);
         }
-        if (ok)
-            wb.commit(lay);
-        else if (wb.locked)
-            wb.abort(lay);
         if (ok) {
             // read-set marks: test every granule of the chunk, then store where clear
             for (uint32_t j0 = nwr; j0 < L; j0 += kChunk) {
@@ -572,6 +605,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
     uint32_t *res = (uint32_t *)a->results;
     WriteBuf<uint32_t, kCacheMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
     const uint32_t epoch = a->epoch;
+    const uint32_t clock_base = ld_agent(&cnt->clock_base);
     LaneState ls = first_txn(n);
 
     while (refill(ls, a->hot, n)) {
@@ -595,36 +629,64 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
             base = (uint32_t)(((mix64(key) & (nsets - 1) & ~1ull) | (key & 1ull)) * kSetWords);
             nh = put ? 25u : 17u;
         }
-        uint64_t sum1 = 0;
-        if (ok)
-            for (uint32_t j = 0; j < nh; ++j) {
-                uint64_t l = ld_agent(lay.lock(base + header_word(j)));
-                ok &= !(l & kLockBit);
-                sum1 += l;
-            }
-        hw_order();
-        uint32_t hdr[25];
-#pragma unroll
-        for (uint32_t j = 0; j < 25; ++j) hdr[j] = (ok && j < nh) ? lay.load(base + header_word(j)) : 0u;
+        uint32_t hdr[25], gv[8];
         int hit = -1;
+        bool get_hit = false;
+        uint64_t sum1 = 0;
+        uint32_t rv = 0;
+        if constexpr (Lay::kFused) {
+            // slot layout, TL2-style (as in the OPLIST kernel): one snapshot,
+            // each slot load gives value and version together
+            rv = __builtin_amdgcn_readfirstlane(ld_agent(&a->hot->clock.v));
+            hw_order();
 #pragma unroll
-        for (int w = 7; w >= 0; --w)
-            if (ok && ((uint64_t)hdr[2 * w] | ((uint64_t)hdr[2 * w + 1] << 32)) == key) hit = w;
-        // GET hit: second read phase over the way's value words
-        const bool get_hit = ok && !put && hit >= 0;
-        if (get_hit)
-            for (uint32_t i = 0; i < 8; ++i) {
-                uint64_t l = ld_agent(lay.lock(base + kValBase + 8 * hit + i));
-                ok &= !(l & kLockBit);
-                sum1 += l;
+            for (uint32_t j = 0; j < 25; ++j) {
+                const bool in = ok && j < nh;
+                const uint64_t l = in ? ld_agent(lay.lock(base + header_word(j))) : 0;
+                if (in) ok &= !(l & kLockBit) && Slot::version(l) <= rv;
+                hdr[j] = (uint32_t)l;
             }
-        hw_order();
+#pragma unroll
+            for (int w = 7; w >= 0; --w)
+                if (ok && ((uint64_t)hdr[2 * w] | ((uint64_t)hdr[2 * w + 1] << 32)) == key) hit = w;
+            get_hit = ok && !put && hit >= 0;
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i) {
+                const uint64_t l = get_hit ? ld_agent(lay.lock(base + kValBase + 8 * hit + i)) : 0;
+                if (get_hit) ok &= !(l & kLockBit) && Slot::version(l) <= rv;
+                gv[i] = (uint32_t)l;
+            }
+        } else {
+            if (ok)
+                for (uint32_t j = 0; j < nh; ++j) {
+                    uint64_t l = ld_agent(lay.lock(base + header_word(j)));
+                    ok &= !(l & kLockBit);
+                    sum1 += l;
+                }
+            hw_order();
+#pragma unroll
+            for (uint32_t j = 0; j < 25; ++j) hdr[j] = (ok && j < nh) ? lay.load(base + header_word(j)) : 0u;
+#pragma unroll
+            for (int w = 7; w >= 0; --w)
+                if (ok && ((uint64_t)hdr[2 * w] | ((uint64_t)hdr[2 * w + 1] << 32)) == key) hit = w;
+            // GET hit: second read phase over the way's value words
+            get_hit = ok && !put && hit >= 0;
+            if (get_hit)
+                for (uint32_t i = 0; i < 8; ++i) {
+                    uint64_t l = ld_agent(lay.lock(base + kValBase + 8 * hit + i));
+                    ok &= !(l & kLockBit);
+                    sum1 += l;
+                }
+            hw_order();
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i) gv[i] = (ok && get_hit) ? lay.load(base + kValBase + 8 * hit + i) : 0u;
+        }
         wb.n = 0;
         uint32_t *r = res + 9ull * (act ? ls.txn : 0);
         if (ok && !put) {
             if (hit >= 0) {
                 r[0] = 0x100u | (uint32_t)hit;
-                for (uint32_t i = 0; i < 8; ++i) r[1 + i] = lay.load(base + kValBase + 8 * hit + i);
+                for (uint32_t i = 0; i < 8; ++i) r[1 + i] = gv[i];
                 wb.put(base + kStampBase + hit, tv);
             } else {
                 for (uint32_t i = 0; i < 9; ++i) r[i] = 0u;
@@ -656,19 +718,48 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
         }
         if (ok && wb.n) ok = wb.lock_all(lay);
         hw_order();
-        uint32_t ticket = wave_fetch_add(&a->hot->ticket.v, ok);
-        hw_order();
-        if (ok) {
-            uint64_t sum2 = 0;
-            for (uint32_t j = 0; j < nh && ok; ++j) sum2 += reread(lay, base + header_word(j), wb, ok);
-            if (get_hit)
-                for (uint32_t i = 0; i < 8 && ok; ++i) sum2 += reread(lay, base + kValBase + 8 * hit + i, wb, ok);
-            ok &= sum2 == sum1;
+        uint32_t ticket;
+        if constexpr (Lay::kFused) {
+            const bool upd = wb.n != 0;
+            const uint32_t wver = wave_fetch_add(&a->hot->clock.v, ok && upd);
+            hw_order();
+            if (ok && upd && wver != rv) {
+                for (uint32_t j = 0; j < nh; ++j) {
+                    const uint32_t w = base + header_word(j);
+                    const uint64_t l = ld_agent(lay.lock(w));
+                    if (((l & kLockBit) && !wb.mine(lay, w)) || Slot::version(l) > rv) ok = false;
+                }
+                if (get_hit)
+                    for (uint32_t i = 0; i < 8; ++i) {
+                        const uint32_t w = base + kValBase + 8 * hit + i;
+                        const uint64_t l = ld_agent(lay.lock(w));
+                        if (((l & kLockBit) && !wb.mine(lay, w)) || Slot::version(l) > rv) ok = false;
+                    }
+            }
+            if (ok && upd && wver >= kClockLimit) {
+                latch_error(cnt, HETM_ECAPACITY, ls.txn);
+                ok = false;
+            }
+            if (ok && upd)
+                wb.commit(lay, wver + 1);
+            else if (wb.locked)
+                wb.abort(lay);
+            ticket = upd ? 2u * (wver - clock_base) + 1u : 2u * (rv - clock_base);
+        } else {
+            ticket = wave_fetch_add(&a->hot->ticket.v, ok);
+            hw_order();
+            if (ok) {
+                uint64_t sum2 = 0;
+                for (uint32_t j = 0; j < nh && ok; ++j) sum2 += reread(lay, base + header_word(j), wb, ok);
+                if (get_hit)
+                    for (uint32_t i = 0; i < 8 && ok; ++i) sum2 += reread(lay, base + kValBase + 8 * hit + i, wb, ok);
+                ok &= sum2 == sum1;
+            }
+            if (ok)
+                wb.commit(lay);
+            else if (wb.locked)
+                wb.abort(lay);
         }
-        if (ok)
-            wb.commit(lay);
-        else if (wb.locked)
-            wb.abort(lay);
         if (ok) {
             for (uint32_t j = 0; j < nh; ++j) rs_mark(rs, div32(base + header_word(j), G));
             if (get_hit)

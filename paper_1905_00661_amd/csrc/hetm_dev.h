@@ -49,15 +49,23 @@ struct alignas(256) HotCounter {
     uint32_t pad_[63];
 };
 struct HotCounters {
-    HotCounter ticket;            // next commit ticket
+    HotCounter ticket;            // next commit ticket (split layout)
     HotCounter queue_head;        // next transaction of the current batch (after the static first pass)
+    HotCounter clock;             // version clock of the slot layout; persists across rounds
 };
+
+// Slot layout: versions are clock values, 31 bits wide.  The host resets
+// every version (and the clock) between rounds once the clock passes
+// kClockReset; a writer that would still reach kClockLimit latches
+// HETM_ECAPACITY instead of committing.
+constexpr uint32_t kClockReset = 1u << 30;
+constexpr uint32_t kClockLimit = 0x7FFFFFF0u;
 
 struct DevCounters {
     uint32_t conflict;            // OR of the validation flags of the round
     int32_t error;                // first latched error code (HETM_E*), 0 if none
     uint32_t ticket_snapshot;     // tickets handed out in the round (at finish)
-    uint32_t unused_;
+    uint32_t clock_base;          // slot layout: the version clock when the round began
     unsigned long long max_ts;    // largest ts of this round's applied log chunks
     unsigned long long floor_ts;  // watermark: largest ts applied by earlier rounds
     unsigned long long committed; // local commits in this round
@@ -276,6 +284,7 @@ void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_
 void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uint32_t *count, uint64_t n_words,
                     uint32_t granule, uint32_t word_bytes, bool slot, hipStream_t s);
 void launch_to_slots(const uint32_t *src, uint64_t *slots, uint64_t n, hipStream_t s);
+void launch_version_reset(uint64_t *slots, uint64_t n, HotCounters *hot, DevCounters *cnt, hipStream_t s);
 void launch_from_slots(const uint64_t *slots, uint32_t *dst, uint64_t n, hipStream_t s);
 
 constexpr uint32_t kScanWordsPerBlock = 2048;   // bitmap words per compaction block

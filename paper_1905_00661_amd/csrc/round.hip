@@ -412,6 +412,18 @@ __global__ __launch_bounds__(256) void k_restore(U *stmr, const U *host, const u
     }
 }
 
+// Slot layout: every version back to 0 and the clock with them (between
+// rounds, when the clock has run far; no lock is held then).
+__global__ __launch_bounds__(256) void k_version_reset(uint64_t *slots, uint64_t n, HotCounters *hot,
+                                                       DevCounters *cnt) {
+    for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < n; w += (uint64_t)gridDim.x * blockDim.x)
+        slots[w] &= 0xFFFFFFFFull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st_agent(&hot->clock.v, 0u);
+        st_agent(&cnt->clock_base, 0u);
+    }
+}
+
 // Slot layout <-> plain words (initial image in, state out).
 __global__ __launch_bounds__(256) void k_to_slots(const uint32_t *src, uint64_t *slots, uint64_t n) {
     for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < n; w += (uint64_t)gridDim.x * blockDim.x)
@@ -431,7 +443,7 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         c.conflict = ld_agent(&cnt->conflict);
         c.error = err;
         c.ticket_snapshot = ld_agent(&a->hot->ticket.v);
-        c.unused_ = 0;
+        c.clock_base = ld_agent(&a->hot->clock.v);     // the next round begins here
         c.max_ts = ld_agent(&cnt->max_ts);
         c.floor_ts = ld_agent(&cnt->floor_ts);
         c.committed = ld_agent(&cnt->committed);
@@ -451,6 +463,7 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
             st_agent(&cnt->floor_ts, (unsigned long long)f);
             st_agent(&cnt->conflict, 0u);
             st_agent(&a->hot->ticket.v, 0u);
+            st_agent(&cnt->clock_base, c.clock_base);
             st_agent(&cnt->max_ts, 0ull);
             st_agent(&cnt->committed, 0ull);
             st_agent(&cnt->retries, 0ull);
@@ -587,6 +600,10 @@ void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uin
     else
         hipLaunchKernelGGL((k_restore<uint64_t, 0>), dim3(grid), dim3(256), 0, s, (uint64_t *)stmr,
                            (const uint64_t *)host, ids, count, granule, n_words);
+}
+
+void launch_version_reset(uint64_t *slots, uint64_t n, HotCounters *hot, DevCounters *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_version_reset, dim3(stream_grid(n, 256, 16384)), dim3(256), 0, s, slots, n, hot, cnt);
 }
 
 void launch_to_slots(const uint32_t *src, uint64_t *slots, uint64_t n, hipStream_t s) {

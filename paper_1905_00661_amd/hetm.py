@@ -33,7 +33,7 @@ EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_a
            "hetm_copyback_dirty", "hetm_round", "hetm_strerror", "hetm_last_error", "hetm_sync",
            "hetm_stats_get", "hetm_read_state", "hetm_state_bytes", "hetm_host_tm_create",
            "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts",
-           "hetm_serve", "hetm_set_exec_workgroups", "hetm_early_validate"]
+           "hetm_serve", "hetm_set_exec_workgroups", "hetm_early_validate", "hetm_set_version_clock"]
 
 P = ctypes.c_void_p
 U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -96,7 +96,8 @@ class hetm_stats(ctypes.Structure):
     _fields_ = [("rounds", U64), ("rounds_conflicted", U64), ("txns_committed", U64),
                 ("txns_aborted", U64), ("local_retries", U64), ("log_entries", U64),
                 ("dirty_granules", U64), ("watermark", U64), ("device_bytes", U64),
-                ("us_host_scatter", ctypes.c_double), ("us_merge_wait", ctypes.c_double)]
+                ("us_host_scatter", ctypes.c_double), ("us_merge_wait", ctypes.c_double),
+                ("version_resets", U64)]
 
 
 class HetmError(RuntimeError):
@@ -136,6 +137,7 @@ def lib() -> ctypes.CDLL:
             "hetm_host_run_cache_puts": ([P, P, U64, U32, P, P, U64, ctypes.POINTER(U64)], ctypes.c_int),
             "hetm_set_exec_workgroups": ([P, U32], ctypes.c_int),
             "hetm_early_validate": ([P, P, U64, P], ctypes.c_int),
+            "hetm_set_version_clock": ([P, U32], ctypes.c_int),
             "hetm_serve": ([P, ctypes.POINTER(hetm_serve_spec), P, ctypes.POINTER(hetm_serve_report)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
@@ -383,6 +385,9 @@ class Context:
         _check(lib().hetm_early_validate(self.ctx, log_dev.data_ptr() if n else None, n,
                                          ctypes.byref(d) if wait else None), "hetm_early_validate", self.ctx)
         return int(d.value) if wait else None
+
+    def set_version_clock(self, value: int) -> None:
+        _check(lib().hetm_set_version_clock(self.ctx, value), "hetm_set_version_clock", self.ctx)
 
     def set_exec_workgroups(self, wg: int) -> None:
         _check(lib().hetm_set_exec_workgroups(self.ctx, wg), "hetm_set_exec_workgroups", self.ctx)

@@ -65,12 +65,21 @@ REPLAY = {wl.PROG_OPLIST: orc.replay_oplist, wl.PROG_TRANSFER: orc.replay_transf
 
 def oracle_round(ri: wl.RoundInputs, tickets: np.ndarray, H0: np.ndarray, S0=None, TS0=None, floor=0,
                  policy=orc.POLICY_CPU_WINS):
-    order = orc.order_from_tickets(tickets)
+    order = orc.order_from_tickets(tickets, even_ties=True)
     S = (ri.init if S0 is None else S0).copy()
     TS = np.zeros(ri.n_words, np.uint64) if TS0 is None else TS0.copy()
     H = H0.copy()
     out = orc.round_generic(REPLAY[ri.program], S, H, TS, ri.granule, ri.batch, order, ri.log, floor, policy)
     out.update({"S": S, "H": H, "TS": TS, "order": order})
+    # transactions sharing a ticket must be read-only (they commute)
+    tied = orc.tied_tickets(tickets)
+    if tied.size:
+        if ri.program == wl.PROG_OPLIST:
+            assert not ri.batch.n_writes[tied].any(), "an update transaction shares its ticket"
+        elif ri.program == wl.PROG_CACHE:
+            assert not out["results"].reshape(-1, 9)[tied, 0].any(), "a writing cache op shares its ticket"
+        else:
+            raise AssertionError("tickets of this program must be unique")
     return out
 
 

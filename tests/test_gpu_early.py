@@ -90,7 +90,7 @@ def test_doom_stops_later_batches(hm, wl):
     host_t.numpy()[:] = H1.view(np.uint8)
     c, nd = _close(hm, ctx, log2_t, 2000, host_t)
     assert c == 0
-    order = orc.order_from_tickets(bC.tickets_np())
+    order = orc.order_from_tickets(bC.tickets_np(), even_ties=True)
     S = H0.copy()
     o = orc.round_generic(orc.replay_oplist, S, H1.copy(), TS, G, C, order, log2, int(TS.max()))
     assert np.array_equal(bC.results_np(), o["results"])

@@ -56,7 +56,7 @@ def test_c1_steps(hm, wl):
     t1, t2 = b1.tickets_np(), b2.tickets_np()
     tickets = np.concatenate([t1, t2])
     import oracle as orc
-    order = orc.order_from_tickets(tickets)
+    order = orc.order_from_tickets(tickets, even_ties=True)
     S = ri.init.copy()
     res, oRS, oWS = orc.replay_oplist(S, ri.granule, ri.batch, order)
     assert np.array_equal(np.concatenate([b1.results_np(), b2.results_np()]), res)
@@ -180,6 +180,36 @@ def test_gpu_wins_policy(hm, wl, variant, form):
     ctx.close()
 
 
+def test_version_clock_reset(hm, wl):
+    """Slot layout: the clock moved to just below the reset threshold runs
+    past it during a round; the round still matches the oracle, every version
+    is 0 afterwards, and the next rounds match the oracle continued."""
+    N = 1 << 16
+    base = wl.c1("w")
+    ctx = hm.Context(N, 4, 1, init=base.init, batch_capacity=4096, log_capacity=10000)
+    ctx.set_version_clock((1 << 30) - 100)
+    S, TS, floor = base.init.copy(), np.zeros(N, np.uint64), 0
+    for r in range(3):
+        g0 = np.random.default_rng(700 + r)
+        batch = wl.c2_batch(g0, N, 4096, 0.5, tid0=r << 12)
+        log = wl.host_log_uniform(g0, 2000, N // 2, N, floor)
+        ri = wl.RoundInputs(cfg="clock", n_words=N, word_bytes=4, granule=1, program=1, init=S, batch=batch, log=log,
+                            watermark=floor)
+        H0 = wl.host_replica(S, log)
+        g = gpu_round(ri, ctx=ctx, host=H0, keep=True)
+        o = oracle_round(ri, g["tickets"], H0, S0=S, TS0=TS, floor=floor)
+        assert_round_equal(g, o, ri)
+        S, TS, floor = o["S"], o["TS"], int(o["max_ts"])
+        if r == 0:
+            slots = ctx.read_state(hm.HETM_STATE_LOCKS)
+            assert not (slots >> np.uint64(32)).any(), "versions survived the reset"
+            assert ctx.stats().version_resets == 1
+    assert ctx.stats().version_resets == 1
+    with pytest.raises(hm.HetmError):
+        ctx.set_version_clock(0)                  # backwards
+    ctx.close()
+
+
 def test_log_preconditions(hm, wl):
     """A log word outside the STMR (EINVAL) or a timestamp not above the
     watermark (EORDER) applies nothing; a tie at a word's winning timestamp
@@ -281,7 +311,7 @@ def test_async_merge_back_to_back(hm, wl):
         torch.cuda.synchronize()
         res = ctx.round(b, log_t, log.shape[0], host_t)
         keep.append((b, log_t))
-        o = orc.round_oplist(S, H, TS, G, batch, orc.order_from_tickets(b.tickets_np()), log, floor)
+        o = orc.round_oplist(S, H, TS, G, batch, orc.order_from_tickets(b.tickets_np(), even_ties=True), log, floor)
         assert res.conflict == o["conflict"] == (1 if r == 3 else 0)
         assert res.merge_pending == (0 if r == 3 else 1)
         assert np.array_equal(b.results_np(), o["results"])
