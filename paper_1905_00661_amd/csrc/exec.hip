@@ -311,11 +311,6 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     uint32_t *ix = s_dyn + wv * max_ops * kWave + lane_id();     // ix[j * kWave]: word j of this lane's txn
     const uint32_t epoch = a->epoch;
     const uint32_t clock_base = ld_agent(&cnt->clock_base);
-    // Slot layout: the clock snapshot of the next attempt, loaded at the end
-    // of the previous one so the contended clock line is off the critical
-    // path.  An older snapshot is still a valid one (it was read before the
-    // attempt's slot loads); it only fails more reads.
-    uint32_t rv_next = Lay::kFused ? ld_agent(&a->hot->clock.v) : 0u;
     LaneState ls = first_txn(n);
 
     while (refill(ls, a->hot, n)) {
@@ -325,6 +320,10 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
             __builtin_amdgcn_s_sleep(2);
             continue;
         }
+        // Slot layout: the attempt's clock snapshot is issued first, so its
+        // latency (the clock line is contended) overlaps the loads of the
+        // transaction's descriptor and word list
+        const uint32_t rv_load = Lay::kFused ? ld_agent(&a->hot->clock.v) : 0u;
         uint32_t o = 0, L = 0, nwr = 0, tv = 0;
         bool malformed = false;
         if (act) {
@@ -363,7 +362,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
             // ticket or second pass; an update locks its writes, draws its
             // write version wv from the clock and re-checks its reads only
             // if another writer drew in between (wv != rv).
-            const uint32_t rv = __builtin_amdgcn_readfirstlane(rv_next);
+            const uint32_t rv = __builtin_amdgcn_readfirstlane(rv_load);
             hw_order();   // the snapshot load has completed before any slot load issues
             for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
                 uint32_t w[kChunk];
@@ -410,7 +409,6 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
                 wb.commit(lay, wv + 1);
             else if (wb.locked)
                 wb.abort(lay);
-            rv_next = ld_agent(&a->hot->clock.v);
             ticket = upd ? 2u * (wv - clock_base) + 1u : 2u * (rv - clock_base);
         } else {
             // Split layout: first pass over the read stripes, then the values
@@ -612,11 +610,6 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
     WriteBuf<uint32_t, kCacheMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
     const uint32_t epoch = a->epoch;
     const uint32_t clock_base = ld_agent(&cnt->clock_base);
-    // Slot layout: the clock snapshot of the next attempt, loaded at the end
-    // of the previous one so the contended clock line is off the critical
-    // path.  An older snapshot is still a valid one (it was read before the
-    // attempt's slot loads); it only fails more reads.
-    uint32_t rv_next = Lay::kFused ? ld_agent(&a->hot->clock.v) : 0u;
     LaneState ls = first_txn(n);
 
     while (refill(ls, a->hot, n)) {
@@ -626,6 +619,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
             __builtin_amdgcn_s_sleep(2);
             continue;
         }
+        const uint32_t rv_load = Lay::kFused ? ld_agent(&a->hot->clock.v) : 0u;   // as in the OPLIST kernel
         bool ok = act;
         uint64_t key = 0;
         uint32_t put = 0, tv = 0, base = 0, nh = 0;
@@ -648,7 +642,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
         if constexpr (Lay::kFused) {
             // slot layout, TL2-style (as in the OPLIST kernel): one snapshot,
             // each slot load gives value and version together
-            rv = __builtin_amdgcn_readfirstlane(rv_next);
+            rv = __builtin_amdgcn_readfirstlane(rv_load);
             hw_order();   // the snapshot load has completed before any slot load issues
 #pragma unroll
             for (uint32_t j = 0; j < 25; ++j) {
@@ -755,7 +749,6 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
                 wb.commit(lay, wver + 1);
             else if (wb.locked)
                 wb.abort(lay);
-            rv_next = ld_agent(&a->hot->clock.v);
             ticket = upd ? 2u * (wver - clock_base) + 1u : 2u * (rv - clock_base);
         } else {
             ticket = wave_fetch_add(&a->hot->ticket.v, ok);
