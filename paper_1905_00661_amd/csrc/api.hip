@@ -53,13 +53,12 @@ int dev_alloc(hetm_ctx *c, T **p, uint64_t bytes) {
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
-// Default transaction-kernel grid: 1.5 workgroups (6 waves) per compute unit.
-// Measured on the large synthetic round, fewer concurrent transactions mean
-// fewer local aborts and less cache turnover between a transaction's first
-// read and its revalidation (exec 1.79 ms at 1.5/CU vs 2.47 ms at full
-// occupancy), and the free CU slots let the merge copy of the previous round
-// run beside the kernel.
-uint32_t default_exec_workgroups(int cus) { return (uint32_t)(cus * 3 / 2); }
+// Default transaction-kernel grid: one workgroup (4 waves) per compute unit.
+// Measured on the large synthetic round (batched loads, slot layout), fewer
+// concurrent transactions mean fewer local aborts and less cache turnover:
+// the kernel takes 894 us at 1/CU, 1016 us at 1.5/CU, 1313 us at 3/CU and
+// 1258 us at 0.5/CU.  The autotuner picks per workload.
+uint32_t default_exec_workgroups(int cus) { return (uint32_t)cus; }
 
 uint32_t ilog2(uint64_t x) {
     uint32_t r = 0;
