@@ -229,7 +229,7 @@ int check_host_replica(hetm_ctx *c, void *host, const void **dev) {
 
 // Waits until every staged merge copy has reached the host replica.
 int drain_merges(hetm_ctx *c) {
-    if (c->cap_stream) HIP_TRY(c, hipStreamSynchronize(c->cap_stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->copy_stream) HIP_TRY(c, hipStreamSynchronize(c->copy_stream));
     if (c->merger) {
         const uint64_t last = std::max(c->merge_seq[0], c->merge_seq[1]);
@@ -248,7 +248,6 @@ int drain_merges(hetm_ctx *c) {
 int build_graph(hetm_ctx *c) {
     if (c->graph_exec) return HETM_OK;
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    if (!c->caller_ready) HIP_TRY(c, hipEventCreateWithFlags(&c->caller_ready, hipEventDisableTiming));
     hipStream_t s = c->cap_stream;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     // The arguments enter the graph as the by-value parameters of a one-thread
@@ -316,7 +315,7 @@ int stage_to_host(hetm_ctx *c, int b, uint64_t D) {
     if (prev && hetm::merge_wait(c->merger, prev) != HETM_OK)
         return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
     if (D > c->host_cap[b]) return fail(c, HETM_ECAPACITY, "%llu dirty granules", (unsigned long long)D);
-    HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->graph_done[b], 0));
+    HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->ev[3], 0));      // after the round's graph
     if (D) {
         HIP_TRY(c, hipMemcpyAsync(c->host_ids[b], c->stage_ids[b], D * 4, hipMemcpyDeviceToHost, c->copy_stream));
         HIP_TRY(c, hipMemcpyAsync(c->host_stage[b], c->staging[b], D * gbytes, hipMemcpyDeviceToHost, c->copy_stream));
@@ -365,9 +364,9 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
     }
     if ((rc = build_graph(c))) return rc;
     c->graph_program = c->args.program;
-    hipStream_t s = c->cap_stream;
-    HIP_TRY(c, hipEventRecord(c->caller_ready, c->stream));   // after the caller's uploads, staged log, ...
-    HIP_TRY(c, hipStreamWaitEvent(s, c->caller_ready, 0));
+    // the graph runs on the caller's stream, after the caller's earlier work
+    // there (uploads, a staged log); it was captured on a private stream
+    hipStream_t s = c->stream;
     const int b = c->buf;
     if (c->cfg.async_merge) {
         // the staging buffer this round fills must have reached the host
@@ -386,7 +385,6 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
     HIP_TRY(c, hipEventRecord(c->ev[3], s));
-    if (c->cfg.async_merge) HIP_TRY(c, hipEventRecord(c->graph_done[b], s));
     c->round_open = true;
     c->round_hdev = hdev;
     c->round_buf = b;
@@ -397,7 +395,7 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     if (!c->round_open) return fail(c, HETM_ESTATE, "no round open");
     c->round_open = false;
     ++c->epoch;
-    hipStream_t s = c->cap_stream;
+    hipStream_t s = c->stream;
     const void *hdev = c->round_hdev;
     const int b = c->round_buf;
     int rc;
@@ -537,8 +535,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
         }
         c->merger = hetm::merge_worker_create();
         for (int b = 0; b < 2; ++b)
-            if (hipEventCreateWithFlags(&c->graph_done[b], hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming) != hipSuccess) {
+            if (hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming) != hipSuccess) {
                 hetm_free(c);
                 return HETM_EDEVICE;
             }
@@ -635,9 +632,7 @@ int hetm_free(hetm_ctx *c) {
     if (c->cnt_host) (void)hipHostFree(c->cnt_host);
     if (c->early_host) (void)hipHostFree(c->early_host);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->caller_ready) (void)hipEventDestroy(c->caller_ready);
     for (int b = 0; b < 2; ++b) {
-        if (c->graph_done[b]) (void)hipEventDestroy(c->graph_done[b]);
         if (c->copied[b]) (void)hipEventDestroy(c->copied[b]);
         if (c->staging[b]) (void)hipFree(c->staging[b]);
         if (c->stage_ids[b]) (void)hipFree(c->stage_ids[b]);

@@ -15,8 +15,7 @@ using hetm::HotCounters;
 struct hetm_ctx {
     hetm_config cfg{};
     hipStream_t stream = nullptr;      // the caller's stream (nullptr = default stream)
-    hipStream_t cap_stream = nullptr;  // private non-blocking stream: captures and runs the round graph
-    hipEvent_t caller_ready = nullptr; // orders the graph after the caller's earlier work
+    hipStream_t cap_stream = nullptr;  // private non-blocking stream the round graph is captured on
     int device = 0;
     uint32_t exec_wg = 0;
     uint32_t log_entry_bytes = 16;
@@ -58,7 +57,6 @@ struct hetm_ctx {
     bool closed_recorded = false;           // closed_ev has been recorded
     uint32_t *early_host = nullptr;         // pinned: doomed flag read back
     uint32_t epoch = 1;                     // number of the open round (tags a doomed round)
-    hipEvent_t graph_done[2] = {};
     hipEvent_t copied[2] = {};
     bool pending[2] = {false, false};
     int buf = 0;

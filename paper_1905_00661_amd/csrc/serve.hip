@@ -217,8 +217,8 @@ struct Serve {
     int fetch_after_round(RoundSet &r) {
         const uint64_t n = r.reqs.size();
         if (!n) return HETM_OK;
-        if (hipMemcpyAsync(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost, c->cap_stream) != hipSuccess ||
-            hipMemcpyAsync(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost, c->cap_stream) != hipSuccess)
+        if (hipMemcpyAsync(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipMemcpyAsync(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
             return HETM_EDEVICE;
         return HETM_OK;
     }
