@@ -180,7 +180,11 @@ int hetm_free(hetm_ctx *ctx);
  * program's descriptor struct (host struct, device arrays).  results
  * (device) and tickets (device, uint32 [n]) receive each transaction's
  * values and its commit ticket: ascending tickets give a serial order that
- * explains every result (gaps allowed).  Results stay speculative until the
+ * explains every result (gaps allowed).  For u32 words with stripe 1,
+ * read-only transactions that read at the same snapshot of the version
+ * clock share an even ticket (they commute; any order among them explains
+ * the results); every writing transaction's ticket is odd and unique.
+ * Tickets compare within one round.  Results stay speculative until the
  * round's outcome is known (§III).  Asynchronous; may be called several
  * times per round.  Errors: EINVAL, ECAPACITY (n > batch_capacity),
  * ESTATE (after validation started in this round); ERETRY latched. */
