@@ -262,6 +262,12 @@ __device__ __forceinline__ bool doomed(DevCounters *cnt, uint32_t epoch) {
     if (lane_id() == 0) st_agent(&cnt->conflict, 1u);
     return true;
 }
+// The same with the flag loaded earlier (one iteration's latency hidden).
+__device__ __forceinline__ bool doomed(DevCounters *cnt, uint32_t epoch, uint32_t loaded) {
+    if (__builtin_amdgcn_readfirstlane(loaded) != epoch) return false;
+    if (lane_id() == 0) st_agent(&cnt->conflict, 1u);
+    return true;
+}
 
 template <typename Lay>
 __device__ __forceinline__ Lay make_layout(const DevArgs *a);
@@ -312,10 +318,12 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     const uint32_t epoch = a->epoch;
     const uint32_t clock_base = ld_agent(&cnt->clock_base);
     LaneState ls = first_txn(n);
+    uint32_t doom = ld_agent(&cnt->doomed);   // the doom flag, loaded one iteration ahead of its check
 
     while (refill(ls, a->hot, n)) {
         const bool act = lane_turn(ls, n);
-        if (doomed(cnt, epoch)) break;
+        if (doomed(cnt, epoch, doom)) break;
+        doom = ld_agent(&cnt->doomed);     // in flight across this iteration, checked at the next
         if (!__ballot(act)) {          // every lane is backing off
             __builtin_amdgcn_s_sleep(2);
             continue;
@@ -474,18 +482,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
                 wb.abort(lay);
         }
         if (ok) {
-            // read-set marks: test every granule of the chunk, then store where clear
-            for (uint32_t j0 = nwr; j0 < L; j0 += kChunk) {
-                uint32_t g[kChunk];
-                uint8_t b[kChunk];
-#pragma unroll
-                for (uint32_t k = 0; k < kChunk; ++k) g[k] = div32(ix[(j0 + k < L ? j0 + k : j0) * kWave], G);
-#pragma unroll
-                for (uint32_t k = 0; k < kChunk; ++k) b[k] = rs[g[k]];
-#pragma unroll
-                for (uint32_t k = 0; k < kChunk; ++k)
-                    if (j0 + k < L && !b[k]) st_agent(&rs[g[k]], (uint8_t)1);
-            }
+            for (uint32_t j = nwr; j < L; ++j) rs_mark(rs, div32(ix[j * kWave], G));
             wb.mark_writes(rs, ws, G);
         }
         settle(ls, act, malformed, ok, ticket, a->tickets, cnt, a->retry_cap);

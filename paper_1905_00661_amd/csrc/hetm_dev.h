@@ -240,18 +240,15 @@ __device__ __forceinline__ void bitmap_set(uint32_t *bm, uint32_t g) {
     if (!(cur & b)) __hip_atomic_fetch_or(bm + w, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The read set is a byte map, so marking a granule is an idempotent store
-// instead of an atomic OR on a shared bitmap word (a committed transaction
-// marks every granule it read: millions per round).  The test is a plain
-// load -- a stale zero only costs a repeated store -- and the store goes to
-// the device coherence point, where early validation can see it while the
-// batch still runs.
-__device__ __forceinline__ void rs_mark(uint8_t *rs, uint32_t g) {
-    if (!rs[g]) st_agent(&rs[g], (uint8_t)1);
-}
-__device__ __forceinline__ void rs_mark(gmem<uint8_t> *rs, uint32_t g) {
-    if (!rs[g]) st_agent(&rs[g], (uint8_t)1);
-}
+// The read set is a byte map, so marking a granule is an idempotent plain
+// byte store instead of an atomic OR on a shared bitmap word (a committed
+// transaction marks every granule it read: millions per round).  The L2s
+// merge the stores and write back only the bytes they dirtied, and the
+// kernel boundary makes every mark visible to validation; early validation,
+// running beside the kernel, sees the marks of finished batches and those of
+// the running one as their lines are written back.
+__device__ __forceinline__ void rs_mark(uint8_t *rs, uint32_t g) { rs[g] = 1; }
+__device__ __forceinline__ void rs_mark(gmem<uint8_t> *rs, uint32_t g) { rs[g] = 1; }
 __device__ __forceinline__ void bitmap_set(gmem<uint32_t> *bm, uint32_t g) {
     uint32_t w = g >> 5, b = 1u << (g & 31);
     uint32_t cur = ld_agent(bm + w);
