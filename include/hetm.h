@@ -210,15 +210,17 @@ int hetm_validate_apply_log(hetm_ctx *ctx, const void *log, uint64_t n, uint32_t
 /* Early validation (§IV-D), step API of a PLAIN context: validates, without
  * applying, a chunk of the host log (n entries, device memory or pinned host
  * memory, complete when the call is made: the CPU's transactions wrote it)
- * against the read-set bitmap as it stands while batches submitted with
- * hetm_submit_batch may still be executing.  It runs on a stream of its own,
+ * against the read-set map as it stands while batches submitted with
+ * hetm_submit_batch may still be executing: it sees the marks of finished
+ * batches, and those of the running one once their cache lines reach
+ * device memory.  It runs on a stream of its own,
  * ordered only after the previous round's merge, so it overlaps the
  * transaction kernels.  A hit dooms the round: the CPU wins, so the running
  * transaction kernel stops at its next iteration, later batches of the round
  * execute nothing, and the round's outcome is a conflict.  Every chunk must
  * still go through hetm_validate_apply_log, which applies it; early
- * validation may miss a conflict (the bitmap is still growing), never invent
- * one.  Entries that fail the log's preconditions are skipped here and
+ * validation may miss a conflict (the read set is still growing), never
+ * invent one.  Entries that fail the log's preconditions are skipped here and
  * reported by hetm_validate_apply_log.  The chunk is read until the round's
  * merge starts.
  * doomed_out (host, nullable): if given, waits for this chunk and stores 1 if
