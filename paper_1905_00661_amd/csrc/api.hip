@@ -256,7 +256,7 @@ int build_graph(hetm_ctx *c) {
     // device copy node would issue PCIe reads that queue behind the previous
     // round's merge copy (device-to-host posted writes) and stall the launch.
     launch_set_args(c->args, c->dargs, s);
-    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, s);
+    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s);
     launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
     launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
     launch_compact(c->dargs, c->args.n_scan_blocks, s);
@@ -463,7 +463,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     const hetm_config &k = *cfg;
     if (k.n_words == 0 || k.n_words > (1ull << 32) || (k.word_bytes != 4 && k.word_bytes != 8) ||
         k.granule_words == 0 || !is_pow2(k.lock_stripe_words) || k.max_txn_ops == 0 || k.max_txn_ops > 64 ||
-        k.batch_capacity == 0 || k.batch_capacity >= (1ull << 32) || k.log_capacity == 0 ||
+        k.batch_capacity == 0 || k.batch_capacity > (1ull << 31) || k.log_capacity == 0 ||
         k.log_capacity >= (1ull << 32) || k.mode > HETM_MODE_GRAPH || k.async_merge > 1 ||
         (k.async_merge && k.mode != HETM_MODE_GRAPH))
         return HETM_EINVAL;
@@ -510,6 +510,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     TRY(dev_alloc(c, &c->blocksums, nblocks * 4));
     TRY(dev_alloc(c, &c->blockruns, nblocks * 4));
     TRY(dev_alloc(c, &c->ids, nG * 4));
+    TRY(dev_alloc(c, &c->order, k.batch_capacity * 4));
     TRY(dev_alloc(c, &c->log_staging, k.log_capacity * c->log_entry_bytes));
     TRY(dev_alloc(c, &c->cnt, sizeof(DevCounters)));
     TRY(dev_alloc(c, &c->hot, sizeof(HotCounters)));
@@ -593,6 +594,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     a.stmr = c->stmr, a.locks = c->locks, a.ts = c->ts, a.rs = c->rs, a.ws = c->ws;
     a.word_shift = c->slot ? 1u : 0u;
     a.suspect = c->suspect, a.multi = c->multi, a.blocksums = c->blocksums, a.blockruns = c->blockruns, a.ids_scratch = c->ids;
+    a.order = c->order;
     a.cnt = c->cnt;
     a.hot = c->hot;
     a.gdiv = make_div32((uint32_t)G);
@@ -624,7 +626,7 @@ int hetm_free(hetm_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->suspect, c->multi, c->blocksums, c->blockruns,
-                   c->ids, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
+                   c->ids, c->order, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->hargs) (void)hipHostFree(c->hargs);
@@ -655,7 +657,7 @@ int hetm_submit_batch(hetm_ctx *c, uint32_t program, const void *descs, uint64_t
     int rc = set_batch_args(c, program, descs, n_txns, results, tickets);
     if (rc) return rc;
     if ((rc = push_args(c))) return rc;
-    launch_exec(program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->stream);
+    launch_exec(program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, c->stream);
     HIP_TRY(c, hipGetLastError());
     return HETM_OK;
 }
@@ -727,7 +729,7 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     if (r->n_txns) {
         if ((rc = push_args(c))) return rc;
-        launch_exec(r->program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, s);
+        launch_exec(r->program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s);
         HIP_TRY(c, hipGetLastError());
     }
     HIP_TRY(c, hipEventRecord(c->ev[1], s));

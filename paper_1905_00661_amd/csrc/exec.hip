@@ -218,6 +218,61 @@ __device__ __forceinline__ bool refill(LaneState &ls, HotCounters *hot, uint32_t
     return __ballot(ls.txn < n) != 0;
 }
 
+// OPLIST work split.  A wave whose lanes mix read-only transactions and
+// updates runs every attempt at the pace of its update lanes (try-locks,
+// the clock draw, revalidation) while the read-only lanes wait; at one
+// update in ten, nearly every wave of 64 holds several.  So k_partition
+// splits the batch into a read-only list (the front of `order`) and an
+// update list (its back), and each wave draws from one list until that
+// runs dry, then from the other.  Serializability does not depend on which
+// transactions run together.
+struct KindQueues {
+    const gmem<uint32_t> *order;
+    uint32_t n, n_ro, n_upd;
+    bool upd;   // wave-uniform: the list this wave draws from
+};
+
+__device__ __forceinline__ KindQueues kind_queues(const DevArgs *a) {
+    KindQueues q;
+    q.order = glob(a->order);
+    q.n = a->n_txns;
+    q.n_ro = ld_agent(&a->hot->n_ro.v);
+    q.n_upd = ld_agent(&a->hot->n_upd.v);
+    // Update waves get a share of the grid 1.5x the update share of the
+    // batch (an update attempt takes longer), at least one if there are
+    // updates; the first wave of every workgroup comes first, which spreads
+    // them over the compute units.
+    const uint32_t waves = gridDim.x * kExecWaves;
+    const uint32_t rank = (threadIdx.x / kWave) * gridDim.x + blockIdx.x;
+    uint32_t upd_waves = 0;
+    if (q.n_upd) {
+        const uint64_t w = (3ull * q.n_upd * waves + 2ull * q.n - 1) / (2ull * q.n);
+        upd_waves = (uint32_t)(w < 1 ? 1 : (w > waves ? waves : w));
+    }
+    q.upd = rank < upd_waves;
+    return q;
+}
+
+// Refill lanes without work from the wave's list, switching the wave to the
+// other list for good once its own is used up; returns false when the whole
+// wave is out of work.  Reached by all 64 lanes.
+__device__ __forceinline__ bool refill(LaneState &ls, KindQueues &q, HotCounters *hot) {
+    bool need = ls.txn == kNoTxn;
+    for (int pass = 0; pass < 2 && __ballot(need); ++pass) {
+        const bool upd = q.upd;
+        const uint32_t lim = upd ? q.n_upd : q.n_ro;
+        const uint32_t got = wave_fetch_add(upd ? &hot->queue_upd.v : &hot->queue_head.v, need);
+        if (need && got < lim) {
+            ls.txn = upd ? q.order[q.n - 1 - got] : q.order[got];
+            ls.attempts = 0;
+            need = false;
+        }
+        if (__ballot(need)) q.upd = !upd;
+    }
+    if (need) ls.txn = kDoneTxn;   // both lists used up
+    return __ballot(ls.txn < q.n) != 0;
+}
+
 // After an attempt: account, then free the lane on commit, retry cap, or a
 // malformed transaction (already latched as HETM_EINVAL, never executed).
 __device__ __forceinline__ void settle(LaneState &ls, bool act, bool malformed, bool ok, uint32_t ticket,
@@ -317,10 +372,11 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     uint32_t *ix = s_dyn + wv * max_ops * kWave + lane_id();     // ix[j * kWave]: word j of this lane's txn
     const uint32_t epoch = a->epoch;
     const uint32_t clock_base = ld_agent(&cnt->clock_base);
-    LaneState ls = first_txn(n);
+    LaneState ls;                               // every lane starts without a transaction
+    KindQueues q = kind_queues(a);
     uint32_t doom = ld_agent(&cnt->doomed);   // the doom flag, loaded one iteration ahead of its check
 
-    while (refill(ls, a->hot, n)) {
+    while (refill(ls, q, a->hot)) {
         const bool act = lane_turn(ls, n);
         if (doomed(cnt, epoch, doom)) break;
         doom = ld_agent(&cnt->doomed);     // in flight across this iteration, checked at the next
@@ -774,7 +830,78 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
 }
 
 __global__ void k_begin_batch(const DevArgs *__restrict__ a) {
-    if (threadIdx.x == 0) st_agent(&a->hot->queue_head.v, 0u);
+    if (threadIdx.x == 0) {
+        st_agent(&a->hot->queue_head.v, 0u);
+        st_agent(&a->hot->queue_upd.v, 0u);
+        st_agent(&a->hot->n_ro.v, 0u);
+        st_agent(&a->hot->n_upd.v, 0u);
+    }
+}
+
+// The OPLIST kind split: transaction i is an update iff nw[i] != 0.  A
+// block takes tiles of kPartPerThread x kPartBlock consecutive transactions
+// (grid-stride, so one launch shape serves every batch size): each thread
+// classifies kPartPerThread of them, a block scan places them, and one
+// atomic per list and tile reserves the tile's range, so both lists hold
+// ascending ids within a tile.
+constexpr uint32_t kPartPerThread = 16;
+constexpr uint32_t kPartBlock = 256;
+constexpr uint64_t kPartTile = (uint64_t)kPartPerThread * kPartBlock;
+constexpr uint32_t kPartMaxBlocks = 1024;
+
+__global__ __launch_bounds__(kPartBlock) void k_partition(const DevArgs *__restrict__ a) {
+    __shared__ uint32_t s_sum[kPartBlock / kWave];
+    __shared__ uint32_t s_base[2];
+    const uint32_t n = a->n_txns;
+    const gmem<uint8_t> *nw = glob(a->nw);
+    gmem<uint32_t> *order = glob(a->order);
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    for (uint64_t tile = blockIdx.x; tile * kPartTile < n; tile += gridDim.x) {
+        const uint64_t first = tile * kPartTile + (uint64_t)threadIdx.x * kPartPerThread;
+        uint32_t kinds = 0, n_ro = 0, n_upd = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kPartPerThread; ++k) {
+            if (first + k < n) {
+                const uint32_t u = nw[first + k] != 0;
+                kinds |= u << k;
+                n_upd += u;
+                n_ro += 1u - u;
+            }
+        }
+        // block-exclusive prefix of both counts at once (each <= 4096 per tile)
+        const uint32_t v = n_ro << 16 | n_upd;
+        uint32_t inc = v;
+        for (uint32_t o = 1; o < kWave; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o);
+            if (lane >= o) inc += t;
+        }
+        if (lane == kWave - 1) s_sum[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (uint32_t w = 0; w < kPartBlock / kWave; ++w) {
+            if (w < wave) before += s_sum[w];
+            total += s_sum[w];
+        }
+        if (threadIdx.x == 0) {
+            s_base[0] = (total >> 16) ? __hip_atomic_fetch_add(&a->hot->n_ro.v, total >> 16, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT) : 0u;
+            s_base[1] = (total & 0xFFFFu) ? __hip_atomic_fetch_add(&a->hot->n_upd.v, total & 0xFFFFu,
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        }
+        __syncthreads();
+        const uint32_t excl = before + inc - v;
+        uint32_t pr = s_base[0] + (excl >> 16), pu = s_base[1] + (excl & 0xFFFFu);
+#pragma unroll
+        for (uint32_t k = 0; k < kPartPerThread; ++k) {
+            if (first + k < n) {
+                if ((kinds >> k) & 1u)
+                    order[n - 1 - pu++] = (uint32_t)(first + k);
+                else
+                    order[pr++] = (uint32_t)(first + k);
+            }
+        }
+        __syncthreads();   // s_sum and s_base are reused by the next tile
+    }
 }
 
 }  // namespace
@@ -788,11 +915,15 @@ hipError_t exec_prepare(uint32_t max_ops) {
                                lds);
 }
 
-void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, bool slot, hipStream_t s) {
+void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, bool slot,
+                 uint64_t batch_capacity, hipStream_t s) {
     hipLaunchKernelGGL(k_begin_batch, dim3(1), dim3(64), 0, s, a);
     dim3 grid(workgroups), block(kExecWaves * kWave);
     const uint32_t lds = oplist_lds_bytes(max_ops);
     if (program == HETM_PROG_OPLIST) {
+        const uint64_t tiles = (batch_capacity + kPartTile - 1) / kPartTile;
+        hipLaunchKernelGGL(k_partition, dim3((uint32_t)(tiles < kPartMaxBlocks ? tiles : kPartMaxBlocks)),
+                           dim3(kPartBlock), 0, s, a);
         if (slot)
             hipLaunchKernelGGL(k_exec_oplist<Slot>, grid, block, lds, s, a);
         else

@@ -28,6 +28,7 @@ struct hetm_ctx {
     uint8_t *rs = nullptr;             // read set, one byte per granule
     uint32_t *ws = nullptr, *suspect = nullptr, *multi = nullptr;
     uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;
+    uint32_t *order = nullptr;    // batch_capacity transaction ids (the OPLIST kind split)
     void *log_staging = nullptr;
     DevCounters *cnt = nullptr;
     HotCounters *hot = nullptr;

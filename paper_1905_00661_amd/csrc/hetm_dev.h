@@ -50,8 +50,12 @@ struct alignas(256) HotCounter {
 };
 struct HotCounters {
     HotCounter ticket;            // next commit ticket (split layout)
-    HotCounter queue_head;        // next transaction of the current batch (after the static first pass)
+    HotCounter queue_head;        // next transaction of the current batch (after the static first pass);
+                                  // OPLIST: next entry of the read-only list
     HotCounter clock;             // version clock of the slot layout; persists across rounds
+    HotCounter queue_upd;         // OPLIST: next entry of the update list
+    HotCounter n_ro;              // OPLIST: length of the read-only list (the partition's cursor)
+    HotCounter n_upd;             // OPLIST: length of the update list (the partition's cursor)
 };
 
 // Slot layout: versions are clock values, 31 bits wide.  The host resets
@@ -95,6 +99,7 @@ struct DevArgs {
     uint32_t *blocksums;    // compaction: per-block dirty counts, then offsets
     uint32_t *blockruns;
     uint32_t *ids_scratch;  // ceil(N/G) dirty granule ids
+    uint32_t *order;        // OPLIST batch split by kind: read-only ids from the front, update ids from the back
     DevCounters *cnt;
     HotCounters *hot;
     Div32 gdiv;             // division by G
@@ -264,7 +269,9 @@ const void *set_args_kernel();   // host handle of the argument-upload kernel
 void launch_clear_error(DevCounters *cnt, hipStream_t s);
 // slot: the context keeps u32 words in the slot layout (value, version and
 // lock in one u64 per word) instead of a value array plus a lock table
-void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, bool slot, hipStream_t s);
+// OPLIST also launches the kind split, sized for batch_capacity transactions
+void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, bool slot,
+                 uint64_t batch_capacity, hipStream_t s);
 // allows the OPLIST kernel the dynamic LDS a context's max_ops needs
 hipError_t exec_prepare(uint32_t max_ops);
 // dynamic LDS of the OPLIST transaction kernel: each lane's word list
