@@ -282,16 +282,18 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_count(const DevArgs *_
     c = block_sum(c, sh);
     r = block_sum(r, sh);
     if (threadIdx.x == 0) {
+        // the sums are device-coherent stores: once they have completed,
+        // the last block's device-coherent loads (issued after it saw the
+        // final ticket) return them
         st_agent(&a->blocksums[blockIdx.x], c);
         st_agent(&a->blockruns[blockIdx.x], r);
-        fence_release();
+        hw_order();
         uint32_t done = __hip_atomic_fetch_add(&cnt->scan_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = done == gridDim.x - 1;
     }
     __syncthreads();
     if (!s_last) return;
     // last block: exclusive scan of the block sums, in place
-    fence_acquire();
     const uint32_t nb = gridDim.x;
     const uint32_t per = (nb + kScanThreads - 1) / kScanThreads;
     const uint32_t lo = threadIdx.x * per, hi = min(lo + per, nb);
@@ -315,31 +317,43 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_count(const DevArgs *_
     }
 }
 
+// A block takes its kScanWordsPerBlock bitmap words in kWordsPerThread
+// rounds of one word per thread: a round's ids (at most 32 per thread) are
+// placed in LDS by a block scan, then stored with consecutive threads on
+// consecutive ids.  Dirty granules cluster (a hot range can fill whole
+// bitmap words), and a thread storing its own ids one by one would write
+// up to 256 scattered positions in turn.
 __global__ __launch_bounds__(kScanThreads) void k_compact_emit(const DevArgs *__restrict__ a) {
     __shared__ uint32_t sh[kScanThreads / kWave];
+    __shared__ uint32_t s_ids[kScanThreads * 32];
     const uint32_t *ws = a->ws;
     const uint32_t nbw = a->n_bm_words;
     uint32_t *ids = a->ids_scratch, *ids_out = a->ids_out;
-    const uint64_t w0 = (uint64_t)blockIdx.x * kScanWordsPerBlock + threadIdx.x * kWordsPerThread;
+    uint32_t pos = ld_agent(&a->blocksums[blockIdx.x]);   // in flight with the bitmap loads
+    const uint64_t blk0 = (uint64_t)blockIdx.x * kScanWordsPerBlock + threadIdx.x;
     uint32_t x[kWordsPerThread];
-    uint32_t c = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < kWordsPerThread; ++i) {
-        x[i] = (w0 + i < nbw) ? ws[w0 + i] : 0u;
-        c += __popc(x[i]);
+    for (uint32_t r = 0; r < kWordsPerThread; ++r) {
+        const uint64_t w = blk0 + r * kScanThreads;
+        x[r] = w < nbw ? ws[w] : 0u;
     }
-    uint32_t total;
-    uint32_t pos = ld_agent(&a->blocksums[blockIdx.x]) + block_exclusive_scan(c, sh, total);
 #pragma unroll
-    for (uint32_t i = 0; i < kWordsPerThread; ++i) {
-        uint32_t v = x[i];
+    for (uint32_t r = 0; r < kWordsPerThread; ++r) {
+        const uint64_t w = blk0 + r * kScanThreads;
+        uint32_t v = x[r], total;
+        uint32_t p = block_exclusive_scan(__popc(v), sh, total);
         while (v) {
-            const uint32_t g = (uint32_t)((w0 + i) * 32 + __ffs(v) - 1);
-            ids[pos] = g;
-            if (ids_out) ids_out[pos] = g;
-            ++pos;
+            s_ids[p++] = (uint32_t)(w * 32 + __ffs(v) - 1);
             v &= v - 1;
         }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < total; k += kScanThreads) {
+            const uint32_t g = s_ids[k];
+            ids[pos + k] = g;
+            if (ids_out) ids_out[pos + k] = g;
+        }
+        pos += total;
+        __syncthreads();   // s_ids is refilled by the next round
     }
 }
 
@@ -374,6 +388,39 @@ __global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uin
 // gather: the round's dirty ids and count are staged always; on success the
 // granules themselves are packed into the staging buffer (a conflict leaves
 // the restore to the host side, after the previous copy has landed).
+// Slot layout with granules of a multiple of 4 words: a lane moves 4 words,
+// two 16-byte loads of two slots each and one 16-byte store of their values
+// (qpg = granule / 4, a power of two: a granule's quads are qpg_shift bits).
+__global__ __launch_bounds__(256) void k_gather_slots(const DevArgs *__restrict__ a, uint32_t qpg_shift,
+                                                      uint64_t n_words) {
+    DevCounters *cnt = a->cnt;
+    if (ld_agent(&cnt->error)) return;
+    const uint32_t outcome = ld_agent(&cnt->conflict);
+    const uint64_t D = ld_agent(&cnt->n_dirty);
+    const uint32_t *ids = a->ids_scratch;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    for (uint64_t i = t0; i < D; i += stride) a->stage_ids[i] = ids[i];
+    if (t0 == 0) *a->stage_count = (uint32_t)D;
+    if (outcome && a->policy != HETM_POLICY_GPU_WINS) return;   // restored from the host instead
+    const uint4 *slots = (const uint4 *)a->stmr;   // two slots per 16 bytes
+    const uint32_t *words = (const uint32_t *)a->stmr;
+    uint4 *stg = (uint4 *)a->staging;
+    const uint64_t work = D << qpg_shift;
+    const uint64_t qmask = (1ull << qpg_shift) - 1;
+    for (uint64_t u = t0; u < work; u += stride) {
+        const uint64_t q = ((uint64_t)ids[u >> qpg_shift] << qpg_shift) + (u & qmask);   // quad: words 4q .. 4q+3
+        if (4 * q + 3 < n_words) {
+            const uint4 s0 = slots[2 * q], s1 = slots[2 * q + 1];
+            stg[u] = make_uint4(s0.x, s0.z, s1.x, s1.z);
+        } else {
+            uint32_t *st = (uint32_t *)(stg + u);
+            for (uint32_t k = 0; k < 4; ++k)
+                if (4 * q + k < n_words) st[k] = words[2 * (4 * q + k)];
+        }
+    }
+}
+
 template <typename U, int DS>
 __global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, uint32_t upg, uint64_t total_units) {
     DevCounters *cnt = a->cnt;
@@ -571,7 +618,11 @@ void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_
     const uint64_t gbytes = (uint64_t)granule * word_bytes;
     const uint64_t n_granules = (n_words + granule - 1) / granule;
     const uint32_t wgrid = stream_grid(n_granules * granule, 256, 16384);
-    if (slot) {
+    if (slot && granule % 4 == 0 && ((granule / 4) & (granule / 4 - 1)) == 0) {
+        const uint32_t qpg = granule / 4;
+        hipLaunchKernelGGL(k_gather_slots, dim3(stream_grid(n_granules * qpg, 256, 16384)), dim3(256), 0, s, a,
+                           (uint32_t)__builtin_ctz(qpg), n_words);
+    } else if (slot) {
         hipLaunchKernelGGL((k_gather<uint32_t, 1>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
     } else if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0) {
         const uint32_t upg = (uint32_t)(gbytes / 16);
