@@ -39,14 +39,15 @@ def log(*a):
 
 def exec_alg_bytes(batch) -> float:
     """Algorithmic bytes the execution kernel moves for a batch of u32 words
-    in the slot layout (value, version and lock in one u64 per word): per
-    transaction, offsets 8 B, n_writes 1 B, tid 4 B, ticket 4 B; per read,
-    index 4 B, the slot read before and after the commit ticket 16 B, the
-    result 4 B; per write, the slot read and CAS-locked 24 B, re-read and
-    stored with the new value 16 B."""
+    in the slot layout (value, version and lock in one u64 per word), one
+    attempt per transaction: per transaction, its list entry 4 B, offsets
+    8 B, n_writes 1 B, tid 4 B, ticket 4 B; per read, index 4 B, slot 8 B,
+    result 4 B, read-set byte 1 B; per read of an updating transaction, the
+    revalidating slot load 8 B; per write, the CAS that locks the slot 16 B,
+    the store that publishes it 8 B, the write-set bitmap word 4 B."""
     L = np.diff(batch.offsets.astype(np.int64))
     nw = batch.n_writes.astype(np.int64)
-    return float(batch.n * 17 + L.sum() * 24 + nw.sum() * 40)
+    return float(batch.n * 21 + L.sum() * 17 + L[nw > 0].sum() * 8 + nw.sum() * 28)
 
 
 VALIDATE_APPLY_BYTES_PER_ENTRY = 40.0   # 16 B entry + 4 B bitmap + 8+8 B TS + 4 B value
@@ -141,7 +142,7 @@ def main():
                     help="first run a plain 1 GiB device copy, the known-size reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs a round on one GPU; there is no multi-GPU path, so --gpus must be 1"}))
         sys.exit(2)
 
     import torch
