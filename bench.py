@@ -122,8 +122,10 @@ def serve_forms(args, hm, wl, torch) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    # a job of 50 rounds: the final drain (the last round's merge copy, part
+    # of the job) weighs on the per-round figure as it would in a longer run
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2-words", type=int, default=28)
     ap.add_argument("--log2-txns", type=int, default=20)
     ap.add_argument("--log2-log", type=int, default=20)

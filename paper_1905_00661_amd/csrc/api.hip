@@ -240,14 +240,35 @@ int drain_merges(hetm_ctx *c) {
     return HETM_OK;
 }
 
-// Captures the round once on a private non-blocking stream (the default
-// stream cannot be captured).  The graph also runs there, after an event
-// from the caller's stream, so that it never waits on unrelated work (the
-// legacy default stream synchronizes with other blocking streams) and the
-// merge copy of the previous round, on its own stream, overlaps it.
-int build_graph(hetm_ctx *c) {
-    if (c->graph_exec) return HETM_OK;
+void drop_graphs(hetm_ctx *c) {
+    for (auto &g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g = hetm_ctx::RoundGraph{};
+    }
+}
+
+// Captures the round for one merge policy on a private non-blocking stream
+// (the default stream cannot be captured); it is launched on the caller's
+// stream.  Under CPU wins with the double-buffered merge, compaction and the
+// gather of the dirty granules fork off after the transaction kernel and
+// join before the finish: they read only the GPU's write set, and a round
+// without conflict applies the host log to granules the GPU neither read
+// nor wrote (its written granules are in its read set).  In a conflicted
+// round the gathered data is not used (the host restores those granules),
+// and the staged ids it restores from do not depend on the log.  Under GPU
+// wins a conflicted round's apply adds the log's granules to the write set,
+// so compaction has to follow it.
+int build_graph(hetm_ctx *c, uint32_t policy) {
+    hetm_ctx::RoundGraph &rg = c->graphs[policy];
+    if (rg.exec) return HETM_OK;
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const bool fork = c->cfg.async_merge && policy == HETM_POLICY_CPU_WINS;
+    if (fork && !c->cap_branch) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_branch, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    }
     hipStream_t s = c->cap_stream;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     // The arguments enter the graph as the by-value parameters of a one-thread
@@ -257,41 +278,59 @@ int build_graph(hetm_ctx *c) {
     // round's merge copy (device-to-host posted writes) and stall the launch.
     launch_set_args(c->args, c->dargs, s);
     launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s);
-    launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
-    launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
-    launch_compact(c->dargs, c->args.n_scan_blocks, s);
-    if (c->cfg.async_merge)
-        launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
-    else
-        launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
+    hipError_t ce = hipSuccess;
+    if (fork) {
+        hipStream_t br = c->cap_branch;
+        if (ce == hipSuccess) ce = hipEventRecord(c->fork_ev, s);
+        if (ce == hipSuccess) ce = hipStreamWaitEvent(br, c->fork_ev, 0);
+        launch_compact(c->dargs, c->args.n_scan_blocks, br);
+        launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, br);
+        if (ce == hipSuccess) ce = hipEventRecord(c->join_ev, br);
+        launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
+        launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
+        if (ce == hipSuccess) ce = hipStreamWaitEvent(s, c->join_ev, 0);
+    } else {
+        launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
+        launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
+        launch_compact(c->dargs, c->args.n_scan_blocks, s);
+        if (c->cfg.async_merge)
+            launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
+        else
+            launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
+    }
     launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, s);
     (void)hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
-    if (e != hipSuccess) return fail(c, HETM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(c, HETM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : ce));
+    }
+    e = hipGraphInstantiate(&rg.exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(g);
+        rg.exec = nullptr;
         return fail(c, HETM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
     }
-    c->graph = g;
+    rg.graph = g;
+    rg.program = c->args.program;
     // find the argument-upload node
     size_t nn = 0;
     HIP_TRY(c, hipGraphGetNodes(g, nullptr, &nn));
     hipGraphNode_t nodes[64];
     if (nn > 64) return fail(c, HETM_EDEVICE, "unexpected graph size %zu", nn);
     HIP_TRY(c, hipGraphGetNodes(g, nodes, &nn));
-    c->args_node = nullptr;
+    rg.args_node = nullptr;
     for (size_t i = 0; i < nn; ++i) {
         hipGraphNodeType t;
         if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
         hipKernelNodeParams kp{};
         if (hipGraphKernelNodeGetParams(nodes[i], &kp) == hipSuccess && kp.func == set_args_kernel()) {
-            c->args_node = nodes[i];
-            c->args_params = kp;
+            rg.args_node = nodes[i];
+            rg.args_params = kp;
         }
     }
-    if (!c->args_node) return fail(c, HETM_EDEVICE, "argument node not found in the round graph");
+    if (!rg.args_node) return fail(c, HETM_EDEVICE, "argument node not found in the round graph");
     return HETM_OK;
 }
 
@@ -356,14 +395,9 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
     c->args.host = const_cast<void *>(hdev);
     c->args.ids_out = r->ids_out;
     c->round_host = r->host_replica;
-    if (c->graph_exec && c->graph_program != c->args.program) {
-        (void)hipGraphExecDestroy(c->graph_exec);
-        (void)hipGraphDestroy(c->graph);
-        c->graph_exec = nullptr;
-        c->graph = nullptr;
-    }
-    if ((rc = build_graph(c))) return rc;
-    c->graph_program = c->args.program;
+    if (c->graphs[r->policy].exec && c->graphs[r->policy].program != c->args.program) drop_graphs(c);
+    if ((rc = build_graph(c, r->policy))) return rc;
+    const hetm_ctx::RoundGraph &rg = c->graphs[r->policy];
     // the graph runs on the caller's stream, after the caller's earlier work
     // there (uploads, a staged log); it was captured on a private stream
     hipStream_t s = c->stream;
@@ -378,12 +412,12 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
     c->args.epoch = c->epoch;
     DevArgs *dst = c->dargs;
     void *kargs[2] = {&c->args, &dst};
-    hipKernelNodeParams kp = c->args_params;
+    hipKernelNodeParams kp = rg.args_params;
     kp.kernelParams = kargs;
     kp.extra = nullptr;
-    HIP_TRY(c, hipGraphExecKernelNodeSetParams(c->graph_exec, c->args_node, &kp));
+    HIP_TRY(c, hipGraphExecKernelNodeSetParams(rg.exec, rg.args_node, &kp));
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
-    HIP_TRY(c, hipGraphLaunch(c->graph_exec, s));
+    HIP_TRY(c, hipGraphLaunch(rg.exec, s));
     HIP_TRY(c, hipEventRecord(c->ev[3], s));
     c->round_open = true;
     c->round_hdev = hdev;
@@ -614,15 +648,16 @@ int hetm_free(hetm_ctx *c) {
     if (!c) return HETM_EINVAL;
     (void)hipSetDevice(c->device);
     // every queue of the context drains before its memory goes
-    for (hipStream_t s : {c->stream, c->cap_stream, c->copy_stream, c->early_stream})
+    for (hipStream_t s : {c->stream, c->cap_stream, c->cap_branch, c->copy_stream, c->early_stream})
         if (s) (void)hipStreamSynchronize(s);
     hetm::merge_worker_destroy(c->merger);     // finishes the queued scatters first
     for (int b = 0; b < 2; ++b) {
         if (c->host_stage[b]) (void)hipHostFree(c->host_stage[b]);
         if (c->host_ids[b]) (void)hipHostFree(c->host_ids[b]);
     }
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
+    drop_graphs(c);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->suspect, c->multi, c->blocksums, c->blockruns,
@@ -634,6 +669,7 @@ int hetm_free(hetm_ctx *c) {
     if (c->cnt_host) (void)hipHostFree(c->cnt_host);
     if (c->early_host) (void)hipHostFree(c->early_host);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->cap_branch) (void)hipStreamDestroy(c->cap_branch);
     for (int b = 0; b < 2; ++b) {
         if (c->copied[b]) (void)hipEventDestroy(c->copied[b]);
         if (c->staging[b]) (void)hipFree(c->staging[b]);
@@ -804,12 +840,9 @@ int hetm_set_exec_workgroups(hetm_ctx *c, uint32_t workgroups) {
         workgroups = default_exec_workgroups(cus);
     }
     c->exec_wg = workgroups;
-    if (c->graph_exec) {
+    if (c->graphs[0].exec || c->graphs[1].exec) {
         (void)hipStreamSynchronize(c->stream);
-        (void)hipGraphExecDestroy(c->graph_exec);
-        (void)hipGraphDestroy(c->graph);
-        c->graph_exec = nullptr;
-        c->graph = nullptr;
+        drop_graphs(c);
     }
     return HETM_OK;
 }

@@ -15,7 +15,7 @@ using hetm::HotCounters;
 struct hetm_ctx {
     hetm_config cfg{};
     hipStream_t stream = nullptr;      // the caller's stream (nullptr = default stream)
-    hipStream_t cap_stream = nullptr;  // private non-blocking stream the round graph is captured on
+    hipStream_t cap_stream = nullptr;  // private non-blocking stream the round graphs are captured on
     int device = 0;
     uint32_t exec_wg = 0;
     uint32_t log_entry_bytes = 16;
@@ -43,11 +43,18 @@ struct hetm_ctx {
 
     DevArgs args{};                  // host copy of the current arguments
     hipEvent_t ev[4] = {};
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    uint32_t graph_program = 0;
-    hipGraphNode_t args_node = nullptr;     // the graph's argument-upload kernel node
-    hipKernelNodeParams args_params{};
+    // The round graph, one per merge policy (captured on first use).  With
+    // the double-buffered merge and CPU wins, the dirty-granule compaction
+    // and gather run on a branch of their own beside validation and apply.
+    struct RoundGraph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        uint32_t program = 0;
+        hipGraphNode_t args_node = nullptr;   // the argument-upload kernel node
+        hipKernelNodeParams args_params{};
+    } graphs[2];
+    hipStream_t cap_branch = nullptr;       // capture only: the merge branch
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 
     // double-buffered merge (GRAPH mode with async_merge)
     hipStream_t copy_stream = nullptr;
