@@ -201,7 +201,8 @@ int hetm_submit_batch(hetm_ctx *ctx, uint32_t program, const void *descs, uint64
  * device before anything of the chunk is applied; a chunk failing them
  * applies nothing.  Two entries (in any chunks of the round) carrying one
  * word's winning ts give EORDER and leave that word unspecified.
- * flags_bits (device, nullable, ceil(n/32) uint32) receives bit k = flag k.
+ * flags_bits (device, nullable, ceil(n/32) uint32) receives bit k = flag k
+ * (unspecified if the chunk fails its preconditions).
  * conflict_out (host, nullable): if given, the call synchronizes and
  * stores the round outcome so far (0/1), returning any latched error. */
 int hetm_validate_apply_log(hetm_ctx *ctx, const void *log, uint64_t n, uint32_t *flags_bits,

@@ -227,8 +227,12 @@ int check_host_replica(hetm_ctx *c, void *host, const void **dev) {
     return HETM_OK;
 }
 
+int issue_merge(hetm_ctx *c, hipEvent_t after);
+
 // Waits until every staged merge copy has reached the host replica.
 int drain_merges(hetm_ctx *c) {
+    int rc = issue_merge(c, nullptr);
+    if (rc) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (c->copy_stream) HIP_TRY(c, hipStreamSynchronize(c->copy_stream));
     if (c->merger) {
@@ -277,8 +281,10 @@ int build_graph(hetm_ctx *c, uint32_t policy) {
     // device copy node would issue PCIe reads that queue behind the previous
     // round's merge copy (device-to-host posted writes) and stall the launch.
     launch_set_args(c->args, c->dargs, s);
-    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s);
     hipError_t ce = hipSuccess;
+    if (c->cfg.async_merge && !c->exec_ev) ce = hipEventCreateWithFlags(&c->exec_ev, hipEventDisableTiming);
+    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s,
+                c->cfg.async_merge ? c->exec_ev : nullptr);
     if (fork) {
         hipStream_t br = c->cap_branch;
         if (ce == hipSuccess) ce = hipEventRecord(c->fork_ev, s);
@@ -344,9 +350,10 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
 }
 
 // Success path of the double-buffered merge for staging buffer b holding D
-// packed granules: DMA on the copy stream after the graph, then a job for
+// packed granules bound for host replica `host`: DMA on the copy stream
+// after the round's graph (c->ev[3], not yet re-recorded), then a job for
 // the merge worker.
-int stage_to_host(hetm_ctx *c, int b, uint64_t D) {
+int stage_to_host(hetm_ctx *c, int b, uint64_t D, void *host) {
     const uint64_t gbytes = (uint64_t)c->cfg.granule_words * c->cfg.word_bytes;
     // every earlier merge lands before this one starts, so after a round
     // returns only its own merge can still be in flight
@@ -361,9 +368,18 @@ int stage_to_host(hetm_ctx *c, int b, uint64_t D) {
     }
     HIP_TRY(c, hipEventRecord(c->copied[b], c->copy_stream));
     c->merge_seq[b] = hetm::merge_submit(c->merger, c->copied[b], c->host_ids[b], c->host_stage[b], D,
-                                         (uint8_t *)c->round_host, gbytes, c->cfg.n_words * c->cfg.word_bytes);
+                                         (uint8_t *)host, gbytes, c->cfg.n_words * c->cfg.word_bytes);
     c->round_merge_seq = c->merge_seq[b];
     return HETM_OK;
+}
+
+// Issues the deferred copy of the last successful round, after `after`
+// (nullable) on the device.
+int issue_merge(hetm_ctx *c, hipEvent_t after) {
+    if (!c->merge_deferred) return HETM_OK;
+    c->merge_deferred = false;
+    if (after) HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, after, 0));
+    return stage_to_host(c, c->deferred_buf, c->deferred_n, c->deferred_host);
 }
 
 }  // namespace
@@ -418,6 +434,9 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
     HIP_TRY(c, hipGraphExecKernelNodeSetParams(rg.exec, rg.args_node, &kp));
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, hipGraphLaunch(rg.exec, s));
+    // the last round's copy to the host starts with this round's transaction
+    // kernel (its end event, ev[3], is re-recorded only below)
+    if ((rc = issue_merge(c, c->exec_ev))) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[3], s));
     c->round_open = true;
     c->round_hdev = hdev;
@@ -439,9 +458,17 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     c->round_merge_seq = 0;
     if (c->cfg.async_merge) {
         if (!snap.conflict || c->args.policy == HETM_POLICY_GPU_WINS) {
-            // the GPU's granules go to the host replica: DMA the staged granules to pinned host staging on the
-            // copy stream; the merge worker scatters them into the host replica
-            if ((rc = stage_to_host(c, b, snap.n_dirty))) return rc;
+            // the GPU's granules go to the host replica: a DMA of the staged granules to pinned host staging on
+            // the copy stream (issued by the next round_begin, or by whatever waits for merges first), then
+            // the merge worker scatters them into the host replica.  The previous round's merge, issued when
+            // this round began, lands before this round returns.
+            const uint64_t prev = std::max(c->merge_seq[0], c->merge_seq[1]);
+            if (prev && hetm::merge_wait(c->merger, prev) != HETM_OK)
+                return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
+            c->merge_deferred = true;
+            c->deferred_buf = b;
+            c->deferred_n = snap.n_dirty;
+            c->deferred_host = c->round_host;
             c->pending[b] = true;
             c->last_copy = b;
             c->buf = b ^ 1;
@@ -463,6 +490,8 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
 }
 
 uint64_t last_merge_seq(hetm_ctx *c) { return c->round_merge_seq; }
+
+int issue_deferred_merge(hetm_ctx *c) { return issue_merge(c, nullptr); }
 
 uint64_t merged_seq(hetm_ctx *c) { return c->merger ? merge_done(c->merger) : 0; }
 
@@ -647,6 +676,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
 int hetm_free(hetm_ctx *c) {
     if (!c) return HETM_EINVAL;
     (void)hipSetDevice(c->device);
+    if (c->merge_deferred) (void)issue_merge(c, nullptr);   // the last round's copy still reaches the host
     // every queue of the context drains before its memory goes
     for (hipStream_t s : {c->stream, c->cap_stream, c->cap_branch, c->copy_stream, c->early_stream})
         if (s) (void)hipStreamSynchronize(s);
@@ -657,6 +687,7 @@ int hetm_free(hetm_ctx *c) {
     }
     drop_graphs(c);
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->exec_ev) (void)hipEventDestroy(c->exec_ev);
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);

@@ -958,7 +958,7 @@ hipError_t exec_prepare(uint32_t max_ops) {
 }
 
 void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, bool slot,
-                 uint64_t batch_capacity, hipStream_t s) {
+                 uint64_t batch_capacity, hipStream_t s, hipEvent_t exec_started) {
     hipLaunchKernelGGL(k_begin_batch, dim3(1), dim3(64), 0, s, a);
     dim3 grid(workgroups), block(kExecWaves * kWave);
     const uint32_t lds = oplist_lds_bytes(max_ops);
@@ -966,6 +966,9 @@ void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32
         const uint64_t tiles = (batch_capacity + kPartTile - 1) / kPartTile;
         hipLaunchKernelGGL(k_partition, dim3((uint32_t)(tiles < kPartMaxBlocks ? tiles : kPartMaxBlocks)),
                            dim3(kPartBlock), 0, s, a);
+    }
+    if (exec_started) (void)hipEventRecord(exec_started, s);
+    if (program == HETM_PROG_OPLIST) {
         if (slot)
             hipLaunchKernelGGL(k_exec_oplist<Slot>, grid, block, lds, s, a);
         else

@@ -55,6 +55,16 @@ struct hetm_ctx {
     } graphs[2];
     hipStream_t cap_branch = nullptr;       // capture only: the merge branch
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipEvent_t exec_ev = nullptr;           // recorded by the round graph as its transaction kernel starts
+
+    // A successful round's copy to the host is issued once the next round's
+    // transaction kernel has started (or when something waits for merges):
+    // the copy's host-bound writes would otherwise delay the next round's
+    // first, host-reading steps (argument upload, kernel dispatch).
+    bool merge_deferred = false;
+    int deferred_buf = 0;
+    uint64_t deferred_n = 0;
+    void *deferred_host = nullptr;
 
     // double-buffered merge (GRAPH mode with async_merge)
     hipStream_t copy_stream = nullptr;
@@ -98,9 +108,12 @@ namespace hetm {
 // synchronous merge, restore on conflict) and fills *res.
 int round_begin(hetm_ctx *c, const hetm_round_args *r);
 int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res);
-// Double-buffered merge progress: the merge job of the round round_end just
-// closed (0 if it left nothing in flight), the last job whose granules are
-// in the host replica, and a wait for a job.
+// Double-buffered merge progress.  A successful round's copy to the host is
+// issued by the next round_begin (as its transaction kernel starts) or by
+// issue_deferred_merge; last_merge_seq is the most recently issued job (0
+// after a round that left nothing to merge), merged_seq the last job whose
+// granules are in the host replica, wait_merged a wait for a job.
+int issue_deferred_merge(hetm_ctx *c);
 uint64_t last_merge_seq(hetm_ctx *c);
 uint64_t merged_seq(hetm_ctx *c);
 int wait_merged(hetm_ctx *c, uint64_t seq);

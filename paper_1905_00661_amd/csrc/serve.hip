@@ -351,6 +351,9 @@ struct Serve {
                 {
                     Span t(&rep->us_wait_round);
                     if ((err = hetm::round_end(c, &a[cur], &res))) return err;
+                    // a served request completes when its round's merge lands:
+                    // start the copy now rather than with the next round
+                    if ((err = hetm::issue_deferred_merge(c))) return err;
                 }
                 Span t(&rep->us_settle);
                 std::vector<uint64_t> done;
