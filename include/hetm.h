@@ -279,6 +279,8 @@ typedef struct {
                                   host's round, whose log was not applied      */
     uint32_t gpu_losses;       /* rounds in a row, this one included, whose GPU
                                   transactions aborted (starvation signal)     */
+    double   us_exec_kernel;   /* PLAIN: the transaction kernel alone (us_exec
+                                  also covers the batch set-up kernels)        */
 } hetm_round_result;
 
 /* A whole round: execution, validation+apply, merge, reset, in the

@@ -610,8 +610,8 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
         hetm_free(c);
         return HETM_ENOMEM;
     }
-    for (auto &e : c->ev)
-        if (hipEventCreate(&e) != hipSuccess) {
+    for (hipEvent_t *e : {&c->ev[0], &c->ev[1], &c->ev[2], &c->ev[3], &c->ev_kernel})
+        if (hipEventCreate(e) != hipSuccess) {
             hetm_free(c);
             return HETM_EDEVICE;
         }
@@ -691,6 +691,7 @@ int hetm_free(hetm_ctx *c) {
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->ev_kernel) (void)hipEventDestroy(c->ev_kernel);
     void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->suspect, c->multi, c->blocksums, c->blockruns,
                    c->ids, c->order, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
     for (void *p : dev)
@@ -796,7 +797,8 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     if (r->n_txns) {
         if ((rc = push_args(c))) return rc;
-        launch_exec(r->program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s);
+        launch_exec(r->program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s,
+                    c->ev_kernel);
         HIP_TRY(c, hipGetLastError());
     }
     HIP_TRY(c, hipEventRecord(c->ev[1], s));
@@ -818,6 +820,7 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     c->stats.log_entries += r->n_log;
     if (res) {
         res->us_exec = elapsed_us(c->ev[0], c->ev[1]);
+        res->us_exec_kernel = r->n_txns ? elapsed_us(c->ev_kernel, c->ev[1]) : 0.0;
         res->us_validate = elapsed_us(c->ev[1], c->ev[2]);
         res->us_merge = elapsed_us(c->ev[2], c->ev[3]);
         res->us_total = elapsed_us(c->ev[0], c->ev[3]);

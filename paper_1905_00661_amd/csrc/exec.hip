@@ -883,9 +883,10 @@ __global__ void k_begin_batch(const DevArgs *__restrict__ a) {
 // The OPLIST kind split: transaction i is an update iff nw[i] != 0.  A
 // block takes tiles of kPartPerThread x kPartBlock consecutive transactions
 // (grid-stride, so one launch shape serves every batch size): each thread
-// classifies kPartPerThread of them, a block scan places them, and one
-// atomic per list and tile reserves the tile's range, so both lists hold
-// ascending ids within a tile.
+// classifies kPartPerThread of them, a block scan places them in LDS, one
+// atomic per list and tile reserves the tile's range, and the block stores
+// both ranges with consecutive threads on consecutive entries; both lists
+// hold ascending ids within a tile.
 constexpr uint32_t kPartPerThread = 16;
 constexpr uint32_t kPartBlock = 256;
 constexpr uint64_t kPartTile = (uint64_t)kPartPerThread * kPartBlock;
@@ -894,6 +895,7 @@ constexpr uint32_t kPartMaxBlocks = 1024;
 __global__ __launch_bounds__(kPartBlock) void k_partition(const DevArgs *__restrict__ a) {
     __shared__ uint32_t s_sum[kPartBlock / kWave];
     __shared__ uint32_t s_base[2];
+    __shared__ uint32_t s_ids[kPartTile];   // read-only ids from the front, update ids from the back
     const uint32_t n = a->n_txns;
     const gmem<uint8_t> *nw = glob(a->nw);
     gmem<uint32_t> *order = glob(a->order);
@@ -930,19 +932,23 @@ __global__ __launch_bounds__(kPartBlock) void k_partition(const DevArgs *__restr
             s_base[1] = (total & 0xFFFFu) ? __hip_atomic_fetch_add(&a->hot->n_upd.v, total & 0xFFFFu,
                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         }
-        __syncthreads();
         const uint32_t excl = before + inc - v;
-        uint32_t pr = s_base[0] + (excl >> 16), pu = s_base[1] + (excl & 0xFFFFu);
+        uint32_t pr = excl >> 16, pu = excl & 0xFFFFu;   // within the tile
 #pragma unroll
         for (uint32_t k = 0; k < kPartPerThread; ++k) {
             if (first + k < n) {
                 if ((kinds >> k) & 1u)
-                    order[n - 1 - pu++] = (uint32_t)(first + k);
+                    s_ids[kPartTile - 1 - pu++] = (uint32_t)(first + k);
                 else
-                    order[pr++] = (uint32_t)(first + k);
+                    s_ids[pr++] = (uint32_t)(first + k);
             }
         }
-        __syncthreads();   // s_sum and s_base are reused by the next tile
+        __syncthreads();
+        const uint32_t tot_ro = total >> 16, tot_upd = total & 0xFFFFu, base_ro = s_base[0], base_upd = s_base[1];
+        for (uint32_t k = threadIdx.x; k < tot_ro; k += kPartBlock) order[base_ro + k] = s_ids[k];
+        for (uint32_t k = threadIdx.x; k < tot_upd; k += kPartBlock)
+            order[n - 1 - (base_upd + k)] = s_ids[kPartTile - 1 - k];
+        __syncthreads();   // s_sum, s_base and s_ids are reused by the next tile
     }
 }
 

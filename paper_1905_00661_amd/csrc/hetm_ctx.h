@@ -43,6 +43,7 @@ struct hetm_ctx {
 
     DevArgs args{};                  // host copy of the current arguments
     hipEvent_t ev[4] = {};
+    hipEvent_t ev_kernel = nullptr;    // PLAIN rounds: just before the transaction kernel
     // The round graph, one per merge policy (captured on first use).  With
     // the double-buffered merge and CPU wins, the dirty-granule compaction
     // and gather run on a branch of their own beside validation and apply.

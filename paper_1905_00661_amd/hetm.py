@@ -69,7 +69,7 @@ class hetm_round_result(ctypes.Structure):
                 ("n_local_retries", U64), ("n_dirty", U64), ("n_runs", U64), ("max_ts", U64),
                 ("merge_pending", U32), ("doomed", U32), ("us_exec", ctypes.c_double), ("us_validate", ctypes.c_double),
                 ("us_merge", ctypes.c_double), ("us_total", ctypes.c_double),
-                ("host_discarded", U32), ("gpu_losses", U32)]
+                ("host_discarded", U32), ("gpu_losses", U32), ("us_exec_kernel", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
