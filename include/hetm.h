@@ -285,17 +285,24 @@ typedef struct {
 
 /* A whole round: execution, validation+apply, merge, reset, in the
  * context's mode.  With async_merge, a successful round returns as soon as
- * its dirty granules are staged in HBM (merge_pending = 1); the host replica
- * holds them after hetm_sync or once the next round returns (each round
- * waits for the previous merge before starting its own).  Until then the
- * caller must not write the host replica: the merge would overwrite granules
- * it shares with those writes.  A conflicting round first waits for the
- * previous round's merge, then restores its dirty granules from the host
- * replica before returning.  PLAIN launches one kernel per step and reads the
+ * its dirty granules are staged in HBM (merge_pending = 1); their copy to
+ * the host starts with the next round's transaction kernel, and the host
+ * replica holds them after hetm_sync or once the round after the next
+ * returns (two rounds' merges may be in flight, one per staging buffer).
+ * Until then the caller must not write the host replica: the merge would
+ * overwrite granules it shares with those writes.  A conflicting round
+ * first waits for every earlier merge, then restores its dirty granules
+ * from the host replica before returning.  PLAIN launches one kernel per step and reads the
  * outcome on the host before the merge; GRAPH replays one captured hipGraph
  * whose merge kernels read the outcome on the device.  Synchronizes and
  * fills *res.  On conflict every transaction of the round is reported
- * aborted and the caller may resubmit it. */
+ * aborted and the caller may resubmit it.  A round that latches a device
+ * error (a malformed transaction or log entry, the retry cap) returns it
+ * and is discarded as a conflicting round under CPU wins: its GPU
+ * transactions are undone (their granules restored from the host
+ * replica), its log chunk is not applied, its bitmaps and counters are
+ * cleared.  The host writes of that log reach the GPU replica once a
+ * corrected log carrying them is applied in a later round. */
 int hetm_round(hetm_ctx *ctx, const hetm_round_args *args, hetm_round_result *res);
 
 /* ------------------------------------------------------------- auxiliary */

@@ -178,6 +178,21 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
     return HETM_OK;
 }
 
+// A whole round that latched a device error is discarded as a conflicting
+// round is under CPU wins: the latch is cleared, the GPU's dirty granules
+// are restored from the host replica, the bitmaps and counters are reset.
+// The round's log chunk was not applied (the apply pass skips on an error).
+int discard_round(hetm_ctx *c, int32_t code, uint32_t where, const void *hdev) {
+    launch_clear_error(c->cnt, c->stream);
+    const uint32_t policy = c->args.policy;
+    c->args.policy = HETM_POLICY_CPU_WINS;   // the copy restores the device side
+    int rc = enqueue_merge(c, 1u, hdev, nullptr);
+    c->args.policy = policy;
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return fail(c, code, "device reported %s at index %u; the round was discarded", hetm_strerror(code), where);
+}
+
 // Slot layout: once the version clock has run past kClockReset, every
 // version and the clock go back to 0 before the next round (queued on the
 // context's stream, which the next round's work follows).
@@ -355,10 +370,10 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
 // the merge worker.
 int stage_to_host(hetm_ctx *c, int b, uint64_t D, void *host) {
     const uint64_t gbytes = (uint64_t)c->cfg.granule_words * c->cfg.word_bytes;
-    // every earlier merge lands before this one starts, so after a round
-    // returns only its own merge can still be in flight
-    const uint64_t prev = std::max(c->merge_seq[0], c->merge_seq[1]);
-    if (prev && hetm::merge_wait(c->merger, prev) != HETM_OK)
+    // the job that last used this host staging buffer has been scattered out
+    // of it (the other buffer's job may still be scattering: this DMA
+    // overlaps it)
+    if (c->merge_seq[b] && hetm::merge_wait(c->merger, c->merge_seq[b]) != HETM_OK)
         return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
     if (D > c->host_cap[b]) return fail(c, HETM_ECAPACITY, "%llu dirty granules", (unsigned long long)D);
     HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->ev[3], 0));      // after the round's graph
@@ -454,16 +469,19 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     int rc;
     HIP_TRY(c, hipStreamSynchronize(s));
     const DevCounters snap = *c->snap_host;
-    if (snap.error) return take_device_error(c, snap.error, snap.err_index);
     c->round_merge_seq = 0;
+    if (snap.error) {
+        // the restore reads the host replica: earlier merges land first
+        if (c->cfg.async_merge && (rc = drain_merges(c))) return rc;
+        return discard_round(c, snap.error, snap.err_index, hdev);
+    }
     if (c->cfg.async_merge) {
         if (!snap.conflict || c->args.policy == HETM_POLICY_GPU_WINS) {
             // the GPU's granules go to the host replica: a DMA of the staged granules to pinned host staging on
             // the copy stream (issued by the next round_begin, or by whatever waits for merges first), then
-            // the merge worker scatters them into the host replica.  The previous round's merge, issued when
-            // this round began, lands before this round returns.
-            const uint64_t prev = std::max(c->merge_seq[0], c->merge_seq[1]);
-            if (prev && hetm::merge_wait(c->merger, prev) != HETM_OK)
+            // the merge worker scatters them into the host replica.  The merge of the round before the last
+            // (the last job on this round's buffer) lands before this round returns.
+            if (c->merge_seq[b] && hetm::merge_wait(c->merger, c->merge_seq[b]) != HETM_OK)
                 return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
             c->merge_deferred = true;
             c->deferred_buf = b;
@@ -810,7 +828,7 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
     DevCounters k;
     if ((rc = read_counters(c, &k))) return rc;
-    if (k.error) return take_device_error(c, k.error, k.err_index);
+    if (k.error) return discard_round(c, k.error, k.err_index, hdev);
     if ((rc = enqueue_merge(c, k.conflict, hdev, r->ids_out))) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[3], s));
     HIP_TRY(c, hipStreamSynchronize(s));

@@ -354,6 +354,8 @@ __device__ __forceinline__ Split<uint64_t> make_layout<Split<uint64_t>>(const De
 // length load a word already in the chunk (a cache hit) instead of
 // branching, which keeps the loads in one straight-line block.
 constexpr uint32_t kChunk = 8;
+static_assert(kChunk == 8, "the vector result stores cover a chunk of 8");
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 
 template <typename Lay>
 __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs *__restrict__ a) {
@@ -371,6 +373,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     const gmem<uint32_t> *off = glob(a->off), *idx = glob(a->idx), *tid = glob(a->tid);
     const gmem<uint8_t> *nw = glob(a->nw);
     gmem<uint32_t> *res = glob((uint32_t *)a->results);
+    const bool res_aligned = ((uintptr_t)a->results & 15u) == 0;
     WriteBuf<uint32_t, kOplistMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
     uint32_t *ix = s_dyn + wv * max_ops * kWave + lane_id();     // ix[j * kWave]: word j of this lane's txn
     const uint32_t epoch = a->epoch;
@@ -444,15 +447,22 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
 #pragma unroll
                     for (uint32_t k = 0; k < kOplistMaxWrites; ++k) seen[k] = l[k];
                 }
+                // a whole chunk of results 16-byte aligned goes out in two 16-byte stores
+                const bool vec = res_aligned && j0 + kChunk <= L && ((o + j0) & 3u) == 0;
 #pragma unroll
                 for (uint32_t k = 0; k < kChunk; ++k) {
                     const uint32_t j = j0 + k;
                     if (j < L) {
                         ok &= !(l[k] & kLockBit) && Slot::version(l[k]) <= rv;
                         const uint32_t v = (uint32_t)l[k];
-                        res[o + j] = v;
+                        if (!vec) res[o + j] = v;
                         if (j < nwr) wb.put(w[k], v + tv);
                     }
+                }
+                if (vec) {
+                    gmem<U32x4> *r4 = (gmem<U32x4> *)(res + o + j0);
+                    r4[0] = U32x4{(uint32_t)l[0], (uint32_t)l[1], (uint32_t)l[2], (uint32_t)l[3]};
+                    r4[1] = U32x4{(uint32_t)l[4], (uint32_t)l[5], (uint32_t)l[6], (uint32_t)l[7]};
                 }
             }
             const bool upd = nwr != 0;
