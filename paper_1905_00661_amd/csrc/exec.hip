@@ -374,6 +374,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     const gmem<uint8_t> *nw = glob(a->nw);
     gmem<uint32_t> *res = glob((uint32_t *)a->results);
     const bool res_aligned = ((uintptr_t)a->results & 15u) == 0;
+    const bool idx_aligned = ((uintptr_t)a->idx & 15u) == 0;
     WriteBuf<uint32_t, kOplistMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
     uint32_t *ix = s_dyn + wv * max_ops * kWave + lane_id();     // ix[j * kWave]: word j of this lane's txn
     const uint32_t epoch = a->epoch;
@@ -404,11 +405,19 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
             L = e - o;
             malformed = e < o || L > max_ops || nwr > L || nwr > kOplistMaxWrites;
             if (malformed) L = 0;
-            // the word list, into LDS
+            // the word list, into LDS (a chunk of eight 16-byte aligned
+            // indices with two 16-byte loads)
             for (uint32_t j0 = 0; j0 < L; j0 += kChunk) {
                 uint32_t w[kChunk];
+                if (idx_aligned && j0 + kChunk <= L && ((o + j0) & 3u) == 0) {
+                    const gmem<U32x4> *q = (const gmem<U32x4> *)(idx + o + j0);
+                    const U32x4 q0 = q[0], q1 = q[1];
+                    w[0] = q0.x; w[1] = q0.y; w[2] = q0.z; w[3] = q0.w;
+                    w[4] = q1.x; w[5] = q1.y; w[6] = q1.z; w[7] = q1.w;
+                } else {
 #pragma unroll
-                for (uint32_t k = 0; k < kChunk; ++k) w[k] = idx[o + (j0 + k < L ? j0 + k : j0)];
+                    for (uint32_t k = 0; k < kChunk; ++k) w[k] = idx[o + (j0 + k < L ? j0 + k : j0)];
+                }
 #pragma unroll
                 for (uint32_t k = 0; k < kChunk; ++k)
                     if (j0 + k < L) {
