@@ -54,10 +54,10 @@ int dev_alloc(hetm_ctx *c, T **p, uint64_t bytes) {
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
 // Default transaction-kernel grid: one workgroup (4 waves) per compute unit.
-// Measured on the large synthetic round (batched loads, slot layout), fewer
-// concurrent transactions mean fewer local aborts and less cache turnover:
-// the kernel takes 894 us at 1/CU, 1016 us at 1.5/CU, 1313 us at 3/CU and
-// 1258 us at 0.5/CU.  The autotuner picks per workload.
+// Measured on the large synthetic round (slot layout, waves of one kind):
+// 586 us at 1/CU, 647 at 1.5, 714 at 2, 913 at 3 and 655 at 0.75 -- more
+// concurrent transactions abort more and queue longer on the same memory
+// path, fewer leave it idle.  The autotuner picks per workload.
 uint32_t default_exec_workgroups(int cus) { return (uint32_t)cus; }
 
 uint32_t ilog2(uint64_t x) {
