@@ -105,6 +105,15 @@ struct Serve {
                       hipMalloc((void **)&r.d_tick, mb * 4) == hipSuccess &&
                       hipEventCreateWithFlags(&r.uploaded, hipEventDisableTiming) == hipSuccess;
             if (!ok) return HETM_ENOMEM;
+            // touch the host buffers now: their first writes would otherwise
+            // fault page by page inside the first rounds
+            memset(r.h_off, 0, (mb + 1) * 4);
+            memset(r.h_idx, 0, max_ops_round * 4);
+            memset(r.h_tid, 0, mb * 4);
+            memset(r.h_nw, 0, mb);
+            memset(r.h_log, 0, nl * sizeof(hetm_log_entry4));
+            memset(r.h_res, 0, max_ops_round * 4);
+            memset(r.h_tick, 0, mb * 4);
         }
         return HETM_OK;
     }
