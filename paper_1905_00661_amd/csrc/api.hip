@@ -382,9 +382,11 @@ int stage_to_host(hetm_ctx *c, int b, uint64_t D, void *host) {
         HIP_TRY(c, hipMemcpyAsync(c->host_stage[b], c->staging[b], D * gbytes, hipMemcpyDeviceToHost, c->copy_stream));
     }
     HIP_TRY(c, hipEventRecord(c->copied[b], c->copy_stream));
-    c->merge_seq[b] = hetm::merge_submit(c->merger, c->copied[b], c->host_ids[b], c->host_stage[b], D,
-                                         (uint8_t *)host, gbytes, c->cfg.n_words * c->cfg.word_bytes);
-    c->round_merge_seq = c->merge_seq[b];
+    const uint64_t seq = hetm::merge_submit(c->merger, c->copied[b], c->host_ids[b], c->host_stage[b], D,
+                                            (uint8_t *)host, gbytes, c->cfg.n_words * c->cfg.word_bytes);
+    if (!seq) return fail(c, HETM_ENOMEM, "merge job could not be queued");
+    c->merge_seq[b] = seq;
+    c->round_merge_seq = seq;
     return HETM_OK;
 }
 
@@ -616,6 +618,10 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
             return HETM_EDEVICE;
         }
         c->merger = hetm::merge_worker_create();
+        if (!c->merger) {
+            hetm_free(c);
+            return HETM_ENOMEM;
+        }
         for (int b = 0; b < 2; ++b)
             if (hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming) != hipSuccess) {
                 hetm_free(c);

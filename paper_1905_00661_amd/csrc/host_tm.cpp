@@ -55,11 +55,16 @@ void parallel_for(uint64_t n, uint32_t threads, Fn fn) {
         return;
     }
     std::vector<std::thread> ts;
+    ts.reserve(threads);
     const uint64_t per = (n + threads - 1) / threads;
     for (uint32_t t = 0; t < threads; ++t) {
         const uint64_t lo = t * per, hi = std::min(n, lo + per);
         if (lo >= hi) break;
-        ts.emplace_back(fn, t, lo, hi);
+        try {
+            ts.emplace_back(fn, t, lo, hi);
+        } catch (...) {
+            fn(t, lo, hi);   // no thread to spare: this slice runs here
+        }
     }
     for (auto &t : ts) t.join();
 }
@@ -114,7 +119,15 @@ int hetm_host_run_transfers(hetm_host_tm *t, const uint32_t *src, const uint32_t
         if (src[i] >= t->n_words || dst[i] >= t->n_words) return HETM_EINVAL;
     int64_t *H = (int64_t *)t->H;
     if (n_threads == 0) n_threads = 1;
-    std::vector<std::vector<hetm_log_entry8>> logs(n_threads);
+    // each slice's log reserved up front (two entries per transfer at most),
+    // so the worker threads never allocate
+    std::vector<std::vector<hetm_log_entry8>> logs;
+    try {
+        logs.resize(n_threads);
+        for (auto &lg : logs) lg.reserve(2 * ((n + n_threads - 1) / n_threads));
+    } catch (...) {
+        return HETM_ENOMEM;
+    }
     parallel_for(n, n_threads, [&](uint32_t tid, uint64_t lo, uint64_t hi) {
         auto &lg = logs[tid];
         for (uint64_t i = lo; i < hi; ++i) {
@@ -160,7 +173,15 @@ int hetm_host_run_cache_puts(hetm_host_tm *t, const uint64_t *keys, uint64_t n, 
         if (keys[i] == 0) return HETM_EINVAL;
     uint32_t *H = (uint32_t *)t->H;
     if (n_threads == 0) n_threads = 1;
-    std::vector<std::vector<hetm_log_entry4>> logs(n_threads);
+    // each slice's log reserved up front (twelve entries per PUT), so the
+    // worker threads never allocate
+    std::vector<std::vector<hetm_log_entry4>> logs;
+    try {
+        logs.resize(n_threads);
+        for (auto &lg : logs) lg.reserve(12 * ((n + n_threads - 1) / n_threads));
+    } catch (...) {
+        return HETM_ENOMEM;
+    }
     parallel_for(n, n_threads, [&](uint32_t tid, uint64_t lo, uint64_t hi) {
         auto &lg = logs[tid];
         for (uint64_t i = lo; i < hi; ++i) {

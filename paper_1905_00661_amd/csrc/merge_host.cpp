@@ -86,8 +86,12 @@ struct ScatterPool {
             if (--pending == 0) cv_done.notify_one();
         }
     }
+    // as many helpers as start (none if the system refuses threads)
     void start() {
-        for (unsigned k = 0; k + 1 < kMaxParts; ++k) th.emplace_back([this, k] { helper(k); });
+        try {
+            for (unsigned k = 0; k + 1 < kMaxParts; ++k) th.emplace_back([this, k] { helper(k); });
+        } catch (...) {
+        }
     }
     void finish() {
         {
@@ -99,7 +103,8 @@ struct ScatterPool {
     }
     void scatter(const Job &j) {
         const uint64_t bytes = j.n * j.gbytes;
-        const unsigned p = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(kMaxParts, bytes >> 21));
+        const unsigned p = (unsigned)std::max<uint64_t>(
+            1, std::min<uint64_t>(std::min<uint64_t>(kMaxParts, th.size() + 1), bytes >> 21));
         if (p == 1 || th.empty()) {
             scatter_range(j, 0, j.n);
             return;
@@ -157,10 +162,19 @@ struct MergeWorker {
 };
 
 MergeWorker *merge_worker_create() {
-    auto *w = new MergeWorker;
-    w->pool.start();
-    w->th = std::thread([w] { w->run(); });
-    return w;
+    MergeWorker *w = nullptr;
+    try {
+        w = new MergeWorker;
+        w->pool.start();
+        w->th = std::thread([w] { w->run(); });
+        return w;
+    } catch (...) {
+        if (w) {
+            w->pool.finish();
+            delete w;
+        }
+        return nullptr;
+    }
 }
 
 void merge_worker_destroy(MergeWorker *w) {
@@ -180,8 +194,12 @@ uint64_t merge_submit(MergeWorker *w, hipEvent_t ready, const uint32_t *ids, con
     uint64_t seq;
     {
         std::lock_guard<std::mutex> l(w->m);
+        try {
+            w->q.push_back(Job{ready, ids, data, n, host, gbytes, total_bytes, w->issued + 1});
+        } catch (...) {
+            return 0;
+        }
         seq = ++w->issued;
-        w->q.push_back(Job{ready, ids, data, n, host, gbytes, total_bytes, seq});
     }
     w->cv_job.notify_one();
     return seq;

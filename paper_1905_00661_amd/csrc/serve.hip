@@ -30,7 +30,15 @@ void parallel_for(uint64_t n, uint64_t grain, F f) {
     }
     const uint64_t per = (n + T - 1) / T;
     std::vector<std::thread> th;
-    for (unsigned t = 1; t < T; ++t) th.emplace_back(f, std::min(n, t * per), std::min(n, (t + 1) * per));
+    th.reserve(T);
+    for (unsigned t = 1; t < T; ++t) {
+        const uint64_t lo = std::min(n, t * per), hi = std::min(n, (t + 1) * per);
+        try {
+            th.emplace_back(f, lo, hi);
+        } catch (...) {
+            f(lo, hi);   // no thread to spare: this slice runs here
+        }
+    }
     f(0, std::min(n, per));
     for (auto &x : th) x.join();
 }
@@ -436,12 +444,19 @@ extern "C" int hetm_serve(hetm_ctx *c, const hetm_serve_spec *sp, void *host_rep
     rep->round_conflict = rc_out, rep->max_rounds = max_rounds, rep->round_log_end = rl_out;
 
     Serve S(c, *sp, host_replica, rep);
-    S.latency_us.assign(sp->n_requests, 0.0);
-    int rc = S.alloc();
-    if (rc == HETM_OK) {
-        S.t0 = clk::now();
-        rc = sp->pipelined ? S.run_pipelined() : S.run_plain();
-        if (rc == HETM_OK) rc = hetm_sync(c);
+    int rc;
+    try {   // no C++ exception crosses the C ABI
+        S.latency_us.assign(sp->n_requests, 0.0);
+        rc = S.alloc();
+        if (rc == HETM_OK) {
+            S.t0 = clk::now();
+            rc = sp->pipelined ? S.run_pipelined() : S.run_plain();
+            if (rc == HETM_OK) rc = hetm_sync(c);
+        }
+    } catch (const std::bad_alloc &) {
+        rc = HETM_ENOMEM;
+    } catch (...) {
+        rc = HETM_EDEVICE;
     }
     S.release();
     if (rc) return rc;
@@ -449,7 +464,12 @@ extern "C" int hetm_serve(hetm_ctx *c, const hetm_serve_spec *sp, void *host_rep
     rep->wall_s = S.last_commit_s - (sp->n_requests ? sp->arrival_s[0] : 0.0);
     rep->throughput = rep->wall_s > 0 ? S.served / rep->wall_s : 0;
     if (sp->n_requests) {
-        std::vector<double> l = S.latency_us;
+        std::vector<double> l;
+        try {
+            l = S.latency_us;
+        } catch (...) {
+            return HETM_ENOMEM;
+        }
         std::sort(l.begin(), l.end());
         auto pct = [&](double q) { return l[std::min<size_t>(l.size() - 1, (size_t)(q * (l.size() - 1) + 0.5))]; };
         rep->p50_latency_us = pct(0.50);
