@@ -334,43 +334,43 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_count(const DevArgs *_
     }
 }
 
-// A block takes its kScanWordsPerBlock bitmap words in kWordsPerThread
-// rounds of one word per thread: a round's ids (at most 32 per thread) are
-// placed in LDS by a block scan, then stored with consecutive threads on
-// consecutive ids.  Dirty granules cluster (a hot range can fill whole
-// bitmap words), and a thread storing its own ids one by one would write
-// up to 256 scattered positions in turn.
+// One block per kScanThreads bitmap words (one word per thread), in one
+// round: the block adds up the popcounts of the words before its own within
+// its counting block (at most kWordsPerThread - 1 coalesced loads per
+// thread) to the counting block's offset, places its ids in LDS with a
+// block scan and stores them with consecutive threads on consecutive ids.
+// Dirty granules cluster (a hot range fills whole bitmap words); a thread
+// storing its own ids one by one made 256 scattered stores in turn, and
+// eight rounds per block left the kernel slow beside the apply pass.
 __global__ __launch_bounds__(kScanThreads) void k_compact_emit(const DevArgs *__restrict__ a) {
     __shared__ uint32_t sh[kScanThreads / kWave];
     __shared__ uint32_t s_ids[kScanThreads * 32];
     const uint32_t *ws = a->ws;
     const uint32_t nbw = a->n_bm_words;
     uint32_t *ids = a->ids_scratch, *ids_out = a->ids_out;
-    uint32_t pos = ld_agent(&a->blocksums[blockIdx.x]);   // in flight with the bitmap loads
-    const uint64_t blk0 = (uint64_t)blockIdx.x * kScanWordsPerBlock + threadIdx.x;
-    uint32_t x[kWordsPerThread];
-#pragma unroll
-    for (uint32_t r = 0; r < kWordsPerThread; ++r) {
-        const uint64_t w = blk0 + r * kScanThreads;
-        x[r] = w < nbw ? ws[w] : 0u;
+    const uint32_t cb = blockIdx.x / kWordsPerThread, sub = blockIdx.x % kWordsPerThread;   // counting block, part
+    const uint64_t cb0 = (uint64_t)cb * kScanWordsPerBlock;
+    const uint64_t w = cb0 + (uint64_t)sub * kScanThreads + threadIdx.x;
+    const uint32_t base = ld_agent(&a->blocksums[cb]);   // in flight with the bitmap loads
+    const uint32_t x = w < nbw ? ws[w] : 0u;
+    uint32_t before = 0;
+    for (uint32_t k = 0; k < sub; ++k) {
+        const uint64_t v = cb0 + (uint64_t)k * kScanThreads + threadIdx.x;
+        before += v < nbw ? __popc(ws[v]) : 0u;
     }
-#pragma unroll
-    for (uint32_t r = 0; r < kWordsPerThread; ++r) {
-        const uint64_t w = blk0 + r * kScanThreads;
-        uint32_t v = x[r], total;
-        uint32_t p = block_exclusive_scan(__popc(v), sh, total);
-        while (v) {
-            s_ids[p++] = (uint32_t)(w * 32 + __ffs(v) - 1);
-            v &= v - 1;
-        }
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < total; k += kScanThreads) {
-            const uint32_t g = s_ids[k];
-            ids[pos + k] = g;
-            if (ids_out) ids_out[pos + k] = g;
-        }
-        pos += total;
-        __syncthreads();   // s_ids is refilled by the next round
+    before = block_sum(before, sh);
+    uint32_t v = x, total;
+    uint32_t p = block_exclusive_scan(__popc(v), sh, total);
+    while (v) {
+        s_ids[p++] = (uint32_t)(w * 32 + __ffs(v) - 1);
+        v &= v - 1;
+    }
+    __syncthreads();
+    const uint32_t pos = base + before;
+    for (uint32_t k = threadIdx.x; k < total; k += kScanThreads) {
+        const uint32_t g = s_ids[k];
+        ids[pos + k] = g;
+        if (ids_out) ids_out[pos + k] = g;
     }
 }
 
@@ -602,7 +602,7 @@ void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipSt
 
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_compact_count, dim3(n_scan_blocks), dim3(kScanThreads), 0, s, a);
-    hipLaunchKernelGGL(k_compact_emit, dim3(n_scan_blocks), dim3(kScanThreads), 0, s, a);
+    hipLaunchKernelGGL(k_compact_emit, dim3(n_scan_blocks * kWordsPerThread), dim3(kScanThreads), 0, s, a);
 }
 
 void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, bool slot, hipStream_t s) {
