@@ -322,3 +322,35 @@ def test_async_merge_back_to_back(hm, wl):
     assert np.array_equal(host, H)
     assert np.array_equal(ctx.read_state(hm.HETM_STATE_TS), TS)
     ctx.close()
+
+
+def test_async_merge_close_without_sync(hm, wl):
+    """With the double-buffered merge, a round's copy to the host starts with
+    the next round; closing the context without a sync still issues the last
+    round's copy and lands every merge in the host replica, in order."""
+    import torch
+    import oracle as orc
+    N, G = 1 << 16, 16
+    init = np.random.default_rng(91).integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    ctx = hm.Context(N, 4, G, init=init, batch_capacity=1 << 12, log_capacity=1 << 10, mode=1, async_merge=True)
+    host_t = hm.pinned(N * 4)
+    host = host_t.numpy().view(np.uint32)
+    host[:] = init
+    S, H, TS, floor = init.copy(), init.copy(), np.zeros(N, np.uint64), 0
+    keep = []
+    for r in range(3):
+        batch = wl.c2_batch(np.random.default_rng(400 + r), N, 1 << 12, 0.5, tid0=r << 12)
+        log = wl.host_log_uniform(np.random.default_rng(500 + r), 1 << 10, N // 2, N, floor)
+        host[N // 2:] = wl.host_replica(host.copy(), log)[N // 2:]
+        H = wl.host_replica(H, log)
+        b = hm.Batch(1, batch)
+        log_t = hm.to_device(log)
+        torch.cuda.synchronize()
+        say(f"close without sync: round {r}")
+        res = ctx.round(b, log_t, log.shape[0], host_t)
+        keep.append((b, log_t))
+        o = orc.round_oplist(S, H, TS, G, batch, orc.order_from_tickets(b.tickets_np(), even_ties=True), log, floor)
+        assert res.conflict == o["conflict"] == 0 and res.merge_pending == 1
+        floor = int(o["max_ts"])
+    ctx.close()
+    assert np.array_equal(host, H)
