@@ -267,8 +267,9 @@ typedef struct {
     uint64_t n_dirty;          /* write-set granules merged                     */
     uint64_t n_runs;           /* maximal runs of consecutive dirty granules    */
     uint64_t max_ts;           /* watermark after the round                     */
-    uint32_t merge_pending;    /* 1: the copy to the host replica is still in
-                                  flight (async_merge); hetm_sync waits for it   */
+    uint32_t merge_pending;    /* 1: the copy to the host replica is still to
+                                  be issued or in flight (async_merge);
+                                  hetm_sync issues it and waits for it         */
     uint32_t doomed;           /* 1: early validation found the conflict and the
                                   transaction kernels stopped short            */
     double   us_exec;          /* step times from HIP events (PLAIN mode)       */
@@ -292,9 +293,10 @@ typedef struct {
  * Until then the caller must not write the host replica: the merge would
  * overwrite granules it shares with those writes.  A conflicting round
  * first waits for every earlier merge, then restores its dirty granules
- * from the host replica before returning.  PLAIN launches one kernel per step and reads the
- * outcome on the host before the merge; GRAPH replays one captured hipGraph
- * whose merge kernels read the outcome on the device.  Synchronizes and
+ * from the host replica before returning.  PLAIN launches one kernel per
+ * step and reads the outcome on the host before the merge; GRAPH replays
+ * one captured hipGraph whose merge kernels read the outcome on the
+ * device.  Synchronizes and
  * fills *res.  On conflict every transaction of the round is reported
  * aborted and the caller may resubmit it.  A round that latches a device
  * error (a malformed transaction or log entry, the retry cap) returns it
