@@ -6,7 +6,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <condition_variable>
 #include <deque>
+#include <functional>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -19,29 +22,72 @@ using clk = std::chrono::steady_clock;
 
 double seconds_since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
 
-// Runs f(lo, hi) over [0, n) split across up to 6 threads (this one
-// included), one per `grain` items; small ranges stay on this thread.
-template <class F>
-void parallel_for(uint64_t n, uint64_t grain, F f) {
-    const unsigned T = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(6, n / grain));
-    if (T == 1) {
-        f(0, n);
-        return;
-    }
-    const uint64_t per = (n + T - 1) / T;
+// Persistent helper threads of the serving loop: run(n, grain, f) cuts
+// [0, n) into up to (helpers + 1) slices of at least `grain` items and runs
+// f(lo, hi) on each, slice 0 on the calling thread.  Threads that cannot be
+// started are simply not there (fewer slices).
+struct Pool {
+    static constexpr unsigned kMaxThreads = 12;
     std::vector<std::thread> th;
-    th.reserve(T);
-    for (unsigned t = 1; t < T; ++t) {
-        const uint64_t lo = std::min(n, t * per), hi = std::min(n, (t + 1) * per);
+    std::mutex m;
+    std::condition_variable cv_go, cv_done;
+    const std::function<void(uint64_t, uint64_t)> *fn = nullptr;
+    uint64_t n = 0, per = 0, gen = 0;
+    unsigned parts = 0, pending = 0;
+    bool stop = false;
+
+    void start() {
         try {
-            th.emplace_back(f, lo, hi);
+            for (unsigned k = 0; k + 1 < kMaxThreads; ++k) th.emplace_back([this, k] { helper(k); });
         } catch (...) {
-            f(lo, hi);   // no thread to spare: this slice runs here
         }
     }
-    f(0, std::min(n, per));
-    for (auto &x : th) x.join();
-}
+    void finish() {
+        {
+            std::lock_guard<std::mutex> l(m);
+            stop = true;
+        }
+        cv_go.notify_all();
+        for (auto &x : th) x.join();
+        th.clear();
+    }
+    void helper(unsigned k) {   // takes slice k + 1
+        uint64_t seen = 0;
+        for (;;) {
+            std::unique_lock<std::mutex> l(m);
+            cv_go.wait(l, [&] { return stop || gen != seen; });
+            if (stop) return;
+            seen = gen;
+            const auto *f = fn;
+            const uint64_t lo = std::min(n, (uint64_t)(k + 1) * per), hi = std::min(n, lo + per);
+            const bool mine = k + 1 < parts && lo < hi;
+            l.unlock();
+            if (mine) (*f)(lo, hi);
+            l.lock();
+            if (--pending == 0) cv_done.notify_one();
+        }
+    }
+    void run(uint64_t count, uint64_t grain, const std::function<void(uint64_t, uint64_t)> &f) {
+        const unsigned p = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(th.size() + 1, count / grain));
+        if (p == 1) {
+            f(0, count);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> l(m);
+            fn = &f;
+            n = count;
+            per = (count + p - 1) / p;
+            parts = p;
+            pending = (unsigned)th.size();
+            ++gen;
+        }
+        cv_go.notify_all();
+        f(0, std::min(count, per));
+        std::unique_lock<std::mutex> l(m);
+        cv_done.wait(l, [&] { return pending == 0; });
+    }
+};
 
 // Adds the time from its construction to its destruction to *acc (microseconds).
 struct Span {
@@ -73,6 +119,7 @@ struct Serve {
     hetm_serve_report *rep;
     hipStream_t upload = nullptr;
     RoundSet set[2];
+    Pool pool;
     std::deque<uint64_t> requeue;
     uint64_t head = 0;            // next request not yet admitted
     uint64_t log_pos = 0;         // host log entries consumed
@@ -96,6 +143,7 @@ struct Serve {
         max_ops_round = mb * c->cfg.max_txn_ops;
         const uint64_t nl = std::max<uint64_t>(sp.host_log_per_round, 1);
         if (hipStreamCreateWithFlags(&upload, hipStreamNonBlocking) != hipSuccess) return HETM_EDEVICE;
+        pool.start();
         for (auto &r : set) {
             bool ok = hipHostMalloc((void **)&r.h_off, (mb + 1) * 4, 0) == hipSuccess &&
                       hipHostMalloc((void **)&r.h_idx, max_ops_round * 4, 0) == hipSuccess &&
@@ -137,6 +185,7 @@ struct Serve {
             if (r.uploaded) (void)hipEventDestroy(r.uploaded);
         }
         if (upload) (void)hipStreamDestroy(upload);
+        pool.finish();
     }
 
     uint64_t arrived() const {
@@ -178,7 +227,7 @@ struct Serve {
             o += (uint32_t)req_ops(r.reqs[k]);
         }
         r.h_off[n_req] = o;
-        parallel_for(n_req, 16384, [&](uint64_t lo, uint64_t hi) {
+        pool.run(n_req, 2048, [&](uint64_t lo, uint64_t hi) {
             for (uint64_t k = lo; k < hi; ++k) {
                 const uint64_t i = r.reqs[k];
                 const uint32_t *src = sp.idx + sp.offsets[i];
@@ -266,7 +315,7 @@ struct Serve {
                 hipMemcpy(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
                 return HETM_EDEVICE;
         }
-        parallel_for(n, 16384, [&](uint64_t lo, uint64_t hi) {
+        pool.run(n, 2048, [&](uint64_t lo, uint64_t hi) {
             for (uint64_t k = lo; k < hi; ++k) {
                 const uint64_t i = r.reqs[k];
                 if (rep->results) {
