@@ -86,7 +86,11 @@ def serve_forms(args, hm, wl, torch) -> dict:
     """The serving configuration: open-loop Poisson arrivals of lognormal
     (median 4, capped at 64 ops) transactions over a 2^27-word STMR with 5%
     hot words; rounds admitted under a 2 GiB budget; continuous batching
-    (pipelined) against plain per-round serving at the same rate."""
+    (pipelined) against plain per-round serving at the same rate.  Each form
+    serves the stream once untimed on its context (first kernel launches,
+    graph capture, first copies of the process and context), then again
+    for the reported figures, its host log moved later in time so that it
+    follows the first call's."""
     N = 1 << 27
     host_lo = N - N // 16
     g = wl.rng("c5", 0, 3)
@@ -107,13 +111,19 @@ def serve_forms(args, hm, wl, torch) -> dict:
         ctx = hm.Context(N, 4, 64, init=init, max_ops=64, batch_capacity=1 << 20, log_capacity=per_round, **kw)
         host = hm.pinned(N * 4)
         host.numpy()[:] = init.view(np.uint8)
-        o = ctx.serve(req["arrival_s"], req["batch"], host, hlog, per_round, 1 << 20, 2 << 30, pipelined)
+        ctx.serve(req["arrival_s"], req["batch"], host, hlog, per_round, 1 << 20, 2 << 30, pipelined)
+        ctx.sync()
+        later = hlog.copy()
+        later["ts"] += np.uint64(1 << 40)
+        st0 = ctx.stats()
+        o = ctx.serve(req["arrival_s"], req["batch"], host, later, per_round, 1 << 20, 2 << 30, pipelined)
         st = ctx.stats()
         ctx.close()
         res[name] = {"throughput_txn_s": o["throughput"], "p50_latency_us": o["p50_latency_us"],
                      "p99_latency_us": o["p99_latency_us"], "rounds": int(o["rounds"]),
                      "conflicted_rounds": int(o["conflicted_rounds"]),
-                     "host_scatter_ms": st.us_host_scatter / 1e3, "merge_wait_ms": st.us_merge_wait / 1e3,
+                     "host_scatter_ms": (st.us_host_scatter - st0.us_host_scatter) / 1e3,
+                     "merge_wait_ms": (st.us_merge_wait - st0.us_merge_wait) / 1e3,
                      "serving_thread_ms": {k: round(o["us_" + k] / 1e3, 2) for k in
                                            ("pack", "wait_round", "settle", "host_commit", "wait_merge", "idle")}}
     return res

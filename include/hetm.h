@@ -382,10 +382,15 @@ uint64_t hetm_state_bytes(hetm_ctx *ctx, uint32_t what);
  * A conflicting round is aborted (CPU wins, §IV-E) and its requests are
  * admitted again first.  Starvation guard (§IV-E): with starvation_limit K,
  * after K aborted rounds in a row the next round to be packed carries no
- * host writes, so it validates; the host's log waits for the round after; a request's latency runs from its arrival to the
- * commit of the round that executed it successfully.  All arrays are host
- * memory owned by the caller.  Errors: EINVAL, ESTATE (context mode),
- * ECAPACITY (a request larger than the budget), latched device errors. */
+ * host writes, so it validates; the host's log waits for the round after.
+ * A request's latency runs from its arrival to the commit of the round that
+ * executed it successfully.  The first rounds served in a process, and the
+ * first on a context, carry one-time set-up (first kernel launches, graph
+ * capture, first copies of each kind), whose backlog shows in that call's
+ * tail latency; a later call on the context runs without it.  All arrays
+ * are host memory owned by the caller.  Errors: EINVAL, ESTATE (context
+ * mode), ECAPACITY (a request larger than the budget), latched device
+ * errors. */
 typedef struct {
     uint64_t        n_requests;
     const double   *arrival_s;          /* [n] seconds from the start, non-decreasing */

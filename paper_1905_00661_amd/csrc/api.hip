@@ -53,6 +53,14 @@ int dev_alloc(hetm_ctx *c, T **p, uint64_t bytes) {
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
+// Write one byte of every 4 KiB page of a fresh pinned buffer, so that the
+// host's first accesses to it (the merge worker's scatter) do not fault page
+// by page inside the first rounds.
+void touch_pages(void *p, uint64_t bytes) {
+    volatile uint8_t *q = (volatile uint8_t *)p;
+    for (uint64_t i = 0; i < bytes; i += 4096) q[i] = 0;
+}
+
 // Default transaction-kernel grid: one workgroup (4 waves) per compute unit.
 // Measured on the large synthetic round (slot layout, waves of one kind):
 // 586 us at 1/CU, 647 at 1.5, 714 at 2, 913 at 3 and 655 at 0.75 -- more
@@ -611,6 +619,8 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
                 hetm_free(c);
                 return HETM_ENOMEM;
             }
+            touch_pages(c->host_stage[b], nG * G * k.word_bytes);
+            touch_pages(c->host_ids[b], nG * 4);
             c->host_cap[b] = nG;
         }
         if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
