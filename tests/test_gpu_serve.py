@@ -114,6 +114,32 @@ def test_serve_matches_oracle(hm, wl, pipelined, rate, inject):
     ctx.close()
 
 
+@pytest.mark.parametrize("pipelined", [True, False])
+def test_serve_twice_on_one_context(hm, wl, pipelined):
+    """Two serve calls on one context, the second with the host log moved
+    later in time: each call matches the oracle replay continued from the
+    state the previous call left, and both replicas agree after each."""
+    g = wl.rng("c5", 0, 3)
+    init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    req = wl.c5_requests(g, 20000, 2e7, n_words=N, host_lo=HOST_LO)
+    log = host_stream(wl, 5, 1 << 20, HOST_LO, N)
+    ctx = make_ctx(hm, init, pipelined)
+    host_t = hm.pinned(N * 4)
+    host_t.numpy()[:] = init.view(np.uint8)
+    S = init
+    for call in range(2):
+        lg = log.copy()
+        lg["ts"] += np.uint64(call << 40)
+        out = ctx.serve(req["arrival_s"], req["batch"], host_t, lg, 4096, 8192, 64 << 20, pipelined)
+        say(f"serve call {call} pipelined={pipelined}: rounds={out['rounds']} p99={out['p99_latency_us']:.0f}us")
+        assert out["served"] == 20000
+        S, res = replay_served(S, req["batch"], out, lg, 4096, 64)
+        assert np.array_equal(out["results"], res), f"call {call}: request results differ from the oracle replay"
+        assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S)
+        assert np.array_equal(host_t.numpy().view(np.uint32), S)
+    ctx.close()
+
+
 @pytest.mark.parametrize("pipelined", [False, True])
 def test_serve_starvation_guard(hm, wl, pipelined):
     """Every host log chunk writes a hot GPU word, so every round with host
