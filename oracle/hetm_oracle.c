@@ -354,19 +354,23 @@ int orc_validate(const void *log, int W, uint64_t n, const uint32_t *RS, uint64_
  * outcome is the entry with the largest timestamp per word.
  *
  * Timestamps must totally order the updates of one word (§IV-B), so the
- * result is undetermined when a word's winning timestamp is carried by two
- * or more entries -- of this chunk, or of this chunk and an earlier chunk
- * of the same round.  That case returns -3 after the apply; ties below a
- * word's winning timestamp do not change the result and pass.
+ * result is undetermined when the timestamp that would win a word is
+ * carried by two or more entries -- two of this chunk, or one of this chunk
+ * and the winner an earlier chunk of the same round left in TS.  Ties below
+ * a word's winning timestamp do not change the result and pass.
  *
- * Preconditions, checked before anything is applied: word < N (else -1) and
- * floor < ts < 2^63 (else -3), where floor is the largest timestamp applied
- * in earlier rounds.  *max_ts receives the largest ts seen.
+ * A chunk is checked whole before anything of it is applied; a chunk that
+ * fails a check applies nothing (S and TS unchanged):
+ *   word < N (else -1);  floor < ts < 2^63 (else -3), where floor is the
+ *   largest timestamp applied in earlier rounds;  no tie at a winning
+ *   timestamp (else -3).
+ * *max_ts receives the largest ts of the chunk (floor if it is empty).
  */
-static int cmp_u64_pair(const void *a, const void *b)
+static int cmp_word_ts(const void *a, const void *b)
 {
-    const uint64_t *x = a, *y = b;
-    return x[0] < y[0] ? -1 : x[0] > y[0] ? 1 : 0;
+    const uint64_t *x = a, *y = b;           /* (word, ts) pairs */
+    if (x[0] != y[0]) return x[0] < y[0] ? -1 : 1;
+    return x[1] < y[1] ? -1 : x[1] > y[1] ? 1 : 0;
 }
 
 int orc_apply(void *S, int W, uint64_t *TS, uint64_t N, const void *log, uint64_t n,
@@ -375,43 +379,43 @@ int orc_apply(void *S, int W, uint64_t *TS, uint64_t N, const void *log, uint64_
     if (W != 4 && W != 8) return ORC_EINVAL;
     for (uint64_t k = 0; k < n; k++)
         if (entry_word(log, W, k) >= N) return ORC_EINVAL;
+    uint64_t mx = floor;
     for (uint64_t k = 0; k < n; k++) {
         uint64_t ts = entry_ts(log, W, k);
         if (ts <= floor || ts >= TS_LIMIT) return ORC_EORDER;
-    }
-    uint64_t *before = malloc((n ? n : 1) * sizeof(uint64_t));
-    if (!before) return ORC_EINVAL;
-    for (uint64_t k = 0; k < n; k++) before[k] = TS[entry_word(log, W, k)];
-    uint64_t mx = floor;
-    for (uint64_t k = 0; k < n; k++) {
-        uint64_t w = entry_word(log, W, k), ts = entry_ts(log, W, k);
         if (ts > mx) mx = ts;
-        if (ts > TS[w]) {                      /* freshness test */
+    }
+    /* the tie check: group the chunk's (word, ts) pairs by word; the last
+     * pair of a group carries the word's largest ts m.  If m would win
+     * (m > TS[w]) it must be carried by one entry only; if m equals TS[w]
+     * it ties the winner of an earlier chunk. */
+    uint64_t *pairs = malloc((n ? n : 1) * 2 * sizeof(uint64_t));
+    if (!pairs) return ORC_EINVAL;
+    for (uint64_t k = 0; k < n; k++) {
+        pairs[2 * k] = entry_word(log, W, k);
+        pairs[2 * k + 1] = entry_ts(log, W, k);
+    }
+    qsort(pairs, n, 2 * sizeof(uint64_t), cmp_word_ts);
+    int rc = ORC_OK;
+    for (uint64_t i = 0; i < n && rc == ORC_OK; i++) {
+        int last_of_word = i + 1 == n || pairs[2 * (i + 1)] != pairs[2 * i];
+        if (!last_of_word) continue;
+        uint64_t w = pairs[2 * i], m = pairs[2 * i + 1];
+        int dup = i > 0 && pairs[2 * (i - 1)] == w && pairs[2 * (i - 1) + 1] == m;
+        if (m == TS[w] || (m > TS[w] && dup)) rc = ORC_EORDER;
+    }
+    free(pairs);
+    if (rc != ORC_OK) return rc;
+    for (uint64_t k = 0; k < n; k++) {         /* the freshness rule, entry by entry */
+        uint64_t w = entry_word(log, W, k), ts = entry_ts(log, W, k);
+        if (ts > TS[w]) {
             if (W == 4) ((uint32_t *)S)[w] = ((const orc_entry4 *)log)[k].value;
             else        ((uint64_t *)S)[w] = ((const orc_entry8 *)log)[k].value;
             TS[w] = ts;
         }
     }
-    /* ties at a word's winning timestamp: the winners of this chunk sorted
-     * by word must be distinct, and none may equal a winner of an earlier
-     * chunk (its timestamp already in TS before this chunk) */
-    int rc = ORC_OK;
-    uint64_t *win = malloc((n ? n : 1) * sizeof(uint64_t));
-    uint64_t nwin = 0;
-    if (!win) { free(before); return ORC_EINVAL; }
-    for (uint64_t k = 0; k < n; k++) {
-        uint64_t w = entry_word(log, W, k), ts = entry_ts(log, W, k);
-        if (ts != TS[w]) continue;
-        if (before[k] == ts) rc = ORC_EORDER;
-        win[nwin++] = w;
-    }
-    qsort(win, nwin, sizeof(uint64_t), cmp_u64_pair);
-    for (uint64_t i = 1; i < nwin; i++)
-        if (win[i] == win[i - 1]) rc = ORC_EORDER;
-    free(win);
-    free(before);
     if (max_ts) *max_ts = mx;
-    return rc;
+    return ORC_OK;
 }
 
 /* -------------------------------------------------------------- merge */

@@ -210,6 +210,8 @@ def _lww(S0, log, TS0=None):
     w, v, ts = log["word"].astype(np.int64), log["value"], log["ts"]
     keep = np.ones(w.shape[0], bool) if TS0 is None else ts > TS0[w]
     w, v, ts = w[keep], v[keep], ts[keep]
+    if w.shape[0] == 0:
+        return S
     o = np.lexsort((ts, w))
     last = np.r_[w[o][1:] != w[o][:-1], True]
     S[w[o][last]] = v[o][last]
@@ -269,8 +271,9 @@ def test_apply_preconditions(orc):
     huge = _mk_log([(1, 5, 11), (2, 5, 1 << 63)])
     assert orc.apply_rc(S, TS, huge, 10) == orc.EORDER
     assert np.array_equal(S, np.arange(N)) and not TS.any()     # nothing applied
-    dup = _mk_log([(3, 5, 20), (3, 6, 20)])
+    dup = _mk_log([(3, 5, 20), (3, 6, 20), (4, 1, 12)])
     assert orc.apply_rc(S, TS, dup, 10) == orc.EORDER
+    assert np.array_equal(S, np.arange(N)) and not TS.any()     # a tied chunk applies nothing either
 
 
 def test_apply_ties_only_matter_at_the_winner(orc):
@@ -285,11 +288,57 @@ def test_apply_ties_only_matter_at_the_winner(orc):
         assert S[3] == 7 and TS[3] == 30
     S, TS = np.zeros(N, np.uint32), np.zeros(N, np.uint64)
     assert orc.apply_rc(S, TS, _mk_log([(3, 5, 20), (4, 1, 21)]), 10) == orc.OK
-    assert orc.apply_rc(S, TS, _mk_log([(3, 6, 20)]), 10) == orc.EORDER      # ties chunk 1's winner
+    assert orc.apply_rc(S, TS, _mk_log([(3, 6, 20), (5, 2, 22)]), 10) == orc.EORDER   # ties chunk 1's winner
+    assert S[3] == 5 and TS[3] == 20 and S[5] == 0 and TS[5] == 0               # ... and applies nothing
     S, TS = np.zeros(N, np.uint32), np.zeros(N, np.uint64)
     assert orc.apply_rc(S, TS, _mk_log([(3, 5, 20)]), 10) == orc.OK
     assert orc.apply_rc(S, TS, _mk_log([(3, 6, 20), (3, 9, 25)]), 10) == orc.OK   # superseded tie
     assert S[3] == 9
+
+
+def _tie_free(log, TS0):
+    """Brute force of the ordering rule on a small log: for every word the
+    largest chunk timestamp m, if it is not older than TS0[word], must be
+    carried by exactly one entry and differ from TS0[word]."""
+    for w in np.unique(log["word"]):
+        ts = log["ts"][log["word"] == w]
+        m = ts.max()
+        if m == TS0[w] or (m > TS0[w] and (ts == m).sum() > 1):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_apply_checks_whole_chunk_first(orc, seed):
+    """Small logs with many repeated (word, ts) pairs, applied as one or two
+    chunks: the oracle rejects a chunk exactly when the brute-force rule says
+    it is ambiguous, and a rejected chunk leaves S and TS as they were; an
+    accepted one gives last-writer-wins by (ts) over the fresher entries."""
+    g = np.random.default_rng(900 + seed)
+    N = 6
+    S0 = g.integers(0, 100, size=N, dtype=np.uint64).astype(np.uint32)
+    S, TS = S0.copy(), np.zeros(N, np.uint64)
+    for chunk in range(2):
+        n = int(g.integers(1, 7))
+        log = np.zeros(n, orc.LOG4)
+        log["word"] = g.integers(0, N, size=n)
+        log["value"] = g.integers(0, 1000, size=n)
+        log["ts"] = g.integers(11, 15, size=n)
+        before_S, before_TS = S.copy(), TS.copy()
+        rc = orc.apply_rc(S, TS, log, 10)
+        if _tie_free(log, before_TS):
+            assert rc == orc.OK
+            assert np.array_equal(S, _lww(before_S, log, before_TS))
+            assert np.array_equal(TS, np.maximum(before_TS, _tsmax(log, N)))
+        else:
+            assert rc == orc.EORDER
+            assert np.array_equal(S, before_S) and np.array_equal(TS, before_TS)
+
+
+def _tsmax(log, N):
+    m = np.zeros(N, np.uint64)
+    np.maximum.at(m, log["word"].astype(np.int64), log["ts"])
+    return m
 
 
 def test_apply_word64_log(orc):
