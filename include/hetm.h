@@ -74,17 +74,18 @@ extern "C" {
  * applied and the GPU's dirty granules are restored from the host replica.
  * GPU_WINS: the host's round is discarded instead -- validation runs over
  * the whole log first and the log is applied only if it found no conflict;
- * on a conflict the GPU's transactions commit, TS and the watermark stay
- * as they were, and the granules written by either side are copied GPU ->
- * host replica, which undoes the host's writes there (the host must also
- * discard the rest of its round's effects, e.g. from a shadow copy). */
+ * on a conflict the GPU's transactions commit, nothing of the log is
+ * applied, the watermark stays as it was, and the granules written by
+ * either side are copied GPU -> host replica, which undoes the host's
+ * writes there (the host must also discard the rest of its round's
+ * effects, e.g. from a shadow copy). */
 #define HETM_POLICY_CPU_WINS 0u
 #define HETM_POLICY_GPU_WINS 1u
 
 typedef struct hetm_ctx hetm_ctx;
 
 typedef struct {
-    uint64_t n_words;            /* N: STMR size in words, 1 <= N <= 2^32        */
+    uint64_t n_words;            /* N: STMR size in words, 1 <= N < 2^32         */
     uint32_t word_bytes;         /* W: 4 (OPLIST, CACHE) or 8 (TRANSFER)         */
     uint32_t granule_words;      /* G: words per bitmap bit, >= 1                */
     uint32_t lock_stripe_words;  /* S: words per lock, power of two, >= 1        */
@@ -160,8 +161,9 @@ typedef struct {
 
 /* Allocates the GPU replica of the STMR (N words of W bytes), its lock table
  * (one u64 per S words: bit 63 lock, bits 0..62 version), the per-word
- * timestamp array TS (u64, zeroed; §IV-C.2), the read-set and write-set
- * granule bitmaps (N/G bits each, §IV-B) and round scratch, all in HBM and
+ * timestamp array TS (u64, zeroed; §IV-C.2; written only for rounds that
+ * take several log chunks), the read-set and write-set granule bitmaps
+ * (N/G bits each, §IV-B), the bucketed log and round scratch, all in HBM and
  * outside the STMR, so merges may overwrite the STMR non-transactionally
  * (§IV-B, additional assumptions).  init_image (host-or-device, N*W bytes,
  * NULL = zeros) becomes the replica.  The watermark starts at 0.
@@ -195,12 +197,19 @@ int hetm_submit_batch(hetm_ctx *ctx, uint32_t program, const void *descs, uint64
  * n entries of the context's entry type, n <= log_capacity).  Entry k is
  * flagged iff the granule of its word is set in the read-set bitmap; flags
  * accumulate into the round outcome.  The chunk is then applied even if it
- * conflicts: word w takes the value of the entry with the largest ts among
- * those fresher than TS[w], and TS[w] that ts.  Preconditions: word < N
- * (else EINVAL) and watermark < ts < 2^63 (else EORDER), checked on the
- * device before anything of the chunk is applied; a chunk failing them
- * applies nothing.  Two entries (in any chunks of the round) carrying one
- * word's winning ts give EORDER and leave that word unspecified.
+ * conflicts: word w takes the value of the chunk's entry with the largest ts
+ * for w, unless an earlier chunk of the round applied an entry for w with a
+ * larger ts (per-word timestamps, §IV-C.2; entries of earlier rounds are
+ * older than every entry by the watermark precondition).  Checked on the
+ * device before anything of the chunk is applied -- a chunk failing a
+ * check applies nothing: word < N (else EINVAL); watermark < ts < 2^63
+ * (else EORDER); the ts that would win a word is carried by one entry only,
+ * of this chunk or of the round's earlier chunks (else EORDER); the entries
+ * of one bucket of the chunk fit the resolve table (else ECAPACITY; only a
+ * chunk whose words collide by the thousand in the bucketing hashes fails
+ * it).
+ * The latched index is the entry's position for the first two checks and
+ * the word for a tie.
  * flags_bits (device, nullable, ceil(n/32) uint32) receives bit k = flag k
  * (unspecified if the chunk fails its preconditions).
  * conflict_out (host, nullable): if given, the call synchronizes and
@@ -344,15 +353,16 @@ int hetm_set_exec_workgroups(hetm_ctx *ctx, uint32_t workgroups);
 int hetm_set_version_clock(hetm_ctx *ctx, uint32_t value);
 
 /* Copies context state out (synchronizes).  what: 0 STMR (N*W bytes),
- * 1 TS (N u64), 2 read-set bitmap, 3 write-set bitmap (ceil(ceil(N/G)/32)
- * u32 each, bit g of word g/32 for granule g; the device keeps the read set
- * as one byte per granule and this call packs it), 4 lock table
- * (ceil(N/S) u64: bit 63 lock, the rest version; for u32 words with S = 1
- * the replica keeps value, version and lock of a word in one u64 -- bits
- * 0..31 value, 32..62 version, 63 lock -- and this returns those words).
- * dst host-or-device, bytes = its size. */
+ * 2 read-set bitmap, 3 write-set bitmap (ceil(ceil(N/G)/32) u32 each, bit g
+ * of word g/32 for granule g; the device keeps the read set as one byte per
+ * granule and this call packs it), 4 lock table (ceil(N/S) u64: bit 63
+ * lock, the rest version; for u32 words with S = 1 the replica keeps value,
+ * version and lock of a word in one u64 -- bits 0..31 value, 32..62
+ * version, 63 lock -- and this returns those words).  1 is not a state: the
+ * per-word timestamps of the apply are kept only while a round takes
+ * several log chunks (hetm_validate_apply_log).  dst host-or-device,
+ * bytes = its size. */
 #define HETM_STATE_STMR 0u
-#define HETM_STATE_TS   1u
 #define HETM_STATE_RS   2u
 #define HETM_STATE_WS   3u
 #define HETM_STATE_LOCKS 4u

@@ -160,8 +160,10 @@ int enqueue_validate(hetm_ctx *c, const void *dev_log, uint64_t n, uint32_t *fla
     c->args.flags = flags;
     int rc = push_args(c);
     if (rc) return rc;
-    launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, c->stream);
-    launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, c->stream);
+    launch_validate(c->dargs, c->cfg.word_bytes, c->log_bins, c->log_tiles, c->chunks_in_round > 0, c->cnt,
+                    c->stream);
+    launch_apply(c->dargs, c->cfg.word_bytes, c->log_bins, c->stream);
+    ++c->chunks_in_round;
     HIP_TRY(c, hipGetLastError());
     return HETM_OK;
 }
@@ -182,6 +184,7 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
     HIP_TRY(c, hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipEventRecord(c->closed_ev, c->stream));
     c->closed_recorded = true;
+    c->chunks_in_round = 0;
     ++c->epoch;
     return HETM_OK;
 }
@@ -315,12 +318,12 @@ int build_graph(hetm_ctx *c, uint32_t policy) {
         launch_compact(c->dargs, c->args.n_scan_blocks, br);
         launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, br);
         if (ce == hipSuccess) ce = hipEventRecord(c->join_ev, br);
-        launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
-        launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
+        launch_validate(c->dargs, c->cfg.word_bytes, c->log_bins, c->log_tiles, false, c->cnt, s);
+        launch_apply(c->dargs, c->cfg.word_bytes, c->log_bins, s);
         if (ce == hipSuccess) ce = hipStreamWaitEvent(s, c->join_ev, 0);
     } else {
-        launch_validate(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
-        launch_apply(c->dargs, c->cfg.word_bytes, c->cfg.log_capacity, s);
+        launch_validate(c->dargs, c->cfg.word_bytes, c->log_bins, c->log_tiles, false, c->cnt, s);
+        launch_apply(c->dargs, c->cfg.word_bytes, c->log_bins, s);
         launch_compact(c->dargs, c->args.n_scan_blocks, s);
         if (c->cfg.async_merge)
             launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
@@ -552,7 +555,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     if (!cfg || !out) return HETM_EINVAL;
     *out = nullptr;
     const hetm_config &k = *cfg;
-    if (k.n_words == 0 || k.n_words > (1ull << 32) || (k.word_bytes != 4 && k.word_bytes != 8) ||
+    if (k.n_words == 0 || k.n_words >= (1ull << 32) || (k.word_bytes != 4 && k.word_bytes != 8) ||
         k.granule_words == 0 || !is_pow2(k.lock_stripe_words) || k.max_txn_ops == 0 || k.max_txn_ops > 64 ||
         k.batch_capacity == 0 || k.batch_capacity > (1ull << 31) || k.log_capacity == 0 ||
         k.log_capacity >= (1ull << 32) || k.mode > HETM_MODE_GRAPH || k.async_merge > 1 ||
@@ -596,8 +599,14 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     TRY(dev_alloc(c, &c->ts, N * 8));
     TRY(dev_alloc(c, &c->rs, nrw * 4));
     TRY(dev_alloc(c, &c->ws, nbw * 4));
-    TRY(dev_alloc(c, &c->suspect, ((k.log_capacity + 63) / 64) * 8));
-    TRY(dev_alloc(c, &c->multi, ((k.log_capacity + 63) / 64) * 8));
+    c->log_bins = log_bins_for(k.log_capacity);
+    c->log_tiles = log_tiles_for(k.log_capacity);
+    TRY(dev_alloc(c, &c->log_hist, (uint64_t)c->log_tiles * c->log_bins * 4));
+    TRY(dev_alloc(c, &c->log_bstart, (c->log_bins + 1) * 4ull));
+    TRY(dev_alloc(c, &c->log_bwin, c->log_bins * 4ull));
+    TRY(dev_alloc(c, &c->log_totals, c->log_bins * 4ull));
+    TRY(dev_alloc(c, &c->log_sorted, k.log_capacity * c->log_entry_bytes));
+    TRY(dev_alloc(c, &c->log_win, k.log_capacity * c->log_entry_bytes));
     TRY(dev_alloc(c, &c->blocksums, nblocks * 4));
     TRY(dev_alloc(c, &c->blockruns, nblocks * 4));
     TRY(dev_alloc(c, &c->ids, nG * 4));
@@ -690,7 +699,10 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     DevArgs &a = c->args;
     a.stmr = c->stmr, a.locks = c->locks, a.ts = c->ts, a.rs = c->rs, a.ws = c->ws;
     a.word_shift = c->slot ? 1u : 0u;
-    a.suspect = c->suspect, a.multi = c->multi, a.blocksums = c->blocksums, a.blockruns = c->blockruns, a.ids_scratch = c->ids;
+    a.blocksums = c->blocksums, a.blockruns = c->blockruns, a.ids_scratch = c->ids;
+    a.log_hist = c->log_hist, a.log_bstart = c->log_bstart, a.log_bwin = c->log_bwin, a.log_totals = c->log_totals;
+    a.log_sorted = c->log_sorted, a.log_win = c->log_win;
+    a.log_bins = c->log_bins, a.log_bin_bits = ilog2(c->log_bins), a.log_tiles = c->log_tiles;
     a.order = c->order;
     a.cnt = c->cnt;
     a.hot = c->hot;
@@ -726,8 +738,9 @@ int hetm_free(hetm_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->ev_kernel) (void)hipEventDestroy(c->ev_kernel);
-    void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->suspect, c->multi, c->blocksums, c->blockruns,
-                   c->ids, c->order, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
+    void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->log_hist, c->log_bstart, c->log_bwin, c->log_totals,
+                   c->log_sorted, c->log_win, c->blocksums, c->blockruns, c->ids, c->order, c->log_staging, c->cnt,
+                   c->hot, c->snap_dev, c->dargs};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->hargs) (void)hipHostFree(c->hargs);
@@ -937,7 +950,6 @@ uint64_t hetm_state_bytes(hetm_ctx *c, uint32_t what) {
     const uint64_t N = c->cfg.n_words;
     switch (what) {
     case HETM_STATE_STMR: return N * c->cfg.word_bytes;
-    case HETM_STATE_TS: return N * 8;
     case HETM_STATE_RS:
     case HETM_STATE_WS: return (uint64_t)c->args.n_bm_words * 4;
     case HETM_STATE_LOCKS: return ((N + c->cfg.lock_stripe_words - 1) / c->cfg.lock_stripe_words) * 8;
@@ -948,7 +960,6 @@ uint64_t hetm_state_bytes(hetm_ctx *c, uint32_t what) {
 int hetm_read_state(hetm_ctx *c, uint32_t what, void *dst, uint64_t bytes) {
     if (!c || !dst) return HETM_EINVAL;
     const void *src = what == HETM_STATE_STMR ? c->stmr
-                      : what == HETM_STATE_TS  ? (const void *)c->ts
                       : what == HETM_STATE_RS  ? (const void *)c->rs
                       : what == HETM_STATE_WS  ? (const void *)c->ws
                       : what == HETM_STATE_LOCKS ? (c->slot ? c->stmr : (const void *)c->locks)

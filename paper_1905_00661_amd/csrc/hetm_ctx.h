@@ -26,7 +26,11 @@ struct hetm_ctx {
     uint64_t *locks = nullptr;
     uint64_t *ts = nullptr;
     uint8_t *rs = nullptr;             // read set, one byte per granule
-    uint32_t *ws = nullptr, *suspect = nullptr, *multi = nullptr;
+    uint32_t *ws = nullptr;
+    // the log chunk bucketed by word (validation and apply)
+    uint32_t log_bins = 0, log_tiles = 0;
+    uint32_t *log_hist = nullptr, *log_bstart = nullptr, *log_bwin = nullptr, *log_totals = nullptr;
+    void *log_sorted = nullptr, *log_win = nullptr;
     uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;
     uint32_t *order = nullptr;    // batch_capacity transaction ids (the OPLIST kind split)
     void *log_staging = nullptr;
@@ -97,6 +101,7 @@ struct hetm_ctx {
     int round_buf = 0;
 
     bool in_validation = false;      // this round's log has started
+    uint32_t chunks_in_round = 0;    // log chunks the open round has taken (step API)
     uint32_t gpu_losses = 0;         // rounds in a row whose GPU transactions aborted
     hetm_stats stats{};
     char err[512] = {0};

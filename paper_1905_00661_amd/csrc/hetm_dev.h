@@ -75,6 +75,7 @@ struct DevCounters {
     unsigned long long committed; // local commits in this round
     unsigned long long retries;   // local aborts in this round
     unsigned long long chunk_max_ts;  // the current chunk's, folded in when it applies
+    unsigned long long chunk_min_inv; // bitwise NOT of the current chunk's smallest ts (0: none yet)
     uint32_t n_dirty;             // write-set granules found by the compaction
     uint32_t n_runs;              // maximal runs of consecutive dirty granules
     uint32_t retry_txn;           // first transaction that hit the retry cap
@@ -82,7 +83,9 @@ struct DevCounters {
     uint32_t err_index;           // index of the first bad log entry / transaction
     uint32_t chunk_conflict;      // the current chunk's flags, folded in when it applies
     uint32_t doomed;              // epoch of the last round early validation doomed
-    uint32_t pad_[3];
+    uint32_t log_ticket;          // blocks finished in the log apply pass
+    uint32_t win_pending;         // the last applied chunk's winners have not written their ts yet
+    uint32_t pad_;
 };
 
 // Everything a kernel needs: constant context state plus the arguments of
@@ -94,8 +97,13 @@ struct DevArgs {
     uint64_t *ts;
     uint8_t *rs;            // read set: one byte per granule (see rs_mark)
     uint32_t *ws;
-    uint32_t *suspect;      // apply pass 1 -> 2: entry met its own ts (a tie), one bit per entry
-    uint32_t *multi;        // apply pass 1 -> 2: entry met another entry of the round for its word
+    // the log chunk bucketed by word (validation + apply):
+    uint32_t *log_hist;     // [tiles][bins] entries of each tile per bucket, then each tile's offset in it
+    uint32_t *log_bstart;   // [bins + 1] first position of each bucket
+    uint32_t *log_bwin;     // [bins] winning entries (one per word) each bucket resolved
+    uint32_t *log_totals;   // [bins] entries per bucket (scan pass)
+    void *log_sorted;       // [log_capacity] the chunk's entries grouped by bucket
+    void *log_win;          // [log_capacity] each bucket's winners, at the bucket's positions
     uint32_t *blocksums;    // compaction: per-block dirty counts, then offsets
     uint32_t *blockruns;
     uint32_t *ids_scratch;  // ceil(N/G) dirty granule ids
@@ -114,6 +122,10 @@ struct DevArgs {
     uint32_t retry_cap;
     uint32_t max_ops;
     uint32_t n_scan_blocks;
+    uint32_t log_bins;      // buckets of a log chunk, a power of two
+    uint32_t log_bin_bits;  // log2(log_bins)
+    uint32_t log_tiles;     // count / scatter blocks the launches are sized for (log_capacity / tile)
+    uint32_t pad1_;
     // ---- current call
     uint32_t program;
     uint32_t n_txns;
@@ -277,8 +289,18 @@ void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32
 hipError_t exec_prepare(uint32_t max_ops);
 // dynamic LDS of the OPLIST transaction kernel: each lane's word list
 constexpr uint32_t oplist_lds_bytes(uint32_t max_ops) { return kExecWaves * max_ops * kWave * 4u; }
-void launch_validate(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);
-void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s);
+// Validation and apply of one host log chunk (§IV-C.2): launch_validate
+// runs the count, scan, scatter and resolve passes, launch_apply the stores.
+// bins and tiles are the context's log_bins and log_tiles; later_chunk: the
+// round already applied a chunk, whose winners first write their timestamps.
+void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint32_t tiles, bool later_chunk,
+                     DevCounters *cnt, hipStream_t s);
+void launch_apply(const DevArgs *a, uint32_t word_bytes, uint32_t bins, hipStream_t s);
+// Sizing of the bucketed log for a chunk capacity.
+constexpr uint32_t kLogTile = 4096;             // entries per count / scatter block
+constexpr uint32_t kLogMaxBins = 4096;
+uint32_t log_bins_for(uint64_t log_capacity);
+inline uint32_t log_tiles_for(uint64_t log_capacity) { return (uint32_t)((log_capacity + kLogTile - 1) / kLogTile); }
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s);
 void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, bool slot, hipStream_t s);
 void launch_finish(const DevArgs *a, DevCounters *snap, uint32_t n_rs_words, hipStream_t s);

@@ -1,19 +1,7 @@
-// round.hip -- validation, apply and merge of one SHeTM round (§IV-C.2,
-// §IV-C.3) and the round reset, for gfx950.
+// round.hip -- early validation, merge and reset of one SHeTM round
+// (§IV-C.3, §IV-D) for gfx950.  Validation and apply of the host log are in
+// log_apply.hip.
 //
-//  validate : streams the host log chunk (16- or 24-byte entries, coalesced)
-//             against the read-set bitmap; a wave ballot gives 64 flag bits
-//             per store; checks the entry preconditions.
-//  apply    : two passes instead of a per-word lock.  Pass 1 raises TS[w] to
-//             the largest timestamp of the entries for w with a 64-bit atomic
-//             max; the first entry of the round for a word stores its value
-//             right away, later ones are flagged.  Pass 2 scans the flag bits
-//             and lets the flagged entry whose timestamp equals the final
-//             TS[w] store; a tie flag on it means two entries carry w's
-//             winning timestamp (an ordering error).  The result is the
-//             freshest entry per word, independent of arrival order, with no
-//             spinning, and the random accesses of pass 2 are only for words
-//             the chunk writes more than once.
 //  compact  : popcount + prefix sum over the write-set bitmap (per-block
 //             counts, the last block scans the block sums, then each block
 //             emits ascending dirty granule ids); runs of consecutive ids are
@@ -41,86 +29,6 @@ struct Entry8 {
     uint64_t ts;
 };
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        uint64_t t = __shfl_xor((unsigned long long)v, o);
-        v = t > v ? t : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ void store_bits(uint32_t *dst, uint64_t kb, uint64_t m, uint32_t nwords) {
-    uint64_t w = kb >> 5;
-    dst[w] = (uint32_t)m;
-    if (w + 1 < nwords) dst[w + 1] = (uint32_t)(m >> 32);
-}
-
-// ------------------------------------------------------------------ validate
-// Checks the chunk's preconditions and stages its max ts.  Under GPU wins it
-// also tests every entry against the read set, since a conflict decides
-// whether the chunk is applied at all; under CPU wins the chunk is applied
-// either way, and the apply pass makes the test itself, so the read-set
-// loads overlap its TS atomics instead of taking a pass of their own.
-template <typename E>
-__global__ __launch_bounds__(256) void k_validate(const DevArgs *__restrict__ a) {
-    const E *log = (const E *)a->log;
-    const uint64_t n = a->n_log, N = a->n_words;
-    const Div32 G = a->gdiv;
-    const uint8_t *rs = a->rs;
-    const bool test = a->policy == HETM_POLICY_GPU_WINS;
-    uint32_t *flags = test ? a->flags : nullptr;
-    DevCounters *cnt = a->cnt;
-    const uint64_t floor_ts = ld_agent(&cnt->floor_ts);
-    const uint32_t nflagw = (uint32_t)((n + 31) / 32);
-    const uint32_t lane = lane_id();
-    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t mx = 0;
-    bool conflict = false;
-    for (uint64_t kb = wave * kWave; kb < n; kb += stride) {
-        const uint64_t k = kb + lane;
-        bool f = false;
-        if (k < n) {
-            const E e = log[k];
-            if (e.word >= N) {
-                latch_error(cnt, HETM_EINVAL, (uint32_t)k);
-            } else if (e.ts <= floor_ts || e.ts >= kTsLimit) {
-                latch_error(cnt, HETM_EORDER, (uint32_t)k);
-            } else {
-                if (test) f = ld_agent(&rs[div32(e.word, G)]) != 0;
-                mx = e.ts > mx ? e.ts : mx;
-            }
-        }
-        const uint64_t m = __ballot(f);
-        if (flags && lane == 0) store_bits(flags, kb, m, nflagw);
-        conflict |= m != 0;
-    }
-    // Staged per chunk (a chunk that fails its preconditions must not count),
-    // reduced per block first: same-address atomics serialize, so each block
-    // issues at most one, and only when it raises the value.
-    __shared__ unsigned long long s_mx[256 / kWave];
-    __shared__ uint32_t s_cf[256 / kWave];
-    mx = wave_max_u64(mx);
-    const uint64_t cf = __ballot(conflict);
-    if (lane == 0) {
-        s_mx[threadIdx.x / kWave] = mx;
-        s_cf[threadIdx.x / kWave] = cf != 0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long bm = 0;
-        uint32_t bc = 0;
-        for (uint32_t i = 0; i < blockDim.x / kWave; ++i) {
-            bm = s_mx[i] > bm ? s_mx[i] : bm;
-            bc |= s_cf[i];
-        }
-        if (bm > ld_agent(&cnt->chunk_max_ts))
-            __hip_atomic_fetch_max(&cnt->chunk_max_ts, bm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (bc && !ld_agent(&cnt->chunk_conflict))
-            __hip_atomic_fetch_or(&cnt->chunk_conflict, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
 // -------------------------------------------------------- early validation
 // Validation only (no apply) of a host log chunk against the read-set bitmap
 // as it stands while the batch still executes (§IV-D, early validation).  A
@@ -140,111 +48,6 @@ __global__ __launch_bounds__(256) void k_early_validate(const E *__restrict__ lo
         hit = ld_agent(&rs[g]) != 0;
     }
     if (__ballot(hit) && lane_id() == 0) st_agent(&cnt->doomed, epoch);
-}
-
-// ------------------------------------------------------------------- apply
-// Pass 1: atomic max of the entry's ts into TS[w].  If the old value is at
-// or below the watermark, no entry of this round has touched w before: the
-// entry stores its value at once (if a later entry of the round raises TS
-// further, that entry is flagged and re-stores in pass 2).  Otherwise the
-// entry is flagged "multi", and "tie" too if the old value equals its own ts.
-template <typename E, typename Word>
-__global__ __launch_bounds__(256) void k_apply_max(const DevArgs *__restrict__ a) {
-    DevCounters *cnt = a->cnt;
-    if (ld_agent(&cnt->error)) return;   // a chunk failing its preconditions applies nothing
-    // GPU_WINS and a conflict: the host's round is discarded, nothing of its
-    // log is applied; its granules join the write set, so the merge copies
-    // the GPU's values over the host's writes
-    const bool discard = a->policy == HETM_POLICY_GPU_WINS && ld_agent(&cnt->chunk_conflict) != 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {   // the chunk counts: fold its outcome into the round's
-        if (ld_agent(&cnt->chunk_conflict)) st_agent(&cnt->conflict, 1u);
-        const unsigned long long m = ld_agent(&cnt->chunk_max_ts);
-        if (!discard && m > ld_agent(&cnt->max_ts)) st_agent(&cnt->max_ts, m);
-    }
-    const E *log = (const E *)a->log;
-    const uint64_t n = a->n_log;
-    if (discard) {
-        const Div32 G = a->gdiv;
-        for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
-            bitmap_set(a->ws, div32(log[k].word, G));
-        return;
-    }
-    const uint64_t floor_ts = ld_agent(&cnt->floor_ts);
-    uint64_t *ts = a->ts;
-    Word *stmr = (Word *)a->stmr;
-    const uint32_t wsh = a->word_shift;      // slot layout: a word's value sits at u32 index 2w
-    uint32_t *tie = a->suspect, *multi = a->multi;
-    // CPU wins: the read-set test of validation happens here (see k_validate)
-    const bool test = a->policy != HETM_POLICY_GPU_WINS;
-    const uint8_t *rs = a->rs;
-    const Div32 G = a->gdiv;
-    uint32_t *flags = a->flags;
-    const uint32_t nw = (uint32_t)((n + 31) / 32);
-    const uint32_t lane = lane_id();
-    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    bool conflict = false;
-    for (uint64_t kb = wave * kWave; kb < n; kb += stride) {
-        const uint64_t k = kb + lane;
-        bool t = false, m = false, f = false;
-        if (k < n) {
-            const E e = log[k];
-            if (test) f = ld_agent(&rs[div32(e.word, G)]) != 0;
-            const uint64_t old = __hip_atomic_fetch_max(&ts[e.word], (uint64_t)e.ts, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-            if (old <= floor_ts)
-                stmr[(uint64_t)e.word << wsh] = (Word)e.value;
-            else
-                m = true;
-            t = old == e.ts;
-        }
-        const uint64_t tb = __ballot(t), mb = __ballot(m), fb = __ballot(f);
-        if (lane == 0) {
-            store_bits(tie, kb, tb, nw);
-            store_bits(multi, kb, mb, nw);
-            if (test && flags) store_bits(flags, kb, fb, nw);
-        }
-        conflict |= fb != 0;
-    }
-    // at most one atomic per wave, and only for a conflict
-    if (test && conflict && lane == 0 && !ld_agent(&cnt->conflict))
-        __hip_atomic_fetch_or(&cnt->conflict, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Pass 2: only flagged entries; the one whose ts is the final TS[w] stores
-// its value, and a tie flag on it means two entries carry w's winning ts.
-template <typename E, typename Word>
-__global__ __launch_bounds__(256) void k_apply_store(const DevArgs *__restrict__ a) {
-    DevCounters *cnt = a->cnt;
-    if (ld_agent(&cnt->error)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {   // pass 1 consumed the chunk counters
-        st_agent(&cnt->chunk_conflict, 0u);
-        st_agent(&cnt->chunk_max_ts, 0ull);
-    }
-    if (a->policy == HETM_POLICY_GPU_WINS && ld_agent(&cnt->conflict)) return;   // log discarded
-    const E *log = (const E *)a->log;
-    const uint64_t n = a->n_log;
-    const uint64_t *ts = a->ts;
-    const uint32_t *tie = a->suspect, *multi = a->multi;
-    Word *stmr = (Word *)a->stmr;
-    const uint32_t wsh = a->word_shift;      // slot layout: a word's value sits at u32 index 2w
-    const uint64_t nwords = (n + 31) / 32;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < nwords; w += stride) {
-        uint32_t m = multi[w];
-        const uint32_t t = tie[w];
-        while (m) {
-            const uint32_t b = __ffs(m) - 1;
-            m &= m - 1;
-            const uint64_t k = w * 32 + b;
-            const E e = log[k];
-            if (ts[e.word] != e.ts) continue;     // a fresher entry holds the word
-            if ((t >> b) & 1u)
-                latch_error(cnt, HETM_EORDER, (uint32_t)k);
-            else
-                stmr[(uint64_t)e.word << wsh] = (Word)e.value;
-        }
-    }
 }
 
 // ------------------------------------------------------------------ compact
@@ -518,8 +321,11 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         c.scan_ticket = 0;
         c.err_index = ld_agent(&cnt->err_index);
         c.chunk_max_ts = 0;
+        c.chunk_min_inv = 0;
         c.chunk_conflict = 0;
-        c.pad_[0] = c.pad_[1] = c.pad_[2] = 0;
+        c.log_ticket = 0;
+        c.win_pending = 0;
+        c.pad_ = 0;
         c.doomed = ld_agent(&cnt->doomed);
         if (!err) {
             const uint64_t f = c.max_ts > c.floor_ts ? c.max_ts : c.floor_ts;
@@ -533,6 +339,7 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
             st_agent(&cnt->retries, 0ull);
             st_agent(&cnt->n_dirty, 0u);
             st_agent(&cnt->n_runs, 0u);
+            st_agent(&cnt->win_pending, 0u);    // the next round's first chunk needs no timestamps
         }
         *snap = c;
     }
@@ -556,6 +363,8 @@ __global__ void k_clear_error(DevCounters *cnt) {
         st_agent(&cnt->retry_txn, 0u);
         st_agent(&cnt->chunk_conflict, 0u);
         st_agent(&cnt->chunk_max_ts, 0ull);
+        st_agent(&cnt->chunk_min_inv, 0ull);
+        st_agent(&cnt->log_ticket, 0u);
     }
 }
 
@@ -575,29 +384,6 @@ const void *set_args_kernel() { return reinterpret_cast<const void *>(&k_set_arg
 
 void launch_clear_error(DevCounters *cnt, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_error, dim3(1), dim3(64), 0, s, cnt);
-}
-
-void launch_validate(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s) {
-    // each block makes (at most) one same-address atomic on the chunk's
-    // counters after a device-coherent load of them: 1024 blocks measured
-    // 14 us per 2^20 entries against 26 us at 4096
-    const uint32_t grid = stream_grid(max_log, 256, 1024);
-    if (word_bytes == 4)
-        hipLaunchKernelGGL(k_validate<Entry4>, dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_validate<Entry8>, dim3(grid), dim3(256), 0, s, a);
-}
-
-void launch_apply(const DevArgs *a, uint32_t word_bytes, uint64_t max_log, hipStream_t s) {
-    const uint32_t grid = stream_grid(max_log, 256, 8192);
-    const uint32_t grid2 = stream_grid((max_log + 31) / 32, 256, 2048);
-    if (word_bytes == 4) {
-        hipLaunchKernelGGL((k_apply_max<Entry4, uint32_t>), dim3(grid), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_apply_store<Entry4, uint32_t>), dim3(grid2), dim3(256), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_apply_max<Entry8, uint64_t>), dim3(grid), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_apply_store<Entry8, uint64_t>), dim3(grid2), dim3(256), 0, s, a);
-    }
 }
 
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s) {

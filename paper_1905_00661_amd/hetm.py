@@ -27,7 +27,7 @@ HETM_PROG_OPLIST, HETM_PROG_TRANSFER, HETM_PROG_CACHE = 1, 2, 3
 HETM_MODE_PLAIN, HETM_MODE_GRAPH = 0, 1
 HETM_OUTCOME_DEVICE = 0xFFFFFFFF
 HETM_POLICY_CPU_WINS, HETM_POLICY_GPU_WINS = 0, 1
-HETM_STATE_STMR, HETM_STATE_TS, HETM_STATE_RS, HETM_STATE_WS, HETM_STATE_LOCKS = 0, 1, 2, 3, 4
+HETM_STATE_STMR, HETM_STATE_RS, HETM_STATE_WS, HETM_STATE_LOCKS = 0, 2, 3, 4
 
 EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_apply_log",
            "hetm_copyback_dirty", "hetm_round", "hetm_strerror", "hetm_last_error", "hetm_sync",
@@ -370,7 +370,7 @@ class Context:
         hetm_read_state(self.ctx, what, buf.ctypes.data, nb)
         if what == HETM_STATE_STMR:
             return buf.view(np.uint32 if self.word_bytes == 4 else np.int64)
-        if what in (HETM_STATE_TS, HETM_STATE_LOCKS):
+        if what == HETM_STATE_LOCKS:
             return buf.view(np.uint64)
         return buf.view(np.uint32)
 

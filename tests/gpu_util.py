@@ -47,7 +47,6 @@ def gpu_round(ri: wl.RoundInputs, mode=hm.HETM_MODE_PLAIN, stripe=1, host=None, 
         "results": b.results_np(),
         "tickets": b.tickets_np(),
         "S": ctx.read_state(hm.HETM_STATE_STMR).copy(),
-        "TS": ctx.read_state(hm.HETM_STATE_TS).copy(),
         "H": host_t.numpy().view(ri.init.dtype).copy(),
         "flags": hm.tensor_to_numpy(flags_t, np.uint32) if flags else None,
         "ids": hm.tensor_to_numpy(ids_t, np.uint32, int(res.n_dirty)) if ids else None,
@@ -83,7 +82,7 @@ def oracle_round(ri: wl.RoundInputs, tickets: np.ndarray, H0: np.ndarray, S0=Non
     return out
 
 
-def assert_round_equal(g: dict, o: dict, ri: wl.RoundInputs, check_ts=True):
+def assert_round_equal(g: dict, o: dict, ri: wl.RoundInputs):
     """Element-wise, bit-exact comparison of every output of the round."""
     n_log = ri.log.shape[0]
     r = g["res"]
@@ -99,7 +98,5 @@ def assert_round_equal(g: dict, o: dict, ri: wl.RoundInputs, check_ts=True):
     assert np.array_equal(g["S"], o["S"]), f"GPU replica differs at {np.flatnonzero(g['S'] != o['S'])[:8]}"
     assert np.array_equal(g["H"], o["H"]), "host replica differs"
     assert np.array_equal(g["S"], g["H"]), "replicas differ after the merge"
-    if check_ts:
-        assert np.array_equal(g["TS"], o["TS"]), "TS array differs"
     if o["conflict"] == 0 or r.host_discarded:
         assert int(r.n_committed) == ri.batch.n

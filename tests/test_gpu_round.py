@@ -61,7 +61,7 @@ def test_c1_steps(hm, wl):
     res, oRS, oWS = orc.replay_oplist(S, ri.granule, ri.batch, order)
     assert np.array_equal(np.concatenate([b1.results_np(), b2.results_np()]), res)
     assert np.array_equal(RS, oRS) and np.array_equal(WS, oWS)
-    # two log chunks
+    # the log as one chunk (several chunks: test_gpu_log.py)
     log_t = hm.to_device(ri.log)
     flags = torch.zeros(((10000 + 31) // 32) * 4, dtype=torch.uint8, device="cuda")
     c = ctx.validate_apply(log_t, 10000, flags)
@@ -71,7 +71,6 @@ def test_c1_steps(hm, wl):
     assert c == oc == 1
     assert np.array_equal(bits(hm.tensor_to_numpy(flags, np.uint32), 10000), bits(ofl, 10000))
     assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S)
-    assert np.array_equal(ctx.read_state(hm.HETM_STATE_TS), TS)
     H = wl.host_replica(ri.init, ri.log)
     host_t = hm.pinned(H.nbytes)
     host_t.numpy()[:] = H.view(np.uint8)
@@ -211,9 +210,9 @@ def test_version_clock_reset(hm, wl):
 
 
 def test_log_preconditions(hm, wl):
-    """A log word outside the STMR (EINVAL) or a timestamp not above the
-    watermark (EORDER) applies nothing; a tie at a word's winning timestamp
-    is EORDER; the context stays usable."""
+    """A log word outside the STMR (EINVAL), a timestamp not above the
+    watermark (EORDER) or a tie at a word's winning timestamp (EORDER): the
+    chunk applies nothing; the context stays usable."""
     import torch
     N = 256
     init = np.arange(N, dtype=np.uint32)
@@ -232,14 +231,15 @@ def test_log_preconditions(hm, wl):
             ctx.validate_apply(mk(entries), len(entries))
         assert e.value.code == code
         assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), init)
-        assert not ctx.read_state(hm.HETM_STATE_TS).any()
     with pytest.raises(hm.HetmError) as e:
         ctx.validate_apply(mk([(7, 1, 9), (7, 2, 9), (8, 3, 2)]), 3)
     assert e.value.code == hm.HETM_EORDER
+    # the tied chunk applied nothing, not even its untied word
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), init)
     # ties below the winner pass, and the context is usable again
     assert ctx.validate_apply(mk([(9, 1, 20), (9, 2, 20), (9, 3, 30)]), 3) == 0
     S = ctx.read_state(hm.HETM_STATE_STMR)
-    assert S[9] == 3 and S[8] == 3
+    assert S[9] == 3 and S[8] == 8
     ctx.close()
 
 
@@ -320,7 +320,6 @@ def test_async_merge_back_to_back(hm, wl):
     ctx.sync()
     assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S)
     assert np.array_equal(host, H)
-    assert np.array_equal(ctx.read_state(hm.HETM_STATE_TS), TS)
     ctx.close()
 
 
