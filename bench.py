@@ -1,16 +1,33 @@
 """Benchmark: whole SHeTM rounds (GPU side) on one MI355X.
 
-Workload (the large synthetic STMR configuration): 2^28 u32 words (1 GiB),
-batches of 2^20 GPU transactions (90% read-only with 16 reads, 10% update
-with 4 read-modify-writes), 1% hot set drawing 50% of the accesses, a host
-log of 2^20 entries per round in the host-owned half, granule 16 words.
+Headline (`value`): the large synthetic STMR configuration -- 2^28 u32 words
+(1 GiB), batches of 2^20 GPU transactions (90% read-only with 16 reads, 10%
+update with 4 read-modify-writes), 1% hot set drawing 50% of the accesses, a
+host log of 2^20 entries per round in the host-owned half, granule 16 words
+-- in the batched form (one captured hipGraph per round, persistent
+transaction kernel, double-buffered merge), with each round's inputs
+(descriptors, log) resident in HBM when the timed region starts.  A step is
+one whole round: execution, validation + apply of the log, dirty-granule
+compaction, merge into the pinned host replica, reset.
 
-A step is one whole round: execution of the batch, validation + apply of the
-log, dirty-granule compaction, merge copy into the pinned host replica and
-reset.  Inputs (descriptors, per-round logs) are resident in HBM before the
-timed region.  The headline form replays the round as one captured hipGraph;
-the plain form (one launch per step, host reads the outcome) is timed beside
-it and provides per-kernel event timings for the roofline.
+Beside it, on the same GPU:
+  graph_sync_merge / plain  the same rounds with the merge inside the round,
+                            and one launch per step (per-step event timings);
+  ingest                    the batched rounds with every round's descriptors
+                            and log uploaded from pinned host memory and its
+                            results and tickets fetched back, overlapped on
+                            two copy streams (the host-link-inclusive rate);
+  small                     round latency of the plain single round (2^16
+                            words, 4096 4R/4W transactions, 10,000-entry log,
+                            granule 64) and of its partitioned variant;
+  conflict                  the large rounds with one log entry redirected
+                            into the batch's read set in 10% of the rounds;
+  bank / cache              the bank-transfer and object-cache
+                            configurations at full size (retries per commit);
+  served                    the request loop swept over arrival rates, for the
+                            pipelined and one-round-at-a-time forms;
+  cpu_baseline              the C oracle replaying whole large rounds on one
+                            pinned host core.
 
 Prints ONE JSON line.
 """
@@ -31,6 +48,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
+METRIC = "committed txns/s + validate/apply GB/s vs HBM peak; p50/p99 commit latency"
 
 
 def log(*a):
@@ -50,7 +68,21 @@ def exec_alg_bytes(batch) -> float:
     return float(batch.n * 21 + L.sum() * 17 + L[nw > 0].sum() * 8 + nw.sum() * 28)
 
 
-VALIDATE_APPLY_BYTES_PER_ENTRY = 40.0   # 16 B entry + 4 B bitmap + 8+8 B TS + 4 B value
+def exec_scope_bytes(batch) -> float:
+    """The same work counted with the scope table's per-transaction figures
+    for a lock table of one u64 per word: a 16-read read-only transaction
+    452 B, a 4-read-modify-write update 228 B."""
+    nw = batch.n_writes.astype(np.int64)
+    return float((nw == 0).sum() * 452 + (nw > 0).sum() * 228)
+
+
+# validate + apply, bytes per log entry: the scope table's algorithmic count
+# (16 B entry, 4 B bitmap word, 8 + 8 B timestamp read and write, 4 B value)
+# and the bytes the bucketed passes stream (count reads the entry and a
+# read-set byte; scatter reads and writes it; resolve reads it and writes the
+# winner; apply reads the winner and stores the value)
+VALIDATE_APPLY_BYTES_PER_ENTRY = 40.0
+VALIDATE_APPLY_STREAM_BYTES_PER_ENTRY = 16 + 1 + 32 + 32 + 16 + 4
 
 
 KERNEL_SOURCES = {"k_exec_oplist": ("exec.hip", "hetm_dev.h")}
@@ -82,51 +114,447 @@ def load_traffic(kernel: str):
     return int(b.group(1))
 
 
-def serve_forms(args, hm, wl, torch) -> dict:
-    """The serving configuration: open-loop Poisson arrivals of lognormal
-    (median 4, capped at 64 ops) transactions over a 2^27-word STMR with 5%
-    hot words; rounds admitted under a 2 GiB budget; continuous batching
-    (pipelined) against plain per-round serving at the same rate.  Each form
-    serves the stream once untimed on its context (first kernel launches,
-    graph capture, first copies of the process and context), then again
-    for the reported figures, its host log moved later in time so that it
-    follows the first call's."""
+def cpu_info() -> dict:
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+# ------------------------------------------------------------------- legs
+
+def shifted_logs(torch, hm, base_log: np.ndarray, n_log: int, rounds: int, dev: str, inject=None):
+    """Per-round logs resident in HBM: the same words and values, timestamps
+    shifted past the previous round's; inject(r, log) may edit round r's."""
+    base = hm.to_device(base_log, dev)
+    logs = []
+    for r in range(rounds):
+        if inject is not None:
+            lr = base_log.copy()
+            if inject(r, lr):
+                t = hm.to_device(lr, dev)
+            else:
+                t = base.clone()
+        else:
+            t = base.clone()
+        t.view(torch.int64).view(-1, 2)[:, 1].add_(r * n_log)
+        logs.append(t)
+    torch.cuda.synchronize()
+    return logs
+
+
+def large_forms(args, hm, wl, torch, ri, dev) -> dict:
+    """The large configuration in the batched, graph-with-merge and plain forms,
+    inputs resident in HBM."""
+    N, G, n_log = ri.n_words, ri.granule, ri.log.shape[0]
+    n_txn = ri.batch.n
+    rounds = args.warmup + args.steps
+    logs = shifted_logs(torch, hm, ri.log, n_log, rounds + 1, dev)
+    host = hm.pinned(N * 4)
+    host.numpy()[:] = ri.init.view(np.uint8)
+
+    def run(mode: int, async_merge: bool = False):
+        ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=n_txn,
+                         log_capacity=n_log, mode=mode, exec_workgroups=args.exec_wg, async_merge=async_merge)
+        b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
+        flags = torch.zeros(((n_log + 31) // 32) * 4, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        for r in range(args.warmup):
+            ctx.round(b, logs[r], n_log, host, flags)
+        ctx.sync()
+        torch.cuda.synchronize()
+        lat, res = [], []
+        t_start = time.perf_counter()
+        for r in range(args.warmup, rounds):
+            t1 = time.perf_counter()
+            rr = ctx.round(b, logs[r], n_log, host, flags)
+            lat.append(time.perf_counter() - t1)
+            res.append(rr.as_dict())
+        ctx.sync()                       # the last round's merge copy has landed
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        tickets = b.tickets_np().copy()
+        st = ctx.stats()
+        ctx.close()
+        return {"elapsed": elapsed, "lat": lat, "res": res, "tickets": tickets,
+                "scatter_ms": st.us_host_scatter / 1e3 / rounds}
+
+    out = {}
+    log("large: batched form (graph + double-buffered merge) ...")
+    g = run(hm.HETM_MODE_GRAPH, async_merge=True)
+    committed = sum(r["n_committed"] for r in g["res"])
+    out["batched"] = {"value": committed / g["elapsed"], "ms_per_step": 1e3 * g["elapsed"] / args.steps,
+                      "p50_round_ms": 1e3 * pct(g["lat"], 50), "p99_round_ms": 1e3 * pct(g["lat"], 99),
+                      "conflict_rounds": sum(r["conflict"] for r in g["res"]),
+                      "local_retries_per_round": float(np.mean([r["n_local_retries"] for r in g["res"]])),
+                      "dirty_granules_per_round": float(np.mean([r["n_dirty"] for r in g["res"]])),
+                      "graph_us": float(np.mean([r["us_total"] for r in g["res"]])),
+                      "host_scatter_ms_per_round": g["scatter_ms"]}
+    out["tickets"] = g["tickets"]
+    log("large: graph form, merge inside the round ...")
+    s = run(hm.HETM_MODE_GRAPH)
+    out["graph_sync_merge"] = {"value": sum(r["n_committed"] for r in s["res"]) / s["elapsed"],
+                               "ms_per_step": 1e3 * s["elapsed"] / args.steps}
+    log("large: plain form ...")
+    p = run(hm.HETM_MODE_PLAIN)
+    us = {k: float(np.mean([r[k] for r in p["res"]]))
+          for k in ("us_exec", "us_exec_kernel", "us_validate", "us_merge", "us_total")}
+    out["plain"] = {"value": sum(r["n_committed"] for r in p["res"]) / p["elapsed"],
+                    "ms_per_step": 1e3 * p["elapsed"] / args.steps,
+                    "p50_round_ms": 1e3 * pct(p["lat"], 50), "p99_round_ms": 1e3 * pct(p["lat"], 99), **us}
+    return out
+
+
+def ingest_form(args, hm, wl, torch, ri, dev) -> dict:
+    """Batched rounds whose inputs start in pinned host memory: round r+1's
+    descriptors and log go up on one copy stream while round r runs, round
+    r's results and tickets come back on another while round r+1 runs."""
+    N, G, n_log = ri.n_words, ri.granule, ri.log.shape[0]
+    bt = ri.batch
+    rounds = args.warmup + args.steps
+    arrays = [bt.offsets, bt.idx, bt.n_writes, bt.tid]
+    h_desc = []
+    for a in arrays:
+        t = hm.pinned(a.nbytes)
+        t.numpy()[:] = np.ascontiguousarray(a).view(np.uint8).reshape(-1)
+        h_desc.append(t)
+    h_logs = []
+    for r in range(rounds):
+        t = hm.pinned(ri.log.nbytes)
+        lr = ri.log.copy()
+        lr["ts"] += np.uint64(r * n_log)
+        t.numpy()[:] = lr.view(np.uint8)
+        h_logs.append(t)
+    n_res = int(bt.offsets[-1])
+    h_res = hm.pinned(n_res * 4)
+    h_tick = hm.pinned(bt.n * 4)
+    sets = []
+    for _ in range(2):
+        d = [torch.empty(t.numel(), dtype=torch.uint8, device=dev) for t in h_desc]
+        sets.append({"desc": hm.hetm_oplist_desc(*[x.data_ptr() for x in d]), "bufs": d,
+                     "log": torch.empty(ri.log.nbytes, dtype=torch.uint8, device=dev),
+                     "res": torch.empty(n_res * 4, dtype=torch.uint8, device=dev),
+                     "tick": torch.empty(bt.n * 4, dtype=torch.uint8, device=dev)})
+
+    class DevBatch:                         # the binding's Batch interface over one buffer set
+        def __init__(self, st):
+            self.program, self.n, self.desc = hm.HETM_PROG_OPLIST, bt.n, st["desc"]
+            self.results, self.tickets = st["res"], st["tick"]
+
+    host = hm.pinned(N * 4)
+    host.numpy()[:] = ri.init.view(np.uint8)
+    ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=bt.n,
+                     log_capacity=n_log, mode=hm.HETM_MODE_GRAPH, exec_workgroups=args.exec_wg, async_merge=True)
+    main = torch.cuda.current_stream()
+    up, down = torch.cuda.Stream(), torch.cuda.Stream()
+    ev_up = [torch.cuda.Event() for _ in range(2)]
+    ev_done = [torch.cuda.Event() for _ in range(2)]
+    ev_fetched = [torch.cuda.Event() for _ in range(2)]
+
+    def upload(r):
+        st = sets[r % 2]
+        with torch.cuda.stream(up):
+            up.wait_event(ev_fetched[r % 2])          # round r-2's results have left this set
+            for d, h in zip(st["bufs"], h_desc):
+                d.copy_(h, non_blocking=True)
+            st["log"].copy_(h_logs[r], non_blocking=True)
+            ev_up[r % 2].record(up)
+
+    def fetch(r):
+        st = sets[r % 2]
+        with torch.cuda.stream(down):
+            down.wait_event(ev_done[r % 2])
+            h_res.copy_(st["res"], non_blocking=True)
+            h_tick.copy_(st["tick"], non_blocking=True)
+            ev_fetched[r % 2].record(down)
+
+    torch.cuda.synchronize()
+    upload(0)
+    t_start, res = None, []
+    for r in range(rounds):
+        if r == args.warmup:
+            ctx.sync()
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+        if r + 1 < rounds:
+            upload(r + 1)
+        main.wait_event(ev_up[r % 2])
+        rr = ctx.round(DevBatch(sets[r % 2]), sets[r % 2]["log"], n_log, host)
+        ev_done[r % 2].record(main)
+        fetch(r)
+        if r >= args.warmup:
+            res.append(rr.as_dict())
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ctx.close()
+    committed = sum(r["n_committed"] for r in res)
+    h2d = sum(a.nbytes for a in arrays) + ri.log.nbytes
+    d2h = n_res * 4 + bt.n * 4
+    return {"value": committed / elapsed, "unit": "txn/s", "ms_per_step": 1e3 * elapsed / args.steps,
+            "h2d_MB_per_round": h2d / 1e6, "d2h_MB_per_round": d2h / 1e6,
+            "merge_d2h_MB_per_round": float(np.mean([r["n_dirty"] for r in res])) * G * 4 / 1e6,
+            "form": "batched rounds, descriptors and log uploaded from pinned host memory and results fetched, "
+                    "overlapped on two copy streams"}
+
+
+def small_round(args, hm, wl, torch, dev) -> dict:
+    """Latency of the plain single round (2^16 words, 4096 4R/4W, 10,000
+    entries, granule 64) and of its partitioned variant, per form."""
+    out = {}
+    for variant in ("", "p"):
+        ri = wl.c1(variant)
+        n_log = ri.log.shape[0]
+        rounds = 20 + args.small_rounds
+        logs = shifted_logs(torch, hm, ri.log, n_log, rounds, dev)
+        res_v = {}
+        for name, mode in (("plain", hm.HETM_MODE_PLAIN), ("graph", hm.HETM_MODE_GRAPH)):
+            ctx = hm.Context(ri.n_words, 4, ri.granule, init=ri.init, max_ops=4, batch_capacity=ri.batch.n,
+                             log_capacity=n_log, mode=mode)
+            host = hm.pinned(ri.n_words * 4)
+            host.numpy()[:] = ri.init.view(np.uint8)
+            b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
+            torch.cuda.synchronize()
+            lat, conf = [], 0
+            for r in range(rounds):
+                t1 = time.perf_counter()
+                rr = ctx.round(b, logs[r], n_log, host)
+                if r >= 20:
+                    lat.append(1e6 * (time.perf_counter() - t1))
+                    conf += rr.conflict
+            ctx.close()
+            res_v[name] = {"p50_us": pct(lat, 50), "p99_us": pct(lat, 99), "conflict_rounds": conf}
+        out["as_named" if variant == "" else "partitioned"] = res_v
+    out["workload"] = ("2^16 u32 words, 4096 txns of 4 reads + 4 writes, 10,000-entry host log, granule 64 "
+                       "(as named every granule is read, so every round conflicts; partitioned: GPU lower half, "
+                       "log upper half)")
+    out["rounds"] = args.small_rounds
+    return out
+
+
+def conflict_form(args, hm, wl, torch, ri, dev) -> dict:
+    """Batched large rounds where, in a seeded 10% of the rounds, one log
+    entry is redirected to a word the batch reads (CPU wins: the round's GPU
+    transactions abort and its dirty granules come back from the host)."""
+    N, G, n_log = ri.n_words, ri.granule, ri.log.shape[0]
+    rounds = args.warmup + args.steps
+    g = np.random.default_rng(0x190500661)
+    hits = set(int(r) for r in np.flatnonzero(g.random(rounds) < 0.1))
+
+    def inject(r, lr):
+        if r not in hits:
+            return False
+        lr["word"][int(g.integers(0, n_log))] = ri.batch.idx[int(g.integers(0, ri.batch.idx.shape[0]))]
+        return True
+
+    logs = shifted_logs(torch, hm, ri.log, n_log, rounds, dev, inject=inject)
+    host = hm.pinned(N * 4)
+    host.numpy()[:] = ri.init.view(np.uint8)
+    ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=ri.batch.n,
+                     log_capacity=n_log, mode=hm.HETM_MODE_GRAPH, exec_workgroups=args.exec_wg, async_merge=True)
+    b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
+    for r in range(args.warmup):
+        ctx.round(b, logs[r], n_log, host)
+    ctx.sync()
+    torch.cuda.synchronize()
+    lat_ok, lat_cf, committed = [], [], 0
+    t0 = time.perf_counter()
+    for r in range(args.warmup, rounds):
+        t1 = time.perf_counter()
+        rr = ctx.round(b, logs[r], n_log, host)
+        (lat_cf if rr.conflict else lat_ok).append(1e3 * (time.perf_counter() - t1))
+        committed += rr.n_committed
+    ctx.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    return {"value": committed / el, "unit": "txn/s", "rounds": args.steps, "conflict_rounds": len(lat_cf),
+            "p50_clean_round_ms": pct(lat_ok, 50), "p50_conflict_round_ms": pct(lat_cf, 50),
+            "max_conflict_round_ms": max(lat_cf) if lat_cf else None,
+            "form": "batched, CPU wins, r = 10% of rounds conflicting"}
+
+
+def bank_form(args, hm, wl, torch, dev) -> dict:
+    """Bank transfers at full size: 2^24 int64 accounts, U[2^20, 2^21]
+    Zipf(0.9) transfers per round on the GPU, the host TM's 2^15 transfers
+    on its 2^16 accounts per round producing the log."""
+    n_acc, host_acc = 1 << 24, 1 << 16
+    init = np.full(n_acc, 1000, dtype=np.int64)
+    host = hm.pinned(n_acc * 8)
+    hv = host.numpy().view(np.int64)
+    hv[:] = init
+    ctx = hm.Context(n_acc, 8, 64, init=init, max_ops=2, batch_capacity=1 << 21, log_capacity=1 << 16,
+                     mode=hm.HETM_MODE_GRAPH, async_merge=True)
+    tm = hm.HostTM(hv, ts_start=0)
+    rows = []
+    for r in range(args.bank_rounds):
+        d = wl.c3(round_no=r)
+        t1 = time.perf_counter()
+        ts, hlog = tm.transfers(d["host"].src, d["host"].dst, d["host"].amt, threads=8)
+        host_s = time.perf_counter() - t1
+        b = hm.Batch(hm.HETM_PROG_TRANSFER, d["batch"], dev)
+        log_t = hm.to_device(hlog, dev) if hlog.shape[0] else torch.zeros(24, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rr = ctx.round(b, log_t, hlog.shape[0], host)
+        ctx.sync()
+        el = time.perf_counter() - t1
+        rows.append({"n": d["batch"].n, "s": el, "committed": rr.n_committed, "retries": rr.n_local_retries,
+                     "conflict": rr.conflict, "host_s": host_s, "host_n": d["host"].n})
+        log(f"bank round {r}: {d['batch'].n} transfers in {1e3 * el:.1f} ms, retries {rr.n_local_retries}")
+    tm.close()
+    total = float(ctx.read_state(hm.HETM_STATE_STMR).sum())
+    ctx.close()
+    timed = rows[1:] if len(rows) > 1 else rows
+    committed = sum(x["committed"] for x in timed)
+    return {"value": committed / sum(x["s"] for x in timed), "unit": "txn/s",
+            "ms_per_round": 1e3 * float(np.mean([x["s"] for x in timed])),
+            "transfers_per_round": float(np.mean([x["n"] for x in timed])),
+            "retries_per_commit": sum(x["retries"] for x in timed) / max(committed, 1),
+            "conflict_rounds": sum(x["conflict"] for x in rows),
+            "host_tm_txn_s": sum(x["host_n"] for x in rows) / sum(x["host_s"] for x in rows),
+            "balance_conserved": total == 1000.0 * n_acc, "rounds_timed": len(timed),
+            "workload": "2^24 int64 accounts = 1000, U[2^20, 2^21] Zipf(0.9) transfers per round, host TM "
+                        "2^15 transfers on 2^16 accounts (8 threads), granule 64, first round untimed"}
+
+
+def cache_form(args, hm, wl, torch, dev) -> dict:
+    """The object cache at full size: 2^22 sets x 8 ways warmed to 95% by
+    host PUTs, 2^20 GPU requests per round (95% GET / 5% PUT, Zipf 0.99 over
+    2^26 keys, even keys), 2^14 host PUTs on odd keys per round."""
+    nsets = 1 << 22
+    N = nsets * 128
+    g0 = wl.rng("c4", 0, 2)
+    host = hm.pinned(N * 4)
+    hv = host.numpy().view(np.uint32)
+    hv[:] = 0
+    tm = hm.HostTM(hv, stripe=128)
+    keys = g0.permutation(np.arange(1, (1 << 26) + 1, dtype=np.uint64))[: int(nsets * 8 * 0.95)]
+    t1 = time.perf_counter()
+    for k0 in range(0, keys.shape[0], 1 << 21):
+        tm.cache_puts(keys[k0:k0 + (1 << 21)], threads=8)
+    warm_s = time.perf_counter() - t1
+    log(f"cache: table warmed in {warm_s:.1f} s")
+    ctx = hm.Context(N, 4, 128, init=hv.copy(), max_ops=2, batch_capacity=1 << 20, log_capacity=12 << 14,
+                     mode=hm.HETM_MODE_GRAPH, async_merge=True)
+    rows = []
+    for r in range(args.cache_rounds):
+        b = wl.c4_requests(g0, 1 << 20, 1 << 26, theta=0.99, put_frac=0.05, parity=0, tid0=(r + 1) << 24)
+        hk = wl.c4_requests(g0, 1 << 14, 1 << 26, theta=0.99, put_frac=1.0, parity=1).key
+        _, hlog = tm.cache_puts(hk, threads=8)
+        bb = hm.Batch(hm.HETM_PROG_CACHE, b, dev)
+        log_t = hm.to_device(hlog, dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rr = ctx.round(bb, log_t, hlog.shape[0], host)
+        ctx.sync()
+        el = time.perf_counter() - t1
+        rows.append({"s": el, "committed": rr.n_committed, "retries": rr.n_local_retries, "conflict": rr.conflict})
+        log(f"cache round {r}: {1e3 * el:.1f} ms, retries {rr.n_local_retries}")
+    tm.close()
+    ctx.close()
+    timed = rows[1:] if len(rows) > 1 else rows
+    committed = sum(x["committed"] for x in timed)
+    return {"value": committed / sum(x["s"] for x in timed), "unit": "txn/s",
+            "ms_per_round": 1e3 * float(np.mean([x["s"] for x in timed])),
+            "retries_per_commit": sum(x["retries"] for x in timed) / max(committed, 1),
+            "conflict_rounds": sum(x["conflict"] for x in rows), "warmup_s": warm_s, "rounds_timed": len(timed),
+            "workload": "2^22 sets x 8 ways (2 GiB) warmed to 95%, 2^20 requests per round (95% GET / 5% PUT, "
+                        "Zipf 0.99 over 2^26 keys, even keys), 2^14 host PUTs on odd keys, granule 128, "
+                        "first round untimed"}
+
+
+def serve_sweep(args, hm, wl, torch) -> dict:
+    """The serving configuration swept over arrival rates: open-loop Poisson
+    arrivals of lognormal (median 4, capped at 64 ops) transactions over a
+    2^27-word STMR with 5% hot words; rounds admitted under a 2 GiB budget;
+    the pipelined form (continuous batching, double-buffered merge) against
+    one round at a time.  Each form serves a warm-up stream first on its
+    context; every call's host log follows the previous call's."""
     N = 1 << 27
     host_lo = N - N // 16
     g = wl.rng("c5", 0, 3)
     init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
-    req = wl.c5_requests(g, args.serve_requests, args.serve_rate, n_words=N, host_lo=host_lo)
     per_round = 1 << 16
     hlog = wl.host_log_uniform(np.random.default_rng(5), 1 << 23, host_lo, N, 0, shuffle_ts=False)
-    res = {"workload": f"2^27 u32 words, {args.serve_requests} requests at {args.serve_rate:g} txn/s Poisson, "
-                       f"lognormal lengths (median 4, max 64), 5% hot words, host log {per_round}/round, "
-                       f"budget 2 GiB, granule 64"}
-    forms = (("pipelined", True, dict(mode=1, async_merge=True)),
-             ("pipelined_sync_merge", True, dict(mode=1)),
-             ("plain", False, dict(mode=0)))
+    rates = [float(x) for x in args.serve_rates.split(",")]
+    bound_ms = args.serve_p99_bound_ms
+    out = {"workload": f"2^27 u32 words, Poisson arrivals, lognormal lengths (median 4, max 64), 5% hot words, "
+                       f"host log {per_round}/round, budget 2 GiB, granule 64; requests per point: rate x "
+                       f"{args.serve_seconds} s (at least 2^17, at most 2^21)",
+           "p99_bound_ms": bound_ms, "points": {}}
+    forms = (("pipelined", True, dict(mode=1, async_merge=True)), ("plain", False, dict(mode=0)))
+    call = [0]
+
+    def serve(ctx, host, req, pipelined):
+        call[0] += 1
+        later = hlog.copy()
+        later["ts"] += np.uint64(call[0] << 40)
+        return ctx.serve(req["arrival_s"], req["batch"], host, later, per_round, 1 << 20, 2 << 30, pipelined)
+
     for name, pipelined, kw in forms:
-        if args.serve_forms and name not in args.serve_forms.split(","):
-            continue
-        log(f"served form: {name} ...")
         ctx = hm.Context(N, 4, 64, init=init, max_ops=64, batch_capacity=1 << 20, log_capacity=per_round, **kw)
         host = hm.pinned(N * 4)
         host.numpy()[:] = init.view(np.uint8)
-        ctx.serve(req["arrival_s"], req["batch"], host, hlog, per_round, 1 << 20, 2 << 30, pipelined)
+        warm = wl.c5_requests(g, 1 << 17, 1e7, n_words=N, host_lo=host_lo)
+        serve(ctx, host, warm, pipelined)
         ctx.sync()
-        later = hlog.copy()
-        later["ts"] += np.uint64(1 << 40)
-        st0 = ctx.stats()
-        o = ctx.serve(req["arrival_s"], req["batch"], host, later, per_round, 1 << 20, 2 << 30, pipelined)
-        st = ctx.stats()
+        pts = {}
+        for rate in rates:
+            n = int(min(max(rate * args.serve_seconds, 1 << 17), 1 << 21))
+            req = wl.c5_requests(g, n, rate, n_words=N, host_lo=host_lo)
+            log(f"served {name}: {n} requests at {rate:g}/s ...")
+            o = serve(ctx, host, req, pipelined)
+            ctx.sync()
+            pts[f"{rate:g}"] = {"offered_txn_s": rate, "throughput_txn_s": o["throughput"],
+                                "p50_latency_us": o["p50_latency_us"], "p99_latency_us": o["p99_latency_us"],
+                                "rounds": int(o["rounds"]), "requests": n,
+                                "serving_thread_ms": {k: round(o["us_" + k] / 1e3, 2) for k in
+                                                      ("pack", "wait_round", "settle", "host_commit", "wait_merge",
+                                                       "idle")}}
         ctx.close()
-        res[name] = {"throughput_txn_s": o["throughput"], "p50_latency_us": o["p50_latency_us"],
-                     "p99_latency_us": o["p99_latency_us"], "rounds": int(o["rounds"]),
-                     "conflicted_rounds": int(o["conflicted_rounds"]),
-                     "host_scatter_ms": (st.us_host_scatter - st0.us_host_scatter) / 1e3,
-                     "merge_wait_ms": (st.us_merge_wait - st0.us_merge_wait) / 1e3,
-                     "serving_thread_ms": {k: round(o["us_" + k] / 1e3, 2) for k in
-                                           ("pack", "wait_round", "settle", "host_commit", "wait_merge", "idle")}}
-    return res
+        ok = [p for p in pts.values() if p["p99_latency_us"] <= bound_ms * 1e3]
+        out["points"][name] = pts
+        out[f"{name}_best_txn_s_within_p99_bound"] = max((p["throughput_txn_s"] for p in ok), default=None)
+    return out
+
+
+def cpu_baseline(args, orc, ri, tickets) -> dict:
+    """The C oracle replaying whole large rounds (in the GPU's commit order)
+    on one host core for about 10 s."""
+    info = cpu_info()
+    keep = os.sched_getaffinity(0)
+    core = max(keep)
+    os.sched_setaffinity(0, {core})
+    try:
+        order = orc.order_from_tickets(tickets, even_ties=True)
+        el, n_rounds, committed = 0.0, 0, 0
+        N, G = ri.n_words, ri.granule
+        while el < args.cpu_seconds and n_rounds < 40:
+            S, H = ri.init.copy(), ri.init.copy()
+            TS = np.zeros(N, np.uint64)
+            t1 = time.perf_counter()
+            o = orc.round_oplist(S, H, TS, G, ri.batch, order, ri.log, 0)
+            el += time.perf_counter() - t1
+            n_rounds += 1
+            committed += 0 if o["conflict"] else ri.batch.n
+            del S, H, TS
+    finally:
+        os.sched_setaffinity(0, keep)
+    return {"value": committed / el, "unit": "txn/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_rounds} whole rounds of the large configuration ({ri.batch.n} txns, {ri.log.shape[0]} log "
+                      f"entries each, replayed in the GPU's commit order) by the single-threaded C oracle pinned to "
+                      f"core {core}: {el:.1f} s",
+            "host": info}
 
 
 def main():
@@ -142,29 +570,28 @@ def main():
     ap.add_argument("--granule", type=int, default=16)
     ap.add_argument("--p-hot", type=float, default=0.5)
     ap.add_argument("--stripe", type=int, default=1)
-    ap.add_argument("--exec-wg", type=int, default=0, help="transaction-kernel workgroups (0 = occupancy x CUs)")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=3e7, help="Poisson arrival rate of the served form (txn/s)")
-    ap.add_argument("--serve-requests", type=int, default=1 << 21)
-    ap.add_argument("--serve-forms", default="", help="comma list of served forms to run (default: all)")
-    ap.add_argument("--serve-only", action="store_true", help="run only the served forms")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--exec-wg", type=int, default=0, help="transaction-kernel workgroups (0 = one per CU)")
+    ap.add_argument("--legs", default="ingest,small,conflict,bank,cache,served,cpu",
+                    help="comma list of legs beside the headline (ingest, small, conflict, bank, cache, served, cpu)")
+    ap.add_argument("--small-rounds", type=int, default=200)
+    ap.add_argument("--bank-rounds", type=int, default=3)
+    ap.add_argument("--cache-rounds", type=int, default=3)
+    ap.add_argument("--serve-rates", default="1e6,3e6,1e7,3e7,1e8")
+    ap.add_argument("--serve-seconds", type=float, default=0.25)
+    ap.add_argument("--serve-p99-bound-ms", type=float, default=5.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 1 GiB device copy, the known-size reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs a round on one GPU; there is no multi-GPU path, so --gpus must be 1"}))
         sys.exit(2)
+    legs = set(x for x in args.legs.split(",") if x)
 
     import torch
 
     from paper_1905_00661_amd import hetm as hm
     from paper_1905_00661_amd import workloads as wl
-
-    if args.serve_only:
-        print(json.dumps({"served": serve_forms(args, hm, wl, torch)}), flush=True)
-        return
 
     N, n_txn, n_log = 1 << args.log2_words, 1 << args.log2_txns, 1 << args.log2_log
     G = args.granule
@@ -184,125 +611,62 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    rounds = args.warmup + args.steps
 
-    # per-round logs resident in HBM: same words/values, timestamps shifted
-    base_log = hm.to_device(ri.log, dev)
-    logs = []
-    for r in range(rounds + 1):
-        t = base_log.clone()
-        ts = t.view(torch.int64).view(-1, 2)[:, 1]
-        ts.add_(r * n_log)
-        logs.append(t)
-    torch.cuda.synchronize()
-
-    host = hm.pinned(N * 4)
-    host.numpy()[:] = ri.init.view(np.uint8)
-
-    def run(mode: int, k_steps: int, warm: int, async_merge: bool = False):
-        ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=n_txn,
-                         log_capacity=n_log, mode=mode, exec_workgroups=args.exec_wg, async_merge=async_merge)
-        b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
-        flags = torch.zeros(((n_log + 31) // 32) * 4, dtype=torch.uint8, device=dev)
-        torch.cuda.synchronize()
-        res = []
-        for r in range(warm):
-            ctx.round(b, logs[r], n_log, host, flags)
-        torch.cuda.synchronize()
-        lat = []
-        t_start = time.perf_counter()
-        for r in range(warm, warm + k_steps):
-            t1 = time.perf_counter()
-            rr = ctx.round(b, logs[r], n_log, host, flags)
-            lat.append(time.perf_counter() - t1)
-            res.append(rr.as_dict())
-        ctx.sync()                       # the last round's merge copy has landed
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-        tickets = b.tickets_np().copy()
-        st = ctx.stats()
-        ctx.close()
-        run.scatter_ms = st.us_host_scatter / 1e3 / (warm + k_steps)
-        return elapsed, lat, res, tickets
-
-    log("batched form (graph + double-buffered merge) ...")
-    el_g, lat_g, res_g, tickets = run(hm.HETM_MODE_GRAPH, args.steps, args.warmup, async_merge=True)
-    committed = sum(r["n_committed"] for r in res_g)
-    value = committed / el_g
+    large = large_forms(args, hm, wl, torch, ri, dev)
+    bat, plain = large["batched"], large["plain"]
     out = {
-        "metric": "committed txns/s + validate/apply GB/s vs HBM peak; p50/p99 commit latency",
-        "value": value, "unit": "txn/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * el_g / args.steps, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": bat["value"], "unit": "txn/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": bat["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"large synthetic STMR: 2^{args.log2_words} u32 words, 2^{args.log2_txns} txns/batch "
                                f"(90% RO x16 reads, 10% 4RMW), hot 1% at p={args.p_hot}, host log "
                                f"2^{args.log2_log}, granule {G}, lock stripe {args.stripe}",
-                   "form": "batched: hipGraph round, persistent transaction kernel, double-buffered merge"},
-        "p50_round_ms": 1e3 * float(np.percentile(lat_g, 50)),
-        "p99_round_ms": 1e3 * float(np.percentile(lat_g, 99)),
-        "conflict_rounds": sum(r["conflict"] for r in res_g),
-        "local_retries_per_round": float(np.mean([r["n_local_retries"] for r in res_g])),
-        "dirty_granules_per_round": float(np.mean([r["n_dirty"] for r in res_g])),
-        "graph_us": float(np.mean([r["us_total"] for r in res_g])),
-        "host_scatter_ms_per_round": run.scatter_ms,
+                   "form": "batched: hipGraph round, persistent transaction kernel, double-buffered merge; "
+                           "inputs resident in HBM"},
+        **{k: v for k, v in bat.items() if k not in ("value", "ms_per_step")},
+        "graph_sync_merge": large["graph_sync_merge"], "plain": plain,
+        "batched_vs_plain": bat["value"] / plain["value"],
     }
-    log("graph form, merge inside the round ...")
-    el_s, lat_s, res_s, _ = run(hm.HETM_MODE_GRAPH, args.steps, args.warmup)
-    out["graph_sync_merge"] = {"value": sum(r["n_committed"] for r in res_s) / el_s,
-                               "ms_per_step": 1e3 * el_s / args.steps}
+    va = n_log * VALIDATE_APPLY_BYTES_PER_ENTRY / (plain["us_validate"] * 1e-6) / 1e9
+    vs = n_log * VALIDATE_APPLY_STREAM_BYTES_PER_ENTRY / (plain["us_validate"] * 1e-6) / 1e9
+    out["validate_apply"] = {"us_per_chunk": plain["us_validate"], "entries": n_log,
+                             "alg_GBps": va, "alg_frac_of_hbm_peak": va / HBM_PEAK_GBPS,
+                             "alg_bytes_per_entry": VALIDATE_APPLY_BYTES_PER_ENTRY,
+                             "streamed_GBps": vs, "streamed_frac_of_hbm_peak": vs / HBM_PEAK_GBPS,
+                             "streamed_bytes_per_entry": VALIDATE_APPLY_STREAM_BYTES_PER_ENTRY}
+    # roofline of the dominant kernel: the transaction kernel, timed alone by
+    # events on its stream just before and after it in the plain form
+    alg = exec_alg_bytes(ri.batch)
+    ach = alg / (plain["us_exec_kernel"] * 1e-6) / 1e9
+    scope = exec_scope_bytes(ri.batch)
+    out["roofline"] = {"bound": "hbm", "kernel": "k_exec_oplist", "achieved": ach, "peak": HBM_PEAK_GBPS,
+                       "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS, "traffic": load_traffic("k_exec_oplist"),
+                       "alg_bytes_per_launch": alg, "avg_launch_us": plain["us_exec_kernel"],
+                       "scope_bytes_per_launch": scope,
+                       "scope_frac": scope / (plain["us_exec_kernel"] * 1e-6) / 1e9 / HBM_PEAK_GBPS}
 
-    if not args.no_plain:
-        log("plain form ...")
-        el_p, lat_p, res_p, _ = run(hm.HETM_MODE_PLAIN, args.steps, args.warmup)
-        us = {k: float(np.mean([r[k] for r in res_p]))
-              for k in ("us_exec", "us_exec_kernel", "us_validate", "us_merge", "us_total")}
-        out["plain"] = {"value": sum(r["n_committed"] for r in res_p) / el_p, "ms_per_step": 1e3 * el_p / args.steps,
-                        "p50_round_ms": 1e3 * float(np.percentile(lat_p, 50)),
-                        "p99_round_ms": 1e3 * float(np.percentile(lat_p, 99)), **us}
-        out["batched_vs_plain"] = value / out["plain"]["value"]
-        va_bytes = VALIDATE_APPLY_BYTES_PER_ENTRY * n_log
-        out["validate_apply"] = {"achieved_GBps": va_bytes / (us["us_validate"] * 1e-6) / 1e9,
-                                 "frac_of_hbm_peak": va_bytes / (us["us_validate"] * 1e-6) / 1e9 / HBM_PEAK_GBPS,
-                                 "bytes_per_entry": VALIDATE_APPLY_BYTES_PER_ENTRY}
-        # the transaction kernel alone (events on its stream just before and
-        # after it); us_exec also covers the batch set-up kernels
-        steps_us = {"exec": us["us_exec_kernel"], "validate_apply": us["us_validate"], "merge": us["us_merge"]}
-        dominant = max(steps_us, key=steps_us.get)
-        if dominant == "exec":
-            alg = exec_alg_bytes(ri.batch)
-            kern = "k_exec_oplist"
-        elif dominant == "validate_apply":
-            alg = va_bytes
-            kern = "k_validate+k_apply"
-        else:
-            alg = 2.0 * out["dirty_granules_per_round"] * G * 4
-            kern = "k_compact+k_copy"
-        ach = alg / (steps_us[dominant] * 1e-6) / 1e9
-        out["roofline"] = {"bound": "hbm", "kernel": kern, "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBPS, "traffic": load_traffic(kern),
-                           "alg_bytes_per_launch": alg, "avg_launch_us": steps_us[dominant]}
-
-    if not args.no_serve:
-        out["served"] = serve_forms(args, hm, wl, torch)
-
-    if not args.no_cpu:
+    if "ingest" in legs:
+        log("ingest: inputs from pinned host memory, results fetched ...")
+        out["ingest"] = ingest_form(args, hm, wl, torch, ri, dev)
+    if "small" in legs:
+        log("small round latency ...")
+        out["small"] = small_round(args, hm, wl, torch, dev)
+    if "conflict" in legs:
+        log("conflicting rounds ...")
+        out["conflict"] = conflict_form(args, hm, wl, torch, ri, dev)
+    if "bank" in legs:
+        log("bank transfers ...")
+        out["bank"] = bank_form(args, hm, wl, torch, dev)
+    if "cache" in legs:
+        log("object cache ...")
+        out["cache"] = cache_form(args, hm, wl, torch, dev)
+    if "served" in legs:
+        out["served"] = serve_sweep(args, hm, wl, torch)
+    tickets = large.pop("tickets")
+    if "cpu" in legs:
         import oracle as orc
-        log("cpu baseline (oracle, whole rounds for ~10 s) ...")
-        order = orc.order_from_tickets(tickets, even_ties=True)
-        el_c, n_rounds, committed = 0.0, 0, 0
-        while el_c < 10.0 and n_rounds < 40:
-            S, H = ri.init.copy(), ri.init.copy()
-            TS = np.zeros(N, np.uint64)
-            t1 = time.perf_counter()
-            o = orc.round_oplist(S, H, TS, G, ri.batch, order, ri.log, 0)
-            el_c += time.perf_counter() - t1
-            n_rounds += 1
-            committed += 0 if o["conflict"] else ri.batch.n
-            del S, H, TS
-        out["cpu_baseline"] = {"value": committed / el_c, "unit": "txn/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{n_rounds} whole rounds of the same workload ({ri.batch.n} txns, {n_log} "
-                                         f"log entries each, replayed in the GPU's commit order) by the "
-                                         f"single-threaded C oracle: {el_c:.1f} s"}
+        log("cpu baseline (oracle, whole rounds for ~10 s, one pinned core) ...")
+        out["cpu_baseline"] = cpu_baseline(args, orc, ri, tickets)
     print(json.dumps(out), flush=True)
 
 

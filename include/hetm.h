@@ -296,7 +296,7 @@ typedef struct {
 /* A whole round: execution, validation+apply, merge, reset, in the
  * context's mode.  With async_merge, a successful round returns as soon as
  * its dirty granules are staged in HBM (merge_pending = 1); their copy to
- * the host starts with the next round's transaction kernel, and the host
+ * the host is issued once the next round's graph is queued, and the host
  * replica holds them after hetm_sync or once the round after the next
  * returns (two rounds' merges may be in flight, one per staging buffer).
  * Until then the caller must not write the host replica: the merge would
@@ -319,7 +319,9 @@ int hetm_round(hetm_ctx *ctx, const hetm_round_args *args, hetm_round_result *re
 /* ------------------------------------------------------------- auxiliary */
 
 const char *hetm_strerror(int code);
-const char *hetm_last_error(hetm_ctx *ctx);   /* detail of the last failure */
+const char *hetm_last_error(hetm_ctx *ctx);   /* detail of the context's last failure;
+                                                 NULL: of this thread's last failed
+                                                 hetm_alloc_stmr */
 int hetm_sync(hetm_ctx *ctx);                 /* waits for all work, including
                                                  pending merge copies; returns a
                                                  latched error */

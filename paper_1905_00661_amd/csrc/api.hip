@@ -308,9 +308,7 @@ int build_graph(hetm_ctx *c, uint32_t policy) {
     // round's merge copy (device-to-host posted writes) and stall the launch.
     launch_set_args(c->args, c->dargs, s);
     hipError_t ce = hipSuccess;
-    if (c->cfg.async_merge && !c->exec_ev) ce = hipEventCreateWithFlags(&c->exec_ev, hipEventDisableTiming);
-    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s,
-                c->cfg.async_merge ? c->exec_ev : nullptr);
+    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s);
     if (fork) {
         hipStream_t br = c->cap_branch;
         if (ce == hipSuccess) ce = hipEventRecord(c->fork_ev, s);
@@ -462,9 +460,9 @@ int round_begin(hetm_ctx *c, const hetm_round_args *r) {
     HIP_TRY(c, hipGraphExecKernelNodeSetParams(rg.exec, rg.args_node, &kp));
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, hipGraphLaunch(rg.exec, s));
-    // the last round's copy to the host starts with this round's transaction
-    // kernel (its end event, ev[3], is re-recorded only below)
-    if ((rc = issue_merge(c, c->exec_ev))) return rc;
+    // the last round's copy to the host is issued once this round's graph
+    // is queued (its end event, ev[3], is re-recorded only below)
+    if ((rc = issue_merge(c, nullptr))) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[3], s));
     c->round_open = true;
     c->round_hdev = hdev;
@@ -549,7 +547,22 @@ const char *hetm_strerror(int code) {
     }
 }
 
-const char *hetm_last_error(hetm_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+// detail of the last failed hetm_alloc_stmr of this thread (no context exists then)
+static thread_local char g_alloc_err[512] = "no failed allocation";
+
+const char *hetm_last_error(hetm_ctx *ctx) { return ctx ? ctx->err : g_alloc_err; }
+
+namespace {
+// Records why an allocation failed (with the pending HIP error, if any),
+// releases what the context holds and returns code.
+int alloc_fail(hetm_ctx *c, int code, const char *what) {
+    const hipError_t e = hipGetLastError();
+    snprintf(g_alloc_err, sizeof g_alloc_err, "%s%s%s%s%s", what, c && c->err[0] ? ": " : "", c ? c->err : "",
+             e != hipSuccess ? "; HIP: " : "", e != hipSuccess ? hipGetErrorString(e) : "");
+    if (c) hetm_free(c);
+    return code;
+}
+}  // namespace
 
 int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **out) {
     if (!cfg || !out) return HETM_EINVAL;
@@ -568,17 +581,14 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     c->device = k.device;
     c->log_entry_bytes = k.word_bytes == 4 ? sizeof(hetm_log_entry4) : sizeof(hetm_log_entry8);
     int rc = HETM_OK;
-#define TRY(x)                      \
-    do {                            \
-        rc = (x);                   \
-        if (rc) {                   \
-            hetm_free(c);           \
-            return rc;              \
-        }                           \
+#define TRY(x)                                   \
+    do {                                         \
+        rc = (x);                                \
+        if (rc) return alloc_fail(c, rc, #x);    \
     } while (0)
     if (hipSetDevice(k.device) != hipSuccess) {
         delete c;
-        return HETM_EDEVICE;
+        return alloc_fail(nullptr, HETM_EDEVICE, "hipSetDevice");
     }
     c->stream = (hipStream_t)k.stream;
     const uint64_t N = k.n_words, G = k.granule_words;
@@ -624,47 +634,31 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
             // pinned host staging for every granule: sized once, so no
             // allocation (or the device-wide wait of a free) sits in a round
             if (hipHostMalloc((void **)&c->host_stage[b], nG * G * k.word_bytes, hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc((void **)&c->host_ids[b], nG * 4, hipHostMallocDefault) != hipSuccess) {
-                hetm_free(c);
-                return HETM_ENOMEM;
-            }
+                hipHostMalloc((void **)&c->host_ids[b], nG * 4, hipHostMallocDefault) != hipSuccess)
+                return alloc_fail(c, HETM_ENOMEM, "pinned host staging");
             touch_pages(c->host_stage[b], nG * G * k.word_bytes);
             touch_pages(c->host_ids[b], nG * 4);
             c->host_cap[b] = nG;
         }
-        if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
-            hetm_free(c);
-            return HETM_EDEVICE;
-        }
+        if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess)
+            return alloc_fail(c, HETM_EDEVICE, "copy stream");
         c->merger = hetm::merge_worker_create();
-        if (!c->merger) {
-            hetm_free(c);
-            return HETM_ENOMEM;
-        }
+        if (!c->merger) return alloc_fail(c, HETM_ENOMEM, "merge worker");
         for (int b = 0; b < 2; ++b)
-            if (hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming) != hipSuccess) {
-                hetm_free(c);
-                return HETM_EDEVICE;
-            }
+            if (hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming) != hipSuccess)
+                return alloc_fail(c, HETM_EDEVICE, "merge events");
     }
     if (hipHostMalloc((void **)&c->hargs, sizeof(DevArgs), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->snap_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->cnt_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess) {
-        hetm_free(c);
-        return HETM_ENOMEM;
-    }
+        hipHostMalloc((void **)&c->cnt_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess)
+        return alloc_fail(c, HETM_ENOMEM, "pinned host counters");
     for (hipEvent_t *e : {&c->ev[0], &c->ev[1], &c->ev[2], &c->ev[3], &c->ev_kernel})
-        if (hipEventCreate(e) != hipSuccess) {
-            hetm_free(c);
-            return HETM_EDEVICE;
-        }
+        if (hipEventCreate(e) != hipSuccess) return alloc_fail(c, HETM_EDEVICE, "timing events");
     if (hipStreamCreateWithFlags(&c->early_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->closed_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->early_ev, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void **)&c->early_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
-        hetm_free(c);
-        return HETM_EDEVICE;
-    }
+        hipHostMalloc((void **)&c->early_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+        return alloc_fail(c, HETM_EDEVICE, "early-validation stream and events");
     hipStream_t s = c->stream;
     bool ok = (c->slot || hipMemsetAsync(c->locks, 0, nlocks * 8, s) == hipSuccess) &&
               hipMemsetAsync(c->rs, 0, nrw * 4, s) == hipSuccess &&
@@ -672,29 +666,26 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
               hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), s) == hipSuccess &&
               hipMemsetAsync(c->hot, 0, sizeof(HotCounters), s) == hipSuccess &&
               hipMemsetAsync(c->blocksums, 0, nblocks * 4, s) == hipSuccess;
-    if (ok && c->slot && init_image) {
+    if (!ok) return alloc_fail(c, HETM_EDEVICE, "clearing the context's state");
+    if (c->slot && init_image) {
         // the image goes through the TS array (N u64, cleared afterwards)
-        ok = hipMemcpyAsync(c->ts, init_image, N * 4, hipMemcpyDefault, s) == hipSuccess;
-        if (ok) launch_to_slots((const uint32_t *)c->ts, (uint64_t *)c->stmr, N, s);
-        ok = ok && hipGetLastError() == hipSuccess;
-    } else if (ok) {
+        if (hipMemcpyAsync(c->ts, init_image, N * 4, hipMemcpyDefault, s) != hipSuccess)
+            return alloc_fail(c, HETM_EDEVICE, "copying the initial image");
+        (void)hipGetLastError();     // an error left by earlier, unrelated calls must not count here
+        launch_to_slots((const uint32_t *)c->ts, (uint64_t *)c->stmr, N, s);
+        if (hipPeekAtLastError() != hipSuccess) return alloc_fail(c, HETM_EDEVICE, "slot-layout conversion");
+    } else {
         ok = init_image ? hipMemcpyAsync(c->stmr, init_image, N * k.word_bytes, hipMemcpyDefault, s) == hipSuccess
                         : hipMemsetAsync(c->stmr, 0, c->slot ? N * 8 : N * k.word_bytes, s) == hipSuccess;
+        if (!ok) return alloc_fail(c, HETM_EDEVICE, "copying the initial image");
     }
-    ok = ok && hipMemsetAsync(c->ts, 0, N * 8, s) == hipSuccess;
-    if (!ok || hipStreamSynchronize(s) != hipSuccess) {
-        hetm_free(c);
-        return HETM_EDEVICE;
-    }
+    if (hipMemsetAsync(c->ts, 0, N * 8, s) != hipSuccess) return alloc_fail(c, HETM_EDEVICE, "clearing TS");
+    if (hipStreamSynchronize(s) != hipSuccess) return alloc_fail(c, HETM_EDEVICE, "initial synchronization");
     hipDeviceProp_t prop;
     int cus = 256;
     if (hipGetDeviceProperties(&prop, k.device) == hipSuccess) cus = prop.multiProcessorCount;
     c->exec_wg = k.exec_workgroups ? k.exec_workgroups : default_exec_workgroups(cus);
-    if (exec_prepare(k.max_txn_ops) != hipSuccess) {
-        (void)hipGetLastError();
-        hetm_free(c);
-        return HETM_EDEVICE;
-    }
+    if (exec_prepare(k.max_txn_ops) != hipSuccess) return alloc_fail(c, HETM_EDEVICE, "transaction-kernel LDS limit");
 
     DevArgs &a = c->args;
     a.stmr = c->stmr, a.locks = c->locks, a.ts = c->ts, a.rs = c->rs, a.ws = c->ws;
@@ -733,7 +724,6 @@ int hetm_free(hetm_ctx *c) {
     }
     drop_graphs(c);
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
-    if (c->exec_ev) (void)hipEventDestroy(c->exec_ev);
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);

@@ -60,12 +60,11 @@ struct hetm_ctx {
     } graphs[2];
     hipStream_t cap_branch = nullptr;       // capture only: the merge branch
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-    hipEvent_t exec_ev = nullptr;           // recorded by the round graph as its transaction kernel starts
 
     // A successful round's copy to the host is issued once the next round's
-    // transaction kernel has started (or when something waits for merges):
-    // the copy's host-bound writes would otherwise delay the next round's
-    // first, host-reading steps (argument upload, kernel dispatch).
+    // graph is queued (or when something waits for merges): issued at the
+    // round's end instead, the copy's host-bound writes delayed the next
+    // round's first, host-reading steps (argument upload, kernel dispatch).
     bool merge_deferred = false;
     int deferred_buf = 0;
     uint64_t deferred_n = 0;
@@ -115,7 +114,7 @@ namespace hetm {
 int round_begin(hetm_ctx *c, const hetm_round_args *r);
 int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res);
 // Double-buffered merge progress.  A successful round's copy to the host is
-// issued by the next round_begin (as its transaction kernel starts) or by
+// issued by the next round_begin (after it queues its graph) or by
 // issue_deferred_merge; last_merge_seq is the most recently issued job (0
 // after a round that left nothing to merge), merged_seq the last job whose
 // granules are in the host replica, wait_merged a wait for a job.

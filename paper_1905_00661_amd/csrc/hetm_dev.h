@@ -282,7 +282,8 @@ void launch_clear_error(DevCounters *cnt, hipStream_t s);
 // slot: the context keeps u32 words in the slot layout (value, version and
 // lock in one u64 per word) instead of a value array plus a lock table
 // OPLIST also launches the kind split, sized for batch_capacity transactions;
-// exec_started (nullable) is recorded on s just before the transaction kernel
+// exec_started (nullable, not for capture) is recorded on s just before the
+// transaction kernel (PLAIN rounds time the kernel with it)
 void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, bool slot,
                  uint64_t batch_capacity, hipStream_t s, hipEvent_t exec_started = nullptr);
 // allows the OPLIST kernel the dynamic LDS a context's max_ops needs

@@ -164,7 +164,9 @@ def _check(rc: int, what: str, ctx=None):
 
 def hetm_alloc_stmr(cfg: hetm_config, init_image: int | None) -> int:
     out = P()
-    _check(lib().hetm_alloc_stmr(ctypes.byref(cfg), init_image, ctypes.byref(out)), "hetm_alloc_stmr")
+    rc = lib().hetm_alloc_stmr(ctypes.byref(cfg), init_image, ctypes.byref(out))
+    if rc != HETM_OK:
+        raise HetmError(rc, "hetm_alloc_stmr", lib().hetm_last_error(None).decode())
     return out.value
 
 
