@@ -621,6 +621,10 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     TRY(dev_alloc(c, &c->blockruns, nblocks * 4));
     TRY(dev_alloc(c, &c->ids, nG * 4));
     TRY(dev_alloc(c, &c->order, k.batch_capacity * 4));
+    // the hot-object chains of the TRANSFER and CACHE programs
+    TRY(dev_alloc(c, &c->tx_tab, kTxTabSlots * 8ull));
+    TRY(dev_alloc(c, &c->tx_hot, kTxMaxHot * 8ull));
+    TRY(dev_alloc(c, &c->tx_chain, kTxChainWords * 4ull));
     TRY(dev_alloc(c, &c->log_staging, k.log_capacity * c->log_entry_bytes));
     TRY(dev_alloc(c, &c->cnt, sizeof(DevCounters)));
     TRY(dev_alloc(c, &c->hot, sizeof(HotCounters)));
@@ -665,7 +669,9 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
               hipMemsetAsync(c->ws, 0, nbw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), s) == hipSuccess &&
               hipMemsetAsync(c->hot, 0, sizeof(HotCounters), s) == hipSuccess &&
-              hipMemsetAsync(c->blocksums, 0, nblocks * 4, s) == hipSuccess;
+              hipMemsetAsync(c->blocksums, 0, nblocks * 4, s) == hipSuccess &&
+              hipMemsetAsync(c->tx_tab, 0, kTxTabSlots * 8ull, s) == hipSuccess &&
+              hipMemsetAsync(c->tx_chain, 0, kTxChainWords * 4ull, s) == hipSuccess;
     if (!ok) return alloc_fail(c, HETM_EDEVICE, "clearing the context's state");
     if (c->slot && init_image) {
         // the image goes through the TS array (N u64, cleared afterwards)
@@ -695,6 +701,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     a.log_sorted = c->log_sorted, a.log_win = c->log_win;
     a.log_bins = c->log_bins, a.log_bin_bits = ilog2(c->log_bins), a.log_tiles = c->log_tiles;
     a.order = c->order;
+    a.tx_tab = c->tx_tab, a.tx_hot = c->tx_hot, a.tx_chain = c->tx_chain;
     a.cnt = c->cnt;
     a.hot = c->hot;
     a.gdiv = make_div32((uint32_t)G);
@@ -729,8 +736,8 @@ int hetm_free(hetm_ctx *c) {
         if (e) (void)hipEventDestroy(e);
     if (c->ev_kernel) (void)hipEventDestroy(c->ev_kernel);
     void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->log_hist, c->log_bstart, c->log_bwin, c->log_totals,
-                   c->log_sorted, c->log_win, c->blocksums, c->blockruns, c->ids, c->order, c->log_staging, c->cnt,
-                   c->hot, c->snap_dev, c->dargs};
+                   c->log_sorted, c->log_win, c->blocksums, c->blockruns, c->ids, c->order, c->tx_tab, c->tx_hot,
+                   c->tx_chain, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->hargs) (void)hipHostFree(c->hargs);

@@ -607,12 +607,476 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
     flush_counts(ls, cnt);
 }
 
+// CACHE layout constants (see the CACHE kernel below) and the set a key maps to.
+constexpr uint32_t kSetWords = 128, kStampBase = 16, kSetStamp = 24, kValBase = 32;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {   // splitmix64 finalizer
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t cache_set(uint64_t key, uint64_t nsets) {
+    return (uint32_t)((mix64(key) & (nsets - 1) & ~1ull) | (key & 1ull));
+}
+
 // ---------------------------------------------------------------- TRANSFER
 // Reads balances of src and dst (int64 words); if src != dst and the source
 // balance covers amt, moves amt.  Results: [bs | bd | applied] (3 x n int64).
+//
+// Skewed account popularity (the bank workload draws accounts Zipf(0.9))
+// makes a few accounts part of a large share of the batch.  Run as one
+// transaction per lane, every commit on such an account hands its lock to
+// the next lane through device memory, and the lanes in between abort and
+// retry.  So before the transaction kernel a sample of the batch names the
+// hot accounts, each transfer touching one becomes part of that account's
+// chain (the hotter account's, if both are hot), and the kernel runs each
+// chain on one wave: the wave holds the hot account's balance in a register
+// and applies up to 64 transfers per step under the locks of both sides,
+// in lane order, with consecutive commit tickets.  The other transfers form
+// the cold list and run one per lane as before.  Which transfers run
+// together has no bearing on serializability: every transfer still commits
+// under the locks of both of its accounts with its ticket taken inside.
+
+constexpr uint32_t kTxSample = 1u << 16;          // transfers sampled per batch
+constexpr uint32_t kTxHotMin = 4;                 // sample appearances that make an account hot
+constexpr uint32_t kTxMapSlots = 2 * kTxMaxHot;   // LDS map of the hot accounts
+constexpr uint32_t kTxTile = 4096;                // transfers per classify / scatter block and tile
+constexpr uint32_t kTxThreads = 256;
+constexpr uint32_t kNoChain = 0xFFFFFFFFu;
+constexpr uint32_t kNoAccount = 0xFFFFFFFFu;      // free map slot (accounts are below 2^32 - 1)
+
+__device__ __forceinline__ uint32_t tx_hash(uint32_t w) { return w * 0x9E3779B1u; }
+
+// count one appearance of account w in the sample table (key = w + 1 in the
+// high half, count in the low half); a crowded neighbourhood leaves w cold
+__device__ __forceinline__ void tx_count(uint64_t *tab, uint32_t w) {
+    const uint64_t key = (uint64_t)(w + 1) << 32;
+    uint32_t s = tx_hash(w) >> (32 - kTxTabBits);
+    for (uint32_t i = 0; i < 64; ++i, s = (s + 1) & (kTxTabSlots - 1)) {
+        uint64_t cur = ld_agent(&tab[s]);
+        if (cur == 0) {
+            uint64_t exp = 0;
+            if (__hip_atomic_compare_exchange_strong(&tab[s], &exp, key | 1ull, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT))
+                return;
+            cur = exp;
+        }
+        if ((cur & ~0xFFFFFFFFull) == key) {
+            __hip_atomic_fetch_add(&tab[s], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+    }
+}
+
+// The objects a transaction touches, as the hot-object pre-pass sees them:
+// a transfer's two accounts, a cache operation's set.  Returns 0 for a
+// malformed transaction (the transaction kernel reports it).
+template <uint32_t P>
+__device__ __forceinline__ uint32_t tx_objects(const DevArgs *a, uint32_t t, uint32_t &o0, uint32_t &o1) {
+    if constexpr (P == HETM_PROG_TRANSFER) {
+        o0 = a->src[t];
+        o1 = a->dst[t];
+        if (o0 >= a->n_words || o1 >= a->n_words) return 0;
+        return o0 == o1 ? 1 : 2;
+    } else {
+        const uint64_t key = a->key[t];
+        if (key == 0 || a->op[t] > 1) return 0;
+        o0 = o1 = cache_set(key, a->n_words / kSetWords);
+        return 1;
+    }
+}
+
+// every (n / S)-th transaction of the batch, S = min(n, kTxSample)
+template <uint32_t P>
+__global__ __launch_bounds__(kTxThreads) void k_tx_sample(const DevArgs *__restrict__ a) {
+    const uint32_t n = a->n_txns;
+    const uint32_t S = n < kTxSample ? n : kTxSample;
+    const uint32_t step = S ? n / S : 1;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) {
+        uint32_t o0, o1;
+        const uint32_t k = tx_objects<P>(a, i * step, o0, o1);
+        if (k >= 1) tx_count(a->tx_tab, o0);
+        if (k == 2) tx_count(a->tx_tab, o1);
+    }
+}
+
+// one thread per table slot: accounts seen kTxHotMin times or more become
+// chains; every slot is cleared for the next batch
+__global__ __launch_bounds__(kTxThreads) void k_tx_pick(const DevArgs *__restrict__ a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t v = a->tx_tab[i];
+    bool hot = false;
+    uint64_t e = 0;
+    if (v) {
+        a->tx_tab[i] = 0;
+        hot = (uint32_t)v >= kTxHotMin;
+        e = ((uint64_t)(uint32_t)v << 32) | ((v >> 32) - 1);
+    }
+    const uint32_t pos = wave_fetch_add(&a->hot->n_ro.v, hot);
+    if (hot && pos < kTxMaxHot) a->tx_hot[pos] = e;
+}
+
+struct HotMap {
+    uint32_t acc[kTxMapSlots];
+    uint16_t idx[kTxMapSlots];
+};
+
+__device__ __forceinline__ uint32_t tx_n_hot(const DevArgs *a) {
+    const uint32_t h = ld_agent(&a->hot->n_ro.v);
+    return h < kTxMaxHot ? h : kTxMaxHot;
+}
+
+__device__ void load_hot_map(const DevArgs *a, HotMap &m, uint32_t n_hot) {
+    for (uint32_t i = threadIdx.x; i < kTxMapSlots; i += blockDim.x) m.acc[i] = kNoAccount;
+    __syncthreads();
+    for (uint32_t h = threadIdx.x; h < n_hot; h += blockDim.x) {
+        const uint32_t w = (uint32_t)a->tx_hot[h];
+        uint32_t s = tx_hash(w) & (kTxMapSlots - 1);
+        while (atomicCAS(&m.acc[s], kNoAccount, w) != kNoAccount) s = (s + 1) & (kTxMapSlots - 1);
+        m.idx[s] = (uint16_t)h;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t hot_index(const HotMap &m, uint32_t w) {
+    uint32_t s = tx_hash(w) & (kTxMapSlots - 1);
+    for (;;) {
+        const uint32_t k = m.acc[s];
+        if (k == w) return m.idx[s];
+        if (k == kNoAccount) return kNoChain;
+        s = (s + 1) & (kTxMapSlots - 1);
+    }
+}
+
+// the chain a transaction belongs to: its hot object's, the hotter one's (by
+// sample count, then object) if both are hot, none if neither is
+template <uint32_t P>
+__device__ __forceinline__ uint32_t chain_of(const DevArgs *a, const HotMap &m, uint32_t t) {
+    uint32_t o0, o1;
+    const uint32_t k = tx_objects<P>(a, t, o0, o1);
+    if (k == 0) return kNoChain;
+    const uint32_t hs = hot_index(m, o0), hd = k == 1 ? hs : hot_index(m, o1);
+    if (hs == kNoChain) return hd;
+    if (hd == kNoChain || hd == hs) return hs;
+    return a->tx_hot[hs] > a->tx_hot[hd] ? hs : hd;
+}
+
+// classify: cold transactions go to the back of `order`; chain members are
+// counted per chain
+template <uint32_t P>
+__global__ __launch_bounds__(kTxThreads) void k_tx_classify(const DevArgs *__restrict__ a) {
+    __shared__ HotMap m;
+    __shared__ uint32_t hist[kTxMaxHot];
+    const uint32_t n = a->n_txns, n_hot = tx_n_hot(a);
+    for (uint32_t h = threadIdx.x; h < kTxMaxHot; h += blockDim.x) hist[h] = 0;
+    load_hot_map(a, m, n_hot);
+    uint32_t *order = a->order;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kTxTile; t0 < n; t0 += (uint64_t)gridDim.x * kTxTile) {
+        for (uint32_t k = threadIdx.x; k < kTxTile; k += kTxThreads) {   // uniform trip count
+            const uint64_t t = t0 + k;
+            uint32_t c = kNoChain;
+            if (t < n) c = chain_of<P>(a, m, (uint32_t)t);
+            const bool cold = t < n && c == kNoChain;
+            const uint32_t pos = wave_fetch_add(&a->hot->n_upd.v, cold);
+            if (cold) order[n - 1 - pos] = (uint32_t)t;
+            else if (t < n) atomicAdd(&hist[c], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t *count = a->tx_chain;
+    for (uint32_t h = threadIdx.x; h < n_hot; h += blockDim.x)
+        if (hist[h]) __hip_atomic_fetch_add(&count[h], hist[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// one block: each chain's first position in `order` and its cursor, and the
+// chains sorted by length, longest first; the counts are cleared
+__global__ __launch_bounds__(1024) void k_tx_plan(const DevArgs *__restrict__ a) {
+    __shared__ unsigned long long key[kTxMaxHot];
+    __shared__ uint32_t sh[1024 / kWave];
+    const uint32_t n_hot = tx_n_hot(a);
+    uint32_t *count = a->tx_chain, *start = count + kTxMaxHot, *cursor = start + kTxMaxHot + 1,
+             *corder = cursor + kTxMaxHot;
+    constexpr uint32_t kPer = kTxMaxHot / 1024;
+    uint32_t c[kPer], sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+        const uint32_t h = threadIdx.x * kPer + j;
+        c[j] = h < n_hot ? ld_agent(&count[h]) : 0u;
+        sum += c[j];
+        key[h] = h < n_hot ? ((unsigned long long)c[j] << 32) | h : 0ull;
+    }
+    // exclusive prefix of the per-thread sums
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    uint32_t inc = sum;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if ((int)lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) sh[wv] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (uint32_t i = 0; i < wv; ++i) run += sh[i];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+        const uint32_t h = threadIdx.x * kPer + j;
+        if (h < n_hot) {
+            start[h] = run;
+            cursor[h] = run;
+            count[h] = 0;
+        }
+        run += c[j];
+    }
+    if (threadIdx.x == 1023) start[n_hot] = run;
+    __syncthreads();
+    // bitonic sort, descending
+    for (uint32_t k = 2; k <= kTxMaxHot; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < kTxMaxHot; i += 1024) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const bool desc = (i & k) == 0;
+                    const unsigned long long x = key[i], y = key[l];
+                    if (desc ? x < y : x > y) {
+                        key[i] = y;
+                        key[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (uint32_t i = threadIdx.x; i < n_hot; i += 1024) corder[i] = (uint32_t)key[i];
+}
+
+// scatter: chain members into their chain's range of `order`, one atomic per
+// chain and tile reserving the tile's share
+template <uint32_t P>
+__global__ __launch_bounds__(kTxThreads) void k_tx_scatter(const DevArgs *__restrict__ a) {
+    __shared__ HotMap m;
+    __shared__ uint32_t pos[kTxMaxHot];
+    const uint32_t n = a->n_txns, n_hot = tx_n_hot(a);
+    if (n_hot == 0) return;
+    load_hot_map(a, m, n_hot);
+    uint32_t *order = a->order, *cursor = a->tx_chain + 2 * kTxMaxHot + 1;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kTxTile; t0 < n; t0 += (uint64_t)gridDim.x * kTxTile) {
+        for (uint32_t h = threadIdx.x; h < n_hot; h += kTxThreads) pos[h] = 0;
+        __syncthreads();
+        constexpr uint32_t kPer = kTxTile / kTxThreads;
+        uint32_t c[kPer];
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) {
+            const uint64_t t = t0 + j * kTxThreads + threadIdx.x;
+            c[j] = t < n ? chain_of<P>(a, m, (uint32_t)t) : kNoChain;
+            if (c[j] != kNoChain) atomicAdd(&pos[c[j]], 1u);
+        }
+        __syncthreads();
+        for (uint32_t h = threadIdx.x; h < n_hot; h += kTxThreads)
+            if (pos[h]) pos[h] = __hip_atomic_fetch_add(&cursor[h], pos[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j)
+            if (c[j] != kNoChain) order[atomicAdd(&pos[c[j]], 1u)] = (uint32_t)(t0 + j * kTxThreads + threadIdx.x);
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t k) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)k);
+}
+__device__ __forceinline__ int64_t readlane64(int64_t v, uint32_t k) {
+    const uint64_t u = (uint64_t)v;
+    return (int64_t)(((uint64_t)readlane((uint32_t)(u >> 32), k) << 32) | readlane((uint32_t)u, k));
+}
+// lane k's copy of v becomes x (x and k wave-uniform)
+__device__ __forceinline__ uint32_t writelane(uint32_t v, uint32_t x, uint32_t k) { return lane_id() == k ? x : v; }
+__device__ __forceinline__ int64_t writelane64(int64_t v, int64_t x, uint32_t k) { return lane_id() == k ? x : v; }
+
+// One wave applies the chain of hot account X: list[0 .. m) are transfer ids
+// that touch X.  Each step, lanes without a transfer take the chain's next
+// ones; lane 0 locks X's stripe, the first lane of every other stripe the
+// step touches locks it (a lane whose stripe is held elsewhere sits the step
+// out and keeps its transfer); the step's transfers are applied in lane
+// order with X's balance in a scalar register and the other accounts'
+// balances in the registers of the first lane naming them, take consecutive
+// tickets, store, mark the bitmaps and release (version + 1 for a stripe
+// that was written).  Every lock is a try-lock and released within the
+// step, so no wave waits while holding one.
+__device__ void run_chain(const DevArgs *a, const Split<uint64_t> &lay, uint32_t X, const uint32_t *list, uint32_t m,
+                          LaneState &ls, uint32_t *sflag, uint32_t epoch) {
+    DevCounters *cnt = a->cnt;
+    const uint32_t n = a->n_txns;
+    const uint64_t N = a->n_words;
+    const Div32 G = a->gdiv;
+    gmem<uint8_t> *rs = glob(a->rs);
+    gmem<uint32_t> *ws = glob(a->ws);
+    int64_t *res = (int64_t *)a->results;
+    const uint32_t lane = lane_id();
+    const uint32_t xst = lay.stripe(X);
+    uint32_t next = 0, t = kNoTxn, tries = 0;
+    for (;;) {
+        const bool need = t == kNoTxn;
+        const uint64_t nm = __ballot(need);
+        if (need && next + lanes_below(nm) < m) t = list[next + lanes_below(nm)];
+        next = min(m, next + (uint32_t)__popcll(nm));
+        const bool have = t != kNoTxn;
+        if (!__ballot(have)) break;
+        if (doomed(cnt, epoch)) break;
+        uint32_t s = 0, d = 0, am = 0;
+        if (have) {
+            s = a->src[t];
+            d = a->dst[t];
+            am = a->amt[t];
+        }
+        if (have && (s >= N || d >= N)) {      // malformed: reported, never executed
+            latch_error(cnt, HETM_EINVAL, t);
+            t = kNoTxn;
+            continue;
+        }
+        const bool live = t != kNoTxn;
+        const uint32_t y = s == X ? d : s;     // the other account (X itself for a transfer X -> X)
+        const uint32_t yst = lay.stripe(y);
+        // the first live lane naming the same account (its balance) and the
+        // same stripe (its lock)
+        uint32_t vslot = lane, lslot = lane;
+        const uint64_t lm = __ballot(live);
+        for (uint32_t k = 0; k < kWave; ++k) {
+            if (!((lm >> k) & 1u)) continue;
+            const uint32_t yk = readlane(y, k);
+            if (k < lane && vslot == lane && yk == y) vslot = k;
+            if (k < lane && lslot == lane && lay.stripe(yk) == yst) lslot = k;
+        }
+        // lock X's stripe, then every other stripe once
+        uint32_t xl = 0;
+        if (lane == 0) {
+            gmem<uint64_t> *p = lay.lock(X);
+            const uint64_t cur = ld_agent(p);
+            xl = !(cur & kLockBit) && cas_agent(p, cur, cur | kLockBit);
+        }
+        if (!readlane(xl, 0)) {                // another chain holds it (X as its other side): retry
+            if (live) {
+                ls.retries++;
+                if (++tries >= a->retry_cap) {
+                    latch_error(cnt, HETM_ERETRY, t);
+                    t = kNoTxn;
+                }
+            }
+            __builtin_amdgcn_s_sleep(4);
+            continue;
+        }
+        uint32_t mine = 0;                     // this lane holds the lock of stripe yst
+        if (live && lslot == lane && yst != xst) {
+            gmem<uint64_t> *p = lay.lock(y);
+            const uint64_t cur = ld_agent(p);
+            mine = !(cur & kLockBit) && cas_agent(p, cur, cur | kLockBit);
+        }
+        const bool part = live && (yst == xst || __shfl((int)mine, (int)lslot) != 0);
+        hw_order();                            // locks held before any balance is read
+        int64_t xv = 0, yv = 0;
+        if (lane == 0) xv = (int64_t)lay.load(X);
+        if (part && vslot == lane && y != X) yv = (int64_t)lay.load(y);
+        hw_order();
+        int64_t bx = readlane64(xv, 0);
+        int64_t r_bs = 0, r_bd = 0;
+        uint32_t r_ap = 0, ywr = 0, xwr = 0;
+        const uint64_t pm = __ballot(part);
+        for (uint32_t k = 0; k < kWave; ++k) {     // the step's transfers in lane order
+            if (!((pm >> k) & 1u)) continue;
+            const uint32_t sk = readlane(s, k), dk = readlane(d, k), ak = readlane(am, k), vk = readlane(vslot, k);
+            int64_t bs, bd;
+            uint32_t ap = 0;
+            if (sk == dk) {                        // X -> X: reads only
+                bs = bd = bx;
+            } else {
+                int64_t by = readlane64(yv, vk);
+                if (sk == X) {
+                    bs = bx;
+                    bd = by;
+                    ap = bx >= (int64_t)ak;
+                    if (ap) {
+                        bx -= ak;
+                        by += ak;
+                    }
+                } else {
+                    bs = by;
+                    bd = bx;
+                    ap = by >= (int64_t)ak;
+                    if (ap) {
+                        by -= ak;
+                        bx += ak;
+                    }
+                }
+                if (ap) {
+                    yv = writelane64(yv, by, vk);
+                    ywr = writelane(ywr, 1u, vk);
+                    xwr = 1;
+                }
+            }
+            r_bs = writelane64(r_bs, bs, k);
+            r_bd = writelane64(r_bd, bd, k);
+            r_ap = writelane(r_ap, ap, k);
+        }
+        // tickets: the step's transfers in lane order
+        uint32_t base = 0;
+        if (lane == 0 && pm) base = __hip_atomic_fetch_add(&a->hot->ticket.v, (uint32_t)__popcll(pm), __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+        base = readlane(base, 0);
+        if (part && vslot == lane && ywr) st_agent(&lay.vals[y], (uint64_t)yv);
+        if (lane == 0 && xwr) st_agent(&lay.vals[X], (uint64_t)bx);
+        if (part) {
+            res[t] = r_bs;
+            res[n + t] = r_bd;
+            res[2 * (uint64_t)n + t] = r_ap;
+            a->tickets[t] = base + lanes_below(pm);
+        }
+        // which lock-holding lanes' stripes were written
+        sflag[lane] = 0;
+        if (part && r_ap && yst != xst) sflag[lslot] = 1;
+        hw_order();                            // balances stored before any stripe is released
+        if (lane == 0)
+            __hip_atomic_fetch_add(lay.lock(X), xwr ? 1ull - kLockBit : 0ull - kLockBit, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (mine)
+            __hip_atomic_fetch_add(lay.lock(y), sflag[lane] ? 1ull - kLockBit : 0ull - kLockBit, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (part) {
+            const uint32_t gs = div32(s, G), gd = div32(d, G);
+            rs_mark(rs, gs);
+            rs_mark(rs, gd);
+            if (r_ap) {
+                bitmap_set(ws, gs);
+                bitmap_set(ws, gd);
+            }
+            ls.commits++;
+            t = kNoTxn;
+            tries = 0;
+        } else if (live) {
+            ls.retries++;
+            if (++tries >= a->retry_cap) {
+                latch_error(cnt, HETM_ERETRY, t);
+                t = kNoTxn;
+            }
+        }
+    }
+}
+
+// Refill lanes without work from the cold list (the back of `order`);
+// returns false when the whole wave is out of work.  Reached by all 64 lanes.
+__device__ __forceinline__ bool refill_cold(LaneState &ls, const DevArgs *a, uint32_t n, uint32_t n_cold) {
+    const bool need = ls.txn == kNoTxn;
+    if (__ballot(need)) {
+        const uint32_t got = wave_fetch_add(&a->hot->queue_head.v, need);
+        if (need) {
+            ls.txn = got < n_cold ? a->order[n - 1 - got] : kDoneTxn;
+            ls.attempts = 0;
+        }
+    }
+    return __ballot(ls.txn < n) != 0;
+}
+
 __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevArgs *__restrict__ a) {
     __shared__ uint32_t s_addr[kExecWaves][2][kWave];
     __shared__ uint64_t s_val[kExecWaves][2][kWave];
+    __shared__ uint32_t s_flag[kExecWaves][kWave];
     const uint32_t wv = threadIdx.x / kWave;
     const Split<uint64_t> lay = make_layout<Split<uint64_t>>(a);
     gmem<uint8_t> *rs = glob(a->rs);
@@ -624,9 +1088,25 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
     int64_t *res = (int64_t *)a->results;
     WriteBuf<uint64_t, 2> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
     const uint32_t epoch = a->epoch;
-    LaneState ls = first_txn(n);
+    LaneState ls;
 
-    while (refill(ls, a->hot, n)) {
+    // the hot accounts' chains, longest first, one wave each
+    const uint32_t n_hot = ld_agent(&a->hot->n_ro.v) < kTxMaxHot ? ld_agent(&a->hot->n_ro.v) : kTxMaxHot;
+    const uint32_t *start = a->tx_chain + kTxMaxHot, *corder = a->tx_chain + 3 * kTxMaxHot + 1;
+    for (;;) {
+        uint32_t c = 0;
+        if (lane_id() == 0) c = __hip_atomic_fetch_add(&a->hot->queue_upd.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c = readlane(c, 0);
+        if (c >= n_hot) break;
+        const uint32_t h = corder[c];
+        const uint32_t lo = start[h], hi = start[h + 1];
+        run_chain(a, lay, (uint32_t)a->tx_hot[h], a->order + lo, hi - lo, ls, s_flag[wv], epoch);
+        if (doomed(cnt, epoch)) break;
+    }
+
+    // the cold list, one transfer per lane
+    const uint32_t n_cold = ld_agent(&a->hot->n_upd.v);
+    while (refill_cold(ls, a, n, n_cold)) {
         const bool act = lane_turn(ls, n);
         if (doomed(cnt, epoch)) break;
         if (!__ballot(act)) {          // every lane is backing off
@@ -695,17 +1175,170 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_transfer(const DevAr
 // on a hit it reads the value and writes the way's stamp := tid.  PUT also
 // reads the stamps, picks the way holding the key or else the smallest
 // stamp (lowest way on ties) and writes key, value, stamp and set stamp.
-constexpr uint32_t kSetWords = 128, kStampBase = 16, kSetStamp = 24, kValBase = 32;
-
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {   // splitmix64 finalizer
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
 
 // j-th word of the header read list: 8 keys (16 words), set stamp, 8 stamps
 __device__ __forceinline__ uint32_t header_word(uint32_t j) {
     return j < 16 ? j : (j == 16 ? kSetStamp : kStampBase + (j - 17));
+}
+
+// One wave applies the chain of hot set X: list[0 .. m) are the cache
+// operations on it.  Only this chain touches the set (an operation reads and
+// writes its own set only, and every operation on X is in X's chain), so the
+// wave takes no lock: it loads the set once into its registers -- lane L
+// holds words 2L and 2L + 1 -- applies the operations in steps of up to 64,
+// each in lane order with the same steps as the one-lane program, and stores
+// the words it wrote when the chain is done.  Tickets are drawn per step:
+// slot layout, one version-clock value per operation (its written words get
+// that value + 1 as their version, as a commit would); lock table, the
+// ticket counter.
+template <typename Lay>
+__device__ void run_cache_chain(const DevArgs *a, const Lay &lay, uint32_t X, const uint32_t *list, uint32_t m,
+                                LaneState &ls, uint32_t epoch, uint32_t clock_base) {
+    DevCounters *cnt = a->cnt;
+    const Div32 G = a->gdiv;
+    gmem<uint8_t> *rs = glob(a->rs);
+    gmem<uint32_t> *ws = glob(a->ws);
+    uint32_t *res = (uint32_t *)a->results;
+    const uint32_t lane = lane_id();
+    const uint32_t base = X * kSetWords;
+    // the set: value, version and written flag of this lane's two words
+    uint32_t w0 = lay.load(base + 2 * lane), w1 = lay.load(base + 2 * lane + 1);
+    uint32_t v0 = 0, v1 = 0, d0 = 0, d1 = 0;
+    uint32_t next = 0, t = kNoTxn;
+    for (;;) {
+        const bool need = t == kNoTxn;
+        const uint64_t nm = __ballot(need);
+        if (need && next + lanes_below(nm) < m) t = list[next + lanes_below(nm)];
+        next = min(m, next + (uint32_t)__popcll(nm));
+        const bool have = t != kNoTxn;
+        if (!__ballot(have)) break;
+        if (doomed(cnt, epoch)) break;
+        uint64_t key = 0;
+        uint32_t put = 0, tv = 0;
+        if (have) {
+            key = a->key[t];
+            put = a->op[t];
+            tv = a->tid[t];
+        }
+        const uint64_t pm = __ballot(have);
+        // tickets, one per operation in lane order
+        uint32_t first = 0;
+        if (lane == 0)
+            first = __hip_atomic_fetch_add(Lay::kFused ? &a->hot->clock.v : &a->hot->ticket.v, (uint32_t)__popcll(pm),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        first = readlane(first, 0);
+        const uint32_t draw = first + lanes_below(pm);
+        uint32_t r[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        uint32_t way = 0;       // GET: the hit way (8 = miss); PUT: the victim
+        for (uint32_t k = 0; k < kWave; ++k) {
+            if (!((pm >> k) & 1u)) continue;
+            const uint64_t kk = ((uint64_t)readlane((uint32_t)(key >> 32), k) << 32) | readlane((uint32_t)key, k);
+            const uint32_t pk = readlane(put, k), tk = readlane(tv, k);
+            const uint32_t ver = readlane(draw, k) + 1;
+            // lanes 0..7 hold the keys of ways 0..7
+            const uint64_t hm = __ballot(lane < 8 && (((uint64_t)w1 << 32) | w0) == kk);
+            const int hit = hm ? (int)__ffsll((unsigned long long)hm) - 1 : -1;
+            uint32_t st = 0, rv[8] = {0, 0, 0, 0, 0, 0, 0, 0}, wy = 8;
+            if (!pk) {
+                if (hit >= 0) {
+                    st = 0x100u | (uint32_t)hit;
+#pragma unroll
+                    for (uint32_t i = 0; i < 8; ++i) {      // word 32 + 8 hit + i: lane 16 + 4 hit + i/2
+                        const uint32_t L = 16 + 4 * hit + i / 2;
+                        rv[i] = (i & 1) ? readlane(w1, L) : readlane(w0, L);
+                    }
+                    // stamp of the way: word 16 + hit, lane 8 + hit/2
+                    const uint32_t L = 8 + hit / 2;
+                    if (hit & 1) {
+                        w1 = writelane(w1, tk, L), v1 = writelane(v1, ver, L), d1 = writelane(d1, 1u, L);
+                    } else {
+                        w0 = writelane(w0, tk, L), v0 = writelane(v0, ver, L), d0 = writelane(d0, 1u, L);
+                    }
+                    wy = (uint32_t)hit;
+                }
+            } else {
+                uint32_t victim = 0, vmin = readlane(w0, 8);
+#pragma unroll
+                for (uint32_t w = 1; w < 8; ++w) {
+                    const uint32_t sw = (w & 1) ? readlane(w1, 8 + w / 2) : readlane(w0, 8 + w / 2);
+                    if (sw < vmin) {
+                        vmin = sw;
+                        victim = w;
+                    }
+                }
+                if (hit >= 0) victim = (uint32_t)hit;
+                st = 0x200u | (hit >= 0 ? 0x100u : 0u) | victim;
+                uint32_t chk = (uint32_t)mix64(kk);
+#pragma unroll
+                for (uint32_t i = 0; i < 7; ++i) {
+                    rv[i] = (uint32_t)mix64(kk ^ ((uint64_t)tk << 32) ^ i);
+                    chk ^= rv[i];
+                }
+                rv[7] = chk;
+                // key: words 2v, 2v+1 (lane v); values: words 32 + 8v + i (lane 16 + 4v + i/2);
+                // stamp: word 16 + v; set stamp: word 24 (lane 12, low word)
+                w0 = writelane(w0, (uint32_t)kk, victim), v0 = writelane(v0, ver, victim), d0 = writelane(d0, 1u, victim);
+                w1 = writelane(w1, (uint32_t)(kk >> 32), victim), v1 = writelane(v1, ver, victim),
+                d1 = writelane(d1, 1u, victim);
+#pragma unroll
+                for (uint32_t i = 0; i < 8; i += 2) {
+                    const uint32_t L = 16 + 4 * victim + i / 2;
+                    w0 = writelane(w0, rv[i], L), v0 = writelane(v0, ver, L), d0 = writelane(d0, 1u, L);
+                    w1 = writelane(w1, rv[i + 1], L), v1 = writelane(v1, ver, L), d1 = writelane(d1, 1u, L);
+                }
+                const uint32_t L = 8 + victim / 2;
+                if (victim & 1) {
+                    w1 = writelane(w1, tk, L), v1 = writelane(v1, ver, L), d1 = writelane(d1, 1u, L);
+                } else {
+                    w0 = writelane(w0, tk, L), v0 = writelane(v0, ver, L), d0 = writelane(d0, 1u, L);
+                }
+                w0 = writelane(w0, tk, 12), v0 = writelane(v0, ver, 12), d0 = writelane(d0, 1u, 12);
+                wy = victim;
+            }
+            r[0] = writelane(r[0], st, k);
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i) r[1 + i] = writelane(r[1 + i], rv[i], k);
+            way = writelane(way, wy, k);
+        }
+        if (have) {
+            uint32_t *o = res + 9ull * t;
+#pragma unroll
+            for (uint32_t i = 0; i < 9; ++i) o[i] = r[i];
+            const bool upd = put || way < 8;
+            a->tickets[t] = Lay::kFused ? 2u * (draw - clock_base) + 1u : draw;
+            if (Lay::kFused && draw + 1 >= kClockLimit) latch_error(cnt, HETM_ECAPACITY, t);
+            // the bitmaps: what the one-lane program marks for this operation
+            const uint32_t nh = put ? 25u : 17u;
+            for (uint32_t j = 0; j < nh; ++j) rs_mark(rs, div32(base + header_word(j), G));
+            if (!put && way < 8)
+                for (uint32_t i = 0; i < 8; ++i) rs_mark(rs, div32(base + kValBase + 8 * way + i, G));
+            if (upd) {
+                if (put) {
+                    const uint32_t vb = base + kValBase + 8 * way;
+                    uint32_t wl[12] = {base + 2 * way, base + 2 * way + 1, vb, vb + 1, vb + 2, vb + 3, vb + 4, vb + 5,
+                                       vb + 6, vb + 7, base + kStampBase + way, base + kSetStamp};
+                    for (uint32_t j = 0; j < 12; ++j) {
+                        rs_mark(rs, div32(wl[j], G));
+                        bitmap_set(ws, div32(wl[j], G));
+                    }
+                } else {
+                    const uint32_t g = div32(base + kStampBase + way, G);
+                    rs_mark(rs, g);
+                    bitmap_set(ws, g);
+                }
+            }
+            ls.commits++;
+            t = kNoTxn;
+        }
+    }
+    // the words the chain wrote
+    if constexpr (Lay::kFused) {
+        if (d0) st_agent(lay.lock(base + 2 * lane), Slot::make(v0, w0));
+        if (d1) st_agent(lay.lock(base + 2 * lane + 1), Slot::make(v1, w1));
+    } else {
+        if (d0) st_agent(&lay.vals[base + 2 * lane], w0);
+        if (d1) st_agent(&lay.vals[base + 2 * lane + 1], w1);
+    }
 }
 
 template <typename Lay>
@@ -724,9 +1357,25 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
     WriteBuf<uint32_t, kCacheMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
     const uint32_t epoch = a->epoch;
     const uint32_t clock_base = ld_agent(&cnt->clock_base);
-    LaneState ls = first_txn(n);
+    LaneState ls;
 
-    while (refill(ls, a->hot, n)) {
+    // the hot sets' chains, longest first, one wave each
+    const uint32_t n_hot = ld_agent(&a->hot->n_ro.v) < kTxMaxHot ? ld_agent(&a->hot->n_ro.v) : kTxMaxHot;
+    const uint32_t *start = a->tx_chain + kTxMaxHot, *corder = a->tx_chain + 3 * kTxMaxHot + 1;
+    for (;;) {
+        uint32_t c = 0;
+        if (lane_id() == 0) c = __hip_atomic_fetch_add(&a->hot->queue_upd.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c = readlane(c, 0);
+        if (c >= n_hot) break;
+        const uint32_t h = corder[c];
+        const uint32_t lo = start[h], hi = start[h + 1];
+        run_cache_chain(a, lay, (uint32_t)a->tx_hot[h], a->order + lo, hi - lo, ls, epoch, clock_base);
+        if (doomed(cnt, epoch)) break;
+    }
+
+    // the cold list, one operation per lane
+    const uint32_t n_cold = ld_agent(&a->hot->n_upd.v);
+    while (refill_cold(ls, a, n, n_cold)) {
         const bool act = lane_turn(ls, n);
         if (doomed(cnt, epoch)) break;
         if (!__ballot(act)) {          // every lane is backing off
@@ -745,7 +1394,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
                 latch_error(cnt, HETM_EINVAL, ls.txn);
                 ok = false;
             }
-            base = (uint32_t)(((mix64(key) & (nsets - 1) & ~1ull) | (key & 1ull)) * kSetWords);
+            base = cache_set(key, nsets) * kSetWords;
             nh = put ? 25u : 17u;
         }
         uint32_t hdr[25], gv[8];
@@ -991,6 +1640,23 @@ void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32
         const uint64_t tiles = (batch_capacity + kPartTile - 1) / kPartTile;
         hipLaunchKernelGGL(k_partition, dim3((uint32_t)(tiles < kPartMaxBlocks ? tiles : kPartMaxBlocks)),
                            dim3(kPartBlock), 0, s, a);
+    } else {
+        // hot objects from a sample, then their chains and the cold list
+        const uint64_t tiles = (batch_capacity + kTxTile - 1) / kTxTile;
+        const uint32_t tgrid = (uint32_t)(tiles < 512 ? tiles : 512);
+        if (program == HETM_PROG_TRANSFER) {
+            hipLaunchKernelGGL(k_tx_sample<HETM_PROG_TRANSFER>, dim3(256), dim3(kTxThreads), 0, s, a);
+            hipLaunchKernelGGL(k_tx_pick, dim3(kTxTabSlots / kTxThreads), dim3(kTxThreads), 0, s, a);
+            hipLaunchKernelGGL(k_tx_classify<HETM_PROG_TRANSFER>, dim3(tgrid), dim3(kTxThreads), 0, s, a);
+            hipLaunchKernelGGL(k_tx_plan, dim3(1), dim3(1024), 0, s, a);
+            hipLaunchKernelGGL(k_tx_scatter<HETM_PROG_TRANSFER>, dim3(tgrid), dim3(kTxThreads), 0, s, a);
+        } else {
+            hipLaunchKernelGGL(k_tx_sample<HETM_PROG_CACHE>, dim3(256), dim3(kTxThreads), 0, s, a);
+            hipLaunchKernelGGL(k_tx_pick, dim3(kTxTabSlots / kTxThreads), dim3(kTxThreads), 0, s, a);
+            hipLaunchKernelGGL(k_tx_classify<HETM_PROG_CACHE>, dim3(tgrid), dim3(kTxThreads), 0, s, a);
+            hipLaunchKernelGGL(k_tx_plan, dim3(1), dim3(1024), 0, s, a);
+            hipLaunchKernelGGL(k_tx_scatter<HETM_PROG_CACHE>, dim3(tgrid), dim3(kTxThreads), 0, s, a);
+        }
     }
     if (exec_started) (void)hipEventRecord(exec_started, s);
     if (program == HETM_PROG_OPLIST) {

@@ -32,7 +32,9 @@ struct hetm_ctx {
     uint32_t *log_hist = nullptr, *log_bstart = nullptr, *log_bwin = nullptr, *log_totals = nullptr;
     void *log_sorted = nullptr, *log_win = nullptr;
     uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;
-    uint32_t *order = nullptr;    // batch_capacity transaction ids (the OPLIST kind split)
+    uint32_t *order = nullptr;    // batch_capacity transaction ids (OPLIST kind split, TRANSFER chains)
+    uint64_t *tx_tab = nullptr, *tx_hot = nullptr;   // TRANSFER: sample counts, hot accounts
+    uint32_t *tx_chain = nullptr;                    // TRANSFER: chain counts, starts, cursors, order
     void *log_staging = nullptr;
     DevCounters *cnt = nullptr;
     HotCounters *hot = nullptr;

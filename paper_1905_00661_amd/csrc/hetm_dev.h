@@ -53,9 +53,11 @@ struct HotCounters {
     HotCounter queue_head;        // next transaction of the current batch (after the static first pass);
                                   // OPLIST: next entry of the read-only list
     HotCounter clock;             // version clock of the slot layout; persists across rounds
-    HotCounter queue_upd;         // OPLIST: next entry of the update list
-    HotCounter n_ro;              // OPLIST: length of the read-only list (the partition's cursor)
-    HotCounter n_upd;             // OPLIST: length of the update list (the partition's cursor)
+    HotCounter queue_upd;         // OPLIST: next entry of the update list; TRANSFER: next hot-account chain
+    HotCounter n_ro;              // OPLIST: length of the read-only list (the partition's cursor);
+                                  // TRANSFER: hot accounts found by the sample
+    HotCounter n_upd;             // OPLIST: length of the update list (the partition's cursor);
+                                  // TRANSFER: length of the cold list
 };
 
 // Slot layout: versions are clock values, 31 bits wide.  The host resets
@@ -107,7 +109,12 @@ struct DevArgs {
     uint32_t *blocksums;    // compaction: per-block dirty counts, then offsets
     uint32_t *blockruns;
     uint32_t *ids_scratch;  // ceil(N/G) dirty granule ids
-    uint32_t *order;        // OPLIST batch split by kind: read-only ids from the front, update ids from the back
+    uint32_t *order;        // OPLIST batch split by kind: read-only ids from the front, update ids from the back;
+                            // TRANSFER: the hot accounts' chains from the front, the cold list from the back
+    uint64_t *tx_tab;       // TRANSFER: account counts of the batch sample (kTxTabSlots, cleared after use)
+    uint64_t *tx_hot;       // TRANSFER: hot accounts, (sample count << 32) | account, one chain each
+    uint32_t *tx_chain;     // TRANSFER: per chain counts, first positions (+ total), cursors, and the chain
+                            // order (longest first), kTxMaxHot entries each
     DevCounters *cnt;
     HotCounters *hot;
     Div32 gdiv;             // division by G
@@ -316,6 +323,10 @@ void launch_version_reset(uint64_t *slots, uint64_t n, HotCounters *hot, DevCoun
 void launch_from_slots(const uint64_t *slots, uint32_t *dst, uint64_t n, hipStream_t s);
 
 constexpr uint32_t kScanWordsPerBlock = 2048;   // bitmap words per compaction block
+constexpr uint32_t kTxMaxHot = 4096;            // TRANSFER: most hot-account chains per batch
+constexpr uint32_t kTxTabBits = 18;
+constexpr uint32_t kTxTabSlots = 1u << kTxTabBits;   // TRANSFER: sample count table
+constexpr uint32_t kTxChainWords = 4 * kTxMaxHot + 1;
 constexpr uint32_t kScanThreads = 256;
 
 }  // namespace hetm
