@@ -334,6 +334,10 @@ typedef struct {
                                   DMA'd granules into the host replica        */
     double   us_merge_wait;    /* time calls spent waiting for such merges    */
     uint64_t version_resets;   /* slot layout: version-clock resets so far    */
+    uint64_t rollbacks_device; /* conflicting or discarded rounds rolled back
+                                  on the device from the undo log            */
+    uint64_t rollbacks_host;   /* ... restored from the host replica instead
+                                  (no undo log, or it ran out of room)       */
 } hetm_stats;
 int hetm_stats_get(hetm_ctx *ctx, hetm_stats *out);
 

@@ -177,6 +177,7 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
     c->args.ids_out = ids_out;
     int rc = push_args(c);
     if (rc) return rc;
+    launch_undo(c->dargs, c->undo_cap, c->stream);
     launch_compact(c->dargs, c->args.n_scan_blocks, c->stream);
     launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, c->stream);
     launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, c->stream);
@@ -193,8 +194,14 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
 // round is under CPU wins: the latch is cleared, the GPU's dirty granules
 // are restored from the host replica, the bitmaps and counters are reset.
 // The round's log chunk was not applied (the apply pass skips on an error).
-int discard_round(hetm_ctx *c, int32_t code, uint32_t where, const void *hdev) {
+int discard_round(hetm_ctx *c, int32_t code, uint32_t where, const void *hdev, bool undo_ok) {
     launch_clear_error(c->cnt, c->stream);
+    // the merge of a conflicting round rolls it back: from the undo log if
+    // it holds the round, else from the host replica
+    if (undo_ok)
+        c->stats.rollbacks_device++;
+    else
+        c->stats.rollbacks_host++;
     const uint32_t policy = c->args.policy;
     c->args.policy = HETM_POLICY_CPU_WINS;   // the copy restores the device side
     int rc = enqueue_merge(c, 1u, hdev, nullptr);
@@ -224,6 +231,12 @@ void account_round(hetm_ctx *c, const DevCounters &s, uint64_t n_txns, hetm_roun
     else
         c->stats.txns_committed += s.committed;
     c->gpu_losses = gpu_lost ? c->gpu_losses + 1 : 0;
+    if (gpu_lost) {
+        if (c->undo_cap && !s.undo_over)
+            c->stats.rollbacks_device++;
+        else
+            c->stats.rollbacks_host++;
+    }
     c->stats.local_retries += s.retries;
     c->stats.dirty_granules += s.n_dirty;
     c->stats.watermark = s.floor_ts;
@@ -318,10 +331,12 @@ int build_graph(hetm_ctx *c, uint32_t policy) {
         if (ce == hipSuccess) ce = hipEventRecord(c->join_ev, br);
         launch_validate(c->dargs, c->cfg.word_bytes, c->log_bins, c->log_tiles, false, c->cnt, s);
         launch_apply(c->dargs, c->cfg.word_bytes, c->log_bins, s);
+        launch_undo(c->dargs, c->undo_cap, s);     // a conflicting round rolls back on the device
         if (ce == hipSuccess) ce = hipStreamWaitEvent(s, c->join_ev, 0);
     } else {
         launch_validate(c->dargs, c->cfg.word_bytes, c->log_bins, c->log_tiles, false, c->cnt, s);
         launch_apply(c->dargs, c->cfg.word_bytes, c->log_bins, s);
+        launch_undo(c->dargs, c->undo_cap, s);
         launch_compact(c->dargs, c->args.n_scan_blocks, s);
         if (c->cfg.async_merge)
             launch_gather(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
@@ -481,10 +496,11 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     HIP_TRY(c, hipStreamSynchronize(s));
     const DevCounters snap = *c->snap_host;
     c->round_merge_seq = 0;
+    const bool undo_ok = c->undo_cap && !snap.undo_over;   // the round's undo log is whole
     if (snap.error) {
-        // the restore reads the host replica: earlier merges land first
-        if (c->cfg.async_merge && (rc = drain_merges(c))) return rc;
-        return discard_round(c, snap.error, snap.err_index, hdev);
+        // a restore from the host replica reads it: earlier merges land first
+        if (c->cfg.async_merge && !undo_ok && (rc = drain_merges(c))) return rc;
+        return discard_round(c, snap.error, snap.err_index, hdev, undo_ok);
     }
     if (c->cfg.async_merge) {
         if (!snap.conflict || c->args.policy == HETM_POLICY_GPU_WINS) {
@@ -502,9 +518,10 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
             c->last_copy = b;
             c->buf = b ^ 1;
             if (res) res->merge_pending = 1;
-        } else {
-            // conflict (CPU wins): restore the dirty granules from the host
-            // replica once the previous round's copy has landed there
+        } else if (!undo_ok) {
+            // conflict (CPU wins) without a whole undo log: restore the dirty
+            // granules from the host replica once the previous round's copy
+            // has landed there (with one, the round graph rolled it back)
             if ((rc = drain_merges(c))) return rc;
             launch_restore(c->stmr, hdev, c->stage_ids[b], c->stage_count[b], c->cfg.n_words, c->cfg.granule_words,
                            c->cfg.word_bytes, c->slot, s);
@@ -621,6 +638,13 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     TRY(dev_alloc(c, &c->blockruns, nblocks * 4));
     TRY(dev_alloc(c, &c->ids, nG * 4));
     TRY(dev_alloc(c, &c->order, k.batch_capacity * 4));
+    // slot layout: the undo log of the fast rollback, one record per word a
+    // round's transactions write first, room for 8 per transaction of a batch
+    if (c->slot) {
+        const uint64_t cap = std::min<uint64_t>({N, 8 * k.batch_capacity, 0xFFFFFFFFull});
+        TRY(dev_alloc(c, &c->undo, cap * 8));
+        c->undo_cap = (uint32_t)cap;
+    }
     // the hot-object chains of the TRANSFER and CACHE programs
     TRY(dev_alloc(c, &c->tx_tab, kTxTabSlots * 8ull));
     TRY(dev_alloc(c, &c->tx_hot, kTxMaxHot * 8ull));
@@ -672,6 +696,8 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
               hipMemsetAsync(c->blocksums, 0, nblocks * 4, s) == hipSuccess &&
               hipMemsetAsync(c->tx_tab, 0, kTxTabSlots * 8ull, s) == hipSuccess &&
               hipMemsetAsync(c->tx_chain, 0, kTxChainWords * 4ull, s) == hipSuccess;
+    static const uint32_t kNoApply = 0xFFFFFFFFu;
+    ok = ok && hipMemcpyAsync(&c->cnt->apply_floor, &kNoApply, 4, hipMemcpyHostToDevice, s) == hipSuccess;
     if (!ok) return alloc_fail(c, HETM_EDEVICE, "clearing the context's state");
     if (c->slot && init_image) {
         // the image goes through the TS array (N u64, cleared afterwards)
@@ -702,6 +728,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     a.log_bins = c->log_bins, a.log_bin_bits = ilog2(c->log_bins), a.log_tiles = c->log_tiles;
     a.order = c->order;
     a.tx_tab = c->tx_tab, a.tx_hot = c->tx_hot, a.tx_chain = c->tx_chain;
+    a.undo = c->undo, a.undo_cap = c->undo_cap;
     a.cnt = c->cnt;
     a.hot = c->hot;
     a.gdiv = make_div32((uint32_t)G);
@@ -854,7 +881,7 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     HIP_TRY(c, hipEventRecord(c->ev[2], s));
     DevCounters k;
     if ((rc = read_counters(c, &k))) return rc;
-    if (k.error) return discard_round(c, k.error, k.err_index, hdev);
+    if (k.error) return discard_round(c, k.error, k.err_index, hdev, c->undo_cap && !k.undo_over);
     if ((rc = enqueue_merge(c, k.conflict, hdev, r->ids_out))) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[3], s));
     HIP_TRY(c, hipStreamSynchronize(s));

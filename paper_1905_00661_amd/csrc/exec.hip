@@ -69,6 +69,11 @@ struct WriteBuf {
     uint32_t lane;
     uint32_t n;
     uint32_t locked;   // entries whose lock word this lane holds
+    // slot layout, undo log: entries whose word had a version from before the
+    // round (at most base_ver) when locked, and their values then
+    uint32_t first = 0;
+    uint32_t base_ver = 0xFFFFFFFFu;
+    uint32_t prev[MAXW];
 
     __device__ void put(uint32_t w, Word v) {
         addr[n][lane] = w;
@@ -83,6 +88,7 @@ struct WriteBuf {
     template <typename Lay>
     __device__ bool lock_all(const Lay &lay) {
         locked = 0;
+        first = 0;
         int64_t last = -1;
         for (;;) {
             uint32_t kmin = n;
@@ -102,6 +108,12 @@ struct WriteBuf {
                 return false;
             }
             locked |= 1u << kmin;
+            if constexpr (Lay::kFused) {
+#pragma unroll
+                for (int k = 0; k < MAXW; ++k)
+                    if ((uint32_t)k == kmin) prev[k] = (uint32_t)cur;
+                if (Slot::version(cur) <= base_ver) first |= 1u << kmin;
+            }
             last = smin;
         }
     }
@@ -530,10 +542,20 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_oplist(const DevArgs
                 latch_error(cnt, HETM_ECAPACITY, ls.txn);
                 ok = false;
             }
+            // the round's first write of a word (its slot older than the
+            // round) goes to the undo log with the value it replaces
+            uint32_t umask = 0, uw[kOplistMaxWrites], uo[kOplistMaxWrites];
+#pragma unroll
+            for (uint32_t k = 0; k < kOplistMaxWrites; ++k) {
+                uw[k] = wb.at(k < nwr ? k : 0);
+                uo[k] = (uint32_t)seen[k];
+                if (ok && upd && ((wb.locked >> k) & 1u) && Slot::version(seen[k]) <= clock_base) umask |= 1u << k;
+            }
             if (ok && upd)
                 wb.commit(lay, wv + 1);
             else if (wb.locked)
                 wb.abort(lay);
+            if (a->undo_cap) undo_record(a, umask, uw, uo);
             ticket = upd ? 2u * (wv - clock_base) + 1u : 2u * (rv - clock_base);
         } else {
             // Split layout: first pass over the read stripes, then the values
@@ -1201,8 +1223,19 @@ __device__ void run_cache_chain(const DevArgs *a, const Lay &lay, uint32_t X, co
     uint32_t *res = (uint32_t *)a->results;
     const uint32_t lane = lane_id();
     const uint32_t base = X * kSetWords;
-    // the set: value, version and written flag of this lane's two words
-    uint32_t w0 = lay.load(base + 2 * lane), w1 = lay.load(base + 2 * lane + 1);
+    // the set: value, version and written flag of this lane's two words,
+    // and their slots as found (the undo log records the round's first writes)
+    uint64_t f0 = 0, f1 = 0;
+    uint32_t w0, w1;
+    if constexpr (Lay::kFused) {
+        f0 = ld_agent(lay.lock(base + 2 * lane));
+        f1 = ld_agent(lay.lock(base + 2 * lane + 1));
+        w0 = (uint32_t)f0;
+        w1 = (uint32_t)f1;
+    } else {
+        w0 = lay.load(base + 2 * lane);
+        w1 = lay.load(base + 2 * lane + 1);
+    }
     uint32_t v0 = 0, v1 = 0, d0 = 0, d1 = 0;
     uint32_t next = 0, t = kNoTxn;
     for (;;) {
@@ -1335,6 +1368,10 @@ __device__ void run_cache_chain(const DevArgs *a, const Lay &lay, uint32_t X, co
     if constexpr (Lay::kFused) {
         if (d0) st_agent(lay.lock(base + 2 * lane), Slot::make(v0, w0));
         if (d1) st_agent(lay.lock(base + 2 * lane + 1), Slot::make(v1, w1));
+        const uint32_t umask = (d0 && Slot::version(f0) <= clock_base ? 1u : 0u) |
+                               (d1 && Slot::version(f1) <= clock_base ? 2u : 0u);
+        const uint32_t uw[2] = {base + 2 * lane, base + 2 * lane + 1}, uo[2] = {(uint32_t)f0, (uint32_t)f1};
+        if (a->undo_cap) undo_record(a, umask, uw, uo);
     } else {
         if (d0) st_agent(&lay.vals[base + 2 * lane], w0);
         if (d1) st_agent(&lay.vals[base + 2 * lane + 1], w1);
@@ -1357,6 +1394,7 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
     WriteBuf<uint32_t, kCacheMaxWrites> wb{s_addr[wv], s_val[wv], lane_id(), 0, 0};
     const uint32_t epoch = a->epoch;
     const uint32_t clock_base = ld_agent(&cnt->clock_base);
+    wb.base_ver = clock_base;
     LaneState ls;
 
     // the hot sets' chains, longest first, one wave each
@@ -1508,10 +1546,16 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
                 latch_error(cnt, HETM_ECAPACITY, ls.txn);
                 ok = false;
             }
+            // the round's first writes of words go to the undo log
+            const uint32_t umask = ok && upd ? wb.first & wb.locked : 0u;
+            uint32_t uw[kCacheMaxWrites];
+#pragma unroll
+            for (uint32_t k = 0; k < kCacheMaxWrites; ++k) uw[k] = wb.at(k < wb.n ? k : 0);
             if (ok && upd)
                 wb.commit(lay, wver + 1);
             else if (wb.locked)
                 wb.abort(lay);
+            if (a->undo_cap) undo_record(a, umask, uw, wb.prev);
             ticket = upd ? 2u * (wver - clock_base) + 1u : 2u * (rv - clock_base);
         } else {
             ticket = wave_fetch_add(&a->hot->ticket.v, ok);

@@ -34,6 +34,8 @@ struct hetm_ctx {
     uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;
     uint32_t *order = nullptr;    // batch_capacity transaction ids (OPLIST kind split, TRANSFER chains)
     uint64_t *tx_tab = nullptr, *tx_hot = nullptr;   // TRANSFER: sample counts, hot accounts
+    uint64_t *undo = nullptr;                        // slot layout: the round's undo log
+    uint32_t undo_cap = 0;
     uint32_t *tx_chain = nullptr;                    // TRANSFER: chain counts, starts, cursors, order
     void *log_staging = nullptr;
     DevCounters *cnt = nullptr;

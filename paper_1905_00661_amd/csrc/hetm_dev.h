@@ -87,6 +87,12 @@ struct DevCounters {
     uint32_t doomed;              // epoch of the last round early validation doomed
     uint32_t log_ticket;          // blocks finished in the log apply pass
     uint32_t win_pending;         // the last applied chunk's winners have not written their ts yet
+    uint32_t n_undo;              // slot layout: undo records of the round (first writes of a word)
+    uint32_t undo_over;           // the undo log ran out of room (a conflict restores from the host)
+    uint32_t apply_floor;         // slot layout: version of the round's first applied log chunk
+                                  // (0xFFFFFFFF before); every word the log wrote carries a version
+                                  // at or above it, every word a transaction wrote one below
+    uint32_t apply_ver;           // slot layout: version of the chunk being applied
     uint32_t pad_;
 };
 
@@ -111,6 +117,9 @@ struct DevArgs {
     uint32_t *ids_scratch;  // ceil(N/G) dirty granule ids
     uint32_t *order;        // OPLIST batch split by kind: read-only ids from the front, update ids from the back;
                             // TRANSFER: the hot accounts' chains from the front, the cold list from the back
+    uint64_t *undo;         // slot layout: (old value << 32) | word of each word's first write in the round
+    uint32_t undo_cap;      // records the undo log holds (0: no undo log, conflicts restore from the host)
+    uint32_t pad3_;
     uint64_t *tx_tab;       // TRANSFER: account counts of the batch sample (kTxTabSlots, cleared after use)
     uint64_t *tx_hot;       // TRANSFER: hot accounts, (sample count << 32) | account, one chain each
     uint32_t *tx_chain;     // TRANSFER: per chain counts, first positions (+ total), cursors, and the chain
@@ -240,6 +249,38 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Undo log (slot layout): a committed writer that finds a word with a version
+// from before the round (at most the round's clock base) writes it first in
+// the round and records its old value; entry k of word[] / old[] is recorded
+// if bit k of mask is set.  One atomic per wave reserves the wave's records.
+// Past the log's room nothing is recorded and the round falls back to
+// restoring from the host replica.  Reached by all 64 lanes.
+template <int K>
+__device__ __forceinline__ void undo_record(const DevArgs *a, uint32_t mask, const uint32_t (&word)[K],
+                                            const uint32_t (&old)[K]) {
+    const uint32_t lane = __lane_id();
+    const uint32_t count = __popc(mask);
+    uint32_t inc = count;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if ((int)lane >= o) inc += t;
+    }
+    const uint32_t total = __shfl(inc, 63);
+    if (!total) return;
+    uint32_t base = 0;
+    if (lane == 63)
+        base = __hip_atomic_fetch_add(&a->cnt->n_undo, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    base = __shfl(base, 63) + inc - count;
+    if (base + count > a->undo_cap) {
+        if (count) __hip_atomic_store(&a->cnt->undo_over, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    uint32_t at = base;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if ((mask >> k) & 1u) a->undo[at++] = ((uint64_t)old[k] << 32) | word[k];
+}
+
 // One atomic add per wavefront: lanes with `want` receive consecutive
 // values in lane order.  Must be reached by all 64 lanes.
 __device__ __forceinline__ uint32_t wave_fetch_add(uint32_t *ctr, bool want) {
@@ -318,6 +359,9 @@ void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_
                    hipStream_t s);
 void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uint32_t *count, uint64_t n_words,
                     uint32_t granule, uint32_t word_bytes, bool slot, hipStream_t s);
+// the device-side rollback of a conflicting round from the undo log; nothing
+// for a context without one
+void launch_undo(const DevArgs *a, uint32_t undo_cap, hipStream_t s);
 void launch_to_slots(const uint32_t *src, uint64_t *slots, uint64_t n, hipStream_t s);
 void launch_version_reset(uint64_t *slots, uint64_t n, HotCounters *hot, DevCounters *cnt, hipStream_t s);
 void launch_from_slots(const uint64_t *slots, uint32_t *dst, uint64_t n, hipStream_t s);

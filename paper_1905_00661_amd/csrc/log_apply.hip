@@ -208,9 +208,19 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *sh, uint32_
 // within the bucket, in place, and stores the bucket's total.
 __global__ __launch_bounds__(kThreads) void k_log_scan(const DevArgs *__restrict__ a) {
     __shared__ uint32_t sh[kThreads / kWave];
-    if (ld_agent(&a->cnt->error)) return;
+    DevCounters *cnt = a->cnt;
+    if (ld_agent(&cnt->error)) return;
     const uint32_t B = a->log_bins, b = blockIdx.x;
     const uint32_t T = (uint32_t)((a->n_log + kLogTile - 1) / kLogTile);
+    if (b == 0 && threadIdx.x == 0 && a->word_shift) {
+        // slot layout: the chunk's writes get a version of their own, above
+        // every version the round's transactions wrote (the undo log tells
+        // the two apart)
+        const uint32_t v = __hip_atomic_fetch_add(&a->hot->clock.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (v >= kClockLimit) latch_error(cnt, HETM_ECAPACITY, 0);
+        st_agent(&cnt->apply_ver, v);
+        if (ld_agent(&cnt->apply_floor) == 0xFFFFFFFFu) st_agent(&cnt->apply_floor, v);
+    }
     uint32_t *hist = a->log_hist;
     uint32_t base = 0;
     for (uint32_t t0 = 0; t0 < T; t0 += kThreads) {       // one column segment per thread and round
@@ -425,9 +435,10 @@ __global__ __launch_bounds__(kThreads) void k_log_apply(const DevArgs *__restric
         if (discard) {
             const Div32 G = a->gdiv;
             for (uint32_t i = threadIdx.x; i < nw; i += kThreads) bitmap_set(a->ws, div32(win[i].word, G));
-        } else {
-            V *stmr = (V *)a->stmr;
-            const uint32_t wsh = a->word_shift;   // slot layout: a word's value sits at u32 index 2w
+        } else if (a->word_shift) {
+            // slot layout: value and the chunk's version in one store
+            uint64_t *slots = (uint64_t *)a->stmr;
+            const uint64_t ver = (uint64_t)(ld_agent(&cnt->apply_ver) & 0x7FFFFFFFu) << 32;
             for (uint32_t i0 = 0; i0 < nw; i0 += kRegs * kThreads) {
                 E e[kRegs];
 #pragma unroll
@@ -437,7 +448,20 @@ __global__ __launch_bounds__(kThreads) void k_log_apply(const DevArgs *__restric
                 }
 #pragma unroll
                 for (uint32_t r = 0; r < kRegs; ++r)
-                    if (i0 + r * kThreads + threadIdx.x < nw) stmr[(uint64_t)e[r].word << wsh] = (V)e[r].value;
+                    if (i0 + r * kThreads + threadIdx.x < nw) slots[e[r].word] = ver | (uint32_t)e[r].value;
+            }
+        } else {
+            V *stmr = (V *)a->stmr;
+            for (uint32_t i0 = 0; i0 < nw; i0 += kRegs * kThreads) {
+                E e[kRegs];
+#pragma unroll
+                for (uint32_t r = 0; r < kRegs; ++r) {
+                    const uint32_t i = i0 + r * kThreads + threadIdx.x;
+                    e[r] = win[i < nw ? i : 0];
+                }
+#pragma unroll
+                for (uint32_t r = 0; r < kRegs; ++r)
+                    if (i0 + r * kThreads + threadIdx.x < nw) stmr[e[r].word] = (V)e[r].value;
             }
         }
     }

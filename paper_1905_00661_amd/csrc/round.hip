@@ -187,6 +187,7 @@ __global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uin
     if (ld_agent(&cnt->error)) return;
     const uint32_t conflict = a->outcome == HETM_OUTCOME_DEVICE ? ld_agent(&cnt->conflict) : a->outcome;
     const bool restore = conflict && a->policy != HETM_POLICY_GPU_WINS;   // else GPU -> host
+    if (restore && a->undo_cap && !ld_agent(&cnt->undo_over)) return;   // k_undo rolled the round back
     const uint64_t D = ld_agent(&cnt->n_dirty);
     const uint32_t *ids = a->ids_scratch;
     U *dev = (U *)a->stmr;
@@ -279,6 +280,31 @@ __global__ __launch_bounds__(256) void k_restore(U *stmr, const U *host, const u
     }
 }
 
+// Fast rollback (slot layout): a conflicting round (CPU wins; a discarded
+// round merges as one) puts back the old value of every word the
+// round's transactions wrote, from the undo log, except words the host log
+// wrote afterwards (their version is at or above the round's first apply
+// version), whose host value stands.  The GPU replica then equals the host
+// replica (the pre-round state plus the host's writes) with no copy over the
+// host link.  Runs only while the log holds every first write of the round.
+__global__ __launch_bounds__(256) void k_undo(const DevArgs *__restrict__ a) {
+    DevCounters *cnt = a->cnt;
+    if (!a->undo_cap || ld_agent(&cnt->undo_over) || ld_agent(&cnt->error)) return;
+    const uint32_t conflict = a->outcome == HETM_OUTCOME_DEVICE ? ld_agent(&cnt->conflict) : a->outcome;
+    if (!conflict || a->policy == HETM_POLICY_GPU_WINS) return;
+    const uint32_t n = min(ld_agent(&cnt->n_undo), a->undo_cap);
+    const uint32_t floor = ld_agent(&cnt->apply_floor);
+    uint64_t *slots = (uint64_t *)a->stmr;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint64_t rec = a->undo[i];
+        const uint32_t w = (uint32_t)rec;
+        const uint64_t cur = ld_agent(&slots[w]);
+        const uint32_t ver = (uint32_t)(cur >> 32) & 0x7FFFFFFFu;
+        if (ver >= floor) continue;
+        st_agent(&slots[w], ((uint64_t)ver << 32) | (rec >> 32));
+    }
+}
+
 // Slot layout: every version back to 0 and the clock with them (between
 // rounds, when the clock has run far; no lock is held then).
 __global__ __launch_bounds__(256) void k_version_reset(uint64_t *slots, uint64_t n, HotCounters *hot,
@@ -325,6 +351,10 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         c.chunk_conflict = 0;
         c.log_ticket = 0;
         c.win_pending = 0;
+        c.n_undo = ld_agent(&cnt->n_undo);
+        c.undo_over = ld_agent(&cnt->undo_over);
+        c.apply_floor = ld_agent(&cnt->apply_floor);
+        c.apply_ver = 0;
         c.pad_ = 0;
         c.doomed = ld_agent(&cnt->doomed);
         if (!err) {
@@ -340,6 +370,9 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
             st_agent(&cnt->n_dirty, 0u);
             st_agent(&cnt->n_runs, 0u);
             st_agent(&cnt->win_pending, 0u);    // the next round's first chunk needs no timestamps
+            st_agent(&cnt->n_undo, 0u);
+            st_agent(&cnt->undo_over, 0u);
+            st_agent(&cnt->apply_floor, 0xFFFFFFFFu);
         }
         *snap = c;
     }
@@ -457,6 +490,11 @@ void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uin
     else
         hipLaunchKernelGGL((k_restore<uint64_t, 0>), dim3(grid), dim3(256), 0, s, (uint64_t *)stmr,
                            (const uint64_t *)host, ids, count, granule, n_words);
+}
+
+void launch_undo(const DevArgs *a, uint32_t undo_cap, hipStream_t s) {
+    if (!undo_cap) return;
+    hipLaunchKernelGGL(k_undo, dim3(stream_grid(undo_cap, 256, 2048)), dim3(256), 0, s, a);
 }
 
 void launch_version_reset(uint64_t *slots, uint64_t n, HotCounters *hot, DevCounters *cnt, hipStream_t s) {

@@ -97,7 +97,7 @@ class hetm_stats(ctypes.Structure):
                 ("txns_aborted", U64), ("local_retries", U64), ("log_entries", U64),
                 ("dirty_granules", U64), ("watermark", U64), ("device_bytes", U64),
                 ("us_host_scatter", ctypes.c_double), ("us_merge_wait", ctypes.c_double),
-                ("version_resets", U64)]
+                ("version_resets", U64), ("rollbacks_device", U64), ("rollbacks_host", U64)]
 
 
 class HetmError(RuntimeError):
