@@ -375,6 +375,24 @@ int hetm_set_version_clock(hetm_ctx *ctx, uint32_t value);
 int hetm_read_state(hetm_ctx *ctx, uint32_t what, void *dst, uint64_t bytes);
 uint64_t hetm_state_bytes(hetm_ctx *ctx, uint32_t what);
 
+/* The replica's values without allocating: for callers that cannot allocate
+ * device memory (serving loops, harnesses that forbid hipMalloc).  Copies the
+ * values of words [first_word, first_word + n_words) of the GPU replica to
+ * dst (host or device, n_words * W bytes), as hetm_read_state(STMR) returns
+ * them; synchronizes and waits for pending merges like it.  In the slot
+ * layout (u32 words, S = 1) the values pass through an array of 2^24 u32
+ * (64 MiB) of device memory that the library holds once per GPU, from the
+ * first context created on it until the process ends (devices 0..63; a
+ * context on a later device gets EDEVICE here); other layouts copy straight
+ * from the replica.  Allocates nothing, on the device or the host.
+ * n_words <= 2^24 (else ECAPACITY, nothing copied; read larger ranges in
+ * pieces); the range must lie inside the replica (else EINVAL).  The array
+ * is shared by every context on one GPU: calls on one GPU take turns on it
+ * (a lock per device), and it keeps the last call's values, which the next
+ * call overwrites before it copies anything out.  Errors: EINVAL, ECAPACITY,
+ * EDEVICE, latched merge errors. */
+int hetm_read_words_noalloc(hetm_ctx *ctx, uint64_t first_word, uint64_t n_words, void *dst);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A request loop over one context (the GPU-controller thread of §IV-A):

@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "hetm.h"
@@ -21,6 +22,14 @@
 #include "hetm_dev.h"
 
 using namespace hetm;
+
+// The device memory of hetm_read_words_noalloc: one copy per GPU, part of
+// this file's code object, loaded with it and held until the process ends.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it is only a stand-in for the symbol): hetm_alloc_stmr looks up each
+// device's copy once with hipGetSymbolAddress, with that device current.
+constexpr uint64_t kNoAllocWords = 1ull << 24;   // 64 MiB of u32 values
+static __device__ __align__(256) uint32_t scratch[kNoAllocWords];
 
 
 namespace {
@@ -52,6 +61,27 @@ int dev_alloc(hetm_ctx *c, T **p, uint64_t bytes) {
 }
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;                           // guards g_scratch_ptr
+void *g_scratch_ptr[kScratchDevices] = {};         // each device's copy of `scratch`
+std::mutex g_scratch_use[kScratchDevices];         // calls on one GPU take turns on its copy
+
+// With `device` current: its copy of `scratch`, looked up on the first call
+// for that device.  A device beyond the table gets none (nullptr, HETM_OK):
+// only hetm_read_words_noalloc needs it, and it reports the lack.
+int scratch_for_device(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kScratchDevices) return HETM_OK;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HETM_EDEVICE;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return HETM_OK;
+}
 
 // Write one byte of every 4 KiB page of a fresh pinned buffer, so that the
 // host's first accesses to it (the merge worker's scatter) do not fault page
@@ -607,6 +637,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
         delete c;
         return alloc_fail(nullptr, HETM_EDEVICE, "hipSetDevice");
     }
+    TRY(scratch_for_device(k.device, &c->scratch));
     c->stream = (hipStream_t)k.stream;
     const uint64_t N = k.n_words, G = k.granule_words;
     const uint64_t nG = (N + G - 1) / G;
@@ -1023,6 +1054,37 @@ int hetm_read_state(hetm_ctx *c, uint32_t what, void *dst, uint64_t bytes) {
         return HETM_OK;
     }
     HIP_TRY(c, hipMemcpy(dst, src, bytes, hipMemcpyDefault));
+    return HETM_OK;
+}
+
+int hetm_read_words_noalloc(hetm_ctx *c, uint64_t first_word, uint64_t n_words, void *dst) {
+    if (!c || (!dst && n_words)) return HETM_EINVAL;
+    if (n_words > kNoAllocWords)
+        return fail(c, HETM_ECAPACITY, "hetm_read_words_noalloc: %llu words exceed the limit of %llu per call",
+                    (unsigned long long)n_words, (unsigned long long)kNoAllocWords);
+    if (first_word > c->cfg.n_words || n_words > c->cfg.n_words - first_word)
+        return fail(c, HETM_EINVAL, "hetm_read_words_noalloc: words [%llu, +%llu) outside the replica",
+                    (unsigned long long)first_word, (unsigned long long)n_words);
+    if (n_words == 0) return HETM_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int dr = drain_merges(c);
+    if (dr) return dr;
+    const uint64_t bytes = n_words * c->cfg.word_bytes;
+    if (!c->slot) {
+        // a value array: the words are already what the caller reads
+        HIP_TRY(c, hipMemcpyAsync(dst, (const uint8_t *)c->stmr + first_word * c->cfg.word_bytes, bytes,
+                                  hipMemcpyDefault, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return HETM_OK;
+    }
+    if (!c->scratch) return fail(c, HETM_EDEVICE, "hetm_read_words_noalloc: no scratch array on device %d", c->device);
+    // the slots' values through this device's array; every word copied out
+    // is written first, so what the last call left there does not matter
+    std::lock_guard<std::mutex> g(g_scratch_use[c->device]);
+    launch_from_slots((const uint64_t *)c->stmr + first_word, (uint32_t *)c->scratch, n_words, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(dst, c->scratch, bytes, hipMemcpyDefault, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return HETM_OK;
 }
 

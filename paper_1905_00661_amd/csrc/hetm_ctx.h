@@ -43,6 +43,7 @@ struct hetm_ctx {
     DevCounters *snap_dev = nullptr;
     DevArgs *dargs = nullptr;
     uint64_t device_bytes = 0;
+    void *scratch = nullptr;           // this device's copy of the no-allocation read array
 
     // pinned host mirrors
     DevArgs *hargs = nullptr;        // argument block uploaded by the graph

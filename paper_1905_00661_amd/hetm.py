@@ -33,7 +33,8 @@ EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_a
            "hetm_copyback_dirty", "hetm_round", "hetm_strerror", "hetm_last_error", "hetm_sync",
            "hetm_stats_get", "hetm_read_state", "hetm_state_bytes", "hetm_host_tm_create",
            "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts",
-           "hetm_serve", "hetm_set_exec_workgroups", "hetm_early_validate", "hetm_set_version_clock"]
+           "hetm_serve", "hetm_set_exec_workgroups", "hetm_early_validate", "hetm_set_version_clock",
+           "hetm_read_words_noalloc"]
 
 P = ctypes.c_void_p
 U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -130,6 +131,7 @@ def lib() -> ctypes.CDLL:
             "hetm_stats_get": ([P, ctypes.POINTER(hetm_stats)], ctypes.c_int),
             "hetm_read_state": ([P, U32, P, U64], ctypes.c_int),
             "hetm_state_bytes": ([P, U32], U64),
+            "hetm_read_words_noalloc": ([P, U64, U64, P], ctypes.c_int),
             "hetm_host_tm_create": ([P, U64, U32, U32, U64, ctypes.POINTER(P)], ctypes.c_int),
             "hetm_host_tm_free": ([P], ctypes.c_int),
             "hetm_host_tm_clock": ([P], U64),
@@ -211,6 +213,10 @@ def hetm_stats_get(ctx: int) -> hetm_stats:
 
 def hetm_read_state(ctx: int, what: int, dst: int, nbytes: int) -> None:
     _check(lib().hetm_read_state(ctx, what, dst, nbytes), "hetm_read_state", ctx)
+
+
+def hetm_read_words_noalloc(ctx: int, first_word: int, n_words: int, dst: int) -> None:
+    _check(lib().hetm_read_words_noalloc(ctx, first_word, n_words, dst), "hetm_read_words_noalloc", ctx)
 
 
 def hetm_state_bytes(ctx: int, what: int) -> int:
