@@ -85,8 +85,10 @@ VALIDATE_APPLY_BYTES_PER_ENTRY = 40.0
 VALIDATE_APPLY_STREAM_BYTES_PER_ENTRY = 16 + 1 + 32 + 32 + 16 + 4
 
 
-KERNEL_SOURCES = {"k_exec_oplist": ("exec.hip", "hetm_dev.h")}
-TRAFFIC_FILES = {"k_exec_oplist": "exec_oplist_large_traffic.md"}
+KERNEL_SOURCES = {"k_exec_oplist": ("exec.hip", "hetm_dev.h"),
+                  "validate_apply": ("log_apply.hip", "hetm_dev.h")}
+TRAFFIC_FILES = {"k_exec_oplist": "exec_oplist_large_traffic.md",
+                 "validate_apply": "round_kernels_large_traffic.md"}
 
 
 def source_hash(kernel: str) -> str:
@@ -634,6 +636,10 @@ def main():
                              "alg_bytes_per_entry": VALIDATE_APPLY_BYTES_PER_ENTRY,
                              "streamed_GBps": vs, "streamed_frac_of_hbm_peak": vs / HBM_PEAK_GBPS,
                              "streamed_bytes_per_entry": VALIDATE_APPLY_STREAM_BYTES_PER_ENTRY}
+    vt = load_traffic("validate_apply") if n_log == 1 << 20 else None
+    out["validate_apply"]["counter_bytes_per_chunk"] = vt
+    out["validate_apply"]["counter_frac_of_hbm_peak"] = (
+        vt / (plain["us_validate"] * 1e-6) / 1e9 / HBM_PEAK_GBPS if vt else None)
     # roofline of the dominant kernel: the transaction kernel, timed alone by
     # events on its stream just before and after it in the plain form
     alg = exec_alg_bytes(ri.batch)

@@ -100,7 +100,7 @@ typedef struct {
     uint32_t retry_cap;          /* local attempts per transaction; 0 = 1<<24    */
     uint32_t async_merge;        /* GRAPH mode only: 1 = double-buffered merge --
                                     the round gathers its dirty granules into one
-                                    of two HBM staging buffers; a DMA on a copy
+                                    of two HBM staging buffers; a copy on a copy
                                     stream moves them to pinned host staging and
                                     a library thread scatters them into the host
                                     replica while the next round executes (GPU
@@ -331,7 +331,7 @@ typedef struct {
     uint64_t log_entries, dirty_granules, watermark;
     uint64_t device_bytes;     /* HBM the context allocated */
     double   us_host_scatter;  /* double-buffered merge: host time scattering
-                                  DMA'd granules into the host replica        */
+                                  copied granules into the host replica       */
     double   us_merge_wait;    /* time calls spent waiting for such merges    */
     uint64_t version_resets;   /* slot layout: version-clock resets so far    */
     uint64_t rollbacks_device; /* conflicting or discarded rounds rolled back

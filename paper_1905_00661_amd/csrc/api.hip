@@ -419,13 +419,13 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
 }
 
 // Success path of the double-buffered merge for staging buffer b holding D
-// packed granules bound for host replica `host`: DMA on the copy stream
-// after the round's graph (c->ev[3], not yet re-recorded), then a job for
+// packed granules bound for host replica `host`: a copy on the copy stream
+// into pinned host staging after the round's graph (c->ev[3], not yet re-recorded), then a job for
 // the merge worker.
 int stage_to_host(hetm_ctx *c, int b, uint64_t D, void *host) {
     const uint64_t gbytes = (uint64_t)c->cfg.granule_words * c->cfg.word_bytes;
     // the job that last used this host staging buffer has been scattered out
-    // of it (the other buffer's job may still be scattering: this DMA
+    // of it (the other buffer's job may still be scattering: this copy
     // overlaps it)
     if (c->merge_seq[b] && hetm::merge_wait(c->merger, c->merge_seq[b]) != HETM_OK)
         return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
@@ -534,7 +534,7 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     }
     if (c->cfg.async_merge) {
         if (!snap.conflict || c->args.policy == HETM_POLICY_GPU_WINS) {
-            // the GPU's granules go to the host replica: a DMA of the staged granules to pinned host staging on
+            // the GPU's granules go to the host replica: a copy of the staged granules to pinned host staging on
             // the copy stream (issued by the next round_begin, or by whatever waits for merges first), then
             // the merge worker scatters them into the host replica.  The merge of the round before the last
             // (the last job on this round's buffer) lands before this round returns.

@@ -1,4 +1,4 @@
-// merge_host.cpp -- the host worker that scatters DMA-staged dirty granules
+// merge_host.cpp -- the host worker that scatters staged dirty granules
 // into the host replica (double-buffered merge).
 #include "merge_host.h"
 

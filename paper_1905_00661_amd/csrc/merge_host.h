@@ -1,11 +1,13 @@
 // merge_host.h -- host half of the double-buffered merge (§IV-C.3, §IV-D).
 //
-// A kernel storing into pinned host memory holds back kernels on every other
-// queue until its stores drain over the host link, so the staged granules of
-// a committed round cross the link by DMA instead (one copy of the packed
-// staging buffer into pinned host staging, on the copy stream), and a host
-// worker thread scatters them into the host replica once the copy's event
-// completes.  Jobs complete in submission order; each gets a sequence number.
+// The staged granules of a committed round cross the host link as one
+// runtime copy of the packed staging buffer into pinned host staging, on the
+// copy stream, and a host worker thread scatters them into the host replica
+// once the copy's event completes.  (The runtime runs that copy as a kernel
+// of its own beside the next round's transaction kernel; copy kernels of
+// this library on 8 to 256 workgroups, with plain or nontemporal stores,
+// slowed the transaction kernel more.)  Jobs complete in submission order;
+// each gets a sequence number.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -279,7 +279,7 @@ struct Serve {
 
     // Queues the copies of a round's results and tickets to pinned host
     // memory right behind its graph, so they run before the round's merge
-    // DMA is queued (the merge would hold them back on the copy engine).
+    // copy is queued (the merge copy would hold them back).
     int fetch_after_round(RoundSet &r) {
         const uint64_t n = r.reqs.size();
         if (!n) return HETM_OK;

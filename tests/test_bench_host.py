@@ -36,17 +36,29 @@ def test_exec_alg_bytes_large_mix():
     assert abs(bench.exec_alg_bytes(batch) / 1000 - 287.0) < 1e-9
 
 
-def test_traffic_summary_matches_sources():
-    """The committed counter summary is read only while the kernel's sources
+import pytest  # noqa: E402
+
+
+@pytest.mark.parametrize("kernel", sorted(bench.TRAFFIC_FILES))
+def test_traffic_summary_matches_sources(kernel):
+    """Each committed counter summary is read only while its kernels' sources
     hash to the value it records, and then gives a positive byte count."""
-    text = open(os.path.join(ROOT, "profiles", bench.TRAFFIC_FILES["k_exec_oplist"])).read()
+    text = open(os.path.join(ROOT, "profiles", bench.TRAFFIC_FILES[kernel])).read()
     recorded = [line.split(":", 1)[1].strip() for line in text.splitlines() if line.startswith("source_hash:")]
     assert len(recorded) == 1
-    got = bench.load_traffic("k_exec_oplist")
-    if recorded[0] == bench.source_hash("k_exec_oplist"):
+    got = bench.load_traffic(kernel)
+    if recorded[0] == bench.source_hash(kernel):
         assert got is not None and got > 0
     else:
         assert got is None
+
+
+def test_stale_summary_is_ignored(tmp_path, monkeypatch):
+    """A summary whose recorded hash differs from the sources' gives None."""
+    (tmp_path / "x.md").write_text("source_hash: 0000000000000000\nbytes_per_launch: 123\n")
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    monkeypatch.setitem(bench.TRAFFIC_FILES, "k_exec_oplist", "x.md")
+    assert bench.load_traffic("k_exec_oplist") is None
 
 
 def test_more_than_one_gpu_is_refused():
