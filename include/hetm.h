@@ -316,6 +316,43 @@ typedef struct {
  * corrected log carrying them is applied in a later round. */
 int hetm_round(hetm_ctx *ctx, const hetm_round_args *args, hetm_round_result *res);
 
+/* A streamed round (GRAPH mode): the round of hetm_round in three calls, so
+ * that the host can keep executing while its log is shipped in chunks (the
+ * CPU blocks only for the last chunks, §IV-D) and each chunk is validated
+ * early against the GPU's read set while the GPU still executes (early
+ * validation, §IV-D, which cuts the GPU work wasted on a round the CPU is
+ * going to win).
+ *
+ * hetm_round_begin checks the arguments as hetm_round does, launches the
+ * execution part of the round (one captured graph) and returns without
+ * waiting.  args->log / n_log, if given, is the first chunk, pushed as by
+ * hetm_round_push.  Errors: EINVAL, ECAPACITY, ESTATE (PLAIN context, or a
+ * round already open). */
+int hetm_round_begin(hetm_ctx *ctx, const hetm_round_args *args);
+
+/* Appends n log entries (host or device memory, read until hetm_round_end
+ * returns) to the open streamed round's log: they are copied into the
+ * context's log buffer on a stream of their own, beside the running
+ * transactions, and, under CPU wins, checked at once against the read set as
+ * it stands -- without applying anything.  A hit dooms the round: the CPU
+ * wins, so the transaction kernel stops at its next iteration and the
+ * round's outcome is a conflict.  Early validation may miss a conflict (the
+ * read set is still growing) but never invents one: hetm_round_end
+ * validates every pushed entry again.  The chunks of a round hold at most
+ * log_capacity entries together (else ECAPACITY and nothing is appended).
+ * doomed_out (host, nullable): waits for this chunk's check and stores 1 if
+ * the open round is doomed.  Errors: EINVAL, ECAPACITY, ESTATE (no streamed
+ * round open). */
+int hetm_round_push(hetm_ctx *ctx, const void *log, uint64_t n, uint32_t *doomed_out);
+
+/* Ends the open streamed round: validates and applies every pushed entry as
+ * one chunk (in push order: flags_bits of hetm_round_begin, if given, gets
+ * bit k for the k-th pushed entry, ceil(entries pushed / 32) words), then
+ * merges and finishes exactly as hetm_round, synchronizes and fills *res
+ * (res->doomed = 1 if an early validation stopped the round).  Errors: as
+ * hetm_round; ESTATE without an open streamed round. */
+int hetm_round_end(hetm_ctx *ctx, hetm_round_result *res);
+
 /* ------------------------------------------------------------- auxiliary */
 
 const char *hetm_strerror(int code);

@@ -313,12 +313,16 @@ int drain_merges(hetm_ctx *c) {
     return HETM_OK;
 }
 
+void drop_graph(hetm_ctx::RoundGraph &g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = hetm_ctx::RoundGraph{};
+}
+
 void drop_graphs(hetm_ctx *c) {
-    for (auto &g : c->graphs) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        if (g.graph) (void)hipGraphDestroy(g.graph);
-        g = hetm_ctx::RoundGraph{};
-    }
+    for (auto &g : c->graphs) drop_graph(g);
+    for (auto &p : c->sgraphs)
+        for (auto &g : p) drop_graph(g);
 }
 
 // Captures the round for one merge policy on a private non-blocking stream
@@ -332,8 +336,11 @@ void drop_graphs(hetm_ctx *c) {
 // and the staged ids it restores from do not depend on the log.  Under GPU
 // wins a conflicted round's apply adds the log's granules to the write set,
 // so compaction has to follow it.
-int build_graph(hetm_ctx *c, uint32_t policy) {
-    hetm_ctx::RoundGraph &rg = c->graphs[policy];
+// What a captured graph holds: the whole round, or the execution part or
+// the tail (validation and apply, merge, finish) of a streamed round.
+enum class Part { kWhole, kExec, kTail };
+
+int capture_round(hetm_ctx *c, uint32_t policy, Part part, hetm_ctx::RoundGraph &rg) {
     if (rg.exec) return HETM_OK;
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     const bool fork = c->cfg.async_merge && policy == HETM_POLICY_CPU_WINS;
@@ -351,8 +358,11 @@ int build_graph(hetm_ctx *c, uint32_t policy) {
     // round's merge copy (device-to-host posted writes) and stall the launch.
     launch_set_args(c->args, c->dargs, s);
     hipError_t ce = hipSuccess;
-    launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s);
-    if (fork) {
+    if (part != Part::kTail)
+        launch_exec(c->args.program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, s);
+    if (part == Part::kExec) {
+        // the execution part ends here
+    } else if (fork) {
         hipStream_t br = c->cap_branch;
         if (ce == hipSuccess) ce = hipEventRecord(c->fork_ev, s);
         if (ce == hipSuccess) ce = hipStreamWaitEvent(br, c->fork_ev, 0);
@@ -373,8 +383,10 @@ int build_graph(hetm_ctx *c, uint32_t policy) {
         else
             launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
     }
-    launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, s);
-    (void)hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, s);
+    if (part != Part::kExec) {
+        launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, s);
+        (void)hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, s);
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (e != hipSuccess || ce != hipSuccess) {
@@ -406,6 +418,21 @@ int build_graph(hetm_ctx *c, uint32_t policy) {
         }
     }
     if (!rg.args_node) return fail(c, HETM_EDEVICE, "argument node not found in the round graph");
+    return HETM_OK;
+}
+
+int build_graph(hetm_ctx *c, uint32_t policy) { return capture_round(c, policy, Part::kWhole, c->graphs[policy]); }
+
+// Uploads the current arguments into a graph's argument node and launches it.
+int launch_round_graph(hetm_ctx *c, hetm_ctx::RoundGraph &rg, hipStream_t s) {
+    c->args.epoch = c->epoch;
+    DevArgs *dst = c->dargs;
+    void *kargs[2] = {&c->args, &dst};
+    hipKernelNodeParams kp = rg.args_params;
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    HIP_TRY(c, hipGraphExecKernelNodeSetParams(rg.exec, rg.args_node, &kp));
+    HIP_TRY(c, hipGraphLaunch(rg.exec, s));
     return HETM_OK;
 }
 
@@ -457,62 +484,144 @@ int issue_merge(hetm_ctx *c, hipEvent_t after) {
 
 namespace hetm {
 
-int round_begin(hetm_ctx *c, const hetm_round_args *r) {
+// Checks a GRAPH round's arguments and sets them up, except the log (a
+// whole round stages it, a streamed round takes it in pushed chunks).
+int prepare_round(hetm_ctx *c, const hetm_round_args *r, const void **hdev) {
     if (c->cfg.mode != HETM_MODE_GRAPH) return fail(c, HETM_ESTATE, "round_begin needs GRAPH mode");
     if (c->in_validation || c->round_open) return fail(c, HETM_ESTATE, "a round is already open");
     if (r->policy > HETM_POLICY_GPU_WINS) return fail(c, HETM_EINVAL, "bad policy %u", r->policy);
-    c->args.policy = r->policy;
     if (r->n_log > c->cfg.log_capacity) return fail(c, HETM_ECAPACITY, "log %llu > capacity", (unsigned long long)r->n_log);
     if (r->n_log && !r->log) return fail(c, HETM_EINVAL, "null log");
-    const void *hdev = nullptr;
-    int rc = check_host_replica(c, r->host_replica, &hdev);
+    int rc = check_host_replica(c, r->host_replica, hdev);
     if (rc) return rc;
+    c->args.policy = r->policy;
     if (r->n_txns) {
         if ((rc = set_batch_args(c, r->program, r->descs, r->n_txns, r->results, r->tickets))) return rc;
     } else {
         c->args.n_txns = 0;
         if (!c->args.program) c->args.program = HETM_PROG_OPLIST;
     }
-    const void *dlog = nullptr;
-    if (r->n_log && (rc = stage_log(c, r->log, r->n_log, &dlog))) return rc;
-    c->args.log = dlog;
-    c->args.n_log = (uint32_t)r->n_log;
+    c->args.log = nullptr;
+    c->args.n_log = 0;
     c->args.flags = r->flags_bits;
     c->args.outcome = HETM_OUTCOME_DEVICE;
-    c->args.host = const_cast<void *>(hdev);
+    c->args.host = const_cast<void *>(*hdev);
     c->args.ids_out = r->ids_out;
     c->round_host = r->host_replica;
     if (c->graphs[r->policy].exec && c->graphs[r->policy].program != c->args.program) drop_graphs(c);
-    if ((rc = build_graph(c, r->policy))) return rc;
-    const hetm_ctx::RoundGraph &rg = c->graphs[r->policy];
-    // the graph runs on the caller's stream, after the caller's earlier work
-    // there (uploads, a staged log); it was captured on a private stream
-    hipStream_t s = c->stream;
+    for (auto &p : c->sgraphs)
+        if (p[0].exec && p[0].program != c->args.program) drop_graphs(c);
+    return HETM_OK;
+}
+
+// Before a round's graph: the staging buffer it fills must have reached the
+// host (double-buffered merge).
+int wait_staging(hetm_ctx *c, hipStream_t s) {
     const int b = c->buf;
     if (c->cfg.async_merge) {
-        // the staging buffer this round fills must have reached the host
         if (c->pending[b]) HIP_TRY(c, hipStreamWaitEvent(s, c->copied[b], 0));
         c->args.staging = c->staging[b];
         c->args.stage_ids = c->stage_ids[b];
         c->args.stage_count = c->stage_count[b];
     }
-    c->args.epoch = c->epoch;
-    DevArgs *dst = c->dargs;
-    void *kargs[2] = {&c->args, &dst};
-    hipKernelNodeParams kp = rg.args_params;
-    kp.kernelParams = kargs;
-    kp.extra = nullptr;
-    HIP_TRY(c, hipGraphExecKernelNodeSetParams(rg.exec, rg.args_node, &kp));
+    return HETM_OK;
+}
+
+int round_begin(hetm_ctx *c, const hetm_round_args *r) {
+    const void *hdev = nullptr;
+    int rc = prepare_round(c, r, &hdev);
+    if (rc) return rc;
+    const void *dlog = nullptr;
+    if (r->n_log && (rc = stage_log(c, r->log, r->n_log, &dlog))) return rc;
+    c->args.log = dlog;
+    c->args.n_log = (uint32_t)r->n_log;
+    if ((rc = build_graph(c, r->policy))) return rc;
+    // the graph runs on the caller's stream, after the caller's earlier work
+    // there (uploads, a staged log); it was captured on a private stream
+    hipStream_t s = c->stream;
+    if ((rc = wait_staging(c, s))) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[0], s));
-    HIP_TRY(c, hipGraphLaunch(rg.exec, s));
+    if ((rc = launch_round_graph(c, c->graphs[r->policy], s))) return rc;
     // the last round's copy to the host is issued once this round's graph
     // is queued (its end event, ev[3], is re-recorded only below)
     if ((rc = issue_merge(c, nullptr))) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[3], s));
     c->round_open = true;
+    c->round_streamed = false;
     c->round_hdev = hdev;
-    c->round_buf = b;
+    c->round_buf = c->buf;
     return HETM_OK;
+}
+
+int stream_push(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out) {
+    if (!c->round_open || !c->round_streamed) return fail(c, HETM_ESTATE, "no streamed round open");
+    if (n && !log) return fail(c, HETM_EINVAL, "null log");
+    if (n > c->cfg.log_capacity - c->round_pushed)
+        return fail(c, HETM_ECAPACITY, "%llu + %llu log entries > capacity %llu", (unsigned long long)c->round_pushed,
+                    (unsigned long long)n, (unsigned long long)c->cfg.log_capacity);
+    if (n) {
+        hipStream_t es = c->early_stream;
+        // after the last round's tail (it read log_staging and cleared the
+        // read set), beside this round's execution
+        HIP_TRY(c, hipStreamWaitEvent(es, c->exec_queued, 0));
+        uint8_t *dst = (uint8_t *)c->log_staging + c->round_pushed * c->log_entry_bytes;
+        HIP_TRY(c, hipMemcpyAsync(dst, log, n * c->log_entry_bytes, hipMemcpyDefault, es));
+        if (c->args.policy == HETM_POLICY_CPU_WINS) {
+            launch_early_validate(dst, n, c->cfg.word_bytes, c->rs, c->args.gdiv, c->cfg.n_words, c->epoch, c->cnt, es);
+            HIP_TRY(c, hipGetLastError());
+        }
+        HIP_TRY(c, hipEventRecord(c->early_ev, es));
+        c->early_used = true;
+        c->round_pushed += n;
+    }
+    if (doomed_out) {
+        HIP_TRY(c, hipMemcpyAsync(c->early_host, &c->cnt->doomed, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                  c->early_stream));
+        HIP_TRY(c, hipStreamSynchronize(c->early_stream));
+        *doomed_out = *c->early_host == c->epoch;
+    }
+    return HETM_OK;
+}
+
+int stream_begin(hetm_ctx *c, const hetm_round_args *r) {
+    const void *hdev = nullptr;
+    int rc = prepare_round(c, r, &hdev);
+    if (rc) return rc;
+    hetm_ctx::RoundGraph *g = c->sgraphs[r->policy];
+    if ((rc = capture_round(c, r->policy, Part::kExec, g[0]))) return rc;
+    if ((rc = capture_round(c, r->policy, Part::kTail, g[1]))) return rc;
+    g[1].program = g[0].program;
+    hipStream_t s = c->stream;
+    if ((rc = wait_staging(c, s))) return rc;
+    HIP_TRY(c, hipEventRecord(c->ev[0], s));
+    HIP_TRY(c, hipEventRecord(c->exec_queued, s));
+    if ((rc = launch_round_graph(c, g[0], s))) return rc;
+    if ((rc = issue_merge(c, nullptr))) return rc;
+    c->round_open = true;
+    c->round_streamed = true;
+    c->round_pushed = 0;
+    c->round_args = *r;
+    c->round_hdev = hdev;
+    c->round_buf = c->buf;
+    if (r->n_log && (rc = stream_push(c, r->log, r->n_log, nullptr))) return rc;
+    return HETM_OK;
+}
+
+int stream_end(hetm_ctx *c, hetm_round_result *res) {
+    if (!c->round_open || !c->round_streamed) return fail(c, HETM_ESTATE, "no streamed round open");
+    hipStream_t s = c->stream;
+    // every pushed chunk is copied (and early-validated) before the tail
+    if (c->early_used) HIP_TRY(c, hipStreamWaitEvent(s, c->early_ev, 0));
+    c->early_used = false;
+    c->args.log = c->round_pushed ? c->log_staging : nullptr;
+    c->args.n_log = (uint32_t)c->round_pushed;
+    int rc = launch_round_graph(c, c->sgraphs[c->args.policy][1], s);
+    if (rc) return rc;
+    HIP_TRY(c, hipEventRecord(c->ev[3], s));
+    hetm_round_args r = c->round_args;
+    r.n_log = c->round_pushed;
+    c->round_streamed = false;
+    return round_end(c, &r, res);
 }
 
 int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
@@ -716,6 +825,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     if (hipStreamCreateWithFlags(&c->early_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->closed_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->early_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->exec_queued, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void **)&c->early_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
         return alloc_fail(c, HETM_EDEVICE, "early-validation stream and events");
     hipStream_t s = c->stream;
@@ -814,6 +924,7 @@ int hetm_free(hetm_ctx *c) {
     if (c->early_stream) (void)hipStreamDestroy(c->early_stream);
     if (c->closed_ev) (void)hipEventDestroy(c->closed_ev);
     if (c->early_ev) (void)hipEventDestroy(c->early_ev);
+    if (c->exec_queued) (void)hipEventDestroy(c->exec_queued);
     delete c;
     return HETM_OK;
 }
@@ -928,6 +1039,22 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
         res->us_total = elapsed_us(c->ev[0], c->ev[3]);
     }
     return HETM_OK;
+}
+
+int hetm_round_begin(hetm_ctx *c, const hetm_round_args *r) {
+    if (!c || !r) return HETM_EINVAL;
+    return hetm::stream_begin(c, r);
+}
+
+int hetm_round_push(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out) {
+    if (!c) return HETM_EINVAL;
+    return hetm::stream_push(c, log, n, doomed_out);
+}
+
+int hetm_round_end(hetm_ctx *c, hetm_round_result *res) {
+    if (!c) return HETM_EINVAL;
+    if (res) memset(res, 0, sizeof *res);
+    return hetm::stream_end(c, res);
 }
 
 int hetm_early_validate(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out) {

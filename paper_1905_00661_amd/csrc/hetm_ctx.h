@@ -63,6 +63,16 @@ struct hetm_ctx {
         hipGraphNode_t args_node = nullptr;   // the argument-upload kernel node
         hipKernelNodeParams args_params{};
     } graphs[2];
+    // A streamed round (hetm_round_begin / push / end) is the same round in
+    // two graphs, per merge policy: [0] argument upload and execution,
+    // [1] argument upload, validation and apply of every pushed chunk, merge
+    // and finish.  Chunks pushed in between are copied into log_staging and
+    // early-validated on early_stream.
+    RoundGraph sgraphs[2][2];
+    bool round_streamed = false;
+    uint64_t round_pushed = 0;              // log entries pushed into log_staging
+    hetm_round_args round_args{};           // the streamed round's arguments
+    hipEvent_t exec_queued = nullptr;       // before the streamed round's execution graph
     hipStream_t cap_branch = nullptr;       // capture only: the merge branch
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 
@@ -91,7 +101,7 @@ struct hetm_ctx {
     void *staging[2] = {};
     uint32_t *stage_ids[2] = {};
     uint32_t *stage_count[2] = {};
-    uint8_t *host_stage[2] = {};            // pinned: the DMA'd granules, scattered by the merge worker
+    uint8_t *host_stage[2] = {};            // pinned: the copied granules, scattered by the merge worker
     uint32_t *host_ids[2] = {};
     uint64_t host_cap[2] = {0, 0};          // granules the pinned staging holds (all of them)
     uint64_t merge_seq[2] = {0, 0};         // worker job that last read host_stage[b]
@@ -118,6 +128,13 @@ namespace hetm {
 // synchronous merge, restore on conflict) and fills *res.
 int round_begin(hetm_ctx *c, const hetm_round_args *r);
 int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res);
+// Streamed GRAPH round: stream_begin launches the execution part;
+// stream_push copies a log chunk into the round's log and early-validates
+// it beside the execution; stream_end launches the tail (validation and
+// apply of every pushed chunk, merge, finish) and ends as round_end does.
+int stream_begin(hetm_ctx *c, const hetm_round_args *r);
+int stream_push(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out);
+int stream_end(hetm_ctx *c, hetm_round_result *res);
 // Double-buffered merge progress.  A successful round's copy to the host is
 // issued by the next round_begin (after it queues its graph) or by
 // issue_deferred_merge; last_merge_seq is the most recently issued job (0

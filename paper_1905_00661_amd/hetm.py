@@ -34,7 +34,7 @@ EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_a
            "hetm_stats_get", "hetm_read_state", "hetm_state_bytes", "hetm_host_tm_create",
            "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts",
            "hetm_serve", "hetm_set_exec_workgroups", "hetm_early_validate", "hetm_set_version_clock",
-           "hetm_read_words_noalloc"]
+           "hetm_read_words_noalloc", "hetm_round_begin", "hetm_round_push", "hetm_round_end"]
 
 P = ctypes.c_void_p
 U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -132,6 +132,9 @@ def lib() -> ctypes.CDLL:
             "hetm_read_state": ([P, U32, P, U64], ctypes.c_int),
             "hetm_state_bytes": ([P, U32], U64),
             "hetm_read_words_noalloc": ([P, U64, U64, P], ctypes.c_int),
+            "hetm_round_begin": ([P, ctypes.POINTER(hetm_round_args)], ctypes.c_int),
+            "hetm_round_push": ([P, P, U64, P], ctypes.c_int),
+            "hetm_round_end": ([P, ctypes.POINTER(hetm_round_result)], ctypes.c_int),
             "hetm_host_tm_create": ([P, U64, U32, U32, U64, ctypes.POINTER(P)], ctypes.c_int),
             "hetm_host_tm_free": ([P], ctypes.c_int),
             "hetm_host_tm_clock": ([P], U64),
@@ -442,12 +445,33 @@ class Context:
                    round_conflict=rconf[:R], round_log_end=rlog[:R])
         return out
 
+    def _round_args(self, b, log_dev, n_log, host, flags, ids, policy) -> hetm_round_args:
+        return hetm_round_args(program=b.program if b else 0, descs=ctypes.addressof(b.desc) if b else None,
+                               n_txns=b.n if b else 0, results=b.results.data_ptr() if b else None,
+                               tickets=b.tickets.data_ptr() if b else None,
+                               log=log_dev.data_ptr() if n_log else None, n_log=n_log, policy=policy,
+                               flags_bits=flags.data_ptr() if flags is not None else None,
+                               host_replica=host.data_ptr(), ids_out=ids.data_ptr() if ids is not None else None)
+
     def round(self, b: Batch | None, log_dev, n_log: int, host, flags=None, ids=None,
               policy: int = HETM_POLICY_CPU_WINS) -> hetm_round_result:
-        a = hetm_round_args(program=b.program if b else 0, descs=ctypes.addressof(b.desc) if b else None,
-                            n_txns=b.n if b else 0, results=b.results.data_ptr() if b else None,
-                            tickets=b.tickets.data_ptr() if b else None,
-                            log=log_dev.data_ptr() if n_log else None, n_log=n_log, policy=policy,
-                            flags_bits=flags.data_ptr() if flags is not None else None,
-                            host_replica=host.data_ptr(), ids_out=ids.data_ptr() if ids is not None else None)
-        return hetm_round(self.ctx, a)
+        return hetm_round(self.ctx, self._round_args(b, log_dev, n_log, host, flags, ids, policy))
+
+    # -- streamed round (GRAPH mode)
+    def round_begin(self, b: Batch | None, host, log_dev=None, n_log: int = 0, flags=None, ids=None,
+                    policy: int = HETM_POLICY_CPU_WINS) -> None:
+        self._streamed = self._round_args(b, log_dev, n_log, host, flags, ids, policy)   # kept alive
+        _check(lib().hetm_round_begin(self.ctx, ctypes.byref(self._streamed)), "hetm_round_begin", self.ctx)
+
+    def round_push(self, log, n: int, wait: bool = False):
+        """Pushes n entries of `log` (a tensor, host or device); with wait,
+        returns 1 if the open round is doomed."""
+        d = U32(0)
+        _check(lib().hetm_round_push(self.ctx, log.data_ptr() if n else None, n, ctypes.byref(d) if wait else None),
+               "hetm_round_push", self.ctx)
+        return int(d.value) if wait else None
+
+    def round_end(self) -> hetm_round_result:
+        r = hetm_round_result()
+        _check(lib().hetm_round_end(self.ctx, ctypes.byref(r)), "hetm_round_end", self.ctx)
+        return r

@@ -100,3 +100,59 @@ def assert_round_equal(g: dict, o: dict, ri: wl.RoundInputs):
     assert np.array_equal(g["S"], g["H"]), "replicas differ after the merge"
     if o["conflict"] == 0 or r.host_discarded:
         assert int(r.n_committed) == ri.batch.n
+
+
+def streamed_round(ri: wl.RoundInputs, chunks: int = 3, where: str = "device", sync_before_push: bool = False,
+                   async_merge: bool = False, policy=hm.HETM_POLICY_CPU_WINS, host=None, ctx=None, keep=False):
+    """One streamed round (hetm_round_begin / push / end, GRAPH mode), the log
+    pushed in `chunks` consecutive pieces from `where` (device, pinned or
+    pageable host memory).  With sync_before_push the pieces are pushed once
+    the execution part has finished, so early validation sees the whole read
+    set and every transaction has run.  Returns what gpu_round returns."""
+    import torch
+    if ctx is None:
+        ctx = hm.Context(ri.n_words, ri.word_bytes, ri.granule, init=ri.init, batch_capacity=max(ri.batch.n, 1),
+                         log_capacity=max(ri.log.shape[0], 1), mode=hm.HETM_MODE_GRAPH, async_merge=async_merge)
+    H0 = wl.host_replica(ri.init, ri.log) if host is None else host
+    host_t = hm.pinned(H0.nbytes)
+    host_t.numpy()[:] = H0.view(np.uint8)
+    b = hm.Batch(ri.program, ri.batch, ctx.dev)
+    n_log = ri.log.shape[0]
+    raw = np.ascontiguousarray(ri.log).view(np.uint8).reshape(-1)
+    if where == "device":
+        log_t = hm.to_device(ri.log, ctx.dev)
+    elif where == "pinned":
+        log_t = hm.pinned(raw.nbytes)
+        log_t.numpy()[:] = raw
+    else:
+        log_t = torch.from_numpy(raw.copy())
+    eb = ri.log.dtype.itemsize
+    flags_t = torch.zeros(max((n_log + 31) // 32, 1) * 4, dtype=torch.uint8, device=ctx.dev)
+    ids_t = torch.zeros(max(ctx.n_granules, 1) * 4, dtype=torch.uint8, device=ctx.dev)
+    torch.cuda.synchronize()
+    ctx.round_begin(b if ri.batch.n else None, host_t, flags=flags_t, ids=ids_t, policy=policy)
+    if sync_before_push:
+        torch.cuda.synchronize()
+    cuts = np.linspace(0, n_log, chunks + 1).astype(np.int64)
+    doomed = 0
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        if hi > lo:
+            doomed = ctx.round_push(log_t[lo * eb:hi * eb], int(hi - lo), wait=sync_before_push) or doomed
+    res = ctx.round_end()
+    ctx.sync()
+    out = {
+        "res": res,
+        "results": b.results_np(),
+        "tickets": b.tickets_np(),
+        "S": ctx.read_state(hm.HETM_STATE_STMR).copy(),
+        "H": host_t.numpy().view(ri.init.dtype).copy(),
+        "flags": hm.tensor_to_numpy(flags_t, np.uint32),
+        "ids": hm.tensor_to_numpy(ids_t, np.uint32, int(res.n_dirty)),
+        "H0": H0,
+        "doomed_seen": doomed,
+    }
+    if keep:
+        out["ctx"] = ctx
+    else:
+        ctx.close()
+    return out

@@ -40,6 +40,9 @@ def test_strerror_and_null_handling(hm):
     assert L.hetm_round(None, None, None) == hm.HETM_EINVAL
     assert L.hetm_sync(None) == hm.HETM_EINVAL
     assert L.hetm_read_words_noalloc(None, 0, 0, None) == hm.HETM_EINVAL
+    assert L.hetm_round_begin(None, None) == hm.HETM_EINVAL
+    assert L.hetm_round_push(None, None, 0, None) == hm.HETM_EINVAL
+    assert L.hetm_round_end(None, None) == hm.HETM_EINVAL
 
 
 @pytest.mark.parametrize("field,value", [("n_words", 0), ("word_bytes", 2), ("granule_words", 0),

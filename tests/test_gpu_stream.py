@@ -1,0 +1,197 @@
+"""Streamed GRAPH rounds (hetm_round_begin / push / end): the host log is
+shipped in chunks while the round executes (§IV-D, inter-device
+synchronization) and each chunk is validated early against the read set
+(§IV-D, early validation).  The round's outcome is that of the same round
+through hetm_round: bit-exact oracle parity, chunks from device, pinned and
+pageable memory, both merge forms, both policies.  A chunk that hits the read
+set while a large batch still runs dooms the round, which then runs fewer
+transactions than its batch."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from gpu_util import assert_round_equal, oracle_round, say, streamed_round
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_00661_amd import hetm
+    hetm.lib()
+    return hetm
+
+
+@pytest.fixture(scope="module")
+def wl():
+    from paper_1905_00661_amd import workloads
+    return workloads
+
+
+@pytest.mark.parametrize("variant,chunks,where,async_merge", [
+    ("p", 3, "device", False), ("p", 3, "pinned", True), ("p", 1, "pageable", False),
+    ("", 3, "device", False), ("", 2, "pinned", True), ("w", 5, "device", True)])
+def test_streamed_round_parity(hm, wl, variant, chunks, where, async_merge):
+    """The small configuration's round, its log pushed in `chunks` pieces
+    once execution has finished: every output equals the oracle's (the
+    as-named variants conflict, and early validation dooms them after every
+    transaction ran, which changes nothing)."""
+    ri = wl.c1(variant)
+    say(f"streamed round c1{variant}: {chunks} chunks from {where}, async merge {async_merge}")
+    g = streamed_round(ri, chunks=chunks, where=where, sync_before_push=True, async_merge=async_merge)
+    o = oracle_round(ri, g["tickets"], g["H0"])
+    assert_round_equal(g, o, ri)
+    assert g["res"].doomed == (1 if o["conflict"] else 0)
+    assert g["doomed_seen"] == o["conflict"]
+
+
+def test_streamed_gpu_wins(hm, wl):
+    """GPU wins: pushed chunks are not early-validated (the GPU keeps its
+    round); the conflicting host log is discarded as in hetm_round."""
+    ri = wl.c1("w")
+    g = streamed_round(ri, chunks=3, where="device", policy=hm.HETM_POLICY_GPU_WINS)
+    o = oracle_round(ri, g["tickets"], g["H0"], policy=orc.POLICY_GPU_WINS)
+    assert_round_equal(g, o, ri)
+    assert g["res"].doomed == 0
+
+
+def test_streamed_rounds_in_sequence(hm, wl):
+    """Streamed and whole rounds in turn on one context with the double-
+    buffered merge: each matches the oracle, starting from the replicas the
+    last one left."""
+    from gpu_util import gpu_round
+    ri = wl.c1("p")
+    ctx = None
+    S, TS, floor = ri.init.copy(), np.zeros(ri.n_words, np.uint64), 0
+    for k, streamed in enumerate([True, False, True, True]):
+        g = np.random.default_rng(100 + k)
+        batch = wl._oplist_from_lists(np.full(2048, 4, np.uint64), np.full(2048, 4), g.integers(
+            0, ri.n_words // 2, size=4 * 2048, dtype=np.uint64), k * 4096)
+        log = wl.host_log_uniform(g, 6000, ri.n_words // 2, ri.n_words, floor)
+        rk = wl.RoundInputs(cfg="seq", n_words=ri.n_words, word_bytes=4, granule=ri.granule, program=wl.PROG_OPLIST,
+                            init=S.copy(), batch=batch, log=log)
+        H0 = wl.host_replica(S, log)
+        if ctx is None:
+            from paper_1905_00661_amd import hetm
+            ctx = hetm.Context(ri.n_words, 4, ri.granule, init=S, batch_capacity=4096, log_capacity=8192,
+                               mode=hetm.HETM_MODE_GRAPH, async_merge=True)
+        if streamed:
+            out = streamed_round(rk, chunks=4, where="pinned", ctx=ctx, host=H0, keep=True)
+        else:
+            out = gpu_round(rk, ctx=ctx, host=H0, keep=True)
+        o = oracle_round(rk, out["tickets"], H0, S0=S, TS0=TS, floor=floor)
+        assert_round_equal(out, o, rk)
+        S, TS, floor = o["S"], o["TS"], int(out["res"].max_ts)
+    ctx.close()
+
+
+def test_doomed_round_ran_fewer(hm, wl):
+    """A large batch whose transactions all read a hot word first; the host
+    pushes one-entry chunks writing that word until one comes back doomed.
+    The round is a conflict (CPU wins), it ran fewer transactions than its
+    batch, and both replicas equal the host's."""
+    import torch
+    n_words, n = 1 << 22, 1 << 20
+    g = np.random.default_rng(21)
+    init = g.integers(0, 2 ** 32, size=n_words, dtype=np.uint64).astype(np.uint32)
+    idx = g.integers(0, n_words // 2, size=8 * n, dtype=np.uint64)
+    idx[::8] = g.integers(0, 64, size=n, dtype=np.uint64)
+    batch = wl._oplist_from_lists(np.full(n, 8, np.uint64), np.full(n, 2), idx, 0)
+    ctx = hm.Context(n_words, 4, 16, init=init, batch_capacity=n, log_capacity=256, mode=hm.HETM_MODE_GRAPH)
+    b = hm.Batch(1, batch)
+    pieces = wl.host_log_uniform(g, 256, n_words // 2, n_words, 0)
+    pieces["word"] = 5                                  # every piece writes hot word 5,
+    pieces["value"] = 12345                             # the same value: any prefix gives one replica
+    H0 = wl.host_replica(init, pieces)
+    host_t = hm.pinned(n_words * 4)
+    host_t.numpy()[:] = H0.view(np.uint8)
+    log_t = hm.to_device(pieces)
+    eb = pieces.dtype.itemsize
+    torch.cuda.synchronize()
+    ctx.round_begin(b, host_t)
+    pushed, d = 0, 0
+    while not d and pushed < 256:
+        d = ctx.round_push(log_t[pushed * eb:(pushed + 1) * eb], 1, wait=True)
+        pushed += 1
+    res = ctx.round_end()
+    ctx.sync()
+    ran = int(ctx.stats().txns_aborted)                # transactions executed, then aborted
+    say(f"doomed after {pushed} pushed entries; transactions run: {ran} of {n}")
+    assert d == 1 and res.doomed == 1 and res.conflict == 1
+    assert int(res.n_aborted) == n and int(res.n_committed) == 0
+    assert ran < n, "the doomed round ran its whole batch"
+    H = wl.host_replica(init, pieces[:pushed])
+    assert np.array_equal(H, H0)
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), H)
+    assert np.array_equal(host_t.numpy().view(np.uint32), H)
+    # the next round on the context is not doomed by the last one
+    g2 = np.random.default_rng(22)
+    b2 = hm.Batch(1, wl._oplist_from_lists(np.full(4096, 4, np.uint64), np.full(4096, 2), g2.integers(
+        0, n_words // 2, size=4 * 4096, dtype=np.uint64), 1 << 24))
+    log2 = wl.host_log_uniform(g2, 200, n_words // 2, n_words, int(res.max_ts))
+    host_t.numpy()[:] = wl.host_replica(H, log2).view(np.uint8)
+    ctx.round_begin(b2, host_t)
+    assert ctx.round_push(hm.to_device(log2), 200, wait=True) == 0
+    r2 = ctx.round_end()
+    assert r2.conflict == 0 and r2.doomed == 0 and int(r2.n_committed) == 4096
+    ctx.close()
+
+
+def test_stream_errors(hm, wl):
+    """Out-of-order calls give ESTATE; a push past the capacity gives
+    ECAPACITY and appends nothing; a pushed entry outside the replica fails
+    the round (EINVAL) and leaves the context usable."""
+    N = 1 << 12
+    init = np.arange(N, dtype=np.uint32)
+    plain = hm.Context(N, 4, 16, init=init, batch_capacity=16, log_capacity=16, mode=hm.HETM_MODE_PLAIN)
+    host_t = hm.pinned(N * 4)
+    host_t.numpy()[:] = init.view(np.uint8)
+    with pytest.raises(hm.HetmError) as e:
+        plain.round_begin(None, host_t)
+    assert e.value.code == hm.HETM_ESTATE
+    plain.close()
+    ctx = hm.Context(N, 4, 16, init=init, batch_capacity=16, log_capacity=16, mode=hm.HETM_MODE_GRAPH)
+    log = wl.host_log_uniform(np.random.default_rng(1), 16, 0, N, 0)
+    log_t = hm.to_device(log)
+    for call in (lambda: ctx.round_push(log_t, 1), lambda: ctx.round_end()):
+        with pytest.raises(hm.HetmError) as e:
+            call()
+        assert e.value.code == hm.HETM_ESTATE
+    ctx.round_begin(None, host_t)
+    with pytest.raises(hm.HetmError) as e:
+        ctx.round_begin(None, host_t)
+    assert e.value.code == hm.HETM_ESTATE
+    with pytest.raises(hm.HetmError) as e:
+        ctx.round(None, log_t, 0, host_t)
+    assert e.value.code == hm.HETM_ESTATE
+    ctx.round_push(log_t, 10)
+    with pytest.raises(hm.HetmError) as e:
+        ctx.round_push(log_t, 7)
+    assert e.value.code == hm.HETM_ECAPACITY
+    ctx.round_push(log_t[10 * 16:], 6)
+    host_t.numpy()[:] = wl.host_replica(init, log).view(np.uint8)
+    r = ctx.round_end()
+    assert r.conflict == 0 and r.error == 0
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), wl.host_replica(init, log))
+    # a bad entry fails the round's validation: EINVAL, nothing applied
+    S1 = ctx.read_state(hm.HETM_STATE_STMR).copy()
+    bad = wl.host_log_uniform(np.random.default_rng(2), 4, 0, N, int(r.max_ts))
+    bad["word"][2] = N + 3
+    ctx.round_begin(None, host_t)
+    ctx.round_push(hm.to_device(bad), 4)
+    with pytest.raises(hm.HetmError) as e:
+        ctx.round_end()
+    assert e.value.code == hm.HETM_EINVAL
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S1)
+    ok = wl.host_log_uniform(np.random.default_rng(3), 8, 0, N, int(r.max_ts))
+    host_t.numpy()[:] = wl.host_replica(S1, ok).view(np.uint8)
+    ctx.round_begin(None, host_t, hm.to_device(ok), 8)
+    r3 = ctx.round_end()
+    assert r3.error == 0
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), wl.host_replica(S1, ok))
+    ctx.close()
