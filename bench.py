@@ -385,6 +385,100 @@ def conflict_form(args, hm, wl, torch, ri, dev) -> dict:
             "form": "batched, CPU wins, r = 10% of rounds conflicting"}
 
 
+def early_form(args, hm, wl, torch, ri, dev) -> dict:
+    """Early validation on and off (§IV-D; the contention sweep of §V-C):
+    batched large rounds in which a given fraction of the rounds carries one
+    log entry on a word the batch reads.  Off: hetm_round validates the log
+    after execution.  On: a streamed round whose log is pushed in 16 chunks
+    paced over the execution (a host producing its log as it runs), each
+    chunk early-validated; a hit stops the transaction kernel."""
+    N, G, n_log = ri.n_words, ri.granule, ri.log.shape[0]
+    rounds = args.early_rounds
+    n_chunks = 16
+    per = (n_log + n_chunks - 1) // n_chunks
+    eb = ri.log.dtype.itemsize
+    b_idx = ri.batch.idx
+    out = {"form": "batched (GRAPH, double-buffered merge), CPU wins; on: log pushed in 16 chunks paced over "
+                   "the clean round's execution time, each early-validated",
+           "rounds_per_point": rounds, "points": []}
+    ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=ri.batch.n,
+                     log_capacity=n_log, mode=hm.HETM_MODE_GRAPH, exec_workgroups=args.exec_wg, async_merge=True)
+    b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
+    host = hm.pinned(N * 4)
+    host.numpy()[:] = ri.init.view(np.uint8)
+    shift = [0]
+
+    def logs_for(frac, seed):
+        g = np.random.default_rng(seed)
+        hits = g.random(rounds) < frac
+
+        def inject(r, lr):
+            if not hits[r]:
+                return False
+            lr["word"][int(g.integers(0, n_log))] = b_idx[int(g.integers(0, b_idx.shape[0]))]
+            return True
+        ls = shifted_logs(torch, hm, ri.log, n_log, rounds, dev, inject=inject)
+        for t in ls:
+            t.view(torch.int64).view(-1, 2)[:, 1].add_(shift[0])
+        shift[0] += rounds * n_log
+        torch.cuda.synchronize()
+        return ls
+
+    # warm both forms up and time the clean round's execution for the pacing
+    for t in logs_for(0.0, 1)[:3]:
+        ctx.round(b, t, n_log, host)
+    warm = logs_for(0.0, 2)
+    for t in warm[:3]:
+        ctx.round_begin(b, host)
+        for k in range(n_chunks):
+            lo = k * per
+            ctx.round_push(t[lo * eb:min(lo + per, n_log) * eb], min(per, n_log - lo))
+        ctx.round_end()
+    ctx.sync()
+    pace_s = 0.8 * 1e-3 * args.early_exec_ms / n_chunks
+    for frac in args.early_fracs:
+        point = {"conflict_fraction": frac}
+        for mode in ("off", "on"):
+            ls = logs_for(frac, 1000 + int(frac * 100))
+            st0 = ctx.stats()
+            ctx.sync()
+            torch.cuda.synchronize()
+            lat_ok, lat_cf, committed, doomed = [], [], 0, 0
+            t0 = time.perf_counter()
+            for t in ls:
+                t1 = time.perf_counter()
+                if mode == "off":
+                    rr = ctx.round(b, t, n_log, host)
+                else:
+                    ctx.round_begin(b, host)
+                    for k in range(n_chunks):
+                        lo = k * per
+                        ctx.round_push(t[lo * eb:min(lo + per, n_log) * eb], min(per, n_log - lo))
+                        t_next = t1 + (k + 1) * pace_s
+                        while time.perf_counter() < t_next:
+                            pass
+                    rr = ctx.round_end()
+                (lat_cf if rr.conflict else lat_ok).append(1e3 * (time.perf_counter() - t1))
+                committed += rr.n_committed
+                doomed += rr.doomed
+            ctx.sync()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            st1 = ctx.stats()
+            n_cf = len(lat_cf)
+            point[mode] = {"txn_per_s": committed / el, "ms_per_round": 1e3 * el / rounds,
+                           "conflict_rounds": n_cf, "doomed_rounds": doomed,
+                           "mean_clean_round_ms": float(np.mean(lat_ok)) if lat_ok else None,
+                           "mean_conflict_round_ms": float(np.mean(lat_cf)) if lat_cf else None,
+                           "txns_run_per_conflict_round": (st1.txns_aborted - st0.txns_aborted) / n_cf if n_cf else None}
+        out["points"].append(point)
+        log(f"early validation, conflict fraction {frac}: off {point['off']['ms_per_round']:.3f} ms/round, "
+            f"on {point['on']['ms_per_round']:.3f} ms/round")
+    ctx.close()
+    out["batch_txns"] = ri.batch.n
+    return out
+
+
 def bank_form(args, hm, wl, torch, dev) -> dict:
     """Bank transfers at full size: 2^24 int64 accounts, U[2^20, 2^21]
     Zipf(0.9) transfers per round on the GPU, the host TM's 2^15 transfers
@@ -573,8 +667,14 @@ def main():
     ap.add_argument("--p-hot", type=float, default=0.5)
     ap.add_argument("--stripe", type=int, default=1)
     ap.add_argument("--exec-wg", type=int, default=0, help="transaction-kernel workgroups (0 = one per CU)")
-    ap.add_argument("--legs", default="ingest,small,conflict,bank,cache,served,cpu",
-                    help="comma list of legs beside the headline (ingest, small, conflict, bank, cache, served, cpu)")
+    ap.add_argument("--legs", default="ingest,small,conflict,early,bank,cache,served,cpu",
+                    help="comma list of legs beside the headline (ingest, small, conflict, early, bank, cache, "
+                         "served, cpu)")
+    ap.add_argument("--early-rounds", type=int, default=20)
+    ap.add_argument("--early-fracs", type=lambda v: [float(x) for x in v.split(",")], default="0,0.25,0.5,1",
+                    help="fractions of conflicting rounds swept by the early-validation leg")
+    ap.add_argument("--early-exec-ms", type=float, default=0.6,
+                    help="execution time over which the early-validation leg paces its pushes")
     ap.add_argument("--small-rounds", type=int, default=200)
     ap.add_argument("--bank-rounds", type=int, default=3)
     ap.add_argument("--cache-rounds", type=int, default=3)
@@ -660,6 +760,9 @@ def main():
     if "conflict" in legs:
         log("conflicting rounds ...")
         out["conflict"] = conflict_form(args, hm, wl, torch, ri, dev)
+    if "early" in legs:
+        log("early validation on and off ...")
+        out["early"] = early_form(args, hm, wl, torch, ri, dev)
     if "bank" in legs:
         log("bank transfers ...")
         out["bank"] = bank_form(args, hm, wl, torch, dev)

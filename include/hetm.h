@@ -478,6 +478,15 @@ typedef struct {
     uint32_t        starvation_limit;   /* 0: off; else after this many aborted
                                            rounds in a row the host holds back
                                            its writes for one round (§IV-E) */
+    uint32_t        early_validation;   /* pipelined only: 1 = streamed rounds
+                                           (hetm_round_begin / push / end): the
+                                           host commits a round's writes in
+                                           pieces of push_entries while the GPU
+                                           runs it and pushes each piece as it
+                                           is committed, early-validated
+                                           (§IV-D); a hit stops the round */
+    uint32_t        push_entries;       /* entries per pushed piece; 0 = 3072
+                                           (48 KB of 16-byte entries, §IV-D) */
 } hetm_serve_spec;
 
 typedef struct {

@@ -18,6 +18,11 @@
 
 namespace {
 
+// Streamed serving rounds ship the host's writes in pieces of 48 KB of
+// 16-byte log entries, the chunk size the paper settles on for shipping
+// logs while the CPU keeps running (§IV-D).
+constexpr uint64_t kServePushEntries = 48 * 1024 / sizeof(hetm_log_entry4);
+
 using clk = std::chrono::steady_clock;
 
 double seconds_since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
@@ -263,6 +268,21 @@ struct Serve {
         for (uint64_t k = 0; k < r.n_log; ++k) H[r.h_log[k].word] = r.h_log[k].value;
     }
 
+    // Streamed round: the host commits the round's writes piece by piece
+    // while the GPU runs it and ships each piece once committed (pushed into
+    // the round's log and early-validated against the read set as it stands).
+    int host_commit_streamed(const RoundSet &r) {
+        uint32_t *H = (uint32_t *)host;
+        const uint64_t per = sp.push_entries ? sp.push_entries : kServePushEntries;
+        for (uint64_t lo = 0; lo < r.n_log; lo += per) {
+            const uint64_t hi = std::min<uint64_t>(r.n_log, lo + per);
+            for (uint64_t k = lo; k < hi; ++k) H[r.h_log[k].word] = r.h_log[k].value;
+            int e = hetm::stream_push(c, r.d_log + lo, hi - lo, nullptr);
+            if (e) return e;
+        }
+        return HETM_OK;
+    }
+
     hetm_round_args round_args(RoundSet &r, hetm_oplist_desc &d) {
         d = {r.d_off, r.d_idx, r.d_nw, r.d_tid};
         hetm_round_args a{};
@@ -416,7 +436,8 @@ struct Serve {
                 hetm_round_result res{};
                 {
                     Span t(&rep->us_wait_round);
-                    if ((err = hetm::round_end(c, &a[cur], &res))) return err;
+                    err = sp.early_validation ? hetm::stream_end(c, &res) : hetm::round_end(c, &a[cur], &res);
+                    if (err) return err;
                     // a served request completes when its round's merge lands:
                     // start the copy now rather than with the next round
                     if ((err = hetm::issue_deferred_merge(c))) return err;
@@ -435,7 +456,14 @@ struct Serve {
                 if (hipStreamWaitEvent(c->stream, r.uploaded, 0) != hipSuccess) return HETM_EDEVICE;
                 {
                     Span t(&rep->us_wait_round);
-                    if ((err = hetm::round_begin(c, &a[nxt]))) return err;
+                    if (sp.early_validation) {
+                        a[nxt].log = nullptr;         // shipped in pieces as the host commits them
+                        a[nxt].n_log = 0;
+                        err = hetm::stream_begin(c, &a[nxt]);
+                    } else {
+                        err = hetm::round_begin(c, &a[nxt]);
+                    }
+                    if (err) return err;
                     if ((err = fetch_after_round(r))) return err;
                 }
                 // the host's writes of this round go into the host replica
@@ -447,7 +475,11 @@ struct Serve {
                 }
                 {
                     Span t(&rep->us_host_commit);
-                    host_commit(r);
+                    if (sp.early_validation) {
+                        if ((err = host_commit_streamed(r))) return err;
+                    } else {
+                        host_commit(r);
+                    }
                 }
                 Span t(&rep->us_settle);
                 if ((err = poll(false))) return err;    // the last round's merge has landed
@@ -475,6 +507,7 @@ extern "C" int hetm_serve(hetm_ctx *c, const hetm_serve_spec *sp, void *host_rep
         (sp->host_log_len && !sp->host_log))
         return HETM_EINVAL;
     if (sp->pipelined && c->cfg.mode != HETM_MODE_GRAPH) return HETM_ESTATE;
+    if (sp->early_validation && !sp->pipelined) return HETM_EINVAL;
     if (!sp->pipelined && c->cfg.async_merge) return HETM_ESTATE;
     for (uint64_t i = 0; i < sp->n_requests; ++i)
         if (sp->offsets[i + 1] < sp->offsets[i] || sp->offsets[i + 1] - sp->offsets[i] > c->cfg.max_txn_ops ||

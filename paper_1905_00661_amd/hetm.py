@@ -79,7 +79,8 @@ class hetm_round_result(ctypes.Structure):
 class hetm_serve_spec(ctypes.Structure):
     _fields_ = [("n_requests", U64), ("arrival_s", P), ("offsets", P), ("idx", P), ("n_writes", P), ("tid", P),
                 ("host_log", P), ("host_log_len", U64), ("host_log_per_round", U64), ("max_batch", U64),
-                ("mem_budget_bytes", U64), ("pipelined", U32), ("starvation_limit", U32)]
+                ("mem_budget_bytes", U64), ("pipelined", U32), ("starvation_limit", U32),
+                ("early_validation", U32), ("push_entries", U32)]
 
 
 class hetm_serve_report(ctypes.Structure):
@@ -416,7 +417,7 @@ class Context:
 
     def serve(self, arrival_s: np.ndarray, batch, host, host_log: np.ndarray, host_log_per_round: int,
               max_batch: int, mem_budget_bytes: int, pipelined: bool, max_rounds: int = 1 << 16,
-              starvation_limit: int = 0) -> dict:
+              starvation_limit: int = 0, early_validation: bool = False, push_entries: int = 0) -> dict:
         """Runs the request loop (hetm_serve) over OPLIST requests; returns the
         report and per-request latencies, results and commit positions."""
         arrival_s = np.ascontiguousarray(arrival_s, dtype=np.float64)
@@ -432,7 +433,8 @@ class Context:
                                tid=batch.tid.ctypes.data, host_log=host_log.ctypes.data if host_log.size else None,
                                host_log_len=host_log.shape[0], host_log_per_round=host_log_per_round,
                                max_batch=max_batch, mem_budget_bytes=mem_budget_bytes, pipelined=int(pipelined),
-                               starvation_limit=starvation_limit)
+                               starvation_limit=starvation_limit, early_validation=int(early_validation),
+                               push_entries=push_entries)
         rep = hetm_serve_report(latency_us=lat.ctypes.data, results=res.ctypes.data, commit_seq=seq.ctypes.data,
                                 round_conflict=rconf.ctypes.data, max_rounds=max_rounds,
                                 round_log_end=rlog.ctypes.data)

@@ -87,12 +87,15 @@ def make_ctx(hm, init, pipelined, G=64, max_batch=8192):
     return hm.Context(N, 4, G, init=init, max_ops=64, batch_capacity=max_batch, log_capacity=4096, mode=0)
 
 
-@pytest.mark.parametrize("pipelined,rate,inject", [(True, 2e6, 0), (False, 2e6, 0), (False, 5e5, 3 * 4096),
-                                                   (True, 2e7, 0), (True, 5e5, 3 * 4096)])
-def test_serve_matches_oracle(hm, wl, pipelined, rate, inject):
+@pytest.mark.parametrize("pipelined,rate,inject,early", [
+    (True, 2e6, 0, False), (False, 2e6, 0, False), (False, 5e5, 3 * 4096, False), (True, 2e7, 0, False),
+    (True, 5e5, 3 * 4096, False), (True, 2e6, 0, True), (True, 5e5, 3 * 4096, True), (True, 2e7, 997, True)])
+def test_serve_matches_oracle(hm, wl, pipelined, rate, inject, early):
     """20,000 lognormal-length requests (median 4, capped at 64) arriving
     Poisson at `rate`, 5% hot words, host log stream of 4096 entries per
-    round in the host's region (plus injected inter-device conflicts)."""
+    round in the host's region (plus injected inter-device conflicts).  With
+    `early` the rounds are streamed: the host ships its writes in pieces
+    (1000 entries) while the GPU runs, each early-validated."""
     g = wl.rng("c5", 0, 3)
     init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
     req = wl.c5_requests(g, 20000, rate, n_words=N, host_lo=HOST_LO)
@@ -100,8 +103,10 @@ def test_serve_matches_oracle(hm, wl, pipelined, rate, inject):
     ctx = make_ctx(hm, init, pipelined)
     host_t = hm.pinned(N * 4)
     host_t.numpy()[:] = init.view(np.uint8)
-    out = ctx.serve(req["arrival_s"], req["batch"], host_t, log, 4096, 8192, 64 << 20, pipelined)
-    say(f"serve pipelined={pipelined} rate={rate:g}: rounds={out['rounds']} conflicted={out['conflicted_rounds']} "
+    out = ctx.serve(req["arrival_s"], req["batch"], host_t, log, 4096, 8192, 64 << 20, pipelined,
+                    early_validation=early, push_entries=1000 if early else 0)
+    say(f"serve pipelined={pipelined} early={early} rate={rate:g}: rounds={out['rounds']} "
+        f"conflicted={out['conflicted_rounds']} "
         f"p50={out['p50_latency_us']:.0f}us p99={out['p99_latency_us']:.0f}us thr={out['throughput']:.3g}/s")
     assert out["served"] == 20000
     if inject:
