@@ -154,6 +154,45 @@ def shifted_logs(torch, hm, base_log: np.ndarray, n_log: int, rounds: int, dev: 
     return logs
 
 
+def tune_exec(args, hm, torch, ri, dev) -> dict:
+    """Chooses the transaction kernel's workgroup count for the large
+    configuration by timing whole batched rounds at a few widths, cached by
+    workload signature (outside every timed region)."""
+    from paper_1905_00661_amd import autotune
+    N, G, n_log = ri.n_words, ri.granule, ri.log.shape[0]
+    workload = {"program": "oplist", "n_words": N, "word_bytes": 4, "granule": G, "stripe": args.stripe,
+                "n_txns": ri.batch.n, "n_log": n_log, "p_hot": args.p_hot, "ops": "16 reads | 4 rmw",
+                "form": "graph, double-buffered merge"}
+    sig = autotune.signature(workload, torch.cuda.get_device_name(0), autotune.library_hash())
+    cache = autotune.TuneCache(args.tune_cache)
+    if cache.get(sig) is not None:
+        hit = cache.get(sig)
+        return {**hit, "cached": True, "signature": sig}
+    ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=ri.batch.n,
+                     log_capacity=n_log, mode=hm.HETM_MODE_GRAPH, async_merge=True)
+    b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
+    host = hm.pinned(N * 4)
+    host.numpy()[:] = ri.init.view(np.uint8)
+    base = hm.to_device(ri.log, dev)
+    log_t = base.clone()
+    shift = [0]
+
+    def run_round():
+        log_t.copy_(base)
+        log_t.view(torch.int64).view(-1, 2)[:, 1].add_(shift[0])   # timestamps past the last round's
+        shift[0] += n_log
+        ctx.round(b, log_t, n_log, host)
+
+    def sync():
+        ctx.sync()
+        torch.cuda.synchronize()
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    res = autotune.tune_exec_workgroups(ctx.set_exec_workgroups, run_round, cus, sig=sig, cache=cache, sync=sync)
+    ctx.close()
+    return {**res, "signature": sig}
+
+
 def large_forms(args, hm, wl, torch, ri, dev) -> dict:
     """The large configuration in the batched, graph-with-merge and plain forms,
     inputs resident in HBM."""
@@ -667,6 +706,10 @@ def main():
     ap.add_argument("--p-hot", type=float, default=0.5)
     ap.add_argument("--stripe", type=int, default=1)
     ap.add_argument("--exec-wg", type=int, default=0, help="transaction-kernel workgroups (0 = one per CU)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the workgroup tuner (one workgroup per CU unless --exec-wg is given)")
+    ap.add_argument("--tune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "hetm", "tuned.json"),
+                    help="JSON file of tuned workgroup counts by workload signature")
     ap.add_argument("--legs", default="ingest,small,conflict,early,bank,cache,served,cpu",
                     help="comma list of legs beside the headline (ingest, small, conflict, early, bank, cache, "
                          "served, cpu)")
@@ -714,6 +757,12 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    tuned = None
+    if args.exec_wg == 0 and not args.no_tune:
+        log("tuning the transaction kernel's workgroups ...")
+        tuned = tune_exec(args, hm, torch, ri, dev)
+        args.exec_wg = int(tuned["exec_workgroups"])
+        log(f"  {args.exec_wg} workgroups ({'cached' if tuned['cached'] else 'measured'})")
     large = large_forms(args, hm, wl, torch, ri, dev)
     bat, plain = large["batched"], large["plain"]
     out = {
@@ -727,6 +776,10 @@ def main():
                            "inputs resident in HBM"},
         **{k: v for k, v in bat.items() if k not in ("value", "ms_per_step")},
         "graph_sync_merge": large["graph_sync_merge"], "plain": plain,
+        "autotune": ({"signature": tuned["signature"], "exec_workgroups": tuned["exec_workgroups"],
+                      "cached": tuned["cached"],
+                      "table_ms": {str(r["exec_workgroups"]): round(1e3 * r["median_s"], 4) for r in tuned["table"]}}
+                     if tuned else {"exec_workgroups": args.exec_wg, "tuned": False}),
         "batched_vs_plain": bat["value"] / plain["value"],
     }
     va = n_log * VALIDATE_APPLY_BYTES_PER_ENTRY / (plain["us_validate"] * 1e-6) / 1e9

@@ -1,107 +1,123 @@
-"""Autotuner for the SHeTM round on one GPU.
+"""Launch-width tuner for the transaction kernel, cached per workload.
 
-Picks, by measurement on a sample of the caller's workload, the three knobs
-of the round that trade off against each other:
+The persistent transaction kernel's grid (workgroups of 4 waves) trades
+memory-level parallelism against local conflicts: more waves keep more slot
+reads in flight but overlap more transactions, which raises local retries
+and the line-request load on the L2.  Which width wins depends on the
+workload (words, batch size, hot fraction, operations per transaction) and on
+the library's own kernels, so it is measured: whole rounds of the caller's
+workload are timed at a few widths around one workgroup per compute unit and
+the fastest is kept.
 
-* workgroups of the transaction kernel -- more lanes hide more memory
-  latency but overlap more transactions (more local aborts, more cache
-  turnover between a transaction's first read and its revalidation);
-* lock stripe S -- smaller lock tables, more false local conflicts;
-* granule G -- larger granules shrink the bitmaps and their atomics but
-  copy more bytes over the host link at merge time and raise false
-  inter-device conflicts.
-
-Each (G, S) pair gets its own scratch context (they are allocation-time
-parameters); workgroup counts are swept on that context with
-``hetm_set_exec_workgroups``.  The score is committed transactions per
-second of whole double-buffered rounds.  Results are cached by a workload
-signature in a JSON file next to this module.
+Results are cached by a signature of the workload's shape, the device name
+and a hash of the library's sources, so a changed kernel never reuses a
+stale choice.  The granule and the lock stripe are not tuned: the granule
+sets how precisely inter-device conflicts are detected and the stripe how
+many false local conflicts arise, so both belong to the workload.
 """
 from __future__ import annotations
 
+import glob
 import hashlib
 import json
 import os
+import statistics
 import time
+from typing import Callable, Iterable
 
-import numpy as np
-
-from . import hetm as hm
-
-CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_configs.json")
+PKG = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hetm", "tuned.json")
 
 
-def signature(n_words: int, word_bytes: int, program: int, batch, n_log: int) -> str:
-    L = np.diff(batch.offsets.astype(np.int64)) if hasattr(batch, "offsets") else np.zeros(1)
-    nw = batch.n_writes if hasattr(batch, "n_writes") else np.zeros(1)
-    key = (n_words, word_bytes, program, batch.n, n_log, int(L.sum()), int(np.asarray(nw).sum()))
-    return hashlib.sha256(repr(key).encode()).hexdigest()[:16]
+def library_hash() -> str:
+    """Hash of the library's HIP and host sources and its public header."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(PKG, "csrc", "*")))
+    files.append(os.path.join(os.path.dirname(PKG), "include", "hetm.h"))
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def load(sig: str) -> dict | None:
-    try:
-        return json.load(open(CACHE)).get(sig)
-    except (OSError, ValueError):
-        return None
+def signature(workload: dict, device: str, sources: str) -> str:
+    """A key for one workload shape on one device with one build of the
+    library; independent of the dict's insertion order."""
+    blob = json.dumps({"workload": workload, "device": device, "sources": sources}, sort_keys=True)
+    return hashlib.sha256(blob.encode()).hexdigest()[:16]
 
 
-def _store(sig: str, entry: dict) -> None:
-    try:
-        d = json.load(open(CACHE))
-    except (OSError, ValueError):
-        d = {}
-    d[sig] = entry
-    tmp = CACHE + ".tmp"
-    with open(tmp, "w") as f:
-        json.dump(d, f, indent=1, sort_keys=True)
-    os.replace(tmp, CACHE)
+class TuneCache:
+    """A JSON file of signature -> tuned entry.  A missing or unreadable
+    file reads as empty; writes replace the file atomically."""
+
+    def __init__(self, path: str = DEFAULT_CACHE):
+        self.path = path
+
+    def _load(self) -> dict:
+        try:
+            with open(self.path) as f:
+                d = json.load(f)
+            return d if isinstance(d, dict) else {}
+        except (OSError, ValueError):
+            return {}
+
+    def get(self, sig: str) -> dict | None:
+        return self._load().get(sig)
+
+    def put(self, sig: str, entry: dict) -> None:
+        d = self._load()
+        d[sig] = entry
+        os.makedirs(os.path.dirname(self.path) or ".", exist_ok=True)
+        tmp = f"{self.path}.{os.getpid()}.tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
 
 
-def tune(init: np.ndarray, program: int, batch, log: np.ndarray, granules=(16, 64), stripes=(1, 2),
-         workgroups=(256, 384, 512, 768, 1024, 2048), rounds: int = 3, max_ops: int = 16,
-         store: bool = True, verbose: bool = False) -> dict:
-    """Times `rounds` whole rounds for every candidate and returns the best
-    configuration with the full table.  `log` is one round's host log; each
-    timed round re-applies it with timestamps shifted past the previous."""
-    import torch
-    N, W = init.shape[0], init.itemsize
-    n_log = log.shape[0]
-    sig = signature(N, W, program, batch, n_log)
-    dev = "cuda:0"
-    host = hm.pinned(N * W)
-    host.numpy()[:] = init.view(np.uint8)
-    base = hm.to_device(log, dev)
-    ts_col = 1 if W == 4 else 2
+def pick(candidates: Iterable[int], measure: Callable[[int], float], repeats: int = 3) -> tuple[int, list[dict]]:
+    """Measures each candidate `repeats` times (seconds per round) and returns
+    the one with the lowest median, the smaller on a tie, with the table."""
     table = []
-    for G in granules:
-        for S in stripes:
-            ctx = hm.Context(N, W, G, init=init, stripe=S, max_ops=max_ops, batch_capacity=batch.n,
-                             log_capacity=max(n_log, 1), mode=hm.HETM_MODE_GRAPH, async_merge=True)
-            b = hm.Batch(program, batch, dev)
-            shift = 0
-            for wg in workgroups:
-                ctx.set_exec_workgroups(wg)
-                times, committed, retries = [], 0, 0
-                for r in range(rounds + 1):
-                    lg = base.clone()
-                    lg.view(torch.int64).view(-1, ts_col + 1)[:, ts_col].add_(shift)
-                    shift += n_log
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    res = ctx.round(b, lg, n_log, host)
-                    ctx.sync()
-                    if r:                      # the first round warms up (graph capture)
-                        times.append(time.perf_counter() - t0)
-                        committed += res.n_committed
-                        retries += res.n_local_retries
-                row = {"granule": G, "stripe": S, "workgroups": wg, "round_ms": 1e3 * float(np.mean(times)),
-                       "txn_per_s": committed / float(np.sum(times)), "retries_per_round": retries / rounds}
-                table.append(row)
-                if verbose:
-                    print(row, flush=True)
-            ctx.close()
-    best = max(table, key=lambda r: r["txn_per_s"])
-    entry = {"best": best, "table": table}
-    if store:
-        _store(sig, entry)
-    return entry
+    for c in candidates:
+        times = [measure(c) for _ in range(repeats)]
+        table.append({"exec_workgroups": c, "median_s": statistics.median(times), "min_s": min(times)})
+    best = min(table, key=lambda r: (r["median_s"], r["exec_workgroups"]))
+    return best["exec_workgroups"], table
+
+
+def candidates_for(cus: int, fractions: Iterable[float] = (0.5, 0.75, 1.0, 1.5, 2.0)) -> list[int]:
+    return sorted({max(1, int(round(f * cus))) for f in fractions})
+
+
+def tune_exec_workgroups(set_workgroups: Callable[[int], None], run_round: Callable[[], None], cus: int,
+                         sig: str | None = None, cache: TuneCache | None = None, repeats: int = 3,
+                         fractions: Iterable[float] = (0.5, 0.75, 1.0, 1.5, 2.0),
+                         sync: Callable[[], None] = lambda: None,
+                         timer: Callable[[], float] = time.perf_counter) -> dict:
+    """Returns {"exec_workgroups", "table", "cached"} and leaves the context
+    set to the chosen width.  run_round runs one whole round of the workload
+    (returning when the host has its outcome); sync waits for anything it
+    left in flight.  A cached entry for `sig` is used without measuring."""
+    if cache is not None and sig is not None:
+        hit = cache.get(sig)
+        if hit is not None and "exec_workgroups" in hit:
+            set_workgroups(int(hit["exec_workgroups"]))
+            return {**hit, "cached": True}
+
+    def measure(wg: int) -> float:
+        set_workgroups(wg)
+        run_round()                  # the first round at a new width warms it up
+        sync()
+        t0 = timer()
+        run_round()
+        sync()
+        return timer() - t0
+
+    best, table = pick(candidates_for(cus, fractions), measure, repeats)
+    set_workgroups(best)
+    entry = {"exec_workgroups": best, "table": table}
+    if cache is not None and sig is not None:
+        cache.put(sig, entry)
+    return {**entry, "cached": False}
