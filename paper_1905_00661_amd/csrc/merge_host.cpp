@@ -145,7 +145,7 @@ struct MergeWorker {
                 if (q.empty()) return;
                 j = q.front();
             }
-            const int e = hipEventSynchronize(j.ready) == hipSuccess ? HETM_OK : HETM_EDEVICE;
+            const int e = !j.ready || hipEventSynchronize(j.ready) == hipSuccess ? HETM_OK : HETM_EDEVICE;
             const auto t0 = std::chrono::steady_clock::now();
             if (e == HETM_OK) pool.scatter(j);
             const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();

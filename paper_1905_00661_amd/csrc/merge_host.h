@@ -10,7 +10,7 @@
 // each gets a sequence number.
 #pragma once
 
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include <cstdint>
 
@@ -23,8 +23,10 @@ MergeWorker *merge_worker_create();
 // Waits for every queued job, then stops the thread.
 void merge_worker_destroy(MergeWorker *w);
 // After `ready` completes, copies granule k of `data` (gbytes each, packed)
-// to host + ids[k] * gbytes, clipped to total_bytes.  Returns the job's
-// sequence number (> 0), or 0 if the job could not be queued.
+// to host + ids[k] * gbytes, clipped to total_bytes.  A null `ready` is a
+// job whose data is in place already (host-only; nothing to wait for).
+// Returns the job's sequence number (> 0), or 0 if the job could not be
+// queued.
 uint64_t merge_submit(MergeWorker *w, hipEvent_t ready, const uint32_t *ids, const uint8_t *data, uint64_t n,
                       uint8_t *host, uint64_t gbytes, uint64_t total_bytes);
 // Blocks until job `seq` (and all before it) is done; HETM_OK or the first

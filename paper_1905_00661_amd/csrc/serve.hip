@@ -15,6 +15,7 @@
 
 #include "hetm.h"
 #include "hetm_ctx.h"
+#include "host_pool.h"
 
 namespace {
 
@@ -26,73 +27,6 @@ constexpr uint64_t kServePushEntries = 48 * 1024 / sizeof(hetm_log_entry4);
 using clk = std::chrono::steady_clock;
 
 double seconds_since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
-
-// Persistent helper threads of the serving loop: run(n, grain, f) cuts
-// [0, n) into up to (helpers + 1) slices of at least `grain` items and runs
-// f(lo, hi) on each, slice 0 on the calling thread.  Threads that cannot be
-// started are simply not there (fewer slices).
-struct Pool {
-    static constexpr unsigned kMaxThreads = 12;
-    std::vector<std::thread> th;
-    std::mutex m;
-    std::condition_variable cv_go, cv_done;
-    const std::function<void(uint64_t, uint64_t)> *fn = nullptr;
-    uint64_t n = 0, per = 0, gen = 0;
-    unsigned parts = 0, pending = 0;
-    bool stop = false;
-
-    void start() {
-        try {
-            for (unsigned k = 0; k + 1 < kMaxThreads; ++k) th.emplace_back([this, k] { helper(k); });
-        } catch (...) {
-        }
-    }
-    void finish() {
-        {
-            std::lock_guard<std::mutex> l(m);
-            stop = true;
-        }
-        cv_go.notify_all();
-        for (auto &x : th) x.join();
-        th.clear();
-    }
-    void helper(unsigned k) {   // takes slice k + 1
-        uint64_t seen = 0;
-        for (;;) {
-            std::unique_lock<std::mutex> l(m);
-            cv_go.wait(l, [&] { return stop || gen != seen; });
-            if (stop) return;
-            seen = gen;
-            const auto *f = fn;
-            const uint64_t lo = std::min(n, (uint64_t)(k + 1) * per), hi = std::min(n, lo + per);
-            const bool mine = k + 1 < parts && lo < hi;
-            l.unlock();
-            if (mine) (*f)(lo, hi);
-            l.lock();
-            if (--pending == 0) cv_done.notify_one();
-        }
-    }
-    void run(uint64_t count, uint64_t grain, const std::function<void(uint64_t, uint64_t)> &f) {
-        const unsigned p = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(th.size() + 1, count / grain));
-        if (p == 1) {
-            f(0, count);
-            return;
-        }
-        {
-            std::lock_guard<std::mutex> l(m);
-            fn = &f;
-            n = count;
-            per = (count + p - 1) / p;
-            parts = p;
-            pending = (unsigned)th.size();
-            ++gen;
-        }
-        cv_go.notify_all();
-        f(0, std::min(count, per));
-        std::unique_lock<std::mutex> l(m);
-        cv_done.wait(l, [&] { return pending == 0; });
-    }
-};
 
 // Adds the time from its construction to its destruction to *acc (microseconds).
 struct Span {
@@ -124,7 +58,7 @@ struct Serve {
     hetm_serve_report *rep;
     hipStream_t upload = nullptr;
     RoundSet set[2];
-    Pool pool;
+    hetm::Pool pool;
     std::deque<uint64_t> requeue;
     uint64_t head = 0;            // next request not yet admitted
     uint64_t log_pos = 0;         // host log entries consumed
