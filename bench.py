@@ -625,7 +625,7 @@ def serve_sweep(args, hm, wl, torch) -> dict:
     bound_ms = args.serve_p99_bound_ms
     out = {"workload": f"2^27 u32 words, Poisson arrivals, lognormal lengths (median 4, max 64), 5% hot words, "
                        f"host log {per_round}/round, budget 2 GiB, granule 64; requests per point: rate x "
-                       f"{args.serve_seconds} s (at least 2^17, at most 2^21)",
+                       f"{args.serve_seconds} s (at least 2^17, at most 2^23)",
            "p99_bound_ms": bound_ms, "points": {}}
     forms = (("pipelined", True, dict(mode=1, async_merge=True)), ("plain", False, dict(mode=0)))
     call = [0]
@@ -645,7 +645,7 @@ def serve_sweep(args, hm, wl, torch) -> dict:
         ctx.sync()
         pts = {}
         for rate in rates:
-            n = int(min(max(rate * args.serve_seconds, 1 << 17), 1 << 21))
+            n = int(min(max(rate * args.serve_seconds, 1 << 17), 1 << 23))
             req = wl.c5_requests(g, n, rate, n_words=N, host_lo=host_lo)
             log(f"served {name}: {n} requests at {rate:g}/s ...")
             o = serve(ctx, host, req, pipelined)
@@ -721,7 +721,7 @@ def main():
     ap.add_argument("--small-rounds", type=int, default=200)
     ap.add_argument("--bank-rounds", type=int, default=3)
     ap.add_argument("--cache-rounds", type=int, default=3)
-    ap.add_argument("--serve-rates", default="1e6,3e6,1e7,3e7,1e8")
+    ap.add_argument("--serve-rates", default="1e6,1e7,3e7,1e8,2e8,3e8")
     ap.add_argument("--serve-seconds", type=float, default=0.25)
     ap.add_argument("--serve-p99-bound-ms", type=float, default=5.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)

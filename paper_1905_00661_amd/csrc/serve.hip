@@ -36,6 +36,21 @@ struct Span {
     ~Span() { *acc += std::chrono::duration<double, std::micro>(clk::now() - t).count(); }
 };
 
+// The requests of a round: the aborted ones it re-admits, by id, then a
+// contiguous run [lo, hi) of new arrivals (whose word lists, write counts
+// and ids are contiguous in the caller's arrays too).
+struct ReqList {
+    std::vector<uint64_t> ids;
+    uint64_t lo = 0, hi = 0;
+    uint64_t size() const { return ids.size() + (hi - lo); }
+    bool empty() const { return size() == 0; }
+    uint64_t operator[](uint64_t k) const { return k < ids.size() ? ids[k] : lo + (k - ids.size()); }
+    void clear() {
+        ids.clear();
+        lo = hi = 0;
+    }
+};
+
 // One set of round buffers: pinned packing area and device copies.
 struct RoundSet {
     uint32_t *h_off = nullptr, *h_idx = nullptr, *h_tid = nullptr;
@@ -46,7 +61,7 @@ struct RoundSet {
     uint8_t *d_nw = nullptr;
     hetm_log_entry4 *d_log = nullptr;
     hipEvent_t uploaded = nullptr;
-    std::vector<uint64_t> reqs;   // request ids in packing order
+    ReqList reqs;                 // the round's requests in packing order
     uint64_t n_ops = 0, n_log = 0;
     uint64_t log_end = 0;         // host log entries consumed once this round is in
 };
@@ -149,33 +164,66 @@ struct Serve {
                 return false;
             bytes += b;
             r.n_ops += req_ops(i);
-            r.reqs.push_back(i);
+            r.reqs.ids.push_back(i);
             return true;
         };
         while (!requeue.empty() && fits(requeue.front())) requeue.pop_front();
-        if (requeue.empty())
-            while (head < arr && fits(head)) ++head;
+        r.reqs.lo = r.reqs.hi = head;
+        if (!requeue.empty() || head >= arr) return;
+        // then the arrivals [head, j) for the largest j whose footprint fits
+        // (the CSR offsets are prefix sums of the operation counts, and every
+        // bound grows with j: a binary search)
+        auto ok = [&](uint64_t j) {
+            const uint64_t k = j - head, ops = sp.offsets[j] - sp.offsets[head];
+            return r.reqs.ids.size() + k <= sp.max_batch && r.n_ops + ops <= max_ops_round &&
+                   bytes + ops * 8 + k * 17 <= sp.mem_budget_bytes;
+        };
+        uint64_t lo = head, hi = arr;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo + 1) / 2;
+            if (ok(mid))
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        r.n_ops += sp.offsets[lo] - sp.offsets[head];
+        r.reqs.hi = lo;
+        head = lo;
     }
 
     // Packs the admitted requests and the host's next log chunk, uploads them.
     int pack_upload(RoundSet &r) {
-        const uint64_t n_req = r.reqs.size();
+        const ReqList &q = r.reqs;
+        const uint64_t nq = q.ids.size(), nr = q.hi - q.lo;
         uint32_t o = 0;
-        for (size_t k = 0; k < n_req; ++k) {     // offsets (sequential prefix sum)
+        for (size_t k = 0; k < nq; ++k) {        // re-admitted requests: a sequential prefix sum
             r.h_off[k] = o;
-            o += (uint32_t)req_ops(r.reqs[k]);
+            o += (uint32_t)req_ops(q.ids[k]);
         }
-        r.h_off[n_req] = o;
-        pool.run(n_req, 2048, [&](uint64_t lo, uint64_t hi) {
+        pool.run(nq, 2048, [&](uint64_t lo, uint64_t hi) {
             for (uint64_t k = lo; k < hi; ++k) {
-                const uint64_t i = r.reqs[k];
+                const uint64_t i = q.ids[k];
                 const uint32_t *src = sp.idx + sp.offsets[i];
                 uint32_t *dst = r.h_idx + r.h_off[k];
-                for (uint32_t j = 0, L = r.h_off[k + 1] - r.h_off[k]; j < L; ++j) dst[j] = src[j];
+                for (uint32_t j = 0, L = (uint32_t)req_ops(i); j < L; ++j) dst[j] = src[j];
                 r.h_nw[k] = sp.n_writes[i];
                 r.h_tid[k] = sp.tid[i];
             }
         });
+        // the run of arrivals: offsets shifted from the caller's, the rest copied as blocks
+        const uint64_t base = sp.offsets[q.lo], run_ops = sp.offsets[q.hi] - base;
+        const uint32_t o_run = o;
+        pool.run(nr + 1, 1 << 16, [&](uint64_t lo, uint64_t hi) {
+            for (uint64_t t = lo; t < hi; ++t) r.h_off[nq + t] = o_run + (uint32_t)(sp.offsets[q.lo + t] - base);
+        });
+        pool.run(run_ops, 1 << 18, [&](uint64_t lo, uint64_t hi) {
+            memcpy(r.h_idx + o_run + lo, sp.idx + base + lo, (hi - lo) * 4);
+        });
+        pool.run(nr, 1 << 16, [&](uint64_t lo, uint64_t hi) {
+            memcpy(r.h_nw + nq + lo, sp.n_writes + q.lo + lo, hi - lo);
+            memcpy(r.h_tid + nq + lo, sp.tid + q.lo + lo, (hi - lo) * 4);
+        });
+        o = o_run + (uint32_t)run_ops;
         r.n_log = std::min<uint64_t>(sp.host_log_per_round, sp.host_log_len - log_pos);
         if (starve_next) {       // the GPU lost too often: hold the host's writes back one round
             r.n_log = 0;
@@ -185,7 +233,7 @@ struct Serve {
         if (r.n_log) memcpy(r.h_log, sp.host_log + log_pos, r.n_log * sizeof(hetm_log_entry4));
         log_pos += r.n_log;
         r.log_end = log_pos;
-        const uint64_t n = r.reqs.size();
+        const uint64_t n = q.size();
         bool ok = hipMemcpyAsync(r.d_off, r.h_off, (n + 1) * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
                   hipMemcpyAsync(r.d_idx, r.h_idx, std::max<uint64_t>(o, 1) * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
                   hipMemcpyAsync(r.d_nw, r.h_nw, std::max<uint64_t>(n, 1), hipMemcpyHostToDevice, upload) == hipSuccess &&
@@ -246,8 +294,8 @@ struct Serve {
     // After a round's compute: conflict -> requeue; success -> copy results
     // out (unless fetch_after_round already did) and queue the requests for
     // commit stamping.
-    int settle(RoundSet &r, const hetm_round_result &res, std::deque<std::pair<uint64_t, std::vector<uint64_t>>> *pend,
-               std::vector<uint64_t> &done_now, bool fetched = false) {
+    int settle(RoundSet &r, const hetm_round_result &res, std::deque<std::pair<uint64_t, ReqList>> *pend,
+               std::vector<ReqList> &done_now, bool fetched = false) {
         const uint64_t rn = round_no++;
         if (rep->round_conflict && rn < rep->max_rounds) rep->round_conflict[rn] = res.conflict ? 1 : 0;
         if (rep->round_log_end && rn < rep->max_rounds) rep->round_log_end[rn] = r.log_end;
@@ -257,42 +305,57 @@ struct Serve {
             starve_next = true;
             losses = 0;
         }
+        const ReqList &q = r.reqs;
         if (res.conflict) {
             rep->conflicted_rounds++;
-            rep->requeued += r.reqs.size();
-            for (auto it = r.reqs.rbegin(); it != r.reqs.rend(); ++it) requeue.push_front(*it);
+            rep->requeued += q.size();
+            for (uint64_t i = q.hi; i-- > q.lo;) requeue.push_front(i);
+            for (auto it = q.ids.rbegin(); it != q.ids.rend(); ++it) requeue.push_front(*it);
             return HETM_OK;
         }
-        const uint64_t n = r.reqs.size();
+        const uint64_t n = q.size(), nq = q.ids.size();
         if (n && !fetched) {
             if (hipMemcpy(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost) != hipSuccess ||
                 hipMemcpy(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
                 return HETM_EDEVICE;
         }
-        pool.run(n, 2048, [&](uint64_t lo, uint64_t hi) {
-            for (uint64_t k = lo; k < hi; ++k) {
-                const uint64_t i = r.reqs[k];
-                if (rep->results) {
+        if (rep->results) {
+            pool.run(nq, 2048, [&](uint64_t lo, uint64_t hi) {
+                for (uint64_t k = lo; k < hi; ++k) {
                     const uint32_t *src = r.h_res + r.h_off[k];
-                    uint32_t *dst = rep->results + sp.offsets[i];
+                    uint32_t *dst = rep->results + sp.offsets[q.ids[k]];
                     for (uint32_t j = 0, L = r.h_off[k + 1] - r.h_off[k]; j < L; ++j) dst[j] = src[j];
                 }
-                if (rep->commit_seq) rep->commit_seq[i] = (rn << 32) | r.h_tick[k];
-            }
-        });
+            });
+            // the run's results are one block, in the caller's order
+            const uint64_t base = sp.offsets[q.lo], run_ops = sp.offsets[q.hi] - base;
+            pool.run(run_ops, 1 << 18, [&](uint64_t lo, uint64_t hi) {
+                memcpy(rep->results + base + lo, r.h_res + r.h_off[nq] + lo, (hi - lo) * 4);
+            });
+        }
+        if (rep->commit_seq)
+            pool.run(n, 1 << 14, [&](uint64_t lo, uint64_t hi) {
+                for (uint64_t k = lo; k < hi; ++k) rep->commit_seq[q[k]] = (rn << 32) | r.h_tick[k];
+            });
         const uint64_t seq = hetm::last_merge_seq(c);
         if (pend && seq)
-            pend->emplace_back(seq, r.reqs);
+            pend->emplace_back(seq, q);
         else
-            done_now.insert(done_now.end(), r.reqs.begin(), r.reqs.end());
+            done_now.push_back(q);
         return HETM_OK;
     }
 
-    void stamp(const std::vector<uint64_t> &reqs) {
+    void stamp(const ReqList &q) {
         const double now = seconds_since(t0);
-        for (uint64_t i : reqs) latency_us[i] = (now - sp.arrival_s[i]) * 1e6;
-        served += reqs.size();
+        for (uint64_t i : q.ids) latency_us[i] = (now - sp.arrival_s[i]) * 1e6;
+        pool.run(q.hi - q.lo, 1 << 15, [&](uint64_t lo, uint64_t hi) {
+            for (uint64_t i = q.lo + lo; i < q.lo + hi; ++i) latency_us[i] = (now - sp.arrival_s[i]) * 1e6;
+        });
+        served += q.size();
         last_commit_s = now;
+    }
+    void stamp(const std::vector<ReqList> &qs) {
+        for (const ReqList &q : qs) stamp(q);
     }
 
     void wait_for_arrival() {
@@ -329,7 +392,7 @@ struct Serve {
                 if ((err = hetm_round(c, &a, &res))) return err;
             }
             Span t(&rep->us_settle);
-            std::vector<uint64_t> done;
+            std::vector<ReqList> done;
             if ((err = settle(r, res, nullptr, done))) return err;
             stamp(done);
         }
@@ -337,7 +400,7 @@ struct Serve {
     }
 
     int run_pipelined() {
-        std::deque<std::pair<uint64_t, std::vector<uint64_t>>> pend;   // merge job, its requests
+        std::deque<std::pair<uint64_t, ReqList>> pend;   // merge job, its requests
         int cur = -1;            // set of the round on the GPU
         int nxt = -1;            // set packed and uploaded for the next round
         hetm_oplist_desc d[2];
@@ -377,7 +440,7 @@ struct Serve {
                     if ((err = hetm::issue_deferred_merge(c))) return err;
                 }
                 Span t(&rep->us_settle);
-                std::vector<uint64_t> done;
+                std::vector<ReqList> done;
                 if ((err = settle(set[cur], res, &pend, done, true))) return err;
                 stamp(done);
                 cur = -1;
