@@ -41,11 +41,28 @@ def test_c2_full_size(hm, wl):
 
 
 def test_c2_full_size_conflict(hm, wl):
+    """The same at hot fraction 0.9 and granule 64 with a conflicting log:
+    CPU wins, the round rolls back on the device from its undo log."""
     ri = wl.c2(p_hot=0.9, granule=64, conflict_rate=1.0, round_no=1)
     g = gpu_round(ri, mode=1, async_merge=True)
     o = oracle_round(ri, g["tickets"], g["H0"])
     assert_round_equal(g, o, ri)
     assert o["conflict"] == 1
+
+
+@pytest.mark.parametrize("conflict_rate", [0.0, 1.0])
+def test_c2_full_size_streamed(hm, wl, conflict_rate):
+    """The large round as a streamed round: its 2^20-entry log pushed in 16
+    chunks once execution has finished (early validation sees the whole read
+    set), then the tail.  Equal to the oracle in every output."""
+    from gpu_util import streamed_round
+    ri = wl.c2(p_hot=0.5, granule=16, conflict_rate=conflict_rate, round_no=2)
+    say(f"c2 full streamed, conflict rate {conflict_rate}: GPU round")
+    g = streamed_round(ri, chunks=16, where="device", sync_before_push=True, async_merge=True)
+    say("c2 full streamed: oracle round")
+    o = oracle_round(ri, g["tickets"], g["H0"])
+    assert_round_equal(g, o, ri)
+    assert o["conflict"] == int(conflict_rate) and g["res"].doomed == o["conflict"]
 
 
 def test_c3_full_size(hm, wl):
