@@ -22,10 +22,13 @@ Beside it, on the same GPU:
                             granule 64) and of its partitioned variant;
   conflict                  the large rounds with one log entry redirected
                             into the batch's read set in 10% of the rounds;
+  early                     early validation on and off over a sweep of
+                            conflicting-round fractions (streamed rounds);
   bank / cache              the bank-transfer and object-cache
                             configurations at full size (retries per commit);
   served                    the request loop swept over arrival rates, for the
-                            pipelined and one-round-at-a-time forms;
+                            pipelined form, the pipelined form with early
+                            validation, and one round at a time;
   cpu_baseline              the C oracle replaying whole large rounds on one
                             pinned host core.
 
@@ -612,9 +615,11 @@ def serve_sweep(args, hm, wl, torch) -> dict:
     """The serving configuration swept over arrival rates: open-loop Poisson
     arrivals of lognormal (median 4, capped at 64 ops) transactions over a
     2^27-word STMR with 5% hot words; rounds admitted under a 2 GiB budget;
-    the pipelined form (continuous batching, double-buffered merge) against
-    one round at a time.  Each form serves a warm-up stream first on its
-    context; every call's host log follows the previous call's."""
+    the pipelined form (continuous batching, double-buffered merge), the same
+    with streamed rounds whose host writes are shipped in 48 KB pieces and
+    validated early, and one round at a time.  Each form serves a warm-up
+    stream first on its context; every call's host log follows the previous
+    call's."""
     N = 1 << 27
     host_lo = N - N // 16
     g = wl.rng("c5", 0, 3)
@@ -627,28 +632,31 @@ def serve_sweep(args, hm, wl, torch) -> dict:
                        f"host log {per_round}/round, budget 2 GiB, granule 64; requests per point: rate x "
                        f"{args.serve_seconds} s (at least 2^17, at most 2^23)",
            "p99_bound_ms": bound_ms, "points": {}}
-    forms = (("pipelined", True, dict(mode=1, async_merge=True)), ("plain", False, dict(mode=0)))
+    forms = (("pipelined", True, dict(mode=1, async_merge=True), False),
+             ("pipelined_early", True, dict(mode=1, async_merge=True), True),
+             ("plain", False, dict(mode=0), False))
     call = [0]
 
-    def serve(ctx, host, req, pipelined):
+    def serve(ctx, host, req, pipelined, early):
         call[0] += 1
         later = hlog.copy()
         later["ts"] += np.uint64(call[0] << 40)
-        return ctx.serve(req["arrival_s"], req["batch"], host, later, per_round, 1 << 20, 2 << 30, pipelined)
+        return ctx.serve(req["arrival_s"], req["batch"], host, later, per_round, 1 << 20, 2 << 30, pipelined,
+                         early_validation=early)
 
-    for name, pipelined, kw in forms:
+    for name, pipelined, kw, early in forms:
         ctx = hm.Context(N, 4, 64, init=init, max_ops=64, batch_capacity=1 << 20, log_capacity=per_round, **kw)
         host = hm.pinned(N * 4)
         host.numpy()[:] = init.view(np.uint8)
         warm = wl.c5_requests(g, 1 << 17, 1e7, n_words=N, host_lo=host_lo)
-        serve(ctx, host, warm, pipelined)
+        serve(ctx, host, warm, pipelined, early)
         ctx.sync()
         pts = {}
         for rate in rates:
             n = int(min(max(rate * args.serve_seconds, 1 << 17), 1 << 23))
             req = wl.c5_requests(g, n, rate, n_words=N, host_lo=host_lo)
             log(f"served {name}: {n} requests at {rate:g}/s ...")
-            o = serve(ctx, host, req, pipelined)
+            o = serve(ctx, host, req, pipelined, early)
             ctx.sync()
             pts[f"{rate:g}"] = {"offered_txn_s": rate, "throughput_txn_s": o["throughput"],
                                 "p50_latency_us": o["p50_latency_us"], "p99_latency_us": o["p99_latency_us"],
