@@ -30,7 +30,9 @@ Beside it, on the same GPU:
                             pipelined form, the pipelined form with early
                             validation, and one round at a time;
   cpu_baseline              the C oracle replaying whole large rounds on one
-                            pinned host core.
+                            pinned host core;
+  sweep (not by default)    the large rounds over granules 16..4096 and hot
+                            fractions 0, 0.5, 0.9.
 
 Prints ONE JSON line.
 """
@@ -129,6 +131,14 @@ def cpu_info() -> dict:
     except OSError:
         pass
     return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def device_info(torch) -> dict:
+    """What the runtime reports about the GPU the figures come from."""
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "memory_GiB": round(p.total_memory / 2 ** 30, 1),
+            "l2_MiB_per_xcd": round(getattr(p, "L2_cache_size", 0) / 2 ** 20, 1) or None}
 
 
 def pct(a, q):
@@ -368,15 +378,19 @@ def small_round(args, hm, wl, torch, dev) -> dict:
             host.numpy()[:] = ri.init.view(np.uint8)
             b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
             torch.cuda.synchronize()
-            lat, conf = [], 0
+            lat, conf, steps = [], 0, []
             for r in range(rounds):
                 t1 = time.perf_counter()
                 rr = ctx.round(b, logs[r], n_log, host)
                 if r >= 20:
                     lat.append(1e6 * (time.perf_counter() - t1))
                     conf += rr.conflict
+                    steps.append(rr.as_dict())
             ctx.close()
             res_v[name] = {"p50_us": pct(lat, 50), "p99_us": pct(lat, 99), "conflict_rounds": conf}
+            if mode == hm.HETM_MODE_PLAIN:   # per step, from the round's HIP events
+                res_v[name]["p50_step_us"] = {k[3:]: pct([x[k] for x in steps], 50)
+                                              for k in ("us_exec", "us_validate", "us_merge")}
         out["as_named" if variant == "" else "partitioned"] = res_v
     out["workload"] = ("2^16 u32 words, 4096 txns of 4 reads + 4 writes, 10,000-entry host log, granule 64 "
                        "(as named every granule is read, so every round conflicts; partitioned: GPU lower half, "
@@ -425,6 +439,47 @@ def conflict_form(args, hm, wl, torch, ri, dev) -> dict:
             "p50_clean_round_ms": pct(lat_ok, 50), "p50_conflict_round_ms": pct(lat_cf, 50),
             "max_conflict_round_ms": max(lat_cf) if lat_cf else None,
             "form": "batched, CPU wins, r = 10% of rounds conflicting"}
+
+
+def sweep_form(args, hm, wl, torch, dev) -> dict:
+    """The large configuration over granules G in {16, 64, 256, 1024, 4096}
+    and hot fractions {0, 0.5, 0.9}: batched rounds (GRAPH, double-buffered
+    merge), 5 untimed and args.sweep_rounds timed per point, inputs in HBM."""
+    N, n_txn, n_log = 1 << args.log2_words, 1 << args.log2_txns, 1 << args.log2_log
+    pts = []
+    for p_hot in (0.0, 0.5, 0.9):
+        for G in (16, 64, 256, 1024, 4096):
+            ri = wl.c2(n_words=N, n_txn=n_txn, n_log=n_log, p_hot=p_hot, granule=G)
+            rounds = 5 + args.sweep_rounds
+            logs = shifted_logs(torch, hm, ri.log, n_log, rounds, dev)
+            host = hm.pinned(N * 4)
+            host.numpy()[:] = ri.init.view(np.uint8)
+            ctx = hm.Context(N, 4, G, init=ri.init, stripe=args.stripe, max_ops=16, batch_capacity=n_txn,
+                             log_capacity=n_log, mode=hm.HETM_MODE_GRAPH, exec_workgroups=args.exec_wg,
+                             async_merge=True)
+            b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch, dev)
+            for r in range(5):
+                ctx.round(b, logs[r], n_log, host)
+            ctx.sync()
+            torch.cuda.synchronize()
+            res = []
+            t0 = time.perf_counter()
+            for r in range(5, rounds):
+                res.append(ctx.round(b, logs[r], n_log, host).as_dict())
+            ctx.sync()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            ctx.close()
+            dirty = float(np.mean([x["n_dirty"] for x in res]))
+            pts.append({"granule": G, "p_hot": p_hot, "ms_per_round": 1e3 * el / args.sweep_rounds,
+                        "txn_per_s": sum(x["n_committed"] for x in res) / el, "dirty_granules": dirty,
+                        "merge_MB_per_round": dirty * G * 4 / 1e6,
+                        "retries_per_round": float(np.mean([x["n_local_retries"] for x in res]))})
+            log(f"sweep G={G} p_hot={p_hot}: {pts[-1]['ms_per_round']:.3f} ms/round, "
+                f"{pts[-1]['merge_MB_per_round']:.1f} MB merged")
+            del logs, host
+    return {"form": "batched (GRAPH, double-buffered merge), inputs in HBM", "rounds_per_point": args.sweep_rounds,
+            "points": pts}
 
 
 def early_form(args, hm, wl, torch, ri, dev) -> dict:
@@ -606,6 +661,7 @@ def cache_form(args, hm, wl, torch, dev) -> dict:
             "ms_per_round": 1e3 * float(np.mean([x["s"] for x in timed])),
             "retries_per_commit": sum(x["retries"] for x in timed) / max(committed, 1),
             "conflict_rounds": sum(x["conflict"] for x in rows), "warmup_s": warm_s, "rounds_timed": len(timed),
+            "host_tm_puts_s": keys.shape[0] / warm_s, "host_tm_threads": 8,
             "workload": "2^22 sets x 8 ways (2 GiB) warmed to 95%, 2^20 requests per round (95% GET / 5% PUT, "
                         "Zipf 0.99 over 2^26 keys, even keys), 2^14 host PUTs on odd keys, granule 128, "
                         "first round untimed"}
@@ -720,7 +776,8 @@ def main():
                     help="JSON file of tuned workgroup counts by workload signature")
     ap.add_argument("--legs", default="ingest,small,conflict,early,bank,cache,served,cpu",
                     help="comma list of legs beside the headline (ingest, small, conflict, early, bank, cache, "
-                         "served, cpu)")
+                         "served, cpu; also sweep, not run by default)")
+    ap.add_argument("--sweep-rounds", type=int, default=20)
     ap.add_argument("--early-rounds", type=int, default=20)
     ap.add_argument("--early-fracs", type=lambda v: [float(x) for x in v.split(",")], default="0,0.25,0.5,1",
                     help="fractions of conflicting rounds swept by the early-validation leg")
@@ -777,6 +834,7 @@ def main():
         "metric": METRIC, "value": bat["value"], "unit": "txn/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": bat["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "device": device_info(torch),
         "config": {"workload": f"large synthetic STMR: 2^{args.log2_words} u32 words, 2^{args.log2_txns} txns/batch "
                                f"(90% RO x16 reads, 10% 4RMW), hot 1% at p={args.p_hot}, host log "
                                f"2^{args.log2_log}, granule {G}, lock stripe {args.stripe}",
@@ -821,6 +879,9 @@ def main():
     if "conflict" in legs:
         log("conflicting rounds ...")
         out["conflict"] = conflict_form(args, hm, wl, torch, ri, dev)
+    if "sweep" in legs:
+        log("granule and hot-fraction sweep ...")
+        out["sweep"] = sweep_form(args, hm, wl, torch, dev)
     if "early" in legs:
         log("early validation on and off ...")
         out["early"] = early_form(args, hm, wl, torch, ri, dev)
