@@ -331,10 +331,13 @@ int hetm_round(hetm_ctx *ctx, const hetm_round_args *args, hetm_round_result *re
 int hetm_round_begin(hetm_ctx *ctx, const hetm_round_args *args);
 
 /* Appends n log entries (host or device memory, read until hetm_round_end
- * returns) to the open streamed round's log: they are copied into the
- * context's log buffer on a stream of their own, beside the running
- * transactions, and, under CPU wins, checked at once against the read set as
- * it stands -- without applying anything.  A hit dooms the round: the CPU
+ * returns) to the open streamed round's log.  Chunks in device memory that
+ * follow each other in one buffer (the first chunk, then each starting where
+ * the last ended) are read in place; any other chunk, and from then on every
+ * chunk of the round, is copied into the context's log buffer on a stream of
+ * its own, beside the running transactions.  Under CPU wins each chunk is
+ * checked at once against the read set as it stands -- without applying
+ * anything.  A hit dooms the round: the CPU
  * wins, so the transaction kernel stops at its next iteration and the
  * round's outcome is a conflict.  Early validation may miss a conflict (the
  * read set is still growing) but never invents one: hetm_round_end

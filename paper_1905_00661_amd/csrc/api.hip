@@ -117,6 +117,15 @@ const void *device_view(const void *p) {
     return nullptr;
 }
 
+bool is_device_memory(const void *p) {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice;
+}
+
 int push_args(hetm_ctx *c) {
     c->args.epoch = c->epoch;
     launch_set_args(c->args, c->dargs, c->stream);
@@ -561,13 +570,34 @@ int stream_push(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out) 
                     (unsigned long long)n, (unsigned long long)c->cfg.log_capacity);
     if (n) {
         hipStream_t es = c->early_stream;
+        const uint64_t eb = c->log_entry_bytes;
         // after the last round's tail (it read log_staging and cleared the
         // read set), beside this round's execution
         HIP_TRY(c, hipStreamWaitEvent(es, c->exec_queued, 0));
-        uint8_t *dst = (uint8_t *)c->log_staging + c->round_pushed * c->log_entry_bytes;
-        HIP_TRY(c, hipMemcpyAsync(dst, log, n * c->log_entry_bytes, hipMemcpyDefault, es));
+        const void *chunk;
+        const bool follows = c->round_pushed == 0 || (c->round_in_place &&
+                                                       log == (const uint8_t *)c->round_log + c->round_pushed * eb);
+        if (follows && is_device_memory(log)) {
+            // chunks in device memory that follow each other in one buffer
+            // are read in place, by the early check and by the round's tail
+            if (c->round_pushed == 0) {
+                c->round_log = log;
+                c->round_in_place = true;
+            }
+            chunk = log;
+        } else {
+            if (c->round_in_place && c->round_pushed)   // the chunks read in place so far join the buffer
+                HIP_TRY(c, hipMemcpyAsync(c->log_staging, c->round_log, c->round_pushed * eb, hipMemcpyDeviceToDevice,
+                                          es));
+            c->round_in_place = false;
+            c->round_log = c->log_staging;
+            uint8_t *dst = (uint8_t *)c->log_staging + c->round_pushed * eb;
+            HIP_TRY(c, hipMemcpyAsync(dst, log, n * eb, hipMemcpyDefault, es));
+            chunk = dst;
+        }
         if (c->args.policy == HETM_POLICY_CPU_WINS) {
-            launch_early_validate(dst, n, c->cfg.word_bytes, c->rs, c->args.gdiv, c->cfg.n_words, c->epoch, c->cnt, es);
+            launch_early_validate(chunk, n, c->cfg.word_bytes, c->rs, c->args.gdiv, c->cfg.n_words, c->epoch, c->cnt,
+                                  es);
             HIP_TRY(c, hipGetLastError());
         }
         HIP_TRY(c, hipEventRecord(c->early_ev, es));
@@ -600,6 +630,8 @@ int stream_begin(hetm_ctx *c, const hetm_round_args *r) {
     c->round_open = true;
     c->round_streamed = true;
     c->round_pushed = 0;
+    c->round_log = nullptr;
+    c->round_in_place = false;
     c->round_args = *r;
     c->round_hdev = hdev;
     c->round_buf = c->buf;
@@ -613,7 +645,7 @@ int stream_end(hetm_ctx *c, hetm_round_result *res) {
     // every pushed chunk is copied (and early-validated) before the tail
     if (c->early_used) HIP_TRY(c, hipStreamWaitEvent(s, c->early_ev, 0));
     c->early_used = false;
-    c->args.log = c->round_pushed ? c->log_staging : nullptr;
+    c->args.log = c->round_pushed ? c->round_log : nullptr;
     c->args.n_log = (uint32_t)c->round_pushed;
     int rc = launch_round_graph(c, c->sgraphs[c->args.policy][1], s);
     if (rc) return rc;

@@ -70,7 +70,9 @@ struct hetm_ctx {
     // early-validated on early_stream.
     RoundGraph sgraphs[2][2];
     bool round_streamed = false;
-    uint64_t round_pushed = 0;              // log entries pushed into log_staging
+    uint64_t round_pushed = 0;              // log entries pushed so far
+    const void *round_log = nullptr;        // where they are: the caller's device buffer, or log_staging
+    bool round_in_place = false;            // every chunk so far read in place (device memory, consecutive)
     hetm_round_args round_args{};           // the streamed round's arguments
     hipEvent_t exec_queued = nullptr;       // before the streamed round's execution graph
     hipStream_t cap_branch = nullptr;       // capture only: the merge branch

@@ -50,6 +50,48 @@ def test_streamed_round_parity(hm, wl, variant, chunks, where, async_merge):
     assert g["doomed_seen"] == o["conflict"]
 
 
+@pytest.mark.parametrize("variant", ["p", "w"])
+def test_streamed_mixed_chunks(hm, wl, variant):
+    """Chunks read in place (two consecutive slices of one device buffer),
+    then one from another device buffer and one from pinned memory, which
+    move the round's log into the context's buffer: the round equals the
+    oracle's."""
+    import torch
+    ri = wl.c1(variant)
+    n = ri.log.shape[0]
+    cuts = [0, n // 5, n // 2, (3 * n) // 4, n]
+    eb = ri.log.dtype.itemsize
+    raw = np.ascontiguousarray(ri.log).view(np.uint8).reshape(-1)
+    ctx = hm.Context(ri.n_words, 4, ri.granule, init=ri.init, batch_capacity=ri.batch.n, log_capacity=n,
+                     mode=hm.HETM_MODE_GRAPH, async_merge=True)
+    H0 = wl.host_replica(ri.init, ri.log)
+    host_t = hm.pinned(H0.nbytes)
+    host_t.numpy()[:] = H0.view(np.uint8)
+    b = hm.Batch(ri.program, ri.batch, ctx.dev)
+    a_dev = hm.to_device(ri.log, ctx.dev)                                    # parts 0 and 1, in place
+    b_dev = torch.from_numpy(raw[cuts[2] * eb:cuts[3] * eb].copy()).to(ctx.dev)   # part 2, elsewhere
+    c_pin = hm.pinned((cuts[4] - cuts[3]) * eb)                              # part 3, pinned
+    c_pin.numpy()[:] = raw[cuts[3] * eb:]
+    flags_t = torch.zeros(((n + 31) // 32) * 4, dtype=torch.uint8, device=ctx.dev)
+    ids_t = torch.zeros(ctx.n_granules * 4, dtype=torch.uint8, device=ctx.dev)
+    torch.cuda.synchronize()
+    ctx.round_begin(b, host_t, flags=flags_t, ids=ids_t)
+    torch.cuda.synchronize()
+    ctx.round_push(a_dev[:cuts[1] * eb], cuts[1])
+    ctx.round_push(a_dev[cuts[1] * eb:cuts[2] * eb], cuts[2] - cuts[1])
+    ctx.round_push(b_dev, cuts[3] - cuts[2])
+    ctx.round_push(c_pin, cuts[4] - cuts[3])
+    res = ctx.round_end()
+    ctx.sync()
+    g = {"res": res, "results": b.results_np(), "tickets": b.tickets_np(),
+         "S": ctx.read_state(hm.HETM_STATE_STMR).copy(), "H": host_t.numpy().view(np.uint32).copy(),
+         "flags": hm.tensor_to_numpy(flags_t, np.uint32),
+         "ids": hm.tensor_to_numpy(ids_t, np.uint32, int(res.n_dirty)), "H0": H0}
+    o = oracle_round(ri, g["tickets"], H0)
+    assert_round_equal(g, o, ri)
+    ctx.close()
+
+
 def test_streamed_gpu_wins(hm, wl):
     """GPU wins: pushed chunks are not early-validated (the GPU keeps its
     round); the conflicting host log is discarded as in hetm_round."""
