@@ -804,8 +804,12 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     TRY(dev_alloc(c, &c->log_bstart, (c->log_bins + 1) * 4ull));
     TRY(dev_alloc(c, &c->log_bwin, c->log_bins * 4ull));
     TRY(dev_alloc(c, &c->log_totals, c->log_bins * 4ull));
-    TRY(dev_alloc(c, &c->log_sorted, k.log_capacity * c->log_entry_bytes));
-    TRY(dev_alloc(c, &c->log_win, k.log_capacity * c->log_entry_bytes));
+    TRY(dev_alloc(c, &c->log_cursor, c->log_bins * 4ull));
+    // the one-pass layout gives every bucket a region of log_region entries
+    c->log_region = log_region_for(k.log_capacity, c->log_bins);
+    const uint64_t sorted_entries = std::max<uint64_t>(k.log_capacity, (uint64_t)c->log_bins * c->log_region);
+    TRY(dev_alloc(c, &c->log_sorted, sorted_entries * c->log_entry_bytes));
+    TRY(dev_alloc(c, &c->log_win, sorted_entries * c->log_entry_bytes));
     TRY(dev_alloc(c, &c->blocksums, nblocks * 4));
     TRY(dev_alloc(c, &c->blockruns, nblocks * 4));
     TRY(dev_alloc(c, &c->ids, nG * 4));
@@ -863,6 +867,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     hipStream_t s = c->stream;
     bool ok = (c->slot || hipMemsetAsync(c->locks, 0, nlocks * 8, s) == hipSuccess) &&
               hipMemsetAsync(c->rs, 0, nrw * 4, s) == hipSuccess &&
+              hipMemsetAsync(c->log_cursor, 0, c->log_bins * 4ull, s) == hipSuccess &&
               hipMemsetAsync(c->ws, 0, nbw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), s) == hipSuccess &&
               hipMemsetAsync(c->hot, 0, sizeof(HotCounters), s) == hipSuccess &&
@@ -897,6 +902,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     a.word_shift = c->slot ? 1u : 0u;
     a.blocksums = c->blocksums, a.blockruns = c->blockruns, a.ids_scratch = c->ids;
     a.log_hist = c->log_hist, a.log_bstart = c->log_bstart, a.log_bwin = c->log_bwin, a.log_totals = c->log_totals;
+    a.log_cursor = c->log_cursor, a.log_region = c->log_region;
     a.log_sorted = c->log_sorted, a.log_win = c->log_win;
     a.log_bins = c->log_bins, a.log_bin_bits = ilog2(c->log_bins), a.log_tiles = c->log_tiles;
     a.order = c->order;
@@ -936,8 +942,8 @@ int hetm_free(hetm_ctx *c) {
         if (e) (void)hipEventDestroy(e);
     if (c->ev_kernel) (void)hipEventDestroy(c->ev_kernel);
     void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->log_hist, c->log_bstart, c->log_bwin, c->log_totals,
-                   c->log_sorted, c->log_win, c->blocksums, c->blockruns, c->ids, c->order, c->tx_tab, c->tx_hot,
-                   c->tx_chain, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
+                   c->log_cursor, c->log_sorted, c->log_win, c->blocksums, c->blockruns, c->ids, c->order, c->undo,
+                   c->tx_tab, c->tx_hot, c->tx_chain, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->hargs) (void)hipHostFree(c->hargs);

@@ -93,7 +93,7 @@ struct DevCounters {
                                   // (0xFFFFFFFF before); every word the log wrote carries a version
                                   // at or above it, every word a transaction wrote one below
     uint32_t apply_ver;           // slot layout: version of the chunk being applied
-    uint32_t pad_;
+    uint32_t log_overflow;        // a bucket of the current chunk outgrew its region: exact bucketing
 };
 
 // Everything a kernel needs: constant context state plus the arguments of
@@ -110,6 +110,7 @@ struct DevArgs {
     uint32_t *log_bstart;   // [bins + 1] first position of each bucket
     uint32_t *log_bwin;     // [bins] winning entries (one per word) each bucket resolved
     uint32_t *log_totals;   // [bins] entries per bucket (scan pass)
+    uint32_t *log_cursor;   // [bins] entries placed in each bucket's region (bin pass; resolve clears)
     void *log_sorted;       // [log_capacity] the chunk's entries grouped by bucket
     void *log_win;          // [log_capacity] each bucket's winners, at the bucket's positions
     uint32_t *blocksums;    // compaction: per-block dirty counts, then offsets
@@ -140,8 +141,8 @@ struct DevArgs {
     uint32_t n_scan_blocks;
     uint32_t log_bins;      // buckets of a log chunk, a power of two
     uint32_t log_bin_bits;  // log2(log_bins)
-    uint32_t log_tiles;     // count / scatter blocks the launches are sized for (log_capacity / tile)
-    uint32_t pad1_;
+    uint32_t log_tiles;     // bin / scatter blocks the launches are sized for (log_capacity / tile)
+    uint32_t log_region;    // entries each bucket's region holds in the one-pass layout
     // ---- current call
     uint32_t program;
     uint32_t n_txns;
@@ -349,6 +350,11 @@ void launch_apply(const DevArgs *a, uint32_t word_bytes, uint32_t bins, hipStrea
 constexpr uint32_t kLogTile = 4096;             // entries per count / scatter block
 constexpr uint32_t kLogMaxBins = 4096;
 uint32_t log_bins_for(uint64_t log_capacity);
+// Entries each bucket's region holds in the one-pass layout: twice the
+// bucket's mean at capacity, plus a margin.
+inline uint32_t log_region_for(uint64_t log_capacity, uint32_t bins) {
+    return (uint32_t)(2 * ((log_capacity + bins - 1) / bins) + 64);
+}
 inline uint32_t log_tiles_for(uint64_t log_capacity) { return (uint32_t)((log_capacity + kLogTile - 1) / kLogTile); }
 void launch_compact(const DevArgs *a, uint32_t n_scan_blocks, hipStream_t s);
 void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t word_bytes, bool slot, hipStream_t s);

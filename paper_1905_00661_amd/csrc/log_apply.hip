@@ -2,15 +2,18 @@
 // gfx950, with the chunk bucketed by word so that every word's entries meet
 // in one workgroup's LDS and the apply needs no atomics on the timestamps.
 //
-//  count    : one coalesced read of the chunk.  Checks each entry's
+//  bin      : one coalesced read of the chunk.  Checks each entry's
 //             preconditions (word < N, watermark < ts < 2^63), tests it
 //             against the read set (one ballot gives 64 flag bits), keeps the
-//             chunk's largest and smallest ts, and counts its entries per
-//             bucket (a multiplicative hash of the word) in an LDS histogram
-//             written out per tile.
-//  scan     : turns the per-tile counts into each tile's first position in
-//             every bucket; the last block scans the bucket totals.
-//  scatter  : a second read of the chunk places every entry in its bucket.
+//             chunk's largest and smallest ts, counts its entries per bucket
+//             (a multiplicative hash of the word) in an LDS histogram, takes
+//             the tile's share of every bucket's region (twice the bucket's
+//             mean size) with one atomic per bucket, and places each entry
+//             there.
+//  scan,    : only if some bucket outgrew its region (a log that hammers a
+//  scatter    few words): the exact layout.  scan turns the per-tile counts
+//             into each tile's first position in every bucket; scatter reads
+//             the chunk again and places every entry.
 //  resolve  : one workgroup per bucket builds an LDS hash table keyed by word:
 //             the largest ts of each word and the one entry carrying it; a
 //             second entry at a word's winning ts, or a winning ts equal to
@@ -90,15 +93,26 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
     return v;
 }
 
-// ------------------------------------------------------------------- count
+// --------------------------------------------------------------------- bin
 template <typename E>
-__global__ __launch_bounds__(kTileThreads) void k_log_count(const DevArgs *__restrict__ a) {
+__global__ __launch_bounds__(kTileThreads) void k_log_bin(const DevArgs *__restrict__ a) {
     __shared__ uint32_t hist[kLogMaxBins];
+    __shared__ uint32_t base[kLogMaxBins];
     __shared__ unsigned long long s_mx[kTileThreads / kWave], s_mn[kTileThreads / kWave];
     __shared__ uint32_t s_cf[kTileThreads / kWave];
     const uint64_t n = a->n_log;
     const uint64_t t0 = (uint64_t)blockIdx.x * kLogTile;
     if (t0 >= n) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a->word_shift) {
+        // slot layout: the chunk's writes get a version of their own, above
+        // every version the round's transactions wrote (the undo log tells
+        // the two apart)
+        DevCounters *c0 = a->cnt;
+        const uint32_t v = __hip_atomic_fetch_add(&a->hot->clock.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (v >= kClockLimit) latch_error(c0, HETM_ECAPACITY, 0);
+        st_agent(&c0->apply_ver, v);
+        if (ld_agent(&c0->apply_floor) == 0xFFFFFFFFu) st_agent(&c0->apply_floor, v);
+    }
     const uint32_t B = a->log_bins, bbits = a->log_bin_bits;
     for (uint32_t i = threadIdx.x; i < B; i += kTileThreads) hist[i] = 0;
     __syncthreads();
@@ -141,17 +155,43 @@ __global__ __launch_bounds__(kTileThreads) void k_log_count(const DevArgs *__res
         }
     }
     bool conflict = false;
+    uint32_t bk[kPerThread], rank[kPerThread];
 #pragma unroll
     for (uint32_t j = 0; j < kPerThread; ++j) {
-        if (ok[j]) atomicAdd(&hist[bucket_of(e[j].word, bbits)], 1u);
+        bk[j] = bucket_of(e[j].word, bbits);
+        rank[j] = ok[j] ? atomicAdd(&hist[bk[j]], 1u) : 0u;
         const uint64_t m = __ballot(ok[j] && hit[j] != 0);
         const uint64_t kb = t0 + j * kTileThreads + wv * kWave;
         if (flags && lane == 0 && kb < n) store_bits(flags, kb, m, nflagw);
         conflict |= m != 0;
     }
     __syncthreads();
+    // the tile's counts (kept for the exact pass) and its share of each
+    // bucket's region, one atomic per bucket the tile touches
+    const uint32_t C = a->log_region;
     uint32_t *row = a->log_hist + (uint64_t)blockIdx.x * B;
-    for (uint32_t i = threadIdx.x; i < B; i += kTileThreads) row[i] = hist[i];
+    bool over = false;
+    for (uint32_t i = threadIdx.x; i < B; i += kTileThreads) {
+        const uint32_t h = hist[i];
+        row[i] = h;
+        uint32_t at = 0;
+        if (h) {
+            at = __hip_atomic_fetch_add(&a->log_cursor[i], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            over |= at + h > C;
+        }
+        base[i] = at;
+    }
+    if (__ballot(over) && lane == 0) st_agent(&cnt->log_overflow, 1u);
+    __syncthreads();
+    // every entry into its bucket's region (whatever does not fit is placed
+    // again by the exact pass)
+    E *out = (E *)a->log_sorted;
+#pragma unroll
+    for (uint32_t j = 0; j < kPerThread; ++j) {
+        if (!ok[j]) continue;
+        const uint32_t p = base[bk[j]] + rank[j];
+        if (p < C) out[(uint64_t)bk[j] * C + p] = e[j];
+    }
     // the chunk's ts range and conflict, staged (a chunk that fails a check
     // must not count) with at most one atomic per block and counter, and only
     // when it raises the value: same-address atomics serialize
@@ -209,18 +249,9 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *sh, uint32_
 __global__ __launch_bounds__(kThreads) void k_log_scan(const DevArgs *__restrict__ a) {
     __shared__ uint32_t sh[kThreads / kWave];
     DevCounters *cnt = a->cnt;
-    if (ld_agent(&cnt->error)) return;
+    if (!ld_agent(&cnt->log_overflow) || ld_agent(&cnt->error)) return;   // only for the exact layout
     const uint32_t B = a->log_bins, b = blockIdx.x;
     const uint32_t T = (uint32_t)((a->n_log + kLogTile - 1) / kLogTile);
-    if (b == 0 && threadIdx.x == 0 && a->word_shift) {
-        // slot layout: the chunk's writes get a version of their own, above
-        // every version the round's transactions wrote (the undo log tells
-        // the two apart)
-        const uint32_t v = __hip_atomic_fetch_add(&a->hot->clock.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-        if (v >= kClockLimit) latch_error(cnt, HETM_ECAPACITY, 0);
-        st_agent(&cnt->apply_ver, v);
-        if (ld_agent(&cnt->apply_floor) == 0xFFFFFFFFu) st_agent(&cnt->apply_floor, v);
-    }
     uint32_t *hist = a->log_hist;
     uint32_t base = 0;
     for (uint32_t t0 = 0; t0 < T; t0 += kThreads) {       // one column segment per thread and round
@@ -259,7 +290,7 @@ __global__ __launch_bounds__(kTileThreads) void k_log_scatter(const DevArgs *__r
     __shared__ uint32_t sh[kTileThreads / kWave];
     const uint64_t n = a->n_log;
     const uint64_t t0 = (uint64_t)blockIdx.x * kLogTile;
-    if (t0 >= n || ld_agent(&a->cnt->error)) return;
+    if (t0 >= n || !ld_agent(&a->cnt->log_overflow) || ld_agent(&a->cnt->error)) return;   // exact layout only
     const uint32_t B = a->log_bins, bbits = a->log_bin_bits;
     // entries move as u64 words (the word index is the low half of the first)
     constexpr uint32_t kQ = sizeof(E) / 8;
@@ -337,9 +368,25 @@ __global__ __launch_bounds__(kResThreads) void k_log_resolve(const DevArgs *__re
     __shared__ uint32_t s_nwin;
     DevCounters *cnt = a->cnt;
     const uint32_t b = blockIdx.x;
+    if (b >= a->log_bins) return;
+    // the bucket's region count, read and cleared for the next chunk (also
+    // when the chunk failed a check)
+    const uint32_t placed = ld_agent(&a->log_cursor[b]);
+    __syncthreads();
+    if (threadIdx.x == 0) a->log_cursor[b] = 0;
     // an empty chunk leaves the bucket starts unwritten (and apply stores nothing)
-    if (b >= a->log_bins || a->n_log == 0 || ld_agent(&cnt->error)) return;
-    const uint32_t s0 = a->log_bstart[b], c = a->log_bstart[b + 1] - s0;
+    if (a->n_log == 0 || ld_agent(&cnt->error)) return;
+    // the one-pass layout (bucket b's region), or the exact one if a bucket
+    // outgrew its region
+    uint32_t s0, c;
+    if (ld_agent(&cnt->log_overflow)) {
+        s0 = a->log_bstart[b];
+        c = a->log_bstart[b + 1] - s0;
+    } else {
+        s0 = b * a->log_region;
+        c = placed;
+        if (threadIdx.x == 0) a->log_bstart[b] = s0;     // for apply and the ts write-back
+    }
     if (c == 0) {
         if (threadIdx.x == 0) a->log_bwin[b] = 0;
         return;
@@ -480,6 +527,7 @@ __global__ __launch_bounds__(kThreads) void k_log_apply(const DevArgs *__restric
     st_agent(&cnt->chunk_max_ts, 0ull);
     st_agent(&cnt->chunk_min_inv, 0ull);
     st_agent(&cnt->log_ticket, 0u);
+    st_agent(&cnt->log_overflow, 0u);
 }
 
 // ----------------------------------------------------------- ts write-back
@@ -515,7 +563,7 @@ void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint3
             hipLaunchKernelGGL(k_log_ts<Entry4>, dim3(bins), dim3(kThreads), 0, s, a);
             hipLaunchKernelGGL(k_log_ts_done, dim3(1), dim3(64), 0, s, cnt);
         }
-        hipLaunchKernelGGL(k_log_count<Entry4>, dim3(tiles), dim3(kTileThreads), 0, s, a);
+        hipLaunchKernelGGL(k_log_bin<Entry4>, dim3(tiles), dim3(kTileThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_scan, dim3(bins), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_scatter<Entry4>, dim3(tiles), dim3(kTileThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_resolve<Entry4>, dim3(bins), dim3(kResThreads), 0, s, a);
@@ -524,7 +572,7 @@ void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint3
             hipLaunchKernelGGL(k_log_ts<Entry8>, dim3(bins), dim3(kThreads), 0, s, a);
             hipLaunchKernelGGL(k_log_ts_done, dim3(1), dim3(64), 0, s, cnt);
         }
-        hipLaunchKernelGGL(k_log_count<Entry8>, dim3(tiles), dim3(kTileThreads), 0, s, a);
+        hipLaunchKernelGGL(k_log_bin<Entry8>, dim3(tiles), dim3(kTileThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_scan, dim3(bins), dim3(kThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_scatter<Entry8>, dim3(tiles), dim3(kTileThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_resolve<Entry8>, dim3(bins), dim3(kResThreads), 0, s, a);

@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         c.undo_over = ld_agent(&cnt->undo_over);
         c.apply_floor = ld_agent(&cnt->apply_floor);
         c.apply_ver = 0;
-        c.pad_ = 0;
+        c.log_overflow = 0;
         c.doomed = ld_agent(&cnt->doomed);
         if (!err) {
             const uint64_t f = c.max_ts > c.floor_ts ? c.max_ts : c.floor_ts;
@@ -398,6 +398,7 @@ __global__ void k_clear_error(DevCounters *cnt) {
         st_agent(&cnt->chunk_max_ts, 0ull);
         st_agent(&cnt->chunk_min_inv, 0ull);
         st_agent(&cnt->log_ticket, 0u);
+        st_agent(&cnt->log_overflow, 0u);
     }
 }
 

@@ -125,7 +125,8 @@ def test_multi_chunk_step_api(hm, wl, orc):
 
 def test_chunk_with_crowded_buckets(hm, wl, orc):
     """A chunk whose entries pile onto a few words (buckets far above one
-    resolve pass), beside a uniform part, then a chunk older than it on the
+    resolve pass and far above their one-pass regions, so the exact layout
+    is built), beside a uniform part, then a chunk older than it on the
     same words: both match the oracle."""
     N = 1 << 16
     g = np.random.default_rng(21)
