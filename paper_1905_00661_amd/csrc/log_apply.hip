@@ -35,6 +35,8 @@
 // TS, at most the watermark, which no later entry can tie or lose to.
 #include "hetm_dev.h"
 
+#include <algorithm>
+
 namespace hetm {
 
 uint32_t log_bins_for(uint64_t log_capacity) {
@@ -250,19 +252,23 @@ __global__ __launch_bounds__(kThreads) void k_log_scan(const DevArgs *__restrict
     __shared__ uint32_t sh[kThreads / kWave];
     DevCounters *cnt = a->cnt;
     if (!ld_agent(&cnt->log_overflow) || ld_agent(&cnt->error)) return;   // only for the exact layout
-    const uint32_t B = a->log_bins, b = blockIdx.x;
+    const uint32_t B = a->log_bins;
     const uint32_t T = (uint32_t)((a->n_log + kLogTile - 1) / kLogTile);
     uint32_t *hist = a->log_hist;
-    uint32_t base = 0;
-    for (uint32_t t0 = 0; t0 < T; t0 += kThreads) {       // one column segment per thread and round
-        const uint32_t t = t0 + threadIdx.x;
-        const uint32_t v = t < T ? hist[(uint64_t)t * B + b] : 0u;
-        uint32_t total;
-        const uint32_t ex = block_scan<kThreads>(v, sh, &total);
-        if (t < T) hist[(uint64_t)t * B + b] = base + ex;
-        base += total;
+    // a small grid (the launch usually finds nothing to do): each block takes
+    // buckets blockIdx.x, blockIdx.x + gridDim.x, ...
+    for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
+        uint32_t base = 0;
+        for (uint32_t t0 = 0; t0 < T; t0 += kThreads) {       // one column segment per thread and round
+            const uint32_t t = t0 + threadIdx.x;
+            const uint32_t v = t < T ? hist[(uint64_t)t * B + b] : 0u;
+            uint32_t total;
+            const uint32_t ex = block_scan<kThreads>(v, sh, &total);
+            if (t < T) hist[(uint64_t)t * B + b] = base + ex;
+            base += total;
+        }
+        if (threadIdx.x == 0) a->log_totals[b] = base;
     }
-    if (threadIdx.x == 0) a->log_totals[b] = base;
 }
 
 // the buckets' first positions: an exclusive scan of the bucket totals by a
@@ -286,38 +292,44 @@ __device__ __forceinline__ void bucket_starts(const DevArgs *a, uint32_t *start,
 // also publishes them for the later passes).
 template <typename E>
 __global__ __launch_bounds__(kTileThreads) void k_log_scatter(const DevArgs *__restrict__ a) {
-    __shared__ uint32_t pos[kLogMaxBins + 1];
+    __shared__ uint32_t start[kLogMaxBins + 1];
+    __shared__ uint32_t pos[kLogMaxBins];
     __shared__ uint32_t sh[kTileThreads / kWave];
     const uint64_t n = a->n_log;
-    const uint64_t t0 = (uint64_t)blockIdx.x * kLogTile;
-    if (t0 >= n || !ld_agent(&a->cnt->log_overflow) || ld_agent(&a->cnt->error)) return;   // exact layout only
+    if (n == 0 || !ld_agent(&a->cnt->log_overflow) || ld_agent(&a->cnt->error)) return;   // exact layout only
     const uint32_t B = a->log_bins, bbits = a->log_bin_bits;
+    const uint32_t T = (uint32_t)((n + kLogTile - 1) / kLogTile);
+    bucket_starts(a, start, sh);
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i <= B; i += kTileThreads) a->log_bstart[i] = start[i];
     // entries move as u64 words (the word index is the low half of the first)
     constexpr uint32_t kQ = sizeof(E) / 8;
     const uint64_t *log = (const uint64_t *)a->log;
     uint64_t *out = (uint64_t *)a->log_sorted;
-    uint64_t v[kPerThread][kQ];
+    // a small grid (the launch usually finds nothing to do): each block takes
+    // tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+    for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
+        const uint64_t t0 = (uint64_t)t * kLogTile;
+        uint64_t v[kPerThread][kQ];
 #pragma unroll
-    for (uint32_t j = 0; j < kPerThread; ++j) {
-        const uint64_t k = t0 + j * kTileThreads + threadIdx.x;
-        const uint64_t *src = log + (k < n ? k : n - 1) * kQ;
+        for (uint32_t j = 0; j < kPerThread; ++j) {
+            const uint64_t k = t0 + j * kTileThreads + threadIdx.x;
+            const uint64_t *src = log + (k < n ? k : n - 1) * kQ;
 #pragma unroll
-        for (uint32_t q = 0; q < kQ; ++q) v[j][q] = src[q];
-    }
-    bucket_starts(a, pos, sh);
-    __syncthreads();
-    if (blockIdx.x == 0)
-        for (uint32_t i = threadIdx.x; i <= B; i += kTileThreads) a->log_bstart[i] = pos[i];
-    const uint32_t *row = a->log_hist + (uint64_t)blockIdx.x * B;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < B; i += kTileThreads) pos[i] += row[i];
-    __syncthreads();
+            for (uint32_t q = 0; q < kQ; ++q) v[j][q] = src[q];
+        }
+        const uint32_t *row = a->log_hist + (uint64_t)t * B;
+        for (uint32_t i = threadIdx.x; i < B; i += kTileThreads) pos[i] = start[i] + row[i];
+        __syncthreads();
 #pragma unroll
-    for (uint32_t j = 0; j < kPerThread; ++j) {
-        if (t0 + j * kTileThreads + threadIdx.x >= n) continue;
-        uint64_t *dst = out + (uint64_t)atomicAdd(&pos[bucket_of((uint32_t)v[j][0], bbits)], 1u) * kQ;
+        for (uint32_t j = 0; j < kPerThread; ++j) {
+            if (t0 + j * kTileThreads + threadIdx.x >= n) continue;
+            uint64_t *dst = out + (uint64_t)atomicAdd(&pos[bucket_of((uint32_t)v[j][0], bbits)], 1u) * kQ;
 #pragma unroll
-        for (uint32_t q = 0; q < kQ; ++q) dst[q] = v[j][q];
+            for (uint32_t q = 0; q < kQ; ++q) dst[q] = v[j][q];
+        }
+        __syncthreads();
     }
 }
 
@@ -556,6 +568,10 @@ __global__ void k_log_ts_done(DevCounters *cnt) {
 
 }  // namespace
 
+// blocks of the exact-layout passes, which run (and then in full) only when a
+// bucket outgrew its region
+constexpr uint32_t kExactGrid = 64;
+
 void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint32_t tiles, bool later_chunk,
                      DevCounters *cnt, hipStream_t s) {
     if (word_bytes == 4) {
@@ -564,8 +580,8 @@ void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint3
             hipLaunchKernelGGL(k_log_ts_done, dim3(1), dim3(64), 0, s, cnt);
         }
         hipLaunchKernelGGL(k_log_bin<Entry4>, dim3(tiles), dim3(kTileThreads), 0, s, a);
-        hipLaunchKernelGGL(k_log_scan, dim3(bins), dim3(kThreads), 0, s, a);
-        hipLaunchKernelGGL(k_log_scatter<Entry4>, dim3(tiles), dim3(kTileThreads), 0, s, a);
+        hipLaunchKernelGGL(k_log_scan, dim3(std::min(bins, kExactGrid)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_log_scatter<Entry4>, dim3(std::min(tiles, kExactGrid)), dim3(kTileThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_resolve<Entry4>, dim3(bins), dim3(kResThreads), 0, s, a);
     } else {
         if (later_chunk) {
@@ -573,8 +589,8 @@ void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint3
             hipLaunchKernelGGL(k_log_ts_done, dim3(1), dim3(64), 0, s, cnt);
         }
         hipLaunchKernelGGL(k_log_bin<Entry8>, dim3(tiles), dim3(kTileThreads), 0, s, a);
-        hipLaunchKernelGGL(k_log_scan, dim3(bins), dim3(kThreads), 0, s, a);
-        hipLaunchKernelGGL(k_log_scatter<Entry8>, dim3(tiles), dim3(kTileThreads), 0, s, a);
+        hipLaunchKernelGGL(k_log_scan, dim3(std::min(bins, kExactGrid)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL(k_log_scatter<Entry8>, dim3(std::min(tiles, kExactGrid)), dim3(kTileThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_resolve<Entry8>, dim3(bins), dim3(kResThreads), 0, s, a);
     }
 }
