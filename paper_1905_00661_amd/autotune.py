@@ -5,9 +5,12 @@ memory-level parallelism against local conflicts: more waves keep more slot
 reads in flight but overlap more transactions, which raises local retries
 and the line-request load on the L2.  Which width wins depends on the
 workload (words, batch size, hot fraction, operations per transaction) and on
-the library's own kernels, so it is measured: whole rounds of the caller's
-workload are timed at a few widths around one workgroup per compute unit and
-the fastest is kept.
+the library's own kernels, so it is measured: runs of back-to-back rounds of
+the caller's workload (the steady state, where a round's merge overlaps the
+next round) are timed at a few widths around one workgroup per compute unit.
+The fastest is kept only if it beats one workgroup per compute unit by a
+margin; differences below it are noise between runs, not a property of the
+width.
 
 Results are cached by a signature of the workload's shape, the device name
 and a hash of the library's sources, so a changed kernel never reuses a
@@ -76,14 +79,20 @@ class TuneCache:
         os.replace(tmp, self.path)
 
 
-def pick(candidates: Iterable[int], measure: Callable[[int], float], repeats: int = 3) -> tuple[int, list[dict]]:
+def pick(candidates: Iterable[int], measure: Callable[[int], float], repeats: int = 3,
+         default: int | None = None, margin: float = 0.0) -> tuple[int, list[dict]]:
     """Measures each candidate `repeats` times (seconds per round) and returns
-    the one with the lowest median, the smaller on a tie, with the table."""
+    the one with the lowest median, the smaller on a tie, with the table.
+    If `default` is a candidate and its median is within `margin` (a
+    fraction) of the best, the default is returned instead."""
     table = []
     for c in candidates:
         times = [measure(c) for _ in range(repeats)]
         table.append({"exec_workgroups": c, "median_s": statistics.median(times), "min_s": min(times)})
     best = min(table, key=lambda r: (r["median_s"], r["exec_workgroups"]))
+    for r in table:
+        if r["exec_workgroups"] == default and r["median_s"] <= best["median_s"] * (1.0 + margin):
+            return default, table
     return best["exec_workgroups"], table
 
 
@@ -95,11 +104,16 @@ def tune_exec_workgroups(set_workgroups: Callable[[int], None], run_round: Calla
                          sig: str | None = None, cache: TuneCache | None = None, repeats: int = 3,
                          fractions: Iterable[float] = (0.5, 0.75, 1.0, 1.5, 2.0),
                          sync: Callable[[], None] = lambda: None,
-                         timer: Callable[[], float] = time.perf_counter) -> dict:
+                         timer: Callable[[], float] = time.perf_counter,
+                         rounds: int = 8, warm: int = 2, margin: float = 0.02) -> dict:
     """Returns {"exec_workgroups", "table", "cached"} and leaves the context
     set to the chosen width.  run_round runs one whole round of the workload
-    (returning when the host has its outcome); sync waits for anything it
-    left in flight.  A cached entry for `sig` is used without measuring."""
+    (returning when the host has its outcome; work it leaves in flight, such
+    as an overlapped merge, may run on into the next round); sync waits for
+    all of it.  One measurement is `rounds` rounds back to back after `warm`
+    untimed ones, in seconds per round.  One workgroup per compute unit is
+    kept unless another width is faster by more than `margin`.  A cached
+    entry for `sig` is used without measuring."""
     if cache is not None and sig is not None:
         hit = cache.get(sig)
         if hit is not None and "exec_workgroups" in hit:
@@ -108,14 +122,15 @@ def tune_exec_workgroups(set_workgroups: Callable[[int], None], run_round: Calla
 
     def measure(wg: int) -> float:
         set_workgroups(wg)
-        run_round()                  # the first round at a new width warms it up
-        sync()
+        for _ in range(warm):        # rounds at a new width warm it up and fill the pipeline
+            run_round()
         t0 = timer()
-        run_round()
+        for _ in range(rounds):
+            run_round()
         sync()
-        return timer() - t0
+        return (timer() - t0) / rounds
 
-    best, table = pick(candidates_for(cus, fractions), measure, repeats)
+    best, table = pick(candidates_for(cus, fractions), measure, repeats, default=cus, margin=margin)
     set_workgroups(best)
     entry = {"exec_workgroups": best, "table": table}
     if cache is not None and sig is not None:

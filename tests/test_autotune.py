@@ -52,6 +52,14 @@ def test_pick_takes_the_lowest_median_then_the_smaller():
     assert table[0]["min_s"] == 1.0
 
 
+def test_pick_keeps_the_default_within_the_margin():
+    cost = {128: 1.00, 256: 1.015, 512: 1.2}
+    assert autotune.pick(cost, cost.get, repeats=1, default=256, margin=0.02)[0] == 256
+    assert autotune.pick(cost, cost.get, repeats=1, default=256, margin=0.01)[0] == 128
+    assert autotune.pick(cost, cost.get, repeats=1, default=384, margin=0.5)[0] == 128   # not a candidate
+    assert autotune.pick(cost, cost.get, repeats=1)[0] == 128
+
+
 def test_candidates_around_one_per_cu():
     assert autotune.candidates_for(256) == [128, 192, 256, 384, 512]
     assert autotune.candidates_for(1, (0.1, 1.0)) == [1]
@@ -74,14 +82,20 @@ class FakeRounds:
 
 def test_tune_measures_then_uses_the_cache(tmp_path):
     cache = autotune.TuneCache(str(tmp_path / "t.json"))
-    f = FakeRounds(lambda wg: abs(wg - 300) + 1.0)
+    f = FakeRounds(lambda wg: abs(wg - 180) + 1.0)
     r = autotune.tune_exec_workgroups(f.set_wg, f.run, 256, sig="s1", cache=cache, repeats=2, timer=lambda: f.t)
-    assert r["cached"] is False and r["exec_workgroups"] == 256      # nearest candidate to 300
-    assert f.sets[-1] == 256 and f.rounds == 5 * 2 * 2             # five widths, two repeats, warm + timed
-    assert cache.get("s1")["exec_workgroups"] == 256
+    assert r["cached"] is False and r["exec_workgroups"] == 192      # nearest candidate to 180, well ahead of 256
+    assert f.sets[-1] == 192 and f.rounds == 5 * 2 * (2 + 8)       # five widths, two repeats, 2 warm + 8 timed
+    assert [t["median_s"] for t in r["table"]] == [53.0, 13.0, 77.0, 205.0, 333.0]   # seconds per round
+    assert cache.get("s1")["exec_workgroups"] == 192
     g = FakeRounds(lambda wg: 1.0)
     r2 = autotune.tune_exec_workgroups(g.set_wg, g.run, 256, sig="s1", cache=cache, timer=lambda: g.t)
-    assert r2["cached"] is True and r2["exec_workgroups"] == 256
-    assert g.rounds == 0 and g.sets == [256]                        # no round run, the width still set
+    assert r2["cached"] is True and r2["exec_workgroups"] == 192
+    assert g.rounds == 0 and g.sets == [192]                        # no round run, the width still set
     r3 = autotune.tune_exec_workgroups(g.set_wg, g.run, 256, sig="s2", cache=cache, repeats=1, timer=lambda: g.t)
-    assert r3["cached"] is False and r3["exec_workgroups"] == 128   # all equal: the smallest
+    assert r3["cached"] is False and r3["exec_workgroups"] == 256   # all equal: one per CU stays
+    h = FakeRounds(lambda wg: 1.0 if wg == 192 else 1.01)
+    r4 = autotune.tune_exec_workgroups(h.set_wg, h.run, 256, sig="s3", repeats=1, timer=lambda: h.t)
+    assert r4["exec_workgroups"] == 256                              # 1% faster is within the margin
+    r5 = autotune.tune_exec_workgroups(h.set_wg, h.run, 256, sig="s4", repeats=1, timer=lambda: h.t, margin=0.005)
+    assert r5["exec_workgroups"] == 192
