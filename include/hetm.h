@@ -348,6 +348,23 @@ int hetm_round_begin(hetm_ctx *ctx, const hetm_round_args *args);
  * round open). */
 int hetm_round_push(hetm_ctx *ctx, const void *log, uint64_t n, uint32_t *doomed_out);
 
+/* Adds a batch to the open streamed round (the execution phase takes
+ * transactions for as long as it lasts, §IV-C): its n_txns transactions run
+ * after the round's earlier batches and before its tail, against the
+ * replica, read set, write set and version clock as those batches left
+ * them; their tickets continue the round's serial order (a round's tickets
+ * order all its batches together).  They belong to the round: validated,
+ * merged or rolled back with it, and reported in hetm_round_end's counts.
+ * Arguments as in hetm_submit_batch: program must be the round's (that of
+ * hetm_round_begin's batch, or of the first added batch if it had none);
+ * descs, results and tickets are device memory, read and written until
+ * hetm_round_end returns, each batch with its own results and tickets.
+ * n_txns = 0 does nothing.  Errors: EINVAL (another program, a null or
+ * malformed descriptor), ECAPACITY (n_txns > batch_capacity), ESTATE (no
+ * streamed round open); a rejected batch leaves the round as it was. */
+int hetm_round_add(hetm_ctx *ctx, uint32_t program, const void *descs, uint64_t n_txns, void *results,
+                   uint32_t *tickets);
+
 /* Ends the open streamed round: validates and applies every pushed entry as
  * one chunk (in push order: flags_bits of hetm_round_begin, if given, gets
  * bit k for the k-th pushed entry, ceil(entries pushed / 32) words), then
@@ -452,6 +469,13 @@ int hetm_read_words_noalloc(hetm_ctx *ctx, uint64_t first_word, uint64_t n_words
  * host's writes of the next round go into the host replica once that merge
  * has landed, while the GPU already runs the round.  pipelined = 0: one
  * round at a time through hetm_round (a context without async_merge).
+ * With round_period_us > 0 (pipelined only) a round is an execution phase
+ * of that length (§IV-C): the requests that arrive while it is open join it
+ * as further batches, each launched as soon as it is packed, behind the
+ * round's earlier batches (hetm_round_add), while the round's footprint
+ * and max_batch allow; then the round closes and is validated and merged
+ * as one.  Without it a round is one batch, and arrivals wait for the next
+ * round.
  *
  * A conflicting round is aborted (CPU wins, §IV-E) and its requests are
  * admitted again first.  Starvation guard (§IV-E): with starvation_limit K,
@@ -490,6 +514,13 @@ typedef struct {
                                            (§IV-D); a hit stops the round */
     uint32_t        push_entries;       /* entries per pushed piece; 0 = 3072
                                            (48 KB of 16-byte entries, §IV-D) */
+    double          round_period_us;    /* pipelined only: 0 = a round is one
+                                           batch; > 0 = a round stays open this
+                                           long after it starts (the execution
+                                           phase, §IV-C) and requests arriving
+                                           meanwhile join it as further batches
+                                           (hetm_round_add) while its budget
+                                           allows; the round then ends at once */
 } hetm_serve_spec;
 
 typedef struct {
@@ -511,6 +542,7 @@ typedef struct {
        own log commits, waiting for merges, waiting for arrivals */
     double    us_pack, us_wait_round, us_settle, us_host_commit, us_wait_merge, us_idle;
     uint64_t  starved_rounds;           /* rounds run without host writes by the starvation guard */
+    uint64_t  batches;                  /* batches launched (one per round without a round period) */
 } hetm_serve_report;
 
 int hetm_serve(hetm_ctx *ctx, const hetm_serve_spec *spec, void *host_replica, hetm_serve_report *rep);

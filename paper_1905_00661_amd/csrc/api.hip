@@ -639,6 +639,30 @@ int stream_begin(hetm_ctx *c, const hetm_round_args *r) {
     return HETM_OK;
 }
 
+// A further batch of the open streamed round, launched eagerly (not as a
+// replay of the execution graph, whose argument node the previous replay may
+// still be about to read): its argument upload and execution kernels queue
+// behind the round's earlier batches on the context's stream, so they read
+// the round's read set, clock and ticket counter where the earlier batches
+// left them.  The tail validates and merges all batches as one round.
+int stream_add(hetm_ctx *c, uint32_t program, const void *descs, uint64_t n, void *results, uint32_t *tickets) {
+    if (!c->round_open || !c->round_streamed) return fail(c, HETM_ESTATE, "no streamed round open");
+    if (c->round_args.n_txns && program != c->args.program)
+        return fail(c, HETM_EINVAL, "batch of program %u in a round of program %u", program, c->args.program);
+    if (n == 0) return HETM_OK;
+    const DevArgs keep = c->args;
+    int rc = set_batch_args(c, program, descs, n, results, tickets);
+    if (rc) {
+        c->args = keep;      // the round goes on as it was
+        return rc;
+    }
+    if ((rc = push_args(c))) return rc;
+    launch_exec(program, c->dargs, c->exec_wg, c->cfg.max_txn_ops, c->slot, c->cfg.batch_capacity, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    c->round_args.n_txns += n;
+    return HETM_OK;
+}
+
 int stream_end(hetm_ctx *c, hetm_round_result *res) {
     if (!c->round_open || !c->round_streamed) return fail(c, HETM_ESTATE, "no streamed round open");
     hipStream_t s = c->stream;
@@ -1087,6 +1111,12 @@ int hetm_round_begin(hetm_ctx *c, const hetm_round_args *r) {
 int hetm_round_push(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out) {
     if (!c) return HETM_EINVAL;
     return hetm::stream_push(c, log, n, doomed_out);
+}
+
+int hetm_round_add(hetm_ctx *c, uint32_t program, const void *descs, uint64_t n_txns, void *results,
+                   uint32_t *tickets) {
+    if (!c) return HETM_EINVAL;
+    return hetm::stream_add(c, program, descs, n_txns, results, tickets);
 }
 
 int hetm_round_end(hetm_ctx *c, hetm_round_result *res) {

@@ -138,6 +138,9 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res);
 // apply of every pushed chunk, merge, finish) and ends as round_end does.
 int stream_begin(hetm_ctx *c, const hetm_round_args *r);
 int stream_push(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out);
+// stream_add launches one more batch into the open streamed round, after
+// its earlier batches and before its tail.
+int stream_add(hetm_ctx *c, uint32_t program, const void *descs, uint64_t n_txns, void *results, uint32_t *tickets);
 int stream_end(hetm_ctx *c, hetm_round_result *res);
 // Double-buffered merge progress.  A successful round's copy to the host is
 // issued by the next round_begin (after it queues its graph) or by

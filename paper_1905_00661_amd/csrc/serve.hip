@@ -51,7 +51,15 @@ struct ReqList {
     }
 };
 
-// One set of round buffers: pinned packing area and device copies.
+// One batch of a round: its requests and where they sit in the round's
+// packing area (request k0 on, operation o0 on).
+struct Part {
+    ReqList reqs;
+    uint64_t k0 = 0, o0 = 0;
+};
+
+// One set of round buffers: pinned packing area and device copies.  A round
+// packs its batches one after the other into one set.
 struct RoundSet {
     uint32_t *h_off = nullptr, *h_idx = nullptr, *h_tid = nullptr;
     uint8_t *h_nw = nullptr;
@@ -61,9 +69,14 @@ struct RoundSet {
     uint8_t *d_nw = nullptr;
     hetm_log_entry4 *d_log = nullptr;
     hipEvent_t uploaded = nullptr;
-    ReqList reqs;                 // the round's requests in packing order
-    uint64_t n_ops = 0, n_log = 0;
+    std::vector<Part> parts;      // the round's batches in packing order
+    uint64_t n_req = 0, n_ops = 0, n_log = 0;   // packed so far
+    uint64_t bytes = 0;           // the round's device footprint so far
     uint64_t log_end = 0;         // host log entries consumed once this round is in
+    void clear() {
+        parts.clear();
+        n_req = n_ops = bytes = 0;
+    }
 };
 
 struct Serve {
@@ -72,6 +85,7 @@ struct Serve {
     void *host;
     hetm_serve_report *rep;
     hipStream_t upload = nullptr;
+    hipEvent_t batch_done[2] = {nullptr, nullptr};   // ends of the open round's last two batches
     RoundSet set[2];
     hetm::Pool pool;
     std::deque<uint64_t> requeue;
@@ -97,6 +111,8 @@ struct Serve {
         max_ops_round = mb * c->cfg.max_txn_ops;
         const uint64_t nl = std::max<uint64_t>(sp.host_log_per_round, 1);
         if (hipStreamCreateWithFlags(&upload, hipStreamNonBlocking) != hipSuccess) return HETM_EDEVICE;
+        for (auto &e : batch_done)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return HETM_EDEVICE;
         pool.start();
         for (auto &r : set) {
             bool ok = hipHostMalloc((void **)&r.h_off, (mb + 1) * 4, 0) == hipSuccess &&
@@ -139,6 +155,8 @@ struct Serve {
             if (r.uploaded) (void)hipEventDestroy(r.uploaded);
         }
         if (upload) (void)hipStreamDestroy(upload);
+        for (auto &e : batch_done)
+            if (e) (void)hipEventDestroy(e);
         pool.finish();
     }
 
@@ -148,98 +166,118 @@ struct Serve {
     }
     bool work_waiting() const { return !requeue.empty() || head < arrived(); }
 
-    // Admission: aborted requests first, then arrivals in order, while the
-    // round's footprint fits the budget.
-    void admit(RoundSet &r) {
-        const uint64_t fixed = sp.host_log_per_round * sizeof(hetm_log_entry4) +
-                               2ull * ((c->args.n_bm_words) * 4ull);
-        uint64_t bytes = fixed;
+    // Admission of one batch into round r: aborted requests first, then
+    // arrivals in order, while the round's footprint (its log and bitmaps,
+    // then each request's descriptor and results) fits the budget and its
+    // packing area has room.  Returns false if nothing was admitted.
+    bool admit(RoundSet &r) {
+        if (r.parts.empty())
+            r.bytes = sp.host_log_per_round * sizeof(hetm_log_entry4) + 2ull * ((c->args.n_bm_words) * 4ull);
+        Part p;
+        p.k0 = r.n_req;
+        p.o0 = r.n_ops;
+        uint64_t bytes = r.bytes, n_ops = r.n_ops;
         const uint64_t arr = arrived();
-        r.reqs.clear();
-        r.n_ops = 0;
         auto fits = [&](uint64_t i) {
             const uint64_t b = req_ops(i) * 8 + 17;
-            if (r.reqs.size() >= sp.max_batch || bytes + b > sp.mem_budget_bytes ||
-                r.n_ops + req_ops(i) > max_ops_round)
+            if (p.k0 + p.reqs.size() >= sp.max_batch || bytes + b > sp.mem_budget_bytes ||
+                n_ops + req_ops(i) > max_ops_round)
                 return false;
             bytes += b;
-            r.n_ops += req_ops(i);
-            r.reqs.ids.push_back(i);
+            n_ops += req_ops(i);
+            p.reqs.ids.push_back(i);
             return true;
         };
         while (!requeue.empty() && fits(requeue.front())) requeue.pop_front();
-        r.reqs.lo = r.reqs.hi = head;
-        if (!requeue.empty() || head >= arr) return;
-        // then the arrivals [head, j) for the largest j whose footprint fits
-        // (the CSR offsets are prefix sums of the operation counts, and every
-        // bound grows with j: a binary search)
-        auto ok = [&](uint64_t j) {
-            const uint64_t k = j - head, ops = sp.offsets[j] - sp.offsets[head];
-            return r.reqs.ids.size() + k <= sp.max_batch && r.n_ops + ops <= max_ops_round &&
-                   bytes + ops * 8 + k * 17 <= sp.mem_budget_bytes;
-        };
-        uint64_t lo = head, hi = arr;
-        while (lo < hi) {
-            const uint64_t mid = lo + (hi - lo + 1) / 2;
-            if (ok(mid))
-                lo = mid;
-            else
-                hi = mid - 1;
+        p.reqs.lo = p.reqs.hi = head;
+        if (requeue.empty() && head < arr) {
+            // then the arrivals [head, j) for the largest j whose footprint
+            // fits (the CSR offsets are prefix sums of the operation counts,
+            // and every bound grows with j: a binary search)
+            const uint64_t nq = p.reqs.ids.size();
+            auto ok = [&](uint64_t j) {
+                const uint64_t k = j - head, ops = sp.offsets[j] - sp.offsets[head];
+                return p.k0 + nq + k <= sp.max_batch && n_ops + ops <= max_ops_round &&
+                       bytes + ops * 8 + k * 17 <= sp.mem_budget_bytes;
+            };
+            uint64_t lo = head, hi = arr;
+            while (lo < hi) {
+                const uint64_t mid = lo + (hi - lo + 1) / 2;
+                if (ok(mid))
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const uint64_t k = lo - head, ops = sp.offsets[lo] - sp.offsets[head];
+            n_ops += ops;
+            bytes += ops * 8 + k * 17;
+            p.reqs.hi = lo;
+            head = lo;
         }
-        r.n_ops += sp.offsets[lo] - sp.offsets[head];
-        r.reqs.hi = lo;
-        head = lo;
+        if (p.reqs.empty()) return false;
+        r.n_req += p.reqs.size();
+        r.n_ops = n_ops;
+        r.bytes = bytes;
+        r.parts.push_back(std::move(p));
+        return true;
     }
 
-    // Packs the admitted requests and the host's next log chunk, uploads them.
+    // Packs the round's last admitted batch (and, with its first batch, the
+    // host's next log chunk) and uploads them.
     int pack_upload(RoundSet &r) {
-        const ReqList &q = r.reqs;
-        const uint64_t nq = q.ids.size(), nr = q.hi - q.lo;
-        uint32_t o = 0;
+        const Part &p = r.parts.back();
+        const ReqList &q = p.reqs;
+        const uint64_t nq = q.ids.size(), nr = q.hi - q.lo, k0 = p.k0;
+        uint32_t o = (uint32_t)p.o0;
         for (size_t k = 0; k < nq; ++k) {        // re-admitted requests: a sequential prefix sum
-            r.h_off[k] = o;
+            r.h_off[k0 + k] = o;
             o += (uint32_t)req_ops(q.ids[k]);
         }
         pool.run(nq, 2048, [&](uint64_t lo, uint64_t hi) {
             for (uint64_t k = lo; k < hi; ++k) {
                 const uint64_t i = q.ids[k];
                 const uint32_t *src = sp.idx + sp.offsets[i];
-                uint32_t *dst = r.h_idx + r.h_off[k];
+                uint32_t *dst = r.h_idx + r.h_off[k0 + k];
                 for (uint32_t j = 0, L = (uint32_t)req_ops(i); j < L; ++j) dst[j] = src[j];
-                r.h_nw[k] = sp.n_writes[i];
-                r.h_tid[k] = sp.tid[i];
+                r.h_nw[k0 + k] = sp.n_writes[i];
+                r.h_tid[k0 + k] = sp.tid[i];
             }
         });
         // the run of arrivals: offsets shifted from the caller's, the rest copied as blocks
         const uint64_t base = sp.offsets[q.lo], run_ops = sp.offsets[q.hi] - base;
         const uint32_t o_run = o;
         pool.run(nr + 1, 1 << 16, [&](uint64_t lo, uint64_t hi) {
-            for (uint64_t t = lo; t < hi; ++t) r.h_off[nq + t] = o_run + (uint32_t)(sp.offsets[q.lo + t] - base);
+            for (uint64_t t = lo; t < hi; ++t) r.h_off[k0 + nq + t] = o_run + (uint32_t)(sp.offsets[q.lo + t] - base);
         });
         pool.run(run_ops, 1 << 18, [&](uint64_t lo, uint64_t hi) {
             memcpy(r.h_idx + o_run + lo, sp.idx + base + lo, (hi - lo) * 4);
         });
         pool.run(nr, 1 << 16, [&](uint64_t lo, uint64_t hi) {
-            memcpy(r.h_nw + nq + lo, sp.n_writes + q.lo + lo, hi - lo);
-            memcpy(r.h_tid + nq + lo, sp.tid + q.lo + lo, (hi - lo) * 4);
+            memcpy(r.h_nw + k0 + nq + lo, sp.n_writes + q.lo + lo, hi - lo);
+            memcpy(r.h_tid + k0 + nq + lo, sp.tid + q.lo + lo, (hi - lo) * 4);
         });
         o = o_run + (uint32_t)run_ops;
-        r.n_log = std::min<uint64_t>(sp.host_log_per_round, sp.host_log_len - log_pos);
-        if (starve_next) {       // the GPU lost too often: hold the host's writes back one round
-            r.n_log = 0;
-            starve_next = false;
-            rep->starved_rounds++;
+        const bool first = r.parts.size() == 1;
+        if (first) {
+            r.n_log = std::min<uint64_t>(sp.host_log_per_round, sp.host_log_len - log_pos);
+            if (starve_next) {       // the GPU lost too often: hold the host's writes back one round
+                r.n_log = 0;
+                starve_next = false;
+                rep->starved_rounds++;
+            }
+            if (r.n_log) memcpy(r.h_log, sp.host_log + log_pos, r.n_log * sizeof(hetm_log_entry4));
+            log_pos += r.n_log;
+            r.log_end = log_pos;
         }
-        if (r.n_log) memcpy(r.h_log, sp.host_log + log_pos, r.n_log * sizeof(hetm_log_entry4));
-        log_pos += r.n_log;
-        r.log_end = log_pos;
-        const uint64_t n = q.size();
-        bool ok = hipMemcpyAsync(r.d_off, r.h_off, (n + 1) * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
-                  hipMemcpyAsync(r.d_idx, r.h_idx, std::max<uint64_t>(o, 1) * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
-                  hipMemcpyAsync(r.d_nw, r.h_nw, std::max<uint64_t>(n, 1), hipMemcpyHostToDevice, upload) == hipSuccess &&
-                  hipMemcpyAsync(r.d_tid, r.h_tid, std::max<uint64_t>(n, 1) * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
-                  (r.n_log == 0 || hipMemcpyAsync(r.d_log, r.h_log, r.n_log * sizeof(hetm_log_entry4),
-                                                  hipMemcpyHostToDevice, upload) == hipSuccess) &&
+        const uint64_t n = q.size(), o0 = p.o0, ops = o - o0;
+        bool ok = hipMemcpyAsync(r.d_off + k0, r.h_off + k0, (n + 1) * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
+                  (ops == 0 || hipMemcpyAsync(r.d_idx + o0, r.h_idx + o0, ops * 4, hipMemcpyHostToDevice, upload) ==
+                                   hipSuccess) &&
+                  hipMemcpyAsync(r.d_nw + k0, r.h_nw + k0, n, hipMemcpyHostToDevice, upload) == hipSuccess &&
+                  hipMemcpyAsync(r.d_tid + k0, r.h_tid + k0, n * 4, hipMemcpyHostToDevice, upload) == hipSuccess &&
+                  (!first || r.n_log == 0 ||
+                   hipMemcpyAsync(r.d_log, r.h_log, r.n_log * sizeof(hetm_log_entry4), hipMemcpyHostToDevice,
+                                  upload) == hipSuccess) &&
                   hipEventRecord(r.uploaded, upload) == hipSuccess;
         return ok ? HETM_OK : HETM_EDEVICE;
     }
@@ -265,12 +303,19 @@ struct Serve {
         return HETM_OK;
     }
 
+    // The descriptor of batch p of round r (offsets index the round's
+    // packing area, so every batch shares its word lists and results).
+    static hetm_oplist_desc part_desc(const RoundSet &r, const Part &p) {
+        return {r.d_off + p.k0, r.d_idx, r.d_nw + p.k0, r.d_tid + p.k0};
+    }
+
     hetm_round_args round_args(RoundSet &r, hetm_oplist_desc &d) {
-        d = {r.d_off, r.d_idx, r.d_nw, r.d_tid};
+        const Part &p = r.parts.front();
+        d = part_desc(r, p);
         hetm_round_args a{};
         a.program = HETM_PROG_OPLIST;
         a.descs = &d;
-        a.n_txns = r.reqs.size();
+        a.n_txns = p.reqs.size();
         a.results = r.d_res;
         a.tickets = r.d_tick;
         a.log = r.d_log;
@@ -280,13 +325,12 @@ struct Serve {
     }
 
     // Queues the copies of a round's results and tickets to pinned host
-    // memory right behind its graph, so they run before the round's merge
+    // memory behind its last batch, so they run before the round's merge
     // copy is queued (the merge copy would hold them back).
     int fetch_after_round(RoundSet &r) {
-        const uint64_t n = r.reqs.size();
-        if (!n) return HETM_OK;
-        if (hipMemcpyAsync(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-            hipMemcpyAsync(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        if (!r.n_req) return HETM_OK;
+        if ((r.n_ops && hipMemcpyAsync(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess) ||
+            hipMemcpyAsync(r.h_tick, r.d_tick, r.n_req * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
             return HETM_EDEVICE;
         return HETM_OK;
     }
@@ -300,48 +344,55 @@ struct Serve {
         if (rep->round_conflict && rn < rep->max_rounds) rep->round_conflict[rn] = res.conflict ? 1 : 0;
         if (rep->round_log_end && rn < rep->max_rounds) rep->round_log_end[rn] = r.log_end;
         rep->rounds++;
+        rep->batches += r.parts.size();
         losses = res.conflict ? losses + 1 : 0;
         if (sp.starvation_limit && losses >= sp.starvation_limit) {
             starve_next = true;
             losses = 0;
         }
-        const ReqList &q = r.reqs;
         if (res.conflict) {
+            // every batch of the round goes back, in admission order, ahead of what waits
             rep->conflicted_rounds++;
-            rep->requeued += q.size();
-            for (uint64_t i = q.hi; i-- > q.lo;) requeue.push_front(i);
-            for (auto it = q.ids.rbegin(); it != q.ids.rend(); ++it) requeue.push_front(*it);
+            rep->requeued += r.n_req;
+            for (auto pt = r.parts.rbegin(); pt != r.parts.rend(); ++pt) {
+                const ReqList &q = pt->reqs;
+                for (uint64_t i = q.hi; i-- > q.lo;) requeue.push_front(i);
+                for (auto it = q.ids.rbegin(); it != q.ids.rend(); ++it) requeue.push_front(*it);
+            }
             return HETM_OK;
         }
-        const uint64_t n = q.size(), nq = q.ids.size();
-        if (n && !fetched) {
-            if (hipMemcpy(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(r.h_tick, r.d_tick, n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        if (r.n_req && !fetched) {
+            if ((r.n_ops && hipMemcpy(r.h_res, r.d_res, r.n_ops * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+                hipMemcpy(r.h_tick, r.d_tick, r.n_req * 4, hipMemcpyDeviceToHost) != hipSuccess)
                 return HETM_EDEVICE;
         }
-        if (rep->results) {
-            pool.run(nq, 2048, [&](uint64_t lo, uint64_t hi) {
-                for (uint64_t k = lo; k < hi; ++k) {
-                    const uint32_t *src = r.h_res + r.h_off[k];
-                    uint32_t *dst = rep->results + sp.offsets[q.ids[k]];
-                    for (uint32_t j = 0, L = r.h_off[k + 1] - r.h_off[k]; j < L; ++j) dst[j] = src[j];
-                }
-            });
-            // the run's results are one block, in the caller's order
-            const uint64_t base = sp.offsets[q.lo], run_ops = sp.offsets[q.hi] - base;
-            pool.run(run_ops, 1 << 18, [&](uint64_t lo, uint64_t hi) {
-                memcpy(rep->results + base + lo, r.h_res + r.h_off[nq] + lo, (hi - lo) * 4);
-            });
-        }
-        if (rep->commit_seq)
-            pool.run(n, 1 << 14, [&](uint64_t lo, uint64_t hi) {
-                for (uint64_t k = lo; k < hi; ++k) rep->commit_seq[q[k]] = (rn << 32) | r.h_tick[k];
-            });
         const uint64_t seq = hetm::last_merge_seq(c);
-        if (pend && seq)
-            pend->emplace_back(seq, q);
-        else
-            done_now.push_back(q);
+        for (const Part &p : r.parts) {
+            const ReqList &q = p.reqs;
+            const uint64_t n = q.size(), nq = q.ids.size(), k0 = p.k0;
+            if (rep->results) {
+                pool.run(nq, 2048, [&](uint64_t lo, uint64_t hi) {
+                    for (uint64_t k = lo; k < hi; ++k) {
+                        const uint32_t *src = r.h_res + r.h_off[k0 + k];
+                        uint32_t *dst = rep->results + sp.offsets[q.ids[k]];
+                        for (uint32_t j = 0, L = r.h_off[k0 + k + 1] - r.h_off[k0 + k]; j < L; ++j) dst[j] = src[j];
+                    }
+                });
+                // the run's results are one block, in the caller's order
+                const uint64_t base = sp.offsets[q.lo], run_ops = sp.offsets[q.hi] - base;
+                pool.run(run_ops, 1 << 18, [&](uint64_t lo, uint64_t hi) {
+                    memcpy(rep->results + base + lo, r.h_res + r.h_off[k0 + nq] + lo, (hi - lo) * 4);
+                });
+            }
+            if (rep->commit_seq)
+                pool.run(n, 1 << 14, [&](uint64_t lo, uint64_t hi) {
+                    for (uint64_t k = lo; k < hi; ++k) rep->commit_seq[q[k]] = (rn << 32) | r.h_tick[k0 + k];
+                });
+            if (pend && seq)
+                pend->emplace_back(seq, q);
+            else
+                done_now.push_back(q);
+        }
         return HETM_OK;
     }
 
@@ -358,9 +409,10 @@ struct Serve {
         for (const ReqList &q : qs) stamp(q);
     }
 
-    void wait_for_arrival() {
+    // Sleeps until shortly before the next arrival, at most `cap` seconds.
+    void wait_for_arrival(double cap = 1e30) {
         if (head < sp.n_requests) {
-            const double dt = sp.arrival_s[head] - seconds_since(t0);
+            const double dt = std::min(sp.arrival_s[head] - seconds_since(t0), cap);
             if (dt > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(dt - 1e-4));
         }
     }
@@ -375,8 +427,8 @@ struct Serve {
             }
             {
                 Span t(&rep->us_pack);
-                admit(r);
-                if (r.reqs.empty()) return HETM_ECAPACITY;
+                r.clear();
+                if (!admit(r)) return HETM_ECAPACITY;    // a request larger than the budget
                 if ((err = pack_upload(r))) return err;
                 if (hipStreamSynchronize(upload) != hipSuccess) return HETM_EDEVICE;
             }
@@ -399,12 +451,24 @@ struct Serve {
         return HETM_OK;
     }
 
+    // Pipelined rounds: the next round is packed while the current one runs
+    // and starts as soon as it ends, beside its merge.  With a round period
+    // the round stays open that long after it starts (the execution phase,
+    // §IV-C), and requests that arrive meanwhile join it as further batches,
+    // each launched as soon as it is packed, while the round's budget and
+    // packing area have room; such rounds and those with early validation
+    // are streamed rounds.
     int run_pipelined() {
         std::deque<std::pair<uint64_t, ReqList>> pend;   // merge job, its requests
         int cur = -1;            // set of the round on the GPU
         int nxt = -1;            // set packed and uploaded for the next round
         hetm_oplist_desc d[2];
         hetm_round_args a[2];
+        const double period_s = sp.round_period_us * 1e-6;
+        const bool streamed = sp.early_validation || period_s > 0;
+        clk::time_point cur_start;
+        bool admitting = false;  // the open round still takes batches
+        uint64_t nb = 0;         // batches launched in the open round
         auto poll = [&](bool block) {
             while (!pend.empty()) {
                 if (block) {
@@ -418,22 +482,59 @@ struct Serve {
             return HETM_OK;
         };
         while (served < sp.n_requests) {
+            if (admitting) {
+                const double left = period_s - std::chrono::duration<double>(clk::now() - cur_start).count();
+                if (left > 0 && work_waiting()) {
+                    // one batch waits behind the running one: the next is
+                    // admitted once the batch before the last has finished,
+                    // so it takes everything that arrived meanwhile
+                    const hipError_t q = hipEventQuery(batch_done[nb & 1]);
+                    if (q == hipErrorNotReady) {
+                        Span t(&rep->us_idle);
+                        for (int k = 0; k < 256; ++k) __builtin_ia32_pause();
+                        continue;
+                    }
+                    if (q != hipSuccess) return HETM_EDEVICE;
+                    Span t(&rep->us_pack);
+                    RoundSet &r = set[cur];
+                    if (!admit(r)) {            // the round is full: it ends now
+                        admitting = false;
+                        continue;
+                    }
+                    if ((err = pack_upload(r))) return err;
+                    const Part &p = r.parts.back();
+                    hetm_oplist_desc pd = part_desc(r, p);
+                    if (hipStreamWaitEvent(c->stream, r.uploaded, 0) != hipSuccess) return HETM_EDEVICE;
+                    if ((err = hetm::stream_add(c, HETM_PROG_OPLIST, &pd, p.reqs.size(), r.d_res, r.d_tick + p.k0)))
+                        return err;
+                    if (hipEventRecord(batch_done[nb & 1], c->stream) != hipSuccess) return HETM_EDEVICE;
+                    ++nb;
+                    continue;
+                }
+                if (left > 0 && head < sp.n_requests) {   // until the next arrival or the period's end
+                    Span t(&rep->us_idle);
+                    wait_for_arrival(left);
+                    continue;
+                }
+                admitting = false;
+            }
             if (nxt < 0 && work_waiting()) {
                 Span t(&rep->us_pack);
                 const int s = cur < 0 ? 0 : cur ^ 1;
-                admit(set[s]);
-                if (!set[s].reqs.empty()) {
+                set[s].clear();
+                if (admit(set[s])) {
                     if ((err = pack_upload(set[s]))) return err;
                     nxt = s;
                 } else if (cur < 0) {
-                    return HETM_ECAPACITY;
+                    return HETM_ECAPACITY;      // a request larger than the budget
                 }
             }
             if (cur >= 0) {
                 hetm_round_result res{};
                 {
                     Span t(&rep->us_wait_round);
-                    err = sp.early_validation ? hetm::stream_end(c, &res) : hetm::round_end(c, &a[cur], &res);
+                    if (period_s > 0 && (err = fetch_after_round(set[cur]))) return err;   // behind its last batch
+                    err = streamed ? hetm::stream_end(c, &res) : hetm::round_end(c, &a[cur], &res);
                     if (err) return err;
                     // a served request completes when its round's merge lands:
                     // start the copy now rather than with the next round
@@ -456,12 +557,16 @@ struct Serve {
                     if (sp.early_validation) {
                         a[nxt].log = nullptr;         // shipped in pieces as the host commits them
                         a[nxt].n_log = 0;
-                        err = hetm::stream_begin(c, &a[nxt]);
-                    } else {
-                        err = hetm::round_begin(c, &a[nxt]);
                     }
+                    err = streamed ? hetm::stream_begin(c, &a[nxt]) : hetm::round_begin(c, &a[nxt]);
                     if (err) return err;
-                    if ((err = fetch_after_round(r))) return err;
+                    cur_start = clk::now();
+                    admitting = period_s > 0;
+                    if (admitting) {
+                        if (hipEventRecord(batch_done[0], c->stream) != hipSuccess) return HETM_EDEVICE;
+                        nb = 1;
+                    }
+                    if (period_s == 0 && (err = fetch_after_round(r))) return err;
                 }
                 // the host's writes of this round go into the host replica
                 // while the GPU runs it, after the last round's merge has
@@ -505,6 +610,7 @@ extern "C" int hetm_serve(hetm_ctx *c, const hetm_serve_spec *sp, void *host_rep
         return HETM_EINVAL;
     if (sp->pipelined && c->cfg.mode != HETM_MODE_GRAPH) return HETM_ESTATE;
     if (sp->early_validation && !sp->pipelined) return HETM_EINVAL;
+    if (!(sp->round_period_us >= 0) || (sp->round_period_us > 0 && !sp->pipelined)) return HETM_EINVAL;
     if (!sp->pipelined && c->cfg.async_merge) return HETM_ESTATE;
     for (uint64_t i = 0; i < sp->n_requests; ++i)
         if (sp->offsets[i + 1] < sp->offsets[i] || sp->offsets[i + 1] - sp->offsets[i] > c->cfg.max_txn_ops ||

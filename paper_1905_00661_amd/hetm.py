@@ -34,7 +34,7 @@ EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_a
            "hetm_stats_get", "hetm_read_state", "hetm_state_bytes", "hetm_host_tm_create",
            "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts",
            "hetm_serve", "hetm_set_exec_workgroups", "hetm_early_validate", "hetm_set_version_clock",
-           "hetm_read_words_noalloc", "hetm_round_begin", "hetm_round_push", "hetm_round_end"]
+           "hetm_read_words_noalloc", "hetm_round_begin", "hetm_round_push", "hetm_round_add", "hetm_round_end"]
 
 P = ctypes.c_void_p
 U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -80,7 +80,7 @@ class hetm_serve_spec(ctypes.Structure):
     _fields_ = [("n_requests", U64), ("arrival_s", P), ("offsets", P), ("idx", P), ("n_writes", P), ("tid", P),
                 ("host_log", P), ("host_log_len", U64), ("host_log_per_round", U64), ("max_batch", U64),
                 ("mem_budget_bytes", U64), ("pipelined", U32), ("starvation_limit", U32),
-                ("early_validation", U32), ("push_entries", U32)]
+                ("early_validation", U32), ("push_entries", U32), ("round_period_us", ctypes.c_double)]
 
 
 class hetm_serve_report(ctypes.Structure):
@@ -91,7 +91,7 @@ class hetm_serve_report(ctypes.Structure):
                 ("round_conflict", P), ("max_rounds", U64), ("round_log_end", P),
                 ("us_pack", ctypes.c_double), ("us_wait_round", ctypes.c_double), ("us_settle", ctypes.c_double),
                 ("us_host_commit", ctypes.c_double), ("us_wait_merge", ctypes.c_double), ("us_idle", ctypes.c_double),
-                ("starved_rounds", U64)]
+                ("starved_rounds", U64), ("batches", U64)]
 
 
 class hetm_stats(ctypes.Structure):
@@ -135,6 +135,7 @@ def lib() -> ctypes.CDLL:
             "hetm_read_words_noalloc": ([P, U64, U64, P], ctypes.c_int),
             "hetm_round_begin": ([P, ctypes.POINTER(hetm_round_args)], ctypes.c_int),
             "hetm_round_push": ([P, P, U64, P], ctypes.c_int),
+            "hetm_round_add": ([P, U32, P, U64, P, P], ctypes.c_int),
             "hetm_round_end": ([P, ctypes.POINTER(hetm_round_result)], ctypes.c_int),
             "hetm_host_tm_create": ([P, U64, U32, U32, U64, ctypes.POINTER(P)], ctypes.c_int),
             "hetm_host_tm_free": ([P], ctypes.c_int),
@@ -417,7 +418,8 @@ class Context:
 
     def serve(self, arrival_s: np.ndarray, batch, host, host_log: np.ndarray, host_log_per_round: int,
               max_batch: int, mem_budget_bytes: int, pipelined: bool, max_rounds: int = 1 << 16,
-              starvation_limit: int = 0, early_validation: bool = False, push_entries: int = 0) -> dict:
+              starvation_limit: int = 0, early_validation: bool = False, push_entries: int = 0,
+              round_period_us: float = 0.0) -> dict:
         """Runs the request loop (hetm_serve) over OPLIST requests; returns the
         report and per-request latencies, results and commit positions."""
         arrival_s = np.ascontiguousarray(arrival_s, dtype=np.float64)
@@ -434,7 +436,7 @@ class Context:
                                host_log_len=host_log.shape[0], host_log_per_round=host_log_per_round,
                                max_batch=max_batch, mem_budget_bytes=mem_budget_bytes, pipelined=int(pipelined),
                                starvation_limit=starvation_limit, early_validation=int(early_validation),
-                               push_entries=push_entries)
+                               push_entries=push_entries, round_period_us=float(round_period_us))
         rep = hetm_serve_report(latency_us=lat.ctypes.data, results=res.ctypes.data, commit_seq=seq.ctypes.data,
                                 round_conflict=rconf.ctypes.data, max_rounds=max_rounds,
                                 round_log_end=rlog.ctypes.data)
@@ -472,6 +474,12 @@ class Context:
         _check(lib().hetm_round_push(self.ctx, log.data_ptr() if n else None, n, ctypes.byref(d) if wait else None),
                "hetm_round_push", self.ctx)
         return int(d.value) if wait else None
+
+    def round_add(self, b: "Batch") -> None:
+        """Adds batch b to the open streamed round (after its earlier
+        batches, before its tail); b's buffers must live until round_end."""
+        _check(lib().hetm_round_add(self.ctx, b.program, ctypes.addressof(b.desc), b.n, b.results.data_ptr(),
+                                    b.tickets.data_ptr()), "hetm_round_add", self.ctx)
 
     def round_end(self) -> hetm_round_result:
         r = hetm_round_result()

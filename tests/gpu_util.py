@@ -102,13 +102,41 @@ def assert_round_equal(g: dict, o: dict, ri: wl.RoundInputs):
         assert int(r.n_committed) == ri.batch.n
 
 
+def split_batch(program: int, batch, cuts):
+    """The batch as consecutive sub-batches [cuts[k], cuts[k+1])."""
+    parts = []
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        if program == wl.PROG_OPLIST:
+            o = batch.offsets
+            parts.append(wl.OplistBatch(offsets=(o[lo:hi + 1] - o[lo]).astype(np.uint32),
+                                        idx=batch.idx[o[lo]:o[hi]].copy(), n_writes=batch.n_writes[lo:hi].copy(),
+                                        tid=batch.tid[lo:hi].copy()))
+        else:
+            parts.append(wl.TransferBatch(src=batch.src[lo:hi].copy(), dst=batch.dst[lo:hi].copy(),
+                                          amt=batch.amt[lo:hi].copy()))
+    return parts
+
+
+def join_results(program: int, parts: list) -> np.ndarray:
+    """Results of consecutive sub-batches in the whole batch's layout
+    (OPLIST: per operation in order; TRANSFER: three arrays of n)."""
+    if program == wl.PROG_OPLIST:
+        return np.concatenate([b.results_np() for b in parts])
+    return np.concatenate([b.results_np().reshape(3, -1) for b in parts], axis=1).reshape(-1)
+
+
 def streamed_round(ri: wl.RoundInputs, chunks: int = 3, where: str = "device", sync_before_push: bool = False,
-                   async_merge: bool = False, policy=hm.HETM_POLICY_CPU_WINS, host=None, ctx=None, keep=False):
+                   async_merge: bool = False, policy=hm.HETM_POLICY_CPU_WINS, host=None, ctx=None, keep=False,
+                   batches: int = 1, interleave: bool = False):
     """One streamed round (hetm_round_begin / push / end, GRAPH mode), the log
     pushed in `chunks` consecutive pieces from `where` (device, pinned or
     pageable host memory).  With sync_before_push the pieces are pushed once
     the execution part has finished, so early validation sees the whole read
-    set and every transaction has run.  Returns what gpu_round returns."""
+    set and every transaction has run.  With batches > 1 the batch is cut
+    into that many consecutive pieces of uneven size: the first goes to
+    hetm_round_begin, the others to hetm_round_add, all before the first
+    push, or with interleave one before each push.  Returns what gpu_round
+    returns (results and tickets joined in the whole batch's order)."""
     import torch
     if ctx is None:
         ctx = hm.Context(ri.n_words, ri.word_bytes, ri.granule, init=ri.init, batch_capacity=max(ri.batch.n, 1),
@@ -116,7 +144,15 @@ def streamed_round(ri: wl.RoundInputs, chunks: int = 3, where: str = "device", s
     H0 = wl.host_replica(ri.init, ri.log) if host is None else host
     host_t = hm.pinned(H0.nbytes)
     host_t.numpy()[:] = H0.view(np.uint8)
-    b = hm.Batch(ri.program, ri.batch, ctx.dev)
+    n = ri.batch.n
+    if batches > 1:
+        # uneven pieces: a tiny one, then growing ones
+        w = np.array([1] + [2 ** k for k in range(1, batches)], np.float64)
+        cuts = np.concatenate([[0], np.round(np.cumsum(w) / w.sum() * n)]).astype(np.int64)
+        bs = [hm.Batch(ri.program, sb, ctx.dev) for sb in split_batch(ri.program, ri.batch, cuts)]
+    else:
+        bs = [hm.Batch(ri.program, ri.batch, ctx.dev)]
+    b = bs[0]
     n_log = ri.log.shape[0]
     raw = np.ascontiguousarray(ri.log).view(np.uint8).reshape(-1)
     if where == "device":
@@ -130,20 +166,29 @@ def streamed_round(ri: wl.RoundInputs, chunks: int = 3, where: str = "device", s
     flags_t = torch.zeros(max((n_log + 31) // 32, 1) * 4, dtype=torch.uint8, device=ctx.dev)
     ids_t = torch.zeros(max(ctx.n_granules, 1) * 4, dtype=torch.uint8, device=ctx.dev)
     torch.cuda.synchronize()
-    ctx.round_begin(b if ri.batch.n else None, host_t, flags=flags_t, ids=ids_t, policy=policy)
+    ctx.round_begin(b if b.n else None, host_t, flags=flags_t, ids=ids_t, policy=policy)
+    adds = list(bs[1:])
+    if not interleave:
+        for bk in adds:
+            ctx.round_add(bk)
+        adds = []
     if sync_before_push:
         torch.cuda.synchronize()
     cuts = np.linspace(0, n_log, chunks + 1).astype(np.int64)
     doomed = 0
     for lo, hi in zip(cuts[:-1], cuts[1:]):
+        if adds:
+            ctx.round_add(adds.pop(0))
         if hi > lo:
             doomed = ctx.round_push(log_t[lo * eb:hi * eb], int(hi - lo), wait=sync_before_push) or doomed
+    for bk in adds:
+        ctx.round_add(bk)
     res = ctx.round_end()
     ctx.sync()
     out = {
         "res": res,
-        "results": b.results_np(),
-        "tickets": b.tickets_np(),
+        "results": join_results(ri.program, bs),
+        "tickets": np.concatenate([bk.tickets_np() for bk in bs]),
         "S": ctx.read_state(hm.HETM_STATE_STMR).copy(),
         "H": host_t.numpy().view(ri.init.dtype).copy(),
         "flags": hm.tensor_to_numpy(flags_t, np.uint32),

@@ -42,6 +42,7 @@ def test_strerror_and_null_handling(hm):
     assert L.hetm_read_words_noalloc(None, 0, 0, None) == hm.HETM_EINVAL
     assert L.hetm_round_begin(None, None) == hm.HETM_EINVAL
     assert L.hetm_round_push(None, None, 0, None) == hm.HETM_EINVAL
+    assert L.hetm_round_add(None, 1, None, 0, None, None) == hm.HETM_EINVAL
     assert L.hetm_round_end(None, None) == hm.HETM_EINVAL
 
 
@@ -62,7 +63,7 @@ def test_struct_layouts_match_header(hm, tmp_path):
     compiler makes of include/hetm.h."""
     structs = {n: getattr(hm, n) for n in ["hetm_config", "hetm_oplist_desc", "hetm_transfer_desc",
                                            "hetm_cache_desc", "hetm_round_args", "hetm_round_result",
-                                           "hetm_stats"]}
+                                           "hetm_stats", "hetm_serve_spec", "hetm_serve_report"]}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hetm.h"', "int main(void) {"]
     for n, cls in structs.items():
         lines.append(f'printf("{n} sizeof %zu\\n", sizeof({n}));')

@@ -1,5 +1,6 @@
 """Serving (hetm_serve): open-loop arrivals, continuous batching over the
-double-buffered round, re-queue on conflict.  Oracle parity of a whole
+double-buffered round, admission into the running round (round period),
+re-queue on conflict.  Oracle parity of a whole
 served run, and probe requests whose results are the same alone and in the
 mix (tolerance 0)."""
 import numpy as np
@@ -87,15 +88,19 @@ def make_ctx(hm, init, pipelined, G=64, max_batch=8192):
     return hm.Context(N, 4, G, init=init, max_ops=64, batch_capacity=max_batch, log_capacity=4096, mode=0)
 
 
-@pytest.mark.parametrize("pipelined,rate,inject,early", [
-    (True, 2e6, 0, False), (False, 2e6, 0, False), (False, 5e5, 3 * 4096, False), (True, 2e7, 0, False),
-    (True, 5e5, 3 * 4096, False), (True, 2e6, 0, True), (True, 5e5, 3 * 4096, True), (True, 2e7, 997, True)])
-def test_serve_matches_oracle(hm, wl, pipelined, rate, inject, early):
+@pytest.mark.parametrize("pipelined,rate,inject,early,period", [
+    (True, 2e6, 0, False, 0), (False, 2e6, 0, False, 0), (False, 5e5, 3 * 4096, False, 0), (True, 2e7, 0, False, 0),
+    (True, 5e5, 3 * 4096, False, 0), (True, 2e6, 0, True, 0), (True, 5e5, 3 * 4096, True, 0),
+    (True, 2e7, 997, True, 0), (True, 2e6, 0, False, 400), (True, 2e7, 0, False, 1000),
+    (True, 5e5, 3 * 4096, False, 600), (True, 2e7, 997, True, 500)])
+def test_serve_matches_oracle(hm, wl, pipelined, rate, inject, early, period):
     """20,000 lognormal-length requests (median 4, capped at 64) arriving
     Poisson at `rate`, 5% hot words, host log stream of 4096 entries per
     round in the host's region (plus injected inter-device conflicts).  With
     `early` the rounds are streamed: the host ships its writes in pieces
-    (1000 entries) while the GPU runs, each early-validated."""
+    (1000 entries) while the GPU runs, each early-validated.  With a round
+    `period` (µs) the requests that arrive while a round is open join it as
+    further batches."""
     g = wl.rng("c5", 0, 3)
     init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
     req = wl.c5_requests(g, 20000, rate, n_words=N, host_lo=HOST_LO)
@@ -104,11 +109,15 @@ def test_serve_matches_oracle(hm, wl, pipelined, rate, inject, early):
     host_t = hm.pinned(N * 4)
     host_t.numpy()[:] = init.view(np.uint8)
     out = ctx.serve(req["arrival_s"], req["batch"], host_t, log, 4096, 8192, 64 << 20, pipelined,
-                    early_validation=early, push_entries=1000 if early else 0)
-    say(f"serve pipelined={pipelined} early={early} rate={rate:g}: rounds={out['rounds']} "
-        f"conflicted={out['conflicted_rounds']} "
+                    early_validation=early, push_entries=1000 if early else 0, round_period_us=period)
+    say(f"serve pipelined={pipelined} early={early} period={period} rate={rate:g}: rounds={out['rounds']} "
+        f"batches={out['batches']} conflicted={out['conflicted_rounds']} "
         f"p50={out['p50_latency_us']:.0f}us p99={out['p99_latency_us']:.0f}us thr={out['throughput']:.3g}/s")
     assert out["served"] == 20000
+    if period:
+        assert out["batches"] > out["rounds"], "no round took a second batch"
+    else:
+        assert out["batches"] == out["rounds"]
     if inject:
         assert out["conflicted_rounds"] > 0 and out["requeued"] > 0
     S, res = replay_served(init, req["batch"], out, log, 4096, 64)
@@ -145,8 +154,8 @@ def test_serve_twice_on_one_context(hm, wl, pipelined):
     ctx.close()
 
 
-@pytest.mark.parametrize("pipelined", [False, True])
-def test_serve_starvation_guard(hm, wl, pipelined):
+@pytest.mark.parametrize("pipelined,period", [(False, 0), (True, 0), (True, 800)])
+def test_serve_starvation_guard(hm, wl, pipelined, period):
     """Every host log chunk writes a hot GPU word, so every round with host
     writes aborts; with a starvation limit of 2 the guard runs a round
     without host writes after two losses in a row, the GPU makes progress,
@@ -158,7 +167,8 @@ def test_serve_starvation_guard(hm, wl, pipelined):
     ctx = make_ctx(hm, init, pipelined)
     host_t = hm.pinned(N * 4)
     host_t.numpy()[:] = init.view(np.uint8)
-    out = ctx.serve(req["arrival_s"], req["batch"], host_t, log, 4096, 8192, 64 << 20, pipelined, starvation_limit=2)
+    out = ctx.serve(req["arrival_s"], req["batch"], host_t, log, 4096, 8192, 64 << 20, pipelined, starvation_limit=2,
+                    round_period_us=period)
     say(f"starvation guard pipelined={pipelined}: rounds={out['rounds']} conflicted={out['conflicted_rounds']} "
         f"starved={out['starved_rounds']}")
     assert out["served"] == 6000
@@ -170,10 +180,12 @@ def test_serve_starvation_guard(hm, wl, pipelined):
     ctx.close()
 
 
-def test_serve_alone_vs_mix(hm, wl):
+@pytest.mark.parametrize("period", [0, 500])
+def test_serve_alone_vs_mix(hm, wl, period):
     """Probe requests each touch 4 private words no other request touches:
     their results and final words are identical served alone and served
-    inside a 20,000-request mix (tolerance 0)."""
+    inside a 20,000-request mix (tolerance 0), also when the mix's rounds
+    take requests that arrive while they run (a round period)."""
     P0 = HOST_LO - 4096
     n_probe = 512
     g = wl.rng("c5", 1, 3)
@@ -183,11 +195,11 @@ def test_serve_alone_vs_mix(hm, wl):
     mix = wl.c5_requests(g, 20000, 4e6, n_words=N, host_lo=P0)     # the mix stays below the probes
     log = host_stream(wl, 9, 1 << 20, HOST_LO, N)
 
-    def run(arr, batch):
+    def run(arr, batch, period=0):
         ctx = make_ctx(hm, init, True)
         host_t = hm.pinned(N * 4)
         host_t.numpy()[:] = init.view(np.uint8)
-        out = ctx.serve(arr, batch, host_t, log, 1024, 4096, 32 << 20, True)
+        out = ctx.serve(arr, batch, host_t, log, 1024, 4096, 32 << 20, True, round_period_us=period)
         S = ctx.read_state(hm.HETM_STATE_STMR).copy()
         ctx.close()
         return out, S
@@ -202,7 +214,9 @@ def test_serve_alone_vs_mix(hm, wl):
                           idx=np.concatenate([mb.idx, probes.idx]), n_writes=np.concatenate([mb.n_writes, probes.n_writes]),
                           tid=np.concatenate([mb.tid, probes.tid]))
     sub = _subset(allb, order)
-    mixed, S_mixed = run(arr[order], sub)
+    mixed, S_mixed = run(arr[order], sub, period)
+    if period:
+        assert mixed["batches"] > mixed["rounds"]
     pos = np.flatnonzero(order >= mix["arrival_s"].shape[0])            # probes inside the mixed request list
     assert pos.shape[0] == n_probe
     got = np.concatenate([mixed["results"][sub.offsets[p]:sub.offsets[p + 1]] for p in pos])

@@ -3,9 +3,10 @@ shipped in chunks while the round executes (§IV-D, inter-device
 synchronization) and each chunk is validated early against the read set
 (§IV-D, early validation).  The round's outcome is that of the same round
 through hetm_round: bit-exact oracle parity, chunks from device, pinned and
-pageable memory, both merge forms, both policies.  A chunk that hits the read
-set while a large batch still runs dooms the round, which then runs fewer
-transactions than its batch."""
+pageable memory, both merge forms, both policies, rounds fed several
+batches (hetm_round_add).  A chunk that hits the read set while a large
+batch still runs dooms the round, which then runs fewer transactions than
+its batch."""
 from __future__ import annotations
 
 import numpy as np
@@ -48,6 +49,82 @@ def test_streamed_round_parity(hm, wl, variant, chunks, where, async_merge):
     assert_round_equal(g, o, ri)
     assert g["res"].doomed == (1 if o["conflict"] else 0)
     assert g["doomed_seen"] == o["conflict"]
+
+
+@pytest.mark.parametrize("variant,batches,async_merge,interleave", [
+    ("p", 3, False, False), ("", 4, True, False), ("w", 3, False, False), ("p", 5, True, True)])
+def test_streamed_round_batches(hm, wl, variant, batches, async_merge, interleave):
+    """A streamed round fed several batches of uneven size, the first through
+    hetm_round_begin and the others through hetm_round_add (all before the
+    pushes, or one before each push while the earlier ones run): every
+    output equals the oracle's replay of the whole batch in the recorded
+    ticket order, and the round counts every batch's transactions."""
+    ri = wl.c1(variant)
+    say(f"streamed round c1{variant}: {batches} batches, async merge {async_merge}, interleave {interleave}")
+    g = streamed_round(ri, chunks=4, where="device", sync_before_push=not interleave, async_merge=async_merge,
+                       batches=batches, interleave=interleave)
+    o = oracle_round(ri, g["tickets"], g["H0"])
+    assert_round_equal(g, o, ri)
+    if o["conflict"]:
+        assert int(g["res"].n_aborted) == ri.batch.n
+
+
+@pytest.mark.parametrize("steal", [0.0, 0.002])
+def test_streamed_transfer_batches(hm, wl, steal):
+    """Bank transfers (hot-account chains per batch) in a streamed round of
+    five batches: oracle parity and conserved balances; with `steal` some
+    transfers touch the host's accounts and the round conflicts."""
+    d = wl.c3(n_accounts=1 << 16, host_accounts=1 << 10, n_txn=40000, n_host=2000, steal=steal)
+    H = d["init"].copy()
+    tm = hm.HostTM(H)
+    _, log = tm.transfers(d["host"].src, d["host"].dst, d["host"].amt)
+    tm.close()
+    ri = wl.RoundInputs(cfg="c3", n_words=1 << 16, word_bytes=8, granule=16, program=wl.PROG_TRANSFER,
+                        init=d["init"], batch=d["batch"], log=log)
+    g = streamed_round(ri, chunks=2, sync_before_push=True, async_merge=True, host=H, batches=5)
+    o = oracle_round(ri, g["tickets"], H)
+    assert_round_equal(g, o, ri)
+    assert int(g["S"].sum()) == int(d["init"].sum())
+    assert o["conflict"] == (1 if steal else 0)
+
+
+def test_round_add_errors(hm, wl):
+    """hetm_round_add outside a streamed round is ESTATE; a batch of another
+    program is EINVAL and one over the capacity ECAPACITY, and either leaves
+    the round as it was: it ends equal to the oracle's round of the batches
+    that were taken."""
+    import torch
+    ri = wl.c1("p")
+    ctx = hm.Context(ri.n_words, 4, ri.granule, init=ri.init, batch_capacity=ri.batch.n, log_capacity=ri.log.shape[0],
+                     mode=hm.HETM_MODE_GRAPH)
+    host_t = hm.pinned(ri.init.nbytes)
+    H0 = wl.host_replica(ri.init, ri.log)
+    host_t.numpy()[:] = H0.view(np.uint8)
+    from gpu_util import split_batch
+    a, b = split_batch(ri.program, ri.batch, [0, 1000, ri.batch.n])
+    ba, bb = hm.Batch(ri.program, a), hm.Batch(ri.program, b)
+    with pytest.raises(hm.HetmError) as e:
+        ctx.round_add(bb)
+    assert e.value.code == hm.HETM_ESTATE
+    ctx.round_begin(ba, host_t)
+    other = wl.TransferBatch(src=np.zeros(4, np.uint32), dst=np.ones(4, np.uint32), amt=np.ones(4, np.uint32))
+    with pytest.raises(hm.HetmError) as e:
+        ctx.round_add(hm.Batch(hm.HETM_PROG_TRANSFER, other))
+    assert e.value.code == hm.HETM_EINVAL
+    big = wl.c1("p", n_txn=ri.batch.n + 1).batch
+    with pytest.raises(hm.HetmError) as e:
+        ctx.round_add(hm.Batch(ri.program, big))
+    assert e.value.code == hm.HETM_ECAPACITY
+    ctx.round_add(bb)
+    ctx.round_push(hm.to_device(ri.log), ri.log.shape[0])
+    res = ctx.round_end()
+    ctx.sync()
+    g = {"res": res, "results": np.concatenate([ba.results_np(), bb.results_np()]),
+         "tickets": np.concatenate([ba.tickets_np(), bb.tickets_np()]), "flags": None, "ids": None,
+         "S": ctx.read_state(hm.HETM_STATE_STMR).copy(), "H": host_t.numpy().view(np.uint32).copy()}
+    o = oracle_round(ri, g["tickets"], H0)
+    assert_round_equal(g, o, ri)
+    ctx.close()
 
 
 @pytest.mark.parametrize("variant", ["p", "w"])
