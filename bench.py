@@ -683,7 +683,9 @@ def serve_sweep(args, hm, wl, torch) -> dict:
     2^27-word STMR with 5% hot words; rounds admitted under a 2 GiB budget;
     the pipelined form (continuous batching, double-buffered merge), the same
     with streamed rounds whose host writes are shipped in 48 KB pieces and
-    validated early, and one round at a time.  Each form serves a warm-up
+    validated early, the same with a round period (requests that arrive
+    while a round is open join it as further batches), and one round at a
+    time.  Each form serves a warm-up
     stream first on its context; every call's host log follows the previous
     call's."""
     N = 1 << 27
@@ -698,35 +700,38 @@ def serve_sweep(args, hm, wl, torch) -> dict:
                        f"host log {per_round}/round, budget 2 GiB, granule 64; requests per point: rate x "
                        f"{args.serve_seconds} s (at least 2^17, at most 2^23)",
            "p99_bound_ms": bound_ms, "points": {}}
-    forms = (("pipelined", True, dict(mode=1, async_merge=True), False),
-             ("pipelined_early", True, dict(mode=1, async_merge=True), True),
-             ("plain", False, dict(mode=0), False))
+    period = args.serve_period_us
+    out["round_period_us"] = period
+    forms = (("pipelined", True, dict(mode=1, async_merge=True), False, 0.0),
+             ("pipelined_early", True, dict(mode=1, async_merge=True), True, 0.0),
+             ("pipelined_period", True, dict(mode=1, async_merge=True), False, period),
+             ("plain", False, dict(mode=0), False, 0.0))
     call = [0]
 
-    def serve(ctx, host, req, pipelined, early):
+    def serve(ctx, host, req, pipelined, early, period_us):
         call[0] += 1
         later = hlog.copy()
         later["ts"] += np.uint64(call[0] << 40)
         return ctx.serve(req["arrival_s"], req["batch"], host, later, per_round, 1 << 20, 2 << 30, pipelined,
-                         early_validation=early)
+                         early_validation=early, round_period_us=period_us)
 
-    for name, pipelined, kw, early in forms:
+    for name, pipelined, kw, early, period_us in forms:
         ctx = hm.Context(N, 4, 64, init=init, max_ops=64, batch_capacity=1 << 20, log_capacity=per_round, **kw)
         host = hm.pinned(N * 4)
         host.numpy()[:] = init.view(np.uint8)
         warm = wl.c5_requests(g, 1 << 17, 1e7, n_words=N, host_lo=host_lo)
-        serve(ctx, host, warm, pipelined, early)
+        serve(ctx, host, warm, pipelined, early, period_us)
         ctx.sync()
         pts = {}
         for rate in rates:
             n = int(min(max(rate * args.serve_seconds, 1 << 17), 1 << 23))
             req = wl.c5_requests(g, n, rate, n_words=N, host_lo=host_lo)
             log(f"served {name}: {n} requests at {rate:g}/s ...")
-            o = serve(ctx, host, req, pipelined, early)
+            o = serve(ctx, host, req, pipelined, early, period_us)
             ctx.sync()
             pts[f"{rate:g}"] = {"offered_txn_s": rate, "throughput_txn_s": o["throughput"],
                                 "p50_latency_us": o["p50_latency_us"], "p99_latency_us": o["p99_latency_us"],
-                                "rounds": int(o["rounds"]), "requests": n,
+                                "rounds": int(o["rounds"]), "batches": int(o["batches"]), "requests": n,
                                 "serving_thread_ms": {k: round(o["us_" + k] / 1e3, 2) for k in
                                                       ("pack", "wait_round", "settle", "host_commit", "wait_merge",
                                                        "idle")}}
@@ -799,6 +804,8 @@ def main():
     ap.add_argument("--serve-rates", default="1e6,1e7,3e7,1e8,2e8,3e8")
     ap.add_argument("--serve-seconds", type=float, default=0.25)
     ap.add_argument("--serve-p99-bound-ms", type=float, default=5.0)
+    ap.add_argument("--serve-period-us", type=float, default=500.0,
+                    help="round period of the served form that admits arrivals into the running round")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 1 GiB device copy, the known-size reference for HBM counters")
