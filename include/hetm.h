@@ -91,7 +91,8 @@ typedef struct {
     uint32_t lock_stripe_words;  /* S: words per lock, power of two, >= 1        */
     uint32_t max_txn_ops;        /* longest OPLIST transaction, 1..64            */
     uint64_t batch_capacity;     /* most transactions per hetm_submit_batch, 1..2^31 */
-    uint64_t log_capacity;       /* most log entries per hetm_validate_apply_log */
+    uint64_t log_capacity;       /* most log entries per hetm_validate_apply_log,
+                                    1..2^29                                      */
     uint32_t mode;               /* HETM_MODE_*                                  */
     int32_t  device;             /* HIP device ordinal                           */
     void    *stream;             /* hipStream_t for all work; NULL = the device's

@@ -783,7 +783,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     if (k.n_words == 0 || k.n_words >= (1ull << 32) || (k.word_bytes != 4 && k.word_bytes != 8) ||
         k.granule_words == 0 || !is_pow2(k.lock_stripe_words) || k.max_txn_ops == 0 || k.max_txn_ops > 64 ||
         k.batch_capacity == 0 || k.batch_capacity > (1ull << 31) || k.log_capacity == 0 ||
-        k.log_capacity >= (1ull << 32) || k.mode > HETM_MODE_GRAPH || k.async_merge > 1 ||
+        k.log_capacity > (1ull << 29) || k.mode > HETM_MODE_GRAPH || k.async_merge > 1 ||
         (k.async_merge && k.mode != HETM_MODE_GRAPH))
         return HETM_EINVAL;
     hetm_ctx *c = new (std::nothrow) hetm_ctx();
@@ -824,14 +824,17 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     TRY(dev_alloc(c, &c->ws, nbw * 4));
     c->log_bins = log_bins_for(k.log_capacity);
     c->log_tiles = log_tiles_for(k.log_capacity);
-    TRY(dev_alloc(c, &c->log_hist, (uint64_t)c->log_tiles * c->log_bins * 4));
-    TRY(dev_alloc(c, &c->log_bstart, (c->log_bins + 1) * 4ull));
+    // at most one spill chunk per bin block and bucket
+    TRY(dev_alloc(c, &c->log_desc, (uint64_t)c->log_tiles * c->log_bins * 12));
+    TRY(dev_alloc(c, &c->log_bstart, c->log_bins * 4ull));
     TRY(dev_alloc(c, &c->log_bwin, c->log_bins * 4ull));
-    TRY(dev_alloc(c, &c->log_totals, c->log_bins * 4ull));
+    TRY(dev_alloc(c, &c->log_head, c->log_bins * 4ull));
     TRY(dev_alloc(c, &c->log_cursor, c->log_bins * 4ull));
-    // the one-pass layout gives every bucket a region of log_region entries
+    // every bucket has a region of log_region entries; the spill area
+    // behind them takes what does not fit (at most the chunk), and a
+    // contiguous copy of every bucket that spilled (at most the chunk again)
     c->log_region = log_region_for(k.log_capacity, c->log_bins);
-    const uint64_t sorted_entries = std::max<uint64_t>(k.log_capacity, (uint64_t)c->log_bins * c->log_region);
+    const uint64_t sorted_entries = (uint64_t)c->log_bins * c->log_region + 2 * k.log_capacity;
     TRY(dev_alloc(c, &c->log_sorted, sorted_entries * c->log_entry_bytes));
     TRY(dev_alloc(c, &c->log_win, sorted_entries * c->log_entry_bytes));
     TRY(dev_alloc(c, &c->blocksums, nblocks * 4));
@@ -892,6 +895,7 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     bool ok = (c->slot || hipMemsetAsync(c->locks, 0, nlocks * 8, s) == hipSuccess) &&
               hipMemsetAsync(c->rs, 0, nrw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->log_cursor, 0, c->log_bins * 4ull, s) == hipSuccess &&
+              hipMemsetAsync(c->log_head, 0xFF, c->log_bins * 4ull, s) == hipSuccess &&
               hipMemsetAsync(c->ws, 0, nbw * 4, s) == hipSuccess &&
               hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), s) == hipSuccess &&
               hipMemsetAsync(c->hot, 0, sizeof(HotCounters), s) == hipSuccess &&
@@ -925,8 +929,8 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     a.stmr = c->stmr, a.locks = c->locks, a.ts = c->ts, a.rs = c->rs, a.ws = c->ws;
     a.word_shift = c->slot ? 1u : 0u;
     a.blocksums = c->blocksums, a.blockruns = c->blockruns, a.ids_scratch = c->ids;
-    a.log_hist = c->log_hist, a.log_bstart = c->log_bstart, a.log_bwin = c->log_bwin, a.log_totals = c->log_totals;
-    a.log_cursor = c->log_cursor, a.log_region = c->log_region;
+    a.log_desc = c->log_desc, a.log_bstart = c->log_bstart, a.log_bwin = c->log_bwin, a.log_head = c->log_head;
+    a.log_cursor = c->log_cursor, a.log_region = c->log_region, a.log_spill_cap = (uint32_t)(2 * c->cfg.log_capacity);
     a.log_sorted = c->log_sorted, a.log_win = c->log_win;
     a.log_bins = c->log_bins, a.log_bin_bits = ilog2(c->log_bins), a.log_tiles = c->log_tiles;
     a.order = c->order;
@@ -965,7 +969,7 @@ int hetm_free(hetm_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->ev_kernel) (void)hipEventDestroy(c->ev_kernel);
-    void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->log_hist, c->log_bstart, c->log_bwin, c->log_totals,
+    void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->log_desc, c->log_bstart, c->log_bwin, c->log_head,
                    c->log_cursor, c->log_sorted, c->log_win, c->blocksums, c->blockruns, c->ids, c->order, c->undo,
                    c->tx_tab, c->tx_hot, c->tx_chain, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
     for (void *p : dev)

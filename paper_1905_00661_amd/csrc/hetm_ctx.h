@@ -29,8 +29,8 @@ struct hetm_ctx {
     uint32_t *ws = nullptr;
     // the log chunk bucketed by word (validation and apply)
     uint32_t log_bins = 0, log_tiles = 0;
-    uint32_t *log_hist = nullptr, *log_bstart = nullptr, *log_bwin = nullptr, *log_totals = nullptr;
-    uint32_t *log_cursor = nullptr;    // entries placed in each bucket's region (one-pass layout)
+    uint32_t *log_desc = nullptr, *log_bstart = nullptr, *log_bwin = nullptr, *log_head = nullptr;
+    uint32_t *log_cursor = nullptr;    // entries of each bucket
     uint32_t log_region = 0;           // entries a bucket's region holds
     void *log_sorted = nullptr, *log_win = nullptr;
     uint32_t *blocksums = nullptr, *blockruns = nullptr, *ids = nullptr;

@@ -64,6 +64,11 @@ struct HotCounters {
 // every version (and the clock) between rounds once the clock passes
 // kClockReset; a writer that would still reach kClockLimit latches
 // HETM_ECAPACITY instead of committing.
+// Blocks that count themselves finished do so in groups: same-address
+// atomics serialize (about 20 ns apiece here), so a thousand blocks on one
+// counter would cost tens of microseconds; the last block of each group then
+// counts the group on the top counter.
+constexpr uint32_t kSubTickets = 32;
 constexpr uint32_t kClockReset = 1u << 30;
 constexpr uint32_t kClockLimit = 0x7FFFFFF0u;
 
@@ -93,7 +98,9 @@ struct DevCounters {
                                   // (0xFFFFFFFF before); every word the log wrote carries a version
                                   // at or above it, every word a transaction wrote one below
     uint32_t apply_ver;           // slot layout: version of the chunk being applied
-    uint32_t log_overflow;        // a bucket of the current chunk outgrew its region: exact bucketing
+    uint32_t log_spill;           // entries of the current chunk's spill area in use
+    uint32_t log_ndesc;           // spill chunks of the current chunk
+    uint32_t log_sub[kSubTickets];    // apply blocks finished, per group of blocks (b mod kSubTickets)
 };
 
 // Everything a kernel needs: constant context state plus the arguments of
@@ -106,13 +113,14 @@ struct DevArgs {
     uint8_t *rs;            // read set: one byte per granule (see rs_mark)
     uint32_t *ws;
     // the log chunk bucketed by word (validation + apply):
-    uint32_t *log_hist;     // [tiles][bins] entries of each tile per bucket, then each tile's offset in it
-    uint32_t *log_bstart;   // [bins + 1] first position of each bucket
+    uint32_t *log_desc;     // [log_tiles * bins][3] spill chunks: first position, entries, next chunk
+    uint32_t *log_bstart;   // [bins] first position of each bucket's entries (and of its winners)
     uint32_t *log_bwin;     // [bins] winning entries (one per word) each bucket resolved
-    uint32_t *log_totals;   // [bins] entries per bucket (scan pass)
-    uint32_t *log_cursor;   // [bins] entries placed in each bucket's region (bin pass; resolve clears)
-    void *log_sorted;       // [log_capacity] the chunk's entries grouped by bucket
-    void *log_win;          // [log_capacity] each bucket's winners, at the bucket's positions
+    uint32_t *log_head;     // [bins] first spill chunk of each bucket (kLogNone: none; resolve clears)
+    uint32_t *log_cursor;   // [bins] entries of each bucket, region and spill (bin pass; resolve clears)
+    void *log_sorted;       // [bins * log_region + 2 * log_capacity] the chunk's entries grouped by bucket:
+                            // the regions, then the spill area
+    void *log_win;          // same size: each bucket's winners, at the bucket's positions
     uint32_t *blocksums;    // compaction: per-block dirty counts, then offsets
     uint32_t *blockruns;
     uint32_t *ids_scratch;  // ceil(N/G) dirty granule ids
@@ -141,8 +149,9 @@ struct DevArgs {
     uint32_t n_scan_blocks;
     uint32_t log_bins;      // buckets of a log chunk, a power of two
     uint32_t log_bin_bits;  // log2(log_bins)
-    uint32_t log_tiles;     // bin / scatter blocks the launches are sized for (log_capacity / tile)
-    uint32_t log_region;    // entries each bucket's region holds in the one-pass layout
+    uint32_t log_tiles;     // bin blocks the launch is sized for (log_capacity / tile)
+    uint32_t log_region;    // entries each bucket's region holds
+    uint32_t log_spill_cap; // entries of the spill area (twice the chunk capacity)
     // ---- current call
     uint32_t program;
     uint32_t n_txns;
@@ -347,11 +356,12 @@ void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint3
                      DevCounters *cnt, hipStream_t s);
 void launch_apply(const DevArgs *a, uint32_t word_bytes, uint32_t bins, hipStream_t s);
 // Sizing of the bucketed log for a chunk capacity.
-constexpr uint32_t kLogTile = 4096;             // entries per count / scatter block
+constexpr uint32_t kLogTile = 4096;             // entries per bin block
 constexpr uint32_t kLogMaxBins = 4096;
+constexpr uint32_t kLogNone = 0xFFFFFFFFu;      // end of a bucket's spill-chunk list
 uint32_t log_bins_for(uint64_t log_capacity);
-// Entries each bucket's region holds in the one-pass layout: twice the
-// bucket's mean at capacity, plus a margin.
+// Entries each bucket's region holds: twice the bucket's mean at capacity,
+// plus a margin; what does not fit spills.
 inline uint32_t log_region_for(uint64_t log_capacity, uint32_t bins) {
     return (uint32_t)(2 * ((log_capacity + bins - 1) / bins) + 64);
 }

@@ -8,13 +8,14 @@
 //             chunk's largest and smallest ts, counts its entries per bucket
 //             (a multiplicative hash of the word) in an LDS histogram, takes
 //             the tile's share of every bucket's region (twice the bucket's
-//             mean size) with one atomic per bucket, and places each entry
-//             there.
-//  scan,    : only if some bucket outgrew its region (a log that hammers a
-//  scatter    few words): the exact layout.  scan turns the per-tile counts
-//             into each tile's first position in every bucket; scatter reads
-//             the chunk again and places every entry.
-//  resolve  : one workgroup per bucket builds an LDS hash table keyed by word:
+//             mean size) with one atomic per bucket, groups the tile by
+//             bucket in LDS and writes each bucket's run with consecutive
+//             threads.  A run that does not fit in its region (a log that
+//             hammers a few words) goes to a chunk of the spill area linked
+//             to its bucket.
+//  resolve  : a bucket that spilled is first copied into one range of the
+//             spill area.  One workgroup per bucket builds an LDS hash table
+//             keyed by word:
 //             the largest ts of each word and the one entry carrying it; a
 //             second entry at a word's winning ts, or a winning ts equal to
 //             the one an earlier chunk of the round applied, is an ordering
@@ -35,7 +36,6 @@
 // TS, at most the watermark, which no later entry can tie or lose to.
 #include "hetm_dev.h"
 
-#include <algorithm>
 
 namespace hetm {
 
@@ -50,9 +50,9 @@ uint32_t log_bins_for(uint64_t log_capacity) {
 
 namespace {
 
-constexpr uint32_t kThreads = 256;                       // scan and apply blocks
-constexpr uint32_t kTileThreads = 1024;                  // count and scatter blocks
-constexpr uint32_t kPerThread = kLogTile / kTileThreads; // 4 entries per thread in count / scatter
+constexpr uint32_t kThreads = 256;                       // apply and ts write-back blocks
+constexpr uint32_t kTileThreads = 1024;                  // bin blocks
+constexpr uint32_t kPerThread = kLogTile / kTileThreads; // 4 entries per thread in bin
 constexpr uint32_t kResThreads = 512;                    // resolve blocks
 constexpr uint32_t kTableBits = 12;
 constexpr uint32_t kTable = 1u << kTableBits;            // LDS hash-table slots per resolve block
@@ -78,8 +78,12 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t w, uint32_t bits) {
 }
 // table slot of a word within its bucket (other bits of another product)
 __device__ __forceinline__ uint32_t slot_of(uint32_t w) { return (w * 0xC2B2AE35u) >> (32 - kTableBits); }
-// resolve pass of a word when a bucket needs several
-__device__ __forceinline__ uint32_t pass_of(uint32_t w, uint32_t npass) { return ((w * 0x85EBCA6Bu) >> 8) % npass; }
+// resolve pass of a word when a bucket needs several: 24 bits of another
+// product scaled to [0, npass) by a multiply and a shift (no division: the
+// compiled remainder by a run-time divisor was off for some values)
+__device__ __forceinline__ uint32_t pass_of(uint32_t w, uint32_t npass) {
+    return (uint32_t)(((uint64_t)((w * 0x85EBCA6Bu) >> 8) * npass) >> 24);
+}
 
 __device__ __forceinline__ void store_bits(uint32_t *dst, uint64_t kb, uint64_t m, uint32_t nwords) {
     uint64_t w = kb >> 5;
@@ -95,13 +99,38 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
     return v;
 }
 
+// exclusive prefix sum over a block of NT threads (every thread calls it);
+// *total gets the sum
+template <uint32_t NT>
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *sh, uint32_t *total) {
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    uint32_t inc = v;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if ((int)lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) sh[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (uint32_t i = 0; i < NT / kWave; ++i) {
+        before += i < wv ? sh[i] : 0u;
+        all += sh[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
 // --------------------------------------------------------------------- bin
 template <typename E>
 __global__ __launch_bounds__(kTileThreads) void k_log_bin(const DevArgs *__restrict__ a) {
-    __shared__ uint32_t hist[kLogMaxBins];
-    __shared__ uint32_t base[kLogMaxBins];
+    __shared__ uint32_t hist[kLogMaxBins];   // the tile's count per bucket, then its run's start in stage
+    __shared__ uint32_t base[kLogMaxBins];   // the run's start in the bucket's region (past its end: spilled)
+    __shared__ uint32_t spill[kLogMaxBins];  // where the run's spilled part starts in the spill area
+    __shared__ E stage[kLogTile];            // the tile's entries grouped by bucket
     __shared__ unsigned long long s_mx[kTileThreads / kWave], s_mn[kTileThreads / kWave];
     __shared__ uint32_t s_cf[kTileThreads / kWave];
+    __shared__ uint32_t sh[kTileThreads / kWave];
     const uint64_t n = a->n_log;
     const uint64_t t0 = (uint64_t)blockIdx.x * kLogTile;
     if (t0 >= n) return;
@@ -168,31 +197,64 @@ __global__ __launch_bounds__(kTileThreads) void k_log_bin(const DevArgs *__restr
         conflict |= m != 0;
     }
     __syncthreads();
-    // the tile's counts (kept for the exact pass) and its share of each
-    // bucket's region, one atomic per bucket the tile touches
+    // each bucket's run of this tile: its place in the bucket's region (one
+    // atomic per bucket the tile touches), a spill chunk linked to the bucket
+    // for the part that does not fit, and its start in the tile grouped by
+    // bucket (an exclusive scan of the counts); thread t owns buckets
+    // [t per, (t + 1) per)
     const uint32_t C = a->log_region;
-    uint32_t *row = a->log_hist + (uint64_t)blockIdx.x * B;
-    bool over = false;
-    for (uint32_t i = threadIdx.x; i < B; i += kTileThreads) {
+    const uint32_t per = (B + kTileThreads - 1) / kTileThreads, b0 = threadIdx.x * per;
+    uint32_t mine = 0;
+    for (uint32_t i = b0; i < b0 + per && i < B; ++i) {
         const uint32_t h = hist[i];
-        row[i] = h;
-        uint32_t at = 0;
+        uint32_t at = 0, sp = kLogNone;
         if (h) {
             at = __hip_atomic_fetch_add(&a->log_cursor[i], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            over |= at + h > C;
+            const uint32_t fit = at >= C ? 0u : (C - at < h ? C - at : h);
+            if (fit < h) {
+                const uint32_t rest = h - fit;
+                sp = __hip_atomic_fetch_add(&cnt->log_spill, rest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t d = __hip_atomic_fetch_add(&cnt->log_ndesc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint64_t)sp + rest > a->log_spill_cap || d >= a->log_tiles * B) {
+                    latch_error(cnt, HETM_ECAPACITY, i);    // the area holds the chunk twice: not reached
+                    sp = kLogNone;
+                } else {
+                    uint32_t *dd = a->log_desc + 3ull * d;
+                    dd[0] = sp;
+                    dd[1] = rest;
+                    dd[2] = __hip_atomic_exchange(&a->log_head[i], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
         }
         base[i] = at;
+        spill[i] = sp;
+        mine += h;
     }
-    if (__ballot(over) && lane == 0) st_agent(&cnt->log_overflow, 1u);
+    uint32_t placed;
+    uint32_t run = block_scan<kTileThreads>(mine, sh, &placed);
+    for (uint32_t i = b0; i < b0 + per && i < B; ++i) {
+        const uint32_t h = hist[i];
+        hist[i] = run;
+        run += h;
+    }
     __syncthreads();
-    // every entry into its bucket's region (whatever does not fit is placed
-    // again by the exact pass)
-    E *out = (E *)a->log_sorted;
 #pragma unroll
-    for (uint32_t j = 0; j < kPerThread; ++j) {
-        if (!ok[j]) continue;
-        const uint32_t p = base[bk[j]] + rank[j];
-        if (p < C) out[(uint64_t)bk[j] * C + p] = e[j];
+    for (uint32_t j = 0; j < kPerThread; ++j)
+        if (ok[j]) stage[hist[bk[j]] + rank[j]] = e[j];
+    __syncthreads();
+    // every entry into its bucket's region or spill chunk, each run by
+    // consecutive threads
+    E *out = (E *)a->log_sorted;
+    const uint64_t spill_base = (uint64_t)B * C;
+    for (uint32_t k = threadIdx.x; k < placed; k += kTileThreads) {
+        const E x = stage[k];
+        const uint32_t bx = bucket_of(x.word, bbits);
+        const uint32_t q = k - hist[bx], at = base[bx], p = at + q;
+        if (p < C) {
+            out[(uint64_t)bx * C + p] = x;
+        } else if (spill[bx] != kLogNone) {
+            out[spill_base + spill[bx] + (q - (at >= C ? 0u : C - at))] = x;
+        }
     }
     // the chunk's ts range and conflict, staged (a chunk that fails a check
     // must not count) with at most one atomic per block and counter, and only
@@ -220,116 +282,6 @@ __global__ __launch_bounds__(kTileThreads) void k_log_bin(const DevArgs *__restr
             __hip_atomic_fetch_max(&cnt->chunk_min_inv, bn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (bc && !ld_agent(&cnt->chunk_conflict))
             __hip_atomic_fetch_or(&cnt->chunk_conflict, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// exclusive prefix sum over a block of NT threads (every thread calls it);
-// *total gets the sum
-template <uint32_t NT>
-__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *sh, uint32_t *total) {
-    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
-    uint32_t inc = v;
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t t = __shfl_up(inc, o);
-        if ((int)lane >= o) inc += t;
-    }
-    if (lane == kWave - 1) sh[wv] = inc;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-    for (uint32_t i = 0; i < NT / kWave; ++i) {
-        before += i < wv ? sh[i] : 0u;
-        all += sh[i];
-    }
-    __syncthreads();
-    *total = all;
-    return before + inc - v;
-}
-
-// -------------------------------------------------------------------- scan
-// Block b scans bucket b's column of per-tile counts into each tile's offset
-// within the bucket, in place, and stores the bucket's total.
-__global__ __launch_bounds__(kThreads) void k_log_scan(const DevArgs *__restrict__ a) {
-    __shared__ uint32_t sh[kThreads / kWave];
-    DevCounters *cnt = a->cnt;
-    if (!ld_agent(&cnt->log_overflow) || ld_agent(&cnt->error)) return;   // only for the exact layout
-    const uint32_t B = a->log_bins;
-    const uint32_t T = (uint32_t)((a->n_log + kLogTile - 1) / kLogTile);
-    uint32_t *hist = a->log_hist;
-    // a small grid (the launch usually finds nothing to do): each block takes
-    // buckets blockIdx.x, blockIdx.x + gridDim.x, ...
-    for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
-        uint32_t base = 0;
-        for (uint32_t t0 = 0; t0 < T; t0 += kThreads) {       // one column segment per thread and round
-            const uint32_t t = t0 + threadIdx.x;
-            const uint32_t v = t < T ? hist[(uint64_t)t * B + b] : 0u;
-            uint32_t total;
-            const uint32_t ex = block_scan<kThreads>(v, sh, &total);
-            if (t < T) hist[(uint64_t)t * B + b] = base + ex;
-            base += total;
-        }
-        if (threadIdx.x == 0) a->log_totals[b] = base;
-    }
-}
-
-// the buckets' first positions: an exclusive scan of the bucket totals by a
-// block of kTileThreads threads
-__device__ __forceinline__ void bucket_starts(const DevArgs *a, uint32_t *start, uint32_t *sh) {
-    const uint32_t B = a->log_bins;
-    uint32_t base = 0;
-    for (uint32_t b0 = 0; b0 < B; b0 += kTileThreads) {
-        const uint32_t b = b0 + threadIdx.x;
-        const uint32_t v = b < B ? a->log_totals[b] : 0u;
-        uint32_t total;
-        const uint32_t ex = block_scan<kTileThreads>(v, sh, &total);
-        if (b < B) start[b] = base + ex;
-        base += total;
-    }
-    if (threadIdx.x == 0) start[B] = base;
-}
-
-// ----------------------------------------------------------------- scatter
-// Block t places tile t's entries after computing the bucket starts (block 0
-// also publishes them for the later passes).
-template <typename E>
-__global__ __launch_bounds__(kTileThreads) void k_log_scatter(const DevArgs *__restrict__ a) {
-    __shared__ uint32_t start[kLogMaxBins + 1];
-    __shared__ uint32_t pos[kLogMaxBins];
-    __shared__ uint32_t sh[kTileThreads / kWave];
-    const uint64_t n = a->n_log;
-    if (n == 0 || !ld_agent(&a->cnt->log_overflow) || ld_agent(&a->cnt->error)) return;   // exact layout only
-    const uint32_t B = a->log_bins, bbits = a->log_bin_bits;
-    const uint32_t T = (uint32_t)((n + kLogTile - 1) / kLogTile);
-    bucket_starts(a, start, sh);
-    __syncthreads();
-    if (blockIdx.x == 0)
-        for (uint32_t i = threadIdx.x; i <= B; i += kTileThreads) a->log_bstart[i] = start[i];
-    // entries move as u64 words (the word index is the low half of the first)
-    constexpr uint32_t kQ = sizeof(E) / 8;
-    const uint64_t *log = (const uint64_t *)a->log;
-    uint64_t *out = (uint64_t *)a->log_sorted;
-    // a small grid (the launch usually finds nothing to do): each block takes
-    // tiles blockIdx.x, blockIdx.x + gridDim.x, ...
-    for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
-        const uint64_t t0 = (uint64_t)t * kLogTile;
-        uint64_t v[kPerThread][kQ];
-#pragma unroll
-        for (uint32_t j = 0; j < kPerThread; ++j) {
-            const uint64_t k = t0 + j * kTileThreads + threadIdx.x;
-            const uint64_t *src = log + (k < n ? k : n - 1) * kQ;
-#pragma unroll
-            for (uint32_t q = 0; q < kQ; ++q) v[j][q] = src[q];
-        }
-        const uint32_t *row = a->log_hist + (uint64_t)t * B;
-        for (uint32_t i = threadIdx.x; i < B; i += kTileThreads) pos[i] = start[i] + row[i];
-        __syncthreads();
-#pragma unroll
-        for (uint32_t j = 0; j < kPerThread; ++j) {
-            if (t0 + j * kTileThreads + threadIdx.x >= n) continue;
-            uint64_t *dst = out + (uint64_t)atomicAdd(&pos[bucket_of((uint32_t)v[j][0], bbits)], 1u) * kQ;
-#pragma unroll
-            for (uint32_t q = 0; q < kQ; ++q) dst[q] = v[j][q];
-        }
-        __syncthreads();
     }
 }
 
@@ -377,28 +329,54 @@ __device__ __forceinline__ void load_group(const E *in, uint32_t c, uint32_t g0,
 template <typename E>
 __global__ __launch_bounds__(kResThreads) void k_log_resolve(const DevArgs *__restrict__ a) {
     __shared__ Table t;
-    __shared__ uint32_t s_nwin;
+    __shared__ uint32_t s_nwin, s_at;
     DevCounters *cnt = a->cnt;
     const uint32_t b = blockIdx.x;
     if (b >= a->log_bins) return;
-    // the bucket's region count, read and cleared for the next chunk (also
-    // when the chunk failed a check)
-    const uint32_t placed = ld_agent(&a->log_cursor[b]);
+    // the bucket's entry count and spill chunks, read and cleared for the
+    // next chunk (also when the chunk failed a check)
+    const uint32_t c = ld_agent(&a->log_cursor[b]);
+    const uint32_t head = ld_agent(&a->log_head[b]);
     __syncthreads();
-    if (threadIdx.x == 0) a->log_cursor[b] = 0;
+    if (threadIdx.x == 0) {
+        a->log_cursor[b] = 0;
+        a->log_head[b] = kLogNone;
+    }
     // an empty chunk leaves the bucket starts unwritten (and apply stores nothing)
     if (a->n_log == 0 || ld_agent(&cnt->error)) return;
-    // the one-pass layout (bucket b's region), or the exact one if a bucket
-    // outgrew its region
-    uint32_t s0, c;
-    if (ld_agent(&cnt->log_overflow)) {
-        s0 = a->log_bstart[b];
-        c = a->log_bstart[b + 1] - s0;
-    } else {
-        s0 = b * a->log_region;
-        c = placed;
-        if (threadIdx.x == 0) a->log_bstart[b] = s0;     // for apply and the ts write-back
+    const uint32_t C = a->log_region;
+    uint32_t s0 = b * C;
+    if (head != kLogNone) {
+        // the bucket outgrew its region: the region (full) and its spill
+        // chunks are copied into one range of the spill area, where its
+        // winners go too
+        if (threadIdx.x == 0)
+            s_at = __hip_atomic_fetch_add(&cnt->log_spill, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t at = s_at;
+        if ((uint64_t)at + c > a->log_spill_cap) {    // the area holds the chunk twice: not reached
+            if (threadIdx.x == 0) {
+                latch_error(cnt, HETM_ECAPACITY, b);
+                a->log_bwin[b] = 0;
+            }
+            return;
+        }
+        const uint32_t sb = a->log_bins * C;
+        E *sorted = (E *)a->log_sorted;
+        E *dst = sorted + sb + at;
+        for (uint32_t i = threadIdx.x; i < C; i += kResThreads) dst[i] = sorted[s0 + i];
+        uint32_t off = C;
+        for (uint32_t d = head; d != kLogNone;) {
+            const uint32_t *dd = a->log_desc + 3ull * d;
+            const uint32_t st = dd[0], cn = dd[1];
+            for (uint32_t i = threadIdx.x; i < cn; i += kResThreads) dst[off + i] = sorted[sb + st + i];
+            off += cn;
+            d = dd[2];
+        }
+        __syncthreads();    // the copy is read back by the whole block
+        s0 = sb + at;
     }
+    if (threadIdx.x == 0) a->log_bstart[b] = s0;     // for apply and the ts write-back
     if (c == 0) {
         if (threadIdx.x == 0) a->log_bwin[b] = 0;
         return;
@@ -526,11 +504,20 @@ __global__ __launch_bounds__(kThreads) void k_log_apply(const DevArgs *__restric
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t done = __hip_atomic_fetch_add(&cnt->log_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = done == gridDim.x - 1;
+        // the last block folds the chunk's outcome in: a count of finished
+        // blocks per group, then of finished groups
+        const uint32_t g = b % kSubTickets, ng = gridDim.x < kSubTickets ? gridDim.x : kSubTickets;
+        const uint32_t in_g = (gridDim.x - g + kSubTickets - 1) / kSubTickets;
+        bool last = false;
+        if (__hip_atomic_fetch_add(&cnt->log_sub[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == in_g - 1)
+            last = __hip_atomic_fetch_add(&cnt->log_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ng - 1;
+        s_last = last;
     }
     __syncthreads();
     if (!s_last || threadIdx.x != 0) return;
+    for (uint32_t g = 0; g < kSubTickets; ++g) st_agent(&cnt->log_sub[g], 0u);
+    st_agent(&cnt->log_spill, 0u);
+    st_agent(&cnt->log_ndesc, 0u);
     if (ld_agent(&cnt->chunk_conflict)) st_agent(&cnt->conflict, 1u);
     const unsigned long long m = ld_agent(&cnt->chunk_max_ts);
     if (!discard && m > ld_agent(&cnt->max_ts)) st_agent(&cnt->max_ts, m);
@@ -539,7 +526,6 @@ __global__ __launch_bounds__(kThreads) void k_log_apply(const DevArgs *__restric
     st_agent(&cnt->chunk_max_ts, 0ull);
     st_agent(&cnt->chunk_min_inv, 0ull);
     st_agent(&cnt->log_ticket, 0u);
-    st_agent(&cnt->log_overflow, 0u);
 }
 
 // ----------------------------------------------------------- ts write-back
@@ -568,10 +554,6 @@ __global__ void k_log_ts_done(DevCounters *cnt) {
 
 }  // namespace
 
-// blocks of the exact-layout passes, which run (and then in full) only when a
-// bucket outgrew its region
-constexpr uint32_t kExactGrid = 64;
-
 void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint32_t tiles, bool later_chunk,
                      DevCounters *cnt, hipStream_t s) {
     if (word_bytes == 4) {
@@ -580,8 +562,6 @@ void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint3
             hipLaunchKernelGGL(k_log_ts_done, dim3(1), dim3(64), 0, s, cnt);
         }
         hipLaunchKernelGGL(k_log_bin<Entry4>, dim3(tiles), dim3(kTileThreads), 0, s, a);
-        hipLaunchKernelGGL(k_log_scan, dim3(std::min(bins, kExactGrid)), dim3(kThreads), 0, s, a);
-        hipLaunchKernelGGL(k_log_scatter<Entry4>, dim3(std::min(tiles, kExactGrid)), dim3(kTileThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_resolve<Entry4>, dim3(bins), dim3(kResThreads), 0, s, a);
     } else {
         if (later_chunk) {
@@ -589,8 +569,6 @@ void launch_validate(const DevArgs *a, uint32_t word_bytes, uint32_t bins, uint3
             hipLaunchKernelGGL(k_log_ts_done, dim3(1), dim3(64), 0, s, cnt);
         }
         hipLaunchKernelGGL(k_log_bin<Entry8>, dim3(tiles), dim3(kTileThreads), 0, s, a);
-        hipLaunchKernelGGL(k_log_scan, dim3(std::min(bins, kExactGrid)), dim3(kThreads), 0, s, a);
-        hipLaunchKernelGGL(k_log_scatter<Entry8>, dim3(std::min(tiles, kExactGrid)), dim3(kTileThreads), 0, s, a);
         hipLaunchKernelGGL(k_log_resolve<Entry8>, dim3(bins), dim3(kResThreads), 0, s, a);
     }
 }

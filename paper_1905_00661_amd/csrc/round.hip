@@ -178,11 +178,18 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_emit(const DevArgs *__
 }
 
 // --------------------------------------------------------------------- copy
+// Unit u of a list of granules of upg units each: granule i, unit j within
+// it (an exact multiply for the quotient rather than the compiled divide).
+__device__ __forceinline__ void unit_of(uint64_t u, uint32_t upg, const Div32 &du, uint64_t &i, uint64_t &j) {
+    i = u < (1ull << 32) ? div32((uint32_t)u, du) : u / upg;
+    j = u - i * upg;
+}
+
 // Moves the dirty granules in units of U bytes (16 when granules are whole
 // multiples of 16 bytes, else one word); upg = units per granule.  DS = 1:
 // the replica is in the slot layout, unit (word) pos sits at u32 index 2 pos.
 template <typename U, int DS>
-__global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uint32_t upg, uint64_t total_units) {
+__global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uint32_t upg, Div32 du, uint64_t total_units) {
     DevCounters *cnt = a->cnt;
     if (ld_agent(&cnt->error)) return;
     const uint32_t conflict = a->outcome == HETM_OUTCOME_DEVICE ? ld_agent(&cnt->conflict) : a->outcome;
@@ -195,7 +202,8 @@ __global__ __launch_bounds__(256) void k_copy(const DevArgs *__restrict__ a, uin
     const uint64_t work = D * upg;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < work; u += stride) {
-        const uint64_t i = u / upg, j = u - i * upg;
+        uint64_t i, j;
+        unit_of(u, upg, du, i, j);
         const uint64_t pos = (uint64_t)ids[i] * upg + j;
         if (pos >= total_units) continue;
         if (restore)
@@ -243,7 +251,7 @@ __global__ __launch_bounds__(256) void k_gather_slots(const DevArgs *__restrict_
 }
 
 template <typename U, int DS>
-__global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, uint32_t upg, uint64_t total_units) {
+__global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, uint32_t upg, Div32 du, uint64_t total_units) {
     DevCounters *cnt = a->cnt;
     if (ld_agent(&cnt->error)) return;
     const uint32_t outcome = ld_agent(&cnt->conflict);
@@ -258,7 +266,8 @@ __global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, u
     U *stg = (U *)a->staging;
     const uint64_t work = D * upg;
     for (uint64_t u = t0; u < work; u += stride) {
-        const uint64_t i = u / upg, j = u - i * upg;
+        uint64_t i, j;
+        unit_of(u, upg, du, i, j);
         const uint64_t pos = (uint64_t)ids[i] * upg + j;
         if (pos < total_units) stg[u] = dev[pos << DS];
     }
@@ -269,12 +278,13 @@ __global__ __launch_bounds__(256) void k_gather(const DevArgs *__restrict__ a, u
 // replica.
 template <typename U, int DS>
 __global__ __launch_bounds__(256) void k_restore(U *stmr, const U *host, const uint32_t *ids, const uint32_t *count,
-                                                 uint32_t upg, uint64_t total_units) {
+                                                 uint32_t upg, Div32 du, uint64_t total_units) {
     const uint64_t D = ld_agent(count);
     const uint64_t work = D * upg;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < work; u += stride) {
-        const uint64_t i = u / upg, j = u - i * upg;
+        uint64_t i, j;
+        unit_of(u, upg, du, i, j);
         const uint64_t pos = (uint64_t)ld_agent(&ids[i]) * upg + j;
         if (pos < total_units) stmr[pos << DS] = host[pos];
     }
@@ -355,7 +365,9 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         c.undo_over = ld_agent(&cnt->undo_over);
         c.apply_floor = ld_agent(&cnt->apply_floor);
         c.apply_ver = 0;
-        c.log_overflow = 0;
+        c.log_spill = 0;
+        c.log_ndesc = 0;
+        for (uint32_t g = 0; g < kSubTickets; ++g) c.log_sub[g] = 0;
         c.doomed = ld_agent(&cnt->doomed);
         if (!err) {
             const uint64_t f = c.max_ts > c.floor_ts ? c.max_ts : c.floor_ts;
@@ -398,7 +410,9 @@ __global__ void k_clear_error(DevCounters *cnt) {
         st_agent(&cnt->chunk_max_ts, 0ull);
         st_agent(&cnt->chunk_min_inv, 0ull);
         st_agent(&cnt->log_ticket, 0u);
-        st_agent(&cnt->log_overflow, 0u);
+        st_agent(&cnt->log_spill, 0u);
+        st_agent(&cnt->log_ndesc, 0u);
+        for (uint32_t g = 0; g < kSubTickets; ++g) st_agent(&cnt->log_sub[g], 0u);
     }
 }
 
@@ -430,15 +444,16 @@ void launch_copy(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_t 
     const uint64_t n_granules = (n_words + granule - 1) / granule;
     const uint32_t wgrid = stream_grid(n_granules * granule, 256, 16384);
     if (slot) {
-        hipLaunchKernelGGL((k_copy<uint32_t, 1>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
+        hipLaunchKernelGGL((k_copy<uint32_t, 1>), dim3(wgrid), dim3(256), 0, s, a, granule, make_div32(granule), n_words);
     } else if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0) {
         const uint32_t upg = (uint32_t)(gbytes / 16);
         const uint32_t grid = stream_grid(n_granules * upg, 256, 16384);
-        hipLaunchKernelGGL((k_copy<uint4, 0>), dim3(grid), dim3(256), 0, s, a, upg, n_words * word_bytes / 16);
+        hipLaunchKernelGGL((k_copy<uint4, 0>), dim3(grid), dim3(256), 0, s, a, upg, make_div32(upg),
+                           n_words * word_bytes / 16);
     } else if (word_bytes == 4) {
-        hipLaunchKernelGGL((k_copy<uint32_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
+        hipLaunchKernelGGL((k_copy<uint32_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, make_div32(granule), n_words);
     } else {
-        hipLaunchKernelGGL((k_copy<uint64_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
+        hipLaunchKernelGGL((k_copy<uint64_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, make_div32(granule), n_words);
     }
 }
 
@@ -463,15 +478,18 @@ void launch_gather(const DevArgs *a, uint64_t n_words, uint32_t granule, uint32_
         hipLaunchKernelGGL(k_gather_slots, dim3(stream_grid(n_granules * qpg, 256, 16384)), dim3(256), 0, s, a,
                            (uint32_t)__builtin_ctz(qpg), n_words);
     } else if (slot) {
-        hipLaunchKernelGGL((k_gather<uint32_t, 1>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
+        hipLaunchKernelGGL((k_gather<uint32_t, 1>), dim3(wgrid), dim3(256), 0, s, a, granule, make_div32(granule),
+                           n_words);
     } else if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0) {
         const uint32_t upg = (uint32_t)(gbytes / 16);
         hipLaunchKernelGGL((k_gather<uint4, 0>), dim3(stream_grid(n_granules * upg, 256, 16384)), dim3(256), 0, s, a,
-                           upg, n_words * word_bytes / 16);
+                           upg, make_div32(upg), n_words * word_bytes / 16);
     } else if (word_bytes == 4) {
-        hipLaunchKernelGGL((k_gather<uint32_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
+        hipLaunchKernelGGL((k_gather<uint32_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, make_div32(granule),
+                           n_words);
     } else {
-        hipLaunchKernelGGL((k_gather<uint64_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, n_words);
+        hipLaunchKernelGGL((k_gather<uint64_t, 0>), dim3(wgrid), dim3(256), 0, s, a, granule, make_div32(granule),
+                           n_words);
     }
 }
 
@@ -481,16 +499,16 @@ void launch_restore(void *stmr, const void *host, const uint32_t *ids, const uin
     const uint64_t gbytes = (uint64_t)granule * word_bytes;
     if (slot)
         hipLaunchKernelGGL((k_restore<uint32_t, 1>), dim3(grid), dim3(256), 0, s, (uint32_t *)stmr,
-                           (const uint32_t *)host, ids, count, granule, n_words);
+                           (const uint32_t *)host, ids, count, granule, make_div32(granule), n_words);
     else if (gbytes % 16 == 0 && (n_words * word_bytes) % 16 == 0)
         hipLaunchKernelGGL((k_restore<uint4, 0>), dim3(grid), dim3(256), 0, s, (uint4 *)stmr, (const uint4 *)host, ids,
-                           count, (uint32_t)(gbytes / 16), n_words * word_bytes / 16);
+                           count, (uint32_t)(gbytes / 16), make_div32((uint32_t)(gbytes / 16)), n_words * word_bytes / 16);
     else if (word_bytes == 4)
         hipLaunchKernelGGL((k_restore<uint32_t, 0>), dim3(grid), dim3(256), 0, s, (uint32_t *)stmr,
-                           (const uint32_t *)host, ids, count, granule, n_words);
+                           (const uint32_t *)host, ids, count, granule, make_div32(granule), n_words);
     else
         hipLaunchKernelGGL((k_restore<uint64_t, 0>), dim3(grid), dim3(256), 0, s, (uint64_t *)stmr,
-                           (const uint64_t *)host, ids, count, granule, n_words);
+                           (const uint64_t *)host, ids, count, granule, make_div32(granule), n_words);
 }
 
 void launch_undo(const DevArgs *a, uint32_t undo_cap, hipStream_t s) {

@@ -48,7 +48,7 @@ def test_strerror_and_null_handling(hm):
 
 @pytest.mark.parametrize("field,value", [("n_words", 0), ("word_bytes", 2), ("granule_words", 0),
                                          ("lock_stripe_words", 3), ("max_txn_ops", 65), ("mode", 7),
-                                         ("log_capacity", 0)])
+                                         ("log_capacity", 0), ("log_capacity", (1 << 29) + 1)])
 def test_config_rejected_before_touching_a_device(hm, field, value):
     cfg = hm.hetm_config(n_words=1024, word_bytes=4, granule_words=1, lock_stripe_words=1, max_txn_ops=8,
                          batch_capacity=16, log_capacity=16, mode=0, device=0, stream=None)

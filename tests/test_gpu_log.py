@@ -125,9 +125,9 @@ def test_multi_chunk_step_api(hm, wl, orc):
 
 def test_chunk_with_crowded_buckets(hm, wl, orc):
     """A chunk whose entries pile onto a few words (buckets far above one
-    resolve pass and far above their one-pass regions, so the exact layout
-    is built), beside a uniform part, then a chunk older than it on the
-    same words: both match the oracle."""
+    resolve pass and far above their regions, so they spill), beside a
+    uniform part, then a chunk older than it on the same words: both match
+    the oracle."""
     N = 1 << 16
     g = np.random.default_rng(21)
     init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
@@ -149,6 +149,43 @@ def test_chunk_with_crowded_buckets(hm, wl, orc):
         ctx.validate_apply(hm.to_device(ch), ch.shape[0])
         orc.apply(S, TS, ch, 0)
         assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S)
+    ctx.close()
+
+
+@pytest.mark.parametrize("n_hot,hot_frac", [(100, 1.0), (3, 0.5), (20, 0.9)])
+def test_chunk_spilling_many_buckets(hm, wl, orc, n_hot, hot_frac):
+    """A 2^18-entry chunk whose entries fall on few words (`hot_frac` of
+    them on `n_hot` words, the rest uniform), so that many buckets, or a
+    few by far, outgrow their regions and spill; then a second chunk of
+    the same round on the same hot words, which meets the first chunk's
+    winners through TS.  Both match the oracle."""
+    N = 1 << 20
+    g = np.random.default_rng(31 + n_hot)
+    init = g.integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    n1, n2 = 1 << 18, 1 << 16
+    ctx = hm.Context(N, 4, 16, init=init, batch_capacity=16, log_capacity=n1)
+    hot = g.choice(N, size=n_hot, replace=False)
+    ts = g.permutation(np.arange(1, n1 + n2 + 1, dtype=np.uint64))
+    chunks = []
+    for n, tsk in ((n1, ts[:n1]), (n2, ts[n1:])):
+        ch = np.zeros(n, wl.LOG4_DTYPE)
+        ch["word"] = np.where(g.random(n) < hot_frac, hot[g.integers(0, n_hot, size=n)], g.integers(0, N, size=n))
+        ch["value"] = g.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+        ch["ts"] = tsk
+        chunks.append(ch)
+    S, TS = init.copy(), np.zeros(N, np.uint64)
+    for i, ch in enumerate(chunks):
+        say(f"spilling chunk {i}: {ch.shape[0]} entries, {hot_frac:.0%} on {n_hot} words")
+        ctx.validate_apply(hm.to_device(ch), ch.shape[0])
+        orc.apply(S, TS, ch, 0)
+        got = ctx.read_state(hm.HETM_STATE_STMR)
+        bad = np.flatnonzero(got != S)
+        if bad.size:
+            say(f"  {bad.size} words differ, {np.isin(bad, hot).sum()} of them hot; first {bad[:8]}")
+            for w in bad[:6]:
+                k = np.flatnonzero(ch["word"] == w)
+                say(f"  word {w}: got {got[w]} want {S[w]} init {init[w]} entries {list(zip(k, ch['value'][k], ch['ts'][k]))}")
+        assert bad.size == 0
     ctx.close()
 
 
