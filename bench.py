@@ -84,11 +84,11 @@ def exec_scope_bytes(batch) -> float:
 
 # validate + apply, bytes per log entry: the scope table's algorithmic count
 # (16 B entry, 4 B bitmap word, 8 + 8 B timestamp read and write, 4 B value)
-# and the bytes the bucketed passes stream (count reads the entry and a
-# read-set byte; scatter reads and writes it; resolve reads it and writes the
-# winner; apply reads the winner and stores the value)
+# and the bytes the bucketed passes stream (bin reads the entry and a
+# read-set byte and writes the entry into its bucket; resolve reads it and
+# writes the winner; apply reads the winner and stores its 8-byte slot)
 VALIDATE_APPLY_BYTES_PER_ENTRY = 40.0
-VALIDATE_APPLY_STREAM_BYTES_PER_ENTRY = 16 + 1 + 32 + 32 + 16 + 4
+VALIDATE_APPLY_STREAM_BYTES_PER_ENTRY = 16 + 1 + 16 + 32 + 16 + 8
 
 
 KERNEL_SOURCES = {"k_exec_oplist": ("exec.hip", "hetm_dev.h"),
