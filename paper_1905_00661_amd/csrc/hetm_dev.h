@@ -86,7 +86,7 @@ struct DevCounters {
     uint32_t n_dirty;             // write-set granules found by the compaction
     uint32_t n_runs;              // maximal runs of consecutive dirty granules
     uint32_t retry_txn;           // first transaction that hit the retry cap
-    uint32_t scan_ticket;         // blocks finished in the compaction count pass
+    uint32_t scan_ticket;         // groups of blocks finished in the compaction count pass
     uint32_t err_index;           // index of the first bad log entry / transaction
     uint32_t chunk_conflict;      // the current chunk's flags, folded in when it applies
     uint32_t doomed;              // epoch of the last round early validation doomed
@@ -101,6 +101,7 @@ struct DevCounters {
     uint32_t log_spill;           // entries of the current chunk's spill area in use
     uint32_t log_ndesc;           // spill chunks of the current chunk
     uint32_t log_sub[kSubTickets];    // apply blocks finished, per group of blocks (b mod kSubTickets)
+    uint32_t scan_sub[kSubTickets];   // compaction count blocks finished, per group of blocks
 };
 
 // Everything a kernel needs: constant context state plus the arguments of

@@ -108,8 +108,14 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_count(const DevArgs *_
         st_agent(&a->blocksums[blockIdx.x], c);
         st_agent(&a->blockruns[blockIdx.x], r);
         hw_order();
-        uint32_t done = __hip_atomic_fetch_add(&cnt->scan_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = done == gridDim.x - 1;
+        // finished blocks counted per group, then the groups (the last
+        // block of a group counts it after its group's blocks counted)
+        const uint32_t g = blockIdx.x % kSubTickets, ng = gridDim.x < kSubTickets ? gridDim.x : kSubTickets;
+        const uint32_t in_g = (gridDim.x - g + kSubTickets - 1) / kSubTickets;
+        bool last = false;
+        if (__hip_atomic_fetch_add(&cnt->scan_sub[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == in_g - 1)
+            last = __hip_atomic_fetch_add(&cnt->scan_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ng - 1;
+        s_last = last;
     }
     __syncthreads();
     if (!s_last) return;
@@ -134,6 +140,7 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_count(const DevArgs *_
         st_agent(&cnt->n_dirty, total);
         st_agent(&cnt->n_runs, runs);
         st_agent(&cnt->scan_ticket, 0u);
+        for (uint32_t g = 0; g < kSubTickets; ++g) st_agent(&cnt->scan_sub[g], 0u);
     }
 }
 
@@ -367,7 +374,7 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         c.apply_ver = 0;
         c.log_spill = 0;
         c.log_ndesc = 0;
-        for (uint32_t g = 0; g < kSubTickets; ++g) c.log_sub[g] = 0;
+        for (uint32_t g = 0; g < kSubTickets; ++g) c.log_sub[g] = c.scan_sub[g] = 0;
         c.doomed = ld_agent(&cnt->doomed);
         if (!err) {
             const uint64_t f = c.max_ts > c.floor_ts ? c.max_ts : c.floor_ts;
