@@ -261,6 +261,51 @@ def test_doomed_round_ran_fewer(hm, wl):
     ctx.close()
 
 
+def test_doomed_round_with_added_batches(hm, wl):
+    """A streamed round whose first batch reads a hot word everywhere; the
+    host pushes one-entry chunks writing that word until one comes back
+    doomed, then adds three more batches: the round is a conflict, every
+    batch's transactions are reported aborted, the added batches leave at
+    once (the round ran far fewer transactions than it was given), and both
+    replicas equal the host's."""
+    import torch
+    n_words, n = 1 << 22, 1 << 18
+    g = np.random.default_rng(23)
+    init = g.integers(0, 2 ** 32, size=n_words, dtype=np.uint64).astype(np.uint32)
+    batches = []
+    for k in range(4):
+        idx = g.integers(0, n_words // 2, size=8 * n, dtype=np.uint64)
+        idx[::8] = g.integers(0, 64, size=n, dtype=np.uint64)
+        batches.append(hm.Batch(1, wl._oplist_from_lists(np.full(n, 8, np.uint64), np.full(n, 2), idx, k * n)))
+    ctx = hm.Context(n_words, 4, 16, init=init, batch_capacity=n, log_capacity=256, mode=hm.HETM_MODE_GRAPH)
+    pieces = wl.host_log_uniform(g, 256, n_words // 2, n_words, 0)
+    pieces["word"] = 5
+    pieces["value"] = 777
+    host_t = hm.pinned(n_words * 4)
+    host_t.numpy()[:] = wl.host_replica(init, pieces).view(np.uint8)
+    log_t = hm.to_device(pieces)
+    eb = pieces.dtype.itemsize
+    torch.cuda.synchronize()
+    ctx.round_begin(batches[0], host_t)
+    pushed, d = 0, 0
+    while not d and pushed < 256:
+        d = ctx.round_push(log_t[pushed * eb:(pushed + 1) * eb], 1, wait=True)
+        pushed += 1
+    for b in batches[1:]:
+        ctx.round_add(b)
+    res = ctx.round_end()
+    ctx.sync()
+    ran = int(ctx.stats().txns_aborted)
+    say(f"doomed after {pushed} entries, then 3 batches added; transactions run: {ran} of {4 * n}")
+    assert d == 1 and res.doomed == 1 and res.conflict == 1
+    assert int(res.n_aborted) == 4 * n and int(res.n_committed) == 0
+    assert ran < n, "the batches added to a doomed round ran"
+    H = wl.host_replica(init, pieces[:pushed])
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), H)
+    assert np.array_equal(host_t.numpy().view(np.uint32), H)
+    ctx.close()
+
+
 def test_stream_errors(hm, wl):
     """Out-of-order calls give ESTATE; a push past the capacity gives
     ECAPACITY and appends nothing; a pushed entry outside the replica fails
