@@ -219,9 +219,8 @@ int enqueue_merge(hetm_ctx *c, uint32_t outcome, const void *host_dev, uint32_t 
     launch_undo(c->dargs, c->undo_cap, c->stream);
     launch_compact(c->dargs, c->args.n_scan_blocks, c->stream);
     launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, c->stream);
-    launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, c->stream);
+    launch_finish(c->dargs, c->snap_map, c->args.n_rs_words, c->stream);
     HIP_TRY(c, hipGetLastError());
-    HIP_TRY(c, hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipEventRecord(c->closed_ev, c->stream));
     c->closed_recorded = true;
     c->chunks_in_round = 0;
@@ -393,8 +392,7 @@ int capture_round(hetm_ctx *c, uint32_t policy, Part part, hetm_ctx::RoundGraph 
             launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
     }
     if (part != Part::kExec) {
-        launch_finish(c->dargs, c->snap_dev, c->args.n_rs_words, s);
-        (void)hipMemcpyAsync(c->snap_host, c->snap_dev, sizeof(DevCounters), hipMemcpyDeviceToHost, s);
+        launch_finish(c->dargs, c->snap_map, c->args.n_rs_words, s);
     }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
@@ -855,7 +853,6 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
     TRY(dev_alloc(c, &c->log_staging, k.log_capacity * c->log_entry_bytes));
     TRY(dev_alloc(c, &c->cnt, sizeof(DevCounters)));
     TRY(dev_alloc(c, &c->hot, sizeof(HotCounters)));
-    TRY(dev_alloc(c, &c->snap_dev, sizeof(DevCounters)));
     TRY(dev_alloc(c, &c->dargs, sizeof(DevArgs)));
     if (k.async_merge) {
         for (int b = 0; b < 2; ++b) {
@@ -883,6 +880,11 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
         hipHostMalloc((void **)&c->snap_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->cnt_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess)
         return alloc_fail(c, HETM_ENOMEM, "pinned host counters");
+    // the round's finish kernel stores its counter snapshot straight into
+    // pinned host memory (no copy after it on the round's critical path)
+    if (hipHostGetDevicePointer((void **)&c->snap_map, c->snap_host, 0) != hipSuccess || !c->snap_map)
+        return alloc_fail(c, HETM_EDEVICE, "device address of the pinned snapshot");
+    memset(c->snap_host, 0, sizeof(DevCounters));
     for (hipEvent_t *e : {&c->ev[0], &c->ev[1], &c->ev[2], &c->ev[3], &c->ev_kernel})
         if (hipEventCreate(e) != hipSuccess) return alloc_fail(c, HETM_EDEVICE, "timing events");
     if (hipStreamCreateWithFlags(&c->early_stream, hipStreamNonBlocking) != hipSuccess ||
@@ -971,7 +973,7 @@ int hetm_free(hetm_ctx *c) {
     if (c->ev_kernel) (void)hipEventDestroy(c->ev_kernel);
     void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->log_desc, c->log_bstart, c->log_bwin, c->log_head,
                    c->log_cursor, c->log_sorted, c->log_win, c->blocksums, c->blockruns, c->ids, c->order, c->undo,
-                   c->tx_tab, c->tx_hot, c->tx_chain, c->log_staging, c->cnt, c->hot, c->snap_dev, c->dargs};
+                   c->tx_tab, c->tx_hot, c->tx_chain, c->log_staging, c->cnt, c->hot, c->dargs};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->hargs) (void)hipHostFree(c->hargs);

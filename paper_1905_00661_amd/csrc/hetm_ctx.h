@@ -42,7 +42,7 @@ struct hetm_ctx {
     void *log_staging = nullptr;
     DevCounters *cnt = nullptr;
     HotCounters *hot = nullptr;
-    DevCounters *snap_dev = nullptr;
+    DevCounters *snap_map = nullptr;   // snap_host as the device addresses it (the finish kernel writes it)
     DevArgs *dargs = nullptr;
     uint64_t device_bytes = 0;
     void *scratch = nullptr;           // this device's copy of the no-allocation read array
