@@ -42,6 +42,7 @@ import argparse
 import ctypes
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -150,18 +151,13 @@ def pct(a, q):
 
 def shifted_logs(torch, hm, base_log: np.ndarray, n_log: int, rounds: int, dev: str, inject=None):
     """Per-round logs resident in HBM: the same words and values, timestamps
-    shifted past the previous round's; inject(r, log) may edit round r's."""
+    shifted past the previous round's; inject(r, copy) may return an edited
+    copy (copy() makes one) of round r's log, else None."""
     base = hm.to_device(base_log, dev)
     logs = []
     for r in range(rounds):
-        if inject is not None:
-            lr = base_log.copy()
-            if inject(r, lr):
-                t = hm.to_device(lr, dev)
-            else:
-                t = base.clone()
-        else:
-            t = base.clone()
+        lr = inject(r, base_log.copy) if inject is not None else None
+        t = hm.to_device(lr, dev) if lr is not None else base.clone()
         t.view(torch.int64).view(-1, 2)[:, 1].add_(r * n_log)
         logs.append(t)
     torch.cuda.synchronize()
@@ -409,20 +405,22 @@ def small_round(args, hm, wl, torch, dev) -> dict:
     return out
 
 
-def conflict_form(args, hm, wl, torch, ri, dev) -> dict:
-    """Batched large rounds where, in a seeded 10% of the rounds, one log
-    entry is redirected to a word the batch reads (CPU wins: the round's GPU
-    transactions abort and its dirty granules come back from the host)."""
+def conflict_form(args, hm, wl, torch, ri, dev, rate: float = 0.1) -> dict:
+    """Batched large rounds where, in a seeded fraction `rate` of the rounds,
+    one log entry is redirected to a word the batch reads (CPU wins: the
+    round's GPU transactions abort and the device rolls them back)."""
     N, G, n_log = ri.n_words, ri.granule, ri.log.shape[0]
-    rounds = args.warmup + args.steps
+    steps = max(args.steps, min(500, int(math.ceil(5 / rate))))   # about five conflicting rounds at least
+    rounds = args.warmup + steps
     g = np.random.default_rng(0x190500661)
-    hits = set(int(r) for r in np.flatnonzero(g.random(rounds) < 0.1))
+    hits = set(int(r) for r in np.flatnonzero(g.random(rounds) < rate))
 
-    def inject(r, lr):
+    def inject(r, copy):
         if r not in hits:
-            return False
+            return None
+        lr = copy()
         lr["word"][int(g.integers(0, n_log))] = ri.batch.idx[int(g.integers(0, ri.batch.idx.shape[0]))]
-        return True
+        return lr
 
     logs = shifted_logs(torch, hm, ri.log, n_log, rounds, dev, inject=inject)
     host = hm.pinned(N * 4)
@@ -445,10 +443,10 @@ def conflict_form(args, hm, wl, torch, ri, dev) -> dict:
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.close()
-    return {"value": committed / el, "unit": "txn/s", "rounds": args.steps, "conflict_rounds": len(lat_cf),
+    return {"value": committed / el, "unit": "txn/s", "rounds": steps, "conflict_rounds": len(lat_cf),
             "p50_clean_round_ms": pct(lat_ok, 50), "p50_conflict_round_ms": pct(lat_cf, 50),
             "max_conflict_round_ms": max(lat_cf) if lat_cf else None,
-            "form": "batched, CPU wins, r = 10% of rounds conflicting"}
+            "form": f"batched, CPU wins, r = {rate:.0%} of rounds conflicting"}
 
 
 def sweep_form(args, hm, wl, torch, dev) -> dict:
@@ -519,11 +517,12 @@ def early_form(args, hm, wl, torch, ri, dev) -> dict:
         g = np.random.default_rng(seed)
         hits = g.random(rounds) < frac
 
-        def inject(r, lr):
+        def inject(r, copy):
             if not hits[r]:
-                return False
+                return None
+            lr = copy()
             lr["word"][int(g.integers(0, n_log))] = b_idx[int(g.integers(0, b_idx.shape[0]))]
-            return True
+            return lr
         ls = shifted_logs(torch, hm, ri.log, n_log, rounds, dev, inject=inject)
         for t in ls:
             t.view(torch.int64).view(-1, 2)[:, 1].add_(shift[0])
@@ -586,6 +585,24 @@ def early_form(args, hm, wl, torch, ri, dev) -> dict:
     return out
 
 
+# Algorithmic bytes per committed transaction of the bank and cache
+# programs: the descriptor, the words the transaction must read and write,
+# its results and ticket (no lock or map traffic).  TRANSFER: src, dst, amt
+# (12) + two balances read (16) and written (16) + three results (24) +
+# ticket (4).  CACHE: key, op, tid (13) + the set's 8 keys (64) + 9 result
+# words (36) + ticket (4), and a GET's 8-word value read (32) or a PUT's
+# key, value and stamps written (48).
+TRANSFER_BYTES = 12 + 16 + 16 + 24 + 4
+CACHE_BYTES = 13 + 64 + 36 + 4
+CACHE_GET_BYTES, CACHE_PUT_BYTES = 32, 48
+
+
+def small_roofline(bytes_per_s: float) -> dict:
+    gbps = bytes_per_s / 1e9
+    return {"bound": "hot-object serialization (chains run one transaction per lane step)",
+            "alg_GBps": gbps, "peak_GBps": HBM_PEAK_GBPS, "frac": gbps / HBM_PEAK_GBPS}
+
+
 def bank_form(args, hm, wl, torch, dev) -> dict:
     """Bank transfers at full size: 2^24 int64 accounts, U[2^20, 2^21]
     Zipf(0.9) transfers per round on the GPU, the host TM's 2^15 transfers
@@ -619,7 +636,9 @@ def bank_form(args, hm, wl, torch, dev) -> dict:
     ctx.close()
     timed = rows[1:] if len(rows) > 1 else rows
     committed = sum(x["committed"] for x in timed)
-    return {"value": committed / sum(x["s"] for x in timed), "unit": "txn/s",
+    rate = committed / sum(x["s"] for x in timed)
+    return {"value": rate, "unit": "txn/s",
+            "roofline": {**small_roofline(rate * TRANSFER_BYTES), "alg_bytes_per_txn": TRANSFER_BYTES},
             "ms_per_round": 1e3 * float(np.mean([x["s"] for x in timed])),
             "transfers_per_round": float(np.mean([x["n"] for x in timed])),
             "retries_per_commit": sum(x["retries"] for x in timed) / max(committed, 1),
@@ -661,13 +680,18 @@ def cache_form(args, hm, wl, torch, dev) -> dict:
         rr = ctx.round(bb, log_t, hlog.shape[0], host)
         ctx.sync()
         el = time.perf_counter() - t1
-        rows.append({"s": el, "committed": rr.n_committed, "retries": rr.n_local_retries, "conflict": rr.conflict})
+        n_put = int((b.op == wl.CACHE_PUT).sum())
+        rows.append({"s": el, "committed": rr.n_committed, "retries": rr.n_local_retries, "conflict": rr.conflict,
+                     "bytes": rr.n_committed * CACHE_BYTES + (b.n - n_put) * CACHE_GET_BYTES + n_put * CACHE_PUT_BYTES})
         log(f"cache round {r}: {1e3 * el:.1f} ms, retries {rr.n_local_retries}")
     tm.close()
     ctx.close()
     timed = rows[1:] if len(rows) > 1 else rows
     committed = sum(x["committed"] for x in timed)
-    return {"value": committed / sum(x["s"] for x in timed), "unit": "txn/s",
+    secs = sum(x["s"] for x in timed)
+    return {"value": committed / secs, "unit": "txn/s",
+            "roofline": {**small_roofline(sum(x["bytes"] for x in timed) / secs),
+                         "alg_bytes_per_txn": sum(x["bytes"] for x in timed) / max(committed, 1)},
             "ms_per_round": 1e3 * float(np.mean([x["s"] for x in timed])),
             "retries_per_commit": sum(x["retries"] for x in timed) / max(committed, 1),
             "conflict_rounds": sum(x["conflict"] for x in rows), "warmup_s": warm_s, "rounds_timed": len(timed),
@@ -801,6 +825,8 @@ def main():
     ap.add_argument("--small-rounds", type=int, default=200)
     ap.add_argument("--bank-rounds", type=int, default=3)
     ap.add_argument("--cache-rounds", type=int, default=3)
+    ap.add_argument("--conflict-rates", default="0.01,0.1",
+                    help="fractions of rounds with an injected inter-device conflict (conflict leg)")
     ap.add_argument("--serve-rates", default="1e6,1e7,3e7,1e8,2e8,3e8")
     ap.add_argument("--serve-seconds", type=float, default=0.25)
     ap.add_argument("--serve-p99-bound-ms", type=float, default=5.0)
@@ -895,7 +921,11 @@ def main():
         out["small"] = small_round(args, hm, wl, torch, dev)
     if "conflict" in legs:
         log("conflicting rounds ...")
-        out["conflict"] = conflict_form(args, hm, wl, torch, ri, dev)
+        by_rate = {}
+        for rate in [float(x) for x in args.conflict_rates.split(",")]:
+            log(f"conflicting rounds at r = {rate:g} ...")
+            by_rate[f"{rate:g}"] = conflict_form(args, hm, wl, torch, ri, dev, rate)
+        out["conflict"] = {**by_rate.get("0.1", next(iter(by_rate.values()))), "by_rate": by_rate}
     if "sweep" in legs:
         log("granule and hot-fraction sweep ...")
         out["sweep"] = sweep_form(args, hm, wl, torch, dev)
