@@ -374,6 +374,40 @@ int hetm_round_add(hetm_ctx *ctx, uint32_t program, const void *descs, uint64_t 
  * hetm_round; ESTATE without an open streamed round. */
 int hetm_round_end(hetm_ctx *ctx, hetm_round_result *res);
 
+/* Queued rounds (GRAPH mode with async_merge): the rounds of hetm_round,
+ * submitted up to two ahead so that the GPU starts the next round as soon
+ * as one ends, without waiting for the host to take the last outcome and
+ * launch again (the CPU-GPU synchronization point of §IV-C stays at the end
+ * of every round; only the launch of the next round moves ahead of it).
+ *
+ * hetm_round_submit checks the arguments as hetm_round does and launches
+ * the round behind those already queued, without waiting.  Everything
+ * args points to (descriptors, results, tickets, log, flags_bits, ids_out,
+ * host_replica) is read or written until the round is collected.  A round
+ * submitted behind another has the same program.  Errors: EINVAL,
+ * ECAPACITY; ESTATE (PLAIN mode or no async_merge, two rounds queued, a
+ * streamed or step-API round open, another program behind a queued round).
+ *
+ * hetm_round_collect waits for the oldest queued round and handles and
+ * reports it exactly as hetm_round would have (res as there; us_total is
+ * the round's graph time).  The host replica rules of hetm_round apply per
+ * collected round.  A round whose outcome needs the host before the next
+ * may run -- a latched device error, or a conflict under CPU wins that the
+ * undo log cannot roll back -- holds the round queued behind it, which then
+ * runs empty; collect handles the held round (discard, or restore from the
+ * host replica) and launches the one behind it again, so its result is
+ * that of a round run after the held one.  After a device error the round
+ * behind is cancelled instead: its collect returns ESTATE and it did not
+ * run (resubmit it).  Errors: as hetm_round for the collected round;
+ * ESTATE (nothing queued, or the round was cancelled).
+ *
+ * While rounds are queued, every other call that queues work or reads the
+ * state (hetm_round, hetm_round_begin, the step API, hetm_serve, the state
+ * reads, hetm_set_*) returns ESTATE; hetm_sync waits for the queued rounds
+ * without collecting them. */
+int hetm_round_submit(hetm_ctx *ctx, const hetm_round_args *args);
+int hetm_round_collect(hetm_ctx *ctx, hetm_round_result *res);
+
 /* ------------------------------------------------------------- auxiliary */
 
 const char *hetm_strerror(int code);

@@ -140,6 +140,12 @@ int read_counters(hetm_ctx *c, DevCounters *out) {
     return HETM_OK;
 }
 
+// Calls that queue work of their own, or read the state, wait until the
+// rounds queued by hetm_round_submit have been collected.
+int refuse_queued(hetm_ctx *c) {
+    return c->q_n ? fail(c, HETM_ESTATE, "%u queued rounds not collected", c->q_n) : HETM_OK;
+}
+
 // Returns a latched device error (and clears it so the context stays usable).
 int take_device_error(hetm_ctx *c, int32_t code, uint32_t where) {
     if (code == HETM_OK) return HETM_OK;
@@ -258,8 +264,9 @@ void maybe_reset_versions(hetm_ctx *c, uint32_t clock) {
     c->stats.version_resets++;
 }
 
-void account_round(hetm_ctx *c, const DevCounters &s, uint64_t n_txns, hetm_round_result *res) {
-    if (!s.error) maybe_reset_versions(c, s.clock_base);
+void account_round(hetm_ctx *c, const DevCounters &s, uint64_t n_txns, hetm_round_result *res,
+                   bool may_reset = true) {
+    if (!s.error && may_reset) maybe_reset_versions(c, s.clock_base);
     const bool gpu_won = s.conflict && c->args.policy == HETM_POLICY_GPU_WINS;
     const bool gpu_lost = s.conflict && !gpu_won;
     c->stats.rounds++;
@@ -331,6 +338,8 @@ void drop_graphs(hetm_ctx *c) {
     for (auto &g : c->graphs) drop_graph(g);
     for (auto &p : c->sgraphs)
         for (auto &g : p) drop_graph(g);
+    for (auto &p : c->qgraphs)
+        for (auto &g : p) drop_graph(g);
 }
 
 // Captures the round for one merge policy on a private non-blocking stream
@@ -348,7 +357,8 @@ void drop_graphs(hetm_ctx *c) {
 // the tail (validation and apply, merge, finish) of a streamed round.
 enum class Part { kWhole, kExec, kTail };
 
-int capture_round(hetm_ctx *c, uint32_t policy, Part part, hetm_ctx::RoundGraph &rg) {
+// snap: where the finish kernel stores the round's counter snapshot.
+int capture_round(hetm_ctx *c, uint32_t policy, Part part, hetm_ctx::RoundGraph &rg, DevCounters *snap) {
     if (rg.exec) return HETM_OK;
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     const bool fork = c->cfg.async_merge && policy == HETM_POLICY_CPU_WINS;
@@ -392,7 +402,7 @@ int capture_round(hetm_ctx *c, uint32_t policy, Part part, hetm_ctx::RoundGraph 
             launch_copy(c->dargs, c->cfg.n_words, c->cfg.granule_words, c->cfg.word_bytes, c->slot, s);
     }
     if (part != Part::kExec) {
-        launch_finish(c->dargs, c->snap_map, c->args.n_rs_words, s);
+        launch_finish(c->dargs, snap, c->args.n_rs_words, s);
     }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
@@ -428,7 +438,9 @@ int capture_round(hetm_ctx *c, uint32_t policy, Part part, hetm_ctx::RoundGraph 
     return HETM_OK;
 }
 
-int build_graph(hetm_ctx *c, uint32_t policy) { return capture_round(c, policy, Part::kWhole, c->graphs[policy]); }
+int build_graph(hetm_ctx *c, uint32_t policy) {
+    return capture_round(c, policy, Part::kWhole, c->graphs[policy], c->snap_map);
+}
 
 // Uploads the current arguments into a graph's argument node and launches it.
 int launch_round_graph(hetm_ctx *c, hetm_ctx::RoundGraph &rg, hipStream_t s) {
@@ -454,9 +466,9 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
 
 // Success path of the double-buffered merge for staging buffer b holding D
 // packed granules bound for host replica `host`: a copy on the copy stream
-// into pinned host staging after the round's graph (c->ev[3], not yet re-recorded), then a job for
-// the merge worker.
-int stage_to_host(hetm_ctx *c, int b, uint64_t D, void *host) {
+// into pinned host staging once the round's graph has ended (event `after`),
+// then a job for the merge worker.
+int stage_to_host(hetm_ctx *c, int b, uint64_t D, void *host, hipEvent_t after) {
     const uint64_t gbytes = (uint64_t)c->cfg.granule_words * c->cfg.word_bytes;
     // the job that last used this host staging buffer has been scattered out
     // of it (the other buffer's job may still be scattering: this copy
@@ -464,7 +476,7 @@ int stage_to_host(hetm_ctx *c, int b, uint64_t D, void *host) {
     if (c->merge_seq[b] && hetm::merge_wait(c->merger, c->merge_seq[b]) != HETM_OK)
         return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
     if (D > c->host_cap[b]) return fail(c, HETM_ECAPACITY, "%llu dirty granules", (unsigned long long)D);
-    HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, c->ev[3], 0));      // after the round's graph
+    HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, after, 0));      // after the round's graph
     if (D) {
         HIP_TRY(c, hipMemcpyAsync(c->host_ids[b], c->stage_ids[b], D * 4, hipMemcpyDeviceToHost, c->copy_stream));
         HIP_TRY(c, hipMemcpyAsync(c->host_stage[b], c->staging[b], D * gbytes, hipMemcpyDeviceToHost, c->copy_stream));
@@ -484,7 +496,7 @@ int issue_merge(hetm_ctx *c, hipEvent_t after) {
     if (!c->merge_deferred) return HETM_OK;
     c->merge_deferred = false;
     if (after) HIP_TRY(c, hipStreamWaitEvent(c->copy_stream, after, 0));
-    return stage_to_host(c, c->deferred_buf, c->deferred_n, c->deferred_host);
+    return stage_to_host(c, c->deferred_buf, c->deferred_n, c->deferred_host, c->deferred_ev);
 }
 
 }  // namespace
@@ -518,6 +530,9 @@ int prepare_round(hetm_ctx *c, const hetm_round_args *r, const void **hdev) {
     if (c->graphs[r->policy].exec && c->graphs[r->policy].program != c->args.program) drop_graphs(c);
     for (auto &p : c->sgraphs)
         if (p[0].exec && p[0].program != c->args.program) drop_graphs(c);
+    for (auto &p : c->qgraphs)
+        for (auto &g : p)
+            if (g.exec && g.program != c->args.program) drop_graphs(c);
     return HETM_OK;
 }
 
@@ -616,8 +631,8 @@ int stream_begin(hetm_ctx *c, const hetm_round_args *r) {
     int rc = prepare_round(c, r, &hdev);
     if (rc) return rc;
     hetm_ctx::RoundGraph *g = c->sgraphs[r->policy];
-    if ((rc = capture_round(c, r->policy, Part::kExec, g[0]))) return rc;
-    if ((rc = capture_round(c, r->policy, Part::kTail, g[1]))) return rc;
+    if ((rc = capture_round(c, r->policy, Part::kExec, g[0], c->snap_map))) return rc;
+    if ((rc = capture_round(c, r->policy, Part::kTail, g[1], c->snap_map))) return rc;
     g[1].program = g[0].program;
     hipStream_t s = c->stream;
     if ((rc = wait_staging(c, s))) return rc;
@@ -704,6 +719,7 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
             if (c->merge_seq[b] && hetm::merge_wait(c->merger, c->merge_seq[b]) != HETM_OK)
                 return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
             c->merge_deferred = true;
+            c->deferred_ev = c->ev[3];     // re-recorded only after the next round_begin has issued the copy
             c->deferred_buf = b;
             c->deferred_n = snap.n_dirty;
             c->deferred_host = c->round_host;
@@ -725,6 +741,126 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     account_round(c, snap, r->n_txns, res);
     if (res) res->us_total = elapsed_us(c->ev[0], c->ev[3]);
     c->stats.log_entries += r->n_log;
+    return HETM_OK;
+}
+
+// Launches queued round q (its arguments checked and set up again) in its
+// slot's graph; gated: behind a round the host has not collected.
+int launch_queued(hetm_ctx *c, hetm_ctx::Queued &q, bool gated) {
+    const void *hdev = nullptr;
+    int rc = prepare_round(c, &q.r, &hdev);
+    if (rc) return rc;
+    const void *dlog = nullptr;
+    if (q.r.n_log && (rc = stage_log(c, q.r.log, q.r.n_log, &dlog))) return rc;
+    c->args.log = dlog;
+    c->args.n_log = (uint32_t)q.r.n_log;
+    hetm_ctx::RoundGraph &g = c->qgraphs[q.r.policy][q.slot];
+    if ((rc = capture_round(c, q.r.policy, Part::kWhole, g, c->snap_map + q.slot))) return rc;
+    // the slot's staging buffer: the copy of the round that last filled it
+    // was issued when that round was collected
+    hipStream_t s = c->stream;
+    const int b = q.slot;
+    if (c->pending[b]) HIP_TRY(c, hipStreamWaitEvent(s, c->copied[b], 0));
+    c->args.staging = c->staging[b];
+    c->args.stage_ids = c->stage_ids[b];
+    c->args.stage_count = c->stage_count[b];
+    c->args.gated = gated;
+    HIP_TRY(c, hipEventRecord(c->q_begin[b], s));
+    rc = launch_round_graph(c, g, s);
+    c->args.gated = 0;
+    if (rc) return rc;
+    HIP_TRY(c, hipEventRecord(c->q_end[b], s));
+    q.hdev = hdev;
+    return HETM_OK;
+}
+
+int round_submit(hetm_ctx *c, const hetm_round_args *r) {
+    if (c->cfg.mode != HETM_MODE_GRAPH || !c->cfg.async_merge)
+        return fail(c, HETM_ESTATE, "round_submit needs GRAPH mode with the double-buffered merge");
+    if (c->q_n == 2) return fail(c, HETM_ESTATE, "two rounds are queued: collect one first");
+    if (c->in_validation || c->round_open) return fail(c, HETM_ESTATE, "a round is already open");
+    if (c->q_n) {
+        // the queued rounds' graphs stay as they are
+        const uint32_t prog = r->n_txns ? r->program : c->args.program;
+        if (prog != c->args.program)
+            return fail(c, HETM_ESTATE, "program %u behind a queued round of program %u", prog, c->args.program);
+    } else {
+        // a staged copy of an earlier round goes out before a slot's buffer
+        // is reused (its copied event is recorded as it is issued)
+        int rc = issue_merge(c, nullptr);
+        if (rc) return rc;
+    }
+    hetm_ctx::Queued &q = c->queued[(c->q_head + c->q_n) & 1];
+    q = hetm_ctx::Queued{};
+    q.r = *r;
+    q.seq = c->q_seq;
+    q.slot = (int)(c->q_seq & 1);
+    const DevArgs keep = c->args;
+    int rc = launch_queued(c, q, c->q_n > 0);
+    if (rc) {
+        c->args = keep;
+        return rc;
+    }
+    ++c->q_seq;
+    ++c->q_n;
+    return HETM_OK;
+}
+
+int round_collect(hetm_ctx *c, hetm_round_result *res) {
+    if (c->q_n == 0) return fail(c, HETM_ESTATE, "no round queued");
+    hetm_ctx::Queued q = c->queued[c->q_head];
+    hetm_ctx::Queued *next = c->q_n > 1 ? &c->queued[(c->q_head + 1) & 1] : nullptr;
+    c->q_head = (c->q_head + 1) & 1;
+    --c->q_n;
+    if (q.cancelled) return fail(c, HETM_ESTATE, "round not run: the round queued before it failed");
+    HIP_TRY(c, hipEventSynchronize(c->q_end[q.slot]));
+    const DevCounters snap = c->snap_host[q.slot];
+    ++c->epoch;
+    const int b = q.slot;
+    c->buf = b ^ 1;                 // a round outside the queue takes the other buffer next
+    const bool undo_ok = c->undo_cap && !snap.undo_over;
+    int rc;
+    if (snap.hold) {
+        // the round behind ran empty (its upload saw the hold); once it has
+        // ended the stream is idle and this round is handled as round_end
+        // handles it
+        if (next) HIP_TRY(c, hipEventSynchronize(c->q_end[next->slot]));
+        if (snap.error) {
+            if (next) next->cancelled = true;
+            if (!undo_ok && (rc = drain_merges(c))) return rc;
+            return discard_round(c, snap.error, snap.err_index, q.hdev, undo_ok);
+        }
+        // conflict under CPU wins without a whole undo log: the dirty
+        // granules come back from the host replica (done before returning,
+        // as hetm_round does), then the round behind runs for real
+        if ((rc = drain_merges(c))) return rc;
+        launch_restore(c->stmr, q.hdev, c->stage_ids[b], c->stage_count[b], c->cfg.n_words, c->cfg.granule_words,
+                       c->cfg.word_bytes, c->slot, c->stream);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (next && (rc = launch_queued(c, *next, false))) return rc;
+    } else if (!snap.error && (!snap.conflict || q.r.policy == HETM_POLICY_GPU_WINS)) {
+        // the GPU's granules go to the host replica: the round behind is
+        // already queued, so the copy is issued now (after this round's end)
+        if (c->merge_seq[b] && hetm::merge_wait(c->merger, c->merge_seq[b]) != HETM_OK)
+            return fail(c, HETM_EDEVICE, "merge copy to the host replica failed");
+        c->merge_deferred = true;
+        c->deferred_ev = c->q_end[b];
+        c->deferred_buf = b;
+        c->deferred_n = snap.n_dirty;
+        c->deferred_host = q.r.host_replica;
+        c->pending[b] = true;
+        c->last_copy = b;
+        if (res) res->merge_pending = 1;
+        if (next && (rc = issue_merge(c, nullptr))) return rc;
+    }
+    // a version reset queued here runs after the round behind, whose
+    // snapshot then still shows the clock from before it
+    const uint64_t resets = c->stats.version_resets;
+    account_round(c, snap, q.r.n_txns, res, q.seq >= c->reset_floor_seq);
+    if (c->stats.version_resets != resets) c->reset_floor_seq = c->q_seq;
+    if (res) res->us_total = elapsed_us(c->q_begin[b], c->q_end[b]);
+    c->stats.log_entries += q.r.n_log;
     return HETM_OK;
 }
 
@@ -877,15 +1013,16 @@ int hetm_alloc_stmr(const hetm_config *cfg, const void *init_image, hetm_ctx **o
                 return alloc_fail(c, HETM_EDEVICE, "merge events");
     }
     if (hipHostMalloc((void **)&c->hargs, sizeof(DevArgs), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->snap_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->snap_host, 2 * sizeof(DevCounters), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->cnt_host, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess)
         return alloc_fail(c, HETM_ENOMEM, "pinned host counters");
     // the round's finish kernel stores its counter snapshot straight into
     // pinned host memory (no copy after it on the round's critical path)
     if (hipHostGetDevicePointer((void **)&c->snap_map, c->snap_host, 0) != hipSuccess || !c->snap_map)
         return alloc_fail(c, HETM_EDEVICE, "device address of the pinned snapshot");
-    memset(c->snap_host, 0, sizeof(DevCounters));
-    for (hipEvent_t *e : {&c->ev[0], &c->ev[1], &c->ev[2], &c->ev[3], &c->ev_kernel})
+    memset(c->snap_host, 0, 2 * sizeof(DevCounters));
+    for (hipEvent_t *e : {&c->ev[0], &c->ev[1], &c->ev[2], &c->ev[3], &c->ev_kernel, &c->q_begin[0], &c->q_begin[1],
+                          &c->q_end[0], &c->q_end[1]})
         if (hipEventCreate(e) != hipSuccess) return alloc_fail(c, HETM_EDEVICE, "timing events");
     if (hipStreamCreateWithFlags(&c->early_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->closed_ev, hipEventDisableTiming) != hipSuccess ||
@@ -971,6 +1108,8 @@ int hetm_free(hetm_ctx *c) {
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->ev_kernel) (void)hipEventDestroy(c->ev_kernel);
+    for (hipEvent_t e : {c->q_begin[0], c->q_begin[1], c->q_end[0], c->q_end[1]})
+        if (e) (void)hipEventDestroy(e);
     void *dev[] = {c->stmr, c->locks, c->ts, c->rs, c->ws, c->log_desc, c->log_bstart, c->log_bwin, c->log_head,
                    c->log_cursor, c->log_sorted, c->log_win, c->blocksums, c->blockruns, c->ids, c->order, c->undo,
                    c->tx_tab, c->tx_hot, c->tx_chain, c->log_staging, c->cnt, c->hot, c->dargs};
@@ -1000,6 +1139,7 @@ int hetm_free(hetm_ctx *c) {
 int hetm_submit_batch(hetm_ctx *c, uint32_t program, const void *descs, uint64_t n_txns, void *results,
                       uint32_t *tickets) {
     if (!c) return HETM_EINVAL;
+    if (int rc = refuse_queued(c)) return rc;
     if (c->in_validation) return fail(c, HETM_ESTATE, "submit after validation started in this round");
     c->args.policy = HETM_POLICY_CPU_WINS;     // the step API applies each chunk as it comes
     if (n_txns == 0) return HETM_OK;
@@ -1013,6 +1153,7 @@ int hetm_submit_batch(hetm_ctx *c, uint32_t program, const void *descs, uint64_t
 
 int hetm_validate_apply_log(hetm_ctx *c, const void *log, uint64_t n, uint32_t *flags_bits, uint32_t *conflict_out) {
     if (!c) return HETM_EINVAL;
+    if (int rc = refuse_queued(c)) return rc;
     if (n > c->cfg.log_capacity) return fail(c, HETM_ECAPACITY, "log chunk %llu > capacity", (unsigned long long)n);
     if (n && !log) return fail(c, HETM_EINVAL, "null log");
     c->in_validation = true;
@@ -1036,6 +1177,7 @@ int hetm_validate_apply_log(hetm_ctx *c, const void *log, uint64_t n, uint32_t *
 int hetm_copyback_dirty(hetm_ctx *c, uint32_t conflict, void *host_replica, uint64_t *n_dirty_out,
                         uint32_t *ids_out) {
     if (!c) return HETM_EINVAL;
+    if (int rc = refuse_queued(c)) return rc;
     if (conflict > 1 && conflict != HETM_OUTCOME_DEVICE) return fail(c, HETM_EINVAL, "bad outcome %u", conflict);
     const void *hdev = nullptr;
     int rc = check_host_replica(c, host_replica, &hdev);
@@ -1055,6 +1197,7 @@ int hetm_copyback_dirty(hetm_ctx *c, uint32_t conflict, void *host_replica, uint
 int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     if (!c || !r) return HETM_EINVAL;
     if (res) memset(res, 0, sizeof *res);
+    if (int rc = refuse_queued(c)) return rc;
     if (c->cfg.mode == HETM_MODE_GRAPH) {
         int rc = hetm::round_begin(c, r);
         if (rc) return rc;
@@ -1111,7 +1254,19 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
 
 int hetm_round_begin(hetm_ctx *c, const hetm_round_args *r) {
     if (!c || !r) return HETM_EINVAL;
+    if (int rc = refuse_queued(c)) return rc;
     return hetm::stream_begin(c, r);
+}
+
+int hetm_round_submit(hetm_ctx *c, const hetm_round_args *r) {
+    if (!c || !r) return HETM_EINVAL;
+    return hetm::round_submit(c, r);
+}
+
+int hetm_round_collect(hetm_ctx *c, hetm_round_result *res) {
+    if (!c) return HETM_EINVAL;
+    if (res) memset(res, 0, sizeof *res);
+    return hetm::round_collect(c, res);
 }
 
 int hetm_round_push(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out) {
@@ -1133,6 +1288,7 @@ int hetm_round_end(hetm_ctx *c, hetm_round_result *res) {
 
 int hetm_early_validate(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out) {
     if (!c || (n && !log)) return HETM_EINVAL;
+    if (int rc = refuse_queued(c)) return rc;
     if (c->cfg.mode != HETM_MODE_PLAIN) return fail(c, HETM_ESTATE, "early validation needs the step API");
     if (n) {
         const void *dlog = device_view(log);
@@ -1156,6 +1312,7 @@ int hetm_early_validate(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doom
 
 int hetm_set_version_clock(hetm_ctx *c, uint32_t value) {
     if (!c) return HETM_EINVAL;
+    if (int rc = refuse_queued(c)) return rc;
     if (!c->slot) return fail(c, HETM_ESTATE, "the context keeps no version clock (split layout)");
     if (c->round_open || c->in_validation) return fail(c, HETM_ESTATE, "a round is open");
     if (value >= kClockLimit) return fail(c, HETM_EINVAL, "clock %u past the limit", value);
@@ -1170,6 +1327,7 @@ int hetm_set_version_clock(hetm_ctx *c, uint32_t value) {
 
 int hetm_set_exec_workgroups(hetm_ctx *c, uint32_t workgroups) {
     if (!c || c->round_open) return HETM_EINVAL;
+    if (int rc = refuse_queued(c)) return rc;
     if (workgroups == 0) {
         hipDeviceProp_t prop;
         int cus = 256;
@@ -1215,6 +1373,7 @@ uint64_t hetm_state_bytes(hetm_ctx *c, uint32_t what) {
 
 int hetm_read_state(hetm_ctx *c, uint32_t what, void *dst, uint64_t bytes) {
     if (!c || !dst) return HETM_EINVAL;
+    if (int rc = refuse_queued(c)) return rc;
     const void *src = what == HETM_STATE_STMR ? c->stmr
                       : what == HETM_STATE_RS  ? (const void *)c->rs
                       : what == HETM_STATE_WS  ? (const void *)c->ws
@@ -1260,6 +1419,7 @@ int hetm_read_state(hetm_ctx *c, uint32_t what, void *dst, uint64_t bytes) {
 
 int hetm_read_words_noalloc(hetm_ctx *c, uint64_t first_word, uint64_t n_words, void *dst) {
     if (!c || (!dst && n_words)) return HETM_EINVAL;
+    if (int rc = refuse_queued(c)) return rc;
     if (n_words > kNoAllocWords)
         return fail(c, HETM_ECAPACITY, "hetm_read_words_noalloc: %llu words exceed the limit of %llu per call",
                     (unsigned long long)n_words, (unsigned long long)kNoAllocWords);

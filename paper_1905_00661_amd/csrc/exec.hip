@@ -1583,24 +1583,17 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
     flush_counts(ls, cnt);
 }
 
-__global__ void k_begin_batch(const DevArgs *__restrict__ a) {
-    if (threadIdx.x == 0) {
-        st_agent(&a->hot->queue_head.v, 0u);
-        st_agent(&a->hot->queue_upd.v, 0u);
-        st_agent(&a->hot->n_ro.v, 0u);
-        st_agent(&a->hot->n_upd.v, 0u);
-    }
-}
-
 // The OPLIST kind split: transaction i is an update iff nw[i] != 0.  A
 // block takes tiles of kPartPerThread x kPartBlock consecutive transactions
 // (grid-stride, so one launch shape serves every batch size): each thread
 // classifies kPartPerThread of them, a block scan places them in LDS, one
 // atomic per list and tile reserves the tile's range, and the block stores
 // both ranges with consecutive threads on consecutive entries; both lists
-// hold ascending ids within a tile.
+// hold ascending ids within a tile.  Tiles are large (16384 transactions, 64
+// for a 2^20 batch) because every tile's reservations queue on the same two
+// counters, and same-address atomics serialize.
 constexpr uint32_t kPartPerThread = 16;
-constexpr uint32_t kPartBlock = 256;
+constexpr uint32_t kPartBlock = 1024;
 constexpr uint64_t kPartTile = (uint64_t)kPartPerThread * kPartBlock;
 constexpr uint32_t kPartMaxBlocks = 1024;
 
@@ -1624,7 +1617,7 @@ __global__ __launch_bounds__(kPartBlock) void k_partition(const DevArgs *__restr
                 n_ro += 1u - u;
             }
         }
-        // block-exclusive prefix of both counts at once (each <= 4096 per tile)
+        // block-exclusive prefix of both counts at once (each <= 16384 per tile)
         const uint32_t v = n_ro << 16 | n_upd;
         uint32_t inc = v;
         for (uint32_t o = 1; o < kWave; o <<= 1) {
@@ -1677,7 +1670,7 @@ hipError_t exec_prepare(uint32_t max_ops) {
 
 void launch_exec(uint32_t program, const DevArgs *a, uint32_t workgroups, uint32_t max_ops, bool slot,
                  uint64_t batch_capacity, hipStream_t s, hipEvent_t exec_started) {
-    hipLaunchKernelGGL(k_begin_batch, dim3(1), dim3(64), 0, s, a);
+    // the argument upload before these kernels has reset the batch's cursors
     dim3 grid(workgroups), block(kExecWaves * kWave);
     const uint32_t lds = oplist_lds_bytes(max_ops);
     if (program == HETM_PROG_OPLIST) {

@@ -42,7 +42,8 @@ struct hetm_ctx {
     void *log_staging = nullptr;
     DevCounters *cnt = nullptr;
     HotCounters *hot = nullptr;
-    DevCounters *snap_map = nullptr;   // snap_host as the device addresses it (the finish kernel writes it)
+    DevCounters *snap_map = nullptr;   // snap_host as the device addresses it (the finish kernel writes it);
+                                       // two snapshots: [0] every round but queued ones, [s] queued slot s
     DevArgs *dargs = nullptr;
     uint64_t device_bytes = 0;
     void *scratch = nullptr;           // this device's copy of the no-allocation read array
@@ -85,6 +86,7 @@ struct hetm_ctx {
     // round's end instead, the copy's host-bound writes delayed the next
     // round's first, host-reading steps (argument upload, kernel dispatch).
     bool merge_deferred = false;
+    hipEvent_t deferred_ev = nullptr;       // the end of the round whose copy is deferred
     int deferred_buf = 0;
     uint64_t deferred_n = 0;
     void *deferred_host = nullptr;
@@ -111,6 +113,22 @@ struct hetm_ctx {
     uint64_t merge_seq[2] = {0, 0};         // worker job that last read host_stage[b]
     uint64_t round_merge_seq = 0;           // the last closed round's merge job (0: none pending)
     hetm::MergeWorker *merger = nullptr;
+
+    // Rounds queued by hetm_round_submit, oldest first, up to two: slot s
+    // has its own graph per policy, snapshot, staging buffer and events, so
+    // the round behind is launched while the one ahead runs.
+    struct Queued {
+        hetm_round_args r{};
+        const void *hdev = nullptr;
+        uint64_t seq = 0;
+        int slot = 0;
+        bool cancelled = false;      // not run: the round ahead of it failed
+    } queued[2];
+    uint32_t q_head = 0, q_n = 0;
+    uint64_t q_seq = 0;
+    uint64_t reset_floor_seq = 0;   // queued rounds below this number saw the clock before a queued reset
+    RoundGraph qgraphs[2][2];       // [policy][slot]
+    hipEvent_t q_begin[2] = {}, q_end[2] = {};
 
     // the GRAPH round between round_begin and round_end
     bool round_open = false;
@@ -142,6 +160,12 @@ int stream_push(hetm_ctx *c, const void *log, uint64_t n, uint32_t *doomed_out);
 // its earlier batches and before its tail.
 int stream_add(hetm_ctx *c, uint32_t program, const void *descs, uint64_t n_txns, void *results, uint32_t *tickets);
 int stream_end(hetm_ctx *c, hetm_round_result *res);
+// Queued whole rounds: round_submit launches a round behind the ones already
+// queued (up to two); round_collect waits for the oldest and handles its
+// outcome as round_end does, relaunching or cancelling the round behind it
+// when the oldest held it.
+int round_submit(hetm_ctx *c, const hetm_round_args *r);
+int round_collect(hetm_ctx *c, hetm_round_result *res);
 // Double-buffered merge progress.  A successful round's copy to the host is
 // issued by the next round_begin (after it queues its graph) or by
 // issue_deferred_merge; last_merge_seq is the most recently issued job (0

@@ -102,6 +102,8 @@ struct DevCounters {
     uint32_t log_ndesc;           // spill chunks of the current chunk
     uint32_t log_sub[kSubTickets];    // apply blocks finished, per group of blocks (b mod kSubTickets)
     uint32_t scan_sub[kSubTickets];   // compaction count blocks finished, per group of blocks
+    uint32_t hold;                // the last finished round needs the host before another may run
+                                  // (a latched error, or a CPU-wins conflict without a whole undo log)
 };
 
 // Everything a kernel needs: constant context state plus the arguments of
@@ -178,7 +180,8 @@ struct DevArgs {
     uint32_t outcome;       // 0 / 1 / HETM_OUTCOME_DEVICE
     uint32_t epoch;         // the open round's number, as early validation tags a doomed round
     uint32_t policy;        // HETM_POLICY_*: who wins an inter-device conflict
-    uint32_t pad2_;
+    uint32_t gated;         // queued behind a round the host has not collected: runs empty while that
+                            // round holds (cnt->hold); an ungated upload lowers the hold
 };
 
 // ------------------------------------------------------------------ atomics

@@ -376,6 +376,11 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
         c.log_ndesc = 0;
         for (uint32_t g = 0; g < kSubTickets; ++g) c.log_sub[g] = c.scan_sub[g] = 0;
         c.doomed = ld_agent(&cnt->doomed);
+        // a round queued behind this one may run only once the host has
+        // handled an error, or restored the granules of a conflict the undo
+        // log could not roll back
+        c.hold = err != 0 || (c.conflict && a->policy == HETM_POLICY_CPU_WINS && (!a->undo_cap || c.undo_over));
+        st_agent(&cnt->hold, c.hold);
         if (!err) {
             const uint64_t f = c.max_ts > c.floor_ts ? c.max_ts : c.floor_ts;
             c.floor_ts = f;
@@ -404,8 +409,29 @@ __global__ __launch_bounds__(256) void k_finish(const DevArgs *__restrict__ a, D
     }
 }
 
+// The arguments of the work that follows on the stream; also the start of a
+// batch: its work-queue cursors and list lengths go back to zero (every
+// batch's kernels follow an argument upload, and no kernel of the previous
+// batch is still running on the stream).  A round queued behind one the host
+// has not collected yet runs empty (no transactions, no log) if that round
+// holds; the host then handles the held round and launches this one again,
+// ungated.  An ungated upload means the host has seen every earlier round.
 __global__ void k_set_args(DevArgs v, DevArgs *dst) {
-    if (threadIdx.x == 0) *dst = v;
+    if (threadIdx.x == 0) {
+        if (!v.gated) {
+            st_agent(&v.cnt->hold, 0u);
+        } else if (ld_agent(&v.cnt->hold)) {
+            v.n_txns = 0;
+            v.n_log = 0;
+        }
+        *dst = v;
+        if (v.hot) {
+            st_agent(&v.hot->queue_head.v, 0u);
+            st_agent(&v.hot->queue_upd.v, 0u);
+            st_agent(&v.hot->n_ro.v, 0u);
+            st_agent(&v.hot->n_upd.v, 0u);
+        }
+    }
 }
 
 __global__ void k_clear_error(DevCounters *cnt) {

@@ -609,6 +609,7 @@ extern "C" int hetm_serve(hetm_ctx *c, const hetm_serve_spec *sp, void *host_rep
         (sp->host_log_len && !sp->host_log))
         return HETM_EINVAL;
     if (sp->pipelined && c->cfg.mode != HETM_MODE_GRAPH) return HETM_ESTATE;
+    if (c->q_n) return HETM_ESTATE;     // rounds queued by hetm_round_submit are not collected
     if (sp->early_validation && !sp->pipelined) return HETM_EINVAL;
     if (!(sp->round_period_us >= 0) || (sp->round_period_us > 0 && !sp->pipelined)) return HETM_EINVAL;
     if (!sp->pipelined && c->cfg.async_merge) return HETM_ESTATE;

@@ -34,7 +34,8 @@ EXPORTS = ["hetm_alloc_stmr", "hetm_free", "hetm_submit_batch", "hetm_validate_a
            "hetm_stats_get", "hetm_read_state", "hetm_state_bytes", "hetm_host_tm_create",
            "hetm_host_tm_free", "hetm_host_tm_clock", "hetm_host_run_transfers", "hetm_host_run_cache_puts",
            "hetm_serve", "hetm_set_exec_workgroups", "hetm_early_validate", "hetm_set_version_clock",
-           "hetm_read_words_noalloc", "hetm_round_begin", "hetm_round_push", "hetm_round_add", "hetm_round_end"]
+           "hetm_read_words_noalloc", "hetm_round_begin", "hetm_round_push", "hetm_round_add", "hetm_round_end",
+           "hetm_round_submit", "hetm_round_collect"]
 
 P = ctypes.c_void_p
 U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
@@ -137,6 +138,8 @@ def lib() -> ctypes.CDLL:
             "hetm_round_push": ([P, P, U64, P], ctypes.c_int),
             "hetm_round_add": ([P, U32, P, U64, P, P], ctypes.c_int),
             "hetm_round_end": ([P, ctypes.POINTER(hetm_round_result)], ctypes.c_int),
+            "hetm_round_submit": ([P, ctypes.POINTER(hetm_round_args)], ctypes.c_int),
+            "hetm_round_collect": ([P, ctypes.POINTER(hetm_round_result)], ctypes.c_int),
             "hetm_host_tm_create": ([P, U64, U32, U32, U64, ctypes.POINTER(P)], ctypes.c_int),
             "hetm_host_tm_free": ([P], ctypes.c_int),
             "hetm_host_tm_clock": ([P], U64),
@@ -484,4 +487,18 @@ class Context:
     def round_end(self) -> hetm_round_result:
         r = hetm_round_result()
         _check(lib().hetm_round_end(self.ctx, ctypes.byref(r)), "hetm_round_end", self.ctx)
+        return r
+
+    # -- queued rounds (GRAPH mode, async_merge)
+    def round_submit(self, b: Batch | None, log_dev, n_log: int, host, flags=None, ids=None,
+                     policy: int = HETM_POLICY_CPU_WINS) -> None:
+        """Queues a whole round behind those already queued (up to two);
+        b, the log, flags and ids must live until the round is collected."""
+        a = self._round_args(b, log_dev, n_log, host, flags, ids, policy)
+        _check(lib().hetm_round_submit(self.ctx, ctypes.byref(a)), "hetm_round_submit", self.ctx)
+
+    def round_collect(self) -> hetm_round_result:
+        """Waits for the oldest queued round and returns its result."""
+        r = hetm_round_result()
+        _check(lib().hetm_round_collect(self.ctx, ctypes.byref(r)), "hetm_round_collect", self.ctx)
         return r

@@ -44,6 +44,8 @@ def test_strerror_and_null_handling(hm):
     assert L.hetm_round_push(None, None, 0, None) == hm.HETM_EINVAL
     assert L.hetm_round_add(None, 1, None, 0, None, None) == hm.HETM_EINVAL
     assert L.hetm_round_end(None, None) == hm.HETM_EINVAL
+    assert L.hetm_round_submit(None, None) == hm.HETM_EINVAL
+    assert L.hetm_round_collect(None, None) == hm.HETM_EINVAL
 
 
 @pytest.mark.parametrize("field,value", [("n_words", 0), ("word_bytes", 2), ("granule_words", 0),
