@@ -1589,11 +1589,12 @@ __global__ __launch_bounds__(kExecWaves *kWave) void k_exec_cache(const DevArgs 
 // classifies kPartPerThread of them, a block scan places them in LDS, one
 // atomic per list and tile reserves the tile's range, and the block stores
 // both ranges with consecutive threads on consecutive entries; both lists
-// hold ascending ids within a tile.  Tiles are large (16384 transactions, 64
-// for a 2^20 batch) because every tile's reservations queue on the same two
-// counters, and same-address atomics serialize.
+// hold ascending ids within a tile.  The blocks stay at four waves: with
+// queued rounds the split starts beside the previous round's merge copy
+// (a copy kernel on every compute unit), and 16-wave blocks made those
+// rounds slower.
 constexpr uint32_t kPartPerThread = 16;
-constexpr uint32_t kPartBlock = 1024;
+constexpr uint32_t kPartBlock = 256;
 constexpr uint64_t kPartTile = (uint64_t)kPartPerThread * kPartBlock;
 constexpr uint32_t kPartMaxBlocks = 1024;
 
@@ -1617,7 +1618,7 @@ __global__ __launch_bounds__(kPartBlock) void k_partition(const DevArgs *__restr
                 n_ro += 1u - u;
             }
         }
-        // block-exclusive prefix of both counts at once (each <= 16384 per tile)
+        // block-exclusive prefix of both counts at once (each <= 4096 per tile)
         const uint32_t v = n_ro << 16 | n_upd;
         uint32_t inc = v;
         for (uint32_t o = 1; o < kWave; o <<= 1) {
