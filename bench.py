@@ -4,13 +4,15 @@ Headline (`value`): the large synthetic STMR configuration -- 2^28 u32 words
 (1 GiB), batches of 2^20 GPU transactions (90% read-only with 16 reads, 10%
 update with 4 read-modify-writes), 1% hot set drawing 50% of the accesses, a
 host log of 2^20 entries per round in the host-owned half, granule 16 words
--- in the batched form (one captured hipGraph per round, persistent
+-- in the queued batched form (one captured hipGraph per round, each round
+submitted while the one before runs and collected after it, persistent
 transaction kernel, double-buffered merge), with each round's inputs
 (descriptors, log) resident in HBM when the timed region starts.  A step is
 one whole round: execution, validation + apply of the log, dirty-granule
 compaction, merge into the pinned host replica, reset.
 
 Beside it, on the same GPU:
+  batched_per_call          the same rounds one hetm_round call at a time;
   graph_sync_merge / plain  the same rounds with the merge inside the round,
                             and one launch per step (per-step event timings);
   ingest                    the batched rounds with every round's descriptors
@@ -21,14 +23,16 @@ Beside it, on the same GPU:
                             words, 4096 4R/4W transactions, 10,000-entry log,
                             granule 64) and of its partitioned variant;
   conflict                  the large rounds with one log entry redirected
-                            into the batch's read set in 10% of the rounds;
+                            into the batch's read set in 1% and 10% of the
+                            rounds;
   early                     early validation on and off over a sweep of
                             conflicting-round fractions (streamed rounds);
   bank / cache              the bank-transfer and object-cache
                             configurations at full size (retries per commit);
   served                    the request loop swept over arrival rates, for the
                             pipelined form, the pipelined form with early
-                            validation, and one round at a time;
+                            validation or a round period, and one round at
+                            a time;
   cpu_baseline              the C oracle replaying whole large rounds on one
                             pinned host core;
   sweep (not by default)    the large rounds over granules 16..4096 and hot
