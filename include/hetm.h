@@ -391,7 +391,9 @@ int hetm_round_end(hetm_ctx *ctx, hetm_round_result *res);
  * hetm_round_collect waits for the oldest queued round and handles and
  * reports it exactly as hetm_round would have (res as there; us_total is
  * the round's graph time).  The host replica rules of hetm_round apply per
- * collected round.  A round whose outcome needs the host before the next
+ * collected round: writes the host makes for a round submitted behind
+ * another must avoid the granules the round ahead may still merge -- its
+ * GPU write set, and under GPU wins every granule its log wrote.  A round whose outcome needs the host before the next
  * may run -- a latched device error, or a conflict under CPU wins that the
  * undo log cannot roll back -- holds the round queued behind it, which then
  * runs empty; collect handles the held round (discard, or restore from the

@@ -264,10 +264,12 @@ void maybe_reset_versions(hetm_ctx *c, uint32_t clock) {
     c->stats.version_resets++;
 }
 
-void account_round(hetm_ctx *c, const DevCounters &s, uint64_t n_txns, hetm_round_result *res,
+// policy: the round's (a queued round's can differ from the arguments last
+// uploaded, which belong to the round behind it).
+void account_round(hetm_ctx *c, const DevCounters &s, uint64_t n_txns, uint32_t policy, hetm_round_result *res,
                    bool may_reset = true) {
     if (!s.error && may_reset) maybe_reset_versions(c, s.clock_base);
-    const bool gpu_won = s.conflict && c->args.policy == HETM_POLICY_GPU_WINS;
+    const bool gpu_won = s.conflict && policy == HETM_POLICY_GPU_WINS;
     const bool gpu_lost = s.conflict && !gpu_won;
     c->stats.rounds++;
     if (s.conflict) c->stats.rounds_conflicted++;
@@ -738,7 +740,7 @@ int round_end(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
             HIP_TRY(c, hipStreamSynchronize(s));
         }
     }
-    account_round(c, snap, r->n_txns, res);
+    account_round(c, snap, r->n_txns, c->args.policy, res);
     if (res) res->us_total = elapsed_us(c->ev[0], c->ev[3]);
     c->stats.log_entries += r->n_log;
     return HETM_OK;
@@ -795,8 +797,11 @@ int round_submit(hetm_ctx *c, const hetm_round_args *r) {
     q.r = *r;
     q.seq = c->q_seq;
     q.slot = (int)(c->q_seq & 1);
+    // gated behind a round whose outcome is still to come (a cancelled one
+    // will not run, and the discard before it left a hold this upload lowers)
+    const bool gated = c->q_n > 0 && !c->queued[c->q_head].cancelled;
     const DevArgs keep = c->args;
-    int rc = launch_queued(c, q, c->q_n > 0);
+    int rc = launch_queued(c, q, gated);
     if (rc) {
         c->args = keep;
         return rc;
@@ -821,12 +826,14 @@ int round_collect(hetm_ctx *c, hetm_round_result *res) {
     const bool undo_ok = c->undo_cap && !snap.undo_over;
     int rc;
     if (snap.hold) {
-        // the round behind ran empty (its upload saw the hold); once it has
-        // ended the stream is idle and this round is handled as round_end
-        // handles it
-        if (next) HIP_TRY(c, hipEventSynchronize(c->q_end[next->slot]));
+        // the round behind ran empty (its upload saw the hold) and stays
+        // cancelled unless it is launched again below; once it has ended the
+        // stream is idle and this round is handled as round_end handles it
+        if (next) {
+            next->cancelled = true;
+            HIP_TRY(c, hipEventSynchronize(c->q_end[next->slot]));
+        }
         if (snap.error) {
-            if (next) next->cancelled = true;
             if (!undo_ok && (rc = drain_merges(c))) return rc;
             return discard_round(c, snap.error, snap.err_index, q.hdev, undo_ok);
         }
@@ -838,7 +845,10 @@ int round_collect(hetm_ctx *c, hetm_round_result *res) {
                        c->cfg.word_bytes, c->slot, c->stream);
         HIP_TRY(c, hipGetLastError());
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        if (next && (rc = launch_queued(c, *next, false))) return rc;
+        if (next) {
+            if ((rc = launch_queued(c, *next, false))) return rc;
+            next->cancelled = false;
+        }
     } else if (!snap.error && (!snap.conflict || q.r.policy == HETM_POLICY_GPU_WINS)) {
         // the GPU's granules go to the host replica: the round behind is
         // already queued, so the copy is issued now (after this round's end)
@@ -857,7 +867,7 @@ int round_collect(hetm_ctx *c, hetm_round_result *res) {
     // a version reset queued here runs after the round behind, whose
     // snapshot then still shows the clock from before it
     const uint64_t resets = c->stats.version_resets;
-    account_round(c, snap, q.r.n_txns, res, q.seq >= c->reset_floor_seq);
+    account_round(c, snap, q.r.n_txns, q.r.policy, res, q.seq >= c->reset_floor_seq);
     if (c->stats.version_resets != resets) c->reset_floor_seq = c->q_seq;
     if (res) res->us_total = elapsed_us(c->q_begin[b], c->q_end[b]);
     c->stats.log_entries += q.r.n_log;
@@ -1188,7 +1198,7 @@ int hetm_copyback_dirty(hetm_ctx *c, uint32_t conflict, void *host_replica, uint
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         const DevCounters s = *c->snap_host;
         if (s.error) return take_device_error(c, s.error, s.err_index);
-        account_round(c, s, 0, nullptr);
+        account_round(c, s, 0, c->args.policy, nullptr);
         *n_dirty_out = s.n_dirty;
     }
     return HETM_OK;
@@ -1240,7 +1250,7 @@ int hetm_round(hetm_ctx *c, const hetm_round_args *r, hetm_round_result *res) {
     HIP_TRY(c, hipStreamSynchronize(s));
     const DevCounters snap = *c->snap_host;
     if (snap.error) return take_device_error(c, snap.error, snap.err_index);
-    account_round(c, snap, r->n_txns, res);
+    account_round(c, snap, r->n_txns, c->args.policy, res);
     c->stats.log_entries += r->n_log;
     if (res) {
         res->us_exec = elapsed_us(c->ev[0], c->ev[1]);

@@ -47,7 +47,7 @@ class Queue:
         self.floor = 0
         self.pending, self.keep, self.outcomes = [], [], []
 
-    def submit(self, batch, log, lo):
+    def submit(self, batch, log, lo, policy=0):
         import torch
         # the host's transactions write its replica (from word lo up, where
         # no merge copy can be in flight)
@@ -55,24 +55,26 @@ class Queue:
         b = self.hm.Batch(1, batch)
         log_t = self.hm.to_device(log)
         torch.cuda.synchronize()
-        self.ctx.round_submit(b, log_t, log.shape[0], self.host_t)
+        self.ctx.round_submit(b, log_t, log.shape[0], self.host_t, policy=policy)
         self.keep.append((b, log_t))
-        self.pending.append((b, batch, log))
+        self.pending.append((b, batch, log, policy))
 
     def collect(self):
-        b, batch, log = self.pending.pop(0)
+        b, batch, log, policy = self.pending.pop(0)
         res = self.ctx.round_collect()
         orc = self.orc
         self.H = self.wl.host_replica(self.H, log)
         o = orc.round_oplist(self.S, self.H, self.TS, self.G, batch, orc.order_from_tickets(b.tickets_np(),
                                                                                            even_ties=True),
-                             log, self.floor)
+                             log, self.floor, policy)
         say(f"collected: conflict {res.conflict}, dirty {res.n_dirty}")
         assert res.error == 0
         assert res.conflict == o["conflict"]
         assert np.array_equal(b.results_np(), o["results"]), "transaction results differ"
         assert int(res.n_dirty) == o["ids"].shape[0]
-        assert int(res.n_committed) == (0 if o["conflict"] else batch.n)
+        gpu_won = bool(o["conflict"]) and policy == self.hm.HETM_POLICY_GPU_WINS
+        assert int(res.n_committed) == (0 if o["conflict"] and not gpu_won else batch.n)
+        assert res.host_discarded == int(gpu_won)
         self.floor = int(o["max_ts"])
         assert int(res.max_ts) == self.floor
         self.outcomes.append(int(res.conflict))
@@ -132,14 +134,14 @@ def test_queued_error_cancels_next(hm, wl):
     watermark) is discarded when collected: its collect returns EORDER, the
     round queued behind it ran empty and is cancelled (ESTATE, its batch
     untouched), the GPU replica is back where it was before the failed
-    round, and queued rounds after that continue from there."""
+    round, and rounds submitted after that -- the first while the cancelled
+    one is still queued -- run and continue from there."""
     N, G = 1 << 16, 16
     init = np.random.default_rng(78).integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
     q = Queue(hm, wl, N, G, 1, init)
     batch, log, lo = _inputs(wl, 0, N, False)
     q.submit(batch, log, lo)
     q.collect()
-    S_before = q.S.copy()
     bad_batch, bad_log, _ = _inputs(wl, 1, N, False)
     bad_log["ts"][17] = q.floor                    # not above the watermark
     next_batch, next_log, _ = _inputs(wl, 2, N, False)
@@ -153,14 +155,17 @@ def test_queued_error_cancels_next(hm, wl):
     with pytest.raises(hm.HetmError) as e:
         q.ctx.round_collect()
     assert e.value.code == hm.HETM_EORDER
+    # a round submitted while the cancelled one is still queued runs for real
+    # (the host never wrote the failed logs; the next rounds carry fresh ones)
+    batch, log, lo = _inputs(wl, 3, N, False, watermark=q.floor)
+    q.submit(batch, log, lo)
     with pytest.raises(hm.HetmError) as e:
         q.ctx.round_collect()
     assert e.value.code == hm.HETM_ESTATE
     assert not b2.tickets_np().any(), "the cancelled round ran"
+    q.collect()
     q.ctx.sync()
-    assert np.array_equal(q.ctx.read_state(hm.HETM_STATE_STMR), S_before)
-    # the host never wrote the failed logs; the next rounds carry fresh ones
-    for k, r in enumerate((3, 4, 5)):
+    for k, r in enumerate((4, 5, 6)):
         batch, log, lo = _inputs(wl, r, N, False, watermark=q.floor + k * NLOG)
         q.submit(batch, log, lo)
         if len(q.pending) == 2:
@@ -209,3 +214,37 @@ def test_queued_state_errors(hm, wl):
     ctx.sync()
     ctx.read_state(hm.HETM_STATE_STMR)           # allowed again
     ctx.close()
+
+
+def test_queued_policies(hm, wl):
+    """Queued rounds under both policies, one behind the other (each slot
+    holds a graph per policy): round 2 conflicts under GPU wins, so the
+    host's round is discarded and the granules either side wrote go to the
+    host replica, and the CPU-wins round after it continues from there.
+    Every round matches the oracle under its policy."""
+    N, G = 1 << 16, 16
+    init = np.random.default_rng(79).integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
+    q = Queue(hm, wl, N, G, 1, init)
+    policies = [0, 1, 1, 0, 1]
+    wm = 0
+    for r, pol in enumerate(policies):
+        conflict = r == 2
+        if r in (2, 3):
+            # round 2's log writes the GPU's half; and under GPU wins its merge
+            # copies every granule that log wrote, so the host writes again
+            # only once that merge has landed
+            while q.pending:
+                q.collect()
+            q.ctx.sync()
+            wm = max(wm, q.floor)
+        batch, log, lo = _inputs(wl, r, N, conflict, watermark=wm)
+        say(f"queued round {r}, policy {pol}")
+        q.submit(batch, log, lo, policy=pol)
+        # a discarded log does not raise the watermark: later logs start above
+        # the last one submitted either way
+        wm += NLOG
+        if len(q.pending) == 2:
+            q.collect()
+    q.finish()
+    assert q.outcomes == [0, 0, 1, 0, 0]
+    q.ctx.close()
