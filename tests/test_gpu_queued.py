@@ -219,10 +219,10 @@ def test_queued_state_errors(hm, wl):
 
 def test_queued_policies(hm, wl):
     """Queued rounds under both policies, one behind the other (each slot
-    holds a graph per policy): round 2 conflicts under GPU wins, so the
-    host's round is discarded and the granules either side wrote go to the
-    host replica, and the CPU-wins round after it continues from there.
-    Every round matches the oracle under its policy."""
+    holds a graph per policy): the round at r = 2 conflicts under GPU wins,
+    so the host's round is discarded and the granules either side wrote go
+    to the host replica, and the CPU-wins round after it continues from
+    there.  Every round matches the oracle under its policy."""
     N, G = 1 << 16, 16
     init = np.random.default_rng(79).integers(0, 2 ** 32, size=N, dtype=np.uint64).astype(np.uint32)
     q = Queue(hm, wl, N, G, 1, init)
@@ -231,7 +231,7 @@ def test_queued_policies(hm, wl):
     for r, pol in enumerate(policies):
         conflict = r == 2
         if r in (2, 3):
-            # round 2's log writes the GPU's half; and under GPU wins its merge
+            # the r = 2 log writes the GPU's half; and under GPU wins its merge
             # copies every granule that log wrote, so the host writes again
             # only once that merge has landed
             while q.pending:
