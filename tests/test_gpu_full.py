@@ -50,6 +50,60 @@ def test_c2_full_size_conflict(hm, wl):
     assert o["conflict"] == 1
 
 
+def test_c2_full_size_queued(hm, wl):
+    """Three large rounds as the benchmark's headline runs them: each
+    submitted while the one before runs (hetm_round_submit), collected in
+    order.  Every collected round equals the oracle continued from the last
+    in every output it reports, and both replicas equal the oracle's at the
+    end."""
+    import torch
+    N, n, G = 1 << 28, 1 << 20, 16
+    rounds = [wl.c2(p_hot=0.5, granule=G, round_no=3)]
+    rounds += [wl.c2(p_hot=0.5, granule=G, round_no=4 + k, watermark=(k + 1) * n, init=False) for k in range(2)]
+    init = rounds[0].init
+    ctx = hm.Context(N, 4, G, init=init, max_ops=16, batch_capacity=n, log_capacity=n, mode=hm.HETM_MODE_GRAPH,
+                     async_merge=True)
+    host_t = hm.pinned(N * 4)
+    host = host_t.numpy().view(np.uint32)
+    host[:] = init
+    S, H, TS, floor = init.copy(), init.copy(), np.zeros(N, np.uint64), 0
+    keep, pending = [], []
+
+    def collect():
+        nonlocal H, floor
+        b, ri = pending.pop(0)
+        res = ctx.round_collect()
+        say(f"c2 full queued: oracle round {len(keep) - len(pending) - 1}")
+        H = wl.host_replica(H, ri.log)
+        o = orc.round_oplist(S, H, TS, G, ri.batch, orc.order_from_tickets(b.tickets_np(), even_ties=True), ri.log,
+                             floor)
+        assert res.error == 0 and res.conflict == o["conflict"] == 0
+        assert np.array_equal(b.results_np(), o["results"]), "transaction results differ"
+        assert int(res.n_dirty) == o["ids"].shape[0] and int(res.n_runs) == o["n_runs"]
+        assert int(res.n_committed) == n
+        floor = int(o["max_ts"])
+        assert int(res.max_ts) == floor
+
+    for r, ri in enumerate(rounds):
+        # the host's writes land in its half, where no merge copy is in flight
+        host[N // 2:] = wl.host_replica(host.copy(), ri.log)[N // 2:]
+        b = hm.Batch(hm.HETM_PROG_OPLIST, ri.batch)
+        log_t = hm.to_device(ri.log)
+        torch.cuda.synchronize()
+        say(f"c2 full queued: submit round {r}")
+        ctx.round_submit(b, log_t, n, host_t)
+        keep.append((b, log_t))
+        pending.append((b, ri))
+        if len(pending) == 2:
+            collect()
+    while pending:
+        collect()
+    ctx.sync()
+    assert np.array_equal(ctx.read_state(hm.HETM_STATE_STMR), S), "GPU replica differs"
+    assert np.array_equal(host, H), "host replica differs"
+    ctx.close()
+
+
 @pytest.mark.parametrize("conflict_rate", [0.0, 1.0])
 def test_c2_full_size_streamed(hm, wl, conflict_rate):
     """The large round as a streamed round: its 2^20-entry log pushed in 16
